@@ -1,0 +1,210 @@
+"""CPU oracle for the LASTO Hartree step -- TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 C (``oracle.c``) behind ctypes. Only ``tests/``, the smoke check
+and the benchmark's CPU-baseline leg may import this package. The GPU path
+(``paper_0806_1723_amd``) never imports it and shares no code with it.
+
+``build()`` compiles ``liboracle.so`` with gcc (no fast-math, so the
+arithmetic is plain IEEE FP64); importing builds it if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+PI = np.pi
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle library in place; returns its path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        d, i = C.c_double, C.c_int
+        P = C.c_void_p
+        L.oracle_mesh_graded_1d.argtypes = [d, d, i, P, i, d, d, d, d, P, P, P]
+        L.oracle_mesh_graded_1d.restype = i
+        L.oracle_solid_harmonics.argtypes = [d, d, d, P]
+        L.oracle_solid_harmonics.restype = None
+        L.oracle_pseudo_density.argtypes = [P, i, P, i, P, i, i, P, P, P, P, P, P, P, P, P, P, P, i, P]
+        L.oracle_pseudo_density.restype = i
+        L.oracle_moments.argtypes = [P, i, P, i, P, i, P, i, P, P]
+        L.oracle_moments.restype = None
+        L.oracle_boundary_values.argtypes = [P, i, P, i, P, i, i, P, i, P, P]
+        L.oracle_boundary_values.restype = None
+        L.oracle_apply.argtypes = [P, i, P, i, P, i, P, P]
+        L.oracle_apply.restype = None
+        L.oracle_solve.argtypes = [P, i, P, i, P, i, P, P, d, i, i, i, d, i, P, P]
+        L.oracle_solve.restype = i
+        L.oracle_rel_residual.argtypes = [P, i, P, i, P, i, P, P]
+        L.oracle_rel_residual.restype = d
+        L.oracle_interp.argtypes = [P, i, P, i, P, i, P, i, P, P]
+        L.oracle_interp.restype = i
+        L.oracle_hierarchy_sizes.argtypes = [P, i, P, i, P, i, d, i, P, i]
+        L.oracle_hierarchy_sizes.restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------------ API
+def mesh_graded_1d(lo, hi, n, planes, hmin, hmax, gmax=1.2, hmin_step=0.0):
+    """Graded 1-D node coordinates (Section 3's adaptive mesh, grading rule of
+    the oracle header). Returns (x, g, hmin_used)."""
+    planes = _f64(planes).ravel()
+    x = np.zeros(n)
+    g = np.zeros(1)
+    hm = np.zeros(1)
+    rc = lib().oracle_mesh_graded_1d(lo, hi, n, _p(planes), len(planes), hmin, hmax, gmax,
+                                     hmin_step, _p(x), _p(g), _p(hm))
+    if rc != 0:
+        raise ValueError("oracle_mesh_graded_1d failed (%d)" % rc)
+    return x, float(g[0]), float(hm[0])
+
+
+def mesh_for(axes):
+    """Coordinates for the three AxisSpec of a workload."""
+    out = []
+    for a in axes:
+        x, _, _ = mesh_graded_1d(a.lo, a.hi, a.n, a.planes, a.hmin, a.hmax, a.gmax, a.hmin_step)
+        out.append(x)
+    return out
+
+
+def solid_harmonics(x, y, z) -> np.ndarray:
+    S = np.zeros(25)
+    lib().oracle_solid_harmonics(float(x), float(y), float(z), _p(S))
+    return S
+
+
+def pseudo_density(xs, atoms_arr, rho_inter=None, renormalize=True) -> np.ndarray:
+    x, y, z = (_f64(a) for a in xs)
+    A = atoms_arr
+    n = len(A["q"])
+    out = np.zeros((len(z), len(y), len(x)))
+    ri = None if rho_inter is None else _f64(rho_inter)
+    centers = _f64(A["centers"])
+    clm = _f64(A["clm"])
+    assert clm.shape == (n, 24)
+    keep = [centers, _f64(A["q"]), _f64(A["width"]), _f64(A["radius"]), _f64(A["alpha"]),
+            np.ascontiguousarray(A["lmax"], dtype=np.int32), clm,
+            np.ascontiguousarray(A["kind"], dtype=np.int32), _f64(A["rho_R"]), _f64(A["drho_R"])]
+    rc = lib().oracle_pseudo_density(_p(x), len(x), _p(y), len(y), _p(z), len(z), n,
+                                     *[_p(k) for k in keep],
+                                     None if ri is None else _p(ri), int(renormalize), _p(out))
+    if rc != 0:
+        raise ValueError("oracle_pseudo_density failed")
+    return out
+
+
+def moments(xs, rho, lmax_bc=4, center=(0.0, 0.0, 0.0)) -> np.ndarray:
+    x, y, z = (_f64(a) for a in xs)
+    rho = _f64(rho)
+    Q = np.zeros((lmax_bc + 1) ** 2)
+    c = _f64(center)
+    lib().oracle_moments(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(rho), lmax_bc, _p(c), _p(Q))
+    return Q
+
+
+def boundary_values(xs, Q, v, bc_mode=1, lmax_bc=4, center=(0.0, 0.0, 0.0)):
+    """Writes the six faces of v (in place)."""
+    x, y, z = (_f64(a) for a in xs)
+    Qa = _f64(Q)
+    c = _f64(center)
+    assert v.dtype == np.float64 and v.flags.c_contiguous
+    lib().oracle_boundary_values(_p(x), len(x), _p(y), len(y), _p(z), len(z), bc_mode, _p(Qa),
+                                 lmax_bc, _p(c), _p(v))
+    return v
+
+
+def apply(xs, u) -> np.ndarray:
+    x, y, z = (_f64(a) for a in xs)
+    u = _f64(u)
+    out = np.zeros_like(u)
+    lib().oracle_apply(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(u), _p(out))
+    return out
+
+
+def solve(xs, rho, v, rtol=1e-12, max_cycles=200, nu1=2, nu2=2, theta=4.0, coarse_max=5):
+    """In-place V-cycle solve of eq. (3.2); v holds face values and the guess.
+    Returns (cycles, rel_resid, history)."""
+    x, y, z = (_f64(a) for a in xs)
+    rho = _f64(rho)
+    assert v.dtype == np.float64 and v.flags.c_contiguous
+    rel = np.zeros(1)
+    hist = np.zeros(128)
+    cyc = lib().oracle_solve(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(rho), _p(v), rtol,
+                             max_cycles, nu1, nu2, theta, coarse_max, _p(rel), _p(hist))
+    return cyc, float(rel[0]), hist[:min(cyc, 128)].copy()
+
+
+def rel_residual(xs, rho, v) -> float:
+    x, y, z = (_f64(a) for a in xs)
+    return lib().oracle_rel_residual(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(_f64(rho)), _p(_f64(v)))
+
+
+def interp(xs, v, pts) -> np.ndarray:
+    x, y, z = (_f64(a) for a in xs)
+    pts = _f64(pts).reshape(-1, 3)
+    out = np.zeros(len(pts))
+    rc = lib().oracle_interp(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(_f64(v)), len(pts), _p(pts), _p(out))
+    if rc != 0:
+        raise ValueError("oracle_interp needs >= 4 nodes per axis")
+    return out
+
+
+def hierarchy_sizes(xs, theta=4.0, coarse_max=5):
+    x, y, z = (_f64(a) for a in xs)
+    s = np.zeros(64 * 3, dtype=np.int32)
+    nl = lib().oracle_hierarchy_sizes(_p(x), len(x), _p(y), len(y), _p(z), len(z), theta, coarse_max, _p(s), 64)
+    return s[:3 * nl].reshape(nl, 3)
+
+
+def sphere_points(centers, radii, dirs) -> np.ndarray:
+    """C_a + R_a d_k for every atom a and direction k, atom-major."""
+    centers = _f64(centers).reshape(-1, 3)
+    radii = _f64(radii).ravel()
+    dirs = _f64(dirs).reshape(-1, 3)
+    return (centers[:, None, :] + radii[:, None, None] * dirs[None, :, :]).reshape(-1, 3)
+
+
+def hartree_step(xs, atoms_arr, dirs, bc_mode=1, lmax_bc=4, rtol=1e-12, max_cycles=200,
+                 rho_inter=None, renormalize=True, guess=None):
+    """The whole path on the CPU: pseudo-density -> moments -> face values ->
+    solve -> values on the sphere boundaries. Returns a dict."""
+    rho = pseudo_density(xs, atoms_arr, rho_inter, renormalize)
+    center = (0.5 * (xs[0][0] + xs[0][-1]), 0.5 * (xs[1][0] + xs[1][-1]), 0.5 * (xs[2][0] + xs[2][-1]))
+    Q = moments(xs, rho, lmax_bc, center)
+    v = np.zeros_like(rho) if guess is None else _f64(guess).copy()
+    boundary_values(xs, Q, v, bc_mode, lmax_bc, center)
+    cyc, rel, hist = solve(xs, rho, v, rtol, max_cycles)
+    pts = sphere_points(atoms_arr["centers"], atoms_arr["radius"], dirs)
+    vs = interp(xs, v, pts).reshape(len(atoms_arr["q"]), -1)
+    return dict(rho=rho, Q=Q, v=v, cycles=cyc, rel=rel, hist=hist, sphere=vs, center=center)

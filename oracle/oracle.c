@@ -1,0 +1,879 @@
+/*
+ * CPU oracle for the LASTO Hartree step -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct FP64 C. Only the tests, the smoke check and
+ * the benchmark's CPU-baseline leg may load this file's library. It shares no
+ * code with the GPU path (paper_0806_1723_amd/csrc), and the GPU path never
+ * calls it.
+ *
+ * What it computes (paper: Kang, Davenport, Glimm, Keyes, McGuigan, "Linear
+ * Augmented Slater-Type Orbital Method for Free Standing Clusters"):
+ *   - the pseudo-density source of the Coulomb Poisson problem, eq. (3.2) and
+ *     the three constraints under it (same charge inside R, same value and
+ *     slope at R); the monopole is smoothed, the l >= 1 terms go directly on
+ *     the grid (Section 1, the paragraph on the Poisson equation);
+ *   - the finite-difference discretisation of eq. (3.2) on a graded
+ *     tensor-product mesh (Section 3: "large finite adaptive domain", fine
+ *     near atoms, Dirichlet data at its edge) and its multigrid solution
+ *     (Section 3, the sentence naming "a finite difference scheme and a
+ *     multigrid method");
+ *   - the multipole Dirichlet data on the box faces (an extension of the
+ *     zero boundary value of eq. (3.3); the zero mode is kept too);
+ *   - interpolation of V_C onto the sphere boundaries, eq. (3.5)-(3.6).
+ *
+ * Readings where the paper is silent are listed at each function.
+ * Sign: eq. (3.2) is solved literally, Laplacian(V) = +4 pi rho~.
+ * Array layout: [nz][ny][nx], x fastest, boundary nodes included.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------ mesh */
+
+/* Reading of Section 3 ("fine meshes near the atoms and coarse meshes at
+ * large distances"): spacing h(x) = min(hmax, hmin + (g-1) d(x)), d(x) the
+ * distance from x to the nearest atom coordinate on this axis. The node map
+ * xi(x) = int_lo^x dt / h(t) is integrated exactly; g is found by bisection so
+ * that xi(hi) = n-1 (g = 1 if even hmin is coarse enough), and node i sits at
+ * xi^-1(i xi(hi)/(n-1)). */
+static double mesh_F(double d, double g, double hmin, double hmax)
+{
+    /* integral_0^d dt / min(hmax, hmin + (g-1) t) */
+    if (g <= 1.0) return d / hmin;
+    double ds = (hmax - hmin) / (g - 1.0);
+    if (d <= ds) return log1p((g - 1.0) * d / hmin) / (g - 1.0);
+    return log1p((g - 1.0) * ds / hmin) / (g - 1.0) + (d - ds) / hmax;
+}
+
+static double mesh_Finv(double v, double g, double hmin, double hmax)
+{
+    if (g <= 1.0) return v * hmin;
+    double ds = (hmax - hmin) / (g - 1.0);
+    double Fs = log1p((g - 1.0) * ds / hmin) / (g - 1.0);
+    if (v <= Fs) return hmin * expm1((g - 1.0) * v) / (g - 1.0);
+    return ds + (v - Fs) * hmax;
+}
+
+static int cmp_double(const void* a, const void* b)
+{
+    double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+/* breakpoints where d(x) changes slope: lo, planes, midpoints, hi */
+typedef struct { int nb; double* bp; double* pl; } mesh_seg;
+
+static void mesh_segments(double lo, double hi, const double* planes, int np, mesh_seg* s)
+{
+    double* p = (double*)malloc(sizeof(double) * (size_t)(np > 0 ? np : 1));
+    memcpy(p, planes, sizeof(double) * (size_t)np);
+    qsort(p, (size_t)np, sizeof(double), cmp_double);
+    s->bp = (double*)malloc(sizeof(double) * (size_t)(2 * np + 2));
+    s->pl = (double*)malloc(sizeof(double) * (size_t)(2 * np + 2));
+    int nb = 0;
+    s->bp[nb++] = lo;
+    for (int j = 0; j < np; ++j) {
+        if (j > 0) {
+            double mid = 0.5 * (p[j - 1] + p[j]);
+            if (mid > s->bp[nb - 1] && mid < hi) s->bp[nb++] = mid;
+        }
+        if (p[j] > s->bp[nb - 1] && p[j] < hi) s->bp[nb++] = p[j];
+    }
+    s->bp[nb++] = hi;
+    /* nearest plane of each segment (by its midpoint) */
+    for (int k = 0; k + 1 < nb; ++k) {
+        double mid = 0.5 * (s->bp[k] + s->bp[k + 1]);
+        double best = p[0];
+        for (int j = 1; j < np; ++j)
+            if (fabs(p[j] - mid) < fabs(best - mid)) best = p[j];
+        s->pl[k] = best;
+    }
+    s->nb = nb;
+    free(p);
+}
+
+static double mesh_total(const mesh_seg* s, double g, double hmin, double hmax)
+{
+    double t = 0.0;
+    for (int k = 0; k + 1 < s->nb; ++k) {
+        double da = fabs(s->bp[k] - s->pl[k]), db = fabs(s->bp[k + 1] - s->pl[k]);
+        t += fabs(mesh_F(db, g, hmin, hmax) - mesh_F(da, g, hmin, hmax));
+    }
+    return t;
+}
+
+/* returns 0 on success, 1 on bad arguments, 2 if infeasible */
+int oracle_mesh_graded_1d(double lo, double hi, int n, const double* planes, int np,
+                          double hmin, double hmax, double gmax, double hmin_step,
+                          double* x, double* g_out, double* hmin_out)
+{
+    if (n < 3 || !(hi > lo)) return 1;
+    if (np == 0) {
+        for (int i = 0; i < n; ++i) x[i] = lo + (hi - lo) * (double)i / (double)(n - 1);
+        x[0] = lo; x[n - 1] = hi;
+        if (g_out) *g_out = 1.0;
+        if (hmin_out) *hmin_out = (hi - lo) / (double)(n - 1);
+        return 0;
+    }
+    if (!(hmin > 0.0) || hmax < hmin || gmax <= 1.0) return 1;
+    mesh_seg s;
+    mesh_segments(lo, hi, planes, np, &s);
+    double target = (double)(n - 1), g = 1.0;
+    for (;;) {
+        if (mesh_total(&s, 1.0, hmin, hmax) <= target) { g = 1.0; break; }
+        if (mesh_total(&s, gmax, hmin, hmax) <= target) {
+            double a = 1.0, b = gmax;
+            for (int it = 0; it < 200; ++it) {
+                double m = 0.5 * (a + b);
+                if (m <= a || m >= b) break;
+                if (mesh_total(&s, m, hmin, hmax) > target) a = m; else b = m;
+            }
+            g = b;
+            break;
+        }
+        if (hmin_step <= 0.0 || hmin + hmin_step > hmax) {
+            free(s.bp); free(s.pl);
+            return 2;
+        }
+        hmin = hmin + hmin_step;
+    }
+    double T = mesh_total(&s, g, hmin, hmax);
+    /* cumulative xi at the breakpoints */
+    double* cum = (double*)malloc(sizeof(double) * (size_t)s.nb);
+    cum[0] = 0.0;
+    for (int k = 0; k + 1 < s.nb; ++k) {
+        double da = fabs(s.bp[k] - s.pl[k]), db = fabs(s.bp[k + 1] - s.pl[k]);
+        cum[k + 1] = cum[k] + fabs(mesh_F(db, g, hmin, hmax) - mesh_F(da, g, hmin, hmax));
+    }
+    x[0] = lo;
+    x[n - 1] = hi;
+    int k = 0;
+    for (int i = 1; i < n - 1; ++i) {
+        double t = T * (double)i / (double)(n - 1);
+        while (k + 2 < s.nb && cum[k + 1] < t) ++k;
+        double a = s.bp[k], b = s.bp[k + 1], p = s.pl[k];
+        double Fa = mesh_F(fabs(a - p), g, hmin, hmax);
+        double dt = t - cum[k];
+        double xx;
+        if (p <= a) xx = p + mesh_Finv(Fa + dt, g, hmin, hmax);   /* moving away from the plane */
+        else        xx = p - mesh_Finv(Fa - dt, g, hmin, hmax);   /* moving toward it */
+        if (xx < a) xx = a;
+        if (xx > b) xx = b;
+        x[i] = xx;
+    }
+    free(cum); free(s.bp); free(s.pl);
+    if (g_out) *g_out = g;
+    if (hmin_out) *hmin_out = hmin;
+    return 0;
+}
+
+/* ---------------------------------------------------- spherical harmonics */
+
+/* Real solid harmonics S_lm(x,y,z) = r^l y_lm, l <= 4, orthonormal y_lm on the
+ * unit sphere with no Condon-Shortley phase (y_11 proportional to +x), the
+ * real harmonics of eq. (3.1). Index l*l + l + m. Written out explicitly. */
+void oracle_solid_harmonics(double x, double y, double z, double* S)
+{
+    double r2 = x * x + y * y + z * z;
+    double c;
+    S[0] = 0.5 * sqrt(1.0 / PI);
+    c = sqrt(3.0 / (4.0 * PI));
+    S[1] = c * y; S[2] = c * z; S[3] = c * x;
+    S[4] = 0.5 * sqrt(15.0 / PI) * x * y;
+    S[5] = 0.5 * sqrt(15.0 / PI) * y * z;
+    S[6] = 0.25 * sqrt(5.0 / PI) * (3.0 * z * z - r2);
+    S[7] = 0.5 * sqrt(15.0 / PI) * x * z;
+    S[8] = 0.25 * sqrt(15.0 / PI) * (x * x - y * y);
+    S[9] = 0.25 * sqrt(35.0 / (2.0 * PI)) * y * (3.0 * x * x - y * y);
+    S[10] = 0.5 * sqrt(105.0 / PI) * x * y * z;
+    S[11] = 0.25 * sqrt(21.0 / (2.0 * PI)) * y * (5.0 * z * z - r2);
+    S[12] = 0.25 * sqrt(7.0 / PI) * z * (5.0 * z * z - 3.0 * r2);
+    S[13] = 0.25 * sqrt(21.0 / (2.0 * PI)) * x * (5.0 * z * z - r2);
+    S[14] = 0.25 * sqrt(105.0 / PI) * z * (x * x - y * y);
+    S[15] = 0.25 * sqrt(35.0 / (2.0 * PI)) * x * (x * x - 3.0 * y * y);
+    S[16] = 0.75 * sqrt(35.0 / PI) * x * y * (x * x - y * y);
+    S[17] = 0.75 * sqrt(35.0 / (2.0 * PI)) * y * z * (3.0 * x * x - y * y);
+    S[18] = 0.75 * sqrt(5.0 / PI) * x * y * (7.0 * z * z - r2);
+    S[19] = 0.75 * sqrt(5.0 / (2.0 * PI)) * y * z * (7.0 * z * z - 3.0 * r2);
+    S[20] = (3.0 / 16.0) * sqrt(1.0 / PI) * (35.0 * z * z * z * z - 30.0 * z * z * r2 + 3.0 * r2 * r2);
+    S[21] = 0.75 * sqrt(5.0 / (2.0 * PI)) * x * z * (7.0 * z * z - 3.0 * r2);
+    S[22] = (3.0 / 8.0) * sqrt(5.0 / PI) * (x * x - y * y) * (7.0 * z * z - r2);
+    S[23] = 0.75 * sqrt(35.0 / (2.0 * PI)) * x * z * (x * x - 3.0 * y * y);
+    S[24] = (3.0 / 16.0) * sqrt(35.0 / PI) * (x * x * (x * x - 3.0 * y * y) - y * y * (3.0 * x * x - y * y));
+}
+
+/* ------------------------------------------------------------ grid data */
+
+/* dual widths m_i: half the two adjacent spacings; half a spacing at an end */
+static void dual_widths(const double* x, int n, double* m)
+{
+    m[0] = 0.5 * (x[1] - x[0]);
+    m[n - 1] = 0.5 * (x[n - 1] - x[n - 2]);
+    for (int i = 1; i < n - 1; ++i) m[i] = 0.5 * (x[i + 1] - x[i - 1]);
+}
+
+#define IDX(i, j, k, nx, ny) ((size_t)(k) * (size_t)(ny) * (size_t)(nx) + (size_t)(j) * (size_t)(nx) + (size_t)(i))
+
+/* ------------------------------------------------------- pseudo-density */
+
+/* Pseudo-density on the grid nodes, eq. (3.2) source.
+ * kind 0: q s (pi w^2)^(-3/2) exp(-r^2/w^2) for r < 7w, with s chosen so the
+ *         discrete charge sum_n vol_n rho_n of the monopole is exactly q
+ *         (the "same zeroth multipole moment" constraint read on the grid);
+ *         renormalize = 0 sets s = 1.
+ * kind 1: the paper's three constraints (charge q inside R, value rho_R and
+ *         slope drho_R at R) fix an even quartic a + b r^2 + c r^4 inside R,
+ *         with q = 4 pi int_0^R rho~ r^2 dr; zero outside R.
+ * Non-spherical terms (both kinds), put directly on the grid:
+ *         sum_{l=1..lmax} sum_m c_lm S_lm(r) exp(-alpha r^2), for
+ *         alpha r^2 < 42.25.
+ * rho_inter (optional) is added at nodes outside every sphere. */
+int oracle_pseudo_density(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                          int n_atoms, const double* centers, const double* q, const double* width,
+                          const double* radius, const double* alpha, const int* lmax, const double* clm,
+                          const int* kind, const double* rho_R, const double* drho_R,
+                          const double* rho_inter, int renormalize, double* rho)
+{
+    double *mx = malloc(sizeof(double) * nx), *my = malloc(sizeof(double) * ny), *mz = malloc(sizeof(double) * nz);
+    dual_widths(x, nx, mx); dual_widths(y, ny, my); dual_widths(z, nz, mz);
+    size_t N = (size_t)nx * ny * nz;
+    for (size_t t = 0; t < N; ++t) rho[t] = 0.0;
+    for (int a = 0; a < n_atoms; ++a) {
+        if (lmax[a] < 0 || lmax[a] > 4) { free(mx); free(my); free(mz); return 1; }
+        const double cx = centers[3 * a], cy = centers[3 * a + 1], cz = centers[3 * a + 2];
+        if (kind[a] == 0) {
+            double w = width[a], cut = 7.0 * w;
+            double norm = pow(PI * w * w, -1.5);
+            double sum = 0.0;
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        double dx = x[i] - cx, dy = y[j] - cy, dz = z[k] - cz;
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < cut * cut) sum += mx[i] * my[j] * mz[k] * norm * exp(-r2 / (w * w));
+                    }
+            double s = renormalize ? 1.0 / sum : 1.0;
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        double dx = x[i] - cx, dy = y[j] - cy, dz = z[k] - cz;
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < cut * cut) rho[IDX(i, j, k, nx, ny)] += q[a] * s * norm * exp(-r2 / (w * w));
+                    }
+        } else {
+            /* solve the 3x3 system of the constraints for (a0, b, c) */
+            double R = radius[a];
+            double A[3][4] = {
+                {1.0, R * R, R * R * R * R, rho_R[a]},
+                {0.0, 2.0 * R, 4.0 * R * R * R, drho_R[a]},
+                {4.0 * PI * R * R * R / 3.0, 4.0 * PI * pow(R, 5) / 5.0, 4.0 * PI * pow(R, 7) / 7.0, q[a]}};
+            for (int c = 0; c < 3; ++c) {
+                int p = c;
+                for (int r = c + 1; r < 3; ++r) if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+                for (int t = 0; t < 4; ++t) { double tmp = A[c][t]; A[c][t] = A[p][t]; A[p][t] = tmp; }
+                for (int r = 0; r < 3; ++r) {
+                    if (r == c) continue;
+                    double f = A[r][c] / A[c][c];
+                    for (int t = c; t < 4; ++t) A[r][t] -= f * A[c][t];
+                }
+            }
+            double c0 = A[0][3] / A[0][0], c2 = A[1][3] / A[1][1], c4 = A[2][3] / A[2][2];
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        double dx = x[i] - cx, dy = y[j] - cy, dz = z[k] - cz;
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < R * R) rho[IDX(i, j, k, nx, ny)] += c0 + c2 * r2 + c4 * r2 * r2;
+                    }
+        }
+        if (lmax[a] >= 1) {
+            double al = alpha[a], cut2 = 42.25 / al;
+            const double* c = clm + 24 * (size_t)a;
+            double S[25];
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        double dx = x[i] - cx, dy = y[j] - cy, dz = z[k] - cz;
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 >= cut2) continue;
+                        oracle_solid_harmonics(dx, dy, dz, S);
+                        double acc = 0.0;
+                        for (int t = 1; t < (lmax[a] + 1) * (lmax[a] + 1); ++t) acc += c[t - 1] * S[t];
+                        rho[IDX(i, j, k, nx, ny)] += acc * exp(-al * r2);
+                    }
+        }
+    }
+    if (rho_inter) {
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    int outside = 1;
+                    for (int a = 0; a < n_atoms; ++a) {
+                        double dx = x[i] - centers[3 * a], dy = y[j] - centers[3 * a + 1], dz = z[k] - centers[3 * a + 2];
+                        if (dx * dx + dy * dy + dz * dz < radius[a] * radius[a]) { outside = 0; break; }
+                    }
+                    if (outside) rho[IDX(i, j, k, nx, ny)] += rho_inter[IDX(i, j, k, nx, ny)];
+                }
+    }
+    free(mx); free(my); free(mz);
+    return 0;
+}
+
+/* ------------------------------------------------------------- moments */
+
+/* Q_lm = sum_n vol_n rho_n S_lm(x_n - c), l <= lmax_bc (the paper keeps
+ * L <= 4 in the expansions of eq. (3.1)); vol_n is the product of the dual
+ * widths, boundary nodes included with half widths. */
+void oracle_moments(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                    const double* rho, int lmax_bc, const double* c, double* Q)
+{
+    double *mx = malloc(sizeof(double) * nx), *my = malloc(sizeof(double) * ny), *mz = malloc(sizeof(double) * nz);
+    dual_widths(x, nx, mx); dual_widths(y, ny, my); dual_widths(z, nz, mz);
+    int nq = (lmax_bc + 1) * (lmax_bc + 1);
+    for (int t = 0; t < nq; ++t) Q[t] = 0.0;
+    double S[25];
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double f = rho[IDX(i, j, k, nx, ny)];
+                if (f == 0.0) continue;
+                oracle_solid_harmonics(x[i] - c[0], y[j] - c[1], z[k] - c[2], S);
+                double v = mx[i] * my[j] * mz[k] * f;
+                for (int t = 0; t < nq; ++t) Q[t] += v * S[t];
+            }
+    free(mx); free(my); free(mz);
+}
+
+/* Dirichlet data on the six faces: the exterior field of the moments under
+ * Laplacian(V) = 4 pi rho, V(x) = -sum_lm 4 pi/(2l+1) Q_lm S_lm(x')/|x'|^(2l+1)
+ * with x' = x - c. bc_mode 0 writes zeros (eq. (3.3), V_C = 0 on the
+ * boundary). Interior nodes are left untouched. */
+void oracle_boundary_values(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                            int bc_mode, const double* Q, int lmax_bc, const double* c, double* v)
+{
+    double S[25];
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int face = (i == 0 || i == nx - 1 || j == 0 || j == ny - 1 || k == 0 || k == nz - 1);
+                if (!face) continue;
+                double val = 0.0;
+                if (bc_mode == 1) {
+                    double dx = x[i] - c[0], dy = y[j] - c[1], dz = z[k] - c[2];
+                    double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    oracle_solid_harmonics(dx, dy, dz, S);
+                    for (int l = 0; l <= lmax_bc; ++l)
+                        for (int m = -l; m <= l; ++m)
+                            val -= 4.0 * PI / (2.0 * l + 1.0) * Q[l * l + l + m] * S[l * l + l + m] / pow(r, 2 * l + 1);
+                }
+                v[IDX(i, j, k, nx, ny)] = val;
+            }
+}
+
+/* ------------------------------------------------------------ operator */
+
+/* One level of the discrete problem: per axis node coordinates, and for
+ * interior node i the coefficients am = 1/(h_{i-1} m_i), ap = 1/(h_i m_i) of
+ * the three-point second difference on a nonuniform mesh. */
+typedef struct {
+    int n[3];
+    double* x[3];
+    double* m[3];
+    double* am[3];
+    double* ap[3];
+    int* keep[3];     /* index in the next finer level of each node (NULL at level 0) */
+} olevel;
+
+static void level_init(olevel* L, double* const xs[3], const int n[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        int nd = n[d];
+        L->n[d] = nd;
+        L->x[d] = malloc(sizeof(double) * nd);
+        memcpy(L->x[d], xs[d], sizeof(double) * nd);
+        L->m[d] = malloc(sizeof(double) * nd);
+        dual_widths(L->x[d], nd, L->m[d]);
+        L->am[d] = calloc(nd, sizeof(double));
+        L->ap[d] = calloc(nd, sizeof(double));
+        for (int i = 1; i < nd - 1; ++i) {
+            L->am[d][i] = 1.0 / ((L->x[d][i] - L->x[d][i - 1]) * L->m[d][i]);
+            L->ap[d][i] = 1.0 / ((L->x[d][i + 1] - L->x[d][i]) * L->m[d][i]);
+        }
+        L->keep[d] = NULL;
+    }
+}
+
+static void level_free(olevel* L)
+{
+    for (int d = 0; d < 3; ++d) {
+        free(L->x[d]); free(L->m[d]); free(L->am[d]); free(L->ap[d]); free(L->keep[d]);
+    }
+}
+
+/* (A u)_n = sum_d am_d (u_{n-e_d} - u_n) + ap_d (u_{n+e_d} - u_n), interior n */
+static double apply_at(const olevel* L, const double* u, int i, int j, int k)
+{
+    int nx = L->n[0], ny = L->n[1];
+    double c = u[IDX(i, j, k, nx, ny)];
+    return L->am[0][i] * (u[IDX(i - 1, j, k, nx, ny)] - c) + L->ap[0][i] * (u[IDX(i + 1, j, k, nx, ny)] - c)
+         + L->am[1][j] * (u[IDX(i, j - 1, k, nx, ny)] - c) + L->ap[1][j] * (u[IDX(i, j + 1, k, nx, ny)] - c)
+         + L->am[2][k] * (u[IDX(i, j, k - 1, nx, ny)] - c) + L->ap[2][k] * (u[IDX(i, j, k + 1, nx, ny)] - c);
+}
+
+/* interior of Au; faces set to zero */
+void oracle_apply(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                  const double* u, double* Au)
+{
+    double* xs[3] = {(double*)x, (double*)y, (double*)z};
+    int n[3] = {nx, ny, nz};
+    olevel L;
+    level_init(&L, xs, n);
+    size_t N = (size_t)nx * ny * nz;
+    for (size_t t = 0; t < N; ++t) Au[t] = 0.0;
+    #pragma omp parallel for
+    for (int k = 1; k < nz - 1; ++k)
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i) Au[IDX(i, j, k, nx, ny)] = apply_at(&L, u, i, j, k);
+    level_free(&L);
+}
+
+/* residual r = b - A u at interior nodes, zero on faces */
+static void residual(const olevel* L, const double* u, const double* b, double* r)
+{
+    int nx = L->n[0], ny = L->n[1], nz = L->n[2];
+    #pragma omp parallel for
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t t = IDX(i, j, k, nx, ny);
+                if (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1) r[t] = 0.0;
+                else r[t] = b[t] - apply_at(L, u, i, j, k);
+            }
+}
+
+/* W-norm: sqrt(sum_n vol_n v_n^2) over interior nodes, summed in index order */
+static double wnorm(const olevel* L, const double* v)
+{
+    int nx = L->n[0], ny = L->n[1], nz = L->n[2];
+    double s = 0.0;
+    for (int k = 1; k < nz - 1; ++k)
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i) {
+                double a = v[IDX(i, j, k, nx, ny)];
+                s += L->m[0][i] * L->m[1][j] * L->m[2][k] * a * a;
+            }
+    return sqrt(s);
+}
+
+/* Gauss-Seidel on one colour: nodes with (i+j+k) % 2 == colour solve their own
+ * equation with the current neighbour values. */
+static void gs_colour(const olevel* L, double* u, const double* b, int colour)
+{
+    int nx = L->n[0], ny = L->n[1], nz = L->n[2];
+    #pragma omp parallel for
+    for (int k = 1; k < nz - 1; ++k)
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i) {
+                if ((i + j + k) % 2 != colour) continue;
+                double s = L->am[0][i] * u[IDX(i - 1, j, k, nx, ny)] + L->ap[0][i] * u[IDX(i + 1, j, k, nx, ny)]
+                         + L->am[1][j] * u[IDX(i, j - 1, k, nx, ny)] + L->ap[1][j] * u[IDX(i, j + 1, k, nx, ny)]
+                         + L->am[2][k] * u[IDX(i, j, k - 1, nx, ny)] + L->ap[2][k] * u[IDX(i, j, k + 1, nx, ny)];
+                double d = L->am[0][i] + L->ap[0][i] + L->am[1][j] + L->ap[1][j] + L->am[2][k] + L->ap[2][k];
+                u[IDX(i, j, k, nx, ny)] = (s - b[IDX(i, j, k, nx, ny)]) / d;
+            }
+}
+
+/* --------------------------------------------------------- hierarchy */
+
+/* Coarsening reading (the paper names multigrid only): per axis, walking from
+ * the low end, the pair of cells [x_i, x_{i+2}] merges (node i+1 dropped) when
+ * x_{i+2} - x_i <= theta * hmin_level, hmin_level being the smallest spacing
+ * of the level over all three axes; if no axis can merge anything, every pair
+ * whose merged width is <= 2 hmax_level merges (standard coarsening). An axis
+ * with 3 nodes is not coarsened. Returns the number of kept nodes. */
+static int coarsen_axis(const double* x, int n, double tau, int* keep)
+{
+    int nk = 0, i = 0;
+    keep[nk++] = 0;
+    if (n <= 3) {
+        for (int t = 1; t < n; ++t) keep[nk++] = t;
+        return nk;
+    }
+    while (i < n - 1) {
+        if (i + 2 <= n - 1 && x[i + 2] - x[i] <= tau) { keep[nk++] = i + 2; i += 2; }
+        else { keep[nk++] = i + 1; i += 1; }
+    }
+    return nk;
+}
+
+typedef struct {
+    int nlev;
+    olevel lev[64];
+} ohier;
+
+static void hier_build(ohier* H, double* const xs[3], const int n[3], double theta, int coarse_max)
+{
+    H->nlev = 0;
+    level_init(&H->lev[0], xs, n);
+    H->nlev = 1;
+    for (;;) {
+        olevel* F = &H->lev[H->nlev - 1];
+        if (F->n[0] <= coarse_max && F->n[1] <= coarse_max && F->n[2] <= coarse_max) break;
+        if (H->nlev == 64) break;
+        double hmin = 1e300, hmax = 0.0;
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i + 1 < F->n[d]; ++i) {
+                double h = F->x[d][i + 1] - F->x[d][i];
+                if (h < hmin) hmin = h;
+                if (h > hmax) hmax = h;
+            }
+        int* kp[3];
+        int nk[3];
+        int changed = 0;
+        for (int d = 0; d < 3; ++d) {
+            kp[d] = malloc(sizeof(int) * F->n[d]);
+            nk[d] = coarsen_axis(F->x[d], F->n[d], theta * hmin * (1.0 + 1e-12), kp[d]);
+            if (nk[d] < F->n[d]) changed = 1;
+        }
+        if (!changed)
+            for (int d = 0; d < 3; ++d) nk[d] = coarsen_axis(F->x[d], F->n[d], 2.0 * hmax * (1.0 + 1e-12), kp[d]);
+        double* cx[3];
+        for (int d = 0; d < 3; ++d) {
+            cx[d] = malloc(sizeof(double) * nk[d]);
+            for (int t = 0; t < nk[d]; ++t) cx[d][t] = F->x[d][kp[d][t]];
+        }
+        olevel* C = &H->lev[H->nlev];
+        level_init(C, cx, nk);
+        for (int d = 0; d < 3; ++d) { C->keep[d] = kp[d]; free(cx[d]); }
+        H->nlev++;
+    }
+}
+
+static void hier_free(ohier* H)
+{
+    for (int l = 0; l < H->nlev; ++l) level_free(&H->lev[l]);
+}
+
+/* 1-D linear interpolation in physical coordinates from a coarse axis to a
+ * fine axis: P[i][c]. Kept fine node -> weight 1 on its coarse node; a
+ * dropped node between coarse c and c+1 -> (x_{c+1}-x_i)/(x_{c+1}-x_c) on c
+ * and the rest on c+1. Stored densely (tiny 1-D matrices). */
+static double* interp_matrix(const olevel* F, const olevel* C, int d)
+{
+    int nf = F->n[d], nc = C->n[d];
+    double* P = calloc((size_t)nf * nc, sizeof(double));
+    const int* keep = C->keep[d];
+    for (int c = 0; c < nc; ++c) P[(size_t)keep[c] * nc + c] = 1.0;
+    for (int c = 0; c + 1 < nc; ++c) {
+        int a = keep[c], b = keep[c + 1];
+        for (int i = a + 1; i < b; ++i) {
+            double w = (F->x[d][b] - F->x[d][i]) / (F->x[d][b] - F->x[d][a]);
+            P[(size_t)i * nc + c] = w;
+            P[(size_t)i * nc + c + 1] = 1.0 - w;
+        }
+    }
+    return P;
+}
+
+/* restriction r_c = M_c^-1 P^T M_f r (tensor product), the adjoint of the
+ * interpolation in the volume-weighted inner product; coarse faces zero */
+static void restrict_full(const olevel* F, const olevel* C, const double* r, double* rc)
+{
+    double* P[3];
+    for (int d = 0; d < 3; ++d) P[d] = interp_matrix(F, C, d);
+    int fnx = F->n[0], fny = F->n[1], fnz = F->n[2];
+    int cnx = C->n[0], cny = C->n[1], cnz = C->n[2];
+    #pragma omp parallel for
+    for (int K = 0; K < cnz; ++K)
+        for (int J = 0; J < cny; ++J)
+            for (int I = 0; I < cnx; ++I) {
+                size_t t = IDX(I, J, K, cnx, cny);
+                if (I == 0 || J == 0 || K == 0 || I == cnx - 1 || J == cny - 1 || K == cnz - 1) { rc[t] = 0.0; continue; }
+                double s = 0.0;
+                int fi = C->keep[0][I], fj = C->keep[1][J], fk = C->keep[2][K];
+                for (int k = fk - 1; k <= fk + 1; ++k) {
+                    double wz = P[2][(size_t)k * cnz + K];
+                    if (wz == 0.0) continue;
+                    for (int j = fj - 1; j <= fj + 1; ++j) {
+                        double wy = P[1][(size_t)j * cny + J];
+                        if (wy == 0.0) continue;
+                        for (int i = fi - 1; i <= fi + 1; ++i) {
+                            double wx = P[0][(size_t)i * cnx + I];
+                            if (wx == 0.0) continue;
+                            s += wx * F->m[0][i] * wy * F->m[1][j] * wz * F->m[2][k] * r[IDX(i, j, k, fnx, fny)];
+                        }
+                    }
+                }
+                rc[t] = s / (C->m[0][I] * C->m[1][J] * C->m[2][K]);
+            }
+    (void)fnz;
+    for (int d = 0; d < 3; ++d) free(P[d]);
+}
+
+/* u_f += P e_c (tensor product of the 1-D interpolations) at fine interior */
+static void prolong_add(const olevel* F, const olevel* C, const double* e, double* u)
+{
+    double* P[3];
+    for (int d = 0; d < 3; ++d) P[d] = interp_matrix(F, C, d);
+    int nx = F->n[0], ny = F->n[1], nz = F->n[2];
+    int cnx = C->n[0], cny = C->n[1], cnz = C->n[2];
+    /* lo[d][i]: the coarse node at or left of fine node i; only it and the
+     * next coarse node carry nonzero weights in row i of P_d */
+    int* lo[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = malloc(sizeof(int) * F->n[d]);
+        int c = 0;
+        for (int i = 0; i < F->n[d]; ++i) {
+            while (c + 1 < C->n[d] && C->keep[d][c + 1] <= i) ++c;
+            lo[d][i] = c;
+        }
+    }
+    #pragma omp parallel for
+    for (int k = 1; k < nz - 1; ++k)
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i) {
+                double s = 0.0;
+                for (int K = lo[2][k]; K <= lo[2][k] + 1 && K < cnz; ++K) {
+                    double wz = P[2][(size_t)k * cnz + K];
+                    if (wz == 0.0) continue;
+                    for (int J = lo[1][j]; J <= lo[1][j] + 1 && J < cny; ++J) {
+                        double wy = P[1][(size_t)j * cny + J];
+                        if (wy == 0.0) continue;
+                        for (int I = lo[0][i]; I <= lo[0][i] + 1 && I < cnx; ++I) {
+                            double wx = P[0][(size_t)i * cnx + I];
+                            if (wx == 0.0) continue;
+                            s += wx * wy * wz * e[IDX(I, J, K, cnx, cny)];
+                        }
+                    }
+                }
+                u[IDX(i, j, k, nx, ny)] += s;
+            }
+    for (int d = 0; d < 3; ++d) { free(P[d]); free(lo[d]); }
+}
+
+/* coarsest level: Gaussian elimination with partial pivoting on the interior
+ * unknowns (faces hold the given values) */
+static int coarse_direct(const olevel* L, double* u, const double* b)
+{
+    int nx = L->n[0], ny = L->n[1], nz = L->n[2];
+    int ni = nx - 2, nj = ny - 2, nk = nz - 2;
+    int N = ni * nj * nk;
+    if (N <= 0) return 0;
+    double* A = calloc((size_t)N * (N + 1), sizeof(double));
+    for (int k = 1; k < nz - 1; ++k)
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i) {
+                int row = ((k - 1) * nj + (j - 1)) * ni + (i - 1);
+                double* Ar = A + (size_t)row * (N + 1);
+                double rhs = b[IDX(i, j, k, nx, ny)];
+                int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+                double cf[6] = {L->am[0][i], L->ap[0][i], L->am[1][j], L->ap[1][j], L->am[2][k], L->ap[2][k]};
+                double diag = 0.0;
+                for (int t = 0; t < 6; ++t) {
+                    diag += cf[t];
+                    int a = nb[t][0], bb = nb[t][1], c = nb[t][2];
+                    if (a == 0 || bb == 0 || c == 0 || a == nx - 1 || bb == ny - 1 || c == nz - 1)
+                        rhs -= cf[t] * u[IDX(a, bb, c, nx, ny)];
+                    else
+                        Ar[((c - 1) * nj + (bb - 1)) * ni + (a - 1)] += cf[t];
+                }
+                Ar[row] -= diag;
+                Ar[N] = rhs;
+            }
+    for (int c = 0; c < N; ++c) {
+        int p = c;
+        for (int r = c + 1; r < N; ++r)
+            if (fabs(A[(size_t)r * (N + 1) + c]) > fabs(A[(size_t)p * (N + 1) + c])) p = r;
+        if (p != c)
+            for (int t = 0; t <= N; ++t) {
+                double tmp = A[(size_t)c * (N + 1) + t];
+                A[(size_t)c * (N + 1) + t] = A[(size_t)p * (N + 1) + t];
+                A[(size_t)p * (N + 1) + t] = tmp;
+            }
+        double piv = A[(size_t)c * (N + 1) + c];
+        for (int r = c + 1; r < N; ++r) {
+            double f = A[(size_t)r * (N + 1) + c] / piv;
+            if (f == 0.0) continue;
+            for (int t = c; t <= N; ++t) A[(size_t)r * (N + 1) + t] -= f * A[(size_t)c * (N + 1) + t];
+        }
+    }
+    double* sol = malloc(sizeof(double) * N);
+    for (int r = N - 1; r >= 0; --r) {
+        double s = A[(size_t)r * (N + 1) + N];
+        for (int t = r + 1; t < N; ++t) s -= A[(size_t)r * (N + 1) + t] * sol[t];
+        sol[r] = s / A[(size_t)r * (N + 1) + r];
+    }
+    for (int k = 1; k < nz - 1; ++k)
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i)
+                u[IDX(i, j, k, nx, ny)] = sol[((k - 1) * nj + (j - 1)) * ni + (i - 1)];
+    free(sol); free(A);
+    return 0;
+}
+
+/* V(nu1, nu2) cycle on A u = b at level l: nu1 sweeps (red then black), the
+ * restricted residual solved recursively from zero with zero faces, the
+ * interpolated correction added, nu2 sweeps (black then red). */
+static void vcycle(const ohier* H, int l, double* u, const double* b, int nu1, int nu2)
+{
+    const olevel* F = &H->lev[l];
+    if (l == H->nlev - 1) { coarse_direct(F, u, b); return; }
+    for (int s = 0; s < nu1; ++s) { gs_colour(F, u, b, 0); gs_colour(F, u, b, 1); }
+    size_t Nf = (size_t)F->n[0] * F->n[1] * F->n[2];
+    const olevel* C = &H->lev[l + 1];
+    size_t Nc = (size_t)C->n[0] * C->n[1] * C->n[2];
+    double* r = malloc(sizeof(double) * Nf);
+    double* rc = malloc(sizeof(double) * Nc);
+    double* ec = calloc(Nc, sizeof(double));
+    residual(F, u, b, r);
+    restrict_full(F, C, r, rc);
+    vcycle(H, l + 1, ec, rc, nu1, nu2);
+    prolong_add(F, C, ec, u);
+    for (int s = 0; s < nu2; ++s) { gs_colour(F, u, b, 1); gs_colour(F, u, b, 0); }
+    free(r); free(rc); free(ec);
+}
+
+/* Level sizes of the hierarchy (for tests): writes nlev*3 ints. */
+int oracle_hierarchy_sizes(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                           double theta, int coarse_max, int* sizes, int max_levels)
+{
+    double* xs[3] = {(double*)x, (double*)y, (double*)z};
+    int n[3] = {nx, ny, nz};
+    ohier* H = malloc(sizeof(ohier));
+    hier_build(H, xs, n, theta, coarse_max);
+    int nl = H->nlev;
+    for (int l = 0; l < nl && l < max_levels; ++l)
+        for (int d = 0; d < 3; ++d) sizes[3 * l + d] = H->lev[l].n[d];
+    hier_free(H);
+    free(H);
+    return nl;
+}
+
+/* Solve A u = 4 pi rho (eq. (3.2)) with the face values already in v. The
+ * interior of v is the initial guess; on return v holds the iterate.
+ * Stopping rule: ||b - A u||_W <= rtol ||b - A u_bc||_W, u_bc = faces of v
+ * with a zero interior (a guess-independent reference).
+ * Returns cycles run; *rel receives the final relative residual. */
+int oracle_solve(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                 const double* rho, double* v, double rtol, int max_cycles, int nu1, int nu2,
+                 double theta, int coarse_max, double* rel, double* hist)
+{
+    double* xs[3] = {(double*)x, (double*)y, (double*)z};
+    int n[3] = {nx, ny, nz};
+    ohier* H = malloc(sizeof(ohier));
+    hier_build(H, xs, n, theta, coarse_max);
+    const olevel* F = &H->lev[0];
+    size_t N = (size_t)nx * ny * nz;
+    double* b = malloc(sizeof(double) * N);
+    double* r = malloc(sizeof(double) * N);
+    double* ubc = malloc(sizeof(double) * N);
+    for (size_t t = 0; t < N; ++t) b[t] = 4.0 * PI * rho[t];
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t t = IDX(i, j, k, nx, ny);
+                int face = (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1);
+                ubc[t] = face ? v[t] : 0.0;
+            }
+    residual(F, ubc, b, r);
+    double r0 = wnorm(F, r);
+    residual(F, v, b, r);
+    double rn = wnorm(F, r);
+    int cyc = 0;
+    double relv = (r0 > 0.0) ? rn / r0 : 0.0;
+    while (relv > rtol && cyc < max_cycles) {
+        vcycle(H, 0, v, b, nu1, nu2);
+        residual(F, v, b, r);
+        rn = wnorm(F, r);
+        relv = (r0 > 0.0) ? rn / r0 : 0.0;
+        if (hist && cyc < 128) hist[cyc] = relv;
+        ++cyc;
+    }
+    *rel = relv;
+    free(b); free(r); free(ubc);
+    hier_free(H);
+    free(H);
+    return cyc;
+}
+
+/* W-norm relative residual of a given v (faces = Dirichlet data) */
+double oracle_rel_residual(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                           const double* rho, const double* v)
+{
+    double* xs[3] = {(double*)x, (double*)y, (double*)z};
+    int n[3] = {nx, ny, nz};
+    olevel L;
+    level_init(&L, xs, n);
+    size_t N = (size_t)nx * ny * nz;
+    double* b = malloc(sizeof(double) * N);
+    double* r = malloc(sizeof(double) * N);
+    double* ubc = malloc(sizeof(double) * N);
+    for (size_t t = 0; t < N; ++t) b[t] = 4.0 * PI * rho[t];
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t t = IDX(i, j, k, nx, ny);
+                int face = (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1);
+                ubc[t] = face ? v[t] : 0.0;
+            }
+    residual(&L, ubc, b, r);
+    double r0 = wnorm(&L, r);
+    residual(&L, v, b, r);
+    double rn = wnorm(&L, r);
+    free(b); free(r); free(ubc);
+    level_free(&L);
+    return r0 > 0.0 ? rn / r0 : rn;
+}
+
+/* ----------------------------------------------------- interpolation */
+
+/* V_C at arbitrary points by tricubic Lagrange interpolation (the paper
+ * interpolates the grid solution onto the sphere boundaries, Section 1 and
+ * eq. (3.5)-(3.6)). Per axis the 4-node window starts at
+ * clamp(upper_bound(x, p) - 2, 0, n - 4). */
+static int window(const double* x, int n, double p)
+{
+    int ub = 0;
+    while (ub < n && x[ub] <= p) ++ub;   /* first node > p */
+    int i0 = ub - 2;
+    if (i0 < 0) i0 = 0;
+    if (i0 > n - 4) i0 = n - 4;
+    return i0;
+}
+
+static void lagrange4(const double* x, int i0, double p, double* w)
+{
+    for (int a = 0; a < 4; ++a) {
+        double num = 1.0, den = 1.0;
+        for (int b = 0; b < 4; ++b) {
+            if (b == a) continue;
+            num *= (p - x[i0 + b]);
+            den *= (x[i0 + a] - x[i0 + b]);
+        }
+        w[a] = num / den;
+    }
+}
+
+int oracle_interp(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                  const double* v, int npts, const double* pts, double* out)
+{
+    if (nx < 4 || ny < 4 || nz < 4) return 1;
+    for (int p = 0; p < npts; ++p) {
+        double px = pts[3 * p], py = pts[3 * p + 1], pz = pts[3 * p + 2];
+        int i0 = window(x, nx, px), j0 = window(y, ny, py), k0 = window(z, nz, pz);
+        double wx[4], wy[4], wz[4];
+        lagrange4(x, i0, px, wx);
+        lagrange4(y, j0, py, wy);
+        lagrange4(z, k0, pz, wz);
+        double s = 0.0;
+        for (int c = 0; c < 4; ++c)
+            for (int b = 0; b < 4; ++b)
+                for (int a = 0; a < 4; ++a)
+                    s += wx[a] * wy[b] * wz[c] * v[IDX(i0 + a, j0 + b, k0 + c, nx, ny)];
+        out[p] = s;
+    }
+    return 0;
+}
