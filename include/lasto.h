@@ -1,0 +1,227 @@
+/*
+ * lasto.h -- C ABI of the MI355X (gfx950) Hartree step of the LASTO method.
+ *
+ * Paper: Kang, Davenport, Glimm, Keyes, McGuigan, "Linear Augmented
+ * Slater-Type Orbital Method for Free Standing Clusters".
+ *
+ * The Hartree step (the paper's "computation of the potential", Section 3):
+ *   1. a smoothed monopole pseudo-density with the charge of the true sphere
+ *      density, plus the non-spherical terms put directly on the grid
+ *      (Section 1; eq. (3.2) and the three constraints under it);
+ *   2. a finite-difference multigrid solution of the Poisson problem
+ *      Laplacian(V_C) = 4 pi rho~ (eq. (3.2)) on a graded tensor-product mesh
+ *      (Section 3: finite adaptive domain, Dirichlet data at its edge; the
+ *      edge data is the multipole field of the source, or zero as in
+ *      eq. (3.3));
+ *   3. interpolation of V_C onto the atom-sphere boundaries as Dirichlet
+ *      data for the interior problem (Section 1; eq. (3.5)-(3.6)).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns a lasto_status; no C++ exception crosses the ABI.
+ *     On failure lasto_last_error() returns a thread-local message.
+ *   - Grid arrays are dense FP64 [nz][ny][nx], x fastest, boundary nodes
+ *     included, in device memory owned by the caller (for example a torch
+ *     tensor's data_ptr()). The library never frees caller memory.
+ *   - Lengths in bohr, charges in e, potentials in hartree; the equation is
+ *     solved with the sign of eq. (3.2): Laplacian(V) = +4 pi rho, so a
+ *     positive charge q gives V -> -q/r.
+ *   - All device work is enqueued on the grid's HIP stream, ordered after the
+ *     caller's earlier work on that stream. lasto_poisson_solve and
+ *     lasto_sphere_interp return only after their work has completed.
+ *   - A grid owns its multigrid hierarchy and scratch; it is not thread-safe
+ *     (use one grid per host thread).
+ */
+#ifndef LASTO_H
+#define LASTO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lasto_grid_s* lasto_grid;
+
+typedef enum {
+    LASTO_OK = 0,
+    LASTO_ERR_ARG = 1,            /* invalid argument (sizes, NaN, ordering, NULL) */
+    LASTO_ERR_ALLOC = 2,          /* device or host allocation failed */
+    LASTO_ERR_HIP = 3,            /* a HIP runtime call or kernel launch failed */
+    LASTO_ERR_NOT_CONVERGED = 4,  /* tolerance not met within max_iters; v and info hold the last iterate */
+    LASTO_ERR_DIVERGED = 5,       /* residual became NaN/Inf or grew; v holds the last finite iterate */
+    LASTO_ERR_STATE = 6           /* call not valid in the current state */
+} lasto_status;
+
+/* Text of a status code (static storage). */
+const char* lasto_status_string(lasto_status s);
+/* Detail of the last failure on this host thread ("" if none). */
+const char* lasto_last_error(void);
+
+/*
+ * Graded 1-D node coordinates (host only, no device work).
+ *
+ * Section 3 asks for a finite domain with fine meshes near the atoms and
+ * coarse meshes far from them, without fixing a rule. The rule used here:
+ * spacing h(x) = min(hmax, hmin + (g - 1) d(x)), d(x) the distance to the
+ * nearest entry of `planes` (atom coordinates on this axis); the node map
+ * xi(x) = int_lo^x dt/h(t) is integrated in closed form, g in (1, gmax] is
+ * found by bisection so that xi(hi) = n - 1 (g = 1 when even hmin leaves
+ * nodes to spare), and node i is placed at xi^-1(i xi(hi)/(n-1)); x[0] = lo
+ * and x[n-1] = hi exactly. With n_planes = 0 the nodes are uniform.
+ * If no g <= gmax fits and hmin_step > 0, hmin is raised by hmin_step until
+ * one does (hmin_used reports it).
+ *   x_out [n] host, caller-owned. g_out, hmin_used may be NULL.
+ * Errors: LASTO_ERR_ARG for n < 3, hi <= lo, hmin <= 0, hmax < hmin,
+ * gmax <= 1, or an infeasible request.
+ */
+lasto_status lasto_mesh_graded_1d(double lo, double hi, int n, const double* planes, int n_planes,
+                                  double hmin, double hmax, double gmax, double hmin_step,
+                                  double* x_out, double* g_out, double* hmin_used);
+
+/*
+ * Create a grid on the tensor-product mesh x[nx] * y[ny] * z[nz] (host
+ * arrays, strictly increasing, each n >= 4), build the multigrid hierarchy
+ * and allocate its device scratch on the current HIP device.
+ *   hip_stream: a hipStream_t (NULL = the default stream) on which all of
+ *   this grid's work runs.
+ *   n_batch: number of right-hand sides a batched solve may carry (>= 1).
+ * The hierarchy: per axis, a pair of cells merges (its middle node is
+ * dropped) when its merged width is at most 4 times the level's smallest
+ * spacing; when no axis can merge, every pair merges. Coarsening stops when
+ * every axis has at most 5 nodes.
+ * Errors: LASTO_ERR_ARG (sizes, ordering, NaN), LASTO_ERR_ALLOC, LASTO_ERR_HIP.
+ */
+lasto_status lasto_grid_create(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                               int n_batch, void* hip_stream, lasto_grid* out);
+lasto_status lasto_grid_destroy(lasto_grid g);
+/* Number of levels and the node counts of level l (out[3] = nx, ny, nz). */
+lasto_status lasto_grid_levels(lasto_grid g, int* n_levels);
+lasto_status lasto_grid_level_shape(lasto_grid g, int level, int* out3);
+
+/*
+ * One atom of the pseudo-density (host struct, passed by pointer).
+ * kind 0: monopole q s (pi w^2)^(-3/2) exp(-r^2/w^2) for r < 7 w, with s
+ *         making the discrete charge sum_n vol_n rho_n exactly q when
+ *         renormalize != 0 (s = 1 otherwise); vol_n is the product of the
+ *         nodes' dual widths.
+ * kind 1: the paper's pseudo-density (eq. (3.2) and its constraints): inside
+ *         R the even quartic a + b r^2 + c r^4 with 4 pi int_0^R rho~ r^2 dr = q,
+ *         rho~(R) = rho_R and rho~'(R) = drho_R; zero outside R.
+ * Both kinds add the non-spherical terms directly on the grid:
+ *         sum_{l=1..lmax} sum_m clm[l*l+l+m-1] r^l y_lm exp(-alpha r^2) for
+ *         alpha r^2 < 42.25, y_lm the real orthonormal harmonics of eq. (3.1)
+ *         without the Condon-Shortley phase (lmax <= 4, the paper's L <= 4).
+ */
+typedef struct {
+    double center[3];
+    double radius;     /* sphere radius R (kind 1 support; interpolation radius) */
+    double q;          /* charge of the monopole part */
+    int kind;          /* 0 Gaussian, 1 quartic */
+    int lmax;          /* 0..4 */
+    double width;      /* kind 0: w */
+    double rho_R;      /* kind 1: spherical density at R */
+    double drho_R;     /* kind 1: its radial derivative at R */
+    double alpha;      /* radial factor of the l >= 1 terms */
+    double clm[24];    /* (l,m) = (1,-1),(1,0),(1,1),(2,-2),...,(4,4); unused entries ignored */
+} lasto_atom;
+
+/*
+ * Pseudo-density on every grid node (Section 1 and eq. (3.2)).
+ *   atoms: host array [n_atoms].
+ *   rho_interstitial: device [nz][ny][nx] added at nodes outside every
+ *     sphere (|x - C_a| >= R_a), or NULL.
+ *   rho_out: device [nz][ny][nx], overwritten.
+ *   moments_out: host [25] (l <= 4 moments about the box centre, see
+ *     lasto_poisson_solve) or NULL.
+ * Errors: LASTO_ERR_ARG (lmax > 4, kind not 0/1, width <= 0, NaN), LASTO_ERR_HIP.
+ */
+lasto_status lasto_pseudo_density(lasto_grid g, int n_atoms, const lasto_atom* atoms,
+                                  const double* rho_interstitial, int renormalize,
+                                  double* rho_out, double* moments_out);
+
+typedef struct {
+    double rtol;        /* stop when ||b - A v||_W <= rtol ||b - A v_bc||_W (default 1e-10) */
+    int max_iters;      /* outer iterations (PCG steps or V-cycles), default 100 */
+    int nu1, nu2;       /* pre/post red-black sweeps per level (default 2, 2) */
+    int method;         /* 0 MG-preconditioned CG (default), 1 plain V-cycle iteration */
+    int precision;      /* 0 FP64 throughout (default); 1 FP32 V-cycles inside FP64 refinement */
+    int inner_iters;    /* precision 1: FP32 PCG steps per FP64 refinement (default 6) */
+    int guess;          /* 0 use the interior of v as given (default), 1 zero interior */
+    int bc;             /* 0 zero faces (eq. (3.3)), 1 multipole faces (default), 2 faces of v as given */
+    int lmax_bc;        /* multipole order of the face values, 0..4 (default 4) */
+    int debug_nan_iter; /* >= 0: inject a NaN into the residual at that iteration (tests only); default -1 */
+    int profile;        /* 1: time every finest-level smoother launch with HIP events (default 0) */
+} lasto_solve_opts;
+
+typedef struct {
+    int iters;              /* outer iterations run */
+    int vcycles;            /* V-cycles run (all precisions) */
+    int refinements;        /* FP64 refinement steps (precision 1) */
+    double rel_resid;       /* true ||b - A v||_W / ||b - A v_bc||_W at exit */
+    double resid_hist[128]; /* relative residual after each outer iteration */
+    double moments[25];     /* Q_lm used for the face values (bc = 1) */
+    double ms_total;        /* wall time of the call, ms */
+    /* profile = 1: finest-level red-black sweeps (the dominant kernel) */
+    int smooth_launches;    /* sweeps timed */
+    double smooth_ms;       /* summed event-timed duration of those sweeps, ms */
+    double smooth_bytes;    /* their algorithmic HBM bytes: (read u, f + write u) per interior node */
+    int smooth_fp32;        /* launches among them that ran in FP32 */
+} lasto_solve_info;
+
+void lasto_solve_opts_default(lasto_solve_opts* o);
+
+/*
+ * Solve eq. (3.2), Laplacian(V_C) = 4 pi rho, on the grid by finite
+ * differences and multigrid (Section 3).
+ *   rho: device [nz][ny][nx] source.
+ *   v: device [nz][ny][nx], in: initial guess (interior) and, for bc = 2,
+ *      the face values; out: the iterate, faces holding the Dirichlet data.
+ * Discretisation: at interior node n, sum over axes of
+ *   [(v_{n+e} - v_n)/h_+ - (v_n - v_{n-e})/h_-] / m = 4 pi rho_n,
+ * h_-/h_+ the adjacent spacings and m = (h_- + h_+)/2.
+ * Face values for bc = 1: V(x) = -sum_{l<=lmax_bc, m} 4 pi/(2l+1) Q_lm
+ * r^l y_lm(x') / |x'|^(2l+1), x' = x - c, Q_lm = sum_n vol_n rho_n
+ * r_n^l y_lm(x_n - c), c the box centre.
+ * W-norm: ||r||_W^2 = sum over interior nodes of vol_n r_n^2.
+ * Returns LASTO_OK, or LASTO_ERR_NOT_CONVERGED / LASTO_ERR_DIVERGED with v
+ * and info filled, or LASTO_ERR_ARG / LASTO_ERR_HIP.
+ */
+lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, double* v,
+                                 const lasto_solve_opts* opts, lasto_solve_info* info);
+
+/*
+ * V_C on the sphere boundaries (Section 1; eq. (3.5)-(3.6)): the value at
+ * C_a + R_a d_k for every atom a and direction d_k, by tricubic Lagrange
+ * interpolation of the grid values (per axis the 4-node window starts at
+ * clamp(upper_bound(x, p) - 2, 0, n - 4)).
+ *   v: device grid values. centers: host [n_atoms][3]. radii: host [n_atoms].
+ *   dirs: host [n_dir][3] unit vectors, or NULL for the default 64 (8
+ *     Gauss-Legendre nodes in cos(theta) times 8 azimuths 2 pi (b + 1/2)/8,
+ *     theta-major; n_dir must then be 64).
+ *   out: host [n_atoms][n_dir].
+ * Errors: LASTO_ERR_ARG (a point outside the box, n_dir mismatch), LASTO_ERR_HIP.
+ */
+lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n_atoms, const double* centers,
+                                 const double* radii, int n_dir, const double* dirs, double* out);
+
+/*
+ * The discrete operator of eq. (3.2) on the finest level: Au[n] = (A u)_n at
+ * interior nodes (the three-point nonuniform second difference per axis, as
+ * in lasto_poisson_solve); faces of Au are left untouched.
+ *   u, Au: device [nz][ny][nx], distinct buffers.
+ * Errors: LASTO_ERR_ARG (NULL or aliasing), LASTO_ERR_HIP.
+ */
+lasto_status lasto_apply(lasto_grid g, const double* u, double* Au);
+
+/*
+ * One red-black Gauss-Seidel sweep on A u = 4 pi rho at the finest level,
+ * out of place: u_out = S(u_in). Nodes with (i+j+k) % 2 == first_colour are
+ * updated first from u_in, the other colour then from those new values.
+ * Faces of u_out are left untouched (copy them from u_in when needed).
+ * This is the smoother of the multigrid solve, exposed for testing.
+ *   u_in, rho, u_out: device [nz][ny][nx]; u_out must not alias u_in.
+ */
+lasto_status lasto_rb_sweep(lasto_grid g, const double* u_in, const double* rho, double* u_out, int first_colour);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LASTO_H */

@@ -60,6 +60,8 @@ def lib():
         L.oracle_rel_residual.restype = d
         L.oracle_interp.argtypes = [P, i, P, i, P, i, P, i, P, P]
         L.oracle_interp.restype = i
+        L.oracle_rb_sweep.argtypes = [P, i, P, i, P, i, P, P, i, P]
+        L.oracle_rb_sweep.restype = None
         L.oracle_hierarchy_sizes.argtypes = [P, i, P, i, P, i, d, i, P, i]
         L.oracle_hierarchy_sizes.restype = i
         _lib = L
@@ -177,6 +179,15 @@ def interp(xs, v, pts) -> np.ndarray:
     rc = lib().oracle_interp(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(_f64(v)), len(pts), _p(pts), _p(out))
     if rc != 0:
         raise ValueError("oracle_interp needs >= 4 nodes per axis")
+    return out
+
+
+def rb_sweep(xs, u, rho, first=0) -> np.ndarray:
+    """One red-black Gauss-Seidel sweep on A u = 4 pi rho (colour `first` first)."""
+    x, y, z = (_f64(a) for a in xs)
+    u = _f64(u)
+    out = np.zeros_like(u)
+    lib().oracle_rb_sweep(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(u), _p(_f64(rho)), int(first), _p(out))
     return out
 
 

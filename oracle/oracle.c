@@ -256,6 +256,7 @@ int oracle_pseudo_density(const double* x, int nx, const double* y, int ny, cons
                         if (r2 < cut * cut) sum += mx[i] * my[j] * mz[k] * norm * exp(-r2 / (w * w));
                     }
             double s = renormalize ? 1.0 / sum : 1.0;
+            #pragma omp parallel for
             for (int k = 0; k < nz; ++k)
                 for (int j = 0; j < ny; ++j)
                     for (int i = 0; i < nx; ++i) {
@@ -281,6 +282,7 @@ int oracle_pseudo_density(const double* x, int nx, const double* y, int ny, cons
                 }
             }
             double c0 = A[0][3] / A[0][0], c2 = A[1][3] / A[1][1], c4 = A[2][3] / A[2][2];
+            #pragma omp parallel for
             for (int k = 0; k < nz; ++k)
                 for (int j = 0; j < ny; ++j)
                     for (int i = 0; i < nx; ++i) {
@@ -292,10 +294,11 @@ int oracle_pseudo_density(const double* x, int nx, const double* y, int ny, cons
         if (lmax[a] >= 1) {
             double al = alpha[a], cut2 = 42.25 / al;
             const double* c = clm + 24 * (size_t)a;
-            double S[25];
+            #pragma omp parallel for
             for (int k = 0; k < nz; ++k)
                 for (int j = 0; j < ny; ++j)
                     for (int i = 0; i < nx; ++i) {
+                        double S[25];
                         double dx = x[i] - cx, dy = y[j] - cy, dz = z[k] - cz;
                         double r2 = dx * dx + dy * dy + dz * dz;
                         if (r2 >= cut2) continue;
@@ -307,6 +310,7 @@ int oracle_pseudo_density(const double* x, int nx, const double* y, int ny, cons
         }
     }
     if (rho_inter) {
+        #pragma omp parallel for
         for (int k = 0; k < nz; ++k)
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
@@ -876,4 +880,22 @@ int oracle_interp(const double* x, int nx, const double* y, int ny, const double
         out[p] = s;
     }
     return 0;
+}
+
+/* One red-black sweep on A u = 4 pi rho, written to out: nodes of parity
+ * `first` first, then the other colour (for kernel-level parity tests). */
+void oracle_rb_sweep(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                     const double* u, const double* rho, int first, double* out)
+{
+    double* xs[3] = {(double*)x, (double*)y, (double*)z};
+    int n[3] = {nx, ny, nz};
+    olevel L;
+    level_init(&L, xs, n);
+    size_t N = (size_t)nx * ny * nz;
+    double* b = malloc(sizeof(double) * N);
+    for (size_t t = 0; t < N; ++t) { b[t] = 4.0 * PI * rho[t]; out[t] = u[t]; }
+    gs_colour(&L, out, b, first);
+    gs_colour(&L, out, b, 1 - first);
+    free(b);
+    level_free(&L);
 }

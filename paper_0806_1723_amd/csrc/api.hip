@@ -1,0 +1,289 @@
+// C-ABI entry points: errors, the graded mesh helper, the pseudo-density
+// and the sphere-boundary interpolation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace lasto {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+lasto_status fail(lasto_status s, const std::string& msg)
+{
+    set_error(msg);
+    return s;
+}
+
+// ---------------------------------------------------------------- mesh
+// Spacing rule h(d) = min(hmax, hmin + (g-1) d), d = distance to the nearest
+// plane. Phi(d) = int_0^d dt/h(t) in closed form and its inverse.
+struct Spacing {
+    double g, hmin, hmax;
+    double dsat() const { return (hmax - hmin) / (g - 1.0); }
+    double phi(double d) const
+    {
+        if (g <= 1.0) return d / hmin;
+        const double ds = dsat();
+        if (d <= ds) return std::log1p((g - 1.0) * d / hmin) / (g - 1.0);
+        return std::log1p((g - 1.0) * ds / hmin) / (g - 1.0) + (d - ds) / hmax;
+    }
+    double phi_inv(double v) const
+    {
+        if (g <= 1.0) return v * hmin;
+        const double ds = dsat();
+        const double vs = std::log1p((g - 1.0) * ds / hmin) / (g - 1.0);
+        if (v <= vs) return hmin * std::expm1((g - 1.0) * v) / (g - 1.0);
+        return ds + (v - vs) * hmax;
+    }
+};
+
+// Pieces of [lo, hi] on which the distance to the nearest plane is linear:
+// breaks at planes and at midpoints between neighbouring planes.
+struct Piece {
+    double a, b, plane;
+};
+
+static std::vector<Piece> mesh_pieces(double lo, double hi, std::vector<double> planes)
+{
+    std::sort(planes.begin(), planes.end());
+    std::vector<double> br{lo};
+    for (size_t j = 0; j < planes.size(); ++j) {
+        if (j > 0) {
+            const double mid = 0.5 * (planes[j - 1] + planes[j]);
+            if (mid > br.back() && mid < hi) br.push_back(mid);
+        }
+        if (planes[j] > br.back() && planes[j] < hi) br.push_back(planes[j]);
+    }
+    br.push_back(hi);
+    std::vector<Piece> out;
+    for (size_t k = 0; k + 1 < br.size(); ++k) {
+        const double mid = 0.5 * (br[k] + br[k + 1]);
+        double best = planes[0];
+        for (double p : planes)
+            if (std::fabs(p - mid) < std::fabs(best - mid)) best = p;
+        out.push_back({br[k], br[k + 1], best});
+    }
+    return out;
+}
+
+static double piece_length(const Piece& P, const Spacing& S)
+{
+    return std::fabs(S.phi(std::fabs(P.b - P.plane)) - S.phi(std::fabs(P.a - P.plane)));
+}
+
+static double total_length(const std::vector<Piece>& pcs, const Spacing& S)
+{
+    double t = 0.0;
+    for (const Piece& P : pcs) t += piece_length(P, S);
+    return t;
+}
+
+}  // namespace lasto
+
+using namespace lasto;
+
+extern "C" const char* lasto_status_string(lasto_status s)
+{
+    switch (s) {
+    case LASTO_OK: return "ok";
+    case LASTO_ERR_ARG: return "invalid argument";
+    case LASTO_ERR_ALLOC: return "allocation failed";
+    case LASTO_ERR_HIP: return "HIP error";
+    case LASTO_ERR_NOT_CONVERGED: return "not converged";
+    case LASTO_ERR_DIVERGED: return "diverged";
+    case LASTO_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* lasto_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" lasto_status lasto_mesh_graded_1d(double lo, double hi, int n, const double* planes, int n_planes,
+                                             double hmin, double hmax, double gmax, double hmin_step, double* x_out,
+                                             double* g_out, double* hmin_used)
+{
+    if (!x_out || n < 3 || !(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi) || n_planes < 0 ||
+        (n_planes > 0 && !planes))
+        return fail(LASTO_ERR_ARG, "lasto_mesh_graded_1d: bad n, range or arrays");
+    if (n_planes == 0) {
+        for (int i = 0; i < n; ++i) x_out[i] = lo + (hi - lo) * (double)i / (double)(n - 1);
+        x_out[0] = lo;
+        x_out[n - 1] = hi;
+        if (g_out) *g_out = 1.0;
+        if (hmin_used) *hmin_used = (hi - lo) / (double)(n - 1);
+        return LASTO_OK;
+    }
+    if (!(hmin > 0.0) || hmax < hmin || !(gmax > 1.0))
+        return fail(LASTO_ERR_ARG, "lasto_mesh_graded_1d: need hmin > 0, hmax >= hmin, gmax > 1");
+    std::vector<double> pl(planes, planes + n_planes);
+    for (double p : pl)
+        if (!std::isfinite(p)) return fail(LASTO_ERR_ARG, "lasto_mesh_graded_1d: non-finite plane");
+    const std::vector<Piece> pcs = mesh_pieces(lo, hi, pl);
+    const double cells = (double)(n - 1);
+    Spacing S{1.0, hmin, hmax};
+    for (;;) {
+        S.g = 1.0;
+        if (total_length(pcs, S) <= cells) break;
+        S.g = gmax;
+        if (total_length(pcs, S) <= cells) {
+            double a = 1.0, b = gmax;
+            for (int it = 0; it < 200; ++it) {
+                const double m = 0.5 * (a + b);
+                if (m <= a || m >= b) break;
+                S.g = m;
+                if (total_length(pcs, S) > cells) a = m;
+                else b = m;
+            }
+            S.g = b;
+            break;
+        }
+        if (hmin_step <= 0.0 || S.hmin + hmin_step > hmax)
+            return fail(LASTO_ERR_ARG, "lasto_mesh_graded_1d: no growth factor <= gmax fits n nodes");
+        S.hmin += hmin_step;
+    }
+    const double T = total_length(pcs, S);
+    std::vector<double> start(pcs.size() + 1, 0.0);
+    for (size_t k = 0; k < pcs.size(); ++k) start[k + 1] = start[k] + piece_length(pcs[k], S);
+    x_out[0] = lo;
+    x_out[n - 1] = hi;
+    size_t k = 0;
+    for (int i = 1; i < n - 1; ++i) {
+        const double t = T * (double)i / (double)(n - 1);
+        while (k + 1 < pcs.size() && start[k + 1] < t) ++k;
+        const Piece& P = pcs[k];
+        const double pa = S.phi(std::fabs(P.a - P.plane));
+        double x;
+        if (P.plane <= P.a) x = P.plane + S.phi_inv(pa + (t - start[k]));
+        else x = P.plane - S.phi_inv(pa - (t - start[k]));
+        x_out[i] = std::min(std::max(x, P.a), P.b);
+    }
+    if (g_out) *g_out = S.g;
+    if (hmin_used) *hmin_used = S.hmin;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_pseudo_density(lasto_grid g, int n_atoms, const lasto_atom* atoms,
+                                             const double* rho_interstitial, int renormalize, double* rho_out,
+                                             double* moments_out)
+{
+    if (!g || !rho_out || n_atoms < 0 || (n_atoms > 0 && !atoms))
+        return fail(LASTO_ERR_ARG, "lasto_pseudo_density: NULL argument");
+    std::vector<AtomDev> hv((size_t)std::max(n_atoms, 1));
+    for (int a = 0; a < n_atoms; ++a) {
+        const lasto_atom& A = atoms[a];
+        AtomDev& D = hv[a];
+        std::memset(&D, 0, sizeof(D));
+        if (A.kind != 0 && A.kind != 1) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: kind must be 0 or 1");
+        if (A.lmax < 0 || A.lmax > 4) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: lmax must be 0..4");
+        if (A.kind == 0 && !(A.width > 0.0)) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: width must be > 0");
+        if (A.kind == 1 && !(A.radius > 0.0)) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: radius must be > 0");
+        if (A.lmax >= 1 && !(A.alpha > 0.0)) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: alpha must be > 0");
+        double chk = A.q + A.width + A.radius + A.alpha + A.rho_R + A.drho_R + A.center[0] + A.center[1] + A.center[2];
+        for (int c = 0; c < 24; ++c) chk += A.clm[c];
+        if (!std::isfinite(chk)) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: non-finite atom data");
+        for (int d = 0; d < 3; ++d) D.c[d] = A.center[d];
+        D.R = A.radius;
+        D.q = A.q;
+        D.w = A.width;
+        D.alpha = A.alpha;
+        D.rho_R = A.rho_R;
+        D.drho_R = A.drho_R;
+        D.kind = A.kind;
+        D.lmax = A.lmax;
+        for (int c = 0; c < 24; ++c) D.clm[c] = (c < (A.lmax + 1) * (A.lmax + 1) - 1) ? A.clm[c] : 0.0;
+    }
+    const size_t bytes = sizeof(AtomDev) * (size_t)std::max(n_atoms, 1);
+    if (bytes > g->stage_bytes) {
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipFree(g->stage);
+        g->stage = nullptr;
+        LASTO_HIP(hipMalloc(&g->stage, bytes));
+        g->stage_bytes = bytes;
+    }
+    AtomDev* dat = (AtomDev*)g->stage;
+    LASTO_HIP(hipMemcpyAsync(dat, hv.data(), bytes, hipMemcpyHostToDevice, g->stream));
+    if (n_atoms > 0) LASTO_HIP(launch_atom_prep(g, dat, n_atoms, renormalize));
+    LASTO_HIP(launch_pseudo(g, dat, n_atoms, rho_interstitial, rho_out));
+    if (moments_out) {
+        LASTO_HIP(launch_moments(g, rho_out, g->moments));
+        LASTO_HIP(hipMemcpyAsync(moments_out, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, g->stream));
+    }
+    // the staging buffer is reused by the next call: finish before returning
+    LASTO_HIP(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n_atoms, const double* centers,
+                                            const double* radii, int n_dir, const double* dirs, double* out)
+{
+    if (!g || !v || !out || n_atoms < 0 || (n_atoms > 0 && (!centers || !radii)))
+        return fail(LASTO_ERR_ARG, "lasto_sphere_interp: NULL argument");
+    std::vector<double> d;
+    if (dirs) {
+        if (n_dir < 1) return fail(LASTO_ERR_ARG, "lasto_sphere_interp: n_dir must be >= 1");
+        d.assign(dirs, dirs + 3 * (size_t)n_dir);
+    } else {
+        if (n_dir != 64) return fail(LASTO_ERR_ARG, "lasto_sphere_interp: default directions need n_dir = 64");
+        // 8 Gauss-Legendre nodes in cos(theta) (roots of P_8 by Newton) x 8 azimuths
+        double t[8];
+        for (int a = 0; a < 8; ++a) {
+            double xx = std::cos(kPi * (a + 0.75) / 8.5);
+            for (int it = 0; it < 100; ++it) {
+                double p0 = 1.0, p1 = xx;
+                for (int k = 2; k <= 8; ++k) {
+                    const double p2 = ((2.0 * k - 1.0) * xx * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                const double dp = 8.0 * (xx * p1 - p0) / (xx * xx - 1.0);
+                const double dx = p1 / dp;
+                xx -= dx;
+                if (std::fabs(dx) < 1e-16) break;
+            }
+            t[a] = xx;
+        }
+        std::sort(t, t + 8);
+        for (int a = 0; a < 8; ++a) {
+            const double st = std::sqrt(std::max(0.0, 1.0 - t[a] * t[a]));
+            for (int b = 0; b < 8; ++b) {
+                const double ph = 2.0 * kPi * (b + 0.5) / 8.0;
+                d.push_back(st * std::cos(ph));
+                d.push_back(st * std::sin(ph));
+                d.push_back(t[a]);
+            }
+        }
+    }
+    const size_t np = (size_t)n_atoms * n_dir;
+    if (np == 0) return LASTO_OK;
+    std::vector<double> pts(3 * np);
+    const Level& L0 = g->lev[0];
+    for (int a = 0; a < n_atoms; ++a)
+        for (int k = 0; k < n_dir; ++k) {
+            for (int c = 0; c < 3; ++c) {
+                const double p = centers[3 * a + c] + radii[a] * d[3 * k + c];
+                if (!std::isfinite(p) || p < L0.hx[c].front() || p > L0.hx[c].back())
+                    return fail(LASTO_ERR_ARG, "lasto_sphere_interp: point outside the box");
+                pts[3 * ((size_t)a * n_dir + k) + c] = p;
+            }
+        }
+    const size_t bytes = sizeof(double) * 4 * np;
+    if (bytes > g->stage_bytes) {
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipFree(g->stage);
+        g->stage = nullptr;
+        LASTO_HIP(hipMalloc(&g->stage, bytes));
+        g->stage_bytes = bytes;
+    }
+    double* dpts = g->stage;
+    double* dout = g->stage + 3 * np;
+    LASTO_HIP(hipMemcpyAsync(dpts, pts.data(), sizeof(double) * 3 * np, hipMemcpyHostToDevice, g->stream));
+    LASTO_HIP(launch_interp(g, v, dpts, (int)np, dout));
+    LASTO_HIP(hipMemcpyAsync(out, dout, sizeof(double) * np, hipMemcpyDeviceToHost, g->stream));
+    LASTO_HIP(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}

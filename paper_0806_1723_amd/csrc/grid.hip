@@ -1,0 +1,360 @@
+// Grid creation: the multigrid hierarchy of the graded tensor-product mesh,
+// its per-axis device tables, and the device work arrays.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace lasto {
+
+hipError_t init_harmonic_constants();
+template <typename T>
+hipError_t launch_fill_zero(T* a, size_t n, hipStream_t s);
+
+// Pair-merging coarsening of one axis: walking up from node 0, the pair of
+// cells [x_i, x_{i+2}] merges (node i+1 dropped) when x_{i+2} - x_i <= tau.
+// An axis with at most 3 nodes is kept as it is.
+static std::vector<int> coarsen_axis(const std::vector<double>& x, double tau)
+{
+    const int n = (int)x.size();
+    std::vector<int> keep;
+    keep.push_back(0);
+    if (n <= 3) {
+        for (int t = 1; t < n; ++t) keep.push_back(t);
+        return keep;
+    }
+    int i = 0;
+    while (i < n - 1) {
+        if (i + 2 <= n - 1 && x[i + 2] - x[i] <= tau) {
+            keep.push_back(i + 2);
+            i += 2;
+        } else {
+            keep.push_back(i + 1);
+            i += 1;
+        }
+    }
+    return keep;
+}
+
+static void dual_widths(const std::vector<double>& x, std::vector<double>& m)
+{
+    const int n = (int)x.size();
+    m.assign(n, 0.0);
+    m[0] = 0.5 * (x[1] - x[0]);
+    m[n - 1] = 0.5 * (x[n - 1] - x[n - 2]);
+    for (int i = 1; i < n - 1; ++i) m[i] = 0.5 * (x[i + 1] - x[i - 1]);
+}
+
+// Device table layout of level l (doubles): per axis d, am[n] ap[n] m[n] x[n]
+// rw[3n]; then, for l > 0, per axis pw[2 nf] (nf = the finer level's length).
+// Ints: per axis rf[n]; then, for l > 0, per axis pc[nf].
+lasto_status build_level_tables(lasto_grid g, int l)
+{
+    Level& L = g->lev[l];
+    size_t od_own[3], oi_own[3], od_fine[3], oi_fine[3];
+    size_t nd = 0, ni = 0;
+    for (int d = 0; d < 3; ++d) {
+        od_own[d] = nd;
+        oi_own[d] = ni;
+        nd += 7 * (size_t)L.n[d];
+        ni += (size_t)L.n[d];
+    }
+    for (int d = 0; d < 3; ++d) {
+        const size_t nf = l > 0 ? (size_t)g->lev[l - 1].n[d] : 0;
+        od_fine[d] = nd;
+        oi_fine[d] = ni;
+        nd += 2 * nf;
+        ni += nf;
+    }
+    std::vector<double> hd(nd, 0.0);
+    std::vector<int> hi(ni, 0);
+    LASTO_HIP(hipMalloc(&L.dtab, sizeof(double) * nd));
+    LASTO_HIP(hipMalloc(&L.dtabi, sizeof(int) * ni));
+    for (int d = 0; d < 3; ++d) {
+        const int n = L.n[d];
+        const std::vector<double>& x = L.hx[d];
+        std::vector<double> m;
+        dual_widths(x, m);
+        const size_t o = od_own[d];
+        double* am = &hd[o];
+        double* ap = &hd[o + n];
+        double* mm = &hd[o + 2 * n];
+        double* xx = &hd[o + 3 * n];
+        double* rw = &hd[o + 4 * n];
+        int* rf = &hi[oi_own[d]];
+        for (int i = 0; i < n; ++i) {
+            mm[i] = m[i];
+            xx[i] = x[i];
+            if (i > 0 && i < n - 1) {
+                am[i] = 1.0 / ((x[i] - x[i - 1]) * m[i]);
+                ap[i] = 1.0 / ((x[i + 1] - x[i]) * m[i]);
+            }
+        }
+        Axis& A = L.view.ax[d];
+        A.n = n;
+        A.am = L.dtab + o;
+        A.ap = L.dtab + o + n;
+        A.m = L.dtab + o + 2 * n;
+        A.x = L.dtab + o + 3 * n;
+        A.rw = L.dtab + o + 4 * n;
+        A.rf = L.dtabi + oi_own[d];
+        A.pc = nullptr;
+        A.pw = nullptr;
+        if (l == 0) {
+            for (int I = 0; I < n; ++I) {
+                rf[I] = I;
+                rw[3 * I] = 0.0;
+                rw[3 * I + 1] = 1.0;
+                rw[3 * I + 2] = 0.0;
+            }
+            continue;
+        }
+        const Level& F = g->lev[l - 1];
+        const std::vector<double>& xf = F.hx[d];
+        const int nf = F.n[d];
+        std::vector<double> mf;
+        dual_widths(xf, mf);
+        const std::vector<int>& keep = L.keep[d];
+        int* pc = &hi[oi_fine[d]];
+        double* pw = &hd[od_fine[d]];
+        // interpolation: kept fine node -> weight 1 on its coarse node; a
+        // dropped node between coarse c and c+1 -> linear weights in x
+        int c = 0;
+        for (int i = 0; i < nf; ++i) {
+            while (c + 1 < n && keep[c + 1] <= i) ++c;
+            pc[i] = c;
+            if (keep[c] == i) {
+                pw[2 * i] = 1.0;
+                pw[2 * i + 1] = 0.0;
+            } else {
+                const double xa = xf[keep[c]], xb = xf[keep[c + 1]];
+                const double w = (xb - xf[i]) / (xb - xa);
+                pw[2 * i] = w;
+                pw[2 * i + 1] = 1.0 - w;
+            }
+        }
+        // restriction: coarse node I gathers fine nodes keep[I]-1..keep[I]+1
+        // with the transposed interpolation weight times m_fine/m_coarse
+        for (int I = 0; I < n; ++I) {
+            rf[I] = keep[I];
+            for (int s = 0; s < 3; ++s) {
+                const int fi = keep[I] - 1 + s;
+                double w = 0.0;
+                if (fi >= 0 && fi < nf) {
+                    if (pc[fi] == I) w = pw[2 * fi];
+                    else if (pc[fi] + 1 == I) w = pw[2 * fi + 1];
+                    w *= mf[fi] / m[I];
+                }
+                rw[3 * I + s] = w;
+            }
+        }
+        A.pc = L.dtabi + oi_fine[d];
+        A.pw = L.dtab + od_fine[d];
+    }
+    LASTO_HIP(hipMemcpy(L.dtab, hd.data(), sizeof(double) * nd, hipMemcpyHostToDevice));
+    LASTO_HIP(hipMemcpy(L.dtabi, hi.data(), sizeof(int) * ni, hipMemcpyHostToDevice));
+    L.view.nx = L.n[0];
+    L.view.ny = L.n[1];
+    L.view.nz = L.n[2];
+    return LASTO_OK;
+}
+
+static lasto_status alloc_zero(lasto_grid g, void** p, size_t bytes)
+{
+    LASTO_HIP(hipMalloc(p, bytes));
+    LASTO_HIP(launch_fill_zero<unsigned char>((unsigned char*)*p, bytes, g->stream));
+    return LASTO_OK;
+}
+
+static void free_grid(lasto_grid g)
+{
+    for (int l = 0; l < g->nlev; ++l) {
+        Level& L = g->lev[l];
+        (void)hipFree(L.dtab);
+        (void)hipFree(L.dtabi);
+        for (int s = 0; s < 2; ++s) {
+            (void)hipFree(L.u64[s]);
+            (void)hipFree(L.u32[s]);
+        }
+        (void)hipFree(L.f64);
+        (void)hipFree(L.r64);
+        (void)hipFree(L.f32);
+        (void)hipFree(L.r32);
+    }
+    (void)hipFree(g->r);
+    (void)hipFree(g->p[0]);
+    (void)hipFree(g->p[1]);
+    (void)hipFree(g->q);
+    (void)hipFree(g->z);
+    (void)hipFree(g->r32);
+    (void)hipFree(g->p32[0]);
+    (void)hipFree(g->p32[1]);
+    (void)hipFree(g->q32);
+    (void)hipFree(g->e32);
+    (void)hipFree(g->z32);
+    (void)hipFree(g->partials);
+    (void)hipFree(g->scalars);
+    (void)hipFree(g->moments);
+    (void)hipFree(g->stage);
+    if (g->h_scalars) (void)hipHostFree(g->h_scalars);
+    for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
+    g->prof_ev.clear();
+}
+
+}  // namespace lasto
+
+using namespace lasto;
+
+extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                                          int n_batch, void* hip_stream, lasto_grid* out)
+{
+    if (!out) return fail(LASTO_ERR_ARG, "lasto_grid_create: out is NULL");
+    *out = nullptr;
+    if (!x || !y || !z) return fail(LASTO_ERR_ARG, "lasto_grid_create: NULL coordinates");
+    const double* xs[3] = {x, y, z};
+    const int ns[3] = {nx, ny, nz};
+    for (int d = 0; d < 3; ++d) {
+        if (ns[d] < 4) return fail(LASTO_ERR_ARG, "lasto_grid_create: every axis needs at least 4 nodes");
+        if (ns[d] > (1 << 16)) return fail(LASTO_ERR_ARG, "lasto_grid_create: axis too long");
+        for (int i = 0; i < ns[d]; ++i)
+            if (!std::isfinite(xs[d][i])) return fail(LASTO_ERR_ARG, "lasto_grid_create: non-finite coordinate");
+        for (int i = 0; i + 1 < ns[d]; ++i)
+            if (!(xs[d][i + 1] > xs[d][i])) return fail(LASTO_ERR_ARG, "lasto_grid_create: coordinates must increase");
+    }
+    if (n_batch < 1) return fail(LASTO_ERR_ARG, "lasto_grid_create: n_batch must be >= 1");
+    if (hipError_t e = init_harmonic_constants(); e != hipSuccess)
+        return fail(LASTO_ERR_HIP, std::string("harmonic constants: ") + hipGetErrorString(e));
+
+    lasto_grid g = new (std::nothrow) lasto_grid_s();
+    if (!g) return fail(LASTO_ERR_ALLOC, "lasto_grid_create: host allocation");
+    g->stream = (hipStream_t)hip_stream;
+    g->n_batch = n_batch;
+    (void)hipGetDevice(&g->device);
+    for (int d = 0; d < 3; ++d) g->box_center[d] = 0.5 * (xs[d][0] + xs[d][ns[d] - 1]);
+
+    // hierarchy
+    Level& L0 = g->lev[0];
+    for (int d = 0; d < 3; ++d) {
+        L0.n[d] = ns[d];
+        L0.hx[d].assign(xs[d], xs[d] + ns[d]);
+    }
+    g->nlev = 1;
+    for (;;) {
+        Level& F = g->lev[g->nlev - 1];
+        if (F.n[0] <= kCoarseMax && F.n[1] <= kCoarseMax && F.n[2] <= kCoarseMax) break;
+        if (g->nlev == kMaxLevels) break;
+        double hmin = 1e300, hmax = 0.0;
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i + 1 < F.n[d]; ++i) {
+                const double h = F.hx[d][i + 1] - F.hx[d][i];
+                hmin = std::min(hmin, h);
+                hmax = std::max(hmax, h);
+            }
+        std::vector<int> kp[3];
+        bool changed = false;
+        for (int d = 0; d < 3; ++d) {
+            kp[d] = coarsen_axis(F.hx[d], kCoarsenTheta * hmin * (1.0 + 1e-12));
+            if ((int)kp[d].size() < F.n[d]) changed = true;
+        }
+        if (!changed)
+            for (int d = 0; d < 3; ++d) kp[d] = coarsen_axis(F.hx[d], 2.0 * hmax * (1.0 + 1e-12));
+        Level& C = g->lev[g->nlev];
+        for (int d = 0; d < 3; ++d) {
+            C.n[d] = (int)kp[d].size();
+            C.keep[d] = kp[d];
+            C.hx[d].resize(C.n[d]);
+            for (int t = 0; t < C.n[d]; ++t) C.hx[d][t] = F.hx[d][kp[d][t]];
+        }
+        g->nlev++;
+    }
+    {
+        const Level& Lc = g->lev[g->nlev - 1];
+        if ((size_t)Lc.n[0] * Lc.n[1] * Lc.n[2] > 4096) {
+            free_grid(g);
+            delete g;
+            return fail(LASTO_ERR_ARG, "lasto_grid_create: coarsest level too large");
+        }
+    }
+    lasto_status st = LASTO_OK;
+    for (int l = 0; l < g->nlev && st == LASTO_OK; ++l) {
+        Level& L = g->lev[l];
+        L.npts = (size_t)L.n[0] * L.n[1] * L.n[2];
+        st = build_level_tables(g, l);
+        if (st != LASTO_OK) break;
+        for (int s = 0; s < 2 && st == LASTO_OK; ++s) {
+            st = alloc_zero(g, (void**)&L.u64[s], sizeof(double) * L.npts);
+            if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.u32[s], sizeof(float) * L.npts);
+        }
+        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.f64, sizeof(double) * L.npts);
+        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.r64, sizeof(double) * L.npts);
+        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.f32, sizeof(float) * L.npts);
+        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.r32, sizeof(float) * L.npts);
+    }
+    const size_t N = g->lev[0].npts;
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->r, sizeof(double) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p[0], sizeof(double) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p[1], sizeof(double) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->q, sizeof(double) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->z, sizeof(double) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->r32, sizeof(float) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p32[0], sizeof(float) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p32[1], sizeof(float) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->q32, sizeof(float) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->e32, sizeof(float) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->z32, sizeof(float) * N);
+    // one partial per block of any reducing launch on any level (the finest
+    // level's pointwise launch has the most blocks), and 25 per block of the
+    // moment reduction
+    size_t nparts = (size_t)25 * kReduceBlocks;
+    for (int l = 0; l < g->nlev; ++l) {
+        nparts = std::max(nparts, (size_t)interior_blocks(g->lev[l].view));
+        nparts = std::max(nparts, (size_t)smooth_blocks(g->lev[l].view));
+    }
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->partials, sizeof(double) * nparts);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->scalars, sizeof(double) * kNumScalars);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->moments, sizeof(double) * 32);
+    if (st == LASTO_OK) {
+        g->stage_bytes = 1 << 20;
+        st = alloc_zero(g, (void**)&g->stage, g->stage_bytes);
+    }
+    if (st == LASTO_OK) {
+        if (hipHostMalloc((void**)&g->h_scalars, sizeof(double) * kNumScalars) != hipSuccess)
+            st = fail(LASTO_ERR_ALLOC, "lasto_grid_create: pinned host scalars");
+    }
+    if (st == LASTO_OK) {
+        if (hipError_t e = hipStreamSynchronize(g->stream); e != hipSuccess)
+            st = fail(LASTO_ERR_HIP, std::string("lasto_grid_create: ") + hipGetErrorString(e));
+    }
+    if (st != LASTO_OK) {
+        free_grid(g);
+        delete g;
+        return st;
+    }
+    *out = g;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_grid_destroy(lasto_grid g)
+{
+    if (!g) return LASTO_OK;
+    (void)hipStreamSynchronize(g->stream);
+    free_grid(g);
+    delete g;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_grid_levels(lasto_grid g, int* n_levels)
+{
+    if (!g || !n_levels) return fail(LASTO_ERR_ARG, "lasto_grid_levels: NULL argument");
+    *n_levels = g->nlev;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_grid_level_shape(lasto_grid g, int level, int* out3)
+{
+    if (!g || !out3) return fail(LASTO_ERR_ARG, "lasto_grid_level_shape: NULL argument");
+    if (level < 0 || level >= g->nlev) return fail(LASTO_ERR_ARG, "lasto_grid_level_shape: level out of range");
+    for (int d = 0; d < 3; ++d) out3[d] = g->lev[level].n[d];
+    return LASTO_OK;
+}

@@ -1,0 +1,354 @@
+// Solver drivers for eq. (3.2) on the graded mesh: the V-cycle
+// preconditioner, MG-preconditioned CG (FP64), plain V-cycle iteration, and
+// FP32 inner solves inside FP64 defect-correction refinement.
+//
+// Every step is a kernel on the grid's stream; dot products and norms are
+// reduced on the device into a scalar array that later kernels read (so CG's
+// alpha and beta never travel to the host). The host reads one 8-byte norm
+// per outer iteration to decide convergence.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace lasto {
+
+int smooth_blocks(const LevelView& L);
+int interior_blocks(const LevelView& L);
+hipError_t launch_reference_norm(const LevelView& L, const double* u, const double* f, double bscale,
+                                 double* partials, hipStream_t s);
+hipError_t launch_add64(const LevelView& L, double* u, const double* e, hipStream_t s);
+template <typename T>
+hipError_t launch_zero_interior(const LevelView& L, T* u, hipStream_t s);
+hipError_t launch_scale_inplace(const LevelView& L, double* u, double a, hipStream_t s);
+
+constexpr int kCoarseSweeps = 8;
+
+template <typename T> struct Buf;
+template <> struct Buf<double> {
+    static double* u(Level& L, int s) { return L.u64[s]; }
+    static double* f(Level& L) { return L.f64; }
+    static double* r(Level& L) { return L.r64; }
+};
+template <> struct Buf<float> {
+    static float* u(Level& L, int s) { return L.u32[s]; }
+    static float* f(Level& L) { return L.f32; }
+    static float* r(Level& L) { return L.r32; }
+};
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return fail(LASTO_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// A sweep at level l; finest-level sweeps are bracketed by HIP events when
+// profiling is on (the events sit on the same stream as the kernel).
+template <typename T>
+static hipError_t sweep(lasto_grid g, int l, const T* uin, const T* f, T* uout, int first, int zero_in, double* dotp)
+{
+    const LevelView& V = g->lev[l].view;
+    const bool timed = g->prof_on && l == 0;
+    if (timed) {
+        if ((size_t)(2 * g->prof_used + 2) > g->prof_ev.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                g->prof_ev.push_back(e);
+            }
+        }
+        hipError_t err = hipEventRecord(g->prof_ev[2 * g->prof_used], g->stream);
+        if (err != hipSuccess) return err;
+    }
+    hipError_t err = launch_smooth<T>(V, uin, f, uout, T(1), first, zero_in, dotp, g->stream);
+    if (err != hipSuccess) return err;
+    if (timed) {
+        err = hipEventRecord(g->prof_ev[2 * g->prof_used + 1], g->stream);
+        if (err != hipSuccess) return err;
+        const double pts = (double)(V.nx - 2) * (V.ny - 2) * (V.nz - 2);
+        g->prof_bytes += pts * sizeof(T) * (zero_in ? 2.0 : 3.0);
+        if (sizeof(T) == 4) g->prof_fp32++;
+        g->prof_used++;
+    }
+    return hipSuccess;
+}
+
+// V(nu1, nu2) at level l on A e = f with zero faces, starting from e = 0.
+// Pre-smoothing sweeps update red first, post-smoothing black first, and the
+// coarsest level runs a symmetric sweep sequence, so the cycle is a
+// symmetric operator (usable as a CG preconditioner). Level 0 uses the
+// caller's f and scratch pair (e0, e1); the result pointer is returned.
+template <typename T>
+static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T* f, T* e0, T* e1, double* dotp,
+                                 T** result)
+{
+    Level& L = g->lev[l];
+    const LevelView& V = L.view;
+    hipStream_t s = g->stream;
+    if (l == g->nlev - 1) {
+        HIPCHK(launch_coarse_solve<T>(V, e0, f, kCoarseSweeps, s));
+        if (dotp) HIPCHK(launch_dot<T>(V, f, e0, dotp, s));
+        *result = e0;
+        return LASTO_OK;
+    }
+    T* buf[2] = {e0, e1};
+    int cur = 0;
+    // first pre-sweep from zero
+    HIPCHK(sweep<T>(g, l, buf[1], f, buf[0], 0, 1, nullptr));
+    for (int k = 1; k < nu1; ++k) {
+        HIPCHK(sweep<T>(g, l, buf[cur], f, buf[1 - cur], 0, 0, nullptr));
+        cur = 1 - cur;
+    }
+    Level& C = g->lev[l + 1];
+    T* r = Buf<T>::r(L);
+    HIPCHK(launch_residual<T>(V, buf[cur], f, T(1), r, s));
+    HIPCHK(launch_restrict<T>(V, C.view, r, Buf<T>::f(C), s));
+    T* ec = nullptr;
+    lasto_status st = vcycle_level<T>(g, l + 1, nu1, nu2, Buf<T>::f(C), Buf<T>::u(C, 0), Buf<T>::u(C, 1), nullptr, &ec);
+    if (st != LASTO_OK) return st;
+    HIPCHK(launch_prolong_add<T>(V, C.view, ec, buf[cur], s));
+    for (int k = 0; k < nu2; ++k) {
+        const bool last = (k == nu2 - 1);
+        HIPCHK(sweep<T>(g, l, buf[cur], f, buf[1 - cur], 1, 0, last ? dotp : nullptr));
+        cur = 1 - cur;
+    }
+    if (nu2 == 0 && dotp) HIPCHK(launch_dot<T>(V, f, buf[cur], dotp, s));
+    *result = buf[cur];
+    return LASTO_OK;
+}
+
+static lasto_status reduce_to(lasto_grid g, int count, int slot)
+{
+    HIPCHK(launch_reduce(g->partials, 1, count, g->scalars + slot, g->stream));
+    return LASTO_OK;
+}
+
+static lasto_status read_scalars(lasto_grid g, int first, int n)
+{
+    HIPCHK(hipMemcpyAsync(g->h_scalars + first, g->scalars + first, sizeof(double) * n, hipMemcpyDeviceToHost,
+                          g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}
+
+// Inner FP32 PCG on A e = r32 (scaled residual) from e = 0, `iters` steps.
+static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int iters, int* vcycles)
+{
+    Level& L0 = g->lev[0];
+    const LevelView& V = L0.view;
+    hipStream_t s = g->stream;
+    const int nb_s = smooth_blocks(V), nb_i = interior_blocks(V);
+    HIPCHK(launch_zero_interior<float>(V, g->e32, s));
+    float* rr = g->r32;   // working residual (in place)
+    for (int it = 0; it < iters; ++it) {
+        float* z = nullptr;
+        lasto_status st = vcycle_level<float>(g, 0, o.nu1, o.nu2, rr, g->z32, L0.u32[1], g->partials, &z);
+        if (st != LASTO_OK) return st;
+        ++*vcycles;
+        const int nb = (g->nlev == 1) ? nb_i : (o.nu2 > 0 ? nb_s : nb_i);
+        const int srz = S_RZ32_0 + (it & 1), srz_old = S_RZ32_0 + ((it + 1) & 1);
+        if (lasto_status e = reduce_to(g, nb, srz); e != LASTO_OK) return e;
+        float* pn = g->p32[it & 1];
+        float* po = g->p32[(it + 1) & 1];
+        HIPCHK(launch_update_p<float>(V, z, po, pn, g->scalars, srz, srz_old, it == 0, s));
+        HIPCHK(launch_apply_dot<float>(V, pn, g->q32, g->partials, s));
+        if (lasto_status e = reduce_to(g, nb_i, S_PQ32); e != LASTO_OK) return e;
+        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s));
+        if (lasto_status e = reduce_to(g, nb_i, S_RR32); e != LASTO_OK) return e;
+    }
+    return LASTO_OK;
+}
+
+}  // namespace lasto
+
+using namespace lasto;
+
+extern "C" void lasto_solve_opts_default(lasto_solve_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rtol = 1e-10;
+    o->max_iters = 100;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->method = 0;
+    o->precision = 0;
+    o->inner_iters = 6;
+    o->guess = 0;
+    o->bc = 1;
+    o->lmax_bc = 4;
+    o->debug_nan_iter = -1;
+    o->profile = 0;
+}
+
+extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, double* v, const lasto_solve_opts* opts,
+                                            lasto_solve_info* info)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!g) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: NULL grid");
+    if (!rho || !v) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: NULL rho or v");
+    lasto_solve_opts o;
+    if (opts) o = *opts;
+    else lasto_solve_opts_default(&o);
+    if (!(o.rtol > 0.0) || o.max_iters < 1 || o.nu1 < 1 || o.nu2 < 0 || o.nu1 > 16 || o.nu2 > 16)
+        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad rtol/max_iters/nu1/nu2");
+    if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
+        o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 1 || (o.precision == 1 && o.inner_iters < 1))
+        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters");
+    if (o.precision == 1 && o.method != 0)
+        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: mixed precision runs with method 0");
+    lasto_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    hipStream_t s = g->stream;
+    g->prof_on = (o.profile == 1);
+    g->prof_used = 0;
+    g->prof_bytes = 0.0;
+    g->prof_fp32 = 0;
+    struct ProfOff {
+        lasto_grid g;
+        ~ProfOff() { g->prof_on = false; }
+    } prof_off{g};
+    Level& L0 = g->lev[0];
+    const LevelView& V = L0.view;
+    const int nb_i = interior_blocks(V), nb_s = smooth_blocks(V);
+    const double fourpi = 4.0 * kPi;
+
+    // face values
+    if (o.bc == 1) {
+        HIPCHK(launch_moments(g, rho, g->moments));
+        HIPCHK(launch_bc(g, 1, g->moments, o.lmax_bc, v));
+        HIPCHK(hipMemcpyAsync(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, s));
+    } else if (o.bc == 0) {
+        HIPCHK(launch_bc(g, 0, g->moments, 0, v));
+    }
+    if (o.guess == 1) HIPCHK(launch_zero_interior<double>(V, v, s));
+
+    // reference norm ||b - A v_bc||_W and initial residual
+    HIPCHK(launch_reference_norm(V, v, rho, fourpi, g->partials, s));
+    if (lasto_status e = reduce_to(g, nb_i, S_R0); e != LASTO_OK) return e;
+    HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, g->r, g->partials, s));
+    if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
+    if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
+    const double r0sq = g->h_scalars[S_R0];
+    const double r0 = std::sqrt(r0sq);
+    double rel = (r0 > 0.0) ? std::sqrt(g->h_scalars[S_RR]) / r0 : 0.0;
+    if (!std::isfinite(r0) || !std::isfinite(rel)) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: non-finite rho or v");
+
+    lasto_status result = LASTO_OK;
+    double best = rel;
+    int grow = 0;
+    int it = 0, cg_it = 0;
+    while (rel > o.rtol && it < o.max_iters) {
+        if (o.debug_nan_iter == it) HIPCHK(launch_inject_nan(g->r, (size_t)(V.nz / 2) * V.ny * V.nx + (size_t)(V.ny / 2) * V.nx + V.nx / 2, s));
+        if (o.precision == 1) {
+            // FP32 inner PCG on the scaled FP64 residual, then u += |r| e
+            HIPCHK(launch_scale_f64_to_f32(V, g->r, g->r32, g->scalars, S_RR, s));
+            if (lasto_status e = pcg32_inner(g, o, o.inner_iters, &inf.vcycles); e != LASTO_OK) return e;
+            HIPCHK(launch_add_scaled_f32_to_f64(V, v, g->e32, g->scalars, S_RR, s));
+            HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, g->r, g->partials, s));
+            if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
+            inf.refinements++;
+        } else if (o.method == 1) {
+            // plain V-cycle iteration: v += V(r), r = b - A v
+            double* z = nullptr;
+            lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, L0.u64[1], nullptr, &z);
+            if (st != LASTO_OK) return st;
+            inf.vcycles++;
+            HIPCHK(launch_add64(V, v, z, s));
+            HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, g->r, g->partials, s));
+            if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
+        } else {
+            // one MG-preconditioned CG step
+            double* z = nullptr;
+            lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, L0.u64[1], g->partials, &z);
+            if (st != LASTO_OK) return st;
+            inf.vcycles++;
+            const int nb = (g->nlev == 1) ? nb_i : (o.nu2 > 0 ? nb_s : nb_i);
+            const int srz = S_RZ0 + (cg_it & 1), srz_old = S_RZ0 + ((cg_it + 1) & 1);
+            if (lasto_status e = reduce_to(g, nb, srz); e != LASTO_OK) return e;
+            double* pn = g->p[cg_it & 1];
+            double* po = g->p[(cg_it + 1) & 1];
+            HIPCHK(launch_update_p<double>(V, z, po, pn, g->scalars, srz, srz_old, cg_it == 0, s));
+            HIPCHK(launch_apply_dot<double>(V, pn, g->q, g->partials, s));
+            if (lasto_status e = reduce_to(g, nb_i, S_PQ); e != LASTO_OK) return e;
+            HIPCHK(launch_update_xr<double>(V, v, g->r, pn, g->q, g->scalars, srz, S_PQ, g->partials, s));
+            if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
+            cg_it++;
+        }
+        if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;
+        rel = std::sqrt(g->h_scalars[S_RR]) / r0;
+        if (it < 128) inf.resid_hist[it] = rel;
+        ++it;
+        if (!std::isfinite(rel)) {
+            result = LASTO_ERR_DIVERGED;
+            break;
+        }
+        if (rel < best) {
+            best = rel;
+            grow = 0;
+        } else if (rel > 1e3 * best && ++grow >= 3) {
+            result = LASTO_ERR_DIVERGED;
+            break;
+        }
+        if (rel <= o.rtol && o.precision == 0 && o.method == 0) {
+            // the CG residual is a recurrence: confirm with the true residual,
+            // and restart CG from it if the two have drifted apart
+            HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, g->r, g->partials, s));
+            if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
+            if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;
+            rel = std::sqrt(g->h_scalars[S_RR]) / r0;
+            cg_it = 0;
+        }
+    }
+    // true residual of the returned iterate
+    HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, (double*)nullptr, g->partials, s));
+    if (lasto_status e = reduce_to(g, nb_i, S_TMP); e != LASTO_OK) return e;
+    if (lasto_status e = read_scalars(g, S_TMP, 1); e != LASTO_OK) return e;
+    inf.rel_resid = std::sqrt(g->h_scalars[S_TMP]) / r0;
+    inf.iters = it;
+    if (g->prof_on) {
+        // the stream has been synchronised by read_scalars: every event is complete
+        double ms = 0.0;
+        for (int k = 0; k < g->prof_used; ++k) {
+            float e = 0.0f;
+            HIPCHK(hipEventElapsedTime(&e, g->prof_ev[2 * k], g->prof_ev[2 * k + 1]));
+            ms += e;
+        }
+        inf.smooth_launches = g->prof_used;
+        inf.smooth_ms = ms;
+        inf.smooth_bytes = g->prof_bytes;
+        inf.smooth_fp32 = g->prof_fp32;
+    }
+    if (result == LASTO_OK && !(inf.rel_resid <= o.rtol)) result = LASTO_ERR_NOT_CONVERGED;
+    if (!std::isfinite(inf.rel_resid)) result = LASTO_ERR_DIVERGED;
+    inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (info) *info = inf;
+    if (result == LASTO_ERR_NOT_CONVERGED)
+        return fail(result, "lasto_poisson_solve: tolerance not reached within max_iters");
+    if (result == LASTO_ERR_DIVERGED) return fail(result, "lasto_poisson_solve: residual not finite or growing");
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_apply(lasto_grid g, const double* u, double* Au)
+{
+    if (!g || !u || !Au || u == Au) return fail(LASTO_ERR_ARG, "lasto_apply: NULL or aliased buffers");
+    const LevelView& V = g->lev[0].view;
+    HIPCHK(launch_residual<double>(V, u, u, 0.0, Au, g->stream));
+    // launch_residual computes 0*u - A u; negate in place
+    HIPCHK(launch_scale_inplace(V, Au, -1.0, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_rb_sweep(lasto_grid g, const double* u_in, const double* rho, double* u_out,
+                                       int first_colour)
+{
+    if (!g || !u_in || !rho || !u_out || u_in == u_out || (first_colour != 0 && first_colour != 1))
+        return fail(LASTO_ERR_ARG, "lasto_rb_sweep: NULL/aliased buffers or bad colour");
+    const LevelView& V = g->lev[0].view;
+    HIPCHK(launch_smooth<double>(V, u_in, rho, u_out, 4.0 * kPi, first_colour, 0, nullptr, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}

@@ -1,0 +1,329 @@
+// Source, boundary and interpolation kernels of the Hartree step.
+//   k_atom_prep : per-atom constants (Gaussian renormalisation, quartic fit)
+//   k_pseudo    : pseudo-density on every node (Section 1; eq. (3.2) and its
+//                 three constraints)
+//   k_moments   : Q_lm = sum_n vol_n rho_n r^l y_lm(x_n - c), l <= 4 (the
+//                 paper's L <= 4 of eq. (3.1))
+//   k_bc        : multipole field of Q on the six faces (zero: eq. (3.3))
+//   k_interp    : tricubic Lagrange values at the sphere points
+//                 (eq. (3.5)-(3.6) take V_C on the sphere boundaries)
+#include "internal.h"
+
+namespace lasto {
+
+// r^l y_lm normalisation: sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times sqrt(2)
+// for m != 0; index l*l + l + m. Filled once per process.
+__constant__ double c_ynorm[25];
+static bool g_ynorm_ready = false;
+
+hipError_t init_harmonic_constants()
+{
+    if (g_ynorm_ready) return hipSuccess;
+    double h[25];
+    for (int l = 0; l <= 4; ++l)
+        for (int m = -l; m <= l; ++m) {
+            const int am = m < 0 ? -m : m;
+            double ratio = 1.0;   // (l-|m|)!/(l+|m|)!
+            for (int t = l - am + 1; t <= l + am; ++t) ratio /= (double)t;
+            double nrm = std::sqrt((2.0 * l + 1.0) / (4.0 * kPi) * ratio);
+            if (m != 0) nrm *= std::sqrt(2.0);
+            h[l * l + l + m] = nrm;
+        }
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_ynorm), h, sizeof(h));
+    if (e == hipSuccess) g_ynorm_ready = true;
+    return e;
+}
+
+// Real solid harmonics r^l y_lm(x,y,z), l <= lmax <= 4, without the
+// Condon-Shortley phase. Built from the complex Q_l^m = r^l P_l^m(cos t) e^{i m p}:
+//   Q_m^m = (2m-1)!! (x + i y)^m,  Q_{m+1}^m = (2m+1) z Q_m^m,
+//   (l-m+1) Q_{l+1}^m = (2l+1) z Q_l^m - (l+m) r^2 Q_{l-1}^m;
+// then S_l,m = N Re Q_l^m (m >= 0), S_l,-m = N Im Q_l^m.
+__device__ __forceinline__ void solid_harmonics(double x, double y, double z, int lmax, double* S)
+{
+    const double r2 = x * x + y * y + z * z;
+    double mre = 1.0, mim = 0.0;   // Q_m^m
+    double dfact = 1.0;            // (2m-1)!!
+    for (int m = 0; m <= lmax; ++m) {
+        if (m > 0) {
+            // (x+iy)^m = (x+iy)^(m-1) (x+iy); (2m-1)!! = (2m-3)!! (2m-1)
+            const double nre = mre * x - mim * y;
+            const double nim = mre * y + mim * x;
+            mre = nre * (2.0 * m - 1.0);
+            mim = nim * (2.0 * m - 1.0);
+        }
+        (void)dfact;
+        double pre = 0.0, pim = 0.0;     // Q_{l-1}^m
+        double cre = mre, cim = mim;     // Q_l^m at l = m
+        for (int l = m; l <= lmax; ++l) {
+            if (l > m) {
+                // Q_l^m from Q_{l-1}^m (c) and Q_{l-2}^m (p)
+                const double a = (2.0 * (l - 1) + 1.0) / (double)(l - m);
+                const double b = (double)(l - 1 + m) / (double)(l - m);
+                const double nre = a * z * cre - b * r2 * pre;
+                const double nim = a * z * cim - b * r2 * pim;
+                pre = cre; pim = cim;
+                cre = nre; cim = nim;
+            }
+            S[l * l + l + m] = c_ynorm[l * l + l + m] * cre;
+            if (m > 0) S[l * l + l - m] = c_ynorm[l * l + l - m] * cim;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- atoms
+// kind 0: s = 1/((pi w^2)^(-3/2) prod_d sum_i m_d,i exp(-(x_d,i - c_d)^2/w^2))
+//         (the discrete integral of the normalised Gaussian is separable)
+// kind 1: quartic a + b r^2 + c r^4 from value, slope and charge at R, by
+//         Cramer's rule on
+//           [1, R^2, R^4; 0, 2R, 4R^3; 4piR^3/3, 4piR^5/5, 4piR^7/7] (a,b,c) = (rho_R, drho_R, q)
+__global__ void k_atom_prep(LevelView L, AtomDev* atoms, int n_atoms, int renormalize)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_atoms) return;
+    AtomDev& A = atoms[a];
+    if (A.kind == 0) {
+        double s = 1.0;
+        if (renormalize) {
+            const double w2 = A.w * A.w;
+            double prod = pow(kPi * w2, -1.5);
+            for (int d = 0; d < 3; ++d) {
+                double sum = 0.0;
+                for (int i = 0; i < L.ax[d].n; ++i) {
+                    const double t = L.ax[d].x[i] - A.c[d];
+                    sum += L.ax[d].m[i] * exp(-t * t / w2);
+                }
+                prod *= sum;
+            }
+            s = 1.0 / prod;
+        }
+        A.s = s;
+    } else {
+        const double R = A.R, R2 = R * R;
+        const double m00 = 1.0, m01 = R2, m02 = R2 * R2;
+        const double m10 = 0.0, m11 = 2.0 * R, m12 = 4.0 * R * R2;
+        const double f = 4.0 * kPi * R * R2;
+        const double m20 = f / 3.0, m21 = f * R2 / 5.0, m22 = f * R2 * R2 / 7.0;
+        const double r0 = A.rho_R, r1 = A.drho_R, r2 = A.q;
+        const double det = m00 * (m11 * m22 - m12 * m21) - m01 * (m10 * m22 - m12 * m20) + m02 * (m10 * m21 - m11 * m20);
+        const double da = r0 * (m11 * m22 - m12 * m21) - m01 * (r1 * m22 - m12 * r2) + m02 * (r1 * m21 - m11 * r2);
+        const double db = m00 * (r1 * m22 - m12 * r2) - r0 * (m10 * m22 - m12 * m20) + m02 * (m10 * r2 - r1 * m20);
+        const double dc = m00 * (m11 * r2 - r1 * m21) - m01 * (m10 * r2 - r1 * m20) + r0 * (m10 * m21 - m11 * m20);
+        A.coef[0] = da / det;
+        A.coef[1] = db / det;
+        A.coef[2] = dc / det;
+        A.s = 1.0;
+    }
+}
+
+hipError_t launch_atom_prep(lasto_grid g, AtomDev* atoms, int n_atoms, int renormalize)
+{
+    hipLaunchKernelGGL(k_atom_prep, dim3((n_atoms + 63) / 64), dim3(64), 0, g->stream, g->lev[0].view, atoms, n_atoms,
+                       renormalize);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- density
+__global__ __launch_bounds__(256) void k_pseudo(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
+                                                const double* __restrict__ rho_inter, double* __restrict__ rho)
+{
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const size_t n = (size_t)nx * ny * nz;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((size_t)nx * ny));
+    const double px = L.ax[0].x[i], py = L.ax[1].x[j], pz = L.ax[2].x[k];
+    double acc = 0.0;
+    bool outside = true;
+    double S[25];
+    for (int a = 0; a < n_atoms; ++a) {
+        const AtomDev& A = atoms[a];
+        const double dx = px - A.c[0], dy = py - A.c[1], dz = pz - A.c[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < A.R * A.R) outside = false;
+        if (A.kind == 0) {
+            const double cut = 7.0 * A.w;
+            if (r2 < cut * cut) acc += A.q * A.s * pow(kPi * A.w * A.w, -1.5) * exp(-r2 / (A.w * A.w));
+        } else if (r2 < A.R * A.R) {
+            acc += A.coef[0] + r2 * (A.coef[1] + r2 * A.coef[2]);
+        }
+        if (A.lmax >= 1 && A.alpha * r2 < 42.25) {
+            solid_harmonics(dx, dy, dz, A.lmax, S);
+            double s = 0.0;
+            const int nt = (A.lmax + 1) * (A.lmax + 1);
+            for (int c = 1; c < nt; ++c) s += A.clm[c - 1] * S[c];
+            acc += s * exp(-A.alpha * r2);
+        }
+    }
+    if (rho_inter && outside) acc += rho_inter[t];
+    rho[t] = acc;
+}
+
+hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const double* rho_inter, double* rho)
+{
+    const LevelView& L = g->lev[0].view;
+    const size_t n = (size_t)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_pseudo, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g->stream, L, atoms, n_atoms, rho_inter,
+                       rho);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- moments
+constexpr int MO_NT = 256;
+
+__global__ __launch_bounds__(MO_NT) void k_moments(LevelView L, const double* __restrict__ rho, double cx, double cy,
+                                                   double cz, double* __restrict__ part)
+{
+    __shared__ double sh[MO_NT / 64];
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const size_t n = (size_t)nx * ny * nz;
+    double acc[25];
+    for (int c = 0; c < 25; ++c) acc[c] = 0.0;
+    double S[25];
+    for (size_t t = (size_t)blockIdx.x * MO_NT + threadIdx.x; t < n; t += (size_t)gridDim.x * MO_NT) {
+        const double f = rho[t];
+        if (f == 0.0) continue;
+        const int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((size_t)nx * ny));
+        const double w = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * f;
+        solid_harmonics(L.ax[0].x[i] - cx, L.ax[1].x[j] - cy, L.ax[2].x[k] - cz, 4, S);
+        for (int c = 0; c < 25; ++c) acc[c] += w * S[c];
+    }
+    for (int c = 0; c < 25; ++c) {
+        double v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < MO_NT / 64; ++w) s += sh[w];
+            part[(size_t)blockIdx.x * 25 + c] = s;
+        }
+    }
+}
+
+hipError_t launch_moments(lasto_grid g, const double* rho, double* Q)
+{
+    const LevelView& L = g->lev[0].view;
+    hipLaunchKernelGGL(k_moments, dim3(kReduceBlocks), dim3(MO_NT), 0, g->stream, L, rho, g->box_center[0],
+                       g->box_center[1], g->box_center[2], g->partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(g->partials, 25, kReduceBlocks, Q, g->stream);
+}
+
+// ---------------------------------------------------------- face values
+__global__ __launch_bounds__(256) void k_bc(LevelView L, int mode, const double* __restrict__ Q, int lmax_bc, double cx,
+                                            double cy, double cz, double* __restrict__ v)
+{
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const size_t nxy = (size_t)nx * ny, nxz = (size_t)nx * nz, nyz = (size_t)ny * nz;
+    const size_t total = 2 * (nxy + nxz + nyz);
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    int i, j, k;
+    size_t u = t;
+    if (u < 2 * nxy) {
+        const int face = (int)(u / nxy);
+        u %= nxy;
+        i = (int)(u % nx); j = (int)(u / nx); k = face ? nz - 1 : 0;
+    } else if ((u -= 2 * nxy) < 2 * nxz) {
+        const int face = (int)(u / nxz);
+        u %= nxz;
+        i = (int)(u % nx); k = (int)(u / nx); j = face ? ny - 1 : 0;
+    } else {
+        u -= 2 * nxz;
+        const int face = (int)(u / nyz);
+        u %= nyz;
+        j = (int)(u % ny); k = (int)(u / ny); i = face ? nx - 1 : 0;
+    }
+    double val = 0.0;
+    if (mode == 1) {
+        const double dx = L.ax[0].x[i] - cx, dy = L.ax[1].x[j] - cy, dz = L.ax[2].x[k] - cz;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double rinv = 1.0 / sqrt(r2);
+        const double r2inv = rinv * rinv;
+        double S[25];
+        solid_harmonics(dx, dy, dz, lmax_bc, S);
+        double pw = rinv;   // 1/r^(2l+1)
+        for (int l = 0; l <= lmax_bc; ++l) {
+            double s = 0.0;
+            for (int m = -l; m <= l; ++m) s += Q[l * l + l + m] * S[l * l + l + m];
+            val -= 4.0 * kPi / (2.0 * l + 1.0) * s * pw;
+            pw *= r2inv;
+        }
+    }
+    v[((size_t)k * ny + j) * nx + i] = val;
+}
+
+hipError_t launch_bc(lasto_grid g, int mode, const double* Q, int lmax_bc, double* v)
+{
+    const LevelView& L = g->lev[0].view;
+    const size_t total = 2 * ((size_t)L.nx * L.ny + (size_t)L.nx * L.nz + (size_t)L.ny * L.nz);
+    hipLaunchKernelGGL(k_bc, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, g->stream, L, mode, Q, lmax_bc,
+                       g->box_center[0], g->box_center[1], g->box_center[2], v);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------- interpolation
+__device__ __forceinline__ int upper_bound_dev(const double* x, int n, double p)
+{
+    int lo = 0, hi = n;   // first index with x[idx] > p
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (x[mid] <= p) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int window_start(const double* x, int n, double p)
+{
+    int i0 = upper_bound_dev(x, n, p) - 2;
+    if (i0 < 0) i0 = 0;
+    if (i0 > n - 4) i0 = n - 4;
+    return i0;
+}
+
+__device__ __forceinline__ void lagrange_weights(const double* x, int i0, double p, double* w)
+{
+    const double x0 = x[i0], x1 = x[i0 + 1], x2 = x[i0 + 2], x3 = x[i0 + 3];
+    const double d0 = p - x0, d1 = p - x1, d2 = p - x2, d3 = p - x3;
+    w[0] = (d1 * d2 * d3) / ((x0 - x1) * (x0 - x2) * (x0 - x3));
+    w[1] = (d0 * d2 * d3) / ((x1 - x0) * (x1 - x2) * (x1 - x3));
+    w[2] = (d0 * d1 * d3) / ((x2 - x0) * (x2 - x1) * (x2 - x3));
+    w[3] = (d0 * d1 * d2) / ((x3 - x0) * (x3 - x1) * (x3 - x2));
+}
+
+__global__ __launch_bounds__(64) void k_interp(LevelView L, const double* __restrict__ v, const double* __restrict__ pts,
+                                               int npts, double* __restrict__ out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npts) return;
+    const double px = pts[3 * t], py = pts[3 * t + 1], pz = pts[3 * t + 2];
+    const int i0 = window_start(L.ax[0].x, L.nx, px);
+    const int j0 = window_start(L.ax[1].x, L.ny, py);
+    const int k0 = window_start(L.ax[2].x, L.nz, pz);
+    double wx[4], wy[4], wz[4];
+    lagrange_weights(L.ax[0].x, i0, px, wx);
+    lagrange_weights(L.ax[1].x, j0, py, wy);
+    lagrange_weights(L.ax[2].x, k0, pz, wz);
+    double s = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        double sy = 0.0;
+        for (int b = 0; b < 4; ++b) {
+            const double* row = v + ((size_t)(k0 + c) * L.ny + (j0 + b)) * L.nx + i0;
+            sy += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
+        }
+        s += wz[c] * sy;
+    }
+    out[t] = s;
+}
+
+hipError_t launch_interp(lasto_grid g, const double* v, const double* pts, int npts, double* out)
+{
+    const LevelView& L = g->lev[0].view;
+    hipLaunchKernelGGL(k_interp, dim3((npts + 63) / 64), dim3(64), 0, g->stream, L, v, pts, npts, out);
+    return hipGetLastError();
+}
+
+}  // namespace lasto

@@ -1,0 +1,301 @@
+"""ctypes binding of liblasto.so (the C ABI in include/lasto.h).
+
+Argument marshalling only: every step of the Hartree path runs in the HIP
+kernels behind the C ABI. torch supplies device memory and the stream.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblasto.so")
+
+OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_CONVERGED, ERR_DIVERGED, ERR_STATE = range(7)
+
+
+class LastoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("lasto status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Atom(C.Structure):
+    _fields_ = [
+        ("center", C.c_double * 3),
+        ("radius", C.c_double),
+        ("q", C.c_double),
+        ("kind", C.c_int),
+        ("lmax", C.c_int),
+        ("width", C.c_double),
+        ("rho_R", C.c_double),
+        ("drho_R", C.c_double),
+        ("alpha", C.c_double),
+        ("clm", C.c_double * 24),
+    ]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [
+        ("rtol", C.c_double),
+        ("max_iters", C.c_int),
+        ("nu1", C.c_int),
+        ("nu2", C.c_int),
+        ("method", C.c_int),
+        ("precision", C.c_int),
+        ("inner_iters", C.c_int),
+        ("guess", C.c_int),
+        ("bc", C.c_int),
+        ("lmax_bc", C.c_int),
+        ("debug_nan_iter", C.c_int),
+        ("profile", C.c_int),
+    ]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int),
+        ("vcycles", C.c_int),
+        ("refinements", C.c_int),
+        ("rel_resid", C.c_double),
+        ("resid_hist", C.c_double * 128),
+        ("moments", C.c_double * 25),
+        ("ms_total", C.c_double),
+        ("smooth_launches", C.c_int),
+        ("smooth_ms", C.c_double),
+        ("smooth_bytes", C.c_double),
+        ("smooth_fp32", C.c_int),
+    ]
+
+    def as_dict(self) -> dict:
+        n = min(self.iters, 128)
+        return dict(iters=self.iters, vcycles=self.vcycles, refinements=self.refinements,
+                    rel_resid=self.rel_resid, resid_hist=list(self.resid_hist[:n]),
+                    moments=list(self.moments), ms_total=self.ms_total,
+                    smooth_launches=self.smooth_launches, smooth_ms=self.smooth_ms,
+                    smooth_bytes=self.smooth_bytes, smooth_fp32=self.smooth_fp32)
+
+
+# exported names, in header order
+SYMBOLS = [
+    "lasto_status_string", "lasto_last_error", "lasto_mesh_graded_1d", "lasto_grid_create",
+    "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
+    "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp", "lasto_apply",
+    "lasto_rb_sweep",
+]
+
+_lib = None
+
+
+def load():
+    """Load liblasto.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblasto.so is not built; run __graft_entry__.build() "
+                           "(python paper_0806_1723_amd/build.py)")
+    L = C.CDLL(LIB_PATH)
+    P, i, d = C.c_void_p, C.c_int, C.c_double
+    L.lasto_status_string.argtypes = [i]
+    L.lasto_status_string.restype = C.c_char_p
+    L.lasto_last_error.argtypes = []
+    L.lasto_last_error.restype = C.c_char_p
+    L.lasto_mesh_graded_1d.argtypes = [d, d, i, P, i, d, d, d, d, P, P, P]
+    L.lasto_mesh_graded_1d.restype = i
+    L.lasto_grid_create.argtypes = [P, i, P, i, P, i, i, P, C.POINTER(P)]
+    L.lasto_grid_create.restype = i
+    L.lasto_grid_destroy.argtypes = [P]
+    L.lasto_grid_destroy.restype = i
+    L.lasto_grid_levels.argtypes = [P, C.POINTER(i)]
+    L.lasto_grid_levels.restype = i
+    L.lasto_grid_level_shape.argtypes = [P, i, P]
+    L.lasto_grid_level_shape.restype = i
+    L.lasto_pseudo_density.argtypes = [P, i, P, P, i, P, P]
+    L.lasto_pseudo_density.restype = i
+    L.lasto_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
+    L.lasto_solve_opts_default.restype = None
+    L.lasto_poisson_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]
+    L.lasto_poisson_solve.restype = i
+    L.lasto_sphere_interp.argtypes = [P, P, i, P, P, i, P, P]
+    L.lasto_sphere_interp.restype = i
+    L.lasto_apply.argtypes = [P, P, P]
+    L.lasto_apply.restype = i
+    L.lasto_rb_sweep.argtypes = [P, P, P, P, i]
+    L.lasto_rb_sweep.restype = i
+    _lib = L
+    return L
+
+
+def _check(status: int, allow=()):
+    if status != OK and status not in allow:
+        raise LastoError(status, load().lasto_last_error().decode())
+    return status
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t) -> int:
+    """Device pointer of a contiguous float64 CUDA/HIP tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 device tensor")
+    return t.data_ptr()
+
+
+def status_string(s: int) -> str:
+    return load().lasto_status_string(s).decode()
+
+
+def mesh_graded_1d(lo, hi, n, planes, hmin, hmax, gmax=1.2, hmin_step=0.0):
+    """Graded 1-D coordinates (host). Returns (x, g, hmin_used)."""
+    pl = np.ascontiguousarray(planes, dtype=np.float64).ravel()
+    x = np.zeros(n)
+    g = np.zeros(1)
+    hm = np.zeros(1)
+    _check(load().lasto_mesh_graded_1d(lo, hi, n, _np_ptr(pl) if len(pl) else None, len(pl), hmin, hmax, gmax,
+                                       hmin_step, _np_ptr(x), _np_ptr(g), _np_ptr(hm)))
+    return x, float(g[0]), float(hm[0])
+
+
+def mesh_for(axes) -> List[np.ndarray]:
+    return [mesh_graded_1d(a.lo, a.hi, a.n, a.planes, a.hmin, a.hmax, a.gmax, a.hmin_step)[0] for a in axes]
+
+
+def make_atoms(atoms: Sequence) -> C.Array:
+    """lasto_atom array from objects with the fields of inputs.Atom."""
+    arr = (Atom * max(len(atoms), 1))()
+    for k, a in enumerate(atoms):
+        A = arr[k]
+        for c in range(3):
+            A.center[c] = float(a.center[c])
+        A.radius = float(a.radius)
+        A.q = float(a.q)
+        A.kind = int(a.kind)
+        A.lmax = int(a.lmax)
+        A.width = float(a.width)
+        A.rho_R = float(a.rho_R)
+        A.drho_R = float(a.drho_R)
+        A.alpha = float(a.alpha)
+        for c, v in enumerate(np.asarray(a.clm, dtype=np.float64).ravel()[:24]):
+            A.clm[c] = float(v)
+    return arr
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load().lasto_solve_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Grid:
+    """A tensor-product grid with its multigrid hierarchy on the current device."""
+
+    def __init__(self, x, y, z, n_batch: int = 1, stream=None):
+        import torch
+        self.coords = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, z)]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        h = C.c_void_p()
+        xs, ys, zs = self.coords
+        _check(load().lasto_grid_create(_np_ptr(xs), len(xs), _np_ptr(ys), len(ys), _np_ptr(zs), len(zs),
+                                        n_batch, C.c_void_p(sp), C.byref(h)))
+        self.h = h
+        self.shape = (len(zs), len(ys), len(xs))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lasto_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def levels(self) -> List[tuple]:
+        n = C.c_int()
+        _check(load().lasto_grid_levels(self.h, C.byref(n)))
+        out = []
+        for l in range(n.value):
+            s = np.zeros(3, dtype=np.int32)
+            _check(load().lasto_grid_level_shape(self.h, l, _np_ptr(s)))
+            out.append(tuple(int(v) for v in s))
+        return out
+
+    def empty(self):
+        import torch
+        return torch.zeros(self.shape, dtype=torch.float64, device="cuda")
+
+    def pseudo_density(self, atoms, rho_out=None, rho_interstitial=None, renormalize=True, moments=False):
+        arr = make_atoms(atoms)
+        if rho_out is None:
+            rho_out = self.empty()
+        Q = np.zeros(25)
+        _check(load().lasto_pseudo_density(self.h, len(atoms), C.cast(arr, C.c_void_p),
+                                           None if rho_interstitial is None else _dev_ptr(rho_interstitial),
+                                           int(renormalize), _dev_ptr(rho_out), _np_ptr(Q) if moments else None))
+        return (rho_out, Q) if moments else rho_out
+
+    def poisson_solve(self, rho, v, allow_fail: bool = False, **opts):
+        o = default_opts(**opts)
+        info = SolveInfo()
+        st = load().lasto_poisson_solve(self.h, _dev_ptr(rho), _dev_ptr(v), C.byref(o), C.byref(info))
+        d = info.as_dict()
+        d["status"] = st
+        if not allow_fail:
+            _check(st)
+        return d
+
+    def sphere_interp(self, v, centers, radii, dirs=None) -> np.ndarray:
+        centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        radii = np.ascontiguousarray(radii, dtype=np.float64).ravel()
+        na = len(centers)
+        if dirs is None:
+            nd = 64
+            dp = None
+        else:
+            dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+            nd = len(dirs)
+            dp = _np_ptr(dirs)
+        out = np.zeros((na, nd))
+        _check(load().lasto_sphere_interp(self.h, _dev_ptr(v), na, _np_ptr(centers), _np_ptr(radii), nd, dp,
+                                          _np_ptr(out)))
+        return out
+
+    def apply(self, u, Au=None):
+        if Au is None:
+            Au = self.empty()
+        _check(load().lasto_apply(self.h, _dev_ptr(u), _dev_ptr(Au)))
+        return Au
+
+    def rb_sweep(self, u_in, rho, u_out=None, first_colour: int = 0):
+        if u_out is None:
+            u_out = u_in.clone()
+        _check(load().lasto_rb_sweep(self.h, _dev_ptr(u_in), _dev_ptr(rho), _dev_ptr(u_out), first_colour))
+        return u_out
+
+
+def hartree_step(grid: Grid, atoms, rtol=1e-10, dirs=None, **opts):
+    """The whole path on the GPU: pseudo-density -> Poisson solve with
+    multipole faces -> values on the sphere boundaries."""
+    rho = grid.pseudo_density(atoms)
+    v = grid.empty()
+    info = grid.poisson_solve(rho, v, rtol=rtol, **opts)
+    centers = np.array([a.center for a in atoms])
+    radii = np.array([a.radius for a in atoms])
+    sph = grid.sphere_interp(v, centers, radii, dirs)
+    return dict(rho=rho, v=v, info=info, sphere=sph)

@@ -1,0 +1,327 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, element by element at sizes the oracle finishes in
+seconds (spanning several tiles, with ragged tails), and through properties
+at the full 257^3 size."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0806_1723_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0806_1723_amd import lasto
+    lasto.load()
+    return lasto
+
+
+def graded(rng, n, lo=-6.0, hi=6.0):
+    h = rng.uniform(0.4, 1.6, n - 1)
+    x = np.concatenate([[0.0], np.cumsum(h)])
+    return lo + (hi - lo) * x / x[-1]
+
+
+def dual(x):
+    m = np.zeros_like(x)
+    m[1:-1] = 0.5 * (x[2:] - x[:-2])
+    m[0] = 0.5 * (x[1] - x[0])
+    m[-1] = 0.5 * (x[-1] - x[-2])
+    return m
+
+
+def wnorm(xs, a):
+    vol = np.einsum("k,j,i->kji", dual(xs[2]), dual(xs[1]), dual(xs[0]))
+    return math.sqrt(float((vol * a * a)[1:-1, 1:-1, 1:-1].sum()))
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+# ------------------------------------------------------------- kernels
+SHAPES = [(131, 37, 41), (4, 4, 4), (70, 9, 19)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_apply_matches_oracle(torch, L, oracle_mod, shape):
+    say("apply %s" % (shape,))
+    rng = np.random.default_rng(11)
+    xs = [graded(rng, n) for n in shape]
+    u = rng.normal(size=shape[::-1])
+    g = L.Grid(*xs)
+    Au = g.apply(to_dev(torch, u)).cpu().numpy()
+    want = oracle_mod.apply(xs, u)
+    I_ = (slice(1, -1),) * 3
+    assert np.abs(Au[I_] - want[I_]).max() <= 1e-13 * np.abs(want[I_]).max()
+    g.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("first", [0, 1])
+def test_rb_sweep_matches_oracle(torch, L, oracle_mod, shape, first):
+    say("rb_sweep %s first=%d" % (shape, first))
+    rng = np.random.default_rng(12 + first)
+    xs = [graded(rng, n) for n in shape]
+    u = rng.normal(size=shape[::-1])
+    rho = rng.normal(size=shape[::-1])
+    g = L.Grid(*xs)
+    ud = to_dev(torch, u)
+    out = g.rb_sweep(ud, to_dev(torch, rho), first_colour=first)
+    got = out.cpu().numpy()
+    want = oracle_mod.rb_sweep(xs, u, rho, first)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    # faces untouched, deterministic
+    assert np.array_equal(got[0], u[0]) and np.array_equal(got[:, :, -1], u[:, :, -1])
+    out2 = g.rb_sweep(ud, to_dev(torch, rho), first_colour=first)
+    assert torch.equal(out, out2)
+    g.close()
+
+
+# ------------------------------------------------------------- source
+@pytest.mark.parametrize("cid,n", [(1, 33), (2, 65), (2, 129)])
+def test_pseudo_density_and_moments_match_oracle(torch, L, oracle_mod, cid, n):
+    say("pseudo_density config %d n=%d" % (cid, n))
+    w = I.config(cid, n_override=n)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    rho, Q = g.pseudo_density(w.atoms, moments=True)
+    got = rho.cpu().numpy()
+    A = I.atom_arrays(w.atoms)
+    want = oracle_mod.pseudo_density(xs, A)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    Qw = oracle_mod.moments(xs, want, 4)
+    assert np.abs(Q - Qw).max() <= 1e-11 * np.abs(Qw).max()
+    g.close()
+
+
+def test_quartic_and_interstitial_density(torch, L, oracle_mod):
+    say("pseudo_density kind 1 + interstitial")
+    rng = np.random.default_rng(13)
+    xs = [graded(rng, n, -5, 5) for n in (45, 38, 51)]
+    atoms = [I.Atom(center=np.array([0.3, -0.2, 0.1]), q=-1.6, radius=2.3, kind=1, rho_R=0.035, drho_R=-0.089,
+                    lmax=2, clm=rng.normal(0, 0.1, 8)),
+             I.Atom(center=np.array([-2.0, 1.5, 1.0]), q=3.0, width=0.6, radius=1.2, lmax=4,
+                    clm=rng.normal(0, 0.1, 24))]
+    inter = rng.uniform(0, 0.01, size=(51, 38, 45))
+    g = L.Grid(*xs)
+    got = g.pseudo_density(atoms, rho_interstitial=to_dev(torch, inter)).cpu().numpy()
+    want = oracle_mod.pseudo_density(xs, I.atom_arrays(atoms), rho_inter=inter)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    got2 = g.pseudo_density(atoms, renormalize=False).cpu().numpy()
+    want2 = oracle_mod.pseudo_density(xs, I.atom_arrays(atoms), renormalize=False)
+    assert np.abs(got2 - want2).max() <= 1e-12 * np.abs(want2).max()
+    g.close()
+
+
+# --------------------------------------------------------------- solve
+def oracle_solution(oracle_mod, xs, atoms, bc=1, rtol=1e-12):
+    A = I.atom_arrays(atoms)
+    rho = oracle_mod.pseudo_density(xs, A)
+    Q = oracle_mod.moments(xs, rho, 4)
+    v = np.zeros_like(rho)
+    oracle_mod.boundary_values(xs, Q, v, bc, 4)
+    cyc, rel, _ = oracle_mod.solve(xs, rho, v, rtol=rtol)
+    assert rel <= rtol
+    return rho, v
+
+
+SOLVE_CASES = [
+    (1, 33, dict()),
+    (2, 65, dict()),
+    (2, 65, dict(method=1)),
+    (2, 65, dict(precision=1)),
+    (2, 129, dict()),
+    (2, 129, dict(precision=1)),
+    (4, 65, dict()),
+]
+
+
+@pytest.mark.parametrize("cid,n,opts", SOLVE_CASES)
+def test_solve_matches_oracle(torch, L, oracle_mod, cid, n, opts):
+    say("solve config %d n=%d %s" % (cid, n, opts))
+    w = I.config(cid, n_override=n)
+    xs = oracle_mod.mesh_for(w.axes)
+    rho_o, v_o = oracle_solution(oracle_mod, xs, w.atoms)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    v = g.empty()
+    info = g.poisson_solve(rho, v, rtol=1e-12, **opts)
+    assert info["rel_resid"] <= 1e-12
+    got = v.cpu().numpy()
+    faces = np.ones(got.shape, bool)
+    faces[1:-1, 1:-1, 1:-1] = False
+    assert np.abs(got[faces] - v_o[faces]).max() <= 1e-12 * np.abs(v_o[faces]).max()
+    err = wnorm(xs, got - v_o) / wnorm(xs, v_o)
+    say("  rel W-norm error vs oracle %.3e, iters %d" % (err, info["iters"]))
+    assert err <= 1e-9
+    # the oracle's own operator confirms the residual
+    assert oracle_mod.rel_residual(xs, rho_o, got) <= 2e-12
+    g.close()
+
+
+def test_solve_ragged_noncubic_zero_faces(torch, L, oracle_mod):
+    say("solve ragged 70x45x97, bc=0")
+    rng = np.random.default_rng(14)
+    xs = [graded(rng, n, -8, 8) for n in (70, 45, 97)]
+    rho = np.zeros((97, 45, 70))
+    rho[1:-1, 1:-1, 1:-1] = rng.normal(size=(95, 43, 68))
+    g = L.Grid(*xs)
+    v = g.empty()
+    info = g.poisson_solve(to_dev(torch, rho), v, rtol=1e-12, bc=0)
+    got = v.cpu().numpy()
+    want = np.zeros_like(rho)
+    cyc, rel, _ = oracle_mod.solve(xs, rho, want, rtol=1e-12)
+    err = wnorm(xs, got - want) / wnorm(xs, want)
+    assert err <= 1e-9 and info["rel_resid"] <= 1e-12
+    assert np.all(got[0] == 0) and np.all(got[:, :, -1] == 0)
+    g.close()
+
+
+def test_levels_match_oracle_hierarchy(torch, L, oracle_mod):
+    w = I.config(3)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    got = np.array(g.levels())
+    want = oracle_mod.hierarchy_sizes(xs)
+    assert np.array_equal(got, want)
+    g.close()
+
+
+def test_sphere_interp_matches_oracle(torch, L, oracle_mod):
+    say("sphere interp config 2 n=129")
+    w = I.config(2)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    res = L.hartree_step(g, w.atoms)
+    v = res["v"].cpu().numpy()
+    A = I.atom_arrays(w.atoms)
+    pts = oracle_mod.sphere_points(A["centers"], A["radius"], I.default_directions())
+    want = oracle_mod.interp(xs, v, pts).reshape(len(w.atoms), 64)
+    assert np.abs(res["sphere"] - want).max() <= 1e-13 * np.abs(want).max()
+    # explicit directions; radius 0 puts the point exactly on a node, where
+    # the interpolant returns that node's value
+    d = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, -1.0]])
+    c = np.array([[xs[0][60], xs[1][70], xs[2][64]]])
+    got = g.sphere_interp(res["v"], c, [0.0], d)
+    assert got[0, 0] == v[64, 70, 60] and got[0, 1] == v[64, 70, 60]
+    g.close()
+
+
+# --------------------------------------------------- full-size properties
+def test_full_size_257_properties(torch, L, oracle_mod):
+    """The 55-atom 257^3 workload: the oracle's operator confirms the GPU
+    residual for the FP64 and the mixed solve, the two agree, the discrete
+    Gauss law holds, and sampled density values match the oracle."""
+    say("full size 257^3 config 3")
+    w = I.config(3)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    v64 = g.empty()
+    i64 = g.poisson_solve(rho, v64, rtol=1e-10)
+    v32 = g.empty()
+    i32 = g.poisson_solve(rho, v32, rtol=1e-10, precision=1)
+    say("  fp64 iters %d (%.1f ms), mixed refinements %d vcycles %d (%.1f ms)" %
+        (i64["iters"], i64["ms_total"], i32["refinements"], i32["vcycles"], i32["ms_total"]))
+    rho_h = rho.cpu().numpy()
+    a = v64.cpu().numpy()
+    b = v32.cpu().numpy()
+    assert oracle_mod.rel_residual(xs, rho_h, a) <= 1.2e-10
+    assert oracle_mod.rel_residual(xs, rho_h, b) <= 1.2e-10
+    assert wnorm(xs, a - b) / wnorm(xs, a) <= 1e-8
+    # sampled density values against the oracle's full evaluation
+    want = oracle_mod.pseudo_density(xs, I.atom_arrays(w.atoms))
+    rng = np.random.default_rng(15)
+    idx = tuple(rng.integers(0, 257, size=(3, 20000)))
+    assert np.abs(rho_h[idx] - want[idx]).max() <= 1e-12 * np.abs(want).max()
+    assert np.abs(rho_h - want).max() <= 1e-12 * np.abs(want).max()
+    # Gauss: flux through the faces = 4 pi * interior charge (to the tolerance)
+    mx, my, mz = (dual(x) for x in xs)
+    hx, hy, hz = (np.diff(x) for x in xs)
+    s = slice(1, -1)
+    flux = ((a[s, s, 0] - a[s, s, 1]) / hx[0] * np.outer(mz[s], my[s])).sum()
+    flux += ((a[s, s, -1] - a[s, s, -2]) / hx[-1] * np.outer(mz[s], my[s])).sum()
+    flux += ((a[s, 0, s] - a[s, 1, s]) / hy[0] * np.outer(mz[s], mx[s])).sum()
+    flux += ((a[s, -1, s] - a[s, -2, s]) / hy[-1] * np.outer(mz[s], mx[s])).sum()
+    flux += ((a[0, s, s] - a[1, s, s]) / hz[0] * np.outer(my[s], mx[s])).sum()
+    flux += ((a[-1, s, s] - a[-2, s, s]) / hz[-1] * np.outer(my[s], mx[s])).sum()
+    vol = np.einsum("k,j,i->kji", mz, my, mx)
+    q_in = (vol * rho_h)[s, s, s].sum()
+    assert abs(flux - 4 * math.pi * q_in) <= 1e-6 * 4 * math.pi * abs(q_in)
+    g.close()
+
+
+# ------------------------------------------------------------ edge cases
+def test_failure_paths(torch, L, oracle_mod):
+    say("failure paths")
+    w = I.config(2, n_override=57)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    # too few iterations: NOT_CONVERGED with info filled and a finite iterate
+    v = g.empty()
+    info = g.poisson_solve(rho, v, rtol=1e-12, max_iters=1, allow_fail=True)
+    assert info["status"] == L.ERR_NOT_CONVERGED and info["iters"] == 1 and 0 < info["rel_resid"] < 1
+    assert torch.isfinite(v).all()
+    # injected NaN: DIVERGED, iterate still finite
+    v = g.empty()
+    info = g.poisson_solve(rho, v, rtol=1e-12, debug_nan_iter=2, allow_fail=True)
+    assert info["status"] == L.ERR_DIVERGED
+    assert torch.isfinite(v).all()
+    # NaN in the source: ERR_ARG
+    bad = rho.clone()
+    bad[5, 5, 5] = float("nan")
+    with pytest.raises(L.LastoError) as e:
+        g.poisson_solve(bad, g.empty())
+    assert e.value.status == L.ERR_ARG
+    # bad options
+    with pytest.raises(L.LastoError):
+        g.poisson_solve(rho, g.empty(), nu1=0)
+    with pytest.raises(L.LastoError):
+        g.poisson_solve(rho, g.empty(), precision=1, method=1)
+    # faces as given (bc = 2) are kept
+    v = g.empty()
+    v[0].fill_(1.25)
+    g.poisson_solve(rho, v, bc=2, rtol=1e-10)
+    assert bool((v[0] == 1.25).all())
+    # a point outside the box
+    with pytest.raises(L.LastoError):
+        g.sphere_interp(v, np.array([[100.0, 0, 0]]), [1.0])
+    # guess = 1 ignores the interior given
+    v1 = g.empty()
+    v1.fill_(7.0)
+    g.poisson_solve(rho, v1, guess=1, rtol=1e-12)
+    v2 = g.empty()
+    g.poisson_solve(rho, v2, rtol=1e-12)
+    assert float((v1 - v2).abs().max()) <= 1e-9 * float(v2.abs().max())
+    g.close()
+
+
+def test_profile_counts_sweeps(torch, L, oracle_mod):
+    w = I.config(2, n_override=65)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    info = g.poisson_solve(rho, g.empty(), profile=1)
+    assert info["smooth_launches"] == 4 * info["vcycles"]
+    assert info["smooth_ms"] > 0 and info["smooth_bytes"] > 0
+    info = g.poisson_solve(rho, g.empty())
+    assert info["smooth_launches"] == 0
+    g.close()
