@@ -108,6 +108,9 @@ def main():
     log("bench: fp64 solve %.3f ms, iters %d, smoother %.1f GB/s (avg %.1f us)"
         % (fp64_ms, fp64[-1]["iters"], fp64_gbs, f_ms * 1e3 / max(f_l, 1)))
 
+    # algorithmic bytes of one launch (a half-sweep), per interior node of the
+    # grid: 12 B (FP64) or 6 B (FP32) for a half-sweep that reads the other
+    # colour, f and writes its own colour (24 / 12 B per full sweep)
     interior = (n - 2) ** 3
     sm_bpp = (sm_bytes / launches / interior) if launches else 0.0
     out = {
@@ -134,8 +137,8 @@ def main():
         "fp64_smoother_frac": round(fp64_gbs / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_smooth<%s> finest level" % ("float" if mixed else "double"),
-                     "bytes_per_point": round(sm_bpp, 3), "avg_launch_us": round(avg_launch_us, 2),
+                     "kernel": "k_half<%s> (red-black half-sweep, finest level)" % ("float" if mixed else "double"),
+                     "bytes_per_point_per_launch": round(sm_bpp, 3), "avg_launch_us": round(avg_launch_us, 2),
                      "launches": launches},
     }
 

@@ -157,6 +157,10 @@ lasto_status build_level_tables(lasto_grid g, int l)
     L.view.nx = L.n[0];
     L.view.ny = L.n[1];
     L.view.nz = L.n[2];
+    // split-layout row: entries 0..nx/2 of one colour, padded to 16 (128 B in FP64)
+    L.view.W = ((L.n[0] / 2 + 1) + 15) / 16 * 16;
+    L.view.cs = (size_t)L.n[2] * L.n[1] * L.view.W;
+    L.nsplit = 2 * L.view.cs;
     return LASTO_OK;
 }
 
@@ -173,10 +177,8 @@ static void free_grid(lasto_grid g)
         Level& L = g->lev[l];
         (void)hipFree(L.dtab);
         (void)hipFree(L.dtabi);
-        for (int s = 0; s < 2; ++s) {
-            (void)hipFree(L.u64[s]);
-            (void)hipFree(L.u32[s]);
-        }
+        (void)hipFree(L.u64);
+        (void)hipFree(L.u32);
         (void)hipFree(L.f64);
         (void)hipFree(L.r64);
         (void)hipFree(L.f32);
@@ -197,6 +199,7 @@ static void free_grid(lasto_grid g)
     (void)hipFree(g->scalars);
     (void)hipFree(g->moments);
     (void)hipFree(g->stage);
+    (void)hipFree(g->tail_dev);
     if (g->h_scalars) (void)hipHostFree(g->h_scalars);
     for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
     g->prof_ev.clear();
@@ -268,30 +271,25 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
         }
         g->nlev++;
     }
-    {
-        const Level& Lc = g->lev[g->nlev - 1];
-        if ((size_t)Lc.n[0] * Lc.n[1] * Lc.n[2] > 4096) {
-            free_grid(g);
-            delete g;
-            return fail(LASTO_ERR_ARG, "lasto_grid_create: coarsest level too large");
-        }
-    }
     lasto_status st = LASTO_OK;
     for (int l = 0; l < g->nlev && st == LASTO_OK; ++l) {
         Level& L = g->lev[l];
         L.npts = (size_t)L.n[0] * L.n[1] * L.n[2];
         st = build_level_tables(g, l);
         if (st != LASTO_OK) break;
-        for (int s = 0; s < 2 && st == LASTO_OK; ++s) {
-            st = alloc_zero(g, (void**)&L.u64[s], sizeof(double) * L.npts);
-            if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.u32[s], sizeof(float) * L.npts);
+        // V-cycle arrays in the split layout (level 0 uses the Krylov vectors
+        // below for its correction and right-hand side)
+        const size_t ns = L.nsplit;
+        if (l > 0) {
+            st = alloc_zero(g, (void**)&L.u64, sizeof(double) * ns);
+            if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.u32, sizeof(float) * ns);
+            if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.f64, sizeof(double) * ns);
+            if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.f32, sizeof(float) * ns);
         }
-        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.f64, sizeof(double) * L.npts);
-        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.r64, sizeof(double) * L.npts);
-        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.f32, sizeof(float) * L.npts);
-        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.r32, sizeof(float) * L.npts);
+        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.r64, sizeof(double) * ns);
+        if (st == LASTO_OK) st = alloc_zero(g, (void**)&L.r32, sizeof(float) * ns);
     }
-    const size_t N = g->lev[0].npts;
+    const size_t N = g->lev[0].nsplit;
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->r, sizeof(double) * N);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p[0], sizeof(double) * N);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p[1], sizeof(double) * N);
@@ -304,12 +302,12 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->e32, sizeof(float) * N);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->z32, sizeof(float) * N);
     // one partial per block of any reducing launch on any level (the finest
-    // level's pointwise launch has the most blocks), and 25 per block of the
-    // moment reduction
+    // level's pointwise launch has the most blocks; a fused dot spans two
+    // half-sweeps), and 25 per block of the moment reduction
     size_t nparts = (size_t)25 * kReduceBlocks;
     for (int l = 0; l < g->nlev; ++l) {
         nparts = std::max(nparts, (size_t)interior_blocks(g->lev[l].view));
-        nparts = std::max(nparts, (size_t)smooth_blocks(g->lev[l].view));
+        nparts = std::max(nparts, (size_t)2 * half_blocks(g->lev[l].view));
     }
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->partials, sizeof(double) * nparts);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->scalars, sizeof(double) * kNumScalars);
@@ -321,6 +319,30 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
     if (st == LASTO_OK) {
         if (hipHostMalloc((void**)&g->h_scalars, sizeof(double) * kNumScalars) != hipSuccess)
             st = fail(LASTO_ERR_ALLOC, "lasto_grid_create: pinned host scalars");
+    }
+    if (st == LASTO_OK) {
+        // level descriptors of the single-workgroup tail: every level from the
+        // first one with at most kTailMaxPts nodes down to the coarsest
+        g->tail_top = g->nlev - 1;
+        for (int l = 0; l < g->nlev; ++l)
+            if (g->lev[l].npts <= kTailMaxPts) {
+                g->tail_top = l;
+                break;
+            }
+        std::vector<TailLevel> tl(g->nlev);
+        for (int l = 0; l < g->nlev; ++l) {
+            Level& L = g->lev[l];
+            tl[l].V = L.view;
+            tl[l].u64 = l ? L.u64 : g->z;
+            tl[l].f64 = l ? L.f64 : g->r;
+            tl[l].r64 = L.r64;
+            tl[l].u32 = l ? L.u32 : g->z32;
+            tl[l].f32 = l ? L.f32 : g->r32;
+            tl[l].r32 = L.r32;
+        }
+        if (hipMalloc((void**)&g->tail_dev, sizeof(TailLevel) * g->nlev) != hipSuccess ||
+            hipMemcpy(g->tail_dev, tl.data(), sizeof(TailLevel) * g->nlev, hipMemcpyHostToDevice) != hipSuccess)
+            st = fail(LASTO_ERR_HIP, "lasto_grid_create: tail level table");
     }
     if (st == LASTO_OK) {
         if (hipError_t e = hipStreamSynchronize(g->stream); e != hipSuccess)

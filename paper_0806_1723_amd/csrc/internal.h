@@ -69,27 +69,62 @@ struct Axis {
     const double* pw;
 };
 
+// Colour-split storage of multigrid arrays: node (i,j,k) of colour
+// c = (i+j+k) & 1 lives at [c][k][j][i >> 1] in rows of W (padded) entries,
+// cs = nz*ny*W apart between colours. A red-black half-sweep then reads one
+// colour array and writes the other, both contiguous in x.
 struct LevelView {
     int nx, ny, nz;
+    int W;          // padded row length of one colour (>= (nx+1)/2)
+    size_t cs;      // colour stride = nz * ny * W
     Axis ax[3];
 };
 
+__host__ __device__ __forceinline__ size_t sidx(const LevelView& L, int i, int j, int k)
+{
+    return (size_t)((i + j + k) & 1) * L.cs + ((size_t)k * L.ny + j) * L.W + (i >> 1);
+}
+
 struct Level {
     int n[3];
-    size_t npts;
+    size_t npts;       // nx*ny*nz
+    size_t nsplit;     // 2*cs elements of a split array
     std::vector<double> hx[3];     // host copies of coordinates
     std::vector<int> keep[3];      // index in the finer level (level > 0)
     double* dtab = nullptr;        // device table block
     int* dtabi = nullptr;
     LevelView view;
-    // work arrays (level 0: fine-level PCG/V-cycle vectors; coarse: V-cycle vectors)
-    double* u64[2] = {nullptr, nullptr};
+    // V-cycle work arrays (split layout): correction, right-hand side, residual
+    double* u64 = nullptr;
     double* f64 = nullptr;
     double* r64 = nullptr;
-    float* u32[2] = {nullptr, nullptr};
+    float* u32 = nullptr;
     float* f32 = nullptr;
     float* r32 = nullptr;
 };
+
+// A level as the single-workgroup tail kernel sees it (an array of these
+// lives in device memory). Level 0's correction and right-hand side are the
+// fine-level Krylov vectors z and r.
+struct TailLevel {
+    LevelView V;
+    double *u64, *f64, *r64;
+    float *u32, *f32, *r32;
+};
+
+template <typename T> struct TailBuf;
+template <> struct TailBuf<double> {
+    __host__ __device__ static double* u(const TailLevel& t) { return t.u64; }
+    __host__ __device__ static double* f(const TailLevel& t) { return t.f64; }
+    __host__ __device__ static double* r(const TailLevel& t) { return t.r64; }
+};
+template <> struct TailBuf<float> {
+    __host__ __device__ static float* u(const TailLevel& t) { return t.u32; }
+    __host__ __device__ static float* f(const TailLevel& t) { return t.f32; }
+    __host__ __device__ static float* r(const TailLevel& t) { return t.r32; }
+};
+
+constexpr size_t kTailMaxPts = 16384;   // levels at or below this size run in the tail kernel
 
 }  // namespace lasto
 
@@ -99,24 +134,27 @@ struct lasto_grid_s {
     hipStream_t stream = nullptr;
     int device = 0;
     lasto::Level lev[lasto::kMaxLevels];
-    // fine-level Krylov vectors (FP64): residual, search direction (ping-pong), A p, z
+    int tail_top = 0;                      // first level handled by the tail kernel
+    lasto::TailLevel* tail_dev = nullptr;  // device [nlev]
+    // fine-level Krylov vectors (FP64, split layout): residual, preconditioned
+    // residual, search direction (ping-pong), A p
     double* r = nullptr;
+    double* z = nullptr;
     double* p[2] = {nullptr, nullptr};
     double* q = nullptr;
-    double* z = nullptr;
-    // FP32 inner-solve vectors on the fine level
+    // FP32 inner-solve vectors on the fine level (split layout)
     float* r32 = nullptr;
+    float* z32 = nullptr;
     float* p32[2] = {nullptr, nullptr};
     float* q32 = nullptr;
     float* e32 = nullptr;
-    float* z32 = nullptr;
     // reductions
-    double* partials = nullptr;     // [kReduceBlocks * 32]
+    double* partials = nullptr;
     double* scalars = nullptr;      // [kNumScalars]
     double* h_scalars = nullptr;    // pinned host mirror
     double* moments = nullptr;      // device [25]
     // interpolation / atom staging
-    double* stage = nullptr;        // device staging for points / atoms
+    double* stage = nullptr;
     size_t stage_bytes = 0;
     double box_center[3] = {0, 0, 0};
     // optional event timing of the finest-level sweeps (solve opts.profile)
@@ -130,47 +168,67 @@ struct lasto_grid_s {
 namespace lasto {
 
 // ----------------------------------------------------------------- kernels
-// blocks of the smoother and of the pointwise interior launches (each writes
-// one reduction partial per block)
-int smooth_blocks(const LevelView& L);
-int interior_blocks(const LevelView& L);
-// smoother / transfer / krylov launchers (stream-ordered, no host sync)
+// Block counts of the reducing launches (each writes one partial per block).
+int half_blocks(const LevelView& L);       // one half-sweep
+int interior_blocks(const LevelView& L);   // pointwise interior launches
+size_t split_elems(const LevelView& L);
+
+// Red-black half-sweep on A u = bscale f, in place in the split layout:
+// nodes of colour c solve their equation from the other colour's values.
+// zero_in: the other colour is read as zero. dotp (optional): per-block
+// partials of sum vol * f * u_new over the updated nodes.
 template <typename T>
-hipError_t launch_smooth(const LevelView& L, const T* uin, const T* f, T* uout, T bscale, int first,
-                         int zero_in, double* dot_partials, hipStream_t s);
+hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
+                       hipStream_t s);
 template <typename T>
-hipError_t launch_residual(const LevelView& L, const T* u, const T* f, T bscale, T* r, hipStream_t s);
+hipError_t launch_residual(const LevelView& L, const T* u, const T* f, T* r, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s);
+// The same transfers exploiting the red-black ordering of the cycle: after
+// a pre-smoothing that ends with a black half-sweep the residual vanishes on
+// black nodes (residual_colour computes one colour; restrict_red skips black
+// fine nodes), and before a post-smoothing that starts with a black
+// half-sweep only red nodes need the coarse correction (prolong_red).
 template <typename T>
-hipError_t launch_coarse_solve(const LevelView& L, T* u, const T* f, int sweeps, hipStream_t s);
+hipError_t launch_residual_colour(const LevelView& L, const T* u, const T* f, T* r, int colour, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s);
+// V(nu1, nu2) from zero on levels lv[0..nl-1] in one workgroup; the
+// coarsest runs csweeps (red, black) sweeps then csweeps (black, red).
+template <typename T>
+hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweeps, hipStream_t s);
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_apply_dot(const LevelView& L, const T* p, T* q, double* partials, hipStream_t s);
 template <typename T>
-hipError_t launch_residual_norm(const LevelView& L, const double* u, const double* f, double bscale, T* r,
-                                double* partials, hipStream_t s);
-template <typename T>
 hipError_t launch_dot(const LevelView& L, const T* a, const T* b, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pnew, const double* scal,
                            int i_num, int i_den, int first, hipStream_t s);
+// x += alpha p, r -= alpha q (split), alpha = scal[i_num]/scal[i_den]; x is a
+// natural-layout FP64 array when x_nat, else a split T array.
 template <typename T>
-hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal,
-                            int i_num, int i_den, double* partials, hipStream_t s);
-hipError_t launch_add_f32_to_f64(const LevelView& L, double* u, const float* e, hipStream_t s);
-hipError_t launch_scale_f64_to_f32(const LevelView& L, const double* r, float* r32, const double* scal,
-                                   int i_norm2, hipStream_t s);
-hipError_t launch_add_scaled_f32_to_f64(const LevelView& L, double* u, const float* e, const double* scal,
-                                        int i_norm2, hipStream_t s);
+hipError_t launch_update_xr(const LevelView& L, void* x, int x_nat, T* r, const T* p, const T* q,
+                            const double* scal, int i_num, int i_den, double* partials, hipStream_t s);
+// natural-layout fine-level helpers
+hipError_t launch_residual_nat(const LevelView& L, const double* v, const double* rho, double bscale, double* r_split,
+                               double* partials, int interior_zero, hipStream_t s);
+hipError_t launch_apply_nat(const LevelView& L, const double* u, double* Au, hipStream_t s);
+hipError_t launch_add_nat(const LevelView& L, double* v, const double* e_split, hipStream_t s);
+hipError_t launch_scale_to32(const LevelView& L, const double* r, float* r32, const double* scal, int i_norm2,
+                             hipStream_t s);
+hipError_t launch_add_scaled32_nat(const LevelView& L, double* v, const float* e32, const double* scal, int i_norm2,
+                                   hipStream_t s);
+hipError_t launch_nat_to_split(const LevelView& L, const double* a, double* s_out, hipStream_t s);
+hipError_t launch_split_to_nat(const LevelView& L, const double* s_in, double* a, hipStream_t s);
+template <typename T>
+hipError_t launch_fill_zero(T* a, size_t n, hipStream_t s);
 hipError_t launch_inject_nan(double* r, size_t idx, hipStream_t s);
-
-// V-cycle (preconditioner): solve A e = f approximately from e = 0, zero faces.
-template <typename T>
-lasto_status vcycle(lasto_grid g, int nu1, int nu2, T* e_out, const T* f, double* rz_partials);
 
 // source, boundary, interpolation
 struct AtomDev {

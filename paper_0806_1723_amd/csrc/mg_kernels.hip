@@ -6,6 +6,11 @@
 //   (A u)_n = sum_d am_d (u_{n-e_d} - u_n) + ap_d (u_{n+e_d} - u_n)
 // with am = 1/(h_- m), ap = 1/(h_+ m), m = (h_- + h_+)/2: the three-point
 // second difference on a nonuniform mesh. Equation A u = bscale * f.
+//
+// Multigrid arrays use the colour-split layout of internal.h (sidx). Natural
+// [nz][ny][nx] arrays appear only at the fine level (the caller's rho and v).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lasto {
@@ -17,7 +22,8 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Deterministic block sum (fixed tree); result valid in thread 0.
+// Deterministic block sum (fixed tree); result valid in thread 0. Every
+// thread of the block must call it.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh)
 {
@@ -38,255 +44,391 @@ __device__ __forceinline__ int block_linear()
     return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 }
 
-// ---------------------------------------------------------- smoother
-// One fused red-black Gauss-Seidel sweep, out of place: uout = S(uin).
-// Nodes of parity `first` ((i+j+k)&1 == first) are updated from uin; the
-// other colour is then updated from those new values. Because the sweep reads
-// only uin and writes only uout, every tile recomputes the first-colour
-// values it needs on its one-node ring, and the result does not depend on
-// the tiling or on the order in which tiles run.
-//
-// A workgroup owns a TX x TY tile of (i,j) columns and marches in z over a
-// chunk of KC planes, keeping three planes of uin (tile + 2-node ring) and
-// three planes of the half-updated field H (tile + 1-node ring) in LDS.
-constexpr int SM_TX = 64, SM_TY = 4, SM_KC = 16, SM_NT = SM_TX * SM_TY;
-
-template <typename T>
-__global__ __launch_bounds__(SM_NT) void k_smooth(LevelView L, const T* __restrict__ uin,
-                                                   const T* __restrict__ f, T* __restrict__ uout, T bscale,
-                                                   int first, int zero_in, double* __restrict__ dotp)
+__device__ __forceinline__ double vol_at(const LevelView& L, int i, int j, int k)
 {
-    __shared__ T Us[3][SM_TY + 4][SM_TX + 4];
-    __shared__ T Hs[3][SM_TY + 2][SM_TX + 2];
-    __shared__ double red[SM_NT / 64];
+    return L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k];
+}
 
-    const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const int i0 = 1 + blockIdx.x * SM_TX, j0 = 1 + blockIdx.y * SM_TY;
-    const int k0 = 1 + blockIdx.z * SM_KC;
-    const int k1 = min(k0 + SM_KC, nz - 1);
-    const int tid = threadIdx.x;
-    const size_t sxy = (size_t)nx * ny;
-    const double* __restrict__ amx = L.ax[0].am;
-    const double* __restrict__ apx = L.ax[0].ap;
-    const double* __restrict__ amy = L.ax[1].am;
-    const double* __restrict__ apy = L.ax[1].ap;
-    const double* __restrict__ amz = L.ax[2].am;
-    const double* __restrict__ apz = L.ax[2].ap;
+size_t split_elems(const LevelView& L) { return 2 * L.cs; }
 
-    auto loadU = [&](int k) {
-        T(*dst)[SM_TX + 4] = Us[(k + 3) % 3];
-        for (int e = tid; e < (SM_TY + 4) * (SM_TX + 4); e += SM_NT) {
-            const int a = e % (SM_TX + 4), b = e / (SM_TX + 4);
-            const int i = i0 - 2 + a, j = j0 - 2 + b;
-            T val = T(0);
-            if (!zero_in && i >= 0 && i < nx && j >= 0 && j < ny) val = uin[(size_t)k * sxy + (size_t)j * nx + i];
-            dst[b][a] = val;
+// Solve of one node's equation from its six neighbours (GS update).
+template <typename T>
+__device__ __forceinline__ T gs_point(const LevelView& L, const T* __restrict__ u, int i, int j, int k, T fb)
+{
+    const T cxm = (T)L.ax[0].am[i], cxp = (T)L.ax[0].ap[i];
+    const T cym = (T)L.ax[1].am[j], cyp = (T)L.ax[1].ap[j];
+    const T czm = (T)L.ax[2].am[k], czp = (T)L.ax[2].ap[k];
+    T s = cxm * u[sidx(L, i - 1, j, k)] + cxp * u[sidx(L, i + 1, j, k)];
+    s += cym * u[sidx(L, i, j - 1, k)] + cyp * u[sidx(L, i, j + 1, k)];
+    s += czm * u[sidx(L, i, j, k - 1)] + czp * u[sidx(L, i, j, k + 1)];
+    return (s - fb) / (cxm + cxp + cym + cyp + czm + czp);
+}
+
+// (A u) at interior (i,j,k) of a split array
+template <typename T>
+__device__ __forceinline__ T apply_split(const LevelView& L, const T* __restrict__ u, int i, int j, int k, T c)
+{
+    T a = (T)L.ax[0].am[i] * (u[sidx(L, i - 1, j, k)] - c) + (T)L.ax[0].ap[i] * (u[sidx(L, i + 1, j, k)] - c);
+    a += (T)L.ax[1].am[j] * (u[sidx(L, i, j - 1, k)] - c) + (T)L.ax[1].ap[j] * (u[sidx(L, i, j + 1, k)] - c);
+    a += (T)L.ax[2].am[k] * (u[sidx(L, i, j, k - 1)] - c) + (T)L.ax[2].ap[k] * (u[sidx(L, i, j, k + 1)] - c);
+    return a;
+}
+
+// restricted value at coarse (I,J,K): the up-to-3x3x3 fine nodes around
+// (rf[I], rf[J], rf[K]) weighted by rw_x rw_y rw_z (M_c^-1 P^T M_f).
+// RED_ONLY: the fine residual is known to vanish on black nodes (as it does
+// right after a black half-sweep), so they are not read.
+template <typename T, bool RED_ONLY>
+__device__ __forceinline__ T restrict_point(const LevelView& F, const LevelView& C, const T* __restrict__ r, int I,
+                                            int J, int K)
+{
+    const int fi = C.ax[0].rf[I], fj = C.ax[1].rf[J], fk = C.ax[2].rf[K];
+    const double* wx = C.ax[0].rw + 3 * I;
+    const double* wy = C.ax[1].rw + 3 * J;
+    const double* wz = C.ax[2].rw + 3 * K;
+    T acc = T(0);
+    for (int c = 0; c < 3; ++c) {
+        const T z = (T)wz[c];
+        if (z == T(0)) continue;
+        for (int b = 0; b < 3; ++b) {
+            const T y = (T)wy[b];
+            if (y == T(0)) continue;
+            const int jj = fj - 1 + b, kk = fk - 1 + c;
+            T sx = T(0);
+            for (int a = 0; a < 3; ++a) {
+                const T x = (T)wx[a];
+                if (RED_ONLY && ((fi - 1 + a + jj + kk) & 1)) continue;
+                if (x != T(0)) sx += x * r[sidx(F, fi - 1 + a, jj, kk)];
+            }
+            acc += z * y * sx;
         }
-    };
+    }
+    return acc;
+}
 
-    const int kstart = k0 - 1;
-    if (kstart - 1 >= 0) loadU(kstart - 1);
-    loadU(kstart);
+// interpolated coarse correction at fine (i,j,k): the 2x2x2 coarse values
+// around it with linear weights in physical coordinates (weight 1 at kept
+// nodes); coarse neighbours with zero weight are not read
+template <typename T>
+__device__ __forceinline__ T prolong_point(const LevelView& C, const T* __restrict__ e, int i, int j, int k)
+{
+    const int I = C.ax[0].pc[i], J = C.ax[1].pc[j], K = C.ax[2].pc[k];
+    const T wx[2] = {(T)C.ax[0].pw[2 * i], (T)C.ax[0].pw[2 * i + 1]};
+    const T wy[2] = {(T)C.ax[1].pw[2 * j], (T)C.ax[1].pw[2 * j + 1]};
+    const T wz[2] = {(T)C.ax[2].pw[2 * k], (T)C.ax[2].pw[2 * k + 1]};
+    T w = T(0);
+    for (int c = 0; c < 2; ++c) {
+        if (wz[c] == T(0)) continue;
+        T v = T(0);
+        for (int b = 0; b < 2; ++b) {
+            if (wy[b] == T(0)) continue;
+            T a = T(0);
+            for (int q = 0; q < 2; ++q)
+                if (wx[q] != T(0)) a += wx[q] * e[sidx(C, I + q, J + b, K + c)];
+            v += wy[b] * a;
+        }
+        w += wz[c] * v;
+    }
+    return w;
+}
 
-    // tile point owned by this thread for the output step
-    const int tx = tid % SM_TX, ty = tid / SM_TX;
-    const int io = i0 + tx, jo = j0 + ty;
-    const bool own = (io <= nx - 2) && (jo <= ny - 2);
+// --------------------------------------------------------- half-sweep
+// Workgroups are dispatched to the eight XCDs in turn; tile (id % 8) * per +
+// id / 8 hands each XCD a contiguous run of tiles, so tiles that share halo
+// rows share an L2. Ids past the last tile only contribute a zero partial.
+__device__ __forceinline__ int xcd_tile(int id, int per) { return (id & 7) * per + (id >> 3); }
+
+constexpr int HS_X = 64, HS_Y = 4, HS_NT = HS_X * HS_Y, HS_KC_MAX = 16, HS_BLOCKS = 2048;
+
+struct HalfShape {
+    int nbx, nby, nbz, nb, per, grid, kc;
+};
+
+// Planes per thread: as many as keep about HS_BLOCKS workgroups (the z-march
+// saves re-reads, but its planes are a serial chain of loads, so small levels
+// march one plane per thread).
+static HalfShape half_shape(const LevelView& L)
+{
+    HalfShape h;
+    const int mcount = (L.nx - 2) / 2 + 1;   // i >> 1 over every interior i
+    h.nbx = (mcount + HS_X - 1) / HS_X;
+    h.nby = (L.ny - 2 + HS_Y - 1) / HS_Y;
+    const long tiles = (long)h.nbx * h.nby;
+    h.kc = (int)std::min<long>(HS_KC_MAX, std::max<long>(1, (long)(L.nz - 2) * tiles / HS_BLOCKS));
+    h.nbz = (L.nz - 2 + h.kc - 1) / h.kc;
+    h.nb = h.nbx * h.nby * h.nbz;
+    h.per = (h.nb + 7) / 8;
+    h.grid = 8 * h.per;
+    return h;
+}
+
+int half_blocks(const LevelView& L) { return half_shape(L).grid; }
+
+// Nodes of colour c solve their own equation with the other colour's values
+// (RESID = false):
+//   u_n = (sum_d am_d u_{n-e_d} + ap_d u_{n+e_d} - bscale f_n) / sum_d (am_d + ap_d),
+// or (RESID = true) get their residual out_n = bscale f_n - (A u)_n.
+// A thread owns the entries [c][k][j][m] for one (j, m) and marches over a
+// chunk of planes, keeping the other colour's z-neighbours in a register
+// queue (entry m of the other colour on planes k-1, k, k+1 holds both z
+// neighbours and one x neighbour) and loading plane k+1's operands while it
+// computes plane k. `uo` (the other colour), `fc` and `out` (this colour) are
+// distinct arrays, so the loads may run ahead of the store.
+template <typename T, bool RESID>
+__global__ __launch_bounds__(HS_NT) void k_half(LevelView L, const T* __restrict__ uo, const T* __restrict__ fc,
+                                                const T* __restrict__ ucen, T* __restrict__ out, int c, int zero_in,
+                                                T bscale, double* __restrict__ dotp, int nbx, int nby, int nb, int per,
+                                                int kc)
+{
+    __shared__ double red[HS_NT / 64];
+    const int t = xcd_tile(blockIdx.x, per);
     double dot = 0.0;
-
-    for (int kk = kstart; kk <= k1; ++kk) {
-        if (kk + 1 <= nz - 1) loadU(kk + 1);
-        __syncthreads();
-        // H at plane kk over the tile and its one-node ring
-        {
-            T(*H)[SM_TX + 2] = Hs[(kk + 3) % 3];
-            T(*U)[SM_TX + 4] = Us[(kk + 3) % 3];
-            const bool bplane = (kk == 0) || (kk == nz - 1);
-            for (int e = tid; e < (SM_TY + 2) * (SM_TX + 2); e += SM_NT) {
-                const int a = e % (SM_TX + 2), b = e / (SM_TX + 2);
-                const int i = i0 - 1 + a, j = j0 - 1 + b;
-                if (i > nx - 1 || j > ny - 1) continue;
-                T uc = U[b + 1][a + 1];
-                const bool bnode = bplane || i == 0 || i == nx - 1 || j == 0 || j == ny - 1;
-                if (!bnode && (((i + j + kk) & 1) == first)) {
-                    T(*Um)[SM_TX + 4] = Us[(kk + 2) % 3];
-                    T(*Up)[SM_TX + 4] = Us[(kk + 1) % 3];
-                    const T cxm = (T)amx[i], cxp = (T)apx[i], cym = (T)amy[j], cyp = (T)apy[j];
-                    const T czm = (T)amz[kk], czp = (T)apz[kk];
-                    T s = cxm * U[b + 1][a] + cxp * U[b + 1][a + 2];
-                    s += cym * U[b][a + 1] + cyp * U[b + 2][a + 1];
-                    s += czm * Um[b + 1][a + 1] + czp * Up[b + 1][a + 1];
-                    const T d = cxm + cxp + cym + cyp + czm + czp;
-                    uc = (s - bscale * f[(size_t)kk * sxy + (size_t)j * nx + i]) / d;
-                }
-                H[b][a] = uc;
+    const int m = (t % nbx) * HS_X + (threadIdx.x & (HS_X - 1));
+    const int j = 1 + ((t / nbx) % nby) * HS_Y + (threadIdx.x >> 6);
+    if (t < nb && j <= L.ny - 2 && m <= (L.nx - 2) / 2) {
+        const int k0 = 1 + (t / (nbx * nby)) * kc;
+        const int k1 = min(k0 + kc, L.nz - 1);
+        const int nx = L.nx;
+        const int W = L.W;
+        const size_t plane = (size_t)L.ny * W;
+        const size_t row = (size_t)j * W + m;
+        const T cym = (T)L.ax[1].am[j], cyp = (T)L.ax[1].ap[j];
+        const double* __restrict__ amx = L.ax[0].am;
+        const double* __restrict__ apx = L.ax[0].ap;
+        // operands of plane k: z queue, the other x neighbour, y neighbours, f, centre
+        T zm = T(0), zc = T(0), zp = T(0), xo = T(0), ym = T(0), yp = T(0), fv, cv = T(0);
+        auto load_plane = [&](int k, T& x_o, T& y_m, T& y_p, T& f_v, T& c_v) {
+            const size_t at = (size_t)k * plane + row;
+            const int o = (c + j + k) & 1;
+            f_v = fc[at];
+            if (RESID) c_v = ucen[at];
+            if (!zero_in) {
+                x_o = o ? uo[at + 1] : uo[at - (m > 0 ? 1 : 0)];
+                y_m = uo[at - W];
+                y_p = uo[at + W];
             }
+        };
+        if (!zero_in) {
+            zm = uo[(size_t)(k0 - 1) * plane + row];
+            zc = uo[(size_t)k0 * plane + row];
+            zp = uo[(size_t)(k0 + 1) * plane + row];
         }
-        __syncthreads();
-        const int ko = kk - 1;
-        if (ko >= k0 && own) {
-            T(*H)[SM_TX + 2] = Hs[(ko + 3) % 3];
-            const size_t idx = (size_t)ko * sxy + (size_t)jo * nx + io;
-            T out = H[ty + 1][tx + 1];
-            const T fv = f[idx];
-            if (((io + jo + ko) & 1) != first) {
-                T(*Hm)[SM_TX + 2] = Hs[(ko + 2) % 3];
-                T(*Hp)[SM_TX + 2] = Hs[(ko + 1) % 3];
-                const T cxm = (T)amx[io], cxp = (T)apx[io], cym = (T)amy[jo], cyp = (T)apy[jo];
-                const T czm = (T)amz[ko], czp = (T)apz[ko];
-                T s = cxm * H[ty + 1][tx] + cxp * H[ty + 1][tx + 2];
-                s += cym * H[ty][tx + 1] + cyp * H[ty + 2][tx + 1];
-                s += czm * Hm[ty + 1][tx + 1] + czp * Hp[ty + 1][tx + 1];
-                const T d = cxm + cxp + cym + cyp + czm + czp;
-                out = (s - bscale * fv) / d;
+        load_plane(k0, xo, ym, yp, fv, cv);
+        for (int k = k0; k < k1; ++k) {
+            // prefetch plane k+1 (and the z queue's next entry)
+            T xo_n = T(0), ym_n = T(0), yp_n = T(0), fv_n = T(0), cv_n = T(0), znext = T(0);
+            if (k + 1 < k1) {
+                load_plane(k + 1, xo_n, ym_n, yp_n, fv_n, cv_n);
+                if (!zero_in) znext = uo[(size_t)(k + 2) * plane + row];
             }
-            uout[idx] = out;
-            if (dotp) dot += L.ax[0].m[io] * L.ax[1].m[jo] * L.ax[2].m[ko] * (double)fv * (double)out;
+            const int o = (c + j + k) & 1;
+            const int i = o + 2 * m;
+            if (i >= 1 && i <= nx - 2) {
+                const size_t at = (size_t)k * plane + row;
+                const T cxm = (T)amx[i], cxp = (T)apx[i];
+                const T czm = (T)L.ax[2].am[k], czp = (T)L.ax[2].ap[k];
+                T s = T(0);
+                if (!zero_in) {
+                    // x neighbours i-1, i+1 of the other colour sit at m-1+o and m+o
+                    const T xl = o ? zc : xo;
+                    const T xr = o ? xo : zc;
+                    s = cxm * xl + cxp * xr;
+                    s += cym * ym + cyp * yp;
+                    s += czm * zm + czp * zp;
+                }
+                const T d = cxm + cxp + cym + cyp + czm + czp;
+                T res;
+                if (RESID) res = bscale * fv - (s - d * cv);
+                else res = (s - bscale * fv) / d;
+                out[at] = res;
+                if (dotp) dot += vol_at(L, i, j, k) * (double)fv * (double)res;
+            }
+            zm = zc;
+            zc = zp;
+            zp = znext;
+            xo = xo_n;
+            ym = ym_n;
+            yp = yp_n;
+            fv = fv_n;
+            cv = cv_n;
         }
     }
     if (dotp) {
-        const double t = block_sum<SM_NT>(dot, red);
-        if (tid == 0) dotp[block_linear()] = t;
+        const double s = block_sum<HS_NT>(dot, red);
+        if (threadIdx.x == 0) dotp[blockIdx.x] = s;
     }
 }
 
-static dim3 smooth_grid(const LevelView& L)
-{
-    return dim3((L.nx - 2 + SM_TX - 1) / SM_TX, (L.ny - 2 + SM_TY - 1) / SM_TY, (L.nz - 2 + SM_KC - 1) / SM_KC);
-}
-
 template <typename T>
-hipError_t launch_smooth(const LevelView& L, const T* uin, const T* f, T* uout, T bscale, int first, int zero_in,
-                         double* dot_partials, hipStream_t s)
+hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
+                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_smooth<T>, smooth_grid(L), dim3(SM_NT), 0, s, L, uin, f, uout, bscale, first, zero_in,
-                       dot_partials);
+    const HalfShape h = half_shape(L);
+    hipLaunchKernelGGL((k_half<T, false>), dim3(h.grid), dim3(HS_NT), 0, s, L, u + (size_t)(1 - colour) * L.cs,
+                       f + (size_t)colour * L.cs, (const T*)nullptr, u + (size_t)colour * L.cs, colour, zero_in, bscale,
+                       dotp, h.nbx, h.nby, h.nb, h.per, h.kc);
     return hipGetLastError();
 }
 
-int smooth_blocks(const LevelView& L)
+// residual f - A u at the nodes of one colour only (written into that
+// colour of r; the other colour of r is not touched)
+template <typename T>
+hipError_t launch_residual_colour(const LevelView& L, const T* u, const T* f, T* r, int colour, hipStream_t s)
 {
-    dim3 g = smooth_grid(L);
-    return (int)(g.x * g.y * g.z);
+    const HalfShape h = half_shape(L);
+    hipLaunchKernelGGL((k_half<T, true>), dim3(h.grid), dim3(HS_NT), 0, s, L, u + (size_t)(1 - colour) * L.cs,
+                       f + (size_t)colour * L.cs, u + (size_t)colour * L.cs, r + (size_t)colour * L.cs, colour, 0,
+                       T(1), (double*)nullptr, h.nbx, h.nby, h.nb, h.per, h.kc);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------- pointwise 3-D launches
-constexpr int PT_X = 64, PT_Y = 4, PT_NT = PT_X * PT_Y;
+// A workgroup covers a 64 x 4 tile of (i, j) interior columns over a chunk
+// of kp planes (kp chosen to keep about PT_BLOCKS workgroups); split arrays
+// are read through sidx, so a wavefront touches two contiguous runs (one per
+// colour). Reducing kernels write one partial per workgroup.
+constexpr int PT_X = 64, PT_Y = 4, PT_NT = PT_X * PT_Y, PT_BLOCKS = 4096, PT_KP_MAX = 32;
 
-static dim3 interior_grid(const LevelView& L)
+struct PtShape {
+    dim3 grid;
+    int kp;
+};
+
+static PtShape pt_shape(const LevelView& L)
 {
-    return dim3((L.nx - 2 + PT_X - 1) / PT_X, (L.ny - 2 + PT_Y - 1) / PT_Y, L.nz - 2);
+    PtShape p;
+    const int gx = (L.nx - 2 + PT_X - 1) / PT_X, gy = (L.ny - 2 + PT_Y - 1) / PT_Y;
+    const long tiles = (long)gx * gy;
+    p.kp = (int)std::min<long>(PT_KP_MAX, std::max<long>(1, (long)(L.nz - 2) * tiles / PT_BLOCKS));
+    p.grid = dim3(gx, gy, (L.nz - 2 + p.kp - 1) / p.kp);
+    return p;
 }
 
 int interior_blocks(const LevelView& L)
 {
-    dim3 g = interior_grid(L);
+    const dim3 g = pt_shape(L).grid;
     return (int)(g.x * g.y * g.z);
 }
 
+#define INTERIOR_LOOP                                                 \
+    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);       \
+    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);       \
+    const bool inside = (i <= L.nx - 2) && (j <= L.ny - 2);           \
+    const int kb_ = 1 + blockIdx.z * kp;                              \
+    const int ke_ = min(kb_ + kp, L.nz - 1);                          \
+    for (int k = kb_; k < ke_; ++k)
+
+#define PT_LAUNCH(kernel, L, s, ...)                                                         \
+    do {                                                                                     \
+        const PtShape ps_ = pt_shape(L);                                                     \
+        hipLaunchKernelGGL(kernel, ps_.grid, dim3(PT_NT), 0, s, L, ps_.kp, __VA_ARGS__);      \
+    } while (0)
+
+// r = f - A u (split arrays)
 template <typename T>
-__device__ __forceinline__ T apply_at(const LevelView& L, const T* __restrict__ u, int i, int j, int k, size_t idx,
-                                      size_t sxy, int nx)
+__global__ __launch_bounds__(PT_NT) void k_residual(LevelView L, int kp, const T* __restrict__ u,
+                                                    const T* __restrict__ f, T* __restrict__ r)
 {
-    const T c = u[idx];
-    T a = (T)L.ax[0].am[i] * (u[idx - 1] - c) + (T)L.ax[0].ap[i] * (u[idx + 1] - c);
-    a += (T)L.ax[1].am[j] * (u[idx - nx] - c) + (T)L.ax[1].ap[j] * (u[idx + nx] - c);
-    a += (T)L.ax[2].am[k] * (u[idx - sxy] - c) + (T)L.ax[2].ap[k] * (u[idx + sxy] - c);
-    return a;
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        const size_t at = sidx(L, i, j, k);
+        r[at] = f[at] - apply_split(L, u, i, j, k, u[at]);
+    }
 }
 
-// r = bscale f - A u at interior nodes (faces of r untouched, kept zero)
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_residual(LevelView L, const T* __restrict__ u, const T* __restrict__ f,
-                                                    T bscale, T* __restrict__ r)
+hipError_t launch_residual(const LevelView& L, const T* u, const T* f, T* r, hipStream_t s)
 {
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
-    if (i > L.nx - 2 || j > L.ny - 2) return;
-    const size_t sxy = (size_t)L.nx * L.ny;
-    const size_t idx = (size_t)k * sxy + (size_t)j * L.nx + i;
-    r[idx] = bscale * f[idx] - apply_at(L, u, i, j, k, idx, sxy, L.nx);
-}
-
-template <typename T>
-hipError_t launch_residual(const LevelView& L, const T* u, const T* f, T bscale, T* r, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_residual<T>, interior_grid(L), dim3(PT_NT), 0, s, L, u, f, bscale, r);
+    PT_LAUNCH(k_residual<T>, L, s, u, f, r);
     return hipGetLastError();
 }
 
-// r = bscale f - A u (FP64 arithmetic; u = v with faces = Dirichlet data),
-// stored as T; W-norm^2 partials. interior_zero: the interior of u is read as
-// zero (the reference residual of the face data alone).
-template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_residual_norm(LevelView L, const double* __restrict__ u,
-                                                         const double* __restrict__ f, double bscale,
-                                                         T* __restrict__ r, double* __restrict__ part,
-                                                         int interior_zero)
+// Fine level, natural v and rho: r = bscale rho - A v (r in the split layout
+// when given) and partials of ||r||_W^2. interior_zero: the interior of v is
+// read as zero (the reference residual of the face data alone).
+__global__ __launch_bounds__(PT_NT) void k_residual_nat(LevelView L, int kp, const double* __restrict__ v,
+                                                        const double* __restrict__ rho, double bscale,
+                                                        double* __restrict__ r, double* __restrict__ part,
+                                                        int interior_zero)
 {
     __shared__ double red[PT_NT / 64];
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
     double acc = 0.0;
-    if (i <= L.nx - 2 && j <= L.ny - 2) {
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
         const int nx = L.nx, ny = L.ny, nz = L.nz;
         const size_t sxy = (size_t)nx * ny;
         const size_t idx = (size_t)k * sxy + (size_t)j * nx + i;
-        double res;
+        double a;
         if (!interior_zero) {
-            res = bscale * f[idx] - apply_at(L, u, i, j, k, idx, sxy, nx);
+            const double c = v[idx];
+            a = L.ax[0].am[i] * (v[idx - 1] - c) + L.ax[0].ap[i] * (v[idx + 1] - c);
+            a += L.ax[1].am[j] * (v[idx - nx] - c) + L.ax[1].ap[j] * (v[idx + nx] - c);
+            a += L.ax[2].am[k] * (v[idx - sxy] - c) + L.ax[2].ap[k] * (v[idx + sxy] - c);
         } else {
-            // only face neighbours carry values
-            double a = 0.0;
-            if (i == 1) a += L.ax[0].am[i] * u[idx - 1];
-            if (i == nx - 2) a += L.ax[0].ap[i] * u[idx + 1];
-            if (j == 1) a += L.ax[1].am[j] * u[idx - nx];
-            if (j == ny - 2) a += L.ax[1].ap[j] * u[idx + nx];
-            if (k == 1) a += L.ax[2].am[k] * u[idx - sxy];
-            if (k == nz - 2) a += L.ax[2].ap[k] * u[idx + sxy];
-            res = bscale * f[idx] - a;
+            a = 0.0;
+            if (i == 1) a += L.ax[0].am[i] * v[idx - 1];
+            if (i == nx - 2) a += L.ax[0].ap[i] * v[idx + 1];
+            if (j == 1) a += L.ax[1].am[j] * v[idx - nx];
+            if (j == ny - 2) a += L.ax[1].ap[j] * v[idx + nx];
+            if (k == 1) a += L.ax[2].am[k] * v[idx - sxy];
+            if (k == nz - 2) a += L.ax[2].ap[k] * v[idx + sxy];
         }
-        if (r) r[idx] = (T)res;
-        acc = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * res * res;
+        const double res = bscale * rho[idx] - a;
+        if (r) r[sidx(L, i, j, k)] = res;
+        acc += vol_at(L, i, j, k) * res * res;
     }
     const double t = block_sum<PT_NT>(acc, red);
     if (threadIdx.x == 0) part[block_linear()] = t;
 }
 
-template <typename T>
-hipError_t launch_residual_norm(const LevelView& L, const double* u, const double* f, double bscale, T* r,
-                                double* partials, hipStream_t s)
+hipError_t launch_residual_nat(const LevelView& L, const double* v, const double* rho, double bscale, double* r_split,
+                               double* partials, int interior_zero, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_residual_norm<T>, interior_grid(L), dim3(PT_NT), 0, s, L, u, f, bscale, r, partials, 0);
+    PT_LAUNCH(k_residual_nat, L, s, v, rho, bscale, r_split, partials, interior_zero);
     return hipGetLastError();
 }
 
-hipError_t launch_reference_norm(const LevelView& L, const double* u, const double* f, double bscale,
-                                 double* partials, hipStream_t s)
+// Au = A u, natural layout (the diagnostic lasto_apply)
+__global__ __launch_bounds__(PT_NT) void k_apply_nat(LevelView L, int kp, const double* __restrict__ u,
+                                                     double* __restrict__ Au)
 {
-    hipLaunchKernelGGL(k_residual_norm<double>, interior_grid(L), dim3(PT_NT), 0, s, L, u, f, bscale,
-                       (double*)nullptr, partials, 1);
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        const int nx = L.nx;
+        const size_t sxy = (size_t)nx * L.ny;
+        const size_t idx = (size_t)k * sxy + (size_t)j * nx + i;
+        const double c = u[idx];
+        double a = L.ax[0].am[i] * (u[idx - 1] - c) + L.ax[0].ap[i] * (u[idx + 1] - c);
+        a += L.ax[1].am[j] * (u[idx - nx] - c) + L.ax[1].ap[j] * (u[idx + nx] - c);
+        a += L.ax[2].am[k] * (u[idx - sxy] - c) + L.ax[2].ap[k] * (u[idx + sxy] - c);
+        Au[idx] = a;
+    }
+}
+
+hipError_t launch_apply_nat(const LevelView& L, const double* u, double* Au, hipStream_t s)
+{
+    PT_LAUNCH(k_apply_nat, L, s, u, Au);
     return hipGetLastError();
 }
 
-// q = A p and partial <p, q>_W
+// q = A p and partial <p, q>_W (split arrays)
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_apply_dot(LevelView L, const T* __restrict__ p, T* __restrict__ q,
-                                                     double* __restrict__ part)
+__global__ __launch_bounds__(PT_NT) void k_apply_dot(LevelView L, int kp, const T* __restrict__ p,
+                                                     T* __restrict__ q, double* __restrict__ part)
 {
     __shared__ double red[PT_NT / 64];
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
     double acc = 0.0;
-    if (i <= L.nx - 2 && j <= L.ny - 2) {
-        const size_t sxy = (size_t)L.nx * L.ny;
-        const size_t idx = (size_t)k * sxy + (size_t)j * L.nx + i;
-        const T a = apply_at(L, p, i, j, k, idx, sxy, L.nx);
-        q[idx] = a;
-        acc = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * (double)p[idx] * (double)a;
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        const size_t at = sidx(L, i, j, k);
+        const T c = p[at];
+        const T a = apply_split(L, p, i, j, k, c);
+        q[at] = a;
+        acc += vol_at(L, i, j, k) * (double)c * (double)a;
     }
     const double t = block_sum<PT_NT>(acc, red);
     if (threadIdx.x == 0) part[block_linear()] = t;
@@ -295,22 +437,21 @@ __global__ __launch_bounds__(PT_NT) void k_apply_dot(LevelView L, const T* __res
 template <typename T>
 hipError_t launch_apply_dot(const LevelView& L, const T* p, T* q, double* partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_apply_dot<T>, interior_grid(L), dim3(PT_NT), 0, s, L, p, q, partials);
+    PT_LAUNCH(k_apply_dot<T>, L, s, p, q, partials);
     return hipGetLastError();
 }
 
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_dot(LevelView L, const T* __restrict__ a, const T* __restrict__ b,
+__global__ __launch_bounds__(PT_NT) void k_dot(LevelView L, int kp, const T* __restrict__ a, const T* __restrict__ b,
                                                double* __restrict__ part)
 {
     __shared__ double red[PT_NT / 64];
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
     double acc = 0.0;
-    if (i <= L.nx - 2 && j <= L.ny - 2) {
-        const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
-        acc = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * (double)a[idx] * (double)b[idx];
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        const size_t at = sidx(L, i, j, k);
+        acc += vol_at(L, i, j, k) * (double)a[at] * (double)b[at];
     }
     const double t = block_sum<PT_NT>(acc, red);
     if (threadIdx.x == 0) part[block_linear()] = t;
@@ -319,26 +460,22 @@ __global__ __launch_bounds__(PT_NT) void k_dot(LevelView L, const T* __restrict_
 template <typename T>
 hipError_t launch_dot(const LevelView& L, const T* a, const T* b, double* partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dot<T>, interior_grid(L), dim3(PT_NT), 0, s, L, a, b, partials);
+    PT_LAUNCH(k_dot<T>, L, s, a, b, partials);
     return hipGetLastError();
 }
 
 // pnew = z + beta pold, beta = scal[i_num]/scal[i_den] (0 on the first step)
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_update_p(LevelView L, const T* __restrict__ z, const T* __restrict__ pold,
-                                                    T* __restrict__ pnew, const double* __restrict__ scal, int i_num,
-                                                    int i_den, int first)
+__global__ __launch_bounds__(PT_NT) void k_update_p(LevelView L, int kp, const T* __restrict__ z,
+                                                    const T* __restrict__ pold, T* __restrict__ pnew,
+                                                    const double* __restrict__ scal, int i_num, int i_den, int first)
 {
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
-    if (i > L.nx - 2 || j > L.ny - 2) return;
-    const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
-    if (first) {
-        pnew[idx] = z[idx];
-    } else {
-        const T beta = (T)(scal[i_num] / scal[i_den]);
-        pnew[idx] = z[idx] + beta * pold[idx];
+    const T beta = first ? T(0) : (T)(scal[i_num] / scal[i_den]);
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        const size_t at = sidx(L, i, j, k);
+        pnew[at] = first ? z[at] : z[at] + beta * pold[at];
     }
 }
 
@@ -346,7 +483,7 @@ template <typename T>
 hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pnew, const double* scal, int i_num,
                            int i_den, int first, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update_p<T>, interior_grid(L), dim3(PT_NT), 0, s, L, z, pold, pnew, scal, i_num, i_den, first);
+    PT_LAUNCH(k_update_p<T>, L, s, z, pold, pnew, scal, i_num, i_den, first);
     return hipGetLastError();
 }
 
@@ -354,135 +491,142 @@ hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pne
 // A non-finite alpha leaves x and r untouched (the caller then reports the
 // breakdown with x still the last finite iterate).
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_update_xr(LevelView L, T* __restrict__ x, T* __restrict__ r,
-                                                     const T* __restrict__ p, const T* __restrict__ q,
-                                                     const double* __restrict__ scal, int i_num, int i_den,
-                                                     double* __restrict__ part)
+__global__ __launch_bounds__(PT_NT) void k_update_xr(LevelView L, int kp, void* __restrict__ xv, int x_nat,
+                                                     T* __restrict__ r, const T* __restrict__ p,
+                                                     const T* __restrict__ q, const double* __restrict__ scal,
+                                                     int i_num, int i_den, double* __restrict__ part)
 {
     __shared__ double red[PT_NT / 64];
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
     const double ad = scal[i_num] / scal[i_den];
     const bool ok = isfinite(ad);
+    const T alpha = (T)ad;
     double acc = 0.0;
-    if (i <= L.nx - 2 && j <= L.ny - 2) {
-        const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
-        T rv = r[idx];
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        const size_t at = sidx(L, i, j, k);
+        T rv = r[at];
         if (ok) {
-            const T alpha = (T)ad;
-            x[idx] = x[idx] + alpha * p[idx];
-            rv = rv - alpha * q[idx];
-            r[idx] = rv;
+            if (x_nat) {
+                double* x = (double*)xv;
+                const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
+                x[idx] = x[idx] + ad * (double)p[at];
+            } else {
+                T* x = (T*)xv;
+                x[at] = x[at] + alpha * p[at];
+            }
+            rv = rv - alpha * q[at];
+            r[at] = rv;
         }
-        acc = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * (double)rv * (double)rv;
+        acc += vol_at(L, i, j, k) * (double)rv * (double)rv;
     }
     const double t = block_sum<PT_NT>(acc, red);
     if (threadIdx.x == 0) part[block_linear()] = ok ? t : __builtin_nan("");
 }
 
 template <typename T>
-hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
-                            int i_den, double* partials, hipStream_t s)
+hipError_t launch_update_xr(const LevelView& L, void* x, int x_nat, T* r, const T* p, const T* q, const double* scal,
+                            int i_num, int i_den, double* partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update_xr<T>, interior_grid(L), dim3(PT_NT), 0, s, L, x, r, p, q, scal, i_num, i_den, partials);
+    PT_LAUNCH(k_update_xr<T>, L, s, x, x_nat, r, p, q, scal, i_num, i_den, partials);
     return hipGetLastError();
 }
 
-// u += e (interior), FP32 correction into an FP64 iterate (plain V-cycle mode, FP64 e)
-__global__ __launch_bounds__(PT_NT) void k_add64(LevelView L, double* __restrict__ u, const double* __restrict__ e)
+// v (natural) += e (split), interior
+__global__ __launch_bounds__(PT_NT) void k_add_nat(LevelView L, int kp, double* __restrict__ v,
+                                                   const double* __restrict__ e)
 {
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
-    if (i > L.nx - 2 || j > L.ny - 2) return;
-    const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
-    u[idx] += e[idx];
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        v[((size_t)k * L.ny + j) * L.nx + i] += e[sidx(L, i, j, k)];
+    }
 }
 
-hipError_t launch_add64(const LevelView& L, double* u, const double* e, hipStream_t s)
+hipError_t launch_add_nat(const LevelView& L, double* v, const double* e_split, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_add64, interior_grid(L), dim3(PT_NT), 0, s, L, u, e);
+    PT_LAUNCH(k_add_nat, L, s, v, e_split);
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(PT_NT) void k_scale_inplace(LevelView L, double* __restrict__ u, double a)
+// r32 = r / sqrt(scal[i_norm2]) (scaled FP32 copy of the FP64 residual, split)
+__global__ __launch_bounds__(PT_NT) void k_scale_to32(LevelView L, int kp, const double* __restrict__ r,
+                                                      float* __restrict__ r32, const double* __restrict__ scal,
+                                                      int i_norm2)
 {
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
-    if (i > L.nx - 2 || j > L.ny - 2) return;
-    const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
-    u[idx] *= a;
-}
-
-hipError_t launch_scale_inplace(const LevelView& L, double* u, double a, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scale_inplace, interior_grid(L), dim3(PT_NT), 0, s, L, u, a);
-    return hipGetLastError();
-}
-
-// r32 = r / sqrt(scal[i_norm2])  (scaled FP32 copy of the FP64 residual)
-__global__ __launch_bounds__(PT_NT) void k_scale_to32(LevelView L, const double* __restrict__ r, float* __restrict__ r32,
-                                                      const double* __restrict__ scal, int i_norm2)
-{
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
-    if (i > L.nx - 2 || j > L.ny - 2) return;
-    const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
     const double inv = 1.0 / sqrt(scal[i_norm2]);
-    r32[idx] = (float)(r[idx] * inv);
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        const size_t at = sidx(L, i, j, k);
+        r32[at] = (float)(r[at] * inv);
+    }
 }
 
-hipError_t launch_scale_f64_to_f32(const LevelView& L, const double* r, float* r32, const double* scal, int i_norm2,
+hipError_t launch_scale_to32(const LevelView& L, const double* r, float* r32, const double* scal, int i_norm2,
+                             hipStream_t s)
+{
+    PT_LAUNCH(k_scale_to32, L, s, r, r32, scal, i_norm2);
+    return hipGetLastError();
+}
+
+// v (natural) += sqrt(scal[i_norm2]) * e32 (split): the defect correction
+__global__ __launch_bounds__(PT_NT) void k_add_scaled32_nat(LevelView L, int kp, double* __restrict__ v,
+                                                            const float* __restrict__ e,
+                                                            const double* __restrict__ scal, int i_norm2)
+{
+    const double sc = sqrt(scal[i_norm2]);
+    if (!isfinite(sc)) return;
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        v[((size_t)k * L.ny + j) * L.nx + i] += sc * (double)e[sidx(L, i, j, k)];
+    }
+}
+
+hipError_t launch_add_scaled32_nat(const LevelView& L, double* v, const float* e32, const double* scal, int i_norm2,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scale_to32, interior_grid(L), dim3(PT_NT), 0, s, L, r, r32, scal, i_norm2);
+    PT_LAUNCH(k_add_scaled32_nat, L, s, v, e32, scal, i_norm2);
     return hipGetLastError();
 }
 
-// u += sqrt(scal[i_norm2]) * e  (defect correction with the scaled FP32 solution)
-__global__ __launch_bounds__(PT_NT) void k_add_scaled32(LevelView L, double* __restrict__ u, const float* __restrict__ e,
-                                                        const double* __restrict__ scal, int i_norm2)
+// layout conversions
+__global__ __launch_bounds__(PT_NT) void k_nat_to_split(LevelView L, const double* __restrict__ a,
+                                                        double* __restrict__ out)
 {
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
-    if (i > L.nx - 2 || j > L.ny - 2) return;
-    const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
-    const double s = sqrt(scal[i_norm2]);
-    if (!isfinite(s)) return;
-    u[idx] += s * (double)e[idx];
+    const int i = blockIdx.x * PT_X + (threadIdx.x % PT_X);
+    const int j = blockIdx.y * PT_Y + (threadIdx.x / PT_X);
+    const int k = blockIdx.z;
+    if (i >= L.nx || j >= L.ny) return;
+    out[sidx(L, i, j, k)] = a[((size_t)k * L.ny + j) * L.nx + i];
 }
 
-hipError_t launch_add_scaled_f32_to_f64(const LevelView& L, double* u, const float* e, const double* scal, int i_norm2,
-                                        hipStream_t s)
+__global__ __launch_bounds__(PT_NT) void k_split_to_nat(LevelView L, int kp, const double* __restrict__ in,
+                                                        double* __restrict__ a)
 {
-    hipLaunchKernelGGL(k_add_scaled32, interior_grid(L), dim3(PT_NT), 0, s, L, u, e, scal, i_norm2);
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        a[((size_t)k * L.ny + j) * L.nx + i] = in[sidx(L, i, j, k)];
+    }
+}
+
+hipError_t launch_nat_to_split(const LevelView& L, const double* a, double* s_out, hipStream_t s)
+{
+    // every node, faces included
+    const dim3 g((L.nx + PT_X - 1) / PT_X, (L.ny + PT_Y - 1) / PT_Y, L.nz);
+    hipLaunchKernelGGL(k_nat_to_split, g, dim3(PT_NT), 0, s, L, a, s_out);
     return hipGetLastError();
 }
 
-// fill the interior with zeros (a kernel rather than a memset so that a
-// captured graph never records a memset node)
-template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_zero_interior(LevelView L, T* __restrict__ u)
+hipError_t launch_split_to_nat(const LevelView& L, const double* s_in, double* a, hipStream_t s)
 {
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
-    if (i > L.nx - 2 || j > L.ny - 2) return;
-    u[((size_t)k * L.ny + j) * L.nx + i] = T(0);
-}
-
-template <typename T>
-hipError_t launch_zero_interior(const LevelView& L, T* u, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_zero_interior<T>, interior_grid(L), dim3(PT_NT), 0, s, L, u);
+    PT_LAUNCH(k_split_to_nat, L, s, s_in, a);
     return hipGetLastError();
 }
 
-// fill a whole array (n elements) with zeros
+// fill a whole array (n elements) with zeros (a kernel, never a memset)
 template <typename T>
 __global__ void k_fill_zero(T* __restrict__ a, size_t n)
 {
@@ -510,145 +654,208 @@ hipError_t launch_inject_nan(double* r, size_t idx, hipStream_t s)
 }
 
 // ---------------------------------------------------------- transfers
-// rc(I,J,K) = sum over the up-to-3x3x3 fine nodes around (rf[I],rf[J],rf[K])
-// of rw_x rw_y rw_z r: the restriction M_c^-1 P^T M_f, adjoint of the
-// interpolation in the volume-weighted inner product.
-template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_restrict(LevelView F, LevelView C, const T* __restrict__ r,
+template <typename T, bool RED_ONLY>
+__global__ __launch_bounds__(PT_NT) void k_restrict(LevelView C, int kp, LevelView F, const T* __restrict__ r,
                                                     T* __restrict__ rc)
 {
-    const int I = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int J = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int K = 1 + blockIdx.z;
-    if (I > C.nx - 2 || J > C.ny - 2) return;
-    const int fi = C.ax[0].rf[I], fj = C.ax[1].rf[J], fk = C.ax[2].rf[K];
-    const double* wx = C.ax[0].rw + 3 * I;
-    const double* wy = C.ax[1].rw + 3 * J;
-    const double* wz = C.ax[2].rw + 3 * K;
-    const size_t sxy = (size_t)F.nx * F.ny;
-    T acc = T(0);
-    for (int c = 0; c < 3; ++c) {
-        const T z = (T)wz[c];
-        if (z == T(0)) continue;
-        for (int b = 0; b < 3; ++b) {
-            const T y = (T)wy[b];
-            if (y == T(0)) continue;
-            const T* row = r + (size_t)(fk - 1 + c) * sxy + (size_t)(fj - 1 + b) * F.nx + (fi - 1);
-            const T sx = (T)wx[0] * row[0] + (T)wx[1] * row[1] + (T)wx[2] * row[2];
-            acc += z * y * sx;
-        }
+    const LevelView& L = C;
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        rc[sidx(C, i, j, k)] = restrict_point<T, RED_ONLY>(F, C, r, i, j, k);
     }
-    rc[((size_t)K * C.ny + J) * C.nx + I] = acc;
 }
 
 template <typename T>
 hipError_t launch_restrict(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_restrict<T>, interior_grid(C), dim3(PT_NT), 0, s, F, C, r, rc);
+    PT_LAUNCH((k_restrict<T, false>), C, s, F, r, rc);
     return hipGetLastError();
 }
 
-// u(i,j,k) += sum of the 2x2x2 coarse values around it times the linear
-// interpolation weights in physical coordinates (weight 1 at kept nodes).
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_prolong_add(LevelView F, LevelView C, const T* __restrict__ e,
+hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s)
+{
+    PT_LAUNCH((k_restrict<T, true>), C, s, F, r, rc);
+    return hipGetLastError();
+}
+
+// u += P e on the red nodes only: when a black half-sweep follows, it
+// overwrites every black value, so correcting them would be wasted work.
+template <typename T>
+__global__ __launch_bounds__(HS_NT) void k_prolong_red(LevelView F, LevelView C, const T* __restrict__ e,
+                                                       T* __restrict__ u, int nbx, int nby, int nb, int per, int kc)
+{
+    const int t = xcd_tile(blockIdx.x, per);
+    const int m = (t % nbx) * HS_X + (threadIdx.x & (HS_X - 1));
+    const int j = 1 + ((t / nbx) % nby) * HS_Y + (threadIdx.x >> 6);
+    if (t >= nb || j > F.ny - 2 || m > (F.nx - 2) / 2) return;
+    const int k0 = 1 + (t / (nbx * nby)) * kc;
+    const int k1 = min(k0 + kc, F.nz - 1);
+    const size_t plane = (size_t)F.ny * F.W;
+    const size_t row = (size_t)j * F.W + m;
+    for (int k = k0; k < k1; ++k) {
+        const int i = ((j + k) & 1) + 2 * m;
+        if (i < 1 || i > F.nx - 2) continue;
+        u[(size_t)k * plane + row] += prolong_point(C, e, i, j, k);
+    }
+}
+
+template <typename T>
+hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s)
+{
+    const HalfShape h = half_shape(F);
+    hipLaunchKernelGGL(k_prolong_red<T>, dim3(h.grid), dim3(HS_NT), 0, s, F, C, e, u, h.nbx, h.nby, h.nb, h.per, h.kc);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(PT_NT) void k_prolong_add(LevelView F, int kp, LevelView C, const T* __restrict__ e,
                                                        T* __restrict__ u)
 {
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int k = 1 + blockIdx.z;
-    if (i > F.nx - 2 || j > F.ny - 2) return;
-    const int I = C.ax[0].pc[i], J = C.ax[1].pc[j], K = C.ax[2].pc[k];
-    const T x0 = (T)C.ax[0].pw[2 * i], x1 = (T)C.ax[0].pw[2 * i + 1];
-    const T y0 = (T)C.ax[1].pw[2 * j], y1 = (T)C.ax[1].pw[2 * j + 1];
-    const T z0 = (T)C.ax[2].pw[2 * k], z1 = (T)C.ax[2].pw[2 * k + 1];
-    const size_t csxy = (size_t)C.nx * C.ny;
-    const T* e0 = e + (size_t)K * csxy + (size_t)J * C.nx + I;
-    // neighbours with zero weight may sit one past the last coarse node:
-    // read them only when the weight is nonzero
-    T a = x0 * e0[0];
-    if (x1 != T(0)) a += x1 * e0[1];
-    T v = y0 * a;
-    if (y1 != T(0)) {
-        T b = x0 * e0[C.nx];
-        if (x1 != T(0)) b += x1 * e0[C.nx + 1];
-        v += y1 * b;
+    const LevelView& L = F;
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        u[sidx(F, i, j, k)] += prolong_point(C, e, i, j, k);
     }
-    T w = z0 * v;
-    if (z1 != T(0)) {
-        const T* e1 = e0 + csxy;
-        T a2 = x0 * e1[0];
-        if (x1 != T(0)) a2 += x1 * e1[1];
-        T v2 = y0 * a2;
-        if (y1 != T(0)) {
-            T b2 = x0 * e1[C.nx];
-            if (x1 != T(0)) b2 += x1 * e1[C.nx + 1];
-            v2 += y1 * b2;
-        }
-        w += z1 * v2;
-    }
-    const size_t idx = ((size_t)k * F.ny + j) * F.nx + i;
-    u[idx] += w;
 }
 
 template <typename T>
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prolong_add<T>, interior_grid(F), dim3(PT_NT), 0, s, F, C, e, u);
+    PT_LAUNCH(k_prolong_add<T>, F, s, C, e, u);
     return hipGetLastError();
 }
 
-// --------------------------------------------------------- coarsest level
-// One workgroup: `sweeps` red-black sweeps (red, black) then `sweeps` in the
-// reverse order (black, red), from zero, in LDS; symmetric, so the V-cycle
-// stays a symmetric preconditioner. At most 4096 nodes.
-constexpr int CS_MAX = 4096;
+// -------------------------------------------------------------- tail
+// The V-cycle below a small level in ONE workgroup: every step is a loop of
+// the workgroup's threads over the level's nodes followed by a barrier. On
+// levels of a few thousand nodes a launch costs more than the work, so this
+// replaces about a dozen launches per level by one.
+constexpr int TL_NT = 1024;
+
+// One half-sweep of colour c by the whole workgroup. A thread takes up to
+// TL_BATCH nodes at a time and computes all their new values before storing
+// any (nodes of one colour never read each other), so the loads of a batch
+// are in flight together instead of forming a chain.
+constexpr int TL_BATCH = 8;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse(LevelView L, T* __restrict__ u, const T* __restrict__ f, int sweeps)
+__device__ void t_half(const LevelView& V, T* __restrict__ u, const T* __restrict__ f, int c, int zero_in)
 {
-    __shared__ T us[CS_MAX];
-    __shared__ T fs[CS_MAX];
-    const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const int n = nx * ny * nz;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        us[t] = T(0);
-        fs[t] = f[t];
-    }
-    __syncthreads();
-    for (int pass = 0; pass < 2 * sweeps; ++pass) {
-        for (int half = 0; half < 2; ++half) {
-            const int colour = (pass < sweeps) ? half : 1 - half;
-            for (int t = threadIdx.x; t < n; t += blockDim.x) {
-                const int i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
-                if (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1) continue;
-                if (((i + j + k) & 1) != colour) continue;
-                const T cxm = (T)L.ax[0].am[i], cxp = (T)L.ax[0].ap[i];
-                const T cym = (T)L.ax[1].am[j], cyp = (T)L.ax[1].ap[j];
-                const T czm = (T)L.ax[2].am[k], czp = (T)L.ax[2].ap[k];
-                T s = cxm * us[t - 1] + cxp * us[t + 1];
-                s += cym * us[t - nx] + cyp * us[t + nx];
-                s += czm * us[t - nx * ny] + czp * us[t + nx * ny];
-                us[t] = (s - fs[t]) / (cxm + cxp + cym + cyp + czm + czp);
+    const int mcount = (V.nx - 2) / 2 + 1, nyi = V.ny - 2;
+    const int total = mcount * nyi * (V.nz - 2);
+    for (int base = 0; base < total; base += TL_NT * TL_BATCH) {
+        T val[TL_BATCH];
+        size_t at[TL_BATCH];
+        bool ok[TL_BATCH];
+#pragma unroll
+        for (int b = 0; b < TL_BATCH; ++b) {
+            const int t = base + b * TL_NT + threadIdx.x;
+            const int m = t % mcount, j = 1 + (t / mcount) % nyi, k = 1 + t / (mcount * nyi);
+            const int i = ((c + j + k) & 1) + 2 * m;
+            ok[b] = t < total && i >= 1 && i <= V.nx - 2;
+            at[b] = 0;
+            val[b] = T(0);
+            if (!ok[b]) continue;
+            at[b] = sidx(V, i, j, k);
+            if (zero_in) {
+                const T d = (T)(V.ax[0].am[i] + V.ax[0].ap[i] + V.ax[1].am[j] + V.ax[1].ap[j] + V.ax[2].am[k] +
+                                V.ax[2].ap[k]);
+                val[b] = -f[at[b]] / d;
+            } else {
+                val[b] = gs_point(V, u, i, j, k, f[at[b]]);
             }
-            __syncthreads();
         }
+#pragma unroll
+        for (int b = 0; b < TL_BATCH; ++b)
+            if (ok[b]) u[at[b]] = val[b];
     }
-    for (int t = threadIdx.x; t < n; t += blockDim.x) u[t] = us[t];
 }
 
 template <typename T>
-hipError_t launch_coarse_solve(const LevelView& L, T* u, const T* f, int sweeps, hipStream_t s)
+__global__ __launch_bounds__(TL_NT) void k_tail(const TailLevel* __restrict__ lv, int nl, int nu1, int nu2,
+                                                int csweeps)
 {
-    if ((size_t)L.nx * L.ny * L.nz > (size_t)CS_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(256), 0, s, L, u, f, sweeps);
+    // descent
+    for (int l = 0; l + 1 < nl; ++l) {
+        const LevelView& V = lv[l].V;
+        T* u = TailBuf<T>::u(lv[l]);
+        const T* f = TailBuf<T>::f(lv[l]);
+        for (int s = 0; s < nu1; ++s) {
+            t_half<T>(V, u, f, 0, s == 0);
+            __syncthreads();
+            t_half<T>(V, u, f, 1, 0);
+            __syncthreads();
+        }
+        // residual on red nodes only (the black half-sweep just zeroed it on black)
+        T* r = TailBuf<T>::r(lv[l]);
+        const int ni = (V.nx - 2) * (V.ny - 2) * (V.nz - 2);
+        for (int t = threadIdx.x; t < ni; t += TL_NT) {
+            const int i = 1 + t % (V.nx - 2), j = 1 + (t / (V.nx - 2)) % (V.ny - 2), k = 1 + t / ((V.nx - 2) * (V.ny - 2));
+            if ((i + j + k) & 1) continue;
+            const size_t at = sidx(V, i, j, k);
+            r[at] = f[at] - apply_split(V, u, i, j, k, u[at]);
+        }
+        __syncthreads();
+        const LevelView& C = lv[l + 1].V;
+        T* fc = TailBuf<T>::f(lv[l + 1]);
+        const int nc = (C.nx - 2) * (C.ny - 2) * (C.nz - 2);
+        for (int t = threadIdx.x; t < nc; t += TL_NT) {
+            const int I = 1 + t % (C.nx - 2), J = 1 + (t / (C.nx - 2)) % (C.ny - 2), K = 1 + t / ((C.nx - 2) * (C.ny - 2));
+            fc[sidx(C, I, J, K)] = restrict_point<T, true>(V, C, (const T*)r, I, J, K);
+        }
+        __syncthreads();
+    }
+    // coarsest: csweeps sweeps (red, black), then csweeps (black, red), from zero
+    {
+        const LevelView& V = lv[nl - 1].V;
+        T* u = TailBuf<T>::u(lv[nl - 1]);
+        const T* f = TailBuf<T>::f(lv[nl - 1]);
+        for (int pass = 0; pass < 2 * csweeps; ++pass) {
+            for (int h = 0; h < 2; ++h) {
+                const int colour = (pass < csweeps) ? h : 1 - h;
+                t_half<T>(V, u, f, colour, pass == 0 && h == 0);
+                __syncthreads();
+            }
+        }
+    }
+    // ascent
+    for (int l = nl - 2; l >= 0; --l) {
+        const LevelView& V = lv[l].V;
+        const LevelView& C = lv[l + 1].V;
+        T* u = TailBuf<T>::u(lv[l]);
+        const T* f = TailBuf<T>::f(lv[l]);
+        const T* e = TailBuf<T>::u(lv[l + 1]);
+        // correction on red nodes only when a black half-sweep follows
+        const int ni = (V.nx - 2) * (V.ny - 2) * (V.nz - 2);
+        for (int t = threadIdx.x; t < ni; t += TL_NT) {
+            const int i = 1 + t % (V.nx - 2), j = 1 + (t / (V.nx - 2)) % (V.ny - 2), k = 1 + t / ((V.nx - 2) * (V.ny - 2));
+            if (nu2 > 0 && ((i + j + k) & 1)) continue;
+            u[sidx(V, i, j, k)] += prolong_point(C, e, i, j, k);
+        }
+        __syncthreads();
+        for (int s = 0; s < nu2; ++s) {
+            t_half<T>(V, u, f, 1, 0);
+            __syncthreads();
+            t_half<T>(V, u, f, 0, 0);
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweeps, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TL_NT), 0, s, lv, nl, nu1, nu2, csweeps);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ reduction
-// out[c] = sum_b partials[b * stride + c] for c < stride... here stride 1:
-// out[0] = sum of count partials in a fixed order (thread t takes t, t+1024,
-// ..., then a fixed tree), so a given launch shape always gives the same bits.
+// out[c] = sum_b partials[b * stride + c], c < stride, in a fixed order
+// (thread t takes t, t+1024, ..., then a fixed tree): a given launch shape
+// always gives the same bits.
 __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part, int stride, int count,
                                                  double* __restrict__ out)
 {
@@ -674,29 +881,25 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
 }
 
 // ------------------------------------------------- explicit instantiation
-#define INST(T)                                                                                               \
-    template hipError_t launch_smooth<T>(const LevelView&, const T*, const T*, T*, T, int, int, double*,         \
-                                         hipStream_t);                                                         \
-    template hipError_t launch_residual<T>(const LevelView&, const T*, const T*, T, T*, hipStream_t);           \
-    template hipError_t launch_restrict<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
-    template hipError_t launch_prolong_add<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);   \
-    template hipError_t launch_coarse_solve<T>(const LevelView&, T*, const T*, int, hipStream_t);               \
-    template hipError_t launch_apply_dot<T>(const LevelView&, const T*, T*, double*, hipStream_t);              \
-    template hipError_t launch_residual_norm<T>(const LevelView&, const double*, const double*, double, T*,     \
-                                                double*, hipStream_t);                                         \
-    template hipError_t launch_dot<T>(const LevelView&, const T*, const T*, double*, hipStream_t);              \
-    template hipError_t launch_update_p<T>(const LevelView&, const T*, const T*, T*, const double*, int, int,   \
-                                           int, hipStream_t);                                                  \
-    template hipError_t launch_update_xr<T>(const LevelView&, T*, T*, const T*, const T*, const double*, int,   \
-                                            int, double*, hipStream_t);                                        \
-    template hipError_t launch_zero_interior<T>(const LevelView&, T*, hipStream_t);                             \
+#define INST(T)                                                                                                  \
+    template hipError_t launch_half<T>(const LevelView&, T*, const T*, int, int, T, double*, hipStream_t);         \
+    template hipError_t launch_residual<T>(const LevelView&, const T*, const T*, T*, hipStream_t);                 \
+    template hipError_t launch_restrict<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);         \
+    template hipError_t launch_prolong_add<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
+    template hipError_t launch_prolong_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
+    template hipError_t launch_restrict_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);     \
+    template hipError_t launch_residual_colour<T>(const LevelView&, const T*, const T*, T*, int, hipStream_t);    \
+    template hipError_t launch_tail<T>(const TailLevel*, int, int, int, int, hipStream_t);                         \
+    template hipError_t launch_apply_dot<T>(const LevelView&, const T*, T*, double*, hipStream_t);                 \
+    template hipError_t launch_dot<T>(const LevelView&, const T*, const T*, double*, hipStream_t);                 \
+    template hipError_t launch_update_p<T>(const LevelView&, const T*, const T*, T*, const double*, int, int, int,  \
+                                           hipStream_t);                                                          \
+    template hipError_t launch_update_xr<T>(const LevelView&, void*, int, T*, const T*, const T*, const double*,   \
+                                            int, int, double*, hipStream_t);                                      \
     template hipError_t launch_fill_zero<T>(T*, size_t, hipStream_t);
 INST(double)
 INST(float)
 #undef INST
-
-}  // namespace lasto
-
-namespace lasto {
 template hipError_t launch_fill_zero<unsigned char>(unsigned char*, size_t, hipStream_t);
+
 }  // namespace lasto

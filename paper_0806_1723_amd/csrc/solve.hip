@@ -14,25 +14,17 @@
 
 namespace lasto {
 
-int smooth_blocks(const LevelView& L);
-int interior_blocks(const LevelView& L);
-hipError_t launch_reference_norm(const LevelView& L, const double* u, const double* f, double bscale,
-                                 double* partials, hipStream_t s);
-hipError_t launch_add64(const LevelView& L, double* u, const double* e, hipStream_t s);
-template <typename T>
-hipError_t launch_zero_interior(const LevelView& L, T* u, hipStream_t s);
-hipError_t launch_scale_inplace(const LevelView& L, double* u, double a, hipStream_t s);
-
-constexpr int kCoarseSweeps = 8;
+// symmetric sweep pairs on the coarsest level (at most 5^3 nodes, 27 unknowns)
+constexpr int kCoarseSweeps = 4;
 
 template <typename T> struct Buf;
 template <> struct Buf<double> {
-    static double* u(Level& L, int s) { return L.u64[s]; }
+    static double* u(Level& L) { return L.u64; }
     static double* f(Level& L) { return L.f64; }
     static double* r(Level& L) { return L.r64; }
 };
 template <> struct Buf<float> {
-    static float* u(Level& L, int s) { return L.u32[s]; }
+    static float* u(Level& L) { return L.u32; }
     static float* f(Level& L) { return L.f32; }
     static float* r(Level& L) { return L.r32; }
 };
@@ -43,10 +35,10 @@ template <> struct Buf<float> {
         if (e_ != hipSuccess) return fail(LASTO_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// A sweep at level l; finest-level sweeps are bracketed by HIP events when
-// profiling is on (the events sit on the same stream as the kernel).
+// A half-sweep at level l; finest-level half-sweeps are bracketed by HIP
+// events when profiling is on (the events sit on the kernel's stream).
 template <typename T>
-static hipError_t sweep(lasto_grid g, int l, const T* uin, const T* f, T* uout, int first, int zero_in, double* dotp)
+static hipError_t half(lasto_grid g, int l, T* u, const T* f, int colour, int zero_in, double* dotp)
 {
     const LevelView& V = g->lev[l].view;
     const bool timed = g->prof_on && l == 0;
@@ -62,12 +54,14 @@ static hipError_t sweep(lasto_grid g, int l, const T* uin, const T* f, T* uout, 
         hipError_t err = hipEventRecord(g->prof_ev[2 * g->prof_used], g->stream);
         if (err != hipSuccess) return err;
     }
-    hipError_t err = launch_smooth<T>(V, uin, f, uout, T(1), first, zero_in, dotp, g->stream);
+    hipError_t err = launch_half<T>(V, u, f, colour, zero_in, T(1), dotp, g->stream);
     if (err != hipSuccess) return err;
     if (timed) {
         err = hipEventRecord(g->prof_ev[2 * g->prof_used + 1], g->stream);
         if (err != hipSuccess) return err;
-        const double pts = (double)(V.nx - 2) * (V.ny - 2) * (V.nz - 2);
+        // algorithmic bytes: half the interior nodes read f and (unless the
+        // other colour is zero) one other-colour value, and write their own value
+        const double pts = 0.5 * (double)(V.nx - 2) * (V.ny - 2) * (V.nz - 2);
         g->prof_bytes += pts * sizeof(T) * (zero_in ? 2.0 : 3.0);
         if (sizeof(T) == 4) g->prof_fp32++;
         g->prof_used++;
@@ -75,47 +69,61 @@ static hipError_t sweep(lasto_grid g, int l, const T* uin, const T* f, T* uout, 
     return hipSuccess;
 }
 
-// V(nu1, nu2) at level l on A e = f with zero faces, starting from e = 0.
-// Pre-smoothing sweeps update red first, post-smoothing black first, and the
-// coarsest level runs a symmetric sweep sequence, so the cycle is a
-// symmetric operator (usable as a CG preconditioner). Level 0 uses the
-// caller's f and scratch pair (e0, e1); the result pointer is returned.
+// V(nu1, nu2) at level l on A u = f with zero faces, starting from u = 0, in
+// place in the split layout. Pre-smoothing sweeps update red then black,
+// post-smoothing black then red, and the coarsest level runs a symmetric
+// sweep sequence, so the cycle is a symmetric operator (a valid CG
+// preconditioner). With dotp, partials of <f, u>_W over the result are
+// written (count in *ndot).
 template <typename T>
-static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T* f, T* e0, T* e1, double* dotp,
-                                 T** result)
+static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T* f, T* u, double* dotp, int* ndot)
 {
     Level& L = g->lev[l];
     const LevelView& V = L.view;
     hipStream_t s = g->stream;
-    if (l == g->nlev - 1) {
-        HIPCHK(launch_coarse_solve<T>(V, e0, f, kCoarseSweeps, s));
-        if (dotp) HIPCHK(launch_dot<T>(V, f, e0, dotp, s));
-        *result = e0;
+    if (l == g->tail_top) {
+        // the rest of the cycle in one workgroup; its level-0 buffers are the
+        // Krylov vectors, which are the only ones a level-0 cycle is given
+        if (l == 0 && !((void*)u == (void*)g->z || (void*)u == (void*)g->z32))
+            return fail(LASTO_ERR_STATE, "vcycle: level-0 tail needs the grid's Krylov vectors");
+        HIPCHK(launch_tail<T>(g->tail_dev + l, g->nlev - l, nu1, nu2, kCoarseSweeps, s));
+        if (dotp) {
+            HIPCHK(launch_dot<T>(V, f, u, dotp, s));
+            *ndot = interior_blocks(V);
+        }
         return LASTO_OK;
     }
-    T* buf[2] = {e0, e1};
-    int cur = 0;
-    // first pre-sweep from zero
-    HIPCHK(sweep<T>(g, l, buf[1], f, buf[0], 0, 1, nullptr));
-    for (int k = 1; k < nu1; ++k) {
-        HIPCHK(sweep<T>(g, l, buf[cur], f, buf[1 - cur], 0, 0, nullptr));
-        cur = 1 - cur;
+    for (int k = 0; k < nu1; ++k) {
+        HIPCHK(half<T>(g, l, u, f, 0, k == 0, nullptr));
+        HIPCHK(half<T>(g, l, u, f, 1, 0, nullptr));
     }
+    // The pre-smoothing ended with a black half-sweep, so the residual is zero
+    // on black nodes: compute and restrict the red part only. (The black part
+    // of r is never written and stays zero.)
     Level& C = g->lev[l + 1];
     T* r = Buf<T>::r(L);
-    HIPCHK(launch_residual<T>(V, buf[cur], f, T(1), r, s));
-    HIPCHK(launch_restrict<T>(V, C.view, r, Buf<T>::f(C), s));
-    T* ec = nullptr;
-    lasto_status st = vcycle_level<T>(g, l + 1, nu1, nu2, Buf<T>::f(C), Buf<T>::u(C, 0), Buf<T>::u(C, 1), nullptr, &ec);
+    HIPCHK(launch_residual_colour<T>(V, u, f, r, 0, s));
+    HIPCHK(launch_restrict_red<T>(V, C.view, r, Buf<T>::f(C), s));
+    lasto_status st = vcycle_level<T>(g, l + 1, nu1, nu2, Buf<T>::f(C), Buf<T>::u(C), nullptr, nullptr);
     if (st != LASTO_OK) return st;
-    HIPCHK(launch_prolong_add<T>(V, C.view, ec, buf[cur], s));
+    // a post-smoothing that starts with a black half-sweep recomputes every
+    // black value, so only red nodes take the interpolated correction
+    if (nu2 > 0) HIPCHK(launch_prolong_red<T>(V, C.view, Buf<T>::u(C), u, s));
+    else HIPCHK(launch_prolong_add<T>(V, C.view, Buf<T>::u(C), u, s));
+    const int nb = half_blocks(V);
     for (int k = 0; k < nu2; ++k) {
-        const bool last = (k == nu2 - 1);
-        HIPCHK(sweep<T>(g, l, buf[cur], f, buf[1 - cur], 1, 0, last ? dotp : nullptr));
-        cur = 1 - cur;
+        const bool last = (k == nu2 - 1) && dotp;
+        HIPCHK(half<T>(g, l, u, f, 1, 0, last ? dotp : nullptr));
+        HIPCHK(half<T>(g, l, u, f, 0, 0, last ? dotp + nb : nullptr));
     }
-    if (nu2 == 0 && dotp) HIPCHK(launch_dot<T>(V, f, buf[cur], dotp, s));
-    *result = buf[cur];
+    if (dotp) {
+        if (nu2 > 0) {
+            *ndot = 2 * nb;
+        } else {
+            HIPCHK(launch_dot<T>(V, f, u, dotp, s));
+            *ndot = interior_blocks(V);
+        }
+    }
     return LASTO_OK;
 }
 
@@ -133,29 +141,27 @@ static lasto_status read_scalars(lasto_grid g, int first, int n)
     return LASTO_OK;
 }
 
-// Inner FP32 PCG on A e = r32 (scaled residual) from e = 0, `iters` steps.
+// Inner FP32 PCG on A e = r32 (the scaled residual) from e = 0, `iters` steps.
 static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int iters, int* vcycles)
 {
-    Level& L0 = g->lev[0];
-    const LevelView& V = L0.view;
+    const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
-    const int nb_s = smooth_blocks(V), nb_i = interior_blocks(V);
-    HIPCHK(launch_zero_interior<float>(V, g->e32, s));
-    float* rr = g->r32;   // working residual (in place)
+    const int nb_i = interior_blocks(V);
+    HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
+    float* rr = g->r32;   // working residual, updated in place
     for (int it = 0; it < iters; ++it) {
-        float* z = nullptr;
-        lasto_status st = vcycle_level<float>(g, 0, o.nu1, o.nu2, rr, g->z32, L0.u32[1], g->partials, &z);
+        int nd = 0;
+        lasto_status st = vcycle_level<float>(g, 0, o.nu1, o.nu2, rr, g->z32, g->partials, &nd);
         if (st != LASTO_OK) return st;
         ++*vcycles;
-        const int nb = (g->nlev == 1) ? nb_i : (o.nu2 > 0 ? nb_s : nb_i);
         const int srz = S_RZ32_0 + (it & 1), srz_old = S_RZ32_0 + ((it + 1) & 1);
-        if (lasto_status e = reduce_to(g, nb, srz); e != LASTO_OK) return e;
+        if (lasto_status e = reduce_to(g, nd, srz); e != LASTO_OK) return e;
         float* pn = g->p32[it & 1];
         float* po = g->p32[(it + 1) & 1];
-        HIPCHK(launch_update_p<float>(V, z, po, pn, g->scalars, srz, srz_old, it == 0, s));
+        HIPCHK(launch_update_p<float>(V, g->z32, po, pn, g->scalars, srz, srz_old, it == 0, s));
         HIPCHK(launch_apply_dot<float>(V, pn, g->q32, g->partials, s));
         if (lasto_status e = reduce_to(g, nb_i, S_PQ32); e != LASTO_OK) return e;
-        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s));
+        HIPCHK(launch_update_xr<float>(V, g->e32, 0, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s));
         if (lasto_status e = reduce_to(g, nb_i, S_RR32); e != LASTO_OK) return e;
     }
     return LASTO_OK;
@@ -212,7 +218,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     } prof_off{g};
     Level& L0 = g->lev[0];
     const LevelView& V = L0.view;
-    const int nb_i = interior_blocks(V), nb_s = smooth_blocks(V);
+    const int nb_i = interior_blocks(V);
     const double fourpi = 4.0 * kPi;
 
     // face values
@@ -223,12 +229,16 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     } else if (o.bc == 0) {
         HIPCHK(launch_bc(g, 0, g->moments, 0, v));
     }
-    if (o.guess == 1) HIPCHK(launch_zero_interior<double>(V, v, s));
+    if (o.guess == 1) {
+        // zero interior: copy an all-zero split array onto the interior of v
+        HIPCHK(launch_fill_zero<double>(g->q, split_elems(V), s));
+        HIPCHK(launch_split_to_nat(V, g->q, v, s));
+    }
 
-    // reference norm ||b - A v_bc||_W and initial residual
-    HIPCHK(launch_reference_norm(V, v, rho, fourpi, g->partials, s));
+    // reference norm ||b - A v_bc||_W and initial residual r (split)
+    HIPCHK(launch_residual_nat(V, v, rho, fourpi, nullptr, g->partials, 1, s));
     if (lasto_status e = reduce_to(g, nb_i, S_R0); e != LASTO_OK) return e;
-    HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, g->r, g->partials, s));
+    HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
     if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
     if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
     const double r0sq = g->h_scalars[S_R0];
@@ -241,39 +251,38 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     int grow = 0;
     int it = 0, cg_it = 0;
     while (rel > o.rtol && it < o.max_iters) {
-        if (o.debug_nan_iter == it) HIPCHK(launch_inject_nan(g->r, (size_t)(V.nz / 2) * V.ny * V.nx + (size_t)(V.ny / 2) * V.nx + V.nx / 2, s));
+        if (o.debug_nan_iter == it)
+            HIPCHK(launch_inject_nan(g->r, sidx(V, V.nx / 2, V.ny / 2, V.nz / 2), s));
         if (o.precision == 1) {
-            // FP32 inner PCG on the scaled FP64 residual, then u += |r| e
-            HIPCHK(launch_scale_f64_to_f32(V, g->r, g->r32, g->scalars, S_RR, s));
+            // FP32 inner PCG on the scaled FP64 residual, then v += |r| e
+            HIPCHK(launch_scale_to32(V, g->r, g->r32, g->scalars, S_RR, s));
             if (lasto_status e = pcg32_inner(g, o, o.inner_iters, &inf.vcycles); e != LASTO_OK) return e;
-            HIPCHK(launch_add_scaled_f32_to_f64(V, v, g->e32, g->scalars, S_RR, s));
-            HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, g->r, g->partials, s));
+            HIPCHK(launch_add_scaled32_nat(V, v, g->e32, g->scalars, S_RR, s));
+            HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             inf.refinements++;
         } else if (o.method == 1) {
             // plain V-cycle iteration: v += V(r), r = b - A v
-            double* z = nullptr;
-            lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, L0.u64[1], nullptr, &z);
+            lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, nullptr, nullptr);
             if (st != LASTO_OK) return st;
             inf.vcycles++;
-            HIPCHK(launch_add64(V, v, z, s));
-            HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, g->r, g->partials, s));
+            HIPCHK(launch_add_nat(V, v, g->z, s));
+            HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
         } else {
             // one MG-preconditioned CG step
-            double* z = nullptr;
-            lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, L0.u64[1], g->partials, &z);
+            int nd = 0;
+            lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, g->partials, &nd);
             if (st != LASTO_OK) return st;
             inf.vcycles++;
-            const int nb = (g->nlev == 1) ? nb_i : (o.nu2 > 0 ? nb_s : nb_i);
             const int srz = S_RZ0 + (cg_it & 1), srz_old = S_RZ0 + ((cg_it + 1) & 1);
-            if (lasto_status e = reduce_to(g, nb, srz); e != LASTO_OK) return e;
+            if (lasto_status e = reduce_to(g, nd, srz); e != LASTO_OK) return e;
             double* pn = g->p[cg_it & 1];
             double* po = g->p[(cg_it + 1) & 1];
-            HIPCHK(launch_update_p<double>(V, z, po, pn, g->scalars, srz, srz_old, cg_it == 0, s));
+            HIPCHK(launch_update_p<double>(V, g->z, po, pn, g->scalars, srz, srz_old, cg_it == 0, s));
             HIPCHK(launch_apply_dot<double>(V, pn, g->q, g->partials, s));
             if (lasto_status e = reduce_to(g, nb_i, S_PQ); e != LASTO_OK) return e;
-            HIPCHK(launch_update_xr<double>(V, v, g->r, pn, g->q, g->scalars, srz, S_PQ, g->partials, s));
+            HIPCHK(launch_update_xr<double>(V, v, 1, g->r, pn, g->q, g->scalars, srz, S_PQ, g->partials, s));
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             cg_it++;
         }
@@ -295,7 +304,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         if (rel <= o.rtol && o.precision == 0 && o.method == 0) {
             // the CG residual is a recurrence: confirm with the true residual,
             // and restart CG from it if the two have drifted apart
-            HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, g->r, g->partials, s));
+            HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;
             rel = std::sqrt(g->h_scalars[S_RR]) / r0;
@@ -303,13 +312,13 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         }
     }
     // true residual of the returned iterate
-    HIPCHK(launch_residual_norm<double>(V, v, rho, fourpi, (double*)nullptr, g->partials, s));
+    HIPCHK(launch_residual_nat(V, v, rho, fourpi, nullptr, g->partials, 0, s));
     if (lasto_status e = reduce_to(g, nb_i, S_TMP); e != LASTO_OK) return e;
     if (lasto_status e = read_scalars(g, S_TMP, 1); e != LASTO_OK) return e;
     inf.rel_resid = std::sqrt(g->h_scalars[S_TMP]) / r0;
     inf.iters = it;
     if (g->prof_on) {
-        // the stream has been synchronised by read_scalars: every event is complete
+        // read_scalars synchronised the stream: every event has completed
         double ms = 0.0;
         for (int k = 0; k < g->prof_used; ++k) {
             float e = 0.0f;
@@ -334,10 +343,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
 extern "C" lasto_status lasto_apply(lasto_grid g, const double* u, double* Au)
 {
     if (!g || !u || !Au || u == Au) return fail(LASTO_ERR_ARG, "lasto_apply: NULL or aliased buffers");
-    const LevelView& V = g->lev[0].view;
-    HIPCHK(launch_residual<double>(V, u, u, 0.0, Au, g->stream));
-    // launch_residual computes 0*u - A u; negate in place
-    HIPCHK(launch_scale_inplace(V, Au, -1.0, g->stream));
+    HIPCHK(launch_apply_nat(g->lev[0].view, u, Au, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
     return LASTO_OK;
 }
@@ -348,7 +354,13 @@ extern "C" lasto_status lasto_rb_sweep(lasto_grid g, const double* u_in, const d
     if (!g || !u_in || !rho || !u_out || u_in == u_out || (first_colour != 0 && first_colour != 1))
         return fail(LASTO_ERR_ARG, "lasto_rb_sweep: NULL/aliased buffers or bad colour");
     const LevelView& V = g->lev[0].view;
-    HIPCHK(launch_smooth<double>(V, u_in, rho, u_out, 4.0 * kPi, first_colour, 0, nullptr, g->stream));
+    hipStream_t s = g->stream;
+    // the sweep runs in the solver's split layout on grid scratch
+    HIPCHK(launch_nat_to_split(V, u_in, g->z, s));
+    HIPCHK(launch_nat_to_split(V, rho, g->q, s));
+    HIPCHK(launch_half<double>(V, g->z, g->q, first_colour, 0, 4.0 * kPi, nullptr, s));
+    HIPCHK(launch_half<double>(V, g->z, g->q, 1 - first_colour, 0, 4.0 * kPi, nullptr, s));
+    HIPCHK(launch_split_to_nat(V, g->z, u_out, s));
     HIPCHK(hipStreamSynchronize(g->stream));
     return LASTO_OK;
 }

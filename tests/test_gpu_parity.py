@@ -320,8 +320,12 @@ def test_profile_counts_sweeps(torch, L, oracle_mod):
     g = L.Grid(*xs)
     rho = g.pseudo_density(w.atoms)
     info = g.poisson_solve(rho, g.empty(), profile=1)
-    assert info["smooth_launches"] == 4 * info["vcycles"]
-    assert info["smooth_ms"] > 0 and info["smooth_bytes"] > 0
+    # V(2,2): four sweeps of two half-sweeps each on the finest level
+    assert info["smooth_launches"] == 8 * info["vcycles"]
+    assert info["smooth_ms"] > 0
+    # 24 B per interior node per sweep, less 4 B for the sweep from zero
+    n_int = 63 ** 3
+    assert abs(info["smooth_bytes"] - info["vcycles"] * n_int * (4 * 24 - 4)) < 1e-6 * info["smooth_bytes"]
     info = g.poisson_solve(rho, g.empty())
     assert info["smooth_launches"] == 0
     g.close()
