@@ -157,10 +157,49 @@ lasto_status build_level_tables(lasto_grid g, int l)
     L.view.nx = L.n[0];
     L.view.ny = L.n[1];
     L.view.nz = L.n[2];
-    // split-layout row: entries 0..nx/2 of one colour, padded to 16 (128 B in FP64)
-    L.view.W = ((L.n[0] / 2 + 1) + 15) / 16 * 16;
+    // split-layout row: entries 0..nx/2 of one colour plus two spare entries
+    // (a half-sweep pair at the row's end reads one past it), padded to 16
+    // (128 B in FP64)
+    L.view.W = ((L.n[0] / 2 + 3) + 15) / 16 * 16;
     L.view.cs = (size_t)L.n[2] * L.n[1] * L.view.W;
     L.nsplit = 2 * L.view.cs;
+
+    // x coefficients by parity ([p][q][m], node i = p + 2m; zero off the
+    // interior) in FP64 and FP32, and FP32 copies of every axis' am/ap
+    const int W = L.view.W, nx = L.n[0];
+    std::vector<double> xp(6 * (size_t)W, 0.0);
+    for (int p = 0; p < 2; ++p)
+        for (int m = 0; m < W; ++m) {
+            const int i = p + 2 * m;
+            if (i < 1 || i > nx - 2) continue;
+            xp[(p * 3 + 0) * (size_t)W + m] = hd[od_own[0] + i];
+            xp[(p * 3 + 1) * (size_t)W + m] = hd[od_own[0] + nx + i];
+            xp[(p * 3 + 2) * (size_t)W + m] = hd[od_own[0] + 2 * nx + i];
+        }
+    size_t nf = 6 * (size_t)W;
+    for (int d = 0; d < 3; ++d) nf += 2 * (size_t)L.n[d];
+    std::vector<float> hf(nf, 0.0f);
+    for (size_t t = 0; t < 6 * (size_t)W; ++t) hf[t] = (float)xp[t];
+    size_t of = 6 * (size_t)W;
+    size_t ofs[3];
+    for (int d = 0; d < 3; ++d) {
+        ofs[d] = of;
+        for (int i = 0; i < L.n[d]; ++i) {
+            hf[of + i] = (float)hd[od_own[d] + i];
+            hf[of + L.n[d] + i] = (float)hd[od_own[d] + L.n[d] + i];
+        }
+        of += 2 * (size_t)L.n[d];
+    }
+    LASTO_HIP(hipMalloc(&L.dxpar, sizeof(double) * xp.size()));
+    LASTO_HIP(hipMalloc(&L.dtabf, sizeof(float) * hf.size()));
+    LASTO_HIP(hipMemcpy(L.dxpar, xp.data(), sizeof(double) * xp.size(), hipMemcpyHostToDevice));
+    LASTO_HIP(hipMemcpy(L.dtabf, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice));
+    L.view.xpar = L.dxpar;
+    L.view.xparf = L.dtabf;
+    for (int d = 0; d < 3; ++d) {
+        L.view.ax[d].amf = L.dtabf + ofs[d];
+        L.view.ax[d].apf = L.dtabf + ofs[d] + L.n[d];
+    }
     return LASTO_OK;
 }
 
@@ -177,6 +216,8 @@ static void free_grid(lasto_grid g)
         Level& L = g->lev[l];
         (void)hipFree(L.dtab);
         (void)hipFree(L.dtabi);
+        (void)hipFree(L.dxpar);
+        (void)hipFree(L.dtabf);
         (void)hipFree(L.u64);
         (void)hipFree(L.u32);
         (void)hipFree(L.f64);
@@ -189,6 +230,7 @@ static void free_grid(lasto_grid g)
     (void)hipFree(g->p[1]);
     (void)hipFree(g->q);
     (void)hipFree(g->z);
+    (void)hipFree(g->x);
     (void)hipFree(g->r32);
     (void)hipFree(g->p32[0]);
     (void)hipFree(g->p32[1]);
@@ -295,6 +337,7 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p[1], sizeof(double) * N);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->q, sizeof(double) * N);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->z, sizeof(double) * N);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->x, sizeof(double) * N);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->r32, sizeof(float) * N);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p32[0], sizeof(float) * N);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->p32[1], sizeof(float) * N);
@@ -308,6 +351,7 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
     for (int l = 0; l < g->nlev; ++l) {
         nparts = std::max(nparts, (size_t)interior_blocks(g->lev[l].view));
         nparts = std::max(nparts, (size_t)2 * half_blocks(g->lev[l].view));
+        nparts = std::max(nparts, (size_t)row_blocks(g->lev[l].view));
     }
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->partials, sizeof(double) * nparts);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->scalars, sizeof(double) * kNumScalars);

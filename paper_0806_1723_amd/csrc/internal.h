@@ -67,7 +67,14 @@ struct Axis {
     const double* rw;
     const int* pc;
     const double* pw;
+    const float* amf;   // FP32 copies of am, ap
+    const float* apf;
 };
+
+// x coefficients by parity for the half-sweeps: entry [p][q][m] (q = 0 am,
+// 1 ap, 2 dual width) of node i = p + 2m, zero where i is not interior;
+// rows of W entries. One block per precision.
+template <typename T> struct XPar;
 
 // Colour-split storage of multigrid arrays: node (i,j,k) of colour
 // c = (i+j+k) & 1 lives at [c][k][j][i >> 1] in rows of W (padded) entries,
@@ -78,6 +85,15 @@ struct LevelView {
     int W;          // padded row length of one colour (>= (nx+1)/2)
     size_t cs;      // colour stride = nz * ny * W
     Axis ax[3];
+    const double* xpar;   // [2][3][W] x coefficients by parity (FP64)
+    const float* xparf;   // the same in FP32
+};
+
+template <> struct XPar<double> {
+    __host__ __device__ static const double* get(const LevelView& L) { return L.xpar; }
+};
+template <> struct XPar<float> {
+    __host__ __device__ static const float* get(const LevelView& L) { return L.xparf; }
 };
 
 __host__ __device__ __forceinline__ size_t sidx(const LevelView& L, int i, int j, int k)
@@ -93,6 +109,8 @@ struct Level {
     std::vector<int> keep[3];      // index in the finer level (level > 0)
     double* dtab = nullptr;        // device table block
     int* dtabi = nullptr;
+    double* dxpar = nullptr;       // device x-parity table (FP64)
+    float* dtabf = nullptr;        // device FP32 tables (am, ap per axis; x-parity)
     LevelView view;
     // V-cycle work arrays (split layout): correction, right-hand side, residual
     double* u64 = nullptr;
@@ -142,6 +160,7 @@ struct lasto_grid_s {
     double* z = nullptr;
     double* p[2] = {nullptr, nullptr};
     double* q = nullptr;
+    double* x = nullptr;       // PCG correction to v, added to v at convergence
     // FP32 inner-solve vectors on the fine level (split layout)
     float* r32 = nullptr;
     float* z32 = nullptr;
@@ -177,9 +196,13 @@ size_t split_elems(const LevelView& L);
 // nodes of colour c solve their equation from the other colour's values.
 // zero_in: the other colour is read as zero. dotp (optional): per-block
 // partials of sum vol * f * u_new over the updated nodes.
+// *nparts (optional): partials written (one per workgroup; at most half_blocks(L)).
 template <typename T>
 hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
-                       hipStream_t s);
+                       hipStream_t s, int* nparts = nullptr);
+// the same on an array whose faces carry Dirichlet data (written back unchanged)
+template <typename T>
+hipError_t launch_half_keep_faces(const LevelView& L, T* u, const T* f, int colour, T bscale, hipStream_t s);
 template <typename T>
 hipError_t launch_residual(const LevelView& L, const T* u, const T* f, T* r, hipStream_t s);
 template <typename T>
@@ -193,6 +216,10 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, const T* e
 // half-sweep only red nodes need the coarse correction (prolong_red).
 template <typename T>
 hipError_t launch_residual_colour(const LevelView& L, const T* u, const T* f, T* r, int colour, hipStream_t s);
+// q = A p on the nodes of one colour, partials of <p, q>_W over them
+template <typename T>
+hipError_t launch_apply_colour(const LevelView& L, const T* p, T* q, int colour, double* dotp, hipStream_t s,
+                               int* nparts);
 template <typename T>
 hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s);
 template <typename T>
@@ -210,11 +237,11 @@ hipError_t launch_dot(const LevelView& L, const T* a, const T* b, double* partia
 template <typename T>
 hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pnew, const double* scal,
                            int i_num, int i_den, int first, hipStream_t s);
-// x += alpha p, r -= alpha q (split), alpha = scal[i_num]/scal[i_den]; x is a
-// natural-layout FP64 array when x_nat, else a split T array.
+// x += alpha p, r -= alpha q (all split), alpha = scal[i_num]/scal[i_den]
 template <typename T>
-hipError_t launch_update_xr(const LevelView& L, void* x, int x_nat, T* r, const T* p, const T* q,
-                            const double* scal, int i_num, int i_den, double* partials, hipStream_t s);
+hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
+                            int i_den, double* partials, hipStream_t s);
+int row_blocks(const LevelView& L);   // partials of the elementwise split kernels (dot, update_xr)
 // natural-layout fine-level helpers
 hipError_t launch_residual_nat(const LevelView& L, const double* v, const double* rho, double bscale, double* r_split,
                                double* partials, int interior_zero, hipStream_t s);

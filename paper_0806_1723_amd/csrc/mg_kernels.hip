@@ -138,23 +138,64 @@ __device__ __forceinline__ T prolong_point(const LevelView& C, const T* __restri
 // rows share an L2. Ids past the last tile only contribute a zero partial.
 __device__ __forceinline__ int xcd_tile(int id, int per) { return (id & 7) * per + (id >> 3); }
 
-constexpr int HS_X = 64, HS_Y = 4, HS_NT = HS_X * HS_Y, HS_KC_MAX = 16, HS_BLOCKS = 2048;
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <typename T> __device__ __forceinline__ const T* tab_am(const Axis& a);
+template <typename T> __device__ __forceinline__ const T* tab_ap(const Axis& a);
+template <> __device__ __forceinline__ const float* tab_am<float>(const Axis& a) { return a.amf; }
+template <> __device__ __forceinline__ const float* tab_ap<float>(const Axis& a) { return a.apf; }
+template <> __device__ __forceinline__ const double* tab_am<double>(const Axis& a) { return a.am; }
+template <> __device__ __forceinline__ const double* tab_ap<double>(const Axis& a) { return a.ap; }
+
+// 1/d: the hardware reciprocal refined by Newton steps r <- r + r (1 - d r)
+// (one in FP32, two in FP64), within about half an ulp of the quotient
+__device__ __forceinline__ float recip(float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(fmaf(-d, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return r;
+}
+
+enum HalfMode { HM_GS = 0, HM_RESID = 1, HM_APPLY = 2 };
+
+// Over the nodes of colour c (two neighbouring entries m, m+1 of a colour
+// row per thread, loaded as one 8- or 16-byte vector):
+//   HM_GS    out_n = (sum_d am_d u_{n-e_d} + ap_d u_{n+e_d} - bscale f_n) / sum_d (am_d + ap_d)
+//            (the Gauss-Seidel update of a red-black half-sweep; dot += vol f out)
+//   HM_RESID out_n = bscale f_n - (A u)_n
+//   HM_APPLY out_n = (A u)_n                                     (dot += vol u out)
+// The neighbours all have the other colour: entry m of the other colour on
+// planes k-1 and k+1 holds the z neighbours, entries m-1+o and m+o the x
+// neighbours (o = (c+j+k) & 1), rows j-1 and j+1 the y neighbours. A thread
+// marches over a chunk of planes keeping the z neighbours in a register queue
+// and loading plane k+1's operands while it computes plane k. `uo` (other
+// colour), `fc`, `ucen` and `out` (this colour) are distinct arrays, so the
+// loads may run ahead of the stores.
+constexpr int H2_X = 64, H2_Y = 4, H2_NT = H2_X * H2_Y, H2_KC_MAX = 16, H2_BLOCKS = 2048;
 
 struct HalfShape {
     int nbx, nby, nbz, nb, per, grid, kc;
 };
 
-// Planes per thread: as many as keep about HS_BLOCKS workgroups (the z-march
-// saves re-reads, but its planes are a serial chain of loads, so small levels
-// march one plane per thread).
+// Planes per thread: as many as keep about H2_BLOCKS workgroups (the march
+// saves re-reads, but its planes form a serial chain, so small levels march
+// one plane per thread).
 static HalfShape half_shape(const LevelView& L)
 {
     HalfShape h;
-    const int mcount = (L.nx - 2) / 2 + 1;   // i >> 1 over every interior i
-    h.nbx = (mcount + HS_X - 1) / HS_X;
-    h.nby = (L.ny - 2 + HS_Y - 1) / HS_Y;
+    const int npairs = ((L.nx - 2) / 2) / 2 + 1;   // pairs (m, m+1), m even, m <= (nx-2)/2
+    h.nbx = (npairs + H2_X - 1) / H2_X;
+    h.nby = (L.ny - 2 + H2_Y - 1) / H2_Y;
     const long tiles = (long)h.nbx * h.nby;
-    h.kc = (int)std::min<long>(HS_KC_MAX, std::max<long>(1, (long)(L.nz - 2) * tiles / HS_BLOCKS));
+    h.kc = (int)std::min<long>(H2_KC_MAX, std::max<long>(1, (long)(L.nz - 2) * tiles / H2_BLOCKS));
     h.nbz = (L.nz - 2 + h.kc - 1) / h.kc;
     h.nb = h.nbx * h.nby * h.nbz;
     h.per = (h.nb + 7) / 8;
@@ -164,110 +205,201 @@ static HalfShape half_shape(const LevelView& L)
 
 int half_blocks(const LevelView& L) { return half_shape(L).grid; }
 
-// Nodes of colour c solve their own equation with the other colour's values
-// (RESID = false):
-//   u_n = (sum_d am_d u_{n-e_d} + ap_d u_{n+e_d} - bscale f_n) / sum_d (am_d + ap_d),
-// or (RESID = true) get their residual out_n = bscale f_n - (A u)_n.
-// A thread owns the entries [c][k][j][m] for one (j, m) and marches over a
-// chunk of planes, keeping the other colour's z-neighbours in a register
-// queue (entry m of the other colour on planes k-1, k, k+1 holds both z
-// neighbours and one x neighbour) and loading plane k+1's operands while it
-// computes plane k. `uo` (the other colour), `fc` and `out` (this colour) are
-// distinct arrays, so the loads may run ahead of the store.
-template <typename T, bool RESID>
-__global__ __launch_bounds__(HS_NT) void k_half(LevelView L, const T* __restrict__ uo, const T* __restrict__ fc,
-                                                const T* __restrict__ ucen, T* __restrict__ out, int c, int zero_in,
-                                                T bscale, double* __restrict__ dotp, int nbx, int nby, int nb, int per,
-                                                int kc)
+template <typename T> struct HalfOps {
+    typename Vec2<T>::type ym, yp, fv, cv;   // y neighbours, f and centre of a pair
+    T xe;                                    // the x neighbour outside the z queue
+};
+
+template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES>
+__global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restrict__ uo, const T* __restrict__ fc,
+                                                 const T* __restrict__ ucen, T* __restrict__ out, int c, T bscale,
+                                                 double* __restrict__ dotp, int nbx, int nby, int nb, int per, int kc)
 {
-    __shared__ double red[HS_NT / 64];
-    const int t = xcd_tile(blockIdx.x, per);
+    using V2 = typename Vec2<T>::type;
+    __shared__ double red[H2_NT / 64];
+    constexpr bool NEED_U = !ZERO_IN || MODE != HM_GS;
     double dot = 0.0;
-    const int m = (t % nbx) * HS_X + (threadIdx.x & (HS_X - 1));
-    const int j = 1 + ((t / nbx) % nby) * HS_Y + (threadIdx.x >> 6);
-    if (t < nb && j <= L.ny - 2 && m <= (L.nx - 2) / 2) {
+    const int nx = L.nx, nz = L.nz, W = L.W;
+    const size_t plane = (size_t)L.ny * W;
+    const T* __restrict__ xp = XPar<T>::get(L);
+    const T* __restrict__ amz = tab_am<T>(L.ax[2]);
+    const T* __restrict__ apz = tab_ap<T>(L.ax[2]);
+    // Persistent workgroups: workgroup b takes ids b, b + G, ... (G =
+    // gridDim.x, a multiple of 8, so every id it takes maps to a tile of the
+    // XCD it runs on).
+    for (int id = blockIdx.x; id < 8 * per; id += gridDim.x) {
+        const int t = xcd_tile(id, per);
+        const int m = 2 * ((t % nbx) * H2_X + (threadIdx.x & (H2_X - 1)));
+        const int j = 1 + ((t / nbx) % nby) * H2_Y + (threadIdx.x >> 6);
+        if (!(t < nb && j <= L.ny - 2 && m <= (nx - 2) / 2)) continue;
         const int k0 = 1 + (t / (nbx * nby)) * kc;
-        const int k1 = min(k0 + kc, L.nz - 1);
-        const int nx = L.nx;
-        const int W = L.W;
-        const size_t plane = (size_t)L.ny * W;
+        const int k1 = min(k0 + kc, nz - 1);
         const size_t row = (size_t)j * W + m;
-        const T cym = (T)L.ax[1].am[j], cyp = (T)L.ax[1].ap[j];
-        const double* __restrict__ amx = L.ax[0].am;
-        const double* __restrict__ apx = L.ax[0].ap;
-        // operands of plane k: z queue, the other x neighbour, y neighbours, f, centre
-        T zm = T(0), zc = T(0), zp = T(0), xo = T(0), ym = T(0), yp = T(0), fv, cv = T(0);
-        auto load_plane = [&](int k, T& x_o, T& y_m, T& y_p, T& f_v, T& c_v) {
+        // both parities' x coefficients, picked per plane by select (named
+        // values, not an array indexed at run time, so they stay in registers)
+        const V2 axm0 = *(const V2*)(xp + (size_t)0 * W + m), axm1 = *(const V2*)(xp + (size_t)3 * W + m);
+        const V2 axp0 = *(const V2*)(xp + (size_t)1 * W + m), axp1 = *(const V2*)(xp + (size_t)4 * W + m);
+        V2 axv0{}, axv1{};
+        if (DOT) {
+            axv0 = *(const V2*)(xp + (size_t)2 * W + m);
+            axv1 = *(const V2*)(xp + (size_t)5 * W + m);
+        }
+        const T cym = tab_am<T>(L.ax[1])[j], cyp = tab_ap<T>(L.ax[1])[j];
+        const double vy = DOT ? L.ax[1].m[j] : 0.0;
+        // the x neighbour not in the z queue: entry m+2 (o = 1) or m-1 (o = 0; m = 0 has no interior node)
+        const int xoff1 = 2, xoff0 = m > 0 ? -1 : 0;
+        auto load_plane = [&](int k, HalfOps<T>& q) {
             const size_t at = (size_t)k * plane + row;
             const int o = (c + j + k) & 1;
-            f_v = fc[at];
-            if (RESID) c_v = ucen[at];
-            if (!zero_in) {
-                x_o = o ? uo[at + 1] : uo[at - (m > 0 ? 1 : 0)];
-                y_m = uo[at - W];
-                y_p = uo[at + W];
+            if (MODE != HM_APPLY) q.fv = *(const V2*)(fc + at);
+            if (MODE != HM_GS) q.cv = *(const V2*)(ucen + at);
+            if (NEED_U) {
+                q.ym = *(const V2*)(uo + at - W);
+                q.yp = *(const V2*)(uo + at + W);
+                q.xe = uo[at + (o ? xoff1 : xoff0)];
             }
         };
-        if (!zero_in) {
-            zm = uo[(size_t)(k0 - 1) * plane + row];
-            zc = uo[(size_t)k0 * plane + row];
-            zp = uo[(size_t)(k0 + 1) * plane + row];
-        }
-        load_plane(k0, xo, ym, yp, fv, cv);
-        for (int k = k0; k < k1; ++k) {
-            // prefetch plane k+1 (and the z queue's next entry)
-            T xo_n = T(0), ym_n = T(0), yp_n = T(0), fv_n = T(0), cv_n = T(0), znext = T(0);
-            if (k + 1 < k1) {
-                load_plane(k + 1, xo_n, ym_n, yp_n, fv_n, cv_n);
-                if (!zero_in) znext = uo[(size_t)(k + 2) * plane + row];
-            }
+        auto load_z = [&](int k) -> V2 {
+            V2 z{};
+            if (NEED_U) z = *(const V2*)(uo + (size_t)k * plane + row);
+            return z;
+        };
+        // plane k from its operands and the z neighbours (zm, zc, zp)
+        auto compute = [&](int k, const HalfOps<T>& q, const V2& zm, const V2& zc, const V2& zp) {
             const int o = (c + j + k) & 1;
-            const int i = o + 2 * m;
-            if (i >= 1 && i <= nx - 2) {
-                const size_t at = (size_t)k * plane + row;
-                const T cxm = (T)amx[i], cxp = (T)apx[i];
-                const T czm = (T)L.ax[2].am[k], czp = (T)L.ax[2].ap[k];
-                T s = T(0);
-                if (!zero_in) {
-                    // x neighbours i-1, i+1 of the other colour sit at m-1+o and m+o
-                    const T xl = o ? zc : xo;
-                    const T xr = o ? xo : zc;
-                    s = cxm * xl + cxp * xr;
-                    s += cym * ym + cyp * yp;
-                    s += czm * zm + czp * zp;
+            const int i0 = o + 2 * m;
+            const bool ok0 = i0 >= 1 && i0 <= nx - 2;
+            const bool ok1 = i0 + 2 <= nx - 2;
+            const V2 cxm = o ? axm1 : axm0, cxp = o ? axp1 : axp0;
+            const T czm = amz[k], czp = apz[k];
+            // x neighbours of the pair: o = 1: (zc.x, zc.y), (zc.y, xe); o = 0: (xe, zc.x), (zc.x, zc.y)
+            const T xl0 = o ? zc.x : q.xe, xr0 = o ? zc.y : zc.x;
+            const T xl1 = o ? zc.y : zc.x, xr1 = o ? q.xe : zc.y;
+            T r0, r1;
+            if (MODE == HM_GS) {
+                const T cyz = cym + cyp + czm + czp;
+                const T d0 = cxm.x + cxp.x + cyz, d1 = cxm.y + cxp.y + cyz;
+                T s0 = T(0), s1 = T(0);
+                if (NEED_U) {
+                    s0 = cxm.x * xl0 + cxp.x * xr0;
+                    s1 = cxm.y * xl1 + cxp.y * xr1;
+                    s0 += cym * q.ym.x + cyp * q.yp.x;
+                    s1 += cym * q.ym.y + cyp * q.yp.y;
+                    s0 += czm * zm.x + czp * zp.x;
+                    s1 += czm * zm.y + czp * zp.y;
                 }
-                const T d = cxm + cxp + cym + cyp + czm + czp;
-                T res;
-                if (RESID) res = bscale * fv - (s - d * cv);
-                else res = (s - bscale * fv) / d;
-                out[at] = res;
-                if (dotp) dot += vol_at(L, i, j, k) * (double)fv * (double)res;
+                r0 = (s0 - bscale * q.fv.x) * recip(d0);
+                r1 = (s1 - bscale * q.fv.y) * recip(d1);
+            } else {
+                // (A u) in difference form, which keeps FP32 free of cancellation
+                const T c0 = q.cv.x, c1 = q.cv.y;
+                T a0 = cxm.x * (xl0 - c0) + cxp.x * (xr0 - c0);
+                T a1 = cxm.y * (xl1 - c1) + cxp.y * (xr1 - c1);
+                a0 += cym * (q.ym.x - c0) + cyp * (q.yp.x - c0);
+                a1 += cym * (q.ym.y - c1) + cyp * (q.yp.y - c1);
+                a0 += czm * (zm.x - c0) + czp * (zp.x - c0);
+                a1 += czm * (zm.y - c1) + czp * (zp.y - c1);
+                r0 = MODE == HM_RESID ? bscale * q.fv.x - a0 : a0;
+                r1 = MODE == HM_RESID ? bscale * q.fv.y - a1 : a1;
             }
-            zm = zc;
-            zc = zp;
-            zp = znext;
-            xo = xo_n;
-            ym = ym_n;
-            yp = yp_n;
-            fv = fv_n;
-            cv = cv_n;
+            const size_t at = (size_t)k * plane + row;
+            if (ZERO_FACES) {
+                // face and padding entries of this array are zero: store the
+                // pair unconditionally, with zero where a node is not interior
+                V2 w;
+                w.x = ok0 ? r0 : T(0);
+                w.y = ok1 ? r1 : T(0);
+                *(V2*)(out + at) = w;
+            } else {
+                if (ok0) out[at] = r0;
+                if (ok1) out[at + 1] = r1;
+            }
+            if (DOT) {
+                const double vz = vy * L.ax[2].m[k];
+                const T a0 = MODE == HM_APPLY ? q.cv.x : q.fv.x;
+                const T a1 = MODE == HM_APPLY ? q.cv.y : q.fv.y;
+                const V2 av = o ? axv1 : axv0;   // zero off the interior
+                dot += (double)av.x * vz * (double)a0 * (double)r0;
+                dot += (double)av.y * vz * (double)a1 * (double)r1;
+            }
+        };
+        // two planes per step with alternating operand sets (A: even steps,
+        // B: odd), so the next plane's loads are in flight while one plane is
+        // computed and no register copies wait on them
+        HalfOps<T> A{}, B{};
+        V2 z0 = load_z(k0 - 1), z1 = load_z(k0), z2 = load_z(k0 + 1);
+        load_plane(k0, A);
+        for (int k = k0; k < k1; k += 2) {
+            load_plane(min(k + 1, k1 - 1), B);
+            const V2 z3 = load_z(min(k + 2, nz - 1));
+            compute(k, A, z0, z1, z2);
+            if (k + 1 < k1) {
+                load_plane(min(k + 2, k1 - 1), A);
+                const V2 z4 = load_z(min(k + 3, nz - 1));
+                compute(k + 1, B, z1, z2, z3);
+                z0 = z2;
+                z1 = z3;
+                z2 = z4;
+            }
         }
     }
-    if (dotp) {
-        const double s = block_sum<HS_NT>(dot, red);
+    if (DOT) {
+        const double s = block_sum<H2_NT>(dot, red);
         if (threadIdx.x == 0) dotp[blockIdx.x] = s;
     }
 }
 
-template <typename T>
-hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
-                       hipStream_t s)
+// Resident workgroups of one half-sweep variant on the whole device (a
+// multiple of 8, at least 8); the persistent launch never exceeds it, so no
+// workgroup waits for a second round.
+template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES>
+static int half_cap()
+{
+    static const int cap = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 8;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 8;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_half2<T, MODE, ZERO_IN, DOT, ZERO_FACES>, H2_NT,
+                                                         0) != hipSuccess)
+            return 8;
+        return std::max(8, per_cu * cus / 8 * 8);
+    }();
+    return cap;
+}
+
+template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES>
+static hipError_t launch_half2(const LevelView& L, const T* u, const T* f, T* out, int colour, T bscale,
+                               double* dotp, hipStream_t s, int* nparts)
 {
     const HalfShape h = half_shape(L);
-    hipLaunchKernelGGL((k_half<T, false>), dim3(h.grid), dim3(HS_NT), 0, s, L, u + (size_t)(1 - colour) * L.cs,
-                       f + (size_t)colour * L.cs, (const T*)nullptr, u + (size_t)colour * L.cs, colour, zero_in, bscale,
-                       dotp, h.nbx, h.nby, h.nb, h.per, h.kc);
+    const int G = std::min(h.grid, half_cap<T, MODE, ZERO_IN, DOT, ZERO_FACES>());
+    const size_t own = (size_t)colour * L.cs, other = (size_t)(1 - colour) * L.cs;
+    hipLaunchKernelGGL((k_half2<T, MODE, ZERO_IN, DOT, ZERO_FACES>), dim3(G), dim3(H2_NT), 0, s, L, u + other,
+                       f ? f + own : (const T*)nullptr, u + own, out + own, colour, bscale, dotp, h.nbx, h.nby, h.nb,
+                       h.per, h.kc);
+    if (nparts) *nparts = G;
     return hipGetLastError();
+}
+
+// In the multigrid arrays (corrections, right-hand sides, residuals) faces
+// and padding are zero, so the sweeps store pairs unconditionally.
+template <typename T>
+hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
+                       hipStream_t s, int* nparts)
+{
+    if (zero_in) {
+        if (dotp) return launch_half2<T, HM_GS, true, true, true>(L, u, f, u, colour, bscale, dotp, s, nparts);
+        return launch_half2<T, HM_GS, true, false, true>(L, u, f, u, colour, bscale, nullptr, s, nparts);
+    }
+    if (dotp) return launch_half2<T, HM_GS, false, true, true>(L, u, f, u, colour, bscale, dotp, s, nparts);
+    return launch_half2<T, HM_GS, false, false, true>(L, u, f, u, colour, bscale, nullptr, s, nparts);
+}
+
+// the same half-sweep on an array whose faces hold Dirichlet data (kept)
+template <typename T>
+hipError_t launch_half_keep_faces(const LevelView& L, T* u, const T* f, int colour, T bscale, hipStream_t s)
+{
+    return launch_half2<T, HM_GS, false, false, false>(L, u, f, u, colour, bscale, nullptr, s, nullptr);
 }
 
 // residual f - A u at the nodes of one colour only (written into that
@@ -275,11 +407,15 @@ hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zer
 template <typename T>
 hipError_t launch_residual_colour(const LevelView& L, const T* u, const T* f, T* r, int colour, hipStream_t s)
 {
-    const HalfShape h = half_shape(L);
-    hipLaunchKernelGGL((k_half<T, true>), dim3(h.grid), dim3(HS_NT), 0, s, L, u + (size_t)(1 - colour) * L.cs,
-                       f + (size_t)colour * L.cs, u + (size_t)colour * L.cs, r + (size_t)colour * L.cs, colour, 0,
-                       T(1), (double*)nullptr, h.nbx, h.nby, h.nb, h.per, h.kc);
-    return hipGetLastError();
+    return launch_half2<T, HM_RESID, false, false, true>(L, u, f, r, colour, T(1), nullptr, s, nullptr);
+}
+
+// q = A p on one colour, with partials of <p, q>_W over that colour
+template <typename T>
+hipError_t launch_apply_colour(const LevelView& L, const T* p, T* q, int colour, double* dotp, hipStream_t s,
+                               int* nparts)
+{
+    return launch_half2<T, HM_APPLY, false, true, true>(L, p, (const T*)nullptr, q, colour, T(1), dotp, s, nparts);
 }
 
 // ------------------------------------------------- pointwise 3-D launches
@@ -441,17 +577,60 @@ hipError_t launch_apply_dot(const LevelView& L, const T* p, T* q, double* partia
     return hipGetLastError();
 }
 
+// Elementwise Krylov kernels walk the split storage row by row: a
+// workgroup covers 64 entries x 4 rows of one colour over a chunk of planes.
+// Entries off the interior (faces, padding) are zero in every vector these
+// kernels touch and stay zero; their volume weight (parity table) is zero.
+struct RowShape {
+    dim3 grid;
+    int kp;
+};
+
+static RowShape row_shape(const LevelView& L)
+{
+    RowShape r;
+    const int gx = (L.W + PT_X - 1) / PT_X, gy = (L.ny - 2 + PT_Y - 1) / PT_Y;
+    const long tiles = 2L * gx * gy;
+    r.kp = (int)std::min<long>(PT_KP_MAX, std::max<long>(1, (long)(L.nz - 2) * tiles / PT_BLOCKS));
+    r.grid = dim3(gx, gy, 2 * ((L.nz - 2 + r.kp - 1) / r.kp));
+    return r;
+}
+
+int row_blocks(const LevelView& L)
+{
+    const dim3 g = row_shape(L).grid;
+    return (int)(g.x * g.y * g.z);
+}
+
+#define ROW_LOOP                                                          \
+    const int m = blockIdx.x * PT_X + (threadIdx.x % PT_X);               \
+    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);           \
+    const int c = blockIdx.z & 1;                                         \
+    const bool inside = (m < L.W) && (j <= L.ny - 2);                     \
+    const int kb_ = 1 + (blockIdx.z >> 1) * kp;                           \
+    const int ke_ = min(kb_ + kp, L.nz - 1);                              \
+    for (int k = kb_; k < ke_; ++k)
+
+#define ROW_AT ((size_t)c * L.cs + ((size_t)k * L.ny + j) * L.W + m)
+#define ROW_VOL (L.xpar[(size_t)(((c + j + k) & 1) * 3 + 2) * L.W + m] * L.ax[1].m[j] * L.ax[2].m[k])
+
+#define ROW_LAUNCH(kernel, L, s, ...)                                                        \
+    do {                                                                                     \
+        const RowShape rs_ = row_shape(L);                                                   \
+        hipLaunchKernelGGL(kernel, rs_.grid, dim3(PT_NT), 0, s, L, rs_.kp, __VA_ARGS__);      \
+    } while (0)
+
 template <typename T>
 __global__ __launch_bounds__(PT_NT) void k_dot(LevelView L, int kp, const T* __restrict__ a, const T* __restrict__ b,
                                                double* __restrict__ part)
 {
     __shared__ double red[PT_NT / 64];
     double acc = 0.0;
-    INTERIOR_LOOP
+    ROW_LOOP
     {
         if (!inside) continue;
-        const size_t at = sidx(L, i, j, k);
-        acc += vol_at(L, i, j, k) * (double)a[at] * (double)b[at];
+        const size_t at = ROW_AT;
+        acc += ROW_VOL * (double)a[at] * (double)b[at];
     }
     const double t = block_sum<PT_NT>(acc, red);
     if (threadIdx.x == 0) part[block_linear()] = t;
@@ -460,7 +639,7 @@ __global__ __launch_bounds__(PT_NT) void k_dot(LevelView L, int kp, const T* __r
 template <typename T>
 hipError_t launch_dot(const LevelView& L, const T* a, const T* b, double* partials, hipStream_t s)
 {
-    PT_LAUNCH(k_dot<T>, L, s, a, b, partials);
+    ROW_LAUNCH(k_dot<T>, L, s, a, b, partials);
     return hipGetLastError();
 }
 
@@ -471,10 +650,10 @@ __global__ __launch_bounds__(PT_NT) void k_update_p(LevelView L, int kp, const T
                                                     const double* __restrict__ scal, int i_num, int i_den, int first)
 {
     const T beta = first ? T(0) : (T)(scal[i_num] / scal[i_den]);
-    INTERIOR_LOOP
+    ROW_LOOP
     {
         if (!inside) continue;
-        const size_t at = sidx(L, i, j, k);
+        const size_t at = ROW_AT;
         pnew[at] = first ? z[at] : z[at] + beta * pold[at];
     }
 }
@@ -483,52 +662,45 @@ template <typename T>
 hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pnew, const double* scal, int i_num,
                            int i_den, int first, hipStream_t s)
 {
-    PT_LAUNCH(k_update_p<T>, L, s, z, pold, pnew, scal, i_num, i_den, first);
+    ROW_LAUNCH(k_update_p<T>, L, s, z, pold, pnew, scal, i_num, i_den, first);
     return hipGetLastError();
 }
 
-// x += alpha p, r -= alpha q, alpha = scal[i_num]/scal[i_den]; partial <r,r>_W.
-// A non-finite alpha leaves x and r untouched (the caller then reports the
-// breakdown with x still the last finite iterate).
+// x += alpha p, r -= alpha q (all split), alpha = scal[i_num]/scal[i_den];
+// partial <r,r>_W. A non-finite alpha leaves x and r untouched (the caller
+// then reports the breakdown with x still the last finite iterate).
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_update_xr(LevelView L, int kp, void* __restrict__ xv, int x_nat,
-                                                     T* __restrict__ r, const T* __restrict__ p,
-                                                     const T* __restrict__ q, const double* __restrict__ scal,
-                                                     int i_num, int i_den, double* __restrict__ part)
+__global__ __launch_bounds__(PT_NT) void k_update_xr(LevelView L, int kp, T* __restrict__ x, T* __restrict__ r,
+                                                     const T* __restrict__ p, const T* __restrict__ q,
+                                                     const double* __restrict__ scal, int i_num, int i_den,
+                                                     double* __restrict__ part)
 {
     __shared__ double red[PT_NT / 64];
     const double ad = scal[i_num] / scal[i_den];
     const bool ok = isfinite(ad);
     const T alpha = (T)ad;
     double acc = 0.0;
-    INTERIOR_LOOP
+    ROW_LOOP
     {
         if (!inside) continue;
-        const size_t at = sidx(L, i, j, k);
+        const size_t at = ROW_AT;
         T rv = r[at];
         if (ok) {
-            if (x_nat) {
-                double* x = (double*)xv;
-                const size_t idx = ((size_t)k * L.ny + j) * L.nx + i;
-                x[idx] = x[idx] + ad * (double)p[at];
-            } else {
-                T* x = (T*)xv;
-                x[at] = x[at] + alpha * p[at];
-            }
+            x[at] = x[at] + alpha * p[at];
             rv = rv - alpha * q[at];
             r[at] = rv;
         }
-        acc += vol_at(L, i, j, k) * (double)rv * (double)rv;
+        acc += ROW_VOL * (double)rv * (double)rv;
     }
     const double t = block_sum<PT_NT>(acc, red);
     if (threadIdx.x == 0) part[block_linear()] = ok ? t : __builtin_nan("");
 }
 
 template <typename T>
-hipError_t launch_update_xr(const LevelView& L, void* x, int x_nat, T* r, const T* p, const T* q, const double* scal,
-                            int i_num, int i_den, double* partials, hipStream_t s)
+hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
+                            int i_den, double* partials, hipStream_t s)
 {
-    PT_LAUNCH(k_update_xr<T>, L, s, x, x_nat, r, p, q, scal, i_num, i_den, partials);
+    ROW_LAUNCH(k_update_xr<T>, L, s, x, r, p, q, scal, i_num, i_den, partials);
     return hipGetLastError();
 }
 
@@ -555,10 +727,10 @@ __global__ __launch_bounds__(PT_NT) void k_scale_to32(LevelView L, int kp, const
                                                       int i_norm2)
 {
     const double inv = 1.0 / sqrt(scal[i_norm2]);
-    INTERIOR_LOOP
+    ROW_LOOP
     {
         if (!inside) continue;
-        const size_t at = sidx(L, i, j, k);
+        const size_t at = ROW_AT;
         r32[at] = (float)(r[at] * inv);
     }
 }
@@ -566,7 +738,7 @@ __global__ __launch_bounds__(PT_NT) void k_scale_to32(LevelView L, int kp, const
 hipError_t launch_scale_to32(const LevelView& L, const double* r, float* r32, const double* scal, int i_norm2,
                              hipStream_t s)
 {
-    PT_LAUNCH(k_scale_to32, L, s, r, r32, scal, i_norm2);
+    ROW_LAUNCH(k_scale_to32, L, s, r, r32, scal, i_norm2);
     return hipGetLastError();
 }
 
@@ -683,12 +855,12 @@ hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* 
 // u += P e on the red nodes only: when a black half-sweep follows, it
 // overwrites every black value, so correcting them would be wasted work.
 template <typename T>
-__global__ __launch_bounds__(HS_NT) void k_prolong_red(LevelView F, LevelView C, const T* __restrict__ e,
+__global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C, const T* __restrict__ e,
                                                        T* __restrict__ u, int nbx, int nby, int nb, int per, int kc)
 {
     const int t = xcd_tile(blockIdx.x, per);
-    const int m = (t % nbx) * HS_X + (threadIdx.x & (HS_X - 1));
-    const int j = 1 + ((t / nbx) % nby) * HS_Y + (threadIdx.x >> 6);
+    const int m = (t % nbx) * PT_X + (threadIdx.x & (PT_X - 1));
+    const int j = 1 + ((t / nbx) % nby) * PT_Y + (threadIdx.x >> 6);
     if (t >= nb || j > F.ny - 2 || m > (F.nx - 2) / 2) return;
     const int k0 = 1 + (t / (nbx * nby)) * kc;
     const int k1 = min(k0 + kc, F.nz - 1);
@@ -704,8 +876,14 @@ __global__ __launch_bounds__(HS_NT) void k_prolong_red(LevelView F, LevelView C,
 template <typename T>
 hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s)
 {
-    const HalfShape h = half_shape(F);
-    hipLaunchKernelGGL(k_prolong_red<T>, dim3(h.grid), dim3(HS_NT), 0, s, F, C, e, u, h.nbx, h.nby, h.nb, h.per, h.kc);
+    // one red entry per thread: (m, j) tiles of 64 x 4, planes chunked as in the sweeps
+    const int mcount = (F.nx - 2) / 2 + 1;
+    const int nbx = (mcount + PT_X - 1) / PT_X, nby = (F.ny - 2 + PT_Y - 1) / PT_Y;
+    const long tiles = (long)nbx * nby;
+    const int kc = (int)std::min<long>(16, std::max<long>(1, (long)(F.nz - 2) * tiles / 2048));
+    const int nbz = (F.nz - 2 + kc - 1) / kc;
+    const int nb = nbx * nby * nbz, per = (nb + 7) / 8;
+    hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * per), dim3(PT_NT), 0, s, F, C, e, u, nbx, nby, nb, per, kc);
     return hipGetLastError();
 }
 
@@ -733,44 +911,108 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, const T* e
 // the workgroup's threads over the level's nodes followed by a barrier. On
 // levels of a few thousand nodes a launch costs more than the work, so this
 // replaces about a dozen launches per level by one.
-constexpr int TL_NT = 1024;
+//
+// Threads are assigned to (x, y) columns once per step (ncols columns, ng
+// threads per column taking every ng-th plane), so no node needs an integer
+// division to find its indices; a thread computes TL_BATCH planes before
+// storing any of them, so their loads are in flight together.
+constexpr int TL_NT = 1024, TL_BATCH = 4;
 
-// One half-sweep of colour c by the whole workgroup. A thread takes up to
-// TL_BATCH nodes at a time and computes all their new values before storing
-// any (nodes of one colour never read each other), so the loads of a batch
-// are in flight together instead of forming a chain.
-constexpr int TL_BATCH = 8;
+struct Cols {
+    int ncols, ng, col, grp;
+    bool active;
+};
 
-template <typename T>
-__device__ void t_half(const LevelView& V, T* __restrict__ u, const T* __restrict__ f, int c, int zero_in)
+__device__ __forceinline__ Cols tail_cols(int ncols)
 {
-    const int mcount = (V.nx - 2) / 2 + 1, nyi = V.ny - 2;
-    const int total = mcount * nyi * (V.nz - 2);
-    for (int base = 0; base < total; base += TL_NT * TL_BATCH) {
+    Cols c;
+    c.ncols = ncols;
+    c.ng = max(1, TL_NT / max(ncols, 1));
+    c.active = (int)threadIdx.x < ncols * c.ng;
+    c.col = (int)threadIdx.x % max(ncols, 1);
+    c.grp = (int)threadIdx.x / max(ncols, 1);
+    return c;
+}
+
+// half-sweep of colour c (RESID: residual of colour c into r instead)
+template <typename T, bool RESID>
+__device__ void t_half(const LevelView& V, T* __restrict__ u, const T* __restrict__ f, T* __restrict__ r, int c,
+                       int zero_in)
+{
+    const int mcount = (V.nx - 2) / 2 + 1;
+    const Cols cl = tail_cols(mcount * (V.ny - 2));
+    if (!cl.active) return;
+    const int m = cl.col % mcount, j = 1 + cl.col / mcount;
+    for (int kb = 1 + cl.grp; kb <= V.nz - 2; kb += cl.ng * TL_BATCH) {
         T val[TL_BATCH];
         size_t at[TL_BATCH];
         bool ok[TL_BATCH];
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
-            const int t = base + b * TL_NT + threadIdx.x;
-            const int m = t % mcount, j = 1 + (t / mcount) % nyi, k = 1 + t / (mcount * nyi);
+            const int k = kb + b * cl.ng;
             const int i = ((c + j + k) & 1) + 2 * m;
-            ok[b] = t < total && i >= 1 && i <= V.nx - 2;
+            ok[b] = k <= V.nz - 2 && i >= 1 && i <= V.nx - 2;
             at[b] = 0;
             val[b] = T(0);
             if (!ok[b]) continue;
             at[b] = sidx(V, i, j, k);
-            if (zero_in) {
+            if (RESID) {
+                val[b] = f[at[b]] - apply_split(V, (const T*)u, i, j, k, u[at[b]]);
+            } else if (zero_in) {
                 const T d = (T)(V.ax[0].am[i] + V.ax[0].ap[i] + V.ax[1].am[j] + V.ax[1].ap[j] + V.ax[2].am[k] +
                                 V.ax[2].ap[k]);
                 val[b] = -f[at[b]] / d;
             } else {
-                val[b] = gs_point(V, u, i, j, k, f[at[b]]);
+                val[b] = gs_point(V, (const T*)u, i, j, k, f[at[b]]);
             }
         }
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b)
-            if (ok[b]) u[at[b]] = val[b];
+            if (ok[b]) (RESID ? r : u)[at[b]] = val[b];
+    }
+}
+
+template <typename T>
+__device__ void t_restrict_red(const LevelView& F, const LevelView& C, const T* __restrict__ r, T* __restrict__ fc)
+{
+    const Cols cl = tail_cols((C.nx - 2) * (C.ny - 2));
+    if (!cl.active) return;
+    const int I = 1 + cl.col % (C.nx - 2), J = 1 + cl.col / (C.nx - 2);
+    for (int kb = 1 + cl.grp; kb <= C.nz - 2; kb += cl.ng * TL_BATCH) {
+        T val[TL_BATCH];
+#pragma unroll
+        for (int b = 0; b < TL_BATCH; ++b) {
+            const int K = kb + b * cl.ng;
+            val[b] = K <= C.nz - 2 ? restrict_point<T, true>(F, C, r, I, J, K) : T(0);
+        }
+#pragma unroll
+        for (int b = 0; b < TL_BATCH; ++b) {
+            const int K = kb + b * cl.ng;
+            if (K <= C.nz - 2) fc[sidx(C, I, J, K)] = val[b];
+        }
+    }
+}
+
+template <typename T>
+__device__ void t_prolong(const LevelView& F, const LevelView& C, const T* __restrict__ e, T* __restrict__ u,
+                          bool red_only)
+{
+    const Cols cl = tail_cols((F.nx - 2) * (F.ny - 2));
+    if (!cl.active) return;
+    const int i = 1 + cl.col % (F.nx - 2), j = 1 + cl.col / (F.nx - 2);
+    for (int kb = 1 + cl.grp; kb <= F.nz - 2; kb += cl.ng * TL_BATCH) {
+        T val[TL_BATCH];
+#pragma unroll
+        for (int b = 0; b < TL_BATCH; ++b) {
+            const int k = kb + b * cl.ng;
+            const bool ok = k <= F.nz - 2 && !(red_only && ((i + j + k) & 1));
+            val[b] = ok ? prolong_point(C, e, i, j, k) : T(0);
+        }
+#pragma unroll
+        for (int b = 0; b < TL_BATCH; ++b) {
+            const int k = kb + b * cl.ng;
+            if (k <= F.nz - 2 && !(red_only && ((i + j + k) & 1))) u[sidx(F, i, j, k)] += val[b];
+        }
     }
 }
 
@@ -783,29 +1025,17 @@ __global__ __launch_bounds__(TL_NT) void k_tail(const TailLevel* __restrict__ lv
         const LevelView& V = lv[l].V;
         T* u = TailBuf<T>::u(lv[l]);
         const T* f = TailBuf<T>::f(lv[l]);
+        T* r = TailBuf<T>::r(lv[l]);
         for (int s = 0; s < nu1; ++s) {
-            t_half<T>(V, u, f, 0, s == 0);
+            t_half<T, false>(V, u, f, r, 0, s == 0);
             __syncthreads();
-            t_half<T>(V, u, f, 1, 0);
+            t_half<T, false>(V, u, f, r, 1, 0);
             __syncthreads();
         }
         // residual on red nodes only (the black half-sweep just zeroed it on black)
-        T* r = TailBuf<T>::r(lv[l]);
-        const int ni = (V.nx - 2) * (V.ny - 2) * (V.nz - 2);
-        for (int t = threadIdx.x; t < ni; t += TL_NT) {
-            const int i = 1 + t % (V.nx - 2), j = 1 + (t / (V.nx - 2)) % (V.ny - 2), k = 1 + t / ((V.nx - 2) * (V.ny - 2));
-            if ((i + j + k) & 1) continue;
-            const size_t at = sidx(V, i, j, k);
-            r[at] = f[at] - apply_split(V, u, i, j, k, u[at]);
-        }
+        t_half<T, true>(V, u, f, r, 0, 0);
         __syncthreads();
-        const LevelView& C = lv[l + 1].V;
-        T* fc = TailBuf<T>::f(lv[l + 1]);
-        const int nc = (C.nx - 2) * (C.ny - 2) * (C.nz - 2);
-        for (int t = threadIdx.x; t < nc; t += TL_NT) {
-            const int I = 1 + t % (C.nx - 2), J = 1 + (t / (C.nx - 2)) % (C.ny - 2), K = 1 + t / ((C.nx - 2) * (C.ny - 2));
-            fc[sidx(C, I, J, K)] = restrict_point<T, true>(V, C, (const T*)r, I, J, K);
-        }
+        t_restrict_red<T>(V, lv[l + 1].V, r, TailBuf<T>::f(lv[l + 1]));
         __syncthreads();
     }
     // coarsest: csweeps sweeps (red, black), then csweeps (black, red), from zero
@@ -816,7 +1046,7 @@ __global__ __launch_bounds__(TL_NT) void k_tail(const TailLevel* __restrict__ lv
         for (int pass = 0; pass < 2 * csweeps; ++pass) {
             for (int h = 0; h < 2; ++h) {
                 const int colour = (pass < csweeps) ? h : 1 - h;
-                t_half<T>(V, u, f, colour, pass == 0 && h == 0);
+                t_half<T, false>(V, u, f, (T*)nullptr, colour, pass == 0 && h == 0);
                 __syncthreads();
             }
         }
@@ -824,22 +1054,15 @@ __global__ __launch_bounds__(TL_NT) void k_tail(const TailLevel* __restrict__ lv
     // ascent
     for (int l = nl - 2; l >= 0; --l) {
         const LevelView& V = lv[l].V;
-        const LevelView& C = lv[l + 1].V;
         T* u = TailBuf<T>::u(lv[l]);
         const T* f = TailBuf<T>::f(lv[l]);
-        const T* e = TailBuf<T>::u(lv[l + 1]);
         // correction on red nodes only when a black half-sweep follows
-        const int ni = (V.nx - 2) * (V.ny - 2) * (V.nz - 2);
-        for (int t = threadIdx.x; t < ni; t += TL_NT) {
-            const int i = 1 + t % (V.nx - 2), j = 1 + (t / (V.nx - 2)) % (V.ny - 2), k = 1 + t / ((V.nx - 2) * (V.ny - 2));
-            if (nu2 > 0 && ((i + j + k) & 1)) continue;
-            u[sidx(V, i, j, k)] += prolong_point(C, e, i, j, k);
-        }
+        t_prolong<T>(V, lv[l + 1].V, TailBuf<T>::u(lv[l + 1]), u, nu2 > 0);
         __syncthreads();
         for (int s = 0; s < nu2; ++s) {
-            t_half<T>(V, u, f, 1, 0);
+            t_half<T, false>(V, u, f, (T*)nullptr, 1, 0);
             __syncthreads();
-            t_half<T>(V, u, f, 0, 0);
+            t_half<T, false>(V, u, f, (T*)nullptr, 0, 0);
             __syncthreads();
         }
     }
@@ -882,20 +1105,22 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
 
 // ------------------------------------------------- explicit instantiation
 #define INST(T)                                                                                                  \
-    template hipError_t launch_half<T>(const LevelView&, T*, const T*, int, int, T, double*, hipStream_t);         \
+    template hipError_t launch_half<T>(const LevelView&, T*, const T*, int, int, T, double*, hipStream_t, int*);   \
+    template hipError_t launch_half_keep_faces<T>(const LevelView&, T*, const T*, int, T, hipStream_t);          \
     template hipError_t launch_residual<T>(const LevelView&, const T*, const T*, T*, hipStream_t);                 \
     template hipError_t launch_restrict<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);         \
     template hipError_t launch_prolong_add<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
     template hipError_t launch_prolong_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
     template hipError_t launch_restrict_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);     \
     template hipError_t launch_residual_colour<T>(const LevelView&, const T*, const T*, T*, int, hipStream_t);    \
+    template hipError_t launch_apply_colour<T>(const LevelView&, const T*, T*, int, double*, hipStream_t, int*);   \
     template hipError_t launch_tail<T>(const TailLevel*, int, int, int, int, hipStream_t);                         \
     template hipError_t launch_apply_dot<T>(const LevelView&, const T*, T*, double*, hipStream_t);                 \
     template hipError_t launch_dot<T>(const LevelView&, const T*, const T*, double*, hipStream_t);                 \
     template hipError_t launch_update_p<T>(const LevelView&, const T*, const T*, T*, const double*, int, int, int,  \
                                            hipStream_t);                                                          \
-    template hipError_t launch_update_xr<T>(const LevelView&, void*, int, T*, const T*, const T*, const double*,   \
-                                            int, int, double*, hipStream_t);                                      \
+    template hipError_t launch_update_xr<T>(const LevelView&, T*, T*, const T*, const T*, const double*, int, int, \
+                                            double*, hipStream_t);                                                \
     template hipError_t launch_fill_zero<T>(T*, size_t, hipStream_t);
 INST(double)
 INST(float)

@@ -38,7 +38,8 @@ template <> struct Buf<float> {
 // A half-sweep at level l; finest-level half-sweeps are bracketed by HIP
 // events when profiling is on (the events sit on the kernel's stream).
 template <typename T>
-static hipError_t half(lasto_grid g, int l, T* u, const T* f, int colour, int zero_in, double* dotp)
+static hipError_t half(lasto_grid g, int l, T* u, const T* f, int colour, int zero_in, double* dotp,
+                       int* nparts = nullptr)
 {
     const LevelView& V = g->lev[l].view;
     const bool timed = g->prof_on && l == 0;
@@ -54,7 +55,7 @@ static hipError_t half(lasto_grid g, int l, T* u, const T* f, int colour, int ze
         hipError_t err = hipEventRecord(g->prof_ev[2 * g->prof_used], g->stream);
         if (err != hipSuccess) return err;
     }
-    hipError_t err = launch_half<T>(V, u, f, colour, zero_in, T(1), dotp, g->stream);
+    hipError_t err = launch_half<T>(V, u, f, colour, zero_in, T(1), dotp, g->stream, nparts);
     if (err != hipSuccess) return err;
     if (timed) {
         err = hipEventRecord(g->prof_ev[2 * g->prof_used + 1], g->stream);
@@ -89,7 +90,7 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
         HIPCHK(launch_tail<T>(g->tail_dev + l, g->nlev - l, nu1, nu2, kCoarseSweeps, s));
         if (dotp) {
             HIPCHK(launch_dot<T>(V, f, u, dotp, s));
-            *ndot = interior_blocks(V);
+            *ndot = row_blocks(V);
         }
         return LASTO_OK;
     }
@@ -110,18 +111,19 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     // black value, so only red nodes take the interpolated correction
     if (nu2 > 0) HIPCHK(launch_prolong_red<T>(V, C.view, Buf<T>::u(C), u, s));
     else HIPCHK(launch_prolong_add<T>(V, C.view, Buf<T>::u(C), u, s));
-    const int nb = half_blocks(V);
+    int nb1 = 0, nb2 = 0;
     for (int k = 0; k < nu2; ++k) {
         const bool last = (k == nu2 - 1) && dotp;
-        HIPCHK(half<T>(g, l, u, f, 1, 0, last ? dotp : nullptr));
-        HIPCHK(half<T>(g, l, u, f, 0, 0, last ? dotp + nb : nullptr));
+        HIPCHK(half<T>(g, l, u, f, 1, 0, last ? dotp : nullptr, &nb1));
+        // the second half-sweep's partials follow the first's
+        HIPCHK(half<T>(g, l, u, f, 0, 0, last ? dotp + nb1 : nullptr, &nb2));
     }
     if (dotp) {
         if (nu2 > 0) {
-            *ndot = 2 * nb;
+            *ndot = nb1 + nb2;
         } else {
             HIPCHK(launch_dot<T>(V, f, u, dotp, s));
-            *ndot = interior_blocks(V);
+            *ndot = row_blocks(V);
         }
     }
     return LASTO_OK;
@@ -130,6 +132,18 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
 static lasto_status reduce_to(lasto_grid g, int count, int slot)
 {
     HIPCHK(launch_reduce(g->partials, 1, count, g->scalars + slot, g->stream));
+    return LASTO_OK;
+}
+
+// q = A p over both colours; partials of <p, q>_W (count returned)
+template <typename T>
+static lasto_status apply_dot(lasto_grid g, const T* p, T* q, int* count)
+{
+    const LevelView& V = g->lev[0].view;
+    int nb0 = 0, nb1 = 0;
+    HIPCHK(launch_apply_colour<T>(V, p, q, 0, g->partials, g->stream, &nb0));
+    HIPCHK(launch_apply_colour<T>(V, p, q, 1, g->partials + nb0, g->stream, &nb1));
+    *count = nb0 + nb1;
     return LASTO_OK;
 }
 
@@ -146,7 +160,7 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
 {
     const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
-    const int nb_i = interior_blocks(V);
+    const int nb_r = row_blocks(V);
     HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
     float* rr = g->r32;   // working residual, updated in place
     for (int it = 0; it < iters; ++it) {
@@ -159,10 +173,11 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
         float* pn = g->p32[it & 1];
         float* po = g->p32[(it + 1) & 1];
         HIPCHK(launch_update_p<float>(V, g->z32, po, pn, g->scalars, srz, srz_old, it == 0, s));
-        HIPCHK(launch_apply_dot<float>(V, pn, g->q32, g->partials, s));
-        if (lasto_status e = reduce_to(g, nb_i, S_PQ32); e != LASTO_OK) return e;
-        HIPCHK(launch_update_xr<float>(V, g->e32, 0, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s));
-        if (lasto_status e = reduce_to(g, nb_i, S_RR32); e != LASTO_OK) return e;
+        int npq = 0;
+        if (lasto_status e = apply_dot<float>(g, pn, g->q32, &npq); e != LASTO_OK) return e;
+        if (lasto_status e = reduce_to(g, npq, S_PQ32); e != LASTO_OK) return e;
+        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s));
+        if (lasto_status e = reduce_to(g, nb_r, S_RR32); e != LASTO_OK) return e;
     }
     return LASTO_OK;
 }
@@ -250,6 +265,10 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     double best = rel;
     int grow = 0;
     int it = 0, cg_it = 0;
+    // CG accumulates its correction in the split array x (zero now) and adds
+    // it to v when it stops or restarts
+    const bool cg = (o.precision == 0 && o.method == 0);
+    if (cg) HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
     while (rel > o.rtol && it < o.max_iters) {
         if (o.debug_nan_iter == it)
             HIPCHK(launch_inject_nan(g->r, sidx(V, V.nx / 2, V.ny / 2, V.nz / 2), s));
@@ -280,10 +299,11 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             double* pn = g->p[cg_it & 1];
             double* po = g->p[(cg_it + 1) & 1];
             HIPCHK(launch_update_p<double>(V, g->z, po, pn, g->scalars, srz, srz_old, cg_it == 0, s));
-            HIPCHK(launch_apply_dot<double>(V, pn, g->q, g->partials, s));
-            if (lasto_status e = reduce_to(g, nb_i, S_PQ); e != LASTO_OK) return e;
-            HIPCHK(launch_update_xr<double>(V, v, 1, g->r, pn, g->q, g->scalars, srz, S_PQ, g->partials, s));
-            if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
+            int npq = 0;
+            if (lasto_status e = apply_dot<double>(g, pn, g->q, &npq); e != LASTO_OK) return e;
+            if (lasto_status e = reduce_to(g, npq, S_PQ); e != LASTO_OK) return e;
+            HIPCHK(launch_update_xr<double>(V, g->x, g->r, pn, g->q, g->scalars, srz, S_PQ, g->partials, s));
+            if (lasto_status e = reduce_to(g, row_blocks(V), S_RR); e != LASTO_OK) return e;
             cg_it++;
         }
         if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;
@@ -301,9 +321,12 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             result = LASTO_ERR_DIVERGED;
             break;
         }
-        if (rel <= o.rtol && o.precision == 0 && o.method == 0) {
-            // the CG residual is a recurrence: confirm with the true residual,
-            // and restart CG from it if the two have drifted apart
+        if (rel <= o.rtol && cg) {
+            // the CG residual is a recurrence: fold the correction into v,
+            // confirm with the true residual, and restart CG from it if the
+            // two have drifted apart
+            HIPCHK(launch_add_nat(V, v, g->x, s));
+            HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
             HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;
@@ -311,7 +334,10 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             cg_it = 0;
         }
     }
-    // true residual of the returned iterate
+    // fold any CG correction not yet in v (the loop stopped on max_iters or
+    // a breakdown; x holds the last finite correction), then the true
+    // residual of the returned iterate
+    if (cg) HIPCHK(launch_add_nat(V, v, g->x, s));
     HIPCHK(launch_residual_nat(V, v, rho, fourpi, nullptr, g->partials, 0, s));
     if (lasto_status e = reduce_to(g, nb_i, S_TMP); e != LASTO_OK) return e;
     if (lasto_status e = read_scalars(g, S_TMP, 1); e != LASTO_OK) return e;
@@ -358,8 +384,8 @@ extern "C" lasto_status lasto_rb_sweep(lasto_grid g, const double* u_in, const d
     // the sweep runs in the solver's split layout on grid scratch
     HIPCHK(launch_nat_to_split(V, u_in, g->z, s));
     HIPCHK(launch_nat_to_split(V, rho, g->q, s));
-    HIPCHK(launch_half<double>(V, g->z, g->q, first_colour, 0, 4.0 * kPi, nullptr, s));
-    HIPCHK(launch_half<double>(V, g->z, g->q, 1 - first_colour, 0, 4.0 * kPi, nullptr, s));
+    HIPCHK(launch_half_keep_faces<double>(V, g->z, g->q, first_colour, 4.0 * kPi, s));
+    HIPCHK(launch_half_keep_faces<double>(V, g->z, g->q, 1 - first_colour, 4.0 * kPi, s));
     HIPCHK(launch_split_to_nat(V, g->z, u_out, s));
     HIPCHK(hipStreamSynchronize(g->stream));
     return LASTO_OK;
