@@ -10,8 +10,8 @@ Prints ONE JSON line. `value` is the time-to-tolerance of the Poisson solve
 GPU is reported beside it. `roofline` is the finest-level red-black sweep
 (the dominant kernel), timed with HIP events on its own stream inside the
 timed steps. `cpu_baseline` is the C oracle timed on the host cores on a
-bounded sample (a few V-cycles of the same 257^3 solve), extrapolated with
-its measured contraction to the same tolerance.
+bounded sample: whole FP64 solves of the same 257^3 problem to the same
+tolerance, repeated for about ten seconds.
 """
 import argparse
 import json
@@ -27,6 +27,26 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel (finest-level FP32 half-sweep,
+# launch mix of one mixed solve), from two rocprofv3 --pmc runs of
+# `bench.py --steps 1 --warmup 0 --no-cpu` (FETCH_SIZE, then WRITE_SIZE), each
+# counter scaled by what it reads for a 512 MiB device copy
+# (`bench.py --copy-calibration 512`: FETCH_SIZE x2.000, WRITE_SIZE x1.000).
+# Summary: profiles/k_half2_fp32_finest_257_traffic.md. The figure belongs to
+# the kernel source it was measured on and to the same solve form; `traffic`
+# is reported as null when either differs.
+COUNTER_TRAFFIC = {"kernel_sha256_16": "819d3f239d9dcf0a", "form": (1, 0, 6, 2, 2), "bytes_per_launch": 107.70e6}
+
+
+def half_sweep_source_digest():
+    """First 16 hex digits of the SHA-256 of the half-sweep kernel's source."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_0806_1723_amd", "csrc", "mg_kernels.hip")
+    src = open(path).read()
+    a = src.index("template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES, bool TOP>\n__global__")
+    b = src.index("// Resident workgroups of one half-sweep variant")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -40,12 +60,19 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--n", type=int, default=0, help="override the mesh size of the config")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-cycles", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU time over which the oracle baseline repeats whole solves")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported (the Poisson solve would "
               "shard by z-slabs with halo exchange, see the design notes)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch
@@ -66,10 +93,13 @@ def main():
     centers = np.array([a.center for a in w.atoms])
     radii = np.array([a.radius for a in w.atoms])
 
+    form = dict(precision=mixed, method=0, inner_iters=6, nu1=2, nu2=2)
+
     def step(profile, precision):
         g.pseudo_density(w.atoms, rho_out=rho)
         v.zero_()
-        info = g.poisson_solve(rho, v, rtol=w.rtol, precision=precision, profile=profile)
+        opts = dict(form, precision=precision)
+        info = g.poisson_solve(rho, v, rtol=w.rtol, profile=profile, **opts)
         sph = g.sphere_interp(v, centers, radii)
         return info, sph
 
@@ -113,6 +143,11 @@ def main():
     # colour, f and writes its own colour (24 / 12 B per full sweep)
     interior = (n - 2) ** 3
     sm_bpp = (sm_bytes / launches / interior) if launches else 0.0
+    traffic = None
+    form_key = (form["precision"], form["method"], form["inner_iters"], form["nu1"], form["nu2"])
+    if (n == 257 and args.config == 3 and form_key == COUNTER_TRAFFIC["form"]
+            and half_sweep_source_digest() == COUNTER_TRAFFIC["kernel_sha256_16"]):
+        traffic = COUNTER_TRAFFIC["bytes_per_launch"]
     out = {
         "metric": "time-to-1e-10-residual per Poisson solve at 257^3; smoother HBM GB/s vs peak",
         "value": round(solve_ms, 4),
@@ -136,41 +171,62 @@ def main():
         "fp64_smoother_gbs": round(fp64_gbs, 1),
         "fp64_smoother_frac": round(fp64_gbs / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_half<%s> (red-black half-sweep, finest level)" % ("float" if mixed else "double"),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": round(sm_bytes / launches) if launches else 0,
+                     "kernel": "k_half2<%s, GS, *, *, true, true> (red-black half-sweep, finest level)"
+                               % ("float" if mixed else "double"),
                      "bytes_per_point_per_launch": round(sm_bpp, 3), "avg_launch_us": round(avg_launch_us, 2),
                      "launches": launches},
     }
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, xs, rho.cpu().numpy(), args.cpu_cycles)
+        out["cpu_baseline"] = cpu_baseline(w, xs, rho.cpu().numpy(), args.cpu_seconds)
     g.close()
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, xs, rho, cycles):
-    """The oracle (plain C FP64 V(2,2) cycles, OpenMP) on the same solve: a
-    few cycles timed, then scaled to the cycles its measured contraction
-    needs for the same tolerance."""
+def cpu_baseline(w, xs, rho, min_seconds):
+    """The oracle (plain C FP64 V(2,2) cycles, OpenMP) on the same 257^3
+    solve: whole solves to the same tolerance from the same faces, repeated
+    until about `min_seconds` of CPU time have passed; the median solve."""
     import numpy as np
     import oracle
     oracle.lib()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     center = tuple(0.5 * (x[0] + x[-1]) for x in xs)
     Q = oracle.moments(xs, rho, 4, center)
-    v = np.zeros_like(rho)
-    oracle.boundary_values(xs, Q, v, 1, 4, center)
-    t0 = time.perf_counter()
-    cyc, rel, hist = oracle.solve(xs, rho, v, rtol=w.rtol, max_cycles=cycles)
-    dt = time.perf_counter() - t0
-    rate = (hist[-1] / hist[0]) ** (1.0 / max(len(hist) - 1, 1)) if len(hist) > 1 else hist[0]
-    need = cyc if rel <= w.rtol else cyc + math.ceil(math.log(w.rtol / rel) / math.log(rate))
-    est_ms = dt * 1e3 / cyc * need
-    log("bench: oracle %d cycles in %.2f s (%d threads), contraction %.3f, est. %d cycles to %.0e"
-        % (cyc, dt, cores, rate, need, w.rtol))
-    return {"value": round(est_ms, 1), "unit": "ms", "cores": cores, "kind": "oracle",
-            "sample": "%d V(2,2) cycles of the %d^3 solve (%.2f s), extrapolated to %d cycles by the "
-                      "measured contraction %.3f" % (cyc, len(xs[0]), dt, need, rate)}
+    v0 = np.zeros_like(rho)
+    oracle.boundary_values(xs, Q, v0, 1, 4, center)
+    times, cyc, rel = [], 0, 0.0
+    t_start = time.perf_counter()
+    while not times or (time.perf_counter() - t_start < min_seconds and len(times) < 50):
+        v = v0.copy()
+        t0 = time.perf_counter()
+        cyc, rel, _ = oracle.solve(xs, rho, v, rtol=w.rtol, max_cycles=60)
+        times.append(time.perf_counter() - t0)
+    total = time.perf_counter() - t_start
+    ms = statistics.median(times) * 1e3
+    log("bench: oracle %d solves in %.1f s (%d threads), %d cycles each, rel %.2e, median %.1f ms"
+        % (len(times), total, cores, cyc, rel, ms))
+    return {"value": round(ms, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+            "sample": "%d whole FP64 solves of the %d^3 problem to %.0e (%d V(2,2) cycles each, %.1f s in "
+                      "all); median per solve" % (len(times), len(xs[0]), w.rtol, cyc, total)}
+
+
+def copy_calibration(mib):
+    """A plain device copy of known size (torch's copy kernel), for scaling
+    hardware byte counters: FETCH_SIZE and WRITE_SIZE of one dispatch should
+    each read `mib` MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "bytes_read": n * 4, "bytes_written": n * 4,
+                      "dispatches": 5}), flush=True)
 
 
 if __name__ == "__main__":

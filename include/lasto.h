@@ -141,9 +141,10 @@ typedef struct {
     double rtol;        /* stop when ||b - A v||_W <= rtol ||b - A v_bc||_W (default 1e-10) */
     int max_iters;      /* outer iterations (PCG steps or V-cycles), default 100 */
     int nu1, nu2;       /* pre/post red-black sweeps per level (default 2, 2) */
-    int method;         /* 0 MG-preconditioned CG (default), 1 plain V-cycle iteration */
+    int method;         /* 0 MG-preconditioned CG (default), 1 plain V-cycle iteration; with
+                           precision 1 it selects the inner FP32 solver the same way */
     int precision;      /* 0 FP64 throughout (default); 1 FP32 V-cycles inside FP64 refinement */
-    int inner_iters;    /* precision 1: FP32 PCG steps per FP64 refinement (default 6) */
+    int inner_iters;    /* precision 1: FP32 PCG steps or V-cycles per FP64 refinement (default 6) */
     int guess;          /* 0 use the interior of v as given (default), 1 zero interior */
     int bc;             /* 0 zero faces (eq. (3.3)), 1 multipole faces (default), 2 faces of v as given */
     int lmax_bc;        /* multipole order of the face values, 0..4 (default 4) */

@@ -197,22 +197,21 @@ size_t split_elems(const LevelView& L);
 // zero_in: the other colour is read as zero. dotp (optional): per-block
 // partials of sum vol * f * u_new over the updated nodes.
 // *nparts (optional): partials written (one per workgroup; at most half_blocks(L)).
+// top: finest-level launch (a kernel of its own name, same code).
+// ev0, ev1 (optional): events stamped with the dispatch's own start and end.
 template <typename T>
 hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
-                       hipStream_t s, int* nparts = nullptr);
+                       hipStream_t s, int* nparts = nullptr, int top = 0, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 // the same on an array whose faces carry Dirichlet data (written back unchanged)
 template <typename T>
 hipError_t launch_half_keep_faces(const LevelView& L, T* u, const T* f, int colour, T bscale, hipStream_t s);
 template <typename T>
-hipError_t launch_residual(const LevelView& L, const T* u, const T* f, T* r, hipStream_t s);
-template <typename T>
-hipError_t launch_restrict(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s);
-template <typename T>
 hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s);
-// The same transfers exploiting the red-black ordering of the cycle: after
-// a pre-smoothing that ends with a black half-sweep the residual vanishes on
-// black nodes (residual_colour computes one colour; restrict_red skips black
-// fine nodes), and before a post-smoothing that starts with a black
+// Transfers exploiting the red-black ordering of the cycle: after a
+// pre-smoothing that ends with a black half-sweep the residual vanishes on
+// black nodes (residual_colour computes one colour; restrict_red reads red
+// fine nodes only), and before a post-smoothing that starts with a black
 // half-sweep only red nodes need the coarse correction (prolong_red).
 template <typename T>
 hipError_t launch_residual_colour(const LevelView& L, const T* u, const T* f, T* r, int colour, hipStream_t s);
@@ -224,14 +223,13 @@ template <typename T>
 hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s);
-// V(nu1, nu2) from zero on levels lv[0..nl-1] in one workgroup; the
-// coarsest runs csweeps (red, black) sweeps then csweeps (black, red).
+// V(nu1, nu2) on levels lv[0..nl-1] in one workgroup, from zero (lv[0]
+// from its current u unless top_zero); the coarsest runs csweeps (red,
+// black) sweeps then csweeps (black, red).
 template <typename T>
-hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweeps, hipStream_t s);
+hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweeps, int top_zero, hipStream_t s);
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s);
-template <typename T>
-hipError_t launch_apply_dot(const LevelView& L, const T* p, T* q, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_dot(const LevelView& L, const T* a, const T* b, double* partials, hipStream_t s);
 template <typename T>
@@ -270,6 +268,13 @@ struct AtomDev {
     int kind;
     int lmax;
     double clm[24];
+    // filled on the device by k_atom_prep:
+    double pre;       // kind 0: q s (pi w^2)^(-3/2)
+    double iw2;       // kind 0: 1 / w^2
+    double cut2;      // squared radius of the l = 0 term (kind 0: (7 w)^2, kind 1: R^2)
+    double lcut2;     // squared radius of the l >= 1 terms (alpha r^2 < 42.25), -1 without them
+    double cull2;     // squared radius beyond which the atom adds nothing (and is not "inside")
+    double cn[24];    // clm times the r^l y_lm normalisation
 };
 hipError_t launch_atom_prep(lasto_grid g, AtomDev* atoms, int n_atoms, int renormalize);
 hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const double* rho_inter, double* rho);

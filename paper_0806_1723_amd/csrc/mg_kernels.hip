@@ -11,6 +11,8 @@
 // [nz][ny][nx] arrays appear only at the fine level (the caller's rho and v).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace lasto {
@@ -74,62 +76,102 @@ __device__ __forceinline__ T apply_split(const LevelView& L, const T* __restrict
     return a;
 }
 
-// restricted value at coarse (I,J,K): the up-to-3x3x3 fine nodes around
-// (rf[I], rf[J], rf[K]) weighted by rw_x rw_y rw_z (M_c^-1 P^T M_f).
-// RED_ONLY: the fine residual is known to vanish on black nodes (as it does
-// right after a black half-sweep), so they are not read.
-template <typename T, bool RED_ONLY>
-__device__ __forceinline__ T restrict_point(const LevelView& F, const LevelView& C, const T* __restrict__ r, int I,
-                                            int J, int K)
+// Restriction R = M_c^-1 P^T M_f gathers, per axis, the fine nodes rf-1..rf+1
+// of coarse node I with weights rw. The solver restricts only residuals that
+// vanish on black nodes (right after a black half-sweep), so only red fine
+// nodes are read. In a fine row of parity q = (jj + kk) & 1 the red nodes are
+// those with i = q (mod 2), at entry i >> 1 of the red colour row; the red
+// taps of coarse I in that row are therefore entries m0 = (fi - 1) >> 1 and
+// m0 + 1, weighted (wx1 on fi alone) when fi = q (mod 2), else (wx0, wx2 on
+// fi - 1, fi + 1). RTaps holds both weight pairs of one coarse I.
+template <typename T> struct RTaps {
+    T s0, s1;   // fi red
+    T d0, d1;   // fi black
+    int m0, e;  // first entry, parity of fi
+};
+
+template <typename T>
+__device__ __forceinline__ RTaps<T> restrict_taps(const LevelView& C, int I)
 {
-    const int fi = C.ax[0].rf[I], fj = C.ax[1].rf[J], fk = C.ax[2].rf[K];
-    const double* wx = C.ax[0].rw + 3 * I;
+    RTaps<T> x;
+    const int fi = C.ax[0].rf[I];
+    const double* w = C.ax[0].rw + 3 * I;
+    x.e = fi & 1;
+    x.m0 = (fi - 1) >> 1;
+    x.s0 = x.e ? (T)w[1] : T(0);
+    x.s1 = x.e ? T(0) : (T)w[1];
+    x.d0 = (T)w[0];
+    x.d1 = (T)w[2];
+    return x;
+}
+
+// restricted red residual at coarse (I, J, K), I given by its taps. The 18
+// loads are unconditional (zero weights included, every index inside the fine
+// array) so that they are all in flight at once.
+template <typename T>
+__device__ __forceinline__ T restrict_red_at(const LevelView& F, const LevelView& C, const T* __restrict__ r,
+                                             const RTaps<T>& x, int J, int K)
+{
+    const int fj = C.ax[1].rf[J], fk = C.ax[2].rf[K];
     const double* wy = C.ax[1].rw + 3 * J;
     const double* wz = C.ax[2].rw + 3 * K;
     T acc = T(0);
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const T z = (T)wz[c];
-        if (z == T(0)) continue;
+        T plane = T(0);
+#pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const T y = (T)wy[b];
-            if (y == T(0)) continue;
             const int jj = fj - 1 + b, kk = fk - 1 + c;
-            T sx = T(0);
-            for (int a = 0; a < 3; ++a) {
-                const T x = (T)wx[a];
-                if (RED_ONLY && ((fi - 1 + a + jj + kk) & 1)) continue;
-                if (x != T(0)) sx += x * r[sidx(F, fi - 1 + a, jj, kk)];
-            }
-            acc += z * y * sx;
+            const bool same = ((jj + kk) & 1) == x.e;
+            const T* row = r + ((size_t)kk * F.ny + jj) * F.W + x.m0;   // red colour: the first half of r
+            plane += (T)wy[b] * ((same ? x.s0 : x.d0) * row[0] + (same ? x.s1 : x.d1) * row[1]);
         }
+        acc += (T)wz[c] * plane;
     }
     return acc;
 }
 
-// interpolated coarse correction at fine (i,j,k): the 2x2x2 coarse values
-// around it with linear weights in physical coordinates (weight 1 at kept
-// nodes); coarse neighbours with zero weight are not read
+// Prolongation: fine node i lies in coarse cell (pc_i, pc_i + 1) with linear
+// weights in physical coordinates (1 and 0 at a kept node). For an interior
+// fine node pc_i + 1 is still a coarse node (possibly on a face), so all eight
+// coarse values can be loaded unconditionally.
+template <typename T> struct PTaps {
+    int I;
+    T w0, w1;
+};
+
 template <typename T>
-__device__ __forceinline__ T prolong_point(const LevelView& C, const T* __restrict__ e, int i, int j, int k)
+__device__ __forceinline__ PTaps<T> prolong_taps(const Axis& a, int i)
 {
-    const int I = C.ax[0].pc[i], J = C.ax[1].pc[j], K = C.ax[2].pc[k];
-    const T wx[2] = {(T)C.ax[0].pw[2 * i], (T)C.ax[0].pw[2 * i + 1]};
-    const T wy[2] = {(T)C.ax[1].pw[2 * j], (T)C.ax[1].pw[2 * j + 1]};
-    const T wz[2] = {(T)C.ax[2].pw[2 * k], (T)C.ax[2].pw[2 * k + 1]};
-    T w = T(0);
+    PTaps<T> t;
+    t.I = a.pc[i];
+    t.w0 = (T)a.pw[2 * i];
+    t.w1 = (T)a.pw[2 * i + 1];
+    return t;
+}
+
+// interpolated coarse correction at fine (i, j, k), i given by its taps
+template <typename T>
+__device__ __forceinline__ T prolong_at(const LevelView& C, const T* __restrict__ e, const PTaps<T>& x, int j, int k)
+{
+    const PTaps<T> y = prolong_taps<T>(C.ax[1], j), z = prolong_taps<T>(C.ax[2], k);
+    const int ma = x.I >> 1, mb = (x.I + 1) >> 1;
+    T acc = T(0);
+#pragma unroll
     for (int c = 0; c < 2; ++c) {
-        if (wz[c] == T(0)) continue;
-        T v = T(0);
+        T s = T(0);
+#pragma unroll
         for (int b = 0; b < 2; ++b) {
-            if (wy[b] == T(0)) continue;
-            T a = T(0);
-            for (int q = 0; q < 2; ++q)
-                if (wx[q] != T(0)) a += wx[q] * e[sidx(C, I + q, J + b, K + c)];
-            v += wy[b] * a;
+            const int Jb = y.I + b, Kc = z.I + c;
+            const size_t row = ((size_t)Kc * C.ny + Jb) * C.W;
+            const int ca = (x.I + Jb + Kc) & 1;   // colour of coarse node I; I + 1 has the other
+            const T va = e[(size_t)ca * C.cs + row + ma];
+            const T vb = e[(size_t)(ca ^ 1) * C.cs + row + mb];
+            s += (b ? y.w1 : y.w0) * (x.w0 * va + x.w1 * vb);
         }
-        w += wz[c] * v;
+        acc += (c ? z.w1 : z.w0) * s;
     }
-    return w;
+    return acc;
 }
 
 // --------------------------------------------------------- half-sweep
@@ -210,7 +252,9 @@ template <typename T> struct HalfOps {
     T xe;                                    // the x neighbour outside the z queue
 };
 
-template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES>
+// TOP marks finest-level launches; it changes no code, only the kernel's name,
+// so that a kernel trace separates the finest level from the coarse ones.
+template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES, bool TOP>
 __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restrict__ uo, const T* __restrict__ fc,
                                                  const T* __restrict__ ucen, T* __restrict__ out, int c, T bscale,
                                                  double* __restrict__ dotp, int nbx, int nby, int nb, int per, int kc)
@@ -352,14 +396,14 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
 // Resident workgroups of one half-sweep variant on the whole device (a
 // multiple of 8, at least 8); the persistent launch never exceeds it, so no
 // workgroup waits for a second round.
-template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES>
+template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES, bool TOP>
 static int half_cap()
 {
     static const int cap = [] {
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess) return 8;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 8;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_half2<T, MODE, ZERO_IN, DOT, ZERO_FACES>, H2_NT,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_half2<T, MODE, ZERO_IN, DOT, ZERO_FACES, TOP>, H2_NT,
                                                          0) != hipSuccess)
             return 8;
         return std::max(8, per_cu * cus / 8 * 8);
@@ -367,32 +411,50 @@ static int half_cap()
     return cap;
 }
 
-template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES>
+// ev0/ev1 (optional): events that take the dispatch's own start and end
+// timestamps (hipExtLaunchKernelGGL), i.e. the kernel's execution time alone.
+template <typename T, int MODE, bool ZERO_IN, bool DOT, bool ZERO_FACES, bool TOP = false>
 static hipError_t launch_half2(const LevelView& L, const T* u, const T* f, T* out, int colour, T bscale,
-                               double* dotp, hipStream_t s, int* nparts)
+                               double* dotp, hipStream_t s, int* nparts, hipEvent_t ev0 = nullptr,
+                               hipEvent_t ev1 = nullptr)
 {
     const HalfShape h = half_shape(L);
-    const int G = std::min(h.grid, half_cap<T, MODE, ZERO_IN, DOT, ZERO_FACES>());
+    const int G = std::min(h.grid, half_cap<T, MODE, ZERO_IN, DOT, ZERO_FACES, TOP>());
     const size_t own = (size_t)colour * L.cs, other = (size_t)(1 - colour) * L.cs;
-    hipLaunchKernelGGL((k_half2<T, MODE, ZERO_IN, DOT, ZERO_FACES>), dim3(G), dim3(H2_NT), 0, s, L, u + other,
-                       f ? f + own : (const T*)nullptr, u + own, out + own, colour, bscale, dotp, h.nbx, h.nby, h.nb,
-                       h.per, h.kc);
+    const T* fo = f ? f + own : (const T*)nullptr;
+    if (ev0 && ev1)
+        hipExtLaunchKernelGGL((k_half2<T, MODE, ZERO_IN, DOT, ZERO_FACES, TOP>), dim3(G), dim3(H2_NT), 0, s, ev0, ev1,
+                              0, L, u + other, fo, u + own, out + own, colour, bscale, dotp, h.nbx, h.nby, h.nb, h.per,
+                              h.kc);
+    else
+        hipLaunchKernelGGL((k_half2<T, MODE, ZERO_IN, DOT, ZERO_FACES, TOP>), dim3(G), dim3(H2_NT), 0, s, L,
+                           u + other, fo, u + own, out + own, colour, bscale, dotp, h.nbx, h.nby, h.nb, h.per, h.kc);
     if (nparts) *nparts = G;
     return hipGetLastError();
 }
 
 // In the multigrid arrays (corrections, right-hand sides, residuals) faces
 // and padding are zero, so the sweeps store pairs unconditionally.
-template <typename T>
-hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
-                       hipStream_t s, int* nparts)
+template <typename T, bool TOP>
+static hipError_t launch_half_t(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale,
+                                double* dotp, hipStream_t s, int* nparts, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (zero_in) {
-        if (dotp) return launch_half2<T, HM_GS, true, true, true>(L, u, f, u, colour, bscale, dotp, s, nparts);
-        return launch_half2<T, HM_GS, true, false, true>(L, u, f, u, colour, bscale, nullptr, s, nparts);
+        if (dotp)
+            return launch_half2<T, HM_GS, true, true, true, TOP>(L, u, f, u, colour, bscale, dotp, s, nparts, ev0, ev1);
+        return launch_half2<T, HM_GS, true, false, true, TOP>(L, u, f, u, colour, bscale, nullptr, s, nparts, ev0, ev1);
     }
-    if (dotp) return launch_half2<T, HM_GS, false, true, true>(L, u, f, u, colour, bscale, dotp, s, nparts);
-    return launch_half2<T, HM_GS, false, false, true>(L, u, f, u, colour, bscale, nullptr, s, nparts);
+    if (dotp)
+        return launch_half2<T, HM_GS, false, true, true, TOP>(L, u, f, u, colour, bscale, dotp, s, nparts, ev0, ev1);
+    return launch_half2<T, HM_GS, false, false, true, TOP>(L, u, f, u, colour, bscale, nullptr, s, nparts, ev0, ev1);
+}
+
+template <typename T>
+hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
+                       hipStream_t s, int* nparts, int top, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (top) return launch_half_t<T, true>(L, u, f, colour, zero_in, bscale, dotp, s, nparts, ev0, ev1);
+    return launch_half_t<T, false>(L, u, f, colour, zero_in, bscale, dotp, s, nparts, ev0, ev1);
 }
 
 // the same half-sweep on an array whose faces hold Dirichlet data (kept)
@@ -459,26 +521,6 @@ int interior_blocks(const LevelView& L)
         const PtShape ps_ = pt_shape(L);                                                     \
         hipLaunchKernelGGL(kernel, ps_.grid, dim3(PT_NT), 0, s, L, ps_.kp, __VA_ARGS__);      \
     } while (0)
-
-// r = f - A u (split arrays)
-template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_residual(LevelView L, int kp, const T* __restrict__ u,
-                                                    const T* __restrict__ f, T* __restrict__ r)
-{
-    INTERIOR_LOOP
-    {
-        if (!inside) continue;
-        const size_t at = sidx(L, i, j, k);
-        r[at] = f[at] - apply_split(L, u, i, j, k, u[at]);
-    }
-}
-
-template <typename T>
-hipError_t launch_residual(const LevelView& L, const T* u, const T* f, T* r, hipStream_t s)
-{
-    PT_LAUNCH(k_residual<T>, L, s, u, f, r);
-    return hipGetLastError();
-}
 
 // Fine level, natural v and rho: r = bscale rho - A v (r in the split layout
 // when given) and partials of ||r||_W^2. interior_zero: the interior of v is
@@ -547,33 +589,6 @@ __global__ __launch_bounds__(PT_NT) void k_apply_nat(LevelView L, int kp, const 
 hipError_t launch_apply_nat(const LevelView& L, const double* u, double* Au, hipStream_t s)
 {
     PT_LAUNCH(k_apply_nat, L, s, u, Au);
-    return hipGetLastError();
-}
-
-// q = A p and partial <p, q>_W (split arrays)
-template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_apply_dot(LevelView L, int kp, const T* __restrict__ p,
-                                                     T* __restrict__ q, double* __restrict__ part)
-{
-    __shared__ double red[PT_NT / 64];
-    double acc = 0.0;
-    INTERIOR_LOOP
-    {
-        if (!inside) continue;
-        const size_t at = sidx(L, i, j, k);
-        const T c = p[at];
-        const T a = apply_split(L, p, i, j, k, c);
-        q[at] = a;
-        acc += vol_at(L, i, j, k) * (double)c * (double)a;
-    }
-    const double t = block_sum<PT_NT>(acc, red);
-    if (threadIdx.x == 0) part[block_linear()] = t;
-}
-
-template <typename T>
-hipError_t launch_apply_dot(const LevelView& L, const T* p, T* q, double* partials, hipStream_t s)
-{
-    PT_LAUNCH(k_apply_dot<T>, L, s, p, q, partials);
     return hipGetLastError();
 }
 
@@ -826,67 +841,168 @@ hipError_t launch_inject_nan(double* r, size_t idx, hipStream_t s)
 }
 
 // ---------------------------------------------------------- transfers
-template <typename T, bool RED_ONLY>
-__global__ __launch_bounds__(PT_NT) void k_restrict(LevelView C, int kp, LevelView F, const T* __restrict__ r,
-                                                    T* __restrict__ rc)
+// Both transfers tile their level like the half-sweeps: a workgroup covers
+// 64 x 4 (x, y) columns, and tiles go to the XCDs in contiguous runs
+// (xcd_tile), so fine rows shared by neighbouring tiles are mostly read from
+// one L2. A thread takes KU consecutive planes and issues every gather of all
+// of them before it sums any (their table lookups first, then the values),
+// so it waits on memory twice rather than twice per plane.
+template <typename T> struct TransferUnroll { static constexpr int KU = 4; };
+template <> struct TransferUnroll<double> { static constexpr int KU = 2; };
+
+struct TileShape {
+    int nbx, nby, nb, per;
+};
+
+static TileShape tile_shape(int cols_x, int rows_y, int planes, int ku)
 {
-    const LevelView& L = C;
-    INTERIOR_LOOP
-    {
-        if (!inside) continue;
-        rc[sidx(C, i, j, k)] = restrict_point<T, RED_ONLY>(F, C, r, i, j, k);
-    }
+    TileShape t;
+    t.nbx = (cols_x + PT_X - 1) / PT_X;
+    t.nby = (rows_y + PT_Y - 1) / PT_Y;
+    t.nb = t.nbx * t.nby * ((planes + ku - 1) / ku);
+    t.per = (t.nb + 7) / 8;
+    return t;
 }
 
+// f_coarse = R r on the interior of the coarse level, r vanishing on black
+// fine nodes; one coarse (I, J) column per thread, KU planes
 template <typename T>
-hipError_t launch_restrict(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s)
+__global__ __launch_bounds__(PT_NT) void k_restrict_red(LevelView F, LevelView C, const T* __restrict__ r,
+                                                        T* __restrict__ rc, int nbx, int nby, int nb, int per)
 {
-    PT_LAUNCH((k_restrict<T, false>), C, s, F, r, rc);
-    return hipGetLastError();
+    constexpr int KU = TransferUnroll<T>::KU;
+    const int t = xcd_tile(blockIdx.x, per);
+    const int I = 1 + (t % nbx) * PT_X + (threadIdx.x & (PT_X - 1));
+    const int J = 1 + ((t / nbx) % nby) * PT_Y + (threadIdx.x >> 6);
+    if (t >= nb || J > C.ny - 2) return;
+    const bool inside = I <= C.nx - 2;
+    const int k0 = 1 + (t / (nbx * nby)) * KU;
+    // table lookups of the column and its planes (out-of-range planes are
+    // clamped to the last interior plane and not stored)
+    const RTaps<T> x = restrict_taps<T>(C, inside ? I : C.nx - 2);
+    const int fj = C.ax[1].rf[J];
+    const T wy0 = (T)C.ax[1].rw[3 * J], wy1 = (T)C.ax[1].rw[3 * J + 1], wy2 = (T)C.ax[1].rw[3 * J + 2];
+    int fk[KU];
+    T wz[KU][3];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+        const int K = min(k0 + u, C.nz - 2);
+        fk[u] = C.ax[2].rf[K];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) wz[u][c] = (T)C.ax[2].rw[3 * K + c];
+    }
+    // the gathers: two red entries of each of the 3 x 3 fine rows per plane
+    T g0[KU][3][3], g1[KU][3][3];
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const T* row = r + ((size_t)(fk[u] - 1 + c) * F.ny + (fj - 1 + b)) * F.W + x.m0;
+                g0[u][c][b] = row[0];
+                g1[u][c][b] = row[1];
+            }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T plane = T(0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const bool same = ((fj - 1 + b + fk[u] - 1 + c) & 1) == x.e;
+                const T wy = b == 0 ? wy0 : (b == 1 ? wy1 : wy2);
+                plane += wy * ((same ? x.s0 : x.d0) * g0[u][c][b] + (same ? x.s1 : x.d1) * g1[u][c][b]);
+            }
+            acc += wz[u][c] * plane;
+        }
+        if (inside && k0 + u <= C.nz - 2) rc[sidx(C, I, J, k0 + u)] = acc;
+    }
 }
 
 template <typename T>
 hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s)
 {
-    PT_LAUNCH((k_restrict<T, true>), C, s, F, r, rc);
+    const TileShape ts = tile_shape(C.nx - 2, C.ny - 2, C.nz - 2, TransferUnroll<T>::KU);
+    hipLaunchKernelGGL(k_restrict_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, r, rc, ts.nbx, ts.nby, ts.nb,
+                       ts.per);
     return hipGetLastError();
 }
 
 // u += P e on the red nodes only: when a black half-sweep follows, it
-// overwrites every black value, so correcting them would be wasted work.
+// overwrites every black value, so correcting them would be wasted work. One
+// red entry m of a row per thread, KU planes; its fine node is i = o + 2m
+// with the row parity o = (j + k) & 1, so the taps of both parities are
+// prepared once.
 template <typename T>
 __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C, const T* __restrict__ e,
-                                                       T* __restrict__ u, int nbx, int nby, int nb, int per, int kc)
+                                                       T* __restrict__ u, int nbx, int nby, int nb, int per)
 {
+    constexpr int KU = TransferUnroll<T>::KU;
     const int t = xcd_tile(blockIdx.x, per);
     const int m = (t % nbx) * PT_X + (threadIdx.x & (PT_X - 1));
     const int j = 1 + ((t / nbx) % nby) * PT_Y + (threadIdx.x >> 6);
-    if (t >= nb || j > F.ny - 2 || m > (F.nx - 2) / 2) return;
-    const int k0 = 1 + (t / (nbx * nby)) * kc;
-    const int k1 = min(k0 + kc, F.nz - 1);
+    if (t >= nb || j > F.ny - 2) return;
+    const bool mok = m <= (F.nx - 2) / 2;
+    const int mm = mok ? m : (F.nx - 2) / 2;   // clamped entry for the loads
+    const int i0 = 2 * mm, i1 = 2 * mm + 1;
+    const bool ok0 = mok && i0 >= 1 && i0 <= F.nx - 2;
+    const bool ok1 = mok && i1 <= F.nx - 2;
+    const PTaps<T> x0 = prolong_taps<T>(C.ax[0], min(max(i0, 1), F.nx - 2));
+    const PTaps<T> x1 = prolong_taps<T>(C.ax[0], min(i1, F.nx - 2));
+    const PTaps<T> y = prolong_taps<T>(C.ax[1], j);
+    const int k0 = 1 + (t / (nbx * nby)) * KU;
+    PTaps<T> z[KU];
+#pragma unroll
+    for (int q = 0; q < KU; ++q) z[q] = prolong_taps<T>(C.ax[2], min(k0 + q, F.nz - 2));
     const size_t plane = (size_t)F.ny * F.W;
-    const size_t row = (size_t)j * F.W + m;
-    for (int k = k0; k < k1; ++k) {
-        const int i = ((j + k) & 1) + 2 * m;
-        if (i < 1 || i > F.nx - 2) continue;
-        u[(size_t)k * plane + row] += prolong_point(C, e, i, j, k);
+    const size_t row = (size_t)j * F.W + mm;
+    T va[KU][2][2], vb[KU][2][2], uo[KU];
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+        const int k = min(k0 + q, F.nz - 2);
+        const PTaps<T>& x = ((j + k) & 1) ? x1 : x0;
+        const int ma = x.I >> 1, mb = (x.I + 1) >> 1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int Jb = y.I + b, Kc = z[q].I + c;
+                const size_t crow = ((size_t)Kc * C.ny + Jb) * C.W;
+                const int ca = (x.I + Jb + Kc) & 1;
+                va[q][c][b] = e[(size_t)ca * C.cs + crow + ma];
+                vb[q][c][b] = e[(size_t)(ca ^ 1) * C.cs + crow + mb];
+            }
+        uo[q] = u[(size_t)k * plane + row];
+    }
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+        const int k = k0 + q;
+        const bool odd = (j + k) & 1;
+        const T w0 = odd ? x1.w0 : x0.w0, w1 = odd ? x1.w1 : x0.w1;
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            T sacc = T(0);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) sacc += (b ? y.w1 : y.w0) * (w0 * va[q][c][b] + w1 * vb[q][c][b]);
+            acc += (c ? z[q].w1 : z[q].w0) * sacc;
+        }
+        if (k <= F.nz - 2 && (odd ? ok1 : ok0)) u[(size_t)k * plane + row] = uo[q] + acc;
     }
 }
 
 template <typename T>
 hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s)
 {
-    // one red entry per thread: (m, j) tiles of 64 x 4, planes chunked as in the sweeps
-    const int mcount = (F.nx - 2) / 2 + 1;
-    const int nbx = (mcount + PT_X - 1) / PT_X, nby = (F.ny - 2 + PT_Y - 1) / PT_Y;
-    const long tiles = (long)nbx * nby;
-    const int kc = (int)std::min<long>(16, std::max<long>(1, (long)(F.nz - 2) * tiles / 2048));
-    const int nbz = (F.nz - 2 + kc - 1) / kc;
-    const int nb = nbx * nby * nbz, per = (nb + 7) / 8;
-    hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * per), dim3(PT_NT), 0, s, F, C, e, u, nbx, nby, nb, per, kc);
+    const TileShape ts = tile_shape((F.nx - 2) / 2 + 1, F.ny - 2, F.nz - 2, TransferUnroll<T>::KU);
+    hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, e, u, ts.nbx, ts.nby, ts.nb,
+                       ts.per);
     return hipGetLastError();
 }
 
+// u += P e on every interior node (a V-cycle without post-smoothing)
 template <typename T>
 __global__ __launch_bounds__(PT_NT) void k_prolong_add(LevelView F, int kp, LevelView C, const T* __restrict__ e,
                                                        T* __restrict__ u)
@@ -895,7 +1011,7 @@ __global__ __launch_bounds__(PT_NT) void k_prolong_add(LevelView F, int kp, Leve
     INTERIOR_LOOP
     {
         if (!inside) continue;
-        u[sidx(F, i, j, k)] += prolong_point(C, e, i, j, k);
+        u[sidx(F, i, j, k)] += prolong_at<T>(C, e, prolong_taps<T>(C.ax[0], i), j, k);
     }
 }
 
@@ -978,12 +1094,13 @@ __device__ void t_restrict_red(const LevelView& F, const LevelView& C, const T* 
     const Cols cl = tail_cols((C.nx - 2) * (C.ny - 2));
     if (!cl.active) return;
     const int I = 1 + cl.col % (C.nx - 2), J = 1 + cl.col / (C.nx - 2);
+    const RTaps<T> x = restrict_taps<T>(C, I);
     for (int kb = 1 + cl.grp; kb <= C.nz - 2; kb += cl.ng * TL_BATCH) {
         T val[TL_BATCH];
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
             const int K = kb + b * cl.ng;
-            val[b] = K <= C.nz - 2 ? restrict_point<T, true>(F, C, r, I, J, K) : T(0);
+            val[b] = K <= C.nz - 2 ? restrict_red_at<T>(F, C, r, x, J, K) : T(0);
         }
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
@@ -1000,13 +1117,14 @@ __device__ void t_prolong(const LevelView& F, const LevelView& C, const T* __res
     const Cols cl = tail_cols((F.nx - 2) * (F.ny - 2));
     if (!cl.active) return;
     const int i = 1 + cl.col % (F.nx - 2), j = 1 + cl.col / (F.nx - 2);
+    const PTaps<T> x = prolong_taps<T>(C.ax[0], i);
     for (int kb = 1 + cl.grp; kb <= F.nz - 2; kb += cl.ng * TL_BATCH) {
         T val[TL_BATCH];
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
             const int k = kb + b * cl.ng;
             const bool ok = k <= F.nz - 2 && !(red_only && ((i + j + k) & 1));
-            val[b] = ok ? prolong_point(C, e, i, j, k) : T(0);
+            val[b] = ok ? prolong_at<T>(C, e, x, j, k) : T(0);
         }
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
@@ -1018,7 +1136,7 @@ __device__ void t_prolong(const LevelView& F, const LevelView& C, const T* __res
 
 template <typename T>
 __global__ __launch_bounds__(TL_NT) void k_tail(const TailLevel* __restrict__ lv, int nl, int nu1, int nu2,
-                                                int csweeps)
+                                                int csweeps, int top_zero)
 {
     // descent
     for (int l = 0; l + 1 < nl; ++l) {
@@ -1027,7 +1145,7 @@ __global__ __launch_bounds__(TL_NT) void k_tail(const TailLevel* __restrict__ lv
         const T* f = TailBuf<T>::f(lv[l]);
         T* r = TailBuf<T>::r(lv[l]);
         for (int s = 0; s < nu1; ++s) {
-            t_half<T, false>(V, u, f, r, 0, s == 0);
+            t_half<T, false>(V, u, f, r, 0, s == 0 && (l > 0 || top_zero));
             __syncthreads();
             t_half<T, false>(V, u, f, r, 1, 0);
             __syncthreads();
@@ -1069,9 +1187,9 @@ __global__ __launch_bounds__(TL_NT) void k_tail(const TailLevel* __restrict__ lv
 }
 
 template <typename T>
-hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweeps, hipStream_t s)
+hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweeps, int top_zero, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TL_NT), 0, s, lv, nl, nu1, nu2, csweeps);
+    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TL_NT), 0, s, lv, nl, nu1, nu2, csweeps, top_zero);
     return hipGetLastError();
 }
 
@@ -1105,17 +1223,15 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
 
 // ------------------------------------------------- explicit instantiation
 #define INST(T)                                                                                                  \
-    template hipError_t launch_half<T>(const LevelView&, T*, const T*, int, int, T, double*, hipStream_t, int*);   \
+    template hipError_t launch_half<T>(const LevelView&, T*, const T*, int, int, T, double*, hipStream_t, int*, int, \
+                                       hipEvent_t, hipEvent_t);                                                   \
     template hipError_t launch_half_keep_faces<T>(const LevelView&, T*, const T*, int, T, hipStream_t);          \
-    template hipError_t launch_residual<T>(const LevelView&, const T*, const T*, T*, hipStream_t);                 \
-    template hipError_t launch_restrict<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);         \
     template hipError_t launch_prolong_add<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
     template hipError_t launch_prolong_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
     template hipError_t launch_restrict_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);     \
     template hipError_t launch_residual_colour<T>(const LevelView&, const T*, const T*, T*, int, hipStream_t);    \
     template hipError_t launch_apply_colour<T>(const LevelView&, const T*, T*, int, double*, hipStream_t, int*);   \
-    template hipError_t launch_tail<T>(const TailLevel*, int, int, int, int, hipStream_t);                         \
-    template hipError_t launch_apply_dot<T>(const LevelView&, const T*, T*, double*, hipStream_t);                 \
+    template hipError_t launch_tail<T>(const TailLevel*, int, int, int, int, int, hipStream_t);                    \
     template hipError_t launch_dot<T>(const LevelView&, const T*, const T*, double*, hipStream_t);                 \
     template hipError_t launch_update_p<T>(const LevelView&, const T*, const T*, T*, const double*, int, int, int,  \
                                            hipStream_t);                                                          \

@@ -35,49 +35,46 @@ template <> struct Buf<float> {
         if (e_ != hipSuccess) return fail(LASTO_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// A half-sweep at level l; finest-level half-sweeps are bracketed by HIP
-// events when profiling is on (the events sit on the kernel's stream).
+// A half-sweep at level l. With profiling on, each finest-level half-sweep
+// is launched with a pair of events that take the dispatch's own start and
+// end timestamps, so their difference is the kernel's execution time.
 template <typename T>
 static hipError_t half(lasto_grid g, int l, T* u, const T* f, int colour, int zero_in, double* dotp,
                        int* nparts = nullptr)
 {
     const LevelView& V = g->lev[l].view;
     const bool timed = g->prof_on && l == 0;
-    if (timed) {
-        if ((size_t)(2 * g->prof_used + 2) > g->prof_ev.size()) {
-            for (int k = 0; k < 64; ++k) {
-                hipEvent_t e;
-                hipError_t err = hipEventCreate(&e);
-                if (err != hipSuccess) return err;
-                g->prof_ev.push_back(e);
-            }
+    if (!timed) return launch_half<T>(V, u, f, colour, zero_in, T(1), dotp, g->stream, nparts, l == 0);
+    if ((size_t)(2 * g->prof_used + 2) > g->prof_ev.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            g->prof_ev.push_back(e);
         }
-        hipError_t err = hipEventRecord(g->prof_ev[2 * g->prof_used], g->stream);
-        if (err != hipSuccess) return err;
     }
-    hipError_t err = launch_half<T>(V, u, f, colour, zero_in, T(1), dotp, g->stream, nparts);
+    hipError_t err = launch_half<T>(V, u, f, colour, zero_in, T(1), dotp, g->stream, nparts, 1,
+                                    g->prof_ev[2 * g->prof_used], g->prof_ev[2 * g->prof_used + 1]);
     if (err != hipSuccess) return err;
-    if (timed) {
-        err = hipEventRecord(g->prof_ev[2 * g->prof_used + 1], g->stream);
-        if (err != hipSuccess) return err;
-        // algorithmic bytes: half the interior nodes read f and (unless the
-        // other colour is zero) one other-colour value, and write their own value
-        const double pts = 0.5 * (double)(V.nx - 2) * (V.ny - 2) * (V.nz - 2);
-        g->prof_bytes += pts * sizeof(T) * (zero_in ? 2.0 : 3.0);
-        if (sizeof(T) == 4) g->prof_fp32++;
-        g->prof_used++;
-    }
+    // algorithmic bytes: half the interior nodes read f and (unless the
+    // other colour is zero) one other-colour value, and write their own value
+    const double pts = 0.5 * (double)(V.nx - 2) * (V.ny - 2) * (V.nz - 2);
+    g->prof_bytes += pts * sizeof(T) * (zero_in ? 2.0 : 3.0);
+    if (sizeof(T) == 4) g->prof_fp32++;
+    g->prof_used++;
     return hipSuccess;
 }
 
-// V(nu1, nu2) at level l on A u = f with zero faces, starting from u = 0, in
-// place in the split layout. Pre-smoothing sweeps update red then black,
-// post-smoothing black then red, and the coarsest level runs a symmetric
-// sweep sequence, so the cycle is a symmetric operator (a valid CG
-// preconditioner). With dotp, partials of <f, u>_W over the result are
-// written (count in *ndot).
+// V(nu1, nu2) at level l on A u = f with zero faces, in place in the split
+// layout, starting from u = 0 (zero_start) or from the u given (level 0
+// only; coarse levels always start from zero). Pre-smoothing sweeps update
+// red then black, post-smoothing black then red, and the coarsest level runs
+// a symmetric sweep sequence, so the cycle from zero is a symmetric operator
+// (a valid CG preconditioner). With dotp, partials of <f, u>_W over the
+// result are written (count in *ndot).
 template <typename T>
-static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T* f, T* u, double* dotp, int* ndot)
+static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T* f, T* u, double* dotp, int* ndot,
+                                 bool zero_start = true)
 {
     Level& L = g->lev[l];
     const LevelView& V = L.view;
@@ -87,7 +84,7 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
         // Krylov vectors, which are the only ones a level-0 cycle is given
         if (l == 0 && !((void*)u == (void*)g->z || (void*)u == (void*)g->z32))
             return fail(LASTO_ERR_STATE, "vcycle: level-0 tail needs the grid's Krylov vectors");
-        HIPCHK(launch_tail<T>(g->tail_dev + l, g->nlev - l, nu1, nu2, kCoarseSweeps, s));
+        HIPCHK(launch_tail<T>(g->tail_dev + l, g->nlev - l, nu1, nu2, kCoarseSweeps, zero_start ? 1 : 0, s));
         if (dotp) {
             HIPCHK(launch_dot<T>(V, f, u, dotp, s));
             *ndot = row_blocks(V);
@@ -95,7 +92,7 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
         return LASTO_OK;
     }
     for (int k = 0; k < nu1; ++k) {
-        HIPCHK(half<T>(g, l, u, f, 0, k == 0, nullptr));
+        HIPCHK(half<T>(g, l, u, f, 0, k == 0 && zero_start, nullptr));
         HIPCHK(half<T>(g, l, u, f, 1, 0, nullptr));
     }
     // The pre-smoothing ended with a black half-sweep, so the residual is zero
@@ -152,6 +149,20 @@ static lasto_status read_scalars(lasto_grid g, int first, int n)
     HIPCHK(hipMemcpyAsync(g->h_scalars + first, g->scalars + first, sizeof(double) * n, hipMemcpyDeviceToHost,
                           g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}
+
+// Inner FP32 multigrid on A e = r32 (the scaled residual): `cycles` V-cycles
+// in z32, the first from e = 0, each later one continuing from the current e
+// (a stationary iteration needs no residual of its own: the cycle computes
+// it after its pre-smoothing).
+static lasto_status mg32_inner(lasto_grid g, const lasto_solve_opts& o, int cycles, int* vcycles)
+{
+    for (int c = 0; c < cycles; ++c) {
+        lasto_status st = vcycle_level<float>(g, 0, o.nu1, o.nu2, g->r32, g->z32, nullptr, nullptr, c == 0);
+        if (st != LASTO_OK) return st;
+        ++*vcycles;
+    }
     return LASTO_OK;
 }
 
@@ -218,8 +229,6 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
         o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 1 || (o.precision == 1 && o.inner_iters < 1))
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters");
-    if (o.precision == 1 && o.method != 0)
-        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: mixed precision runs with method 0");
     lasto_solve_info inf;
     std::memset(&inf, 0, sizeof(inf));
     hipStream_t s = g->stream;
@@ -275,8 +284,13 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         if (o.precision == 1) {
             // FP32 inner PCG on the scaled FP64 residual, then v += |r| e
             HIPCHK(launch_scale_to32(V, g->r, g->r32, g->scalars, S_RR, s));
-            if (lasto_status e = pcg32_inner(g, o, o.inner_iters, &inf.vcycles); e != LASTO_OK) return e;
-            HIPCHK(launch_add_scaled32_nat(V, v, g->e32, g->scalars, S_RR, s));
+            if (o.method == 1) {
+                if (lasto_status e = mg32_inner(g, o, o.inner_iters, &inf.vcycles); e != LASTO_OK) return e;
+                HIPCHK(launch_add_scaled32_nat(V, v, g->z32, g->scalars, S_RR, s));
+            } else {
+                if (lasto_status e = pcg32_inner(g, o, o.inner_iters, &inf.vcycles); e != LASTO_OK) return e;
+                HIPCHK(launch_add_scaled32_nat(V, v, g->e32, g->scalars, S_RR, s));
+            }
             HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             inf.refinements++;

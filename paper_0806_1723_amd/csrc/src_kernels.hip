@@ -72,32 +72,49 @@ __device__ __forceinline__ void solid_harmonics(double x, double y, double z, in
 }
 
 // ---------------------------------------------------------------- atoms
+// One workgroup per atom.
 // kind 0: s = 1/((pi w^2)^(-3/2) prod_d sum_i m_d,i exp(-(x_d,i - c_d)^2/w^2))
-//         (the discrete integral of the normalised Gaussian is separable)
+//         (the discrete integral of the normalised Gaussian is separable;
+//         each 1-D sum is split over the workgroup and reduced in a fixed order)
 // kind 1: quartic a + b r^2 + c r^4 from value, slope and charge at R, by
 //         Cramer's rule on
 //           [1, R^2, R^4; 0, 2R, 4R^3; 4piR^3/3, 4piR^5/5, 4piR^7/7] (a,b,c) = (rho_R, drho_R, q)
-__global__ void k_atom_prep(LevelView L, AtomDev* atoms, int n_atoms, int renormalize)
+// Then the per-atom constants the density kernel uses.
+constexpr int AP_NT = 256;
+
+__global__ __launch_bounds__(AP_NT) void k_atom_prep(LevelView L, AtomDev* atoms, int n_atoms, int renormalize)
 {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double red[AP_NT];
+    const int a = blockIdx.x;
     if (a >= n_atoms) return;
     AtomDev& A = atoms[a];
-    if (A.kind == 0) {
-        double s = 1.0;
-        if (renormalize) {
-            const double w2 = A.w * A.w;
-            double prod = pow(kPi * w2, -1.5);
-            for (int d = 0; d < 3; ++d) {
-                double sum = 0.0;
-                for (int i = 0; i < L.ax[d].n; ++i) {
-                    const double t = L.ax[d].x[i] - A.c[d];
-                    sum += L.ax[d].m[i] * exp(-t * t / w2);
-                }
-                prod *= sum;
+    double s = 1.0;
+    if (A.kind == 0 && renormalize) {
+        const double w2 = A.w * A.w;
+        double prod = pow(kPi * w2, -1.5);
+        for (int d = 0; d < 3; ++d) {
+            double sum = 0.0;
+            for (int i = threadIdx.x; i < L.ax[d].n; i += AP_NT) {
+                const double t = L.ax[d].x[i] - A.c[d];
+                sum += L.ax[d].m[i] * exp(-t * t / w2);
             }
-            s = 1.0 / prod;
+            red[threadIdx.x] = sum;
+            __syncthreads();
+            for (int h = AP_NT / 2; h > 0; h >>= 1) {
+                if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+                __syncthreads();
+            }
+            prod *= red[0];
+            __syncthreads();
         }
+        s = 1.0 / prod;
+    }
+    if (threadIdx.x != 0) return;
+    if (A.kind == 0) {
         A.s = s;
+        A.pre = A.q * s * pow(kPi * A.w * A.w, -1.5);
+        A.iw2 = 1.0 / (A.w * A.w);
+        A.cut2 = (7.0 * A.w) * (7.0 * A.w);
     } else {
         const double R = A.R, R2 = R * R;
         const double m00 = 1.0, m01 = R2, m02 = R2 * R2;
@@ -113,58 +130,132 @@ __global__ void k_atom_prep(LevelView L, AtomDev* atoms, int n_atoms, int renorm
         A.coef[1] = db / det;
         A.coef[2] = dc / det;
         A.s = 1.0;
+        A.pre = 0.0;
+        A.iw2 = 0.0;
+        A.cut2 = R2;
     }
+    A.lcut2 = A.lmax >= 1 ? 42.25 / A.alpha * (1.0 + 1e-12) : -1.0;   // culling only (a little wide)
+    A.cull2 = fmax(fmax(A.cut2, A.R * A.R), A.lcut2) * (1.0 + 1e-12);
+    for (int l = 1; l <= 4; ++l)
+        for (int m = -l; m <= l; ++m) A.cn[l * l + l + m - 1] = A.clm[l * l + l + m - 1] * c_ynorm[l * l + l + m];
 }
 
 hipError_t launch_atom_prep(lasto_grid g, AtomDev* atoms, int n_atoms, int renormalize)
 {
-    hipLaunchKernelGGL(k_atom_prep, dim3((n_atoms + 63) / 64), dim3(64), 0, g->stream, g->lev[0].view, atoms, n_atoms,
+    hipLaunchKernelGGL(k_atom_prep, dim3(n_atoms), dim3(AP_NT), 0, g->stream, g->lev[0].view, atoms, n_atoms,
                        renormalize);
     return hipGetLastError();
 }
 
-// --------------------------------------------------------------- density
-__global__ __launch_bounds__(256) void k_pseudo(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
-                                                const double* __restrict__ rho_inter, double* __restrict__ rho)
+// sum_{1 <= l <= lmax, m} cn_lm Q-recurrence values: the l >= 1 part of
+// sum c_lm r^l y_lm at (x, y, z), with cn = c_lm times the normalisation.
+// Same recurrences as solid_harmonics, unrolled so every term has a fixed
+// register (no array indexed at run time).
+__device__ __forceinline__ double clm_sum(double x, double y, double z, int lmax, const double* __restrict__ cn)
 {
-    const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const size_t n = (size_t)nx * ny * nz;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((size_t)nx * ny));
-    const double px = L.ax[0].x[i], py = L.ax[1].x[j], pz = L.ax[2].x[k];
-    double acc = 0.0;
-    bool outside = true;
-    double S[25];
-    for (int a = 0; a < n_atoms; ++a) {
-        const AtomDev& A = atoms[a];
-        const double dx = px - A.c[0], dy = py - A.c[1], dz = pz - A.c[2];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < A.R * A.R) outside = false;
-        if (A.kind == 0) {
-            const double cut = 7.0 * A.w;
-            if (r2 < cut * cut) acc += A.q * A.s * pow(kPi * A.w * A.w, -1.5) * exp(-r2 / (A.w * A.w));
-        } else if (r2 < A.R * A.R) {
-            acc += A.coef[0] + r2 * (A.coef[1] + r2 * A.coef[2]);
+    const double r2 = x * x + y * y + z * z;
+    double s = 0.0;
+    double mre = 1.0, mim = 0.0;   // Q_m^m
+#pragma unroll
+    for (int m = 0; m <= 4; ++m) {
+        if (m > lmax) break;
+        if (m > 0) {
+            const double nre = mre * x - mim * y;
+            const double nim = mre * y + mim * x;
+            mre = nre * (2.0 * m - 1.0);
+            mim = nim * (2.0 * m - 1.0);
         }
-        if (A.lmax >= 1 && A.alpha * r2 < 42.25) {
-            solid_harmonics(dx, dy, dz, A.lmax, S);
-            double s = 0.0;
-            const int nt = (A.lmax + 1) * (A.lmax + 1);
-            for (int c = 1; c < nt; ++c) s += A.clm[c - 1] * S[c];
-            acc += s * exp(-A.alpha * r2);
+        double pre = 0.0, pim = 0.0;
+        double cre = mre, cim = mim;
+#pragma unroll
+        for (int l = m; l <= 4; ++l) {
+            if (l > lmax) break;
+            if (l > m) {
+                const double a = (2.0 * (l - 1) + 1.0) / (double)(l - m);
+                const double b = (double)(l - 1 + m) / (double)(l - m);
+                const double nre = a * z * cre - b * r2 * pre;
+                const double nim = a * z * cim - b * r2 * pim;
+                pre = cre;
+                pim = cim;
+                cre = nre;
+                cim = nim;
+            }
+            if (l >= 1) {
+                s += cn[l * l + l + m - 1] * cre;
+                if (m > 0) s += cn[l * l + l - m - 1] * cim;
+            }
         }
     }
-    if (rho_inter && outside) acc += rho_inter[t];
-    rho[t] = acc;
+    return s;
+}
+
+// --------------------------------------------------------------- density
+// A workgroup covers 64 x 4 x 4 nodes. It first lists, in atom order, the
+// atoms whose cut-off sphere reaches its box (a block-wide ordered
+// compaction), then each thread sums only those atoms at its 4 nodes.
+constexpr int PS_X = 64, PS_Y = 4, PS_Z = 4, PS_NT = PS_X * PS_Y, PS_LIST = 1024;
+
+__global__ __launch_bounds__(PS_NT) void k_pseudo(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
+                                                  const double* __restrict__ rho_inter, double* __restrict__ rho)
+{
+    __shared__ int list[PS_LIST];
+    __shared__ int wcount[PS_NT / 64];
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int i0 = blockIdx.x * PS_X, j0 = blockIdx.y * PS_Y, k0 = blockIdx.z * PS_Z;
+    const int i1 = min(i0 + PS_X, nx) - 1, j1 = min(j0 + PS_Y, ny) - 1, k1 = min(k0 + PS_Z, nz) - 1;
+    const double bx0 = L.ax[0].x[i0], bx1 = L.ax[0].x[i1];
+    const double by0 = L.ax[1].x[j0], by1 = L.ax[1].x[j1];
+    const double bz0 = L.ax[2].x[k0], bz1 = L.ax[2].x[k1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int count = 0;
+    bool all = n_atoms > PS_LIST;   // too many to list: every atom is tested per node
+    for (int base = 0; base < n_atoms && !all; base += PS_NT) {
+        const int a = base + (int)threadIdx.x;
+        bool hit = false;
+        if (a < n_atoms) {
+            const AtomDev& A = atoms[a];
+            const double dx = fmax(fmax(bx0 - A.c[0], A.c[0] - bx1), 0.0);
+            const double dy = fmax(fmax(by0 - A.c[1], A.c[1] - by1), 0.0);
+            const double dz = fmax(fmax(bz0 - A.c[2], A.c[2] - bz1), 0.0);
+            hit = dx * dx + dy * dy + dz * dz < A.cull2;
+        }
+        const unsigned long long mask = __ballot(hit);
+        if (lane == 0) wcount[wid] = __popcll(mask);
+        __syncthreads();
+        int off = count;
+        for (int w = 0; w < wid; ++w) off += wcount[w];
+        if (hit) list[off + __popcll(mask & ((1ull << lane) - 1ull))] = a;
+        for (int w = 0; w < PS_NT / 64; ++w) count += wcount[w];
+        __syncthreads();
+    }
+    const int i = i0 + lane, j = j0 + wid;
+    if (i > i1 || j > j1) return;
+    const double px = L.ax[0].x[i], py = L.ax[1].x[j];
+    const int na = all ? n_atoms : count;
+    for (int k = k0; k <= k1; ++k) {
+        const double pz = L.ax[2].x[k];
+        double acc = 0.0;
+        bool outside = true;
+        for (int t = 0; t < na; ++t) {
+            const AtomDev& A = atoms[all ? t : list[t]];
+            const double dx = px - A.c[0], dy = py - A.c[1], dz = pz - A.c[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= A.cull2) continue;
+            if (r2 < A.R * A.R) outside = false;
+            if (r2 < A.cut2) acc += A.kind == 0 ? A.pre * exp(-r2 * A.iw2) : A.coef[0] + r2 * (A.coef[1] + r2 * A.coef[2]);
+            if (A.lmax >= 1 && A.alpha * r2 < 42.25) acc += clm_sum(dx, dy, dz, A.lmax, A.cn) * exp(-A.alpha * r2);
+        }
+        const size_t at = ((size_t)k * ny + j) * nx + i;
+        if (rho_inter && outside) acc += rho_inter[at];
+        rho[at] = acc;
+    }
 }
 
 hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const double* rho_inter, double* rho)
 {
     const LevelView& L = g->lev[0].view;
-    const size_t n = (size_t)L.nx * L.ny * L.nz;
-    hipLaunchKernelGGL(k_pseudo, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g->stream, L, atoms, n_atoms, rho_inter,
-                       rho);
+    const dim3 grid((L.nx + PS_X - 1) / PS_X, (L.ny + PS_Y - 1) / PS_Y, (L.nz + PS_Z - 1) / PS_Z);
+    hipLaunchKernelGGL(k_pseudo, grid, dim3(PS_NT), 0, g->stream, L, atoms, n_atoms, rho_inter, rho);
     return hipGetLastError();
 }
 

@@ -144,12 +144,17 @@ def oracle_solution(oracle_mod, xs, atoms, bc=1, rtol=1e-12):
 
 SOLVE_CASES = [
     (1, 33, dict()),
+    (1, 25, dict()),                         # 25^3 <= 16384 nodes: the whole cycle in one workgroup
+    (1, 25, dict(precision=1, method=1)),
     (2, 65, dict()),
     (2, 65, dict(method=1)),
     (2, 65, dict(precision=1)),
+    (2, 65, dict(precision=1, method=1)),
     (2, 129, dict()),
     (2, 129, dict(precision=1)),
+    (2, 129, dict(precision=1, method=1)),
     (4, 65, dict()),
+    (4, 65, dict(precision=1, method=1)),
 ]
 
 
@@ -238,14 +243,21 @@ def test_full_size_257_properties(torch, L, oracle_mod):
     i64 = g.poisson_solve(rho, v64, rtol=1e-10)
     v32 = g.empty()
     i32 = g.poisson_solve(rho, v32, rtol=1e-10, precision=1)
-    say("  fp64 iters %d (%.1f ms), mixed refinements %d vcycles %d (%.1f ms)" %
-        (i64["iters"], i64["ms_total"], i32["refinements"], i32["vcycles"], i32["ms_total"]))
+    vmg = g.empty()
+    img = g.poisson_solve(rho, vmg, rtol=1e-10, precision=1, method=1)
+    say("  fp64 iters %d (%.1f ms), mixed PCG refinements %d vcycles %d (%.1f ms), "
+        "mixed MG refinements %d vcycles %d (%.1f ms)" %
+        (i64["iters"], i64["ms_total"], i32["refinements"], i32["vcycles"], i32["ms_total"],
+         img["refinements"], img["vcycles"], img["ms_total"]))
     rho_h = rho.cpu().numpy()
     a = v64.cpu().numpy()
     b = v32.cpu().numpy()
+    c = vmg.cpu().numpy()
     assert oracle_mod.rel_residual(xs, rho_h, a) <= 1.2e-10
     assert oracle_mod.rel_residual(xs, rho_h, b) <= 1.2e-10
+    assert oracle_mod.rel_residual(xs, rho_h, c) <= 1.2e-10
     assert wnorm(xs, a - b) / wnorm(xs, a) <= 1e-8
+    assert wnorm(xs, a - c) / wnorm(xs, a) <= 1e-8
     # sampled density values against the oracle's full evaluation
     want = oracle_mod.pseudo_density(xs, I.atom_arrays(w.atoms))
     rng = np.random.default_rng(15)
@@ -295,7 +307,9 @@ def test_failure_paths(torch, L, oracle_mod):
     with pytest.raises(L.LastoError):
         g.poisson_solve(rho, g.empty(), nu1=0)
     with pytest.raises(L.LastoError):
-        g.poisson_solve(rho, g.empty(), precision=1, method=1)
+        g.poisson_solve(rho, g.empty(), precision=1, method=2)
+    with pytest.raises(L.LastoError):
+        g.poisson_solve(rho, g.empty(), precision=1, inner_iters=0)
     # faces as given (bc = 2) are kept
     v = g.empty()
     v[0].fill_(1.25)
