@@ -34,6 +34,8 @@
 #ifndef LASTO_H
 #define LASTO_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -221,6 +223,94 @@ lasto_status lasto_apply(lasto_grid g, const double* u, double* Au);
  *   u_in, rho, u_out: device [nz][ny][nx]; u_out must not alias u_in.
  */
 lasto_status lasto_rb_sweep(lasto_grid g, const double* u_in, const double* rho, double* u_out, int first_colour);
+
+/*
+ * Dirichlet data on the six faces of v, the boundary step of
+ * lasto_poisson_solve on its own (eq. (3.3) for bc = 0; bc = 1 the multipole
+ * field of the grid moments, as documented at lasto_poisson_solve).
+ *   rho: device source (read for bc = 1). v: device, only faces written.
+ *   moments_out: host [25] Q_lm (bc = 1) or NULL.
+ * Errors: LASTO_ERR_ARG (bc not 0/1, lmax_bc outside 0..4), LASTO_ERR_HIP.
+ */
+lasto_status lasto_boundary_values(lasto_grid g, const double* rho, int bc, int lmax_bc, double* v,
+                                   double* moments_out);
+
+/*
+ * Analytic initial guess: the interior of v becomes the sum over atoms of the
+ * free-space potential of each atom's monopole under eq. (3.2)'s sign
+ * (kind 0: -q erf(r/w)/r; kind 1: the uniform ball of charge q and radius R).
+ * Faces are not touched. Atoms as for lasto_pseudo_density.
+ * Errors: LASTO_ERR_ARG, LASTO_ERR_HIP.
+ */
+lasto_status lasto_analytic_guess(lasto_grid g, int n_atoms, const lasto_atom* atoms, double* v);
+
+/* ------------------------------------------------------------------------
+ * Learned form. The paper's solver has no learned part; this is the learned
+ * initial guess grown beside the multigrid solver: a four-level 3-D U-Net on
+ * the finest grid's index space (channels 16, c1, c2, c3; 3x3x3 convolutions,
+ * stride-2 down-sampling, linear up-sampling with skip sums, a 1x1x1 head),
+ * BF16 activations and FP32 accumulation on the matrix cores, FP32 master
+ * weights trained with Adam by the library's own forward and backward
+ * kernels. Plain multigrid stays the judge: lasto_learned_guess keeps the
+ * correction only if it lowers the residual.
+ */
+typedef struct lasto_net_s* lasto_net;
+
+typedef struct {
+    int nx, ny, nz;              /* node grid the net runs on (the grid's finest level); each >= 8 */
+    int ch[4];                   /* channels per level: ch[0] = 16, the others 16, 32, 48 or 64 */
+    unsigned long long seed;     /* initial weights: He-normal from a splitmix64 / Box-Muller stream */
+    double rho_scale;            /* feature 0 = rho * rho_scale */
+    double pot_scale;            /* feature 4 = v * pot_scale */
+    double h_ref;                /* features 1..3 = log(m_d / h_ref), m_d the dual width along axis d */
+    double out_scale;            /* the correction is out_scale times the net's output */
+} lasto_net_config;
+
+/* Create a net on a stream (NULL: the default stream). Errors: LASTO_ERR_ARG,
+ * LASTO_ERR_ALLOC, LASTO_ERR_HIP. The net owns all its device memory. */
+lasto_status lasto_net_create(const lasto_net_config* cfg, void* hip_stream, lasto_net* out);
+lasto_status lasto_net_destroy(lasto_net n);
+/* Flat FP32 parameter vector: per convolution W[27][cin][cout] then b[cout]
+ * (8 convolutions in forward order), then the head w[16] and its bias. */
+lasto_status lasto_net_param_count(lasto_net n, long long* count);
+lasto_status lasto_net_get_params(lasto_net n, float* host, long long count);
+lasto_status lasto_net_set_params(lasto_net n, const float* host, long long count);
+/* gradients of the last lasto_net_backward, same layout */
+lasto_status lasto_net_get_grads(lasto_net n, float* host, long long count);
+
+/*
+ * Net input features from a source and a potential on grid g (whose finest
+ * level must match the net's grid): x = device [nz][ny][nx][8] BF16 (bit
+ * patterns as uint16), channels rho * rho_scale, log(m_x / h_ref),
+ * log(m_y / h_ref), log(m_z / h_ref), v * pot_scale, face indicator, 0, 0.
+ */
+lasto_status lasto_net_features(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x);
+/* y = device [nz][ny][nx] FP32: the net's output for features x */
+lasto_status lasto_net_forward(lasto_net n, const uint16_t* x, float* y);
+/* After lasto_net_forward(x): gradients of L = sum_v weight[v] (y[v] - target[v])^2
+ * (target, weight device FP32 [nz][ny][nx]); *loss (host, may be NULL) = L. */
+lasto_status lasto_net_backward(lasto_net n, const uint16_t* x, const float* target, const float* weight,
+                                double* loss);
+/* one Adam step (beta 0.9, 0.999, eps 1e-8) with the last gradients */
+lasto_status lasto_net_adam_step(lasto_net n, float lr);
+/* forward + backward + Adam */
+lasto_status lasto_net_train_step(lasto_net n, const uint16_t* x, const float* target, const float* weight,
+                                  float lr, double* loss);
+
+/*
+ * Learned initial guess: v holds the Dirichlet data on its faces and an
+ * initial guess inside (for instance lasto_analytic_guess). Two candidates
+ * are formed: v and v + out_scale * net(features(rho, v)); each gets one
+ * red-black sweep of eq. (3.2)'s discrete form (red, then black; faces kept),
+ * and the one with the smaller relative residual
+ * ||4 pi rho - A v||_W / ||4 pi rho - A v_bc||_W is returned in v.
+ *   rel: host [2] or NULL: that residual for the plain and the learned candidate.
+ *   accepted: host, may be NULL: 1 if the learned candidate was kept.
+ * Uses the grid's solver scratch (not to be called during a solve on the same grid).
+ * Errors: LASTO_ERR_ARG (grid and net sizes differ), LASTO_ERR_HIP.
+ */
+lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
+                                 int* accepted);
 
 #ifdef __cplusplus
 }

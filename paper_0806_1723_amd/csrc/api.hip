@@ -167,25 +167,26 @@ extern "C" lasto_status lasto_mesh_graded_1d(double lo, double hi, int n, const 
     return LASTO_OK;
 }
 
-extern "C" lasto_status lasto_pseudo_density(lasto_grid g, int n_atoms, const lasto_atom* atoms,
-                                             const double* rho_interstitial, int renormalize, double* rho_out,
-                                             double* moments_out)
+// Validate an atom table, copy it to the grid's staging buffer and derive the
+// per-atom constants on the device (k_atom_prep). The staging buffer is reused
+// by the next call, so callers finish their kernels before returning.
+static lasto_status stage_atoms(lasto_grid g, int n_atoms, const lasto_atom* atoms, int renormalize, const char* who,
+                                AtomDev** out)
 {
-    if (!g || !rho_out || n_atoms < 0 || (n_atoms > 0 && !atoms))
-        return fail(LASTO_ERR_ARG, "lasto_pseudo_density: NULL argument");
     std::vector<AtomDev> hv((size_t)std::max(n_atoms, 1));
+    const std::string w(who);
     for (int a = 0; a < n_atoms; ++a) {
         const lasto_atom& A = atoms[a];
         AtomDev& D = hv[a];
         std::memset(&D, 0, sizeof(D));
-        if (A.kind != 0 && A.kind != 1) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: kind must be 0 or 1");
-        if (A.lmax < 0 || A.lmax > 4) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: lmax must be 0..4");
-        if (A.kind == 0 && !(A.width > 0.0)) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: width must be > 0");
-        if (A.kind == 1 && !(A.radius > 0.0)) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: radius must be > 0");
-        if (A.lmax >= 1 && !(A.alpha > 0.0)) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: alpha must be > 0");
+        if (A.kind != 0 && A.kind != 1) return fail(LASTO_ERR_ARG, w + ": kind must be 0 or 1");
+        if (A.lmax < 0 || A.lmax > 4) return fail(LASTO_ERR_ARG, w + ": lmax must be 0..4");
+        if (A.kind == 0 && !(A.width > 0.0)) return fail(LASTO_ERR_ARG, w + ": width must be > 0");
+        if (A.kind == 1 && !(A.radius > 0.0)) return fail(LASTO_ERR_ARG, w + ": radius must be > 0");
+        if (A.lmax >= 1 && !(A.alpha > 0.0)) return fail(LASTO_ERR_ARG, w + ": alpha must be > 0");
         double chk = A.q + A.width + A.radius + A.alpha + A.rho_R + A.drho_R + A.center[0] + A.center[1] + A.center[2];
         for (int c = 0; c < 24; ++c) chk += A.clm[c];
-        if (!std::isfinite(chk)) return fail(LASTO_ERR_ARG, "lasto_pseudo_density: non-finite atom data");
+        if (!std::isfinite(chk)) return fail(LASTO_ERR_ARG, w + ": non-finite atom data");
         for (int d = 0; d < 3; ++d) D.c[d] = A.center[d];
         D.R = A.radius;
         D.q = A.q;
@@ -208,12 +209,36 @@ extern "C" lasto_status lasto_pseudo_density(lasto_grid g, int n_atoms, const la
     AtomDev* dat = (AtomDev*)g->stage;
     LASTO_HIP(hipMemcpyAsync(dat, hv.data(), bytes, hipMemcpyHostToDevice, g->stream));
     if (n_atoms > 0) LASTO_HIP(launch_atom_prep(g, dat, n_atoms, renormalize));
+    *out = dat;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_pseudo_density(lasto_grid g, int n_atoms, const lasto_atom* atoms,
+                                             const double* rho_interstitial, int renormalize, double* rho_out,
+                                             double* moments_out)
+{
+    if (!g || !rho_out || n_atoms < 0 || (n_atoms > 0 && !atoms))
+        return fail(LASTO_ERR_ARG, "lasto_pseudo_density: NULL argument");
+    AtomDev* dat = nullptr;
+    if (lasto_status st = stage_atoms(g, n_atoms, atoms, renormalize, "lasto_pseudo_density", &dat); st != LASTO_OK)
+        return st;
     LASTO_HIP(launch_pseudo(g, dat, n_atoms, rho_interstitial, rho_out));
     if (moments_out) {
         LASTO_HIP(launch_moments(g, rho_out, g->moments));
         LASTO_HIP(hipMemcpyAsync(moments_out, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, g->stream));
     }
     // the staging buffer is reused by the next call: finish before returning
+    LASTO_HIP(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_analytic_guess(lasto_grid g, int n_atoms, const lasto_atom* atoms, double* v)
+{
+    if (!g || !v || n_atoms < 0 || (n_atoms > 0 && !atoms))
+        return fail(LASTO_ERR_ARG, "lasto_analytic_guess: NULL argument");
+    AtomDev* dat = nullptr;
+    if (lasto_status st = stage_atoms(g, n_atoms, atoms, 1, "lasto_analytic_guess", &dat); st != LASTO_OK) return st;
+    LASTO_HIP(launch_guess(g, dat, n_atoms, v));
     LASTO_HIP(hipStreamSynchronize(g->stream));
     return LASTO_OK;
 }

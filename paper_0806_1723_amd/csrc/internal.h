@@ -280,6 +280,13 @@ hipError_t launch_atom_prep(lasto_grid g, AtomDev* atoms, int n_atoms, int renor
 hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const double* rho_inter, double* rho);
 hipError_t launch_moments(lasto_grid g, const double* rho, double* Q);
 hipError_t launch_bc(lasto_grid g, int mode, const double* Q, int lmax_bc, double* v);
+hipError_t launch_guess(lasto_grid g, const AtomDev* atoms, int n_atoms, double* v);
+// v (natural, interior) += s * y (FP32, natural)
+hipError_t launch_add_f32_nat(const LevelView& L, double* v, const float* y, double s, hipStream_t st);
+// learned guess: features of (rho, v) and the net's forward pass on the grid's
+// stream; *y is the net's output buffer (finest-level nodes, FP32)
+lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, const double* v, const float** y,
+                               double* out_scale);
 hipError_t launch_interp(lasto_grid g, const double* v, const double* pts, int npts, double* out);
 
 // device table block builder

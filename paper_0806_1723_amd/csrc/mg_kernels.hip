@@ -736,6 +736,24 @@ hipError_t launch_add_nat(const LevelView& L, double* v, const double* e_split, 
     return hipGetLastError();
 }
 
+// v (natural) += s * y (FP32, natural), interior
+__global__ __launch_bounds__(PT_NT) void k_add_f32_nat(LevelView L, int kp, double* __restrict__ v,
+                                                       const float* __restrict__ y, double s)
+{
+    INTERIOR_LOOP
+    {
+        if (!inside) continue;
+        const size_t at = ((size_t)k * L.ny + j) * L.nx + i;
+        v[at] += s * (double)y[at];
+    }
+}
+
+hipError_t launch_add_f32_nat(const LevelView& L, double* v, const float* y, double s, hipStream_t st)
+{
+    PT_LAUNCH(k_add_f32_nat, L, st, v, y, s);
+    return hipGetLastError();
+}
+
 // r32 = r / sqrt(scal[i_norm2]) (scaled FP32 copy of the FP64 residual, split)
 __global__ __launch_bounds__(PT_NT) void k_scale_to32(LevelView L, int kp, const double* __restrict__ r,
                                                       float* __restrict__ r32, const double* __restrict__ scal,

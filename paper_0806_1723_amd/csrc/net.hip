@@ -1,0 +1,531 @@
+// Network runtime of the learned initial guess and coarse correction: a
+// four-level 3-D U-Net on a node grid's index space (the paper has no learned
+// part; this is the learned form grown beside the multigrid solver).
+//
+//   e0 = relu(conv(x))            level 0, c0 channels (x: 8 input features)
+//   e1 = relu(conv_s2(e0))        level 1, c1
+//   e2 = relu(conv_s2(e1))        level 2, c2
+//   e3 = relu(conv_s2(e2))        level 3, c3
+//   m3 = relu(conv(e3))           level 3, c3
+//   d2 = relu(conv(m3)); u2 = up(d2) + e2     level 2, c2
+//   d1 = relu(conv(u2)); u1 = up(d1) + e1     level 1, c1
+//   d0 = relu(conv(u1)); u0 = up(d0) + e0     level 0, c0
+//   y  = w . u0 + b               level 0, one FP32 value per node
+//
+// Level l + 1 has (n + 1) / 2 nodes per axis; conv is 3x3x3 with zero
+// padding; conv_s2 samples every other node; up is linear in index space.
+// Parameters live as FP32 masters in one flat vector (per convolution
+// W[27][cin][cout] then b[cout]; then the head w[c0], b); Adam updates them and
+// re-packs the BF16 copies the matrix-core kernels read.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "net_internal.h"
+
+using namespace lasto::net;
+
+namespace {
+
+constexpr int kSplits = 64;     // node shares of the weight-gradient reductions
+constexpr int kInFeatures = 8;  // padded input channels
+
+struct Layer {
+    int cin, cout, mode;   // forward mode CONV_SAME / CONV_DOWN
+    int lin, lout;         // input and output levels
+    int kpad, kpad_adj, cin_rows;
+    size_t w_off, b_off;   // in the parameter vector
+    uint16_t* wp = nullptr;   // packed forward weights [cout][kpad]
+    uint16_t* wa = nullptr;   // packed adjoint weights [cin_rows][kpad_adj] (not for layer 0)
+};
+
+uint64_t splitmix64(uint64_t& s)
+{
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// standard normal deviates by the Box-Muller transform of two uniforms
+double normal(uint64_t& s)
+{
+    const double u1 = ((splitmix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((splitmix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * lasto::kPi * u2);
+}
+
+}  // namespace
+
+struct lasto_net_s {
+    lasto_net_config cfg;
+    hipStream_t stream = nullptr;
+    int dim[4][3];
+    long nvox[4];
+    int c[4];
+    std::vector<Layer> layers;   // 8 convolutions
+    size_t nparam = 0, head_off = 0;
+    float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    // activations (BF16 channels-last)
+    uint16_t *e[4] = {}, *m3 = nullptr, *d[3] = {}, *u[3] = {};
+    // gradients
+    uint16_t *du[3] = {}, *gg[8] = {};
+    float* y = nullptr;
+    uint16_t* xin = nullptr;   // features for the learned guess (allocated on first use)
+    float* part = nullptr;
+    size_t part_n = 0;
+    float* dwt = nullptr;   // [cout][kpad] of the largest layer
+    double* lossp = nullptr;
+    float* hpart = nullptr;
+    int step = 0;
+    bool fwd_done = false;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+lasto_status net_fail(lasto_status s, const std::string& msg) { return lasto::fail(s, msg); }
+
+#define NCHK(expr)                                                                                      \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return net_fail(LASTO_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+lasto_status nalloc(lasto_net n, T** p, size_t count)
+{
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
+        return net_fail(LASTO_ERR_ALLOC, "lasto_net: device allocation failed");
+    n->allocs.push_back(q);
+    *p = (T*)q;
+    return LASTO_OK;
+}
+
+ConvGeom fwd_geom(const lasto_net_s* n, const Layer& L)
+{
+    ConvGeom g;
+    g.nx = n->dim[L.lout][0];
+    g.ny = n->dim[L.lout][1];
+    g.nz = n->dim[L.lout][2];
+    g.ix = n->dim[L.lin][0];
+    g.iy = n->dim[L.lin][1];
+    g.iz = n->dim[L.lin][2];
+    g.cin = L.cin;
+    g.cout = L.cout;
+    g.kpad = L.kpad;
+    g.mode = L.mode;
+    return g;
+}
+
+// the adjoint launch: gradient of the layer's output (lout, cout channels) to
+// its input (lin, cin channels)
+ConvGeom adj_geom(const lasto_net_s* n, const Layer& L)
+{
+    ConvGeom g;
+    g.nx = n->dim[L.lin][0];
+    g.ny = n->dim[L.lin][1];
+    g.nz = n->dim[L.lin][2];
+    g.ix = n->dim[L.lout][0];
+    g.iy = n->dim[L.lout][1];
+    g.iz = n->dim[L.lout][2];
+    g.cin = L.cout;
+    g.cout = L.cin;
+    g.kpad = L.kpad_adj;
+    g.mode = L.mode == CONV_SAME ? CONV_ADJ : CONV_ADJD;
+    return g;
+}
+
+lasto_status pack_all(lasto_net n)
+{
+    for (size_t i = 0; i < n->layers.size(); ++i) {
+        const Layer& L = n->layers[i];
+        NCHK(launch_pack_weights(n->w + L.w_off, L.cin, L.cout, L.wp, L.kpad, L.wa, L.kpad_adj, L.cin_rows, n->stream));
+    }
+    return LASTO_OK;
+}
+
+void free_net(lasto_net n)
+{
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    for (void* p : n->allocs) (void)hipFree(p);
+    delete n;
+}
+
+// weight and bias gradients of layer i from its input activation and the
+// gradient of its (pre-ReLU) output, into the gradient vector
+lasto_status layer_grads(lasto_net n, int i, const uint16_t* in, const uint16_t* gout)
+{
+    const Layer& L = n->layers[i];
+    const ConvGeom g = fwd_geom(n, L);
+    NCHK(launch_conv_wgrad(g, in, gout, n->part, kSplits, n->stream));
+    NCHK(launch_sum_splits(n->part, kSplits, (long)L.cout * L.kpad, n->dwt, 0, n->stream));
+    NCHK(launch_unpack_wgrad(n->dwt, L.cin, L.cout, L.kpad, n->g + L.w_off, n->stream));
+    NCHK(launch_chan_sum(gout, n->nvox[L.lout], L.cout, n->part, kSplits, n->stream));
+    NCHK(launch_sum_splits(n->part, kSplits, L.cout, n->g + L.b_off, 0, n->stream));
+    return LASTO_OK;
+}
+
+}  // namespace
+
+extern "C" lasto_status lasto_net_create(const lasto_net_config* cfg, void* hip_stream, lasto_net* out)
+{
+    if (!cfg || !out) return net_fail(LASTO_ERR_ARG, "lasto_net_create: NULL argument");
+    *out = nullptr;
+    for (int d = 0; d < 3; ++d)
+        if ((&cfg->nx)[d] < 8) return net_fail(LASTO_ERR_ARG, "lasto_net_create: each axis needs >= 8 nodes");
+    for (int l = 0; l < 4; ++l)
+        if (cfg->ch[l] < 16 || cfg->ch[l] > 64 || cfg->ch[l] % 16)
+            return net_fail(LASTO_ERR_ARG, "lasto_net_create: channels must be 16, 32, 48 or 64");
+    if (cfg->ch[0] > 16) return net_fail(LASTO_ERR_ARG, "lasto_net_create: level-0 channels must be 16");
+    if (!(cfg->rho_scale > 0.0) || !(cfg->pot_scale > 0.0) || !(cfg->h_ref > 0.0) || !(cfg->out_scale > 0.0))
+        return net_fail(LASTO_ERR_ARG, "lasto_net_create: scales must be > 0");
+    lasto_net n = new lasto_net_s();
+    n->cfg = *cfg;
+    n->stream = (hipStream_t)hip_stream;
+    int nn[3] = {cfg->nx, cfg->ny, cfg->nz};
+    for (int l = 0; l < 4; ++l) {
+        for (int d = 0; d < 3; ++d) {
+            n->dim[l][d] = nn[d];
+            nn[d] = (nn[d] + 1) / 2;
+        }
+        n->nvox[l] = (long)n->dim[l][0] * n->dim[l][1] * n->dim[l][2];
+        n->c[l] = cfg->ch[l];
+    }
+    const int* c = n->c;
+    // (cin, cout, mode, lin, lout)
+    const int spec[8][5] = {{kInFeatures, c[0], CONV_SAME, 0, 0}, {c[0], c[1], CONV_DOWN, 0, 1},
+                            {c[1], c[2], CONV_DOWN, 1, 2},       {c[2], c[3], CONV_DOWN, 2, 3},
+                            {c[3], c[3], CONV_SAME, 3, 3},       {c[3], c[2], CONV_SAME, 3, 3},
+                            {c[2], c[1], CONV_SAME, 2, 2},       {c[1], c[0], CONV_SAME, 1, 1}};
+    size_t off = 0, max_part = 0, max_dwt = 0;
+    for (int i = 0; i < 8; ++i) {
+        Layer L;
+        L.cin = spec[i][0];
+        L.cout = spec[i][1];
+        L.mode = spec[i][2];
+        L.lin = spec[i][3];
+        L.lout = spec[i][4];
+        L.kpad = kpad_of(L.cin);
+        L.kpad_adj = kpad_of(L.cout);
+        L.cin_rows = (L.cin + 15) / 16 * 16;
+        L.w_off = off;
+        off += 27 * (size_t)L.cin * L.cout;
+        L.b_off = off;
+        off += L.cout;
+        max_part = std::max(max_part, (size_t)kSplits * L.cout * L.kpad);
+        max_dwt = std::max(max_dwt, (size_t)L.cout * L.kpad);
+        n->layers.push_back(L);
+    }
+    n->head_off = off;
+    off += c[0] + 1;
+    n->nparam = off;
+    lasto_status st = LASTO_OK;
+    auto A = [&](auto** p, size_t cnt) {
+        if (st == LASTO_OK) st = nalloc(n, p, cnt);
+    };
+    A(&n->w, n->nparam);
+    A(&n->m, n->nparam);
+    A(&n->v, n->nparam);
+    A(&n->g, n->nparam);
+    for (Layer& L : n->layers) {
+        A(&L.wp, (size_t)L.cout * L.kpad);
+        if (&L != &n->layers[0]) A(&L.wa, (size_t)L.cin_rows * L.kpad_adj);
+    }
+    for (int l = 0; l < 4; ++l) A(&n->e[l], n->nvox[l] * c[l]);
+    A(&n->m3, n->nvox[3] * c[3]);
+    for (int l = 0; l < 3; ++l) {
+        A(&n->d[l], n->nvox[l + 1] * c[l]);   // d_l lives on level l + 1 with c_l channels
+        A(&n->u[l], n->nvox[l] * c[l]);
+        A(&n->du[l], n->nvox[l] * c[l]);
+    }
+    // per-layer output gradients (pre-ReLU), on the layer's output level
+    for (int i = 0; i < 8; ++i) A(&n->gg[i], n->nvox[n->layers[i].lout] * n->layers[i].cout);
+    A(&n->y, n->nvox[0]);
+    A(&n->part, std::max(max_part, (size_t)kSplits * 64));
+    A(&n->dwt, max_dwt);
+    A(&n->lossp, kSplits);
+    A(&n->hpart, (size_t)kSplits * (c[0] + 1));
+    if (st != LASTO_OK) {
+        free_net(n);
+        return st;
+    }
+    n->part_n = max_part;
+    // He-normal convolution weights, zero biases, a small head
+    std::vector<float> h(n->nparam, 0.0f);
+    uint64_t s = cfg->seed;
+    for (const Layer& L : n->layers) {
+        const double sd = std::sqrt(2.0 / (27.0 * L.cin));
+        for (size_t e = 0; e < 27 * (size_t)L.cin * L.cout; ++e) h[L.w_off + e] = (float)(sd * normal(s));
+    }
+    for (int q = 0; q < c[0]; ++q) h[n->head_off + q] = (float)(0.01 * normal(s));
+    if (hipMemcpy(n->w, h.data(), sizeof(float) * n->nparam, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(n->m, 0, sizeof(float) * n->nparam) != hipSuccess ||
+        hipMemset(n->v, 0, sizeof(float) * n->nparam) != hipSuccess ||
+        hipMemset(n->g, 0, sizeof(float) * n->nparam) != hipSuccess) {
+        free_net(n);
+        return net_fail(LASTO_ERR_HIP, "lasto_net_create: initial upload failed");
+    }
+    st = pack_all(n);
+    if (st == LASTO_OK && hipStreamSynchronize(n->stream) != hipSuccess) st = net_fail(LASTO_ERR_HIP, "lasto_net_create: sync");
+    if (st != LASTO_OK) {
+        free_net(n);
+        return st;
+    }
+    *out = n;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_destroy(lasto_net n)
+{
+    if (!n) return net_fail(LASTO_ERR_ARG, "lasto_net_destroy: NULL net");
+    free_net(n);
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_param_count(lasto_net n, long long* count)
+{
+    if (!n || !count) return net_fail(LASTO_ERR_ARG, "lasto_net_param_count: NULL argument");
+    *count = (long long)n->nparam;
+    return LASTO_OK;
+}
+
+static lasto_status copy_vec(lasto_net n, float* dev, float* host, long long count, bool to_host, const char* who)
+{
+    if (!n || !host) return net_fail(LASTO_ERR_ARG, std::string(who) + ": NULL argument");
+    if (count != (long long)n->nparam) return net_fail(LASTO_ERR_ARG, std::string(who) + ": count != parameter count");
+    NCHK(hipStreamSynchronize(n->stream));
+    if (to_host) NCHK(hipMemcpy(host, dev, sizeof(float) * n->nparam, hipMemcpyDeviceToHost));
+    else NCHK(hipMemcpy(dev, host, sizeof(float) * n->nparam, hipMemcpyHostToDevice));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_get_params(lasto_net n, float* host, long long count)
+{
+    return copy_vec(n, n ? n->w : nullptr, host, count, true, "lasto_net_get_params");
+}
+
+extern "C" lasto_status lasto_net_set_params(lasto_net n, const float* host, long long count)
+{
+    lasto_status st = copy_vec(n, n ? n->w : nullptr, const_cast<float*>(host), count, false, "lasto_net_set_params");
+    if (st != LASTO_OK) return st;
+    st = pack_all(n);
+    if (st != LASTO_OK) return st;
+    NCHK(hipStreamSynchronize(n->stream));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_get_grads(lasto_net n, float* host, long long count)
+{
+    return copy_vec(n, n ? n->g : nullptr, host, count, true, "lasto_net_get_grads");
+}
+
+namespace lasto {
+
+// forward pass on the net's stream; y (device, nvox[0] FP32) receives the output
+lasto_status net_forward_async(lasto_net n, const uint16_t* x, float* y)
+{
+    const int* c = n->c;
+    auto conv = [&](int i, const uint16_t* in, uint16_t* out) -> hipError_t {
+        const Layer& L = n->layers[i];
+        ConvEpilogue ep;
+        ep.bias = n->w + L.b_off;
+        ep.relu = 1;
+        ep.out_bf16 = out;
+        return launch_conv(fwd_geom(n, L), in, L.wp, ep, n->stream);
+    };
+    NCHK(conv(0, x, n->e[0]));
+    NCHK(conv(1, n->e[0], n->e[1]));
+    NCHK(conv(2, n->e[1], n->e[2]));
+    NCHK(conv(3, n->e[2], n->e[3]));
+    NCHK(conv(4, n->e[3], n->m3));
+    NCHK(conv(5, n->m3, n->d[2]));
+    const int* D = &n->dim[0][0];
+    NCHK(launch_upsample_add(n->d[2], D[9], D[10], D[11], n->e[2], n->u[2], D[6], D[7], D[8], c[2], n->stream));
+    NCHK(conv(6, n->u[2], n->d[1]));
+    NCHK(launch_upsample_add(n->d[1], D[6], D[7], D[8], n->e[1], n->u[1], D[3], D[4], D[5], c[1], n->stream));
+    NCHK(conv(7, n->u[1], n->d[0]));
+    NCHK(launch_upsample_add(n->d[0], D[3], D[4], D[5], n->e[0], n->u[0], D[0], D[1], D[2], c[0], n->stream));
+    NCHK(launch_head(n->u[0], n->nvox[0], c[0], n->w + n->head_off, y ? y : n->y, n->stream));
+    n->fwd_done = true;
+    return LASTO_OK;
+}
+
+// Input features of the net at every node of the grid's finest level
+// (channels-last BF16, 8 per node):
+//   0: rho * rho_scale
+//   1..3: log(m_d / h_ref), m_d the dual width along axis d
+//   4: v * pot_scale (an initial guess inside, the Dirichlet data on faces)
+//   5: 1 on faces, 0 inside;  6, 7: 0
+__global__ void k_features(LevelView L, const double* __restrict__ rho, const double* __restrict__ v, double s_rho,
+                           double s_pot, double h_ref, uint16_t* __restrict__ x)
+{
+    const long n = (long)L.nx * L.ny * L.nz;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % L.nx), j = (int)((e / L.nx) % L.ny), k = (int)(e / ((long)L.nx * L.ny));
+        const bool face = i == 0 || j == 0 || k == 0 || i == L.nx - 1 || j == L.ny - 1 || k == L.nz - 1;
+        uint16_t* o = x + (size_t)e * 8;
+        o[0] = f2bf((float)(rho[e] * s_rho));
+        o[1] = f2bf((float)log(L.ax[0].m[i] / h_ref));
+        o[2] = f2bf((float)log(L.ax[1].m[j] / h_ref));
+        o[3] = f2bf((float)log(L.ax[2].m[k] / h_ref));
+        o[4] = f2bf((float)(v[e] * s_pot));
+        o[5] = f2bf(face ? 1.0f : 0.0f);
+        o[6] = 0;
+        o[7] = 0;
+    }
+}
+
+lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x)
+{
+    const LevelView& L = g->lev[0].view;
+    if (L.nx != n->dim[0][0] || L.ny != n->dim[0][1] || L.nz != n->dim[0][2])
+        return fail(LASTO_ERR_ARG, "lasto_net: the net's grid does not match the grid's finest level");
+    const long nv = (long)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)std::min<long>((nv + 255) / 256, 16384)), dim3(256), 0, g->stream, L,
+                       rho, v, n->cfg.rho_scale, n->cfg.pot_scale, n->cfg.h_ref, x);
+    NCHK(hipGetLastError());
+    return LASTO_OK;
+}
+
+// features and forward pass on the grid's stream (the net's own stream is
+// synchronised first); *y receives the net's output buffer
+lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, const double* v, const float** y,
+                               double* out_scale)
+{
+    if (!n->xin) {
+        if (lasto_status st = nalloc(n, &n->xin, (size_t)n->nvox[0] * kInFeatures); st != LASTO_OK) return st;
+    }
+    NCHK(hipStreamSynchronize(n->stream));
+    if (lasto_status st = net_features_async(g, n, rho, v, n->xin); st != LASTO_OK) return st;
+    hipStream_t keep = n->stream;
+    n->stream = g->stream;
+    lasto_status st = net_forward_async(n, n->xin, n->y);
+    n->stream = keep;
+    if (st != LASTO_OK) return st;
+    *y = n->y;
+    *out_scale = n->cfg.out_scale;
+    return LASTO_OK;
+}
+
+}  // namespace lasto
+
+extern "C" lasto_status lasto_net_features(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x)
+{
+    if (!g || !n || !rho || !v || !x) return net_fail(LASTO_ERR_ARG, "lasto_net_features: NULL argument");
+    if (lasto_status st = lasto::net_features_async(g, n, rho, v, x); st != LASTO_OK) return st;
+    NCHK(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_forward(lasto_net n, const uint16_t* x, float* y)
+{
+    if (!n || !x || !y) return net_fail(LASTO_ERR_ARG, "lasto_net_forward: NULL argument");
+    lasto_status st = lasto::net_forward_async(n, x, y);
+    if (st != LASTO_OK) return st;
+    NCHK(hipMemcpyAsync(n->y, y, sizeof(float) * n->nvox[0], hipMemcpyDeviceToDevice, n->stream));
+    NCHK(hipStreamSynchronize(n->stream));
+    return LASTO_OK;
+}
+
+// gradients of sum_v weight[v] (y[v] - target[v])^2 for the last forward
+// input; *loss receives that sum
+extern "C" lasto_status lasto_net_backward(lasto_net n, const uint16_t* x, const float* target, const float* weight,
+                                           double* loss)
+{
+    if (!n || !x || !target || !weight) return net_fail(LASTO_ERR_ARG, "lasto_net_backward: NULL argument");
+    if (!n->fwd_done) return net_fail(LASTO_ERR_STATE, "lasto_net_backward: no forward pass to differentiate");
+    const int* c = n->c;
+    const int* D = &n->dim[0][0];
+    hipStream_t s = n->stream;
+    // head: loss, du0 = dL/du0, head-weight gradient
+    NCHK(launch_head_loss_bwd(n->u[0], n->nvox[0], c[0], n->w + n->head_off, n->y, target, weight, n->du[0], n->lossp,
+                              n->hpart, kSplits, s));
+    NCHK(launch_sum_splits(n->hpart, kSplits, c[0] + 1, n->g + n->head_off, 0, s));
+    // u0 = up(d0) + e0: layer 7's output gradient is up^T(du0), masked by its ReLU
+    NCHK(launch_upsample_adj(n->du[0], D[0], D[1], D[2], n->gg[7], D[3], D[4], D[5], c[0], n->d[0], s));
+    if (lasto_status e = layer_grads(n, 7, n->u[1], n->gg[7]); e != LASTO_OK) return e;
+    {
+        ConvEpilogue ep;
+        ep.out_bf16 = n->du[1];
+        NCHK(launch_conv(adj_geom(n, n->layers[7]), n->gg[7], n->layers[7].wa, ep, s));
+    }
+    NCHK(launch_upsample_adj(n->du[1], D[3], D[4], D[5], n->gg[6], D[6], D[7], D[8], c[1], n->d[1], s));
+    if (lasto_status e = layer_grads(n, 6, n->u[2], n->gg[6]); e != LASTO_OK) return e;
+    {
+        ConvEpilogue ep;
+        ep.out_bf16 = n->du[2];
+        NCHK(launch_conv(adj_geom(n, n->layers[6]), n->gg[6], n->layers[6].wa, ep, s));
+    }
+    NCHK(launch_upsample_adj(n->du[2], D[6], D[7], D[8], n->gg[5], D[9], D[10], D[11], c[2], n->d[2], s));
+    if (lasto_status e = layer_grads(n, 5, n->m3, n->gg[5]); e != LASTO_OK) return e;
+    {
+        ConvEpilogue ep;   // through layer 5 to m3, masked by m3's ReLU
+        ep.mask = n->m3;
+        ep.out_bf16 = n->gg[4];
+        NCHK(launch_conv(adj_geom(n, n->layers[5]), n->gg[5], n->layers[5].wa, ep, s));
+    }
+    if (lasto_status e = layer_grads(n, 4, n->e[3], n->gg[4]); e != LASTO_OK) return e;
+    {
+        ConvEpilogue ep;   // to e3
+        ep.mask = n->e[3];
+        ep.out_bf16 = n->gg[3];
+        NCHK(launch_conv(adj_geom(n, n->layers[4]), n->gg[4], n->layers[4].wa, ep, s));
+    }
+    if (lasto_status e = layer_grads(n, 3, n->e[2], n->gg[3]); e != LASTO_OK) return e;
+    {
+        ConvEpilogue ep;   // to e2: through the stride-2 layer 3 plus the skip into u2
+        ep.addend = n->du[2];
+        ep.mask = n->e[2];
+        ep.out_bf16 = n->gg[2];
+        NCHK(launch_conv(adj_geom(n, n->layers[3]), n->gg[3], n->layers[3].wa, ep, s));
+    }
+    if (lasto_status e = layer_grads(n, 2, n->e[1], n->gg[2]); e != LASTO_OK) return e;
+    {
+        ConvEpilogue ep;
+        ep.addend = n->du[1];
+        ep.mask = n->e[1];
+        ep.out_bf16 = n->gg[1];
+        NCHK(launch_conv(adj_geom(n, n->layers[2]), n->gg[2], n->layers[2].wa, ep, s));
+    }
+    if (lasto_status e = layer_grads(n, 1, n->e[0], n->gg[1]); e != LASTO_OK) return e;
+    {
+        ConvEpilogue ep;
+        ep.addend = n->du[0];
+        ep.mask = n->e[0];
+        ep.out_bf16 = n->gg[0];
+        NCHK(launch_conv(adj_geom(n, n->layers[1]), n->gg[1], n->layers[1].wa, ep, s));
+    }
+    if (lasto_status e = layer_grads(n, 0, x, n->gg[0]); e != LASTO_OK) return e;
+    std::vector<double> lp(kSplits);
+    NCHK(hipMemcpyAsync(lp.data(), n->lossp, sizeof(double) * kSplits, hipMemcpyDeviceToHost, s));
+    NCHK(hipStreamSynchronize(s));
+    double l = 0.0;
+    for (double q : lp) l += q;
+    if (loss) *loss = l;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_adam_step(lasto_net n, float lr)
+{
+    if (!n || !(lr > 0.0f)) return net_fail(LASTO_ERR_ARG, "lasto_net_adam_step: NULL net or lr <= 0");
+    n->step++;
+    NCHK(launch_adam(n->w, n->m, n->v, n->g, (long)n->nparam, lr, n->step, n->stream));
+    if (lasto_status e = pack_all(n); e != LASTO_OK) return e;
+    NCHK(hipStreamSynchronize(n->stream));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_train_step(lasto_net n, const uint16_t* x, const float* target, const float* weight,
+                                             float lr, double* loss)
+{
+    if (!n || !x) return net_fail(LASTO_ERR_ARG, "lasto_net_train_step: NULL argument");
+    lasto_status st = lasto::net_forward_async(n, x, n->y);
+    if (st != LASTO_OK) return st;
+    st = lasto_net_backward(n, x, target, weight, loss);
+    if (st != LASTO_OK) return st;
+    return lasto_net_adam_step(n, lr);
+}

@@ -380,6 +380,89 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     return LASTO_OK;
 }
 
+extern "C" lasto_status lasto_boundary_values(lasto_grid g, const double* rho, int bc, int lmax_bc, double* v,
+                                              double* moments_out)
+{
+    if (!g || !v || (bc == 1 && !rho)) return fail(LASTO_ERR_ARG, "lasto_boundary_values: NULL argument");
+    if ((bc != 0 && bc != 1) || lmax_bc < 0 || lmax_bc > 4)
+        return fail(LASTO_ERR_ARG, "lasto_boundary_values: bc must be 0 or 1, lmax_bc 0..4");
+    if (bc == 1) {
+        HIPCHK(launch_moments(g, rho, g->moments));
+        HIPCHK(launch_bc(g, 1, g->moments, lmax_bc, v));
+        if (moments_out)
+            HIPCHK(hipMemcpyAsync(moments_out, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, g->stream));
+    } else {
+        HIPCHK(launch_bc(g, 0, g->moments, 0, v));
+    }
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}
+
+// ||4 pi rho - A v||_W (interior_zero: of the face data alone), squared, into slot
+static lasto_status resid_norm2(lasto_grid g, const double* rho, const double* v, int interior_zero, int slot)
+{
+    const LevelView& V = g->lev[0].view;
+    HIPCHK(launch_residual_nat(V, v, rho, 4.0 * kPi, nullptr, g->partials, interior_zero, g->stream));
+    return reduce_to(g, interior_blocks(V), slot);
+}
+
+// one red-black sweep on A v = 4 pi rho in place on natural v (faces kept),
+// through the split layout in the grid's z (iterate) and p[0] (source) vectors
+static lasto_status smooth_nat(lasto_grid g, const double* rho, double* v)
+{
+    const LevelView& V = g->lev[0].view;
+    HIPCHK(launch_nat_to_split(V, v, g->z, g->stream));
+    HIPCHK(launch_nat_to_split(V, rho, g->p[0], g->stream));
+    HIPCHK(launch_half_keep_faces<double>(V, g->z, g->p[0], 0, 4.0 * kPi, g->stream));
+    HIPCHK(launch_half_keep_faces<double>(V, g->z, g->p[0], 1, 4.0 * kPi, g->stream));
+    HIPCHK(launch_split_to_nat(V, g->z, v, g->stream));
+    return LASTO_OK;
+}
+
+// The learned guess is judged, like the guess it corrects, after one
+// red-black sweep: the sweep removes rough error at the grid scale, which a
+// multigrid cycle removes cheaply anyway, and leaves the smooth error that
+// decides how many cycles remain.
+extern "C" lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
+                                            int* accepted)
+{
+    if (!g || !n || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_learned_guess: NULL argument");
+    const LevelView& V = g->lev[0].view;
+    hipStream_t s = g->stream;
+    const size_t nn = (size_t)V.nx * V.ny * V.nz;
+    // natural-layout copies live in the grid's x and p[1] vectors
+    if (split_elems(V) < nn) return fail(LASTO_ERR_STATE, "lasto_learned_guess: scratch too small");
+    double* keep_guess = g->x;
+    double* keep_learned = g->p[1];
+    if (lasto_status e = resid_norm2(g, rho, v, 1, S_R0); e != LASTO_OK) return e;
+    HIPCHK(hipMemcpyAsync(keep_guess, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    const float* y = nullptr;
+    double out_scale = 0.0;
+    if (lasto_status e = net_guess_forward(g, n, rho, v, &y, &out_scale); e != LASTO_OK) return e;
+    HIPCHK(launch_add_f32_nat(V, v, y, out_scale, s));
+    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
+    if (lasto_status e = resid_norm2(g, rho, v, 0, S_TMP); e != LASTO_OK) return e;
+    HIPCHK(hipMemcpyAsync(keep_learned, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(v, keep_guess, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
+    if (lasto_status e = resid_norm2(g, rho, v, 0, S_RR); e != LASTO_OK) return e;
+    if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
+    const double r0 = std::sqrt(g->h_scalars[S_R0]);
+    const double plain = r0 > 0.0 ? std::sqrt(g->h_scalars[S_RR]) / r0 : 0.0;
+    const double learned = r0 > 0.0 ? std::sqrt(g->h_scalars[S_TMP]) / r0 : 0.0;
+    const bool keep = std::isfinite(learned) && learned < plain;
+    if (keep) HIPCHK(hipMemcpyAsync(v, keep_learned, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    // the solver's vectors must come back with zero faces and padding
+    for (double* a : {g->x, g->p[0], g->p[1], g->z}) HIPCHK(launch_fill_zero<double>(a, split_elems(V), s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (rel) {
+        rel[0] = plain;
+        rel[1] = learned;
+    }
+    if (accepted) *accepted = keep ? 1 : 0;
+    return LASTO_OK;
+}
+
 extern "C" lasto_status lasto_apply(lasto_grid g, const double* u, double* Au)
 {
     if (!g || !u || !Au || u == Au) return fail(LASTO_ERR_ARG, "lasto_apply: NULL or aliased buffers");
@@ -401,6 +484,9 @@ extern "C" lasto_status lasto_rb_sweep(lasto_grid g, const double* u_in, const d
     HIPCHK(launch_half_keep_faces<double>(V, g->z, g->q, first_colour, 4.0 * kPi, s));
     HIPCHK(launch_half_keep_faces<double>(V, g->z, g->q, 1 - first_colour, 4.0 * kPi, s));
     HIPCHK(launch_split_to_nat(V, g->z, u_out, s));
+    // the solver's vectors must come back with zero faces and padding
+    HIPCHK(launch_fill_zero<double>(g->z, split_elems(V), s));
+    HIPCHK(launch_fill_zero<double>(g->q, split_elems(V), s));
     HIPCHK(hipStreamSynchronize(g->stream));
     return LASTO_OK;
 }

@@ -259,6 +259,49 @@ hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------ analytic guess
+// Interior of v = the sum over atoms of the free-space potential of each
+// atom's monopole under Laplacian(V) = 4 pi rho (so a positive charge gives
+// V -> -q/r): kind 0 (Gaussian of width w) -q erf(r/w)/r, with the limit
+// -2 q / (sqrt(pi) w) at r = 0 and erf taken as 1 beyond 6w; kind 1 (the
+// quartic inside R) the uniform ball, -q (3R^2 - r^2)/(2R^3) inside and -q/r
+// outside. Faces are left as they are.
+__global__ __launch_bounds__(256) void k_guess(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
+                                               double* __restrict__ v)
+{
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int i = 1 + blockIdx.x * 64 + (threadIdx.x & 63), j = 1 + blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i > nx - 2 || j > ny - 2) return;
+    const double px = L.ax[0].x[i], py = L.ax[1].x[j];
+    for (int k = 1 + blockIdx.z * 4; k <= min(nz - 2, 4 + blockIdx.z * 4); ++k) {
+        const double pz = L.ax[2].x[k];
+        double acc = 0.0;
+        for (int a = 0; a < n_atoms; ++a) {
+            const AtomDev& A = atoms[a];
+            const double dx = px - A.c[0], dy = py - A.c[1], dz = pz - A.c[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double r = sqrt(r2);
+            if (A.kind == 0) {
+                if (r < 6.0 * A.w)
+                    acc -= r > 1e-12 * A.w ? A.q * erf(r / A.w) / r : 2.0 * A.q / (sqrt(kPi) * A.w);
+                else
+                    acc -= A.q / r;
+            } else {
+                acc -= r < A.R ? A.q * (3.0 * A.R * A.R - r2) / (2.0 * A.R * A.R * A.R) : A.q / r;
+            }
+        }
+        v[((size_t)k * ny + j) * nx + i] = acc;
+    }
+}
+
+hipError_t launch_guess(lasto_grid g, const AtomDev* atoms, int n_atoms, double* v)
+{
+    const LevelView& L = g->lev[0].view;
+    const dim3 grid((L.nx - 2 + 63) / 64, (L.ny - 2 + 3) / 4, (L.nz - 2 + 3) / 4);
+    hipLaunchKernelGGL(k_guess, grid, dim3(256), 0, g->stream, L, atoms, n_atoms, v);
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------------- moments
 constexpr int MO_NT = 256;
 

@@ -85,8 +85,25 @@ SYMBOLS = [
     "lasto_status_string", "lasto_last_error", "lasto_mesh_graded_1d", "lasto_grid_create",
     "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
     "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp", "lasto_apply",
-    "lasto_rb_sweep",
+    "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess", "lasto_net_create", "lasto_net_destroy",
+    "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
+    "lasto_net_features", "lasto_net_forward", "lasto_net_backward", "lasto_net_adam_step",
+    "lasto_net_train_step", "lasto_learned_guess",
 ]
+
+
+class NetConfig(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int),
+        ("ny", C.c_int),
+        ("nz", C.c_int),
+        ("ch", C.c_int * 4),
+        ("seed", C.c_ulonglong),
+        ("rho_scale", C.c_double),
+        ("pot_scale", C.c_double),
+        ("h_ref", C.c_double),
+        ("out_scale", C.c_double),
+    ]
 
 _lib = None
 
@@ -127,6 +144,31 @@ def load():
     L.lasto_apply.restype = i
     L.lasto_rb_sweep.argtypes = [P, P, P, P, i]
     L.lasto_rb_sweep.restype = i
+    L.lasto_boundary_values.argtypes = [P, P, i, i, P, P]
+    L.lasto_boundary_values.restype = i
+    L.lasto_analytic_guess.argtypes = [P, i, P, P]
+    L.lasto_analytic_guess.restype = i
+    L.lasto_net_create.argtypes = [C.POINTER(NetConfig), P, C.POINTER(P)]
+    L.lasto_net_create.restype = i
+    L.lasto_net_destroy.argtypes = [P]
+    L.lasto_net_destroy.restype = i
+    L.lasto_net_param_count.argtypes = [P, C.POINTER(C.c_longlong)]
+    L.lasto_net_param_count.restype = i
+    for name in ("lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads"):
+        getattr(L, name).argtypes = [P, P, C.c_longlong]
+        getattr(L, name).restype = i
+    L.lasto_net_features.argtypes = [P, P, P, P, P]
+    L.lasto_net_features.restype = i
+    L.lasto_net_forward.argtypes = [P, P, P]
+    L.lasto_net_forward.restype = i
+    L.lasto_net_backward.argtypes = [P, P, P, P, C.POINTER(d)]
+    L.lasto_net_backward.restype = i
+    L.lasto_net_adam_step.argtypes = [P, C.c_float]
+    L.lasto_net_adam_step.restype = i
+    L.lasto_net_train_step.argtypes = [P, P, P, P, C.c_float, C.POINTER(d)]
+    L.lasto_net_train_step.restype = i
+    L.lasto_learned_guess.argtypes = [P, P, P, P, P, C.POINTER(i)]
+    L.lasto_learned_guess.restype = i
     _lib = L
     return L
 
@@ -141,11 +183,12 @@ def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def _dev_ptr(t) -> int:
-    """Device pointer of a contiguous float64 CUDA/HIP tensor."""
+def _dev_ptr(t, dtype=None) -> int:
+    """Device pointer of a contiguous CUDA/HIP tensor (float64 unless dtype is given)."""
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError("expected a contiguous float64 device tensor")
+    dtype = dtype or torch.float64
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("expected a contiguous %s device tensor" % dtype)
     return t.data_ptr()
 
 
@@ -287,6 +330,105 @@ class Grid:
             u_out = u_in.clone()
         _check(load().lasto_rb_sweep(self.h, _dev_ptr(u_in), _dev_ptr(rho), _dev_ptr(u_out), first_colour))
         return u_out
+
+    def boundary_values(self, rho, v, bc: int = 1, lmax_bc: int = 4):
+        Q = np.zeros(25)
+        _check(load().lasto_boundary_values(self.h, _dev_ptr(rho), bc, lmax_bc, _dev_ptr(v), _np_ptr(Q)))
+        return Q
+
+    def analytic_guess(self, atoms, v):
+        arr = make_atoms(atoms)
+        _check(load().lasto_analytic_guess(self.h, len(atoms), C.cast(arr, C.c_void_p), _dev_ptr(v)))
+        return v
+
+    def learned_guess(self, net: "Net", rho, v):
+        rel = np.zeros(2)
+        acc = C.c_int()
+        _check(load().lasto_learned_guess(self.h, net.h, _dev_ptr(rho), _dev_ptr(v), _np_ptr(rel), C.byref(acc)))
+        return dict(rel_before=float(rel[0]), rel_after=float(rel[1]), accepted=bool(acc.value))
+
+
+class Net:
+    """The learned-guess U-Net (weights, Adam state and activations on the device)."""
+
+    def __init__(self, shape, ch=(16, 32, 48, 64), seed=1, rho_scale=0.1, pot_scale=0.01, h_ref=0.25,
+                 out_scale=1.0, stream=None):
+        import torch
+        nz, ny, nx = shape
+        cfg = NetConfig()
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        for k in range(4):
+            cfg.ch[k] = ch[k]
+        cfg.seed = seed
+        cfg.rho_scale, cfg.pot_scale, cfg.h_ref, cfg.out_scale = rho_scale, pot_scale, h_ref, out_scale
+        self.cfg = cfg
+        self.shape = (nz, ny, nx)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        h = C.c_void_p()
+        _check(load().lasto_net_create(C.byref(cfg), C.c_void_p(sp), C.byref(h)))
+        self.h = h
+        n = C.c_longlong()
+        _check(load().lasto_net_param_count(h, C.byref(n)))
+        self.nparam = n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lasto_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        a = np.zeros(self.nparam, dtype=np.float32)
+        _check(load().lasto_net_get_params(self.h, _np_ptr(a), self.nparam))
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        _check(load().lasto_net_set_params(self.h, _np_ptr(a), self.nparam))
+
+    def grads(self) -> np.ndarray:
+        a = np.zeros(self.nparam, dtype=np.float32)
+        _check(load().lasto_net_get_grads(self.h, _np_ptr(a), self.nparam))
+        return a
+
+    def features(self, grid: Grid, rho, v, x=None):
+        """BF16 features as an int16 tensor [nz, ny, nx, 8] (bit patterns)."""
+        import torch
+        if x is None:
+            x = torch.zeros(self.shape + (8,), dtype=torch.int16, device="cuda")
+        _check(load().lasto_net_features(grid.h, self.h, _dev_ptr(rho), _dev_ptr(v), _dev_ptr(x, torch.int16)))
+        return x
+
+    def forward(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.zeros(self.shape, dtype=torch.float32, device="cuda")
+        _check(load().lasto_net_forward(self.h, _dev_ptr(x, torch.int16), _dev_ptr(y, torch.float32)))
+        return y
+
+    def backward(self, x, target, weight) -> float:
+        import torch
+        loss = C.c_double()
+        _check(load().lasto_net_backward(self.h, _dev_ptr(x, torch.int16), _dev_ptr(target, torch.float32),
+                                         _dev_ptr(weight, torch.float32), C.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr: float):
+        _check(load().lasto_net_adam_step(self.h, lr))
+
+    def train_step(self, x, target, weight, lr: float) -> float:
+        import torch
+        loss = C.c_double()
+        _check(load().lasto_net_train_step(self.h, _dev_ptr(x, torch.int16), _dev_ptr(target, torch.float32),
+                                           _dev_ptr(weight, torch.float32), lr, C.byref(loss)))
+        return loss.value
 
 
 def hartree_step(grid: Grid, atoms, rtol=1e-10, dirs=None, **opts):

@@ -1,0 +1,123 @@
+"""Training and use of the learned initial guess (orchestration only: every
+step runs in the library's kernels through the C ABI; torch holds buffers).
+
+The paper's solver has no learned part. This is the learned form grown beside
+it: a U-Net (lasto_net_*) maps features of a source and its analytic
+monopole guess (lasto_analytic_guess, with the multipole faces of
+lasto_boundary_values) to a correction of that guess. Its training labels
+are the method's own FP64 multigrid solutions of the same problems
+(config 4: random 13..55-atom clusters on graded meshes), and plain
+multigrid judges every learned guess (lasto_learned_guess).
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import List
+
+import numpy as np
+
+from . import inputs as I
+from . import lasto
+
+# feature and output scales of the net (fixed, from the statistics of the
+# config-4 problems: densities up to ~15, potentials ~ -100, corrections ~ 0.1)
+NET_SCALES = dict(rho_scale=0.1, pot_scale=0.01, h_ref=0.25, out_scale=0.1)
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    atoms: list
+    grid: "lasto.Grid"
+    rho: object          # device float64 [nz, ny, nx]
+    v_guess: object      # faces + analytic guess inside
+    v_star: object       # FP64 multigrid solution to 1e-10 (the label)
+    solve_info: dict
+
+
+def make_problem(cid: int, sample: int, n: int, rtol: float = 1e-10) -> Problem:
+    """One seeded problem: grid, pseudo-density, faces, analytic guess, label."""
+    w = I.config(cid, n_override=n, sample=sample)
+    xs = lasto.mesh_for(w.axes)
+    g = lasto.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    v = g.empty()
+    g.boundary_values(rho, v, bc=1)
+    g.analytic_guess(w.atoms, v)
+    v_star = v.clone()
+    info = g.poisson_solve(rho, v_star, rtol=rtol, bc=2)
+    return Problem(w.name, w.atoms, g, rho, v, v_star, info)
+
+
+def training_pair(net: "lasto.Net", p: Problem, weighting: str = "volume"):
+    """Features, target (the correction in units of out_scale) and weights
+    over interior nodes (zero on faces): "volume" weighs each node by its
+    dual-cell volume (the W-norm of the error, which the far field's smooth
+    error dominates), "uniform" weighs nodes alike."""
+    import torch
+    x = net.features(p.grid, p.rho, p.v_guess)
+    t = ((p.v_star - p.v_guess) / net.cfg.out_scale).to(torch.float32)
+    wt = torch.zeros_like(t)
+    if weighting == "volume":
+        m = [np.zeros_like(c) for c in p.grid.coords]
+        for c, mm in zip(p.grid.coords, m):
+            mm[1:-1] = 0.5 * (c[2:] - c[:-2])
+        vol = np.einsum("k,j,i->kji", m[2], m[1], m[0])
+        wt.copy_(torch.from_numpy(vol.astype(np.float32)))
+    else:
+        wt[1:-1, 1:-1, 1:-1] = 1.0
+    wt /= wt.sum()
+    t[0, :, :] = 0
+    t[-1, :, :] = 0
+    t[:, 0, :] = 0
+    t[:, -1, :] = 0
+    t[:, :, 0] = 0
+    t[:, :, -1] = 0
+    return x, t.contiguous(), wt.contiguous()
+
+
+def train(net: "lasto.Net", problems: List[Problem], steps: int, lr: float = 2e-3, log_every: int = 0,
+          weighting: str = "volume"):
+    """Adam over the problems in turn; returns the loss history."""
+    pairs = [training_pair(net, p, weighting) for p in problems]
+    hist = []
+    for s in range(steps):
+        x, t, wt = pairs[s % len(pairs)]
+        a = lr * 0.5 * (1.0 + np.cos(np.pi * s / max(steps, 1)))   # cosine decay
+        hist.append(net.train_step(x, t, wt, max(a, lr * 1e-3)))
+        if log_every and (s + 1) % log_every == 0:
+            print("train step %d loss %.4e" % (s + 1, np.mean(hist[-log_every:])), flush=True)
+    return hist
+
+
+def compare(net: "lasto.Net", p: Problem, rtol: float = 1e-10, **opts) -> dict:
+    """Time-to-tolerance and iterations from the faces alone (zero guess), the
+    analytic guess, and the learned guess, same solver and tolerance. Each
+    timing covers the faces, the guess and the solve."""
+    import torch
+    out = {}
+    g, rho = p.grid, p.rho
+
+    def timed(kind):
+        v = g.empty()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.boundary_values(rho, v, bc=1)
+        lg = None
+        if kind != "zero":
+            g.analytic_guess(p.atoms, v)
+        if kind == "learned":
+            lg = g.learned_guess(net, rho, v)
+        info = g.poisson_solve(rho, v, rtol=rtol, bc=2, **opts)
+        torch.cuda.synchronize()
+        r = dict(iters=info["iters"], vcycles=info["vcycles"], ms=(time.perf_counter() - t0) * 1e3,
+                 rel_resid=info["rel_resid"])
+        if lg is not None:
+            r.update(accepted=lg["accepted"], rel_plain=lg["rel_before"], rel_learned=lg["rel_after"])
+        return r, v
+
+    for kind in ("zero", "analytic", "learned"):
+        out[kind], v = timed(kind)
+    out["err_vs_label"] = float((v - p.v_star).abs().max() / p.v_star.abs().max())
+    return out

@@ -1,0 +1,155 @@
+"""GPU parity and behaviour of the learned-guess network: its BF16 matrix-core
+kernels against the CPU reference (oracle/net_ref.py) on identical BF16
+operands, training by the library's own backward pass, and the learned guess
+judged by plain multigrid."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+CH = (16, 32, 48, 64)
+
+
+def say(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0806_1723_amd import lasto
+    lasto.load()
+    return lasto
+
+
+@pytest.fixture(scope="module")
+def R():
+    from oracle import net_ref
+    return net_ref
+
+
+def _features(torch, rng, shape):
+    """random BF16 features as int16 bit patterns on the device, and their values"""
+    a = torch.from_numpy(rng.normal(size=shape + (8,)).astype(np.float32)).to(torch.bfloat16)
+    bits = a.view(torch.int16).contiguous().to("cuda")
+    return bits, a.to(torch.float64).numpy()
+
+
+def _net_with_biases(L, rng, shape, ch=CH, seed=3):
+    net = L.Net(shape, ch=ch, seed=seed)
+    p = net.params().astype(np.float64)
+    from oracle import net_ref as R
+    o = 0
+    for ci, co, _ in R.layer_specs(ch):
+        o += 27 * ci * co
+        p[o:o + co] = rng.normal(scale=0.05, size=co)
+        o += co
+    p[o:o + ch[0]] = rng.normal(scale=0.3, size=ch[0])
+    p[o + ch[0]] = 0.1
+    net.set_params(p.astype(np.float32))
+    return net, net.params().astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", [(20, 27, 37), (9, 16, 8)])
+def test_net_forward_matches_reference(torch, L, R, shape):
+    say("net forward %s" % (shape,))
+    rng = np.random.default_rng(21)
+    net, p = _net_with_biases(L, rng, shape)
+    x_bits, x = _features(torch, rng, shape)
+    y = net.forward(x_bits).cpu().numpy().astype(np.float64)
+    want = R.forward(x, p, CH, bf16=True).numpy()
+    err = np.linalg.norm(y - want) / np.linalg.norm(want)
+    exact = R.forward(x, p, CH, bf16=False).numpy()
+    say("  rel L2 %.3e, max %.3e of %.3e (vs unrounded FP64: %.3e)" % (
+        err, np.abs(y - want).max(), np.abs(want).max(), np.linalg.norm(y - exact) / np.linalg.norm(exact)))
+    assert err <= 2e-3
+    assert np.abs(y - want).max() <= 2e-2 * np.abs(want).max()
+    net.close()
+
+
+def test_net_gradients_match_reference(torch, L, R):
+    shape = (12, 17, 21)
+    say("net gradients %s" % (shape,))
+    rng = np.random.default_rng(22)
+    net, p = _net_with_biases(L, rng, shape)
+    x_bits, x = _features(torch, rng, shape)
+    t = rng.normal(size=shape).astype(np.float32)
+    wt = (rng.uniform(0.5, 1.5, size=shape) / np.prod(shape)).astype(np.float32)
+    net.forward(x_bits)
+    loss = net.backward(x_bits, torch.from_numpy(t).cuda(), torch.from_numpy(wt).cuda())
+    g = net.grads().astype(np.float64)
+    L_ref, g_ref = R.loss_and_grads(x, p, CH, t.astype(np.float64), wt.astype(np.float64), bf16=True)
+    assert abs(loss - L_ref) <= 1e-3 * abs(L_ref)
+    # per parameter tensor (BF16 rounding of the backward's intermediates bounds the agreement)
+    o = 0
+    scale = np.linalg.norm(g_ref)
+    for k, (ci, co, _) in enumerate(R.layer_specs(CH)):
+        for name, size in (("W", 27 * ci * co), ("b", co)):
+            a, b = g[o:o + size], g_ref[o:o + size]
+            err = np.linalg.norm(a - b)
+            say("  layer %d %s: rel %.3e" % (k, name, err / max(np.linalg.norm(b), 1e-300)))
+            assert err <= 3e-2 * np.linalg.norm(b) + 1e-6 * scale
+            o += size
+    a, b = g[o:], g_ref[o:]
+    assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b) + 1e-6 * scale
+    net.close()
+
+
+def test_net_training_lowers_the_loss(torch, L):
+    shape = (17, 17, 17)
+    say("net training %s" % (shape,))
+    rng = np.random.default_rng(23)
+    net = L.Net(shape, ch=(16, 16, 16, 16), seed=4)
+    x_bits, x = _features(torch, rng, shape)
+    # a smooth target the features determine: a blurred feature channel
+    t = torch.from_numpy(np.tanh(x[..., 0] + 0.5 * x[..., 4]).astype(np.float32)).cuda()
+    wt = torch.full(shape, 1.0 / np.prod(shape), dtype=torch.float32, device="cuda")
+    losses = [net.train_step(x_bits, t, wt, 3e-3) for _ in range(60)]
+    say("  loss %.4e -> %.4e" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.5 * losses[0]
+    assert all(np.isfinite(losses))
+    # deterministic: the same steps from the same start give the same loss
+    net2 = L.Net(shape, ch=(16, 16, 16, 16), seed=4)
+    losses2 = [net2.train_step(x_bits, t, wt, 3e-3) for _ in range(60)]
+    assert losses2 == losses
+    net.close()
+    net2.close()
+
+
+def test_learned_guess_beats_the_analytic_guess(torch, L):
+    """Trained on config-4 problems (random clusters, 65^3 graded), the net's
+    correction lowers the smoothed residual of the analytic guess on held-out
+    problems, and the solve from it needs no more iterations."""
+    from paper_0806_1723_amd import learned
+    n = 65
+    say("learned guess, config 4 at %d^3" % n)
+    train_p = [learned.make_problem(4, s, n) for s in range(10)]
+    test_p = [learned.make_problem(4, 1000 + s, n) for s in range(3)]
+    net = L.Net((n, n, n), ch=(16, 32, 32, 32), seed=7, **learned.NET_SCALES)
+    hist = learned.train(net, train_p, steps=800, lr=2e-3)
+    say("  training loss %.3e -> %.3e" % (np.mean(hist[:10]), np.mean(hist[-10:])))
+    # the last 10 steps revisit the first 10 steps' problems
+    assert np.mean(hist[-10:]) < 0.6 * np.mean(hist[:10])
+    better, iters = 0, []
+    for p in test_p:
+        r = learned.compare(net, p, rtol=1e-10, method=1)
+        say("  %s: %s" % (p.name, r))
+        better += r["learned"]["rel_learned"] < r["learned"]["rel_plain"]
+        iters.append((r["zero"]["iters"], r["analytic"]["iters"], r["learned"]["iters"]))
+        assert r["learned"]["rel_resid"] <= 1e-10
+        # the learned guess borrowed the solver's vectors: the same solve again gives the same bits
+        v1, v2 = p.v_star.clone(), p.v_guess.clone()
+        p.grid.poisson_solve(p.rho, v2, rtol=1e-10, bc=2)
+        assert torch.equal(v1, v2)
+    assert better >= 2
+    assert sum(i[2] for i in iters) <= sum(i[1] for i in iters)
+    net.close()

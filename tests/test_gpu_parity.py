@@ -328,6 +328,25 @@ def test_failure_paths(torch, L, oracle_mod):
     g.close()
 
 
+def test_scratch_users_leave_the_solver_clean(torch, L, oracle_mod):
+    """lasto_rb_sweep borrows the solver's vectors: a solve after it on the
+    same grid gives the same bits as before it."""
+    say("solve, rb_sweep, solve on one grid")
+    w = I.config(2, n_override=57)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    v1 = g.empty()
+    g.poisson_solve(rho, v1, rtol=1e-11)
+    rng = np.random.default_rng(17)
+    u = to_dev(torch, rng.normal(size=rho.shape) * 50.0)
+    g.rb_sweep(u, rho)
+    v2 = g.empty()
+    g.poisson_solve(rho, v2, rtol=1e-11)
+    assert torch.equal(v1, v2)
+    g.close()
+
+
 def test_profile_counts_sweeps(torch, L, oracle_mod):
     w = I.config(2, n_override=65)
     xs = oracle_mod.mesh_for(w.axes)
