@@ -84,7 +84,12 @@ lasto_status lasto_mesh_graded_1d(double lo, double hi, int n, const double* pla
  * and allocate its device scratch on the current HIP device.
  *   hip_stream: a hipStream_t (NULL = the default stream) on which all of
  *   this grid's work runs.
- *   n_batch: number of right-hand sides a batched solve may carry (>= 1).
+ *   n_batch: right-hand sides the grid carries, 1..16. A batched grid holds
+ *     n_batch independent problems on the same mesh: every device array of
+ *     the calls below is then [n_batch][nz][ny][nx] (copies back to back),
+ *     every kernel launch of a solve covers all copies at once (they are
+ *     stacked along z, each copy's first and last planes being its own
+ *     faces), and host outputs gain a leading n_batch dimension.
  * The hierarchy: per axis, a pair of cells merges (its middle node is
  * dropped) when its merged width is at most 4 times the level's smallest
  * spacing; when no axis can merge, every pair merges. Coarsening stops when
@@ -131,6 +136,8 @@ typedef struct {
  *   rho_interstitial: device [nz][ny][nx] added at nodes outside every
  *     sphere (|x - C_a| >= R_a), or NULL.
  *   rho_out: device [nz][ny][nx], overwritten.
+ *   Batched grids: atoms holds n_batch tables of n_atoms back to back (copy
+ *   b uses atoms[b * n_atoms ...]); moments_out is [n_batch][25].
  *   moments_out: host [25] (l <= 4 moments about the box centre, see
  *     lasto_poisson_solve) or NULL.
  * Errors: LASTO_ERR_ARG (lmax > 4, kind not 0/1, width <= 0, NaN), LASTO_ERR_HIP.
@@ -167,6 +174,8 @@ typedef struct {
     double smooth_ms;       /* summed event-timed duration of those sweeps, ms */
     double smooth_bytes;    /* their algorithmic HBM bytes: (read u, f + write u) per interior node */
     int smooth_fp32;        /* launches among them that ran in FP32 */
+    int n_batch;            /* right-hand sides solved (the grid's n_batch) */
+    double batch_rel_resid[16]; /* rel_resid of each right-hand side (rel_resid is their maximum) */
 } lasto_solve_info;
 
 void lasto_solve_opts_default(lasto_solve_opts* o);
@@ -184,6 +193,10 @@ void lasto_solve_opts_default(lasto_solve_opts* o);
  * r^l y_lm(x') / |x'|^(2l+1), x' = x - c, Q_lm = sum_n vol_n rho_n
  * r_n^l y_lm(x_n - c), c the box centre.
  * W-norm: ||r||_W^2 = sum over interior nodes of vol_n r_n^2.
+ * Batched grids solve all copies together (one norm and one set of CG
+ * coefficients for the stacked system, i.e. CG on the block-diagonal
+ * operator) until every copy meets rtol against its own reference norm
+ * (info->batch_rel_resid); each copy's faces come from its own moments.
  * Returns LASTO_OK, or LASTO_ERR_NOT_CONVERGED / LASTO_ERR_DIVERGED with v
  * and info filled, or LASTO_ERR_ARG / LASTO_ERR_HIP.
  */
@@ -199,7 +212,8 @@ lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, double* v,
  *   dirs: host [n_dir][3] unit vectors, or NULL for the default 64 (8
  *     Gauss-Legendre nodes in cos(theta) times 8 azimuths 2 pi (b + 1/2)/8,
  *     theta-major; n_dir must then be 64).
- *   out: host [n_atoms][n_dir].
+ *   out: host [n_atoms][n_dir] ([n_batch][n_atoms][n_dir] for a batch; the
+ *     points are the same for every copy).
  * Errors: LASTO_ERR_ARG (a point outside the box, n_dir mismatch), LASTO_ERR_HIP.
  */
 lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n_atoms, const double* centers,

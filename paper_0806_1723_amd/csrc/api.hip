@@ -219,14 +219,20 @@ extern "C" lasto_status lasto_pseudo_density(lasto_grid g, int n_atoms, const la
 {
     if (!g || !rho_out || n_atoms < 0 || (n_atoms > 0 && !atoms))
         return fail(LASTO_ERR_ARG, "lasto_pseudo_density: NULL argument");
+    // a batch has one atom table of n_atoms per right-hand side, back to back
+    const int nb = g->n_batch;
     AtomDev* dat = nullptr;
-    if (lasto_status st = stage_atoms(g, n_atoms, atoms, renormalize, "lasto_pseudo_density", &dat); st != LASTO_OK)
+    if (lasto_status st = stage_atoms(g, nb * n_atoms, atoms, renormalize, "lasto_pseudo_density", &dat);
+        st != LASTO_OK)
         return st;
-    LASTO_HIP(launch_pseudo(g, dat, n_atoms, rho_interstitial, rho_out));
-    if (moments_out) {
-        LASTO_HIP(launch_moments(g, rho_out, g->moments));
-        LASTO_HIP(hipMemcpyAsync(moments_out, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, g->stream));
+    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    for (int b = 0; b < nb; ++b) {
+        LASTO_HIP(launch_pseudo(g, dat + (size_t)b * n_atoms, n_atoms, rho_interstitial ? rho_interstitial + b * N : nullptr,
+                                rho_out + b * N));
+        if (moments_out) LASTO_HIP(launch_moments(g, rho_out + b * N, g->moments + 25 * b));
     }
+    if (moments_out)
+        LASTO_HIP(hipMemcpyAsync(moments_out, g->moments, sizeof(double) * 25 * nb, hipMemcpyDeviceToHost, g->stream));
     // the staging buffer is reused by the next call: finish before returning
     LASTO_HIP(hipStreamSynchronize(g->stream));
     return LASTO_OK;
@@ -236,9 +242,12 @@ extern "C" lasto_status lasto_analytic_guess(lasto_grid g, int n_atoms, const la
 {
     if (!g || !v || n_atoms < 0 || (n_atoms > 0 && !atoms))
         return fail(LASTO_ERR_ARG, "lasto_analytic_guess: NULL argument");
+    const int nb = g->n_batch;
     AtomDev* dat = nullptr;
-    if (lasto_status st = stage_atoms(g, n_atoms, atoms, 1, "lasto_analytic_guess", &dat); st != LASTO_OK) return st;
-    LASTO_HIP(launch_guess(g, dat, n_atoms, v));
+    if (lasto_status st = stage_atoms(g, nb * n_atoms, atoms, 1, "lasto_analytic_guess", &dat); st != LASTO_OK)
+        return st;
+    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    for (int b = 0; b < nb; ++b) LASTO_HIP(launch_guess(g, dat + (size_t)b * n_atoms, n_atoms, v + b * N));
     LASTO_HIP(hipStreamSynchronize(g->stream));
     return LASTO_OK;
 }
@@ -307,8 +316,12 @@ extern "C" lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n
     double* dpts = g->stage;
     double* dout = g->stage + 3 * np;
     LASTO_HIP(hipMemcpyAsync(dpts, pts.data(), sizeof(double) * 3 * np, hipMemcpyHostToDevice, g->stream));
-    LASTO_HIP(launch_interp(g, v, dpts, (int)np, dout));
-    LASTO_HIP(hipMemcpyAsync(out, dout, sizeof(double) * np, hipMemcpyDeviceToHost, g->stream));
-    LASTO_HIP(hipStreamSynchronize(g->stream));
+    // each right-hand side of a batch in turn (same points, its own values)
+    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    for (int b = 0; b < g->n_batch; ++b) {
+        LASTO_HIP(launch_interp(g, v + b * N, dpts, (int)np, dout));
+        LASTO_HIP(hipMemcpyAsync(out + b * np, dout, sizeof(double) * np, hipMemcpyDeviceToHost, g->stream));
+        LASTO_HIP(hipStreamSynchronize(g->stream));
+    }
     return LASTO_OK;
 }

@@ -46,51 +46,141 @@ static void dual_widths(const std::vector<double>& x, std::vector<double>& m)
     for (int i = 1; i < n - 1; ++i) m[i] = 0.5 * (x[i + 1] - x[i - 1]);
 }
 
+// Per-axis tables of one copy: stencil coefficients, dual widths,
+// coordinates, restriction (rf, rw) and prolongation (pc, pw from the finer
+// level; level > 0 only).
+struct AxisTables {
+    std::vector<double> am, ap, m, x, rw, pw;
+    std::vector<int> rf, pc;
+};
+
+static AxisTables axis_tables(lasto_grid g, int l, int d)
+{
+    const Level& L = g->lev[l];
+    const int n = L.n[d];
+    const std::vector<double>& x = L.hx[d];
+    AxisTables t;
+    dual_widths(x, t.m);
+    t.x = x;
+    t.am.assign(n, 0.0);
+    t.ap.assign(n, 0.0);
+    for (int i = 1; i < n - 1; ++i) {
+        t.am[i] = 1.0 / ((x[i] - x[i - 1]) * t.m[i]);
+        t.ap[i] = 1.0 / ((x[i + 1] - x[i]) * t.m[i]);
+    }
+    t.rf.assign(n, 0);
+    t.rw.assign(3 * (size_t)n, 0.0);
+    if (l == 0) {
+        for (int I = 0; I < n; ++I) {
+            t.rf[I] = I;
+            t.rw[3 * I + 1] = 1.0;
+        }
+        return t;
+    }
+    const Level& F = g->lev[l - 1];
+    const std::vector<double>& xf = F.hx[d];
+    const int nf = F.n[d];
+    std::vector<double> mf;
+    dual_widths(xf, mf);
+    const std::vector<int>& keep = L.keep[d];
+    t.pc.assign(nf, 0);
+    t.pw.assign(2 * (size_t)nf, 0.0);
+    // interpolation: kept fine node -> weight 1 on its coarse node; a
+    // dropped node between coarse c and c+1 -> linear weights in x
+    int c = 0;
+    for (int i = 0; i < nf; ++i) {
+        while (c + 1 < n && keep[c + 1] <= i) ++c;
+        t.pc[i] = c;
+        if (keep[c] == i) {
+            t.pw[2 * i] = 1.0;
+        } else {
+            const double xa = xf[keep[c]], xb = xf[keep[c + 1]];
+            const double w = (xb - xf[i]) / (xb - xa);
+            t.pw[2 * i] = w;
+            t.pw[2 * i + 1] = 1.0 - w;
+        }
+    }
+    // restriction: coarse node I gathers fine nodes keep[I]-1..keep[I]+1
+    // with the transposed interpolation weight times m_fine/m_coarse
+    for (int I = 0; I < n; ++I) {
+        t.rf[I] = keep[I];
+        for (int s2 = 0; s2 < 3; ++s2) {
+            const int fi = keep[I] - 1 + s2;
+            double w = 0.0;
+            if (fi >= 0 && fi < nf) {
+                if (t.pc[fi] == I) w = t.pw[2 * fi];
+                else if (t.pc[fi] + 1 == I) w = t.pw[2 * fi + 1];
+                w *= mf[fi] / t.m[I];
+            }
+            t.rw[3 * I + s2] = w;
+        }
+    }
+    return t;
+}
+
+// The z tables of a batch: the copy's tables repeated, with the restriction
+// and prolongation indices shifted to each copy's planes.
+static AxisTables stack_copies(const AxisTables& t, int nb, int n, int nf)
+{
+    if (nb == 1) return t;
+    AxisTables s;
+    for (int b = 0; b < nb; ++b) {
+        s.am.insert(s.am.end(), t.am.begin(), t.am.end());
+        s.ap.insert(s.ap.end(), t.ap.begin(), t.ap.end());
+        s.m.insert(s.m.end(), t.m.begin(), t.m.end());
+        s.x.insert(s.x.end(), t.x.begin(), t.x.end());
+        s.rw.insert(s.rw.end(), t.rw.begin(), t.rw.end());
+        s.pw.insert(s.pw.end(), t.pw.begin(), t.pw.end());
+        for (int v : t.rf) s.rf.push_back(v + b * nf);
+        for (int v : t.pc) s.pc.push_back(v + b * n);
+    }
+    return s;
+}
+
 // Device table layout of level l (doubles): per axis d, am[n] ap[n] m[n] x[n]
 // rw[3n]; then, for l > 0, per axis pw[2 nf] (nf = the finer level's length).
-// Ints: per axis rf[n]; then, for l > 0, per axis pc[nf].
+// Ints: per axis rf[n]; then, for l > 0, per axis pc[nf]. For z, n and nf
+// count all copies of a batch.
 lasto_status build_level_tables(lasto_grid g, int l)
 {
     Level& L = g->lev[l];
+    const int nb = g->n_batch;
+    AxisTables T[3];
+    int nst[3], nfst[3];
+    for (int d = 0; d < 3; ++d) {
+        const int copies = d == 2 ? nb : 1;
+        const int nf = l > 0 ? g->lev[l - 1].n[d] : 0;
+        T[d] = stack_copies(axis_tables(g, l, d), copies, L.n[d], nf);
+        nst[d] = copies * L.n[d];
+        nfst[d] = copies * nf;
+    }
     size_t od_own[3], oi_own[3], od_fine[3], oi_fine[3];
     size_t nd = 0, ni = 0;
     for (int d = 0; d < 3; ++d) {
         od_own[d] = nd;
         oi_own[d] = ni;
-        nd += 7 * (size_t)L.n[d];
-        ni += (size_t)L.n[d];
+        nd += 7 * (size_t)nst[d];
+        ni += (size_t)nst[d];
     }
     for (int d = 0; d < 3; ++d) {
-        const size_t nf = l > 0 ? (size_t)g->lev[l - 1].n[d] : 0;
         od_fine[d] = nd;
         oi_fine[d] = ni;
-        nd += 2 * nf;
-        ni += nf;
+        nd += 2 * (size_t)nfst[d];
+        ni += (size_t)nfst[d];
     }
     std::vector<double> hd(nd, 0.0);
     std::vector<int> hi(ni, 0);
     LASTO_HIP(hipMalloc(&L.dtab, sizeof(double) * nd));
     LASTO_HIP(hipMalloc(&L.dtabi, sizeof(int) * ni));
     for (int d = 0; d < 3; ++d) {
-        const int n = L.n[d];
-        const std::vector<double>& x = L.hx[d];
-        std::vector<double> m;
-        dual_widths(x, m);
+        const int n = nst[d];
         const size_t o = od_own[d];
-        double* am = &hd[o];
-        double* ap = &hd[o + n];
-        double* mm = &hd[o + 2 * n];
-        double* xx = &hd[o + 3 * n];
-        double* rw = &hd[o + 4 * n];
-        int* rf = &hi[oi_own[d]];
-        for (int i = 0; i < n; ++i) {
-            mm[i] = m[i];
-            xx[i] = x[i];
-            if (i > 0 && i < n - 1) {
-                am[i] = 1.0 / ((x[i] - x[i - 1]) * m[i]);
-                ap[i] = 1.0 / ((x[i + 1] - x[i]) * m[i]);
-            }
-        }
+        std::copy(T[d].am.begin(), T[d].am.end(), hd.begin() + o);
+        std::copy(T[d].ap.begin(), T[d].ap.end(), hd.begin() + o + n);
+        std::copy(T[d].m.begin(), T[d].m.end(), hd.begin() + o + 2 * n);
+        std::copy(T[d].x.begin(), T[d].x.end(), hd.begin() + o + 3 * n);
+        std::copy(T[d].rw.begin(), T[d].rw.end(), hd.begin() + o + 4 * n);
+        std::copy(T[d].rf.begin(), T[d].rf.end(), hi.begin() + oi_own[d]);
         Axis& A = L.view.ax[d];
         A.n = n;
         A.am = L.dtab + o;
@@ -101,68 +191,34 @@ lasto_status build_level_tables(lasto_grid g, int l)
         A.rf = L.dtabi + oi_own[d];
         A.pc = nullptr;
         A.pw = nullptr;
-        if (l == 0) {
-            for (int I = 0; I < n; ++I) {
-                rf[I] = I;
-                rw[3 * I] = 0.0;
-                rw[3 * I + 1] = 1.0;
-                rw[3 * I + 2] = 0.0;
-            }
-            continue;
+        if (l > 0) {
+            std::copy(T[d].pw.begin(), T[d].pw.end(), hd.begin() + od_fine[d]);
+            std::copy(T[d].pc.begin(), T[d].pc.end(), hi.begin() + oi_fine[d]);
+            A.pc = L.dtabi + oi_fine[d];
+            A.pw = L.dtab + od_fine[d];
         }
-        const Level& F = g->lev[l - 1];
-        const std::vector<double>& xf = F.hx[d];
-        const int nf = F.n[d];
-        std::vector<double> mf;
-        dual_widths(xf, mf);
-        const std::vector<int>& keep = L.keep[d];
-        int* pc = &hi[oi_fine[d]];
-        double* pw = &hd[od_fine[d]];
-        // interpolation: kept fine node -> weight 1 on its coarse node; a
-        // dropped node between coarse c and c+1 -> linear weights in x
-        int c = 0;
-        for (int i = 0; i < nf; ++i) {
-            while (c + 1 < n && keep[c + 1] <= i) ++c;
-            pc[i] = c;
-            if (keep[c] == i) {
-                pw[2 * i] = 1.0;
-                pw[2 * i + 1] = 0.0;
-            } else {
-                const double xa = xf[keep[c]], xb = xf[keep[c + 1]];
-                const double w = (xb - xf[i]) / (xb - xa);
-                pw[2 * i] = w;
-                pw[2 * i + 1] = 1.0 - w;
-            }
-        }
-        // restriction: coarse node I gathers fine nodes keep[I]-1..keep[I]+1
-        // with the transposed interpolation weight times m_fine/m_coarse
-        for (int I = 0; I < n; ++I) {
-            rf[I] = keep[I];
-            for (int s = 0; s < 3; ++s) {
-                const int fi = keep[I] - 1 + s;
-                double w = 0.0;
-                if (fi >= 0 && fi < nf) {
-                    if (pc[fi] == I) w = pw[2 * fi];
-                    else if (pc[fi] + 1 == I) w = pw[2 * fi + 1];
-                    w *= mf[fi] / m[I];
-                }
-                rw[3 * I + s] = w;
-            }
-        }
-        A.pc = L.dtabi + oi_fine[d];
-        A.pw = L.dtab + od_fine[d];
     }
     LASTO_HIP(hipMemcpy(L.dtab, hd.data(), sizeof(double) * nd, hipMemcpyHostToDevice));
     LASTO_HIP(hipMemcpy(L.dtabi, hi.data(), sizeof(int) * ni, hipMemcpyHostToDevice));
     L.view.nx = L.n[0];
     L.view.ny = L.n[1];
-    L.view.nz = L.n[2];
+    L.view.nz = nst[2];
+    L.view.nzc = L.n[2];
     // split-layout row: entries 0..nx/2 of one colour plus two spare entries
     // (a half-sweep pair at the row's end reads one past it), padded to 16
     // (128 B in FP64)
     L.view.W = ((L.n[0] / 2 + 3) + 15) / 16 * 16;
-    L.view.cs = (size_t)L.n[2] * L.n[1] * L.view.W;
+    L.view.cs = (size_t)L.view.nz * L.n[1] * L.view.W;
     L.nsplit = 2 * L.view.cs;
+    // planes interior to their copy
+    std::vector<unsigned char> zi(nst[2], 0);
+    for (int k = 0; k < nst[2]; ++k) {
+        const int kk = k % L.n[2];
+        zi[k] = (kk >= 1 && kk <= L.n[2] - 2) ? 1 : 0;
+    }
+    LASTO_HIP(hipMalloc(&L.dzint, zi.size()));
+    LASTO_HIP(hipMemcpy(L.dzint, zi.data(), zi.size(), hipMemcpyHostToDevice));
+    L.view.zint = L.dzint;
 
     // x coefficients by parity ([p][q][m], node i = p + 2m; zero off the
     // interior) in FP64 and FP32, and FP32 copies of every axis' am/ap
@@ -176,19 +232,19 @@ lasto_status build_level_tables(lasto_grid g, int l)
             xp[(p * 3 + 1) * (size_t)W + m] = hd[od_own[0] + nx + i];
             xp[(p * 3 + 2) * (size_t)W + m] = hd[od_own[0] + 2 * nx + i];
         }
-    size_t nf = 6 * (size_t)W;
-    for (int d = 0; d < 3; ++d) nf += 2 * (size_t)L.n[d];
-    std::vector<float> hf(nf, 0.0f);
+    size_t nfl = 6 * (size_t)W;
+    for (int d = 0; d < 3; ++d) nfl += 2 * (size_t)nst[d];
+    std::vector<float> hf(nfl, 0.0f);
     for (size_t t = 0; t < 6 * (size_t)W; ++t) hf[t] = (float)xp[t];
     size_t of = 6 * (size_t)W;
     size_t ofs[3];
     for (int d = 0; d < 3; ++d) {
         ofs[d] = of;
-        for (int i = 0; i < L.n[d]; ++i) {
+        for (int i = 0; i < nst[d]; ++i) {
             hf[of + i] = (float)hd[od_own[d] + i];
-            hf[of + L.n[d] + i] = (float)hd[od_own[d] + L.n[d] + i];
+            hf[of + nst[d] + i] = (float)hd[od_own[d] + nst[d] + i];
         }
-        of += 2 * (size_t)L.n[d];
+        of += 2 * (size_t)nst[d];
     }
     LASTO_HIP(hipMalloc(&L.dxpar, sizeof(double) * xp.size()));
     LASTO_HIP(hipMalloc(&L.dtabf, sizeof(float) * hf.size()));
@@ -198,7 +254,7 @@ lasto_status build_level_tables(lasto_grid g, int l)
     L.view.xparf = L.dtabf;
     for (int d = 0; d < 3; ++d) {
         L.view.ax[d].amf = L.dtabf + ofs[d];
-        L.view.ax[d].apf = L.dtabf + ofs[d] + L.n[d];
+        L.view.ax[d].apf = L.dtabf + ofs[d] + nst[d];
     }
     return LASTO_OK;
 }
@@ -217,6 +273,7 @@ static void free_grid(lasto_grid g)
         (void)hipFree(L.dtab);
         (void)hipFree(L.dtabi);
         (void)hipFree(L.dxpar);
+        (void)hipFree(L.dzint);
         (void)hipFree(L.dtabf);
         (void)hipFree(L.u64);
         (void)hipFree(L.u32);
@@ -267,7 +324,7 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
         for (int i = 0; i + 1 < ns[d]; ++i)
             if (!(xs[d][i + 1] > xs[d][i])) return fail(LASTO_ERR_ARG, "lasto_grid_create: coordinates must increase");
     }
-    if (n_batch < 1) return fail(LASTO_ERR_ARG, "lasto_grid_create: n_batch must be >= 1");
+    if (n_batch < 1 || n_batch > kMaxBatch) return fail(LASTO_ERR_ARG, "lasto_grid_create: n_batch must be 1..16");
     if (hipError_t e = init_harmonic_constants(); e != hipSuccess)
         return fail(LASTO_ERR_HIP, std::string("harmonic constants: ") + hipGetErrorString(e));
 
@@ -316,7 +373,7 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
     lasto_status st = LASTO_OK;
     for (int l = 0; l < g->nlev && st == LASTO_OK; ++l) {
         Level& L = g->lev[l];
-        L.npts = (size_t)L.n[0] * L.n[1] * L.n[2];
+        L.npts = (size_t)L.n[0] * L.n[1] * L.n[2] * n_batch;
         st = build_level_tables(g, l);
         if (st != LASTO_OK) break;
         // V-cycle arrays in the split layout (level 0 uses the Krylov vectors
@@ -355,7 +412,14 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
     }
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->partials, sizeof(double) * nparts);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->scalars, sizeof(double) * kNumScalars);
-    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->moments, sizeof(double) * 32);
+    if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->moments, sizeof(double) * 25 * kMaxBatch);
+    if (st == LASTO_OK) {
+        // one copy of the finest level (natural-layout kernels that work per right-hand side)
+        g->cview = g->lev[0].view;
+        g->cview.nz = g->cview.nzc;
+        g->cview.cs = (size_t)g->cview.nz * g->cview.ny * g->cview.W;
+        g->cview.ax[2].n = g->cview.nzc;
+    }
     if (st == LASTO_OK) {
         g->stage_bytes = 1 << 20;
         st = alloc_zero(g, (void**)&g->stage, g->stage_bytes);

@@ -17,7 +17,8 @@ constexpr int kMaxLevels = 40;
 constexpr int kCoarseMax = 5;         // coarsening stops when every axis has <= 5 nodes
 constexpr double kCoarsenTheta = 4.0; // merge cell pairs up to theta * (smallest spacing)
 constexpr int kReduceBlocks = 1024;   // fixed partial count of every reduction (determinism)
-constexpr int kNumScalars = 32;
+constexpr int kMaxBatch = 16;          // right-hand sides of one batched grid
+constexpr int kNumScalars = 32 + 2 * kMaxBatch;
 
 // scalar slots of the device scalar array
 enum Scalar {
@@ -27,6 +28,8 @@ enum Scalar {
     S_R0 = 4,               // reference ||b - A v_bc||_W^2
     S_TMP = 5,
     S_RZ32_0 = 8, S_RZ32_1 = 9, S_PQ32 = 10, S_RR32 = 11,   // inner FP32 PCG
+    S_BR0 = 32,                        // per right-hand side: reference norm^2 [kMaxBatch]
+    S_BRR = 32 + kMaxBatch,            // per right-hand side: residual norm^2 [kMaxBatch]
 };
 
 void set_error(const std::string& msg);
@@ -80,13 +83,21 @@ template <typename T> struct XPar;
 // c = (i+j+k) & 1 lives at [c][k][j][i >> 1] in rows of W (padded) entries,
 // cs = nz*ny*W apart between colours. A red-black half-sweep then reads one
 // colour array and writes the other, both contiguous in x.
+//
+// A batched grid stacks its n_batch right-hand sides along z: copy b owns
+// planes b*nzc .. b*nzc + nzc - 1, its first and last planes are its own
+// Dirichlet faces, and the z tables repeat per copy. zint[k] marks the planes
+// interior to their copy; stencils never couple two copies because every
+// plane next to another copy is a face.
 struct LevelView {
     int nx, ny, nz;
+    int nzc;        // planes per copy (nz = n_batch * nzc)
     int W;          // padded row length of one colour (>= (nx+1)/2)
     size_t cs;      // colour stride = nz * ny * W
     Axis ax[3];
     const double* xpar;   // [2][3][W] x coefficients by parity (FP64)
     const float* xparf;   // the same in FP32
+    const unsigned char* zint;   // [nz] 1 on planes interior to their copy
 };
 
 template <> struct XPar<double> {
@@ -110,6 +121,7 @@ struct Level {
     double* dtab = nullptr;        // device table block
     int* dtabi = nullptr;
     double* dxpar = nullptr;       // device x-parity table (FP64)
+    unsigned char* dzint = nullptr;   // device [nz] interior-plane flags
     float* dtabf = nullptr;        // device FP32 tables (am, ap per axis; x-parity)
     LevelView view;
     // V-cycle work arrays (split layout): correction, right-hand side, residual
@@ -171,7 +183,8 @@ struct lasto_grid_s {
     double* partials = nullptr;
     double* scalars = nullptr;      // [kNumScalars]
     double* h_scalars = nullptr;    // pinned host mirror
-    double* moments = nullptr;      // device [25]
+    double* moments = nullptr;      // device [25 * n_batch]
+    lasto::LevelView cview;         // the finest level as one copy of the batch sees it
     // interpolation / atom staging
     double* stage = nullptr;
     size_t stage_bytes = 0;

@@ -312,8 +312,9 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
         auto compute = [&](int k, const HalfOps<T>& q, const V2& zm, const V2& zc, const V2& zp) {
             const int o = (c + j + k) & 1;
             const int i0 = o + 2 * m;
-            const bool ok0 = i0 >= 1 && i0 <= nx - 2;
-            const bool ok1 = i0 + 2 <= nx - 2;
+            const bool okz = L.zint[k];   // planes next to another copy of a batch are faces
+            const bool ok0 = okz && i0 >= 1 && i0 <= nx - 2;
+            const bool ok1 = okz && i0 + 2 <= nx - 2;
             const V2 cxm = o ? axm1 : axm0, cxp = o ? axp1 : axp0;
             const T czm = amz[k], czp = apz[k];
             // x neighbours of the pair: o = 1: (zc.x, zc.y), (zc.y, xe); o = 0: (xe, zc.x), (zc.x, zc.y)
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                 if (ok1) out[at + 1] = r1;
             }
             if (DOT) {
-                const double vz = vy * L.ax[2].m[k];
+                const double vz = okz ? vy * L.ax[2].m[k] : 0.0;
                 const T a0 = MODE == HM_APPLY ? q.cv.x : q.fv.x;
                 const T a1 = MODE == HM_APPLY ? q.cv.y : q.fv.y;
                 const V2 av = o ? axv1 : axv0;   // zero off the interior
@@ -508,6 +509,7 @@ int interior_blocks(const LevelView& L)
     return (int)(g.x * g.y * g.z);
 }
 
+// (bodies skip planes that are faces of a batch copy: !L.zint[k])
 #define INTERIOR_LOOP                                                 \
     const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);       \
     const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);       \
@@ -534,8 +536,8 @@ __global__ __launch_bounds__(PT_NT) void k_residual_nat(LevelView L, int kp, con
     double acc = 0.0;
     INTERIOR_LOOP
     {
-        if (!inside) continue;
-        const int nx = L.nx, ny = L.ny, nz = L.nz;
+        if (!inside || !L.zint[k]) continue;
+        const int nx = L.nx, ny = L.ny;
         const size_t sxy = (size_t)nx * ny;
         const size_t idx = (size_t)k * sxy + (size_t)j * nx + i;
         double a;
@@ -550,8 +552,8 @@ __global__ __launch_bounds__(PT_NT) void k_residual_nat(LevelView L, int kp, con
             if (i == nx - 2) a += L.ax[0].ap[i] * v[idx + 1];
             if (j == 1) a += L.ax[1].am[j] * v[idx - nx];
             if (j == ny - 2) a += L.ax[1].ap[j] * v[idx + nx];
-            if (k == 1) a += L.ax[2].am[k] * v[idx - sxy];
-            if (k == nz - 2) a += L.ax[2].ap[k] * v[idx + sxy];
+            if (!L.zint[k - 1]) a += L.ax[2].am[k] * v[idx - sxy];
+            if (!L.zint[k + 1]) a += L.ax[2].ap[k] * v[idx + sxy];
         }
         const double res = bscale * rho[idx] - a;
         if (r) r[sidx(L, i, j, k)] = res;
@@ -574,7 +576,7 @@ __global__ __launch_bounds__(PT_NT) void k_apply_nat(LevelView L, int kp, const 
 {
     INTERIOR_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         const int nx = L.nx;
         const size_t sxy = (size_t)nx * L.ny;
         const size_t idx = (size_t)k * sxy + (size_t)j * nx + i;
@@ -643,7 +645,7 @@ __global__ __launch_bounds__(PT_NT) void k_dot(LevelView L, int kp, const T* __r
     double acc = 0.0;
     ROW_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         const size_t at = ROW_AT;
         acc += ROW_VOL * (double)a[at] * (double)b[at];
     }
@@ -667,7 +669,7 @@ __global__ __launch_bounds__(PT_NT) void k_update_p(LevelView L, int kp, const T
     const T beta = first ? T(0) : (T)(scal[i_num] / scal[i_den]);
     ROW_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         const size_t at = ROW_AT;
         pnew[at] = first ? z[at] : z[at] + beta * pold[at];
     }
@@ -697,7 +699,7 @@ __global__ __launch_bounds__(PT_NT) void k_update_xr(LevelView L, int kp, T* __r
     double acc = 0.0;
     ROW_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         const size_t at = ROW_AT;
         T rv = r[at];
         if (ok) {
@@ -725,7 +727,7 @@ __global__ __launch_bounds__(PT_NT) void k_add_nat(LevelView L, int kp, double* 
 {
     INTERIOR_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         v[((size_t)k * L.ny + j) * L.nx + i] += e[sidx(L, i, j, k)];
     }
 }
@@ -742,7 +744,7 @@ __global__ __launch_bounds__(PT_NT) void k_add_f32_nat(LevelView L, int kp, doub
 {
     INTERIOR_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         const size_t at = ((size_t)k * L.ny + j) * L.nx + i;
         v[at] += s * (double)y[at];
     }
@@ -762,7 +764,7 @@ __global__ __launch_bounds__(PT_NT) void k_scale_to32(LevelView L, int kp, const
     const double inv = 1.0 / sqrt(scal[i_norm2]);
     ROW_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         const size_t at = ROW_AT;
         r32[at] = (float)(r[at] * inv);
     }
@@ -784,7 +786,7 @@ __global__ __launch_bounds__(PT_NT) void k_add_scaled32_nat(LevelView L, int kp,
     if (!isfinite(sc)) return;
     INTERIOR_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         v[((size_t)k * L.ny + j) * L.nx + i] += sc * (double)e[sidx(L, i, j, k)];
     }
 }
@@ -812,7 +814,7 @@ __global__ __launch_bounds__(PT_NT) void k_split_to_nat(LevelView L, int kp, con
 {
     INTERIOR_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         a[((size_t)k * L.ny + j) * L.nx + i] = in[sidx(L, i, j, k)];
     }
 }
@@ -935,7 +937,7 @@ __global__ __launch_bounds__(PT_NT) void k_restrict_red(LevelView F, LevelView C
             }
             acc += wz[u][c] * plane;
         }
-        if (inside && k0 + u <= C.nz - 2) rc[sidx(C, I, J, k0 + u)] = acc;
+        if (inside && k0 + u <= C.nz - 2 && C.zint[k0 + u]) rc[sidx(C, I, J, k0 + u)] = acc;
     }
 }
 
@@ -1007,7 +1009,7 @@ __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C,
             for (int b = 0; b < 2; ++b) sacc += (b ? y.w1 : y.w0) * (w0 * va[q][c][b] + w1 * vb[q][c][b]);
             acc += (c ? z[q].w1 : z[q].w0) * sacc;
         }
-        if (k <= F.nz - 2 && (odd ? ok1 : ok0)) u[(size_t)k * plane + row] = uo[q] + acc;
+        if (k <= F.nz - 2 && F.zint[k] && (odd ? ok1 : ok0)) u[(size_t)k * plane + row] = uo[q] + acc;
     }
 }
 
@@ -1028,7 +1030,7 @@ __global__ __launch_bounds__(PT_NT) void k_prolong_add(LevelView F, int kp, Leve
     const LevelView& L = F;
     INTERIOR_LOOP
     {
-        if (!inside) continue;
+        if (!inside || !L.zint[k]) continue;
         u[sidx(F, i, j, k)] += prolong_at<T>(C, e, prolong_taps<T>(C.ax[0], i), j, k);
     }
 }
@@ -1085,7 +1087,7 @@ __device__ void t_half(const LevelView& V, T* __restrict__ u, const T* __restric
         for (int b = 0; b < TL_BATCH; ++b) {
             const int k = kb + b * cl.ng;
             const int i = ((c + j + k) & 1) + 2 * m;
-            ok[b] = k <= V.nz - 2 && i >= 1 && i <= V.nx - 2;
+            ok[b] = k <= V.nz - 2 && i >= 1 && i <= V.nx - 2 && V.zint[k];
             at[b] = 0;
             val[b] = T(0);
             if (!ok[b]) continue;
@@ -1118,12 +1120,12 @@ __device__ void t_restrict_red(const LevelView& F, const LevelView& C, const T* 
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
             const int K = kb + b * cl.ng;
-            val[b] = K <= C.nz - 2 ? restrict_red_at<T>(F, C, r, x, J, K) : T(0);
+            val[b] = K <= C.nz - 2 && C.zint[K] ? restrict_red_at<T>(F, C, r, x, J, K) : T(0);
         }
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
             const int K = kb + b * cl.ng;
-            if (K <= C.nz - 2) fc[sidx(C, I, J, K)] = val[b];
+            if (K <= C.nz - 2 && C.zint[K]) fc[sidx(C, I, J, K)] = val[b];
         }
     }
 }
@@ -1141,13 +1143,13 @@ __device__ void t_prolong(const LevelView& F, const LevelView& C, const T* __res
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
             const int k = kb + b * cl.ng;
-            const bool ok = k <= F.nz - 2 && !(red_only && ((i + j + k) & 1));
+            const bool ok = k <= F.nz - 2 && F.zint[k] && !(red_only && ((i + j + k) & 1));
             val[b] = ok ? prolong_at<T>(C, e, x, j, k) : T(0);
         }
 #pragma unroll
         for (int b = 0; b < TL_BATCH; ++b) {
             const int k = kb + b * cl.ng;
-            if (k <= F.nz - 2 && !(red_only && ((i + j + k) & 1))) u[sidx(F, i, j, k)] += val[b];
+            if (k <= F.nz - 2 && F.zint[k] && !(red_only && ((i + j + k) & 1))) u[sidx(F, i, j, k)] += val[b];
         }
     }
 }

@@ -197,6 +197,36 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
 
 using namespace lasto;
 
+// Dirichlet data on the faces of every right-hand side of the grid (bc 1:
+// multipole field of its own moments, kept in g->moments[25 b]; bc 0: zero)
+static lasto_status set_faces(lasto_grid g, const double* rho, int bc, int lmax_bc, double* v)
+{
+    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    for (int b = 0; b < g->n_batch; ++b) {
+        if (bc == 1) {
+            HIPCHK(launch_moments(g, rho + b * N, g->moments + 25 * b));
+            HIPCHK(launch_bc(g, 1, g->moments + 25 * b, lmax_bc, v + b * N));
+        } else {
+            HIPCHK(launch_bc(g, 0, g->moments, 0, v + b * N));
+        }
+    }
+    return LASTO_OK;
+}
+
+// squared W-norm of 4 pi rho - A v for each right-hand side into
+// S_BR0 + b (interior_zero: of the face data alone) or S_BRR + b
+static lasto_status batch_norms(lasto_grid g, const double* rho, const double* v, int interior_zero)
+{
+    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    const int nb = interior_blocks(g->cview);
+    for (int b = 0; b < g->n_batch; ++b) {
+        HIPCHK(launch_residual_nat(g->cview, v + b * N, rho + b * N, 4.0 * kPi, nullptr, g->partials, interior_zero,
+                                   g->stream));
+        if (lasto_status e = reduce_to(g, nb, (interior_zero ? S_BR0 : S_BRR) + b); e != LASTO_OK) return e;
+    }
+    return LASTO_OK;
+}
+
 extern "C" void lasto_solve_opts_default(lasto_solve_opts* o)
 {
     if (!o) return;
@@ -245,13 +275,10 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     const int nb_i = interior_blocks(V);
     const double fourpi = 4.0 * kPi;
 
-    // face values
-    if (o.bc == 1) {
-        HIPCHK(launch_moments(g, rho, g->moments));
-        HIPCHK(launch_bc(g, 1, g->moments, o.lmax_bc, v));
-        HIPCHK(hipMemcpyAsync(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, s));
-    } else if (o.bc == 0) {
-        HIPCHK(launch_bc(g, 0, g->moments, 0, v));
+    // face values (every right-hand side of a batch from its own moments)
+    if (o.bc == 0 || o.bc == 1) {
+        if (lasto_status e = set_faces(g, rho, o.bc, o.lmax_bc, v); e != LASTO_OK) return e;
+        if (o.bc == 1) HIPCHK(hipMemcpyAsync(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, s));
     }
     if (o.guess == 1) {
         // zero interior: copy an all-zero split array onto the interior of v
@@ -268,6 +295,17 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     const double r0sq = g->h_scalars[S_R0];
     const double r0 = std::sqrt(r0sq);
     double rel = (r0 > 0.0) ? std::sqrt(g->h_scalars[S_RR]) / r0 : 0.0;
+    // A batch iterates on the stacked system (one norm, one set of CG
+    // coefficients for all copies, which is CG on the block-diagonal system)
+    // and then checks every copy against its own reference norm.
+    const int nbat = g->n_batch;
+    double br0[kMaxBatch] = {0.0};
+    if (nbat > 1) {
+        if (lasto_status e = batch_norms(g, rho, v, 1); e != LASTO_OK) return e;
+        if (lasto_status e = read_scalars(g, S_BR0, nbat); e != LASTO_OK) return e;
+        for (int b = 0; b < nbat; ++b) br0[b] = std::sqrt(g->h_scalars[S_BR0 + b]);
+    }
+    double target = o.rtol;
     if (!std::isfinite(r0) || !std::isfinite(rel)) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: non-finite rho or v");
 
     lasto_status result = LASTO_OK;
@@ -278,7 +316,8 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     // it to v when it stops or restarts
     const bool cg = (o.precision == 0 && o.method == 0);
     if (cg) HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
-    while (rel > o.rtol && it < o.max_iters) {
+  for (;;) {
+    while (rel > target && it < o.max_iters) {
         if (o.debug_nan_iter == it)
             HIPCHK(launch_inject_nan(g->r, sidx(V, V.nx / 2, V.ny / 2, V.nz / 2), s));
         if (o.precision == 1) {
@@ -335,7 +374,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             result = LASTO_ERR_DIVERGED;
             break;
         }
-        if (rel <= o.rtol && cg) {
+        if (rel <= target && cg) {
             // the CG residual is a recurrence: fold the correction into v,
             // confirm with the true residual, and restart CG from it if the
             // two have drifted apart
@@ -348,6 +387,21 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             cg_it = 0;
         }
     }
+    if (nbat > 1 && result == LASTO_OK && rel <= target && it < o.max_iters) {
+        // every copy against its own reference norm; tighten the stacked
+        // target while one of them is still above the tolerance
+        if (lasto_status e = batch_norms(g, rho, v, 0); e != LASTO_OK) return e;
+        if (lasto_status e = read_scalars(g, S_BRR, nbat); e != LASTO_OK) return e;
+        double worst = 0.0;
+        for (int b = 0; b < nbat; ++b)
+            if (br0[b] > 0.0) worst = std::max(worst, std::sqrt(g->h_scalars[S_BRR + b]) / br0[b]);
+        if (std::isfinite(worst) && worst > o.rtol) {
+            target *= 0.5 * o.rtol / worst;
+            continue;
+        }
+    }
+    break;
+  }
     // fold any CG correction not yet in v (the loop stopped on max_iters or
     // a breakdown; x holds the last finite correction), then the true
     // residual of the returned iterate
@@ -357,6 +411,19 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     if (lasto_status e = read_scalars(g, S_TMP, 1); e != LASTO_OK) return e;
     inf.rel_resid = std::sqrt(g->h_scalars[S_TMP]) / r0;
     inf.iters = it;
+    inf.n_batch = nbat;
+    if (nbat > 1) {
+        if (lasto_status e = batch_norms(g, rho, v, 0); e != LASTO_OK) return e;
+        if (lasto_status e = read_scalars(g, S_BRR, nbat); e != LASTO_OK) return e;
+        double worst = 0.0;
+        for (int b = 0; b < nbat; ++b) {
+            inf.batch_rel_resid[b] = br0[b] > 0.0 ? std::sqrt(g->h_scalars[S_BRR + b]) / br0[b] : 0.0;
+            worst = std::max(worst, inf.batch_rel_resid[b]);
+        }
+        inf.rel_resid = std::max(inf.rel_resid, worst);
+    } else {
+        inf.batch_rel_resid[0] = inf.rel_resid;
+    }
     if (g->prof_on) {
         // read_scalars synchronised the stream: every event has completed
         double ms = 0.0;
@@ -386,14 +453,10 @@ extern "C" lasto_status lasto_boundary_values(lasto_grid g, const double* rho, i
     if (!g || !v || (bc == 1 && !rho)) return fail(LASTO_ERR_ARG, "lasto_boundary_values: NULL argument");
     if ((bc != 0 && bc != 1) || lmax_bc < 0 || lmax_bc > 4)
         return fail(LASTO_ERR_ARG, "lasto_boundary_values: bc must be 0 or 1, lmax_bc 0..4");
-    if (bc == 1) {
-        HIPCHK(launch_moments(g, rho, g->moments));
-        HIPCHK(launch_bc(g, 1, g->moments, lmax_bc, v));
-        if (moments_out)
-            HIPCHK(hipMemcpyAsync(moments_out, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, g->stream));
-    } else {
-        HIPCHK(launch_bc(g, 0, g->moments, 0, v));
-    }
+    if (lasto_status e = set_faces(g, rho, bc, lmax_bc, v); e != LASTO_OK) return e;
+    if (moments_out && bc == 1)
+        HIPCHK(hipMemcpyAsync(moments_out, g->moments, sizeof(double) * 25 * g->n_batch, hipMemcpyDeviceToHost,
+                              g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
     return LASTO_OK;
 }
@@ -427,6 +490,7 @@ extern "C" lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const dou
                                             int* accepted)
 {
     if (!g || !n || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_learned_guess: NULL argument");
+    if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_learned_guess: one right-hand side per grid");
     const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
     const size_t nn = (size_t)V.nx * V.ny * V.nz;

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(AP_NT) void k_atom_prep(LevelView L, AtomDev* atoms
 
 hipError_t launch_atom_prep(lasto_grid g, AtomDev* atoms, int n_atoms, int renormalize)
 {
-    hipLaunchKernelGGL(k_atom_prep, dim3(n_atoms), dim3(AP_NT), 0, g->stream, g->lev[0].view, atoms, n_atoms,
+    hipLaunchKernelGGL(k_atom_prep, dim3(n_atoms), dim3(AP_NT), 0, g->stream, g->cview, atoms, n_atoms,
                        renormalize);
     return hipGetLastError();
 }
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(PS_NT) void k_pseudo(LevelView L, const AtomDev* __
 
 hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const double* rho_inter, double* rho)
 {
-    const LevelView& L = g->lev[0].view;
+    const LevelView& L = g->cview;   // one right-hand side of a batch
     const dim3 grid((L.nx + PS_X - 1) / PS_X, (L.ny + PS_Y - 1) / PS_Y, (L.nz + PS_Z - 1) / PS_Z);
     hipLaunchKernelGGL(k_pseudo, grid, dim3(PS_NT), 0, g->stream, L, atoms, n_atoms, rho_inter, rho);
     return hipGetLastError();
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void k_guess(LevelView L, const AtomDev* __res
 
 hipError_t launch_guess(lasto_grid g, const AtomDev* atoms, int n_atoms, double* v)
 {
-    const LevelView& L = g->lev[0].view;
+    const LevelView& L = g->cview;   // one right-hand side of a batch
     const dim3 grid((L.nx - 2 + 63) / 64, (L.ny - 2 + 3) / 4, (L.nz - 2 + 3) / 4);
     hipLaunchKernelGGL(k_guess, grid, dim3(256), 0, g->stream, L, atoms, n_atoms, v);
     return hipGetLastError();
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(MO_NT) void k_moments(LevelView L, const double* __
 
 hipError_t launch_moments(lasto_grid g, const double* rho, double* Q)
 {
-    const LevelView& L = g->lev[0].view;
+    const LevelView& L = g->cview;   // one right-hand side of a batch
     hipLaunchKernelGGL(k_moments, dim3(kReduceBlocks), dim3(MO_NT), 0, g->stream, L, rho, g->box_center[0],
                        g->box_center[1], g->box_center[2], g->partials);
     hipError_t e = hipGetLastError();
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void k_bc(LevelView L, int mode, const double*
 
 hipError_t launch_bc(lasto_grid g, int mode, const double* Q, int lmax_bc, double* v)
 {
-    const LevelView& L = g->lev[0].view;
+    const LevelView& L = g->cview;   // one right-hand side of a batch
     const size_t total = 2 * ((size_t)L.nx * L.ny + (size_t)L.nx * L.nz + (size_t)L.ny * L.nz);
     hipLaunchKernelGGL(k_bc, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, g->stream, L, mode, Q, lmax_bc,
                        g->box_center[0], g->box_center[1], g->box_center[2], v);
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(64) void k_interp(LevelView L, const double* __rest
 
 hipError_t launch_interp(lasto_grid g, const double* v, const double* pts, int npts, double* out)
 {
-    const LevelView& L = g->lev[0].view;
+    const LevelView& L = g->cview;   // one right-hand side of a batch
     hipLaunchKernelGGL(k_interp, dim3((npts + 63) / 64), dim3(64), 0, g->stream, L, v, pts, npts, out);
     return hipGetLastError();
 }

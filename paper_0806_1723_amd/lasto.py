@@ -69,6 +69,8 @@ class SolveInfo(C.Structure):
         ("smooth_ms", C.c_double),
         ("smooth_bytes", C.c_double),
         ("smooth_fp32", C.c_int),
+        ("n_batch", C.c_int),
+        ("batch_rel_resid", C.c_double * 16),
     ]
 
     def as_dict(self) -> dict:
@@ -77,7 +79,8 @@ class SolveInfo(C.Structure):
                     rel_resid=self.rel_resid, resid_hist=list(self.resid_hist[:n]),
                     moments=list(self.moments), ms_total=self.ms_total,
                     smooth_launches=self.smooth_launches, smooth_ms=self.smooth_ms,
-                    smooth_bytes=self.smooth_bytes, smooth_fp32=self.smooth_fp32)
+                    smooth_bytes=self.smooth_bytes, smooth_fp32=self.smooth_fp32,
+                    batch_rel_resid=list(self.batch_rel_resid[:max(self.n_batch, 1)]))
 
 
 # exported names, in header order
@@ -256,7 +259,9 @@ class Grid:
         _check(load().lasto_grid_create(_np_ptr(xs), len(xs), _np_ptr(ys), len(ys), _np_ptr(zs), len(zs),
                                         n_batch, C.c_void_p(sp), C.byref(h)))
         self.h = h
-        self.shape = (len(zs), len(ys), len(xs))
+        self.n_batch = n_batch
+        self.copy_shape = (len(zs), len(ys), len(xs))
+        self.shape = self.copy_shape if n_batch == 1 else (n_batch,) + self.copy_shape
 
     def close(self):
         if getattr(self, "h", None):
@@ -283,14 +288,24 @@ class Grid:
         import torch
         return torch.zeros(self.shape, dtype=torch.float64, device="cuda")
 
+    def _atom_table(self, atoms):
+        """A flat atom table: one list per right-hand side for a batch (equal lengths)."""
+        if self.n_batch == 1:
+            return make_atoms(atoms), len(atoms)
+        if len(atoms) != self.n_batch or len({len(a) for a in atoms}) != 1:
+            raise ValueError("a batched grid needs one atom list per right-hand side, all of one length")
+        return make_atoms([a for lst in atoms for a in lst]), len(atoms[0])
+
     def pseudo_density(self, atoms, rho_out=None, rho_interstitial=None, renormalize=True, moments=False):
-        arr = make_atoms(atoms)
+        arr, na = self._atom_table(atoms)
         if rho_out is None:
             rho_out = self.empty()
-        Q = np.zeros(25)
-        _check(load().lasto_pseudo_density(self.h, len(atoms), C.cast(arr, C.c_void_p),
+        Q = np.zeros((self.n_batch, 25))
+        _check(load().lasto_pseudo_density(self.h, na, C.cast(arr, C.c_void_p),
                                            None if rho_interstitial is None else _dev_ptr(rho_interstitial),
                                            int(renormalize), _dev_ptr(rho_out), _np_ptr(Q) if moments else None))
+        if self.n_batch == 1:
+            Q = Q[0]
         return (rho_out, Q) if moments else rho_out
 
     def poisson_solve(self, rho, v, allow_fail: bool = False, **opts):
@@ -314,10 +329,10 @@ class Grid:
             dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
             nd = len(dirs)
             dp = _np_ptr(dirs)
-        out = np.zeros((na, nd))
+        out = np.zeros((self.n_batch, na, nd))
         _check(load().lasto_sphere_interp(self.h, _dev_ptr(v), na, _np_ptr(centers), _np_ptr(radii), nd, dp,
                                           _np_ptr(out)))
-        return out
+        return out[0] if self.n_batch == 1 else out
 
     def apply(self, u, Au=None):
         if Au is None:
@@ -332,13 +347,13 @@ class Grid:
         return u_out
 
     def boundary_values(self, rho, v, bc: int = 1, lmax_bc: int = 4):
-        Q = np.zeros(25)
+        Q = np.zeros((self.n_batch, 25))
         _check(load().lasto_boundary_values(self.h, _dev_ptr(rho), bc, lmax_bc, _dev_ptr(v), _np_ptr(Q)))
-        return Q
+        return Q[0] if self.n_batch == 1 else Q
 
     def analytic_guess(self, atoms, v):
-        arr = make_atoms(atoms)
-        _check(load().lasto_analytic_guess(self.h, len(atoms), C.cast(arr, C.c_void_p), _dev_ptr(v)))
+        arr, na = self._atom_table(atoms)
+        _check(load().lasto_analytic_guess(self.h, na, C.cast(arr, C.c_void_p), _dev_ptr(v)))
         return v
 
     def learned_guess(self, net: "Net", rho, v):

@@ -199,6 +199,64 @@ def test_solve_ragged_noncubic_zero_faces(torch, L, oracle_mod):
     g.close()
 
 
+# -------------------------------------------------------------- batches
+BATCH_OPTS = [dict(), dict(precision=1), dict(method=1), dict(precision=1, method=1)]
+
+
+@pytest.mark.parametrize("opts", BATCH_OPTS)
+def test_batched_solve_matches_oracle_per_copy(torch, L, oracle_mod, opts):
+    """Three right-hand sides (SCF-like perturbations of the 13-atom cluster)
+    stacked in one grid: every copy matches the oracle's solve of that copy."""
+    say("batched solve, 3 x config 2 n=65 %s" % opts)
+    w = I.config(2, n_override=65)
+    xs = oracle_mod.mesh_for(w.axes)
+    batch = [w.atoms] + [I.perturb_atoms(w.atoms, 700 + b) for b in range(2)]
+    g = L.Grid(*xs, n_batch=3)
+    rho, Q = g.pseudo_density(batch, moments=True)
+    assert tuple(rho.shape) == (3, 65, 65, 65) and Q.shape == (3, 25)
+    v = g.empty()
+    info = g.poisson_solve(rho, v, rtol=1e-12, **opts)
+    say("  iters %d vcycles %d per-copy rel %s" % (info["iters"], info["vcycles"], info["batch_rel_resid"]))
+    assert len(info["batch_rel_resid"]) == 3 and max(info["batch_rel_resid"]) <= 1e-12
+    got = v.cpu().numpy()
+    for b, atoms in enumerate(batch):
+        rho_o, v_o = oracle_solution(oracle_mod, xs, atoms)
+        assert np.abs(rho[b].cpu().numpy() - rho_o).max() <= 1e-12 * np.abs(rho_o).max()
+        assert np.abs(Q[b] - oracle_mod.moments(xs, rho_o, 4)).max() <= 1e-11 * np.abs(Q[b]).max()
+        err = wnorm(xs, got[b] - v_o) / wnorm(xs, v_o)
+        say("  copy %d: rel W-norm error vs oracle %.3e" % (b, err))
+        assert err <= 1e-9
+        assert oracle_mod.rel_residual(xs, rho_o, got[b]) <= 2e-12
+    # the batch's sphere values are each copy's own
+    centers = np.array([a.center for a in w.atoms])
+    radii = np.array([a.radius for a in w.atoms])
+    sph = g.sphere_interp(v, centers, radii)
+    assert sph.shape == (3, 13, 64)
+    pts = oracle_mod.sphere_points(centers, radii, I.default_directions())
+    for b in range(3):
+        want = oracle_mod.interp(xs, got[b], pts).reshape(13, 64)
+        assert np.abs(sph[b] - want).max() <= 1e-13 * np.abs(want).max()
+    g.close()
+
+
+def test_batched_operator_and_sweep_match_oracle(torch, L, oracle_mod):
+    say("batched apply / rb_sweep (2 copies, ragged)")
+    rng = np.random.default_rng(31)
+    xs = [graded(rng, n) for n in (37, 21, 18)]
+    u = rng.normal(size=(2, 18, 21, 37))
+    rho = rng.normal(size=(2, 18, 21, 37))
+    g = L.Grid(*xs, n_batch=2)
+    Au = g.apply(to_dev(torch, u)).cpu().numpy()
+    sw = g.rb_sweep(to_dev(torch, u), to_dev(torch, rho)).cpu().numpy()
+    I_ = (slice(1, -1),) * 3
+    for b in range(2):
+        want = oracle_mod.apply(xs, u[b])
+        assert np.abs(Au[b][I_] - want[I_]).max() <= 1e-13 * np.abs(want[I_]).max()
+        want = oracle_mod.rb_sweep(xs, u[b], rho[b], 0)
+        assert np.abs(sw[b] - want).max() <= 1e-12 * np.abs(want).max()
+    g.close()
+
+
 def test_levels_match_oracle_hierarchy(torch, L, oracle_mod):
     w = I.config(3)
     xs = oracle_mod.mesh_for(w.axes)
