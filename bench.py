@@ -86,17 +86,19 @@ def main():
     xs = lasto.mesh_for(w.axes)
     n = len(xs[0])
     mixed = 1 if w.precision == "mixed" else 0
-    g = lasto.Grid(*xs)
+    nb = w.n_batch
+    g = lasto.Grid(*xs, n_batch=nb)
     log("bench: %s, levels %s" % (w.name, [l[0] for l in g.levels()]))
     rho = g.empty()
     v = g.empty()
+    atoms = w.batch_atoms if nb > 1 else w.atoms
     centers = np.array([a.center for a in w.atoms])
     radii = np.array([a.radius for a in w.atoms])
 
     form = dict(precision=mixed, method=0, inner_iters=6, nu1=2, nu2=2)
 
     def step(profile, precision):
-        g.pseudo_density(w.atoms, rho_out=rho)
+        g.pseudo_density(atoms, rho_out=rho)
         v.zero_()
         opts = dict(form, precision=precision)
         info = g.poisson_solve(rho, v, rtol=w.rtol, profile=profile, **opts)
@@ -141,7 +143,7 @@ def main():
     # algorithmic bytes of one launch (a half-sweep), per interior node of the
     # grid: 12 B (FP64) or 6 B (FP32) for a half-sweep that reads the other
     # colour, f and writes its own colour (24 / 12 B per full sweep)
-    interior = (n - 2) ** 3
+    interior = (n - 2) ** 3 * nb
     sm_bpp = (sm_bytes / launches / interior) if launches else 0.0
     traffic = None
     form_key = (form["precision"], form["method"], form["inner_iters"], form["nu1"], form["nu2"])
@@ -161,11 +163,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": n, "atoms": len(w.atoms), "rtol": w.rtol,
+        "config": {"workload": w.name, "n": n, "atoms": len(w.atoms), "rtol": w.rtol, "right_hand_sides": nb,
                    "form": "fp32 V-cycles in fp64 refinement" if mixed else "fp64",
                    "parallelism": "single GPU"},
         "solve": {"iters": last["iters"], "vcycles": last["vcycles"], "refinements": last["refinements"],
-                  "rel_resid": last["rel_resid"]},
+                  "rel_resid": last["rel_resid"], "per_rhs_rel_resid": last["batch_rel_resid"],
+                  "ms_per_rhs": round(solve_ms / nb, 4)},
         "fp64_solve_ms": round(fp64_ms, 4),
         "fp64_iters": fp64[-1]["iters"],
         "fp64_smoother_gbs": round(fp64_gbs, 1),
@@ -180,7 +183,10 @@ def main():
     }
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, xs, rho.cpu().numpy(), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, xs, (rho[0] if nb > 1 else rho).cpu().numpy(), args.cpu_seconds)
+        if nb > 1:
+            out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"] * nb, 1)
+            out["cpu_baseline"]["sample"] += "; times %d right-hand sides" % nb
     g.close()
     print(json.dumps(out), flush=True)
 

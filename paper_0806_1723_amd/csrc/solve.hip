@@ -58,7 +58,7 @@ static hipError_t half(lasto_grid g, int l, T* u, const T* f, int colour, int ze
     if (err != hipSuccess) return err;
     // algorithmic bytes: half the interior nodes read f and (unless the
     // other colour is zero) one other-colour value, and write their own value
-    const double pts = 0.5 * (double)(V.nx - 2) * (V.ny - 2) * (V.nz - 2);
+    const double pts = 0.5 * (double)(V.nx - 2) * (V.ny - 2) * (V.nzc - 2) * (V.nz / V.nzc);
     g->prof_bytes += pts * sizeof(T) * (zero_in ? 2.0 : 3.0);
     if (sizeof(T) == 4) g->prof_fp32++;
     g->prof_used++;
