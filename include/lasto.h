@@ -326,6 +326,25 @@ lasto_status lasto_net_train_step(lasto_net n, const uint16_t* x, const float* t
 lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
                                  int* accepted);
 
+/*
+ * Learned correction of an iterate (the learned coarse correction): a net
+ * maps the residual r = 4 pi rho - A v, scaled to unit RMS s = ||r||_W /
+ * sqrt(sum vol), to the error; the candidate v + s * out_scale * net(r / s)
+ * and v itself each get one red-black sweep, and the one with the smaller
+ * relative residual is returned in v (rel, accepted as for
+ * lasto_learned_guess). Between cycles of a stationary solve this removes
+ * the smooth error a V-cycle reduces slowly, when the net has learned it.
+ * Features: channel 0 = (r / s) * rho_scale, 1..3 as lasto_net_features,
+ * 4 = 0, 5 = face indicator. One right-hand side per grid; uses the grid's
+ * solver scratch. Errors: LASTO_ERR_ARG, LASTO_ERR_HIP.
+ */
+lasto_status lasto_learned_correction(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
+                                      int* accepted);
+/* the correction net's features for iterate v (x as for lasto_net_features);
+ * *r_scale (host) receives s. Errors: LASTO_ERR_ARG (zero residual), LASTO_ERR_HIP. */
+lasto_status lasto_net_correction_features(lasto_grid g, lasto_net n, const double* rho, const double* v,
+                                           uint16_t* x, double* r_scale);
+
 #ifdef __cplusplus
 }
 #endif

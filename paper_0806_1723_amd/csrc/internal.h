@@ -299,7 +299,9 @@ hipError_t launch_add_f32_nat(const LevelView& L, double* v, const float* y, dou
 // learned guess: features of (rho, v) and the net's forward pass on the grid's
 // stream; *y is the net's output buffer (finest-level nodes, FP32)
 lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, const double* v, const float** y,
-                               double* out_scale);
+                               double* out_scale, double rho_mul = 1.0);
+lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x,
+                                double rho_mul);
 hipError_t launch_interp(lasto_grid g, const double* v, const double* pts, int npts, double* out);
 
 // device table block builder

@@ -379,14 +379,15 @@ __global__ void k_features(LevelView L, const double* __restrict__ rho, const do
     }
 }
 
-lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x)
+lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x,
+                                double rho_mul)
 {
     const LevelView& L = g->lev[0].view;
     if (L.nx != n->dim[0][0] || L.ny != n->dim[0][1] || L.nz != n->dim[0][2])
         return fail(LASTO_ERR_ARG, "lasto_net: the net's grid does not match the grid's finest level");
     const long nv = (long)L.nx * L.ny * L.nz;
     hipLaunchKernelGGL(k_features, dim3((unsigned)std::min<long>((nv + 255) / 256, 16384)), dim3(256), 0, g->stream, L,
-                       rho, v, n->cfg.rho_scale, n->cfg.pot_scale, n->cfg.h_ref, x);
+                       rho, v, n->cfg.rho_scale * rho_mul, n->cfg.pot_scale, n->cfg.h_ref, x);
     NCHK(hipGetLastError());
     return LASTO_OK;
 }
@@ -394,13 +395,13 @@ lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, co
 // features and forward pass on the grid's stream (the net's own stream is
 // synchronised first); *y receives the net's output buffer
 lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, const double* v, const float** y,
-                               double* out_scale)
+                               double* out_scale, double rho_mul)
 {
     if (!n->xin) {
         if (lasto_status st = nalloc(n, &n->xin, (size_t)n->nvox[0] * kInFeatures); st != LASTO_OK) return st;
     }
     NCHK(hipStreamSynchronize(n->stream));
-    if (lasto_status st = net_features_async(g, n, rho, v, n->xin); st != LASTO_OK) return st;
+    if (lasto_status st = net_features_async(g, n, rho, v, n->xin, rho_mul); st != LASTO_OK) return st;
     hipStream_t keep = n->stream;
     n->stream = g->stream;
     lasto_status st = net_forward_async(n, n->xin, n->y);
@@ -416,7 +417,7 @@ lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, con
 extern "C" lasto_status lasto_net_features(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x)
 {
     if (!g || !n || !rho || !v || !x) return net_fail(LASTO_ERR_ARG, "lasto_net_features: NULL argument");
-    if (lasto_status st = lasto::net_features_async(g, n, rho, v, x); st != LASTO_OK) return st;
+    if (lasto_status st = lasto::net_features_async(g, n, rho, v, x, 1.0); st != LASTO_OK) return st;
     NCHK(hipStreamSynchronize(g->stream));
     return LASTO_OK;
 }

@@ -527,6 +527,92 @@ extern "C" lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const dou
     return LASTO_OK;
 }
 
+// The residual r = 4 pi rho - A v in natural layout (g->x, faces zero) and
+// its RMS over the interior, s = ||r||_W / sqrt(sum vol); the zero array the
+// correction net reads for its potential channel is g->p[1].
+static lasto_status correction_input(lasto_grid g, const double* rho, const double* v, double* s_r)
+{
+    const LevelView& V = g->lev[0].view;
+    hipStream_t s = g->stream;
+    HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
+    HIPCHK(launch_fill_zero<double>(g->p[1], split_elems(V), s));
+    HIPCHK(launch_residual_nat(V, v, rho, 4.0 * kPi, g->r, g->partials, 0, s));
+    if (lasto_status e = reduce_to(g, interior_blocks(V), S_TMP); e != LASTO_OK) return e;
+    HIPCHK(launch_split_to_nat(V, g->r, g->x, s));
+    HIPCHK(launch_fill_zero<double>(g->r, split_elems(V), s));
+    if (lasto_status e = read_scalars(g, S_TMP, 1); e != LASTO_OK) return e;
+    double vol = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        const std::vector<double>& x = g->lev[0].hx[d];
+        vol *= x[x.size() - 2] - x[1] + 0.5 * (x[1] - x[0]) + 0.5 * (x[x.size() - 1] - x[x.size() - 2]);
+    }
+    *s_r = std::sqrt(g->h_scalars[S_TMP] / vol);
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_correction_features(lasto_grid g, lasto_net n, const double* rho, const double* v,
+                                                      uint16_t* x, double* r_scale)
+{
+    if (!g || !n || !rho || !v || !x || !r_scale)
+        return fail(LASTO_ERR_ARG, "lasto_net_correction_features: NULL argument");
+    if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_net_correction_features: one right-hand side per grid");
+    double sr = 0.0;
+    if (lasto_status e = correction_input(g, rho, v, &sr); e != LASTO_OK) return e;
+    if (!(sr > 0.0) || !std::isfinite(sr)) return fail(LASTO_ERR_ARG, "lasto_net_correction_features: zero residual");
+    if (lasto_status e = net_features_async(g, n, g->x, g->p[1], x, 1.0 / sr); e != LASTO_OK) return e;
+    const LevelView& V = g->lev[0].view;
+    HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), g->stream));
+    HIPCHK(launch_fill_zero<double>(g->p[1], split_elems(V), g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    *r_scale = sr;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_learned_correction(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
+                                                 int* accepted)
+{
+    if (!g || !n || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_learned_correction: NULL argument");
+    if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_learned_correction: one right-hand side per grid");
+    const LevelView& V = g->lev[0].view;
+    hipStream_t s = g->stream;
+    const size_t nn = (size_t)V.nx * V.ny * V.nz;
+    if (split_elems(V) < nn) return fail(LASTO_ERR_STATE, "lasto_learned_correction: scratch too small");
+    if (lasto_status e = resid_norm2(g, rho, v, 1, S_R0); e != LASTO_OK) return e;
+    double sr = 0.0;
+    if (lasto_status e = correction_input(g, rho, v, &sr); e != LASTO_OK) return e;
+    double* keep_plain = g->q;
+    double* keep_learned = g->x;
+    HIPCHK(hipMemcpyAsync(keep_plain, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    const bool live = sr > 0.0 && std::isfinite(sr);
+    if (live) {
+        const float* y = nullptr;
+        double out_scale = 0.0;
+        if (lasto_status e = net_guess_forward(g, n, g->x, g->p[1], &y, &out_scale, 1.0 / sr); e != LASTO_OK)
+            return e;
+        HIPCHK(launch_add_f32_nat(V, v, y, out_scale * sr, s));
+    }
+    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
+    if (lasto_status e = resid_norm2(g, rho, v, 0, S_TMP); e != LASTO_OK) return e;
+    HIPCHK(hipMemcpyAsync(keep_learned, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(v, keep_plain, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
+    if (lasto_status e = resid_norm2(g, rho, v, 0, S_RR); e != LASTO_OK) return e;
+    if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
+    const double r0 = std::sqrt(g->h_scalars[S_R0]);
+    const double plain = r0 > 0.0 ? std::sqrt(g->h_scalars[S_RR]) / r0 : 0.0;
+    const double learned = r0 > 0.0 ? std::sqrt(g->h_scalars[S_TMP]) / r0 : 0.0;
+    const bool keep = live && std::isfinite(learned) && learned < plain;
+    if (keep) HIPCHK(hipMemcpyAsync(v, keep_learned, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    for (double* a : {g->x, g->p[0], g->p[1], g->z, g->q}) HIPCHK(launch_fill_zero<double>(a, split_elems(V), s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (rel) {
+        rel[0] = plain;
+        rel[1] = learned;
+    }
+    if (accepted) *accepted = keep ? 1 : 0;
+    return LASTO_OK;
+}
+
 extern "C" lasto_status lasto_apply(lasto_grid g, const double* u, double* Au)
 {
     if (!g || !u || !Au || u == Au) return fail(LASTO_ERR_ARG, "lasto_apply: NULL or aliased buffers");

@@ -91,7 +91,7 @@ SYMBOLS = [
     "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess", "lasto_net_create", "lasto_net_destroy",
     "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
     "lasto_net_features", "lasto_net_forward", "lasto_net_backward", "lasto_net_adam_step",
-    "lasto_net_train_step", "lasto_learned_guess",
+    "lasto_net_train_step", "lasto_learned_guess", "lasto_learned_correction", "lasto_net_correction_features",
 ]
 
 
@@ -172,6 +172,10 @@ def load():
     L.lasto_net_train_step.restype = i
     L.lasto_learned_guess.argtypes = [P, P, P, P, P, C.POINTER(i)]
     L.lasto_learned_guess.restype = i
+    L.lasto_learned_correction.argtypes = [P, P, P, P, P, C.POINTER(i)]
+    L.lasto_learned_correction.restype = i
+    L.lasto_net_correction_features.argtypes = [P, P, P, P, P, C.POINTER(d)]
+    L.lasto_net_correction_features.restype = i
     _lib = L
     return L
 
@@ -357,10 +361,17 @@ class Grid:
         return v
 
     def learned_guess(self, net: "Net", rho, v):
-        rel = np.zeros(2)
-        acc = C.c_int()
-        _check(load().lasto_learned_guess(self.h, net.h, _dev_ptr(rho), _dev_ptr(v), _np_ptr(rel), C.byref(acc)))
-        return dict(rel_before=float(rel[0]), rel_after=float(rel[1]), accepted=bool(acc.value))
+        return _learned_call(load().lasto_learned_guess, self, net, rho, v)
+
+    def learned_correction(self, net: "Net", rho, v):
+        return _learned_call(load().lasto_learned_correction, self, net, rho, v)
+
+
+def _learned_call(fn, grid, net, rho, v):
+    rel = np.zeros(2)
+    acc = C.c_int()
+    _check(fn(grid.h, net.h, _dev_ptr(rho), _dev_ptr(v), _np_ptr(rel), C.byref(acc)))
+    return dict(rel_before=float(rel[0]), rel_after=float(rel[1]), accepted=bool(acc.value))
 
 
 class Net:
@@ -420,6 +431,16 @@ class Net:
             x = torch.zeros(self.shape + (8,), dtype=torch.int16, device="cuda")
         _check(load().lasto_net_features(grid.h, self.h, _dev_ptr(rho), _dev_ptr(v), _dev_ptr(x, torch.int16)))
         return x
+
+    def correction_features(self, grid: Grid, rho, v, x=None):
+        """(features of iterate v for the correction net, residual RMS s)"""
+        import torch
+        if x is None:
+            x = torch.zeros(self.shape + (8,), dtype=torch.int16, device="cuda")
+        s = C.c_double()
+        _check(load().lasto_net_correction_features(grid.h, self.h, _dev_ptr(rho), _dev_ptr(v),
+                                                    _dev_ptr(x, torch.int16), C.byref(s)))
+        return x, s.value
 
     def forward(self, x, y=None):
         import torch

@@ -23,6 +23,9 @@ from . import lasto
 # feature and output scales of the net (fixed, from the statistics of the
 # config-4 problems: densities up to ~15, potentials ~ -100, corrections ~ 0.1)
 NET_SCALES = dict(rho_scale=0.1, pot_scale=0.01, h_ref=0.25, out_scale=0.1)
+# the correction net reads the residual at unit RMS and returns the error in
+# units of out_scale * RMS (smooth errors are ~ (L / pi)^2 ~ 200 times the residual)
+CORRECTION_SCALES = dict(rho_scale=1.0, pot_scale=0.01, h_ref=0.25, out_scale=100.0)
 
 
 @dataclasses.dataclass
@@ -121,3 +124,57 @@ def compare(net: "lasto.Net", p: Problem, rtol: float = 1e-10, **opts) -> dict:
         out[kind], v = timed(kind)
     out["err_vs_label"] = float((v - p.v_star).abs().max() / p.v_star.abs().max())
     return out
+
+
+def _vol_weights(grid, like):
+    import torch
+    m = [np.zeros_like(c) for c in grid.coords]
+    for c, mm in zip(grid.coords, m):
+        mm[1:-1] = 0.5 * (c[2:] - c[:-2])
+    vol = np.einsum("k,j,i->kji", m[2], m[1], m[0])
+    wt = torch.from_numpy(vol.astype(np.float32)).to(like.device)
+    return (wt / wt.sum()).contiguous()
+
+
+def correction_pairs(net: "lasto.Net", p: Problem, cycles=(1, 2, 3)):
+    """Training pairs of the correction net from the solver's own iterates:
+    after k stationary V-cycles from the analytic guess, the features of the
+    iterate and its error (v* - v_k) in units of out_scale times the residual
+    RMS."""
+    import torch
+    pairs = []
+    for k in cycles:
+        v = p.v_guess.clone()
+        p.grid.poisson_solve(p.rho, v, rtol=1e-14, bc=2, method=1, max_iters=k, allow_fail=True)
+        x, s = net.correction_features(p.grid, p.rho, v)
+        t = ((p.v_star - v) / (net.cfg.out_scale * s)).to(torch.float32).contiguous()
+        pairs.append((x, t, _vol_weights(p.grid, t)))
+    return pairs
+
+
+def train_pairs(net: "lasto.Net", pairs, steps: int, lr: float = 2e-3):
+    hist = []
+    for s in range(steps):
+        x, t, wt = pairs[s % len(pairs)]
+        a = lr * 0.5 * (1.0 + np.cos(np.pi * s / max(steps, 1)))
+        hist.append(net.train_step(x, t, wt, max(a, lr * 1e-3)))
+    return hist
+
+
+def corrected_cycles(p: Problem, net_c, rtol: float = 1e-10, max_cycles: int = 60) -> dict:
+    """Stationary V-cycles from the analytic guess, with (net_c given) or
+    without a learned correction before each cycle; cycles to rtol."""
+    import torch
+    v = p.v_guess.clone()
+    acc, rel = 0, 1.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(1, max_cycles + 1):
+        if net_c is not None:
+            acc += p.grid.learned_correction(net_c, p.rho, v)["accepted"]
+        info = p.grid.poisson_solve(p.rho, v, rtol=rtol, bc=2, method=1, max_iters=1, allow_fail=True)
+        rel = info["rel_resid"]
+        if rel <= rtol:
+            break
+    torch.cuda.synchronize()
+    return dict(cycles=c, accepted=acc, rel_resid=rel, ms=(time.perf_counter() - t0) * 1e3)
