@@ -73,6 +73,9 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.config == 4:
+        bench_learned(args)
+        return
 
     import numpy as np
     import torch
@@ -217,6 +220,104 @@ def cpu_baseline(w, xs, rho, min_seconds):
     return {"value": round(ms, 1), "unit": "ms", "cores": cores, "kind": "oracle",
             "sample": "%d whole FP64 solves of the %d^3 problem to %.0e (%d V(2,2) cycles each, %.1f s in "
                       "all); median per solve" % (len(times), len(xs[0]), w.rtol, cyc, total)}
+
+
+def conv_flops(shape, ch):
+    """Multiply-add flops (2 per MAC) of the learned net's forward pass."""
+    n = list(shape)
+    dims = []
+    for _ in range(4):
+        dims.append(n[0] * n[1] * n[2])
+        n = [(a + 1) // 2 for a in n]
+    c0, c1, c2, c3 = ch
+    layers = [(8, c0, 0), (c0, c1, 1), (c1, c2, 2), (c2, c3, 3), (c3, c3, 3), (c3, c2, 3), (c2, c1, 2), (c1, c0, 1)]
+    return sum(2 * 27 * ci * co * dims[l] for ci, co, l in layers) + 2 * c0 * dims[0]
+
+
+def bench_learned(args):
+    """Config 4: the learned initial guess and the learned correction against
+    plain multigrid on held-out random clusters at 129^3 (nets trained first,
+    on the GPU, by the library's own kernels)."""
+    import numpy as np
+    import torch
+
+    from paper_0806_1723_amd import lasto, learned
+    lasto.load()
+    n = args.n or 129
+    ntrain, ntest = 16, 4
+    t0 = time.perf_counter()
+    train_p = [learned.make_problem(4, s, n) for s in range(ntrain)]
+    test_p = [learned.make_problem(4, 1000 + s, n) for s in range(ntest)]
+    log("bench: %d training and %d test problems at %d^3 in %.1f s" % (ntrain, ntest, n, time.perf_counter() - t0))
+    ch = (16, 32, 32, 32)
+    net = lasto.Net((n, n, n), ch=ch, seed=7, **learned.NET_SCALES)
+    t0 = time.perf_counter()
+    hist = learned.train(net, train_p, steps=1600, lr=2e-3)
+    torch.cuda.synchronize()
+    t_guess = time.perf_counter() - t0
+    net_c = lasto.Net((n, n, n), ch=ch, seed=9, **learned.CORRECTION_SCALES)
+    pairs = [pp for p in train_p for pp in learned.correction_pairs(net_c, p, (1, 2, 3))]
+    t0 = time.perf_counter()
+    hist_c = learned.train_pairs(net_c, pairs, steps=2400, lr=2e-3)
+    torch.cuda.synchronize()
+    t_corr = time.perf_counter() - t0
+    log("bench: trained guess net %.1f s (loss %.3e -> %.3e), correction net %.1f s (loss %.3e -> %.3e)" % (
+        t_guess, np.mean(hist[:ntrain]), np.mean(hist[-ntrain:]), t_corr, np.mean(hist_c[:len(pairs)]),
+        np.mean(hist_c[-len(pairs):])))
+    # forward-pass time and matrix-core rate of the net
+    x = net.features(test_p[0].grid, test_p[0].rho, test_p[0].v_guess)
+    y = torch.zeros((n, n, n), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        net.forward(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        net.forward(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+    flops = conv_flops((n, n, n), ch)
+    rows = []
+    for p in test_p:
+        for _ in range(2):   # second pass timed warm
+            r = learned.compare(net, p, rtol=1e-10)
+        a = learned.corrected_cycles(p, None)
+        b = learned.corrected_cycles(p, net_c)
+        rows.append((r, a, b))
+        log("bench: %s zero %d/%.2f ms analytic %d/%.2f ms learned %d/%.2f ms (accepted %s) | stationary plain %d/%.2f ms"
+            " corrected %d/%.2f ms" % (p.name[:28], r["zero"]["iters"], r["zero"]["ms"], r["analytic"]["iters"],
+                                       r["analytic"]["ms"], r["learned"]["iters"], r["learned"]["ms"],
+                                       r["learned"]["accepted"], a["cycles"], a["ms"], b["cycles"], b["ms"]))
+    med = lambda v: round(float(statistics.median(v)), 3)
+    out = {
+        "metric": "time-to-1e-10-residual per Poisson solve: learned guess vs plain multigrid (V-cycles saved)",
+        "value": med([r["learned"]["ms"] for r, _, _ in rows]),
+        "unit": "ms",
+        "n_gpus": 1, "steps": ntest, "warmup": 1,
+        "ms_per_step": med([r["learned"]["ms"] for r, _, _ in rows]),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 net + f64 solve",
+        "data": "synthetic",
+        "config": {"workload": "random 13-55-atom clusters (seeds 40000+s), graded %d^3, L=48" % n,
+                   "train_problems": ntrain, "test_problems": ntest, "net_channels": list(ch),
+                   "parallelism": "single GPU"},
+        "pcg_iters": {"zero": [r["zero"]["iters"] for r, _, _ in rows],
+                      "analytic": [r["analytic"]["iters"] for r, _, _ in rows],
+                      "learned": [r["learned"]["iters"] for r, _, _ in rows]},
+        "pcg_ms": {"zero": med([r["zero"]["ms"] for r, _, _ in rows]),
+                   "analytic": med([r["analytic"]["ms"] for r, _, _ in rows]),
+                   "learned": med([r["learned"]["ms"] for r, _, _ in rows])},
+        "learned_guess_accepted": [bool(r["learned"]["accepted"]) for r, _, _ in rows],
+        "stationary_cycles": {"plain": [a["cycles"] for _, a, _ in rows],
+                              "learned_correction": [b["cycles"] for _, _, b in rows]},
+        "stationary_ms": {"plain": med([a["ms"] for _, a, _ in rows]),
+                          "learned_correction": med([b["ms"] for _, _, b in rows])},
+        "training_s": {"guess_net": round(t_guess, 2), "correction_net": round(t_corr, 2)},
+        "roofline": {"bound": "mfma", "achieved": round(flops / (fwd_ms * 1e-3) / 1e12, 2), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(flops / (fwd_ms * 1e-3) / 1e12 / 2500.0, 5), "traffic": None,
+                     "kernel": "net forward pass (k_conv<*> BF16 MFMA, all layers)", "gflop": round(flops / 1e9, 2),
+                     "forward_ms": round(fwd_ms, 3)},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def copy_calibration(mib):
