@@ -299,6 +299,10 @@ static void free_grid(lasto_grid g)
     (void)hipFree(g->moments);
     (void)hipFree(g->stage);
     (void)hipFree(g->tail_dev);
+    for (double*& a : g->lscr) {
+        (void)hipFree(a);
+        a = nullptr;
+    }
     if (g->h_scalars) (void)hipHostFree(g->h_scalars);
     for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
     g->prof_ev.clear();

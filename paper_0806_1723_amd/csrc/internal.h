@@ -185,6 +185,10 @@ struct lasto_grid_s {
     double* h_scalars = nullptr;    // pinned host mirror
     double* moments = nullptr;      // device [25 * n_batch]
     lasto::LevelView cview;         // the finest level as one copy of the batch sees it
+    // scratch of the learned entry points (finest-level size, allocated on
+    // first use): natural residual, natural zeros, the two kept candidates,
+    // and the split iterate and source of their judging sweep
+    double* lscr[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // interpolation / atom staging
     double* stage = nullptr;
     size_t stage_bytes = 0;

@@ -53,58 +53,113 @@ __device__ __forceinline__ bool gather_node(int x, int y, int z, Off o, const Co
 }
 
 // ------------------------------------------------------------ forward
-// One wave computes 16 consecutive output nodes of an x row times all NT*16
-// output channels; four waves per workgroup take four such tiles.
-template <int MODE, int NT>
+// One wave computes MT*16 consecutive output nodes (in the flat [z][y][x]
+// order, so rows of any length pack without waste) times all NT*16 output
+// channels; four waves per workgroup. Each 32-wide K chunk's weight
+// fragment is loaded once per wave and used for all MT node tiles. The K
+// loop runs in groups of KB chunks: all gathers and weight loads of a group
+// are issued before its MFMAs. A lane's position in K advances by 32 per
+// chunk; its tap t and channel ci are updated incrementally (no division).
+constexpr int CONV_KB = 2;
+
+template <int MODE, int NT, int MT>
 __global__ __launch_bounds__(256) void k_conv(ConvGeom g, const uint16_t* __restrict__ in,
                                               const uint16_t* __restrict__ wp, ConvEpilogue ep)
 {
     const int lane = threadIdx.x & 63;
     const long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int ntx = (g.nx + 15) / 16;
-    const long ntiles = (long)ntx * g.ny * g.nz;
-    if (tile >= ntiles) return;
-    const int x0 = (int)(tile % ntx) * 16;
-    const int y = (int)((tile / ntx) % g.ny);
-    const int z = (int)(tile / ((long)ntx * g.ny));
+    const long nvox = (long)g.nx * g.ny * g.nz;
+    const long v0 = tile * 16 * MT;
+    if (v0 >= nvox) return;
     const int m = lane & 15, kq = lane >> 4;
-    const int x = x0 + m;
+    // this lane's node in each of the MT tiles (A rows)
+    int xs[MT], ys[MT], zs[MT];
+    bool vok[MT];
+#pragma unroll
+    for (int u = 0; u < MT; ++u) {
+        const long v = v0 + 16 * u + m;
+        vok[u] = v < nvox;
+        const long vv = vok[u] ? v : nvox - 1;
+        xs[u] = (int)(vv % g.nx);
+        ys[u] = (int)((vv / g.nx) % g.ny);
+        zs[u] = (int)(vv / ((long)g.nx * g.ny));
+    }
     const int K = 27 * g.cin;
-    f32x4 acc[NT];
+    f32x4 acc[MT][NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < g.kpad; kc += 32) {
-        const int k = kc + 8 * kq;
-        uint4 a = make_uint4(0, 0, 0, 0);
-        if (k < K && x < g.nx) {
-            const int t = k / g.cin, ci = k - t * g.cin;
-            int xi, yi, zi;
-            if (gather_node<MODE>(x, y, z, tap_off(t), g, xi, yi, zi))
-                a = *(const uint4*)(in + (((size_t)zi * g.iy + yi) * g.ix + xi) * g.cin + ci);
+    for (int u = 0; u < MT; ++u)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[u][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int t = (8 * kq) / g.cin, ci = 8 * kq - t * g.cin;   // this lane's tap and channel at chunk 0
+    for (int kc0 = 0; kc0 < g.kpad; kc0 += 32 * CONV_KB) {
+        uint4 a[CONV_KB][MT], b[CONV_KB][NT];
+#pragma unroll
+        for (int q = 0; q < CONV_KB; ++q) {
+            const int kc = kc0 + 32 * q;
+            const int k = kc + 8 * kq;
+#pragma unroll
+            for (int u = 0; u < MT; ++u) a[q][u] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) b[q][j] = make_uint4(0, 0, 0, 0);
+            if (kc < g.kpad) {
+                if (k < K) {
+                    const Off o = tap_off(t);
+#pragma unroll
+                    for (int u = 0; u < MT; ++u) {
+                        int xi, yi, zi;
+                        if (vok[u] && gather_node<MODE>(xs[u], ys[u], zs[u], o, g, xi, yi, zi))
+                            a[q][u] = *(const uint4*)(in + (((size_t)zi * g.iy + yi) * g.ix + xi) * g.cin + ci);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < NT; ++j) b[q][j] = *(const uint4*)(wp + (size_t)(j * 16 + m) * g.kpad + k);
+            }
+            ci += 32;
+            while (ci >= g.cin) {
+                ci -= g.cin;
+                ++t;
+            }
         }
-        const bf16x8 av = as_bf16x8(a);
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const uint4 b = *(const uint4*)(wp + (size_t)(j * 16 + m) * g.kpad + k);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf16x8(b), acc[j], 0, 0, 0);
+        for (int q = 0; q < CONV_KB; ++q) {
+            if (kc0 + 32 * q >= g.kpad) break;
+#pragma unroll
+            for (int u = 0; u < MT; ++u) {
+                const bf16x8 av = as_bf16x8(a[q][u]);
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf16x8(b[q][j]), acc[u][j], 0, 0, 0);
+            }
         }
     }
-    // epilogue: C[m' = 4 kq + i][n = lane % 16] of tile j is node x0 + m', channel 16 j + n
+    // epilogue: C[m' = 4 kq + i][n = lane % 16] of tile (u, j) is node
+    // v0 + 16 u + m', channel 16 j + n. The operands it reads are loaded for
+    // all four nodes before any is used.
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int co = j * 16 + m;
+        const float bias = ep.bias ? ep.bias[co] : 0.f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int xo = x0 + 4 * kq + i;
-            if (xo >= g.nx) continue;
-            const size_t at = (((size_t)z * g.ny + y) * g.nx + xo) * g.cout + co;
-            float v = acc[j][i];
-            if (ep.bias) v += ep.bias[co];
-            if (ep.relu) v = fmaxf(v, 0.f);
-            if (ep.addend) v += bf2f(ep.addend[at]);
-            if (ep.mask && !(bf2f(ep.mask[at]) > 0.f)) v = 0.f;
-            if (ep.out_f32) ep.out_f32[at] = v;
-            if (ep.out_bf16) ep.out_bf16[at] = f2bf(v);
+        for (int u = 0; u < MT; ++u) {
+            uint16_t add[4] = {0, 0, 0, 0}, msk[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long v = min(v0 + 16 * u + 4 * kq + i, nvox - 1);
+                if (ep.addend) add[i] = ep.addend[(size_t)v * g.cout + co];
+                if (ep.mask) msk[i] = ep.mask[(size_t)v * g.cout + co];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long v = v0 + 16 * u + 4 * kq + i;
+                if (v >= nvox) continue;
+                const size_t at = (size_t)v * g.cout + co;
+                float val = acc[u][j][i] + bias;
+                if (ep.relu) val = fmaxf(val, 0.f);
+                if (ep.addend) val += bf2f(add[i]);
+                if (ep.mask && !(bf2f(msk[i]) > 0.f)) val = 0.f;
+                if (ep.out_f32) ep.out_f32[at] = val;
+                if (ep.out_bf16) ep.out_bf16[at] = f2bf(val);
+            }
         }
     }
 }
@@ -113,13 +168,20 @@ template <int MODE>
 static hipError_t launch_conv_mode(const ConvGeom& g, const uint16_t* in, const uint16_t* wp, const ConvEpilogue& ep,
                                    hipStream_t s)
 {
-    const long tiles = (long)((g.nx + 15) / 16) * g.ny * g.nz;
-    const dim3 grid((unsigned)((tiles + 3) / 4));
-    switch (g.cout / 16) {
-        case 1: hipLaunchKernelGGL((k_conv<MODE, 1>), grid, dim3(256), 0, s, g, in, wp, ep); break;
-        case 2: hipLaunchKernelGGL((k_conv<MODE, 2>), grid, dim3(256), 0, s, g, in, wp, ep); break;
-        case 3: hipLaunchKernelGGL((k_conv<MODE, 3>), grid, dim3(256), 0, s, g, in, wp, ep); break;
-        case 4: hipLaunchKernelGGL((k_conv<MODE, 4>), grid, dim3(256), 0, s, g, in, wp, ep); break;
+    // several node tiles per wave share the weight loads on large levels;
+    // small levels keep one tile per wave so that enough waves exist
+    const long nvox = (long)g.nx * g.ny * g.nz;
+    auto grid = [&](int mt) { return dim3((unsigned)((nvox + 64L * mt - 1) / (64L * mt))); };
+    const bool big = nvox >= 64L * 4 * 2048;
+    switch ((g.cout / 16) * 2 + (big ? 1 : 0)) {
+        case 2: hipLaunchKernelGGL((k_conv<MODE, 1, 1>), grid(1), dim3(256), 0, s, g, in, wp, ep); break;
+        case 3: hipLaunchKernelGGL((k_conv<MODE, 1, 4>), grid(4), dim3(256), 0, s, g, in, wp, ep); break;
+        case 4: hipLaunchKernelGGL((k_conv<MODE, 2, 1>), grid(1), dim3(256), 0, s, g, in, wp, ep); break;
+        case 5: hipLaunchKernelGGL((k_conv<MODE, 2, 4>), grid(4), dim3(256), 0, s, g, in, wp, ep); break;
+        case 6: hipLaunchKernelGGL((k_conv<MODE, 3, 1>), grid(1), dim3(256), 0, s, g, in, wp, ep); break;
+        case 7: hipLaunchKernelGGL((k_conv<MODE, 3, 2>), grid(2), dim3(256), 0, s, g, in, wp, ep); break;
+        case 8: hipLaunchKernelGGL((k_conv<MODE, 4, 1>), grid(1), dim3(256), 0, s, g, in, wp, ep); break;
+        case 9: hipLaunchKernelGGL((k_conv<MODE, 4, 2>), grid(2), dim3(256), 0, s, g, in, wp, ep); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -297,34 +359,62 @@ __device__ __forceinline__ void up_taps(int i, int nc, int& a, int& b, float& wa
     }
 }
 
-__global__ void k_upsample_add(const uint16_t* __restrict__ coarse, int cx, int cy, int cz, const uint16_t* __restrict__ skip,
-                               uint16_t* __restrict__ out, int nx, int ny, int nz, int c)
+// One thread per fine node and group of 8 channels (16-byte loads and
+// stores); a workgroup covers 64 x-consecutive nodes of one (y, z) row, so
+// the row's index arithmetic is done once per thread, not per channel.
+__device__ __forceinline__ void add8(float* acc, uint4 q, float w)
 {
-    const long n = (long)nx * ny * nz * c;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        const int ch = (int)(e % c);
-        const long v = e / c;
-        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long)nx * ny));
-        int xa, xb, ya, yb, za, zb;
-        float wxa, wxb, wya, wyb, wza, wzb;
-        up_taps(x, cx, xa, xb, wxa, wxb);
-        up_taps(y, cy, ya, yb, wya, wyb);
-        up_taps(z, cz, za, zb, wza, wzb);
-        auto C = [&](int xx, int yy, int zz) { return bf2f(coarse[(((size_t)zz * cy + yy) * cx + xx) * c + ch]); };
-        const float val = wza * (wya * (wxa * C(xa, ya, za) + wxb * C(xb, ya, za)) +
-                                 wyb * (wxa * C(xa, yb, za) + wxb * C(xb, yb, za))) +
-                          wzb * (wya * (wxa * C(xa, ya, zb) + wxb * C(xb, ya, zb)) +
-                                 wyb * (wxa * C(xa, yb, zb) + wxb * C(xb, yb, zb)));
-        out[e] = f2bf(val + (skip ? bf2f(skip[e]) : 0.f));
+    const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        acc[2 * h] += w * __uint_as_float(u[h] << 16);
+        acc[2 * h + 1] += w * __uint_as_float(u[h] & 0xffff0000u);
     }
+}
+
+__global__ __launch_bounds__(256) void k_upsample_add(const uint16_t* __restrict__ coarse, int cx, int cy, int cz,
+                                                      const uint16_t* __restrict__ skip, uint16_t* __restrict__ out,
+                                                      int nx, int ny, int nz, int c)
+{
+    const int g8 = c / 8;   // channel groups
+    const int lanes = 64 * g8;
+    const int t = blockIdx.x * 256 + threadIdx.x;   // within the row segment of this block
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int x = t / g8, grp = t - x * g8;
+    if (x >= nx || t >= lanes * ((nx + 63) / 64)) return;
+    int xa, xb, ya, yb, za, zb;
+    float wxa, wxb, wya, wyb, wza, wzb;
+    up_taps(x, cx, xa, xb, wxa, wxb);
+    up_taps(y, cy, ya, yb, wya, wyb);
+    up_taps(z, cz, za, zb, wza, wzb);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int zz[2] = {za, zb}, yy[2] = {ya, yb}, xx[2] = {xa, xb};
+    const float wz[2] = {wza, wzb}, wy[2] = {wya, wyb}, wx[2] = {wxa, wxb};
+#pragma unroll
+    for (int cz2 = 0; cz2 < 2; ++cz2)
+#pragma unroll
+        for (int cy2 = 0; cy2 < 2; ++cy2)
+#pragma unroll
+            for (int cx2 = 0; cx2 < 2; ++cx2) {
+                const float w = wz[cz2] * wy[cy2] * wx[cx2];
+                const uint4 q = *(const uint4*)(coarse + (((size_t)zz[cz2] * cy + yy[cy2]) * cx + xx[cx2]) * c + 8 * grp);
+                add8(acc, q, w);
+            }
+    const size_t at = (((size_t)z * ny + y) * nx + x) * c + 8 * grp;
+    if (skip) add8(acc, *(const uint4*)(skip + at), 1.f);
+    uint32_t o[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) o[h] = (uint32_t)f2bf(acc[2 * h]) | ((uint32_t)f2bf(acc[2 * h + 1]) << 16);
+    *(uint4*)(out + at) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 hipError_t launch_upsample_add(const uint16_t* coarse, int cx, int cy, int cz, const uint16_t* skip, uint16_t* out,
                                int nx, int ny, int nz, int c, hipStream_t s)
 {
-    const long n = (long)nx * ny * nz * c;
-    hipLaunchKernelGGL(k_upsample_add, dim3((unsigned)std::min<long>((n + 255) / 256, 16384)), dim3(256), 0, s, coarse,
-                       cx, cy, cz, skip, out, nx, ny, nz, c);
+    if (c % 8) return hipErrorInvalidValue;
+    const long per_row = (long)((nx + 63) / 64) * 64 * (c / 8);
+    const dim3 grid((unsigned)((per_row + 255) / 256), (unsigned)ny, (unsigned)nz);
+    hipLaunchKernelGGL(k_upsample_add, grid, dim3(256), 0, s, coarse, cx, cy, cz, skip, out, nx, ny, nz, c);
     return hipGetLastError();
 }
 
@@ -383,19 +473,25 @@ hipError_t launch_upsample_adj(const uint16_t* fine, int nx, int ny, int nz, uin
 
 // ------------------------------------------------------ output and loss
 // y[v] = sum_c w[c] a[v][c] + w[c] (the 1x1x1 output layer, FP32 result;
-// the bias is the last weight)
-__global__ void k_head(const uint16_t* __restrict__ a, long nvox, int c, const float* __restrict__ w,
-                       float* __restrict__ y)
+// the bias is the last weight); one node per thread, channels in 16-byte loads
+__global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ a, long nvox, int c,
+                                              const float* __restrict__ w, float* __restrict__ y)
 {
     for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long)gridDim.x * blockDim.x) {
         float s = w[c];
-        for (int q = 0; q < c; ++q) s += w[q] * bf2f(a[(size_t)v * c + q]);
+        for (int q0 = 0; q0 < c; q0 += 8) {
+            float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            add8(acc, *(const uint4*)(a + (size_t)v * c + q0), 1.f);
+#pragma unroll
+            for (int h = 0; h < 8; ++h) s += w[q0 + h] * acc[h];
+        }
         y[v] = s;
     }
 }
 
 hipError_t launch_head(const uint16_t* a, long nvox, int c, const float* w, float* y, hipStream_t s)
 {
+    if (c % 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_head, dim3((unsigned)std::min<long>((nvox + 255) / 256, 16384)), dim3(256), 0, s, a, nvox, c, w,
                        y);
     return hipGetLastError();

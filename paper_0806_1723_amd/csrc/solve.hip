@@ -469,55 +469,63 @@ static lasto_status resid_norm2(lasto_grid g, const double* rho, const double* v
     return reduce_to(g, interior_blocks(V), slot);
 }
 
-// one red-black sweep on A v = 4 pi rho in place on natural v (faces kept),
-// through the split layout in the grid's z (iterate) and p[0] (source) vectors
-static lasto_status smooth_nat(lasto_grid g, const double* rho, double* v)
+// Scratch of the learned entry points (zero-filled once, on first use).
+enum { LS_R = 0, LS_ZERO = 1, LS_PLAIN = 2, LS_LEARNED = 3, LS_SU = 4, LS_SF = 5 };
+
+static lasto_status learned_scratch(lasto_grid g)
 {
-    const LevelView& V = g->lev[0].view;
-    HIPCHK(launch_nat_to_split(V, v, g->z, g->stream));
-    HIPCHK(launch_nat_to_split(V, rho, g->p[0], g->stream));
-    HIPCHK(launch_half_keep_faces<double>(V, g->z, g->p[0], 0, 4.0 * kPi, g->stream));
-    HIPCHK(launch_half_keep_faces<double>(V, g->z, g->p[0], 1, 4.0 * kPi, g->stream));
-    HIPCHK(launch_split_to_nat(V, g->z, v, g->stream));
+    const size_t n = split_elems(g->lev[0].view);
+    for (double*& a : g->lscr) {
+        if (a) continue;
+        HIPCHK(hipMalloc(&a, sizeof(double) * n));
+        HIPCHK(launch_fill_zero<double>(a, n, g->stream));
+    }
     return LASTO_OK;
 }
 
-// The learned guess is judged, like the guess it corrects, after one
-// red-black sweep: the sweep removes rough error at the grid scale, which a
-// multigrid cycle removes cheaply anyway, and leaves the smooth error that
-// decides how many cycles remain.
-extern "C" lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
-                                            int* accepted)
+// one red-black sweep on A v = 4 pi rho in place on natural v (faces kept),
+// through the split layout in the learned scratch
+static lasto_status smooth_nat(lasto_grid g, const double* rho, double* v)
 {
-    if (!g || !n || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_learned_guess: NULL argument");
-    if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_learned_guess: one right-hand side per grid");
+    const LevelView& V = g->lev[0].view;
+    double* su = g->lscr[LS_SU];
+    double* sf = g->lscr[LS_SF];
+    HIPCHK(launch_nat_to_split(V, v, su, g->stream));
+    HIPCHK(launch_nat_to_split(V, rho, sf, g->stream));
+    HIPCHK(launch_half_keep_faces<double>(V, su, sf, 0, 4.0 * kPi, g->stream));
+    HIPCHK(launch_half_keep_faces<double>(V, su, sf, 1, 4.0 * kPi, g->stream));
+    HIPCHK(launch_split_to_nat(V, su, v, g->stream));
+    return LASTO_OK;
+}
+
+// Plain multigrid judges a learned candidate: v (the plain one) and
+// v_learned = v + cscale * y each get one red-black sweep (which removes the
+// grid-scale roughness any cycle removes cheaply, leaving the smooth error
+// that decides how many cycles remain), and v receives the one with the
+// smaller residual.
+static lasto_status judge(lasto_grid g, const double* rho, double* v, const float* y, double cscale, double* rel,
+                          int* accepted)
+{
     const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
     const size_t nn = (size_t)V.nx * V.ny * V.nz;
-    // natural-layout copies live in the grid's x and p[1] vectors
-    if (split_elems(V) < nn) return fail(LASTO_ERR_STATE, "lasto_learned_guess: scratch too small");
-    double* keep_guess = g->x;
-    double* keep_learned = g->p[1];
+    double* keep_plain = g->lscr[LS_PLAIN];
+    double* keep_learned = g->lscr[LS_LEARNED];
     if (lasto_status e = resid_norm2(g, rho, v, 1, S_R0); e != LASTO_OK) return e;
-    HIPCHK(hipMemcpyAsync(keep_guess, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    const float* y = nullptr;
-    double out_scale = 0.0;
-    if (lasto_status e = net_guess_forward(g, n, rho, v, &y, &out_scale); e != LASTO_OK) return e;
-    HIPCHK(launch_add_f32_nat(V, v, y, out_scale, s));
+    HIPCHK(hipMemcpyAsync(keep_plain, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    if (y) HIPCHK(launch_add_f32_nat(V, v, y, cscale, s));
     if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
     if (lasto_status e = resid_norm2(g, rho, v, 0, S_TMP); e != LASTO_OK) return e;
     HIPCHK(hipMemcpyAsync(keep_learned, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(v, keep_guess, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(v, keep_plain, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
     if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
     if (lasto_status e = resid_norm2(g, rho, v, 0, S_RR); e != LASTO_OK) return e;
     if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
     const double r0 = std::sqrt(g->h_scalars[S_R0]);
     const double plain = r0 > 0.0 ? std::sqrt(g->h_scalars[S_RR]) / r0 : 0.0;
     const double learned = r0 > 0.0 ? std::sqrt(g->h_scalars[S_TMP]) / r0 : 0.0;
-    const bool keep = std::isfinite(learned) && learned < plain;
+    const bool keep = y && std::isfinite(learned) && learned < plain;
     if (keep) HIPCHK(hipMemcpyAsync(v, keep_learned, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    // the solver's vectors must come back with zero faces and padding
-    for (double* a : {g->x, g->p[0], g->p[1], g->z}) HIPCHK(launch_fill_zero<double>(a, split_elems(V), s));
     HIPCHK(hipStreamSynchronize(s));
     if (rel) {
         rel[0] = plain;
@@ -527,19 +535,28 @@ extern "C" lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const dou
     return LASTO_OK;
 }
 
-// The residual r = 4 pi rho - A v in natural layout (g->x, faces zero) and
-// its RMS over the interior, s = ||r||_W / sqrt(sum vol); the zero array the
-// correction net reads for its potential channel is g->p[1].
+extern "C" lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
+                                            int* accepted)
+{
+    if (!g || !n || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_learned_guess: NULL argument");
+    if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_learned_guess: one right-hand side per grid");
+    if (lasto_status e = learned_scratch(g); e != LASTO_OK) return e;
+    const float* y = nullptr;
+    double out_scale = 0.0;
+    if (lasto_status e = net_guess_forward(g, n, rho, v, &y, &out_scale); e != LASTO_OK) return e;
+    return judge(g, rho, v, y, out_scale, rel, accepted);
+}
+
+// The residual r = 4 pi rho - A v in natural layout (LS_R, faces zero) and
+// its RMS over the interior, s = ||r||_W / sqrt(sum vol); the correction
+// net's potential channel reads the zero array LS_ZERO.
 static lasto_status correction_input(lasto_grid g, const double* rho, const double* v, double* s_r)
 {
     const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
-    HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
-    HIPCHK(launch_fill_zero<double>(g->p[1], split_elems(V), s));
     HIPCHK(launch_residual_nat(V, v, rho, 4.0 * kPi, g->r, g->partials, 0, s));
     if (lasto_status e = reduce_to(g, interior_blocks(V), S_TMP); e != LASTO_OK) return e;
-    HIPCHK(launch_split_to_nat(V, g->r, g->x, s));
-    HIPCHK(launch_fill_zero<double>(g->r, split_elems(V), s));
+    HIPCHK(launch_split_to_nat(V, g->r, g->lscr[LS_R], s));
     if (lasto_status e = read_scalars(g, S_TMP, 1); e != LASTO_OK) return e;
     double vol = 1.0;
     for (int d = 0; d < 3; ++d) {
@@ -556,13 +573,12 @@ extern "C" lasto_status lasto_net_correction_features(lasto_grid g, lasto_net n,
     if (!g || !n || !rho || !v || !x || !r_scale)
         return fail(LASTO_ERR_ARG, "lasto_net_correction_features: NULL argument");
     if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_net_correction_features: one right-hand side per grid");
+    if (lasto_status e = learned_scratch(g); e != LASTO_OK) return e;
     double sr = 0.0;
     if (lasto_status e = correction_input(g, rho, v, &sr); e != LASTO_OK) return e;
     if (!(sr > 0.0) || !std::isfinite(sr)) return fail(LASTO_ERR_ARG, "lasto_net_correction_features: zero residual");
-    if (lasto_status e = net_features_async(g, n, g->x, g->p[1], x, 1.0 / sr); e != LASTO_OK) return e;
-    const LevelView& V = g->lev[0].view;
-    HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), g->stream));
-    HIPCHK(launch_fill_zero<double>(g->p[1], split_elems(V), g->stream));
+    if (lasto_status e = net_features_async(g, n, g->lscr[LS_R], g->lscr[LS_ZERO], x, 1.0 / sr); e != LASTO_OK)
+        return e;
     HIPCHK(hipStreamSynchronize(g->stream));
     *r_scale = sr;
     return LASTO_OK;
@@ -573,44 +589,17 @@ extern "C" lasto_status lasto_learned_correction(lasto_grid g, lasto_net n, cons
 {
     if (!g || !n || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_learned_correction: NULL argument");
     if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_learned_correction: one right-hand side per grid");
-    const LevelView& V = g->lev[0].view;
-    hipStream_t s = g->stream;
-    const size_t nn = (size_t)V.nx * V.ny * V.nz;
-    if (split_elems(V) < nn) return fail(LASTO_ERR_STATE, "lasto_learned_correction: scratch too small");
-    if (lasto_status e = resid_norm2(g, rho, v, 1, S_R0); e != LASTO_OK) return e;
+    if (lasto_status e = learned_scratch(g); e != LASTO_OK) return e;
     double sr = 0.0;
     if (lasto_status e = correction_input(g, rho, v, &sr); e != LASTO_OK) return e;
-    double* keep_plain = g->q;
-    double* keep_learned = g->x;
-    HIPCHK(hipMemcpyAsync(keep_plain, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    const bool live = sr > 0.0 && std::isfinite(sr);
-    if (live) {
-        const float* y = nullptr;
-        double out_scale = 0.0;
-        if (lasto_status e = net_guess_forward(g, n, g->x, g->p[1], &y, &out_scale, 1.0 / sr); e != LASTO_OK)
+    const float* y = nullptr;
+    double out_scale = 0.0;
+    if (sr > 0.0 && std::isfinite(sr)) {
+        if (lasto_status e = net_guess_forward(g, n, g->lscr[LS_R], g->lscr[LS_ZERO], &y, &out_scale, 1.0 / sr);
+            e != LASTO_OK)
             return e;
-        HIPCHK(launch_add_f32_nat(V, v, y, out_scale * sr, s));
     }
-    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
-    if (lasto_status e = resid_norm2(g, rho, v, 0, S_TMP); e != LASTO_OK) return e;
-    HIPCHK(hipMemcpyAsync(keep_learned, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(v, keep_plain, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
-    if (lasto_status e = resid_norm2(g, rho, v, 0, S_RR); e != LASTO_OK) return e;
-    if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
-    const double r0 = std::sqrt(g->h_scalars[S_R0]);
-    const double plain = r0 > 0.0 ? std::sqrt(g->h_scalars[S_RR]) / r0 : 0.0;
-    const double learned = r0 > 0.0 ? std::sqrt(g->h_scalars[S_TMP]) / r0 : 0.0;
-    const bool keep = live && std::isfinite(learned) && learned < plain;
-    if (keep) HIPCHK(hipMemcpyAsync(v, keep_learned, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    for (double* a : {g->x, g->p[0], g->p[1], g->z, g->q}) HIPCHK(launch_fill_zero<double>(a, split_elems(V), s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (rel) {
-        rel[0] = plain;
-        rel[1] = learned;
-    }
-    if (accepted) *accepted = keep ? 1 : 0;
-    return LASTO_OK;
+    return judge(g, rho, v, y, out_scale * sr, rel, accepted);
 }
 
 extern "C" lasto_status lasto_apply(lasto_grid g, const double* u, double* Au)
