@@ -159,6 +159,8 @@ typedef struct {
     int lmax_bc;        /* multipole order of the face values, 0..4 (default 4) */
     int debug_nan_iter; /* >= 0: inject a NaN into the residual at that iteration (tests only); default -1 */
     int profile;        /* 1: time every finest-level smoother launch with HIP events (default 0) */
+    int inner_first;    /* precision 1: inner steps of the first refinement, 0 = inner_iters (default 0);
+                           its reduction is bounded by FP32 rounding of the operator sooner than later ones */
 } lasto_solve_opts;
 
 typedef struct {

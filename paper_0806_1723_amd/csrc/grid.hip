@@ -210,6 +210,9 @@ lasto_status build_level_tables(lasto_grid g, int l)
     L.view.W = ((L.n[0] / 2 + 3) + 15) / 16 * 16;
     L.view.cs = (size_t)L.view.nz * L.n[1] * L.view.W;
     L.nsplit = 2 * L.view.cs;
+    // the Krylov kernels address split entries with 32-bit indices
+    if (L.nsplit >= ((size_t)1 << 32))
+        return fail(LASTO_ERR_ARG, "lasto_grid_create: a split array of 2^32 or more entries is not supported");
     // planes interior to their copy
     std::vector<unsigned char> zi(nst[2], 0);
     for (int k = 0; k < nst[2]; ++k) {
@@ -413,6 +416,8 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
         nparts = std::max(nparts, (size_t)interior_blocks(g->lev[l].view));
         nparts = std::max(nparts, (size_t)2 * half_blocks(g->lev[l].view));
         nparts = std::max(nparts, (size_t)row_blocks(g->lev[l].view));
+        nparts = std::max(nparts, (size_t)flat_blocks<float>(g->lev[l].view));
+        nparts = std::max(nparts, (size_t)flat_blocks<double>(g->lev[l].view));
     }
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->partials, sizeof(double) * nparts);
     if (st == LASTO_OK) st = alloc_zero(g, (void**)&g->scalars, sizeof(double) * kNumScalars);
@@ -441,6 +446,32 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
                 g->tail_top = l;
                 break;
             }
+        // FP32 LDS tail: from the first level whose correction and
+        // right-hand side, with those of every coarser level, fit in one
+        // workgroup's LDS (keeping 8 KB spare)
+        const int lim = tail_lds_limit() - 8192;
+        size_t need = 0;
+        g->tail32_top = -1;
+        for (int l = g->nlev - 1; l >= 0 && g->nlev - l <= kLdsMaxLevels; --l) {
+            need += 2 * g->lev[l].nsplit;
+            if (lim > 0 && need * sizeof(float) <= (size_t)lim) g->tail32_top = l;
+            else break;
+        }
+        // (only where it takes over at least the levels of the global-memory
+        // tail; a later start would run those levels by separate launches)
+        if (g->tail32_top > g->tail_top) g->tail32_top = -1;
+        if (g->tail32_top >= 0) {
+            LdsPlan& P = g->lds_plan;
+            P.nl = g->nlev - g->tail32_top;
+            int o = 0;
+            for (int q = 0; q < P.nl; ++q) {
+                const int ns = (int)g->lev[g->tail32_top + q].nsplit;
+                P.off[q][0] = o;
+                P.off[q][1] = o + ns;
+                o += 2 * ns;
+            }
+            P.total = o;
+        }
         std::vector<TailLevel> tl(g->nlev);
         for (int l = 0; l < g->nlev; ++l) {
             Level& L = g->lev[l];

@@ -156,6 +156,15 @@ template <> struct TailBuf<float> {
 
 constexpr size_t kTailMaxPts = 16384;   // levels at or below this size run in the tail kernel
 
+// LDS layout of the FP32 tail: per level, the offsets (in floats) of its
+// correction and right-hand side (split layout, 2 cs each)
+constexpr int kLdsMaxLevels = 12;
+struct LdsPlan {
+    int nl;
+    int total;                      // floats
+    int off[kLdsMaxLevels][2];
+};
+
 }  // namespace lasto
 
 struct lasto_grid_s {
@@ -165,6 +174,8 @@ struct lasto_grid_s {
     int device = 0;
     lasto::Level lev[lasto::kMaxLevels];
     int tail_top = 0;                      // first level handled by the tail kernel
+    int tail32_top = -1;                   // first level of the FP32 LDS tail (-1: none)
+    lasto::LdsPlan lds_plan{};
     lasto::TailLevel* tail_dev = nullptr;  // device [nlev]
     // fine-level Krylov vectors (FP64, split layout): residual, preconditioned
     // residual, search direction (ping-pong), A p
@@ -245,6 +256,10 @@ hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e
 // black) sweeps then csweeps (black, red).
 template <typename T>
 hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweeps, int top_zero, hipStream_t s);
+// the FP32 cycle below level lv[0] with every level in LDS (plan from the grid)
+hipError_t launch_tail_lds(const TailLevel* lv, int nu1, int nu2, int csweeps, int top_zero, const LdsPlan& P,
+                           hipStream_t s);
+int tail_lds_limit();   // bytes of LDS one workgroup may use (0 if unknown)
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s);
 template <typename T>
@@ -252,11 +267,14 @@ hipError_t launch_dot(const LevelView& L, const T* a, const T* b, double* partia
 template <typename T>
 hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pnew, const double* scal,
                            int i_num, int i_den, int first, hipStream_t s);
-// x += alpha p, r -= alpha q (all split), alpha = scal[i_num]/scal[i_den]
+// x += alpha p, r -= alpha q (all split), alpha = scal[i_num]/scal[i_den];
+// partials of <r, r>_W (count in *nparts, at most flat_blocks<T>(L))
 template <typename T>
 hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
-                            int i_den, double* partials, hipStream_t s);
-int row_blocks(const LevelView& L);   // partials of the elementwise split kernels (dot, update_xr)
+                            int i_den, double* partials, hipStream_t s, int* nparts);
+template <typename T>
+int flat_blocks(const LevelView& L);
+int row_blocks(const LevelView& L);   // partials of the row-wise split dot
 // natural-layout fine-level helpers
 hipError_t launch_residual_nat(const LevelView& L, const double* v, const double* rho, double bscale, double* r_split,
                                double* partials, int interior_zero, hipStream_t s);

@@ -660,18 +660,84 @@ hipError_t launch_dot(const LevelView& L, const T* a, const T* b, double* partia
     return hipGetLastError();
 }
 
+// ---- Krylov updates over whole split arrays
+// Each array is one flat run of 2 cs entries in rows of W (a multiple of 16),
+// so a thread moves 16 bytes per access without leaving its row and keeps
+// FL_U such accesses of every operand in flight before it stores any. Rows
+// of interior (j, k) are updated whole, as every split kernel treats them;
+// face rows and planes of other copies' faces are left alone. The norm
+// partials use one fixed workgroup count per array size (deterministic).
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    static constexpr int N = 4;
+};
+template <> struct Vec16<double> {
+    typedef double V __attribute__((ext_vector_type(2)));
+    static constexpr int N = 2;
+};
+
+constexpr int FL_NT = 256, FL_U = 4, FL_MAX_BLOCKS = 2048;
+
+struct RowPos {
+    int c, k, j, m;
+    bool live;
+};
+
+// position of split entry q (32-bit: the grid limits 2 cs below 2^32)
+__device__ __forceinline__ RowPos row_pos(const LevelView& L, unsigned q)
+{
+    RowPos p;
+    const unsigned row = q / (unsigned)L.W;
+    p.m = (int)(q - row * (unsigned)L.W);
+    const unsigned ck = row / (unsigned)L.ny;
+    p.j = (int)(row - ck * (unsigned)L.ny);
+    p.c = ck >= (unsigned)L.nz ? 1 : 0;
+    p.k = (int)ck - p.c * L.nz;
+    p.live = p.j >= 1 && p.j <= L.ny - 2 && p.k >= 1 && p.k <= L.nz - 2 && L.zint[p.k];
+    return p;
+}
+
+template <typename T>
+static unsigned flat_vectors(const LevelView& L)
+{
+    return (unsigned)(2 * L.cs / Vec16<T>::N);
+}
+
+template <typename T>
+int flat_blocks(const LevelView& L)
+{
+    const unsigned per = FL_NT * FL_U;
+    return (int)std::max(1u, std::min<unsigned>(FL_MAX_BLOCKS, (flat_vectors<T>(L) + per - 1) / per));
+}
+
 // pnew = z + beta pold, beta = scal[i_num]/scal[i_den] (0 on the first step)
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_update_p(LevelView L, int kp, const T* __restrict__ z,
+__global__ __launch_bounds__(FL_NT) void k_update_p(LevelView L, unsigned nvec, const T* __restrict__ z,
                                                     const T* __restrict__ pold, T* __restrict__ pnew,
                                                     const double* __restrict__ scal, int i_num, int i_den, int first)
 {
+    typedef typename Vec16<T>::V V;
+    constexpr int N = Vec16<T>::N;
     const T beta = first ? T(0) : (T)(scal[i_num] / scal[i_den]);
-    ROW_LOOP
-    {
-        if (!inside || !L.zint[k]) continue;
-        const size_t at = ROW_AT;
-        pnew[at] = first ? z[at] : z[at] + beta * pold[at];
+    const unsigned stride = gridDim.x * FL_NT;
+    for (unsigned e0 = blockIdx.x * FL_NT + threadIdx.x; e0 < nvec; e0 += stride * FL_U) {
+        V zv[FL_U], pv[FL_U];
+        bool lv[FL_U];
+#pragma unroll
+        for (int u = 0; u < FL_U; ++u) {
+            const unsigned e = e0 + u * stride;
+            lv[u] = e < nvec && row_pos(L, e * N).live;
+            zv[u] = V(T(0));
+            pv[u] = V(T(0));
+            if (lv[u]) {
+                zv[u] = reinterpret_cast<const V*>(z)[e];
+                if (!first) pv[u] = reinterpret_cast<const V*>(pold)[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < FL_U; ++u)
+            if (lv[u]) reinterpret_cast<V*>(pnew)[e0 + u * stride] = first ? zv[u] : zv[u] + beta * pv[u];
     }
 }
 
@@ -679,7 +745,8 @@ template <typename T>
 hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pnew, const double* scal, int i_num,
                            int i_den, int first, hipStream_t s)
 {
-    ROW_LAUNCH(k_update_p<T>, L, s, z, pold, pnew, scal, i_num, i_den, first);
+    hipLaunchKernelGGL(k_update_p<T>, dim3(flat_blocks<T>(L)), dim3(FL_NT), 0, s, L, flat_vectors<T>(L), z, pold,
+                       pnew, scal, i_num, i_den, first);
     return hipGetLastError();
 }
 
@@ -687,37 +754,69 @@ hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pne
 // partial <r,r>_W. A non-finite alpha leaves x and r untouched (the caller
 // then reports the breakdown with x still the last finite iterate).
 template <typename T>
-__global__ __launch_bounds__(PT_NT) void k_update_xr(LevelView L, int kp, T* __restrict__ x, T* __restrict__ r,
-                                                     const T* __restrict__ p, const T* __restrict__ q,
-                                                     const double* __restrict__ scal, int i_num, int i_den,
-                                                     double* __restrict__ part)
+__global__ __launch_bounds__(FL_NT) void k_update_xr(LevelView L, unsigned nvec, T* __restrict__ x,
+                                                     T* __restrict__ r, const T* __restrict__ p,
+                                                     const T* __restrict__ q, const double* __restrict__ scal,
+                                                     int i_num, int i_den, double* __restrict__ part)
 {
-    __shared__ double red[PT_NT / 64];
+    typedef typename Vec16<T>::V V;
+    constexpr int N = Vec16<T>::N;
+    __shared__ double red[FL_NT / 64];
     const double ad = scal[i_num] / scal[i_den];
     const bool ok = isfinite(ad);
     const T alpha = (T)ad;
     double acc = 0.0;
-    ROW_LOOP
-    {
-        if (!inside || !L.zint[k]) continue;
-        const size_t at = ROW_AT;
-        T rv = r[at];
-        if (ok) {
-            x[at] = x[at] + alpha * p[at];
-            rv = rv - alpha * q[at];
-            r[at] = rv;
+    const unsigned stride = gridDim.x * FL_NT;
+    for (unsigned e0 = blockIdx.x * FL_NT + threadIdx.x; e0 < nvec; e0 += stride * FL_U) {
+        V xv[FL_U], rv[FL_U], pv[FL_U], qv[FL_U];
+        RowPos ps[FL_U];
+        bool lv[FL_U];
+#pragma unroll
+        for (int u = 0; u < FL_U; ++u) {
+            const unsigned e = e0 + u * stride;
+            ps[u] = row_pos(L, e * N);
+            lv[u] = e < nvec && ps[u].live;
+            xv[u] = rv[u] = pv[u] = qv[u] = V(T(0));
+            if (lv[u]) {
+                rv[u] = reinterpret_cast<const V*>(r)[e];
+                if (ok) {
+                    xv[u] = reinterpret_cast<const V*>(x)[e];
+                    pv[u] = reinterpret_cast<const V*>(p)[e];
+                    qv[u] = reinterpret_cast<const V*>(q)[e];
+                }
+            }
         }
-        acc += ROW_VOL * (double)rv * (double)rv;
+#pragma unroll
+        for (int u = 0; u < FL_U; ++u) {
+            if (!lv[u]) continue;
+            const unsigned e = e0 + u * stride;
+            if (ok) {
+                xv[u] = xv[u] + alpha * pv[u];
+                rv[u] = rv[u] - alpha * qv[u];
+                reinterpret_cast<V*>(x)[e] = xv[u];
+                reinterpret_cast<V*>(r)[e] = rv[u];
+            }
+            // dual volume: x width by parity of i (zero off the interior), y, z widths
+            const double* wx = L.xpar + (size_t)(((ps[u].c + ps[u].j + ps[u].k) & 1) * 3 + 2) * L.W + ps[u].m;
+            const double wyz = L.ax[1].m[ps[u].j] * L.ax[2].m[ps[u].k];
+            double a = 0.0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) a += wx[l] * ((double)rv[u][l] * (double)rv[u][l]);
+            acc += wyz * a;
+        }
     }
-    const double t = block_sum<PT_NT>(acc, red);
-    if (threadIdx.x == 0) part[block_linear()] = ok ? t : __builtin_nan("");
+    const double t = block_sum<FL_NT>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = ok ? t : __builtin_nan("");
 }
 
 template <typename T>
 hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
-                            int i_den, double* partials, hipStream_t s)
+                            int i_den, double* partials, hipStream_t s, int* nparts)
 {
-    ROW_LAUNCH(k_update_xr<T>, L, s, x, r, p, q, scal, i_num, i_den, partials);
+    const int nb = flat_blocks<T>(L);
+    hipLaunchKernelGGL(k_update_xr<T>, dim3(nb), dim3(FL_NT), 0, s, L, flat_vectors<T>(L), x, r, p, q, scal, i_num,
+                       i_den, partials);
+    if (nparts) *nparts = nb;
     return hipGetLastError();
 }
 
@@ -1213,6 +1312,136 @@ hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweep
     return hipGetLastError();
 }
 
+// ------------------------------------------------------ LDS tail (FP32)
+// The same cycle with every level's correction and right-hand side held in
+// LDS, so each of its ~50 barrier-separated steps waits on LDS rather than
+// on the L2 or HBM; the fine residual is formed where the restriction reads
+// it instead of being stored. Only the top level's right-hand side comes in
+// from global memory (and its correction when the cycle continues from it),
+// and only the top level's correction goes back.
+template <typename T>
+__device__ __forceinline__ T resid_at(const LevelView& F, const T* u, const T* f, int i, int j, int k)
+{
+    if (i < 1 || i > F.nx - 2 || j < 1 || j > F.ny - 2 || k < 1 || k > F.nz - 2 || !F.zint[k]) return T(0);
+    const size_t at = sidx(F, i, j, k);
+    return f[at] - apply_split(F, u, i, j, k, u[at]);
+}
+
+// f_coarse = R r with r = f - A u on red fine nodes (black ones vanish after
+// a black half-sweep)
+template <typename T>
+__device__ void t_restrict_red_fly(const LevelView& F, const LevelView& C, const T* u, const T* f, T* fc)
+{
+    const Cols cl = tail_cols((C.nx - 2) * (C.ny - 2));
+    if (!cl.active) return;
+    const int I = 1 + cl.col % (C.nx - 2), J = 1 + cl.col / (C.nx - 2);
+    const int fi = C.ax[0].rf[I], fj = C.ax[1].rf[J];
+    const double* wx = C.ax[0].rw + 3 * I;
+    const double* wy = C.ax[1].rw + 3 * J;
+    for (int K = 1 + cl.grp; K <= C.nz - 2; K += cl.ng) {
+        if (!C.zint[K]) continue;
+        const int fk = C.ax[2].rf[K];
+        const double* wz = C.ax[2].rw + 3 * K;
+        T acc = T(0);
+        for (int c = 0; c < 3; ++c) {
+            if (wz[c] == 0.0) continue;
+            for (int b = 0; b < 3; ++b) {
+                if (wy[b] == 0.0) continue;
+                const int jj = fj - 1 + b, kk = fk - 1 + c;
+                T sx = T(0);
+                for (int a = 0; a < 3; ++a) {
+                    const int ii = fi - 1 + a;
+                    if (wx[a] == 0.0 || ((ii + jj + kk) & 1)) continue;
+                    sx += (T)wx[a] * resid_at(F, u, f, ii, jj, kk);
+                }
+                acc += (T)(wz[c] * wy[b]) * sx;
+            }
+        }
+        fc[sidx(C, I, J, K)] = acc;
+    }
+}
+
+__global__ __launch_bounds__(TL_NT) void k_tail_lds(const TailLevel* __restrict__ lv, int nu1, int nu2, int csweeps,
+                                                    int top_zero, LdsPlan P)
+{
+    extern __shared__ float lds[];
+    const int nl = P.nl;
+    for (int e = threadIdx.x; e < P.total; e += TL_NT) lds[e] = 0.f;
+    __syncthreads();
+    {
+        const size_t n = 2 * lv[0].V.cs;
+        for (size_t e = threadIdx.x; e < n; e += TL_NT) {
+            lds[P.off[0][1] + e] = lv[0].f32[e];
+            if (!top_zero) lds[P.off[0][0] + e] = lv[0].u32[e];
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < nl; ++l) {
+        const LevelView& V = lv[l].V;
+        float* u = lds + P.off[l][0];
+        const float* f = lds + P.off[l][1];
+        for (int s = 0; s < nu1; ++s) {
+            t_half<float, false>(V, u, f, (float*)nullptr, 0, s == 0 && (l > 0 || top_zero));
+            __syncthreads();
+            t_half<float, false>(V, u, f, (float*)nullptr, 1, 0);
+            __syncthreads();
+        }
+        t_restrict_red_fly<float>(V, lv[l + 1].V, u, f, lds + P.off[l + 1][1]);
+        __syncthreads();
+    }
+    {
+        const LevelView& V = lv[nl - 1].V;
+        float* u = lds + P.off[nl - 1][0];
+        const float* f = lds + P.off[nl - 1][1];
+        for (int pass = 0; pass < 2 * csweeps; ++pass) {
+            for (int h = 0; h < 2; ++h) {
+                const int colour = (pass < csweeps) ? h : 1 - h;
+                t_half<float, false>(V, u, f, (float*)nullptr, colour, pass == 0 && h == 0 && (nl > 1 || top_zero));
+                __syncthreads();
+            }
+        }
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+        const LevelView& V = lv[l].V;
+        float* u = lds + P.off[l][0];
+        const float* f = lds + P.off[l][1];
+        t_prolong<float>(V, lv[l + 1].V, lds + P.off[l + 1][0], u, nu2 > 0);
+        __syncthreads();
+        for (int s = 0; s < nu2; ++s) {
+            t_half<float, false>(V, u, f, (float*)nullptr, 1, 0);
+            __syncthreads();
+            t_half<float, false>(V, u, f, (float*)nullptr, 0, 0);
+            __syncthreads();
+        }
+    }
+    {
+        const size_t n = 2 * lv[0].V.cs;
+        for (size_t e = threadIdx.x; e < n; e += TL_NT) lv[0].u32[e] = lds[P.off[0][0] + e];
+    }
+}
+
+hipError_t launch_tail_lds(const TailLevel* lv, int nu1, int nu2, int csweeps, int top_zero, const LdsPlan& P,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tail_lds, dim3(1), dim3(TL_NT), sizeof(float) * (size_t)P.total, s, lv, nu1, nu2, csweeps,
+                       top_zero, P);
+    return hipGetLastError();
+}
+
+// Device limit on one workgroup's LDS, set as the LDS tail's ceiling once
+int tail_lds_limit()
+{
+    static const int lim = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+        if (hipFuncSetAttribute((const void*)k_tail_lds, hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess)
+            return 0;
+        return v;
+    }();
+    return lim;
+}
+
 // ------------------------------------------------------------ reduction
 // out[c] = sum_b partials[b * stride + c], c < stride, in a fixed order
 // (thread t takes t, t+1024, ..., then a fixed tree): a given launch shape
@@ -1256,7 +1485,8 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
     template hipError_t launch_update_p<T>(const LevelView&, const T*, const T*, T*, const double*, int, int, int,  \
                                            hipStream_t);                                                          \
     template hipError_t launch_update_xr<T>(const LevelView&, T*, T*, const T*, const T*, const double*, int, int, \
-                                            double*, hipStream_t);                                                \
+                                            double*, hipStream_t, int*);                                          \
+    template int flat_blocks<T>(const LevelView&);                                                                \
     template hipError_t launch_fill_zero<T>(T*, size_t, hipStream_t);
 INST(double)
 INST(float)

@@ -79,6 +79,17 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     Level& L = g->lev[l];
     const LevelView& V = L.view;
     hipStream_t s = g->stream;
+    if (sizeof(T) == 4 && l == g->tail32_top) {
+        // the rest of the FP32 cycle in one workgroup, all levels in LDS
+        if (l == 0 && ((void*)u != (void*)g->z32 || (const void*)f != (const void*)g->r32))
+            return fail(LASTO_ERR_STATE, "vcycle: level-0 tail needs the grid's Krylov vectors");
+        HIPCHK(launch_tail_lds(g->tail_dev + l, nu1, nu2, kCoarseSweeps, zero_start ? 1 : 0, g->lds_plan, s));
+        if (dotp) {
+            HIPCHK(launch_dot<T>(V, f, u, dotp, s));
+            *ndot = row_blocks(V);
+        }
+        return LASTO_OK;
+    }
     if (l == g->tail_top) {
         // the rest of the cycle in one workgroup; its level-0 buffers are the
         // Krylov vectors, which are the only ones a level-0 cycle is given
@@ -171,7 +182,6 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
 {
     const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
-    const int nb_r = row_blocks(V);
     HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
     float* rr = g->r32;   // working residual, updated in place
     for (int it = 0; it < iters; ++it) {
@@ -187,7 +197,8 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
         int npq = 0;
         if (lasto_status e = apply_dot<float>(g, pn, g->q32, &npq); e != LASTO_OK) return e;
         if (lasto_status e = reduce_to(g, npq, S_PQ32); e != LASTO_OK) return e;
-        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s));
+        int nb_r = 0;
+        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s, &nb_r));
         if (lasto_status e = reduce_to(g, nb_r, S_RR32); e != LASTO_OK) return e;
     }
     return LASTO_OK;
@@ -257,7 +268,8 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     if (!(o.rtol > 0.0) || o.max_iters < 1 || o.nu1 < 1 || o.nu2 < 0 || o.nu1 > 16 || o.nu2 > 16)
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad rtol/max_iters/nu1/nu2");
     if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
-        o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 1 || (o.precision == 1 && o.inner_iters < 1))
+        o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 1 || (o.precision == 1 && o.inner_iters < 1) ||
+        o.inner_first < 0)
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters");
     lasto_solve_info inf;
     std::memset(&inf, 0, sizeof(inf));
@@ -323,11 +335,12 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         if (o.precision == 1) {
             // FP32 inner PCG on the scaled FP64 residual, then v += |r| e
             HIPCHK(launch_scale_to32(V, g->r, g->r32, g->scalars, S_RR, s));
+            const int inner = (inf.refinements == 0 && o.inner_first > 0) ? o.inner_first : o.inner_iters;
             if (o.method == 1) {
-                if (lasto_status e = mg32_inner(g, o, o.inner_iters, &inf.vcycles); e != LASTO_OK) return e;
+                if (lasto_status e = mg32_inner(g, o, inner, &inf.vcycles); e != LASTO_OK) return e;
                 HIPCHK(launch_add_scaled32_nat(V, v, g->z32, g->scalars, S_RR, s));
             } else {
-                if (lasto_status e = pcg32_inner(g, o, o.inner_iters, &inf.vcycles); e != LASTO_OK) return e;
+                if (lasto_status e = pcg32_inner(g, o, inner, &inf.vcycles); e != LASTO_OK) return e;
                 HIPCHK(launch_add_scaled32_nat(V, v, g->e32, g->scalars, S_RR, s));
             }
             HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
@@ -355,8 +368,9 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             int npq = 0;
             if (lasto_status e = apply_dot<double>(g, pn, g->q, &npq); e != LASTO_OK) return e;
             if (lasto_status e = reduce_to(g, npq, S_PQ); e != LASTO_OK) return e;
-            HIPCHK(launch_update_xr<double>(V, g->x, g->r, pn, g->q, g->scalars, srz, S_PQ, g->partials, s));
-            if (lasto_status e = reduce_to(g, row_blocks(V), S_RR); e != LASTO_OK) return e;
+            int nb_r = 0;
+            HIPCHK(launch_update_xr<double>(V, g->x, g->r, pn, g->q, g->scalars, srz, S_PQ, g->partials, s, &nb_r));
+            if (lasto_status e = reduce_to(g, nb_r, S_RR); e != LASTO_OK) return e;
             cg_it++;
         }
         if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;

@@ -53,6 +53,7 @@ class SolveOpts(C.Structure):
         ("lmax_bc", C.c_int),
         ("debug_nan_iter", C.c_int),
         ("profile", C.c_int),
+        ("inner_first", C.c_int),
     ]
 
 

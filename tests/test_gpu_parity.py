@@ -146,6 +146,8 @@ SOLVE_CASES = [
     (1, 33, dict()),
     (1, 25, dict()),                         # 25^3 <= 16384 nodes: the whole cycle in one workgroup
     (1, 25, dict(precision=1, method=1)),
+    (1, 17, dict(precision=1)),              # every FP32 level of the cycle fits in LDS
+    (1, 17, dict(precision=1, method=1)),
     (2, 65, dict()),
     (2, 65, dict(method=1)),
     (2, 65, dict(precision=1)),
