@@ -302,6 +302,7 @@ static void free_grid(lasto_grid g)
     (void)hipFree(g->moments);
     (void)hipFree(g->stage);
     (void)hipFree(g->tail_dev);
+    (void)hipFree(g->lds_tabs);
     for (double*& a : g->lscr) {
         (void)hipFree(a);
         a = nullptr;
@@ -314,6 +315,91 @@ static void free_grid(lasto_grid g)
 }  // namespace lasto
 
 using namespace lasto;
+
+// FP32 LDS tail: from the first level whose corrections, right-hand sides
+// and tables, with those of every coarser level, fit in one workgroup's LDS
+// (keeping 8 KB spare), and only where it takes over at least the levels of
+// the global-memory tail (a later start would run those by separate
+// launches). Builds the plan and the device table run it copies in.
+static lasto_status build_lds_tail(lasto_grid g)
+{
+    g->tail32_top = -1;
+    const int lim = tail_lds_limit() - 8192;
+    if (lim <= 0) return LASTO_OK;
+    auto dims_of = [&](int l, int d) { return d == 2 ? g->lev[l].view.nz : g->lev[l].n[d]; };
+    auto tab_of = [&](int l, bool coarse) {
+        const int f = coarse ? l - 1 : l;
+        return (size_t)lds_tab_size(dims_of(l, 0), dims_of(l, 1), dims_of(l, 2), dims_of(f, 0), dims_of(f, 1),
+                                    dims_of(f, 2), coarse);
+    };
+    for (int t = g->nlev - 1; t >= 0 && g->nlev - t <= kLdsMaxLevels; --t) {
+        size_t need = 0;
+        for (int l = t; l < g->nlev; ++l) need += 2 * g->lev[l].nsplit + tab_of(l, l > t);
+        if (need * sizeof(float) > (size_t)lim) break;
+        g->tail32_top = t;
+    }
+    if (g->tail32_top > g->tail_top) g->tail32_top = -1;
+    if (g->tail32_top < 0) return LASTO_OK;
+    const int top = g->tail32_top;
+    LdsPlan& P = g->lds_plan;
+    P = LdsPlan{};
+    P.nl = g->nlev - top;
+    int o = 0;
+    for (int q = 0; q < P.nl; ++q) {
+        const LevelView& V = g->lev[top + q].view;
+        P.dims[q][0] = V.nx;
+        P.dims[q][1] = V.ny;
+        P.dims[q][2] = V.nz;
+        P.dims[q][3] = V.W;
+        P.dims[q][4] = (int)V.cs;
+        P.off[q][0] = o;
+        P.off[q][1] = o + (int)(2 * V.cs);
+        o += (int)(4 * V.cs);
+    }
+    P.tab0 = o;
+    std::vector<float> tab;
+    for (int q = 0; q < P.nl; ++q) {
+        const int l = top + q;
+        const LevelView& V = g->lev[l].view;
+        P.off[q][2] = o + (int)tab.size();
+        const size_t base = tab.size();
+        tab.resize(base + tab_of(l, q > 0), 0.0f);
+        const int n[3] = {V.nx, V.ny, V.nz};
+        const int fn[3] = {q > 0 ? dims_of(l - 1, 0) : 0, q > 0 ? dims_of(l - 1, 1) : 0, q > 0 ? dims_of(l - 1, 2) : 0};
+        float* b0 = tab.data() + base;
+        LdsTab t = lds_tab(b0, n[0], n[1], n[2], fn[0], fn[1], fn[2], q > 0);
+        auto w = [&](const float* at) { return const_cast<float*>(at); };
+        float* am[3] = {w(t.cxm), w(t.cym), w(t.czm)};
+        float* ap[3] = {w(t.cxp), w(t.cyp), w(t.czp)};
+        float* rf[3] = {w(t.rfx), w(t.rfy), w(t.rfz)};
+        float* rw[3] = {w(t.rwx), w(t.rwy), w(t.rwz)};
+        float* pc[3] = {w(t.pcx), w(t.pcy), w(t.pcz)};
+        float* pw[3] = {w(t.pwx), w(t.pwy), w(t.pwz)};
+        for (int d = 0; d < 3; ++d) {
+            LASTO_HIP(hipMemcpy(am[d], V.ax[d].amf, sizeof(float) * n[d], hipMemcpyDeviceToHost));
+            LASTO_HIP(hipMemcpy(ap[d], V.ax[d].apf, sizeof(float) * n[d], hipMemcpyDeviceToHost));
+            if (q == 0) continue;
+            std::vector<int> vi(std::max(n[d], fn[d]));
+            std::vector<double> vd(3 * (size_t)std::max(n[d], fn[d]));
+            LASTO_HIP(hipMemcpy(vi.data(), V.ax[d].rf, sizeof(int) * n[d], hipMemcpyDeviceToHost));
+            LASTO_HIP(hipMemcpy(vd.data(), V.ax[d].rw, sizeof(double) * 3 * n[d], hipMemcpyDeviceToHost));
+            for (int e = 0; e < n[d]; ++e) rf[d][e] = (float)vi[e];
+            for (int e = 0; e < 3 * n[d]; ++e) rw[d][e] = (float)vd[e];
+            LASTO_HIP(hipMemcpy(vi.data(), V.ax[d].pc, sizeof(int) * fn[d], hipMemcpyDeviceToHost));
+            LASTO_HIP(hipMemcpy(vd.data(), V.ax[d].pw, sizeof(double) * 2 * fn[d], hipMemcpyDeviceToHost));
+            for (int e = 0; e < fn[d]; ++e) pc[d][e] = (float)vi[e];
+            for (int e = 0; e < 2 * fn[d]; ++e) pw[d][e] = (float)vd[e];
+        }
+        std::vector<unsigned char> zi(n[2]);
+        LASTO_HIP(hipMemcpy(zi.data(), V.zint, n[2], hipMemcpyDeviceToHost));
+        for (int k = 0; k < n[2]; ++k) w(t.zin)[k] = zi[k] ? 1.0f : 0.0f;
+    }
+    P.ntab = (int)tab.size();
+    P.total = o + P.ntab;
+    LASTO_HIP(hipMalloc((void**)&g->lds_tabs, sizeof(float) * tab.size()));
+    LASTO_HIP(hipMemcpy(g->lds_tabs, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
+    return LASTO_OK;
+}
 
 extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double* y, int ny, const double* z, int nz,
                                           int n_batch, void* hip_stream, lasto_grid* out)
@@ -446,32 +532,9 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
                 g->tail_top = l;
                 break;
             }
-        // FP32 LDS tail: from the first level whose correction and
-        // right-hand side, with those of every coarser level, fit in one
-        // workgroup's LDS (keeping 8 KB spare)
-        const int lim = tail_lds_limit() - 8192;
-        size_t need = 0;
-        g->tail32_top = -1;
-        for (int l = g->nlev - 1; l >= 0 && g->nlev - l <= kLdsMaxLevels; --l) {
-            need += 2 * g->lev[l].nsplit;
-            if (lim > 0 && need * sizeof(float) <= (size_t)lim) g->tail32_top = l;
-            else break;
-        }
-        // (only where it takes over at least the levels of the global-memory
-        // tail; a later start would run those levels by separate launches)
-        if (g->tail32_top > g->tail_top) g->tail32_top = -1;
-        if (g->tail32_top >= 0) {
-            LdsPlan& P = g->lds_plan;
-            P.nl = g->nlev - g->tail32_top;
-            int o = 0;
-            for (int q = 0; q < P.nl; ++q) {
-                const int ns = (int)g->lev[g->tail32_top + q].nsplit;
-                P.off[q][0] = o;
-                P.off[q][1] = o + ns;
-                o += 2 * ns;
-            }
-            P.total = o;
-        }
+        st = build_lds_tail(g);
+    }
+    if (st == LASTO_OK) {
         std::vector<TailLevel> tl(g->nlev);
         for (int l = 0; l < g->nlev; ++l) {
             Level& L = g->lev[l];

@@ -156,14 +156,66 @@ template <> struct TailBuf<float> {
 
 constexpr size_t kTailMaxPts = 16384;   // levels at or below this size run in the tail kernel
 
-// LDS layout of the FP32 tail: per level, the offsets (in floats) of its
-// correction and right-hand side (split layout, 2 cs each)
+// LDS layout of the FP32 tail. Per level q (0 = the first level it takes):
+// dims nx, ny, nz, W, cs; offsets (floats) of its correction and right-hand
+// side (split layout, 2 cs each, 16-byte aligned) and of its table block.
+// The table blocks are one run of ntab floats at tab0, copied in from a
+// device table the grid builds (layout: lds_tab).
 constexpr int kLdsMaxLevels = 12;
 struct LdsPlan {
     int nl;
-    int total;                      // floats
-    int off[kLdsMaxLevels][2];
+    int total;                      // floats of LDS
+    int tab0, ntab;
+    int dims[kLdsMaxLevels][5];
+    int off[kLdsMaxLevels][3];
 };
+
+// Table block of one level of the LDS tail (FP32): am and ap of x, y, z,
+// interior-plane flags of z (1 or 0); below the first level also the
+// restriction from the finer level (rf as values, rw) and the interpolation
+// back to it (pc as values, pw), indexed as in Axis. fn*: the finer level's
+// sizes.
+struct LdsTab {
+    const float *cxm, *cxp, *cym, *cyp, *czm, *czp, *zin;
+    const float *rfx, *rfy, *rfz, *rwx, *rwy, *rwz;
+    const float *pcx, *pcy, *pcz, *pwx, *pwy, *pwz;
+};
+
+__host__ __device__ __forceinline__ int lds_tab_size(int nx, int ny, int nz, int fnx, int fny, int fnz, bool coarse)
+{
+    int s = 2 * nx + 2 * ny + 3 * nz;
+    if (coarse) s += 4 * (nx + ny + nz) + 3 * (fnx + fny + fnz);
+    return (s + 3) / 4 * 4;
+}
+
+template <typename P>
+__host__ __device__ __forceinline__ LdsTab lds_tab(P* b, int nx, int ny, int nz, int fnx, int fny, int fnz,
+                                                   bool coarse)
+{
+    LdsTab t{};
+    t.cxm = b;
+    t.cxp = t.cxm + nx;
+    t.cym = t.cxp + nx;
+    t.cyp = t.cym + ny;
+    t.czm = t.cyp + ny;
+    t.czp = t.czm + nz;
+    t.zin = t.czp + nz;
+    if (coarse) {
+        t.rfx = t.zin + nz;
+        t.rfy = t.rfx + nx;
+        t.rfz = t.rfy + ny;
+        t.rwx = t.rfz + nz;
+        t.rwy = t.rwx + 3 * nx;
+        t.rwz = t.rwy + 3 * ny;
+        t.pcx = t.rwz + 3 * nz;
+        t.pcy = t.pcx + fnx;
+        t.pcz = t.pcy + fny;
+        t.pwx = t.pcz + fnz;
+        t.pwy = t.pwx + 2 * fnx;
+        t.pwz = t.pwy + 2 * fny;
+    }
+    return t;
+}
 
 }  // namespace lasto
 
@@ -176,6 +228,7 @@ struct lasto_grid_s {
     int tail_top = 0;                      // first level handled by the tail kernel
     int tail32_top = -1;                   // first level of the FP32 LDS tail (-1: none)
     lasto::LdsPlan lds_plan{};
+    float* lds_tabs = nullptr;             // device copy of the LDS tail's tables
     lasto::TailLevel* tail_dev = nullptr;  // device [nlev]
     // fine-level Krylov vectors (FP64, split layout): residual, preconditioned
     // residual, search direction (ping-pong), A p
@@ -256,9 +309,10 @@ hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e
 // black) sweeps then csweeps (black, red).
 template <typename T>
 hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweeps, int top_zero, hipStream_t s);
-// the FP32 cycle below level lv[0] with every level in LDS (plan from the grid)
-hipError_t launch_tail_lds(const TailLevel* lv, int nu1, int nu2, int csweeps, int top_zero, const LdsPlan& P,
-                           hipStream_t s);
+// the FP32 cycle from level P's first with every level in LDS: u, f that
+// level's correction and right-hand side (split), tabs the grid's table run
+hipError_t launch_tail_lds(float* u, const float* f, const float* tabs, int nu1, int nu2, int csweeps, int top_zero,
+                           const LdsPlan& P, hipStream_t s);
 int tail_lds_limit();   // bytes of LDS one workgroup may use (0 if unknown)
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s);

@@ -1313,118 +1313,268 @@ hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweep
 }
 
 // ------------------------------------------------------ LDS tail (FP32)
-// The same cycle with every level's correction and right-hand side held in
-// LDS, so each of its ~50 barrier-separated steps waits on LDS rather than
-// on the L2 or HBM; the fine residual is formed where the restriction reads
-// it instead of being stored. Only the top level's right-hand side comes in
-// from global memory (and its correction when the cycle continues from it),
-// and only the top level's correction goes back.
-template <typename T>
-__device__ __forceinline__ T resid_at(const LevelView& F, const T* u, const T* f, int i, int j, int k)
+// The same cycle with every level's correction, right-hand side and FP32
+// coefficient tables held in one workgroup's LDS. On one compute unit the
+// cycle is bound by instruction issue, not by memory, so each step is a flat
+// loop over its items with 32-bit LDS offsets, table lookups instead of
+// per-node coefficient conversions, and index division by a float
+// reciprocal (exact after one correction for the small counts here). The
+// fine residual is formed where the restriction reads it instead of being
+// stored. Only the top level's right-hand side (and its correction when the
+// cycle continues from one) comes in from global memory, and only its
+// correction goes back.
+
+// q = a / d, r = a - q d for 0 <= a < 2^24 with inv = 1/d rounded: the float
+// quotient is off by at most one, which the two corrections remove
+__device__ __forceinline__ int lh_divmod(int a, int d, float inv, int& r)
 {
-    if (i < 1 || i > F.nx - 2 || j < 1 || j > F.ny - 2 || k < 1 || k > F.nz - 2 || !F.zint[k]) return T(0);
-    const size_t at = sidx(F, i, j, k);
-    return f[at] - apply_split(F, u, i, j, k, u[at]);
+    int q = (int)((float)a * inv);
+    r = a - q * d;
+    if (r >= d) {
+        ++q;
+        r -= d;
+    }
+    if (r < 0) {
+        --q;
+        r += d;
+    }
+    return q;
 }
 
-// f_coarse = R r with r = f - A u on red fine nodes (black ones vanish after
-// a black half-sweep)
-template <typename T>
-__device__ void t_restrict_red_fly(const LevelView& F, const LevelView& C, const T* u, const T* f, T* fc)
+struct LhLevel {
+    int nx, ny, nz, W, cs, P;   // P = ny W, one plane of one colour
+    LdsTab t;
+};
+
+__device__ __forceinline__ LhLevel lh_level(float* lds, const LdsPlan& P, int q)
 {
-    const Cols cl = tail_cols((C.nx - 2) * (C.ny - 2));
-    if (!cl.active) return;
-    const int I = 1 + cl.col % (C.nx - 2), J = 1 + cl.col / (C.nx - 2);
-    const int fi = C.ax[0].rf[I], fj = C.ax[1].rf[J];
-    const double* wx = C.ax[0].rw + 3 * I;
-    const double* wy = C.ax[1].rw + 3 * J;
-    for (int K = 1 + cl.grp; K <= C.nz - 2; K += cl.ng) {
-        if (!C.zint[K]) continue;
-        const int fk = C.ax[2].rf[K];
-        const double* wz = C.ax[2].rw + 3 * K;
-        T acc = T(0);
-        for (int c = 0; c < 3; ++c) {
-            if (wz[c] == 0.0) continue;
-            for (int b = 0; b < 3; ++b) {
-                if (wy[b] == 0.0) continue;
-                const int jj = fj - 1 + b, kk = fk - 1 + c;
-                T sx = T(0);
-                for (int a = 0; a < 3; ++a) {
-                    const int ii = fi - 1 + a;
-                    if (wx[a] == 0.0 || ((ii + jj + kk) & 1)) continue;
-                    sx += (T)wx[a] * resid_at(F, u, f, ii, jj, kk);
+    LhLevel L;
+    L.nx = P.dims[q][0];
+    L.ny = P.dims[q][1];
+    L.nz = P.dims[q][2];
+    L.W = P.dims[q][3];
+    L.cs = P.dims[q][4];
+    L.P = L.ny * L.W;
+    const int* fd = q > 0 ? P.dims[q - 1] : P.dims[q];
+    L.t = lds_tab(lds + P.off[q][2], L.nx, L.ny, L.nz, fd[0], fd[1], fd[2], q > 0);
+    return L;
+}
+
+// half-sweep of colour c (zero_in: the other colour is read as zero)
+__device__ void lh_half(const LhLevel& L, float* u, const float* f, int c, bool zero_in)
+{
+    const int mc = (L.nx - 2) / 2 + 1, ry = L.ny - 2;
+    const int total = mc * ry * (L.nz - 2);
+    const float im = 1.0f / (float)mc, iy = 1.0f / (float)ry;
+    float* uc = u + c * L.cs;
+    const float* uo = u + (1 - c) * L.cs;
+    const float* fc = f + c * L.cs;
+    for (int t = threadIdx.x; t < total; t += TL_NT) {
+        int m, jj;
+        const int row = lh_divmod(t, mc, im, m);
+        const int k = 1 + lh_divmod(row, ry, iy, jj);
+        const int j = 1 + jj;
+        const int o = (c + j + k) & 1, i = o + 2 * m;
+        if (i < 1 || i > L.nx - 2 || L.t.zin[k] == 0.0f) continue;
+        const int at = (k * L.ny + j) * L.W + m;
+        const float cxm = L.t.cxm[i], cxp = L.t.cxp[i], cym = L.t.cym[j], cyp = L.t.cyp[j];
+        const float czm = L.t.czm[k], czp = L.t.czp[k];
+        const float d = cxm + cxp + cym + cyp + czm + czp;
+        float sum = 0.0f;
+        if (!zero_in) {
+            const float* q = uo + at;
+            sum = cxm * q[o - 1] + cxp * q[o];
+            sum += cym * q[-L.W] + cyp * q[L.W];
+            sum += czm * q[-L.P] + czp * q[L.P];
+        }
+        uc[at] = (sum - fc[at]) * recip(d);
+    }
+}
+
+// residual f - A u at a red node (zero off the interior)
+__device__ __forceinline__ float lh_resid_red(const LhLevel& L, const float* u, const float* f, int i, int j, int k)
+{
+    if (i < 1 || i > L.nx - 2 || j < 1 || j > L.ny - 2 || k < 1 || k > L.nz - 2 || L.t.zin[k] == 0.0f) return 0.0f;
+    const int at = (k * L.ny + j) * L.W + (i >> 1);
+    const int o = i & 1;
+    const float cen = u[at];
+    const float* q = u + L.cs + at;   // black neighbours
+    float a = L.t.cxm[i] * (q[o - 1] - cen) + L.t.cxp[i] * (q[o] - cen);
+    a += L.t.cym[j] * (q[-L.W] - cen) + L.t.cyp[j] * (q[L.W] - cen);
+    a += L.t.czm[k] * (q[-L.P] - cen) + L.t.czp[k] * (q[L.P] - cen);
+    return f[at] - a;
+}
+
+// fc = R r, r = f - A u of the fine level on its red nodes (black residuals
+// vanish after the black half-sweep that ends the pre-smoothing)
+__device__ void lh_restrict(const LhLevel& F, const float* u, const float* f, const LhLevel& C, float* fcoarse)
+{
+    const int rx = C.nx - 2, ry = C.ny - 2;
+    const int total = rx * ry * (C.nz - 2);
+    const float ix = 1.0f / (float)rx, iy = 1.0f / (float)ry;
+    for (int t = threadIdx.x; t < total; t += TL_NT) {
+        int I0, J0;
+        const int row = lh_divmod(t, rx, ix, I0);
+        const int K = 1 + lh_divmod(row, ry, iy, J0);
+        const int I = 1 + I0, J = 1 + J0;
+        if (C.t.zin[K] == 0.0f) continue;
+        const int fi = (int)C.t.rfx[I], fj = (int)C.t.rfy[J], fk = (int)C.t.rfz[K];
+        float acc = 0.0f;
+        for (int cz = 0; cz < 3; ++cz) {
+            const float wz = C.t.rwz[3 * K + cz];
+            if (wz == 0.0f) continue;
+            const int kk = fk - 1 + cz;
+            for (int by = 0; by < 3; ++by) {
+                const float wy = C.t.rwy[3 * J + by];
+                if (wy == 0.0f) continue;
+                const int jj = fj - 1 + by;
+                float sx = 0.0f;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int ii = fi - 1 + ax;
+                    const float wx = C.t.rwx[3 * I + ax];
+                    if (wx == 0.0f || ((ii + jj + kk) & 1)) continue;
+                    sx += wx * lh_resid_red(F, u, f, ii, jj, kk);
                 }
-                acc += (T)(wz[c] * wy[b]) * sx;
+                acc += (wz * wy) * sx;
             }
         }
-        fc[sidx(C, I, J, K)] = acc;
+        fcoarse[(K * C.ny + J) * C.W + (I >> 1) + ((I + J + K) & 1) * C.cs] = acc;
     }
 }
 
-__global__ __launch_bounds__(TL_NT) void k_tail_lds(const TailLevel* __restrict__ lv, int nu1, int nu2, int csweeps,
+// u += P e on the fine nodes of colour c (P: trilinear in the coordinates)
+__device__ void lh_prolong(const LhLevel& F, float* u, const LhLevel& C, const float* e, int c)
+{
+    const int mc = (F.nx - 2) / 2 + 1, ry = F.ny - 2;
+    const int total = mc * ry * (F.nz - 2);
+    const float im = 1.0f / (float)mc, iy = 1.0f / (float)ry;
+    for (int t = threadIdx.x; t < total; t += TL_NT) {
+        int m, jj;
+        const int row = lh_divmod(t, mc, im, m);
+        const int k = 1 + lh_divmod(row, ry, iy, jj);
+        const int j = 1 + jj;
+        const int o = (c + j + k) & 1, i = o + 2 * m;
+        if (i < 1 || i > F.nx - 2 || F.t.zin[k] == 0.0f) continue;
+        const int Ix = (int)C.t.pcx[i], Jy = (int)C.t.pcy[j], Kz = (int)C.t.pcz[k];
+        const float wx0 = C.t.pwx[2 * i], wx1 = C.t.pwx[2 * i + 1];
+        const float wy0 = C.t.pwy[2 * j], wy1 = C.t.pwy[2 * j + 1];
+        const float wz0 = C.t.pwz[2 * k], wz1 = C.t.pwz[2 * k + 1];
+        float acc = 0.0f;
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz) {
+            float sy = 0.0f;
+#pragma unroll
+            for (int by = 0; by < 2; ++by) {
+                const int Jb = Jy + by, Kc = Kz + cz;
+                const int rowc = (Kc * C.ny + Jb) * C.W;
+                const int ca = (Ix + Jb + Kc) & 1;   // colour of coarse Ix; Ix + 1 has the other
+                const float va = e[ca * C.cs + rowc + (Ix >> 1)];
+                const float vb = e[(ca ^ 1) * C.cs + rowc + ((Ix + 1) >> 1)];
+                sy += (by ? wy1 : wy0) * (wx0 * va + wx1 * vb);
+            }
+            acc += (cz ? wz1 : wz0) * sy;
+        }
+        u[c * F.cs + (k * F.ny + j) * F.W + m] += acc;
+    }
+}
+
+__global__ __launch_bounds__(TL_NT) void k_tail_lds(float* __restrict__ utop, const float* __restrict__ ftop,
+                                                    const float* __restrict__ tabs, int nu1, int nu2, int csweeps,
                                                     int top_zero, LdsPlan P)
 {
-    extern __shared__ float lds[];
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
     const int nl = P.nl;
-    for (int e = threadIdx.x; e < P.total; e += TL_NT) lds[e] = 0.f;
-    __syncthreads();
+    // every correction to zero (faces and padding stay zero), the tables in,
+    // the top level's right-hand side (and correction) in: 16-byte accesses,
+    // four in flight per thread
+    for (int q = 0; q < nl; ++q) {
+        float4* u4 = reinterpret_cast<float4*>(lds + P.off[q][0]);
+        const int n4 = P.dims[q][4] / 2;   // 2 cs / 4
+        for (int e = threadIdx.x; e < n4; e += TL_NT) u4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     {
-        const size_t n = 2 * lv[0].V.cs;
-        for (size_t e = threadIdx.x; e < n; e += TL_NT) {
-            lds[P.off[0][1] + e] = lv[0].f32[e];
-            if (!top_zero) lds[P.off[0][0] + e] = lv[0].u32[e];
+        const int n4 = P.dims[0][4] / 2;
+        const float4* f4 = reinterpret_cast<const float4*>(ftop);
+        const float4* g4 = reinterpret_cast<const float4*>(utop);
+        float4* lf = reinterpret_cast<float4*>(lds + P.off[0][1]);
+        float4* lu = reinterpret_cast<float4*>(lds + P.off[0][0]);
+        for (int e0 = threadIdx.x; e0 < n4; e0 += 4 * TL_NT) {
+            float4 vf[4], vu[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int e = e0 + b * TL_NT;
+                if (e < n4) {
+                    vf[b] = f4[e];
+                    if (!top_zero) vu[b] = g4[e];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int e = e0 + b * TL_NT;
+                if (e < n4) {
+                    lf[e] = vf[b];
+                    if (!top_zero) lu[e] = vu[b];
+                }
+            }
         }
+        for (int e = threadIdx.x; e < P.ntab; e += TL_NT) lds[P.tab0 + e] = tabs[e];
     }
     __syncthreads();
-    for (int l = 0; l + 1 < nl; ++l) {
-        const LevelView& V = lv[l].V;
-        float* u = lds + P.off[l][0];
-        const float* f = lds + P.off[l][1];
+    for (int q = 0; q + 1 < nl; ++q) {
+        const LhLevel L = lh_level(lds, P, q);
+        float* u = lds + P.off[q][0];
+        const float* f = lds + P.off[q][1];
         for (int s = 0; s < nu1; ++s) {
-            t_half<float, false>(V, u, f, (float*)nullptr, 0, s == 0 && (l > 0 || top_zero));
+            lh_half(L, u, f, 0, s == 0 && (q > 0 || top_zero));
             __syncthreads();
-            t_half<float, false>(V, u, f, (float*)nullptr, 1, 0);
+            lh_half(L, u, f, 1, false);
             __syncthreads();
         }
-        t_restrict_red_fly<float>(V, lv[l + 1].V, u, f, lds + P.off[l + 1][1]);
+        lh_restrict(L, u, f, lh_level(lds, P, q + 1), lds + P.off[q + 1][1]);
         __syncthreads();
     }
     {
-        const LevelView& V = lv[nl - 1].V;
+        // coarsest: csweeps sweeps (red, black), then csweeps (black, red)
+        const LhLevel L = lh_level(lds, P, nl - 1);
         float* u = lds + P.off[nl - 1][0];
         const float* f = lds + P.off[nl - 1][1];
         for (int pass = 0; pass < 2 * csweeps; ++pass) {
             for (int h = 0; h < 2; ++h) {
                 const int colour = (pass < csweeps) ? h : 1 - h;
-                t_half<float, false>(V, u, f, (float*)nullptr, colour, pass == 0 && h == 0 && (nl > 1 || top_zero));
+                lh_half(L, u, f, colour, pass == 0 && h == 0 && (nl > 1 || top_zero));
                 __syncthreads();
             }
         }
     }
-    for (int l = nl - 2; l >= 0; --l) {
-        const LevelView& V = lv[l].V;
-        float* u = lds + P.off[l][0];
-        const float* f = lds + P.off[l][1];
-        t_prolong<float>(V, lv[l + 1].V, lds + P.off[l + 1][0], u, nu2 > 0);
+    for (int q = nl - 2; q >= 0; --q) {
+        const LhLevel L = lh_level(lds, P, q), C = lh_level(lds, P, q + 1);
+        float* u = lds + P.off[q][0];
+        const float* f = lds + P.off[q][1];
+        // only red nodes take the correction when a black half-sweep follows
+        lh_prolong(L, u, C, lds + P.off[q + 1][0], 0);
+        if (nu2 == 0) lh_prolong(L, u, C, lds + P.off[q + 1][0], 1);
         __syncthreads();
         for (int s = 0; s < nu2; ++s) {
-            t_half<float, false>(V, u, f, (float*)nullptr, 1, 0);
+            lh_half(L, u, f, 1, false);
             __syncthreads();
-            t_half<float, false>(V, u, f, (float*)nullptr, 0, 0);
+            lh_half(L, u, f, 0, false);
             __syncthreads();
         }
     }
     {
-        const size_t n = 2 * lv[0].V.cs;
-        for (size_t e = threadIdx.x; e < n; e += TL_NT) lv[0].u32[e] = lds[P.off[0][0] + e];
+        const int n4 = P.dims[0][4] / 2;
+        float4* g4 = reinterpret_cast<float4*>(utop);
+        const float4* lu = reinterpret_cast<const float4*>(lds + P.off[0][0]);
+        for (int e = threadIdx.x; e < n4; e += TL_NT) g4[e] = lu[e];
     }
 }
 
-hipError_t launch_tail_lds(const TailLevel* lv, int nu1, int nu2, int csweeps, int top_zero, const LdsPlan& P,
-                           hipStream_t s)
+hipError_t launch_tail_lds(float* u, const float* f, const float* tabs, int nu1, int nu2, int csweeps, int top_zero,
+                           const LdsPlan& P, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tail_lds, dim3(1), dim3(TL_NT), sizeof(float) * (size_t)P.total, s, lv, nu1, nu2, csweeps,
-                       top_zero, P);
+    hipLaunchKernelGGL(k_tail_lds, dim3(1), dim3(TL_NT), sizeof(float) * (size_t)P.total, s, u, f, tabs, nu1, nu2,
+                       csweeps, top_zero, P);
     return hipGetLastError();
 }
 

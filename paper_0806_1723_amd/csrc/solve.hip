@@ -81,9 +81,8 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     hipStream_t s = g->stream;
     if (sizeof(T) == 4 && l == g->tail32_top) {
         // the rest of the FP32 cycle in one workgroup, all levels in LDS
-        if (l == 0 && ((void*)u != (void*)g->z32 || (const void*)f != (const void*)g->r32))
-            return fail(LASTO_ERR_STATE, "vcycle: level-0 tail needs the grid's Krylov vectors");
-        HIPCHK(launch_tail_lds(g->tail_dev + l, nu1, nu2, kCoarseSweeps, zero_start ? 1 : 0, g->lds_plan, s));
+        HIPCHK(launch_tail_lds((float*)u, (const float*)f, g->lds_tabs, nu1, nu2, kCoarseSweeps, zero_start ? 1 : 0,
+                               g->lds_plan, s));
         if (dotp) {
             HIPCHK(launch_dot<T>(V, f, u, dotp, s));
             *ndot = row_blocks(V);
