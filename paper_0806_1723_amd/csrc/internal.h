@@ -325,7 +325,7 @@ hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pne
 // partials of <r, r>_W (count in *nparts, at most flat_blocks<T>(L))
 template <typename T>
 hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
-                            int i_den, double* partials, hipStream_t s, int* nparts);
+                            int i_den, double* partials, hipStream_t s, int* nparts, int first = 0);
 template <typename T>
 int flat_blocks(const LevelView& L);
 int row_blocks(const LevelView& L);   // partials of the row-wise split dot
@@ -334,15 +334,18 @@ hipError_t launch_residual_nat(const LevelView& L, const double* v, const double
                                double* partials, int interior_zero, hipStream_t s);
 hipError_t launch_apply_nat(const LevelView& L, const double* u, double* Au, hipStream_t s);
 hipError_t launch_add_nat(const LevelView& L, double* v, const double* e_split, hipStream_t s);
-hipError_t launch_scale_to32(const LevelView& L, const double* r, float* r32, const double* scal, int i_norm2,
-                             hipStream_t s);
-hipError_t launch_add_scaled32_nat(const LevelView& L, double* v, const float* e32, const double* scal, int i_norm2,
-                                   hipStream_t s);
+// r32 = bscale rho - A v in FP32 (split), partials of ||r||_W^2 (FP64)
+hipError_t launch_residual_nat32(const LevelView& L, const double* v, const double* rho, double bscale, float* r32,
+                                 double* partials, hipStream_t s);
+// v (natural) += e32 (+ alpha p32 when p32 is given, alpha = scal[i_num]/scal[i_den])
+hipError_t launch_add32_nat(const LevelView& L, double* v, const float* e32, const float* p32, const double* scal,
+                            int i_num, int i_den, hipStream_t s);
 hipError_t launch_nat_to_split(const LevelView& L, const double* a, double* s_out, hipStream_t s);
 hipError_t launch_split_to_nat(const LevelView& L, const double* s_in, double* a, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_zero(T* a, size_t n, hipStream_t s);
 hipError_t launch_inject_nan(double* r, size_t idx, hipStream_t s);
+hipError_t launch_inject_nan(float* r, size_t idx, hipStream_t s);
 
 // source, boundary, interpolation
 struct AtomDev {

@@ -563,10 +563,76 @@ __global__ __launch_bounds__(PT_NT) void k_residual_nat(LevelView L, int kp, con
     if (threadIdx.x == 0) part[block_linear()] = t;
 }
 
+// The same residual of the iterate itself (interior read), marching each
+// thread's (i, j) column up its chunk of planes: the centre values of planes
+// k-1, k, k+1 stay in registers, and plane k+1's x and y neighbours and rho
+// are loaded before plane k is computed, so two planes' loads are in flight.
+// r (split, FP64 or FP32; optional) and partials of ||r||_W^2.
+template <typename TO>
+__global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, const double* __restrict__ v,
+                                                          const double* __restrict__ rho, double bscale,
+                                                          TO* __restrict__ r, double* __restrict__ part)
+{
+    __shared__ double red[PT_NT / 64];
+    double acc = 0.0;
+    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
+    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
+    const int kb = 1 + blockIdx.z * kp;
+    const int ke = min(kb + kp, L.nz - 1);
+    if (i <= L.nx - 2 && j <= L.ny - 2) {
+        const int nx = L.nx;
+        const size_t sxy = (size_t)nx * L.ny;
+        const size_t col = (size_t)j * nx + i;
+        const double cxm = L.ax[0].am[i], cxp = L.ax[0].ap[i], cym = L.ax[1].am[j], cyp = L.ax[1].ap[j];
+        const double vxy = L.ax[0].m[i] * L.ax[1].m[j];
+        struct Ops {
+            double xm, xp, ym, yp, b;
+        };
+        auto load = [&](int k) {
+            Ops o;
+            const size_t idx = (size_t)k * sxy + col;
+            o.xm = v[idx - 1];
+            o.xp = v[idx + 1];
+            o.ym = v[idx - nx];
+            o.yp = v[idx + nx];
+            o.b = rho[idx];
+            return o;
+        };
+        double zm = v[(size_t)(kb - 1) * sxy + col], zc = v[(size_t)kb * sxy + col];
+        Ops A = load(kb);
+        for (int k = kb; k < ke; ++k) {
+            const double zp = v[(size_t)(k + 1) * sxy + col];
+            Ops B = A;
+            if (k + 1 < ke) B = load(k + 1);
+            if (L.zint[k]) {
+                double a = cxm * (A.xm - zc) + cxp * (A.xp - zc);
+                a += cym * (A.ym - zc) + cyp * (A.yp - zc);
+                a += L.ax[2].am[k] * (zm - zc) + L.ax[2].ap[k] * (zp - zc);
+                const double res = bscale * A.b - a;
+                if (r) r[sidx(L, i, j, k)] = (TO)res;
+                acc += vxy * L.ax[2].m[k] * res * res;
+            }
+            zm = zc;
+            zc = zp;
+            A = B;
+        }
+    }
+    const double t = block_sum<PT_NT>(acc, red);
+    if (threadIdx.x == 0) part[block_linear()] = t;
+}
+
 hipError_t launch_residual_nat(const LevelView& L, const double* v, const double* rho, double bscale, double* r_split,
                                double* partials, int interior_zero, hipStream_t s)
 {
-    PT_LAUNCH(k_residual_nat, L, s, v, rho, bscale, r_split, partials, interior_zero);
+    if (interior_zero) PT_LAUNCH(k_residual_nat, L, s, v, rho, bscale, r_split, partials, interior_zero);
+    else PT_LAUNCH(k_residual_march<double>, L, s, v, rho, bscale, r_split, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_nat32(const LevelView& L, const double* v, const double* rho, double bscale, float* r32,
+                                 double* partials, hipStream_t s)
+{
+    PT_LAUNCH(k_residual_march<float>, L, s, v, rho, bscale, r32, partials);
     return hipGetLastError();
 }
 
@@ -750,14 +816,15 @@ hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pne
     return hipGetLastError();
 }
 
-// x += alpha p, r -= alpha q (all split), alpha = scal[i_num]/scal[i_den];
-// partial <r,r>_W. A non-finite alpha leaves x and r untouched (the caller
-// then reports the breakdown with x still the last finite iterate).
+// x += alpha p (x = alpha p on the first step), r -= alpha q (all split),
+// alpha = scal[i_num]/scal[i_den]; partial <r,r>_W. A non-finite alpha leaves
+// x and r untouched (the caller then reports the breakdown with x still the
+// last finite iterate).
 template <typename T>
 __global__ __launch_bounds__(FL_NT) void k_update_xr(LevelView L, unsigned nvec, T* __restrict__ x,
                                                      T* __restrict__ r, const T* __restrict__ p,
                                                      const T* __restrict__ q, const double* __restrict__ scal,
-                                                     int i_num, int i_den, double* __restrict__ part)
+                                                     int i_num, int i_den, double* __restrict__ part, int first)
 {
     typedef typename Vec16<T>::V V;
     constexpr int N = Vec16<T>::N;
@@ -780,7 +847,7 @@ __global__ __launch_bounds__(FL_NT) void k_update_xr(LevelView L, unsigned nvec,
             if (lv[u]) {
                 rv[u] = reinterpret_cast<const V*>(r)[e];
                 if (ok) {
-                    xv[u] = reinterpret_cast<const V*>(x)[e];
+                    if (!first) xv[u] = reinterpret_cast<const V*>(x)[e];
                     pv[u] = reinterpret_cast<const V*>(p)[e];
                     qv[u] = reinterpret_cast<const V*>(q)[e];
                 }
@@ -795,6 +862,8 @@ __global__ __launch_bounds__(FL_NT) void k_update_xr(LevelView L, unsigned nvec,
                 rv[u] = rv[u] - alpha * qv[u];
                 reinterpret_cast<V*>(x)[e] = xv[u];
                 reinterpret_cast<V*>(r)[e] = rv[u];
+            } else if (first) {
+                reinterpret_cast<V*>(x)[e] = V(T(0));   // the iterate is still e = 0
             }
             // dual volume: x width by parity of i (zero off the interior), y, z widths
             const double* wx = L.xpar + (size_t)(((ps[u].c + ps[u].j + ps[u].k) & 1) * 3 + 2) * L.W + ps[u].m;
@@ -811,11 +880,11 @@ __global__ __launch_bounds__(FL_NT) void k_update_xr(LevelView L, unsigned nvec,
 
 template <typename T>
 hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
-                            int i_den, double* partials, hipStream_t s, int* nparts)
+                            int i_den, double* partials, hipStream_t s, int* nparts, int first)
 {
     const int nb = flat_blocks<T>(L);
     hipLaunchKernelGGL(k_update_xr<T>, dim3(nb), dim3(FL_NT), 0, s, L, flat_vectors<T>(L), x, r, p, q, scal, i_num,
-                       i_den, partials);
+                       i_den, partials, first);
     if (nparts) *nparts = nb;
     return hipGetLastError();
 }
@@ -855,45 +924,31 @@ hipError_t launch_add_f32_nat(const LevelView& L, double* v, const float* y, dou
     return hipGetLastError();
 }
 
-// r32 = r / sqrt(scal[i_norm2]) (scaled FP32 copy of the FP64 residual, split)
-__global__ __launch_bounds__(PT_NT) void k_scale_to32(LevelView L, int kp, const double* __restrict__ r,
-                                                      float* __restrict__ r32, const double* __restrict__ scal,
-                                                      int i_norm2)
+// v (natural) += e (FP32, split) and, with p given, + alpha p, alpha =
+// scal[i_num]/scal[i_den] (the last step of an inner PCG folded into v; a
+// non-finite alpha adds e alone), interior
+__global__ __launch_bounds__(PT_NT) void k_add32_nat(LevelView L, int kp, double* __restrict__ v,
+                                                     const float* __restrict__ e, const float* __restrict__ p,
+                                                     const double* __restrict__ scal, int i_num, int i_den)
 {
-    const double inv = 1.0 / sqrt(scal[i_norm2]);
-    ROW_LOOP
-    {
-        if (!inside || !L.zint[k]) continue;
-        const size_t at = ROW_AT;
-        r32[at] = (float)(r[at] * inv);
+    float alpha = 0.0f;
+    if (p) {
+        const double ad = scal[i_num] / scal[i_den];
+        alpha = isfinite(ad) ? (float)ad : 0.0f;
     }
-}
-
-hipError_t launch_scale_to32(const LevelView& L, const double* r, float* r32, const double* scal, int i_norm2,
-                             hipStream_t s)
-{
-    ROW_LAUNCH(k_scale_to32, L, s, r, r32, scal, i_norm2);
-    return hipGetLastError();
-}
-
-// v (natural) += sqrt(scal[i_norm2]) * e32 (split): the defect correction
-__global__ __launch_bounds__(PT_NT) void k_add_scaled32_nat(LevelView L, int kp, double* __restrict__ v,
-                                                            const float* __restrict__ e,
-                                                            const double* __restrict__ scal, int i_norm2)
-{
-    const double sc = sqrt(scal[i_norm2]);
-    if (!isfinite(sc)) return;
     INTERIOR_LOOP
     {
         if (!inside || !L.zint[k]) continue;
-        v[((size_t)k * L.ny + j) * L.nx + i] += sc * (double)e[sidx(L, i, j, k)];
+        const size_t at = sidx(L, i, j, k);
+        const float d = p ? e[at] + alpha * p[at] : e[at];
+        v[((size_t)k * L.ny + j) * L.nx + i] += (double)d;
     }
 }
 
-hipError_t launch_add_scaled32_nat(const LevelView& L, double* v, const float* e32, const double* scal, int i_norm2,
-                                   hipStream_t s)
+hipError_t launch_add32_nat(const LevelView& L, double* v, const float* e32, const float* p32, const double* scal,
+                            int i_num, int i_den, hipStream_t s)
 {
-    PT_LAUNCH(k_add_scaled32_nat, L, s, v, e32, scal, i_norm2);
+    PT_LAUNCH(k_add32_nat, L, s, v, e32, p32, scal, i_num, i_den);
     return hipGetLastError();
 }
 
@@ -948,14 +1003,21 @@ hipError_t launch_fill_zero(T* a, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_inject_nan(double* r, size_t idx)
+template <typename T>
+__global__ void k_inject_nan(T* r, size_t idx)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) r[idx] = __builtin_nan("");
+    if (threadIdx.x == 0 && blockIdx.x == 0) r[idx] = (T)__builtin_nan("");
 }
 
 hipError_t launch_inject_nan(double* r, size_t idx, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_inject_nan, dim3(1), dim3(64), 0, s, r, idx);
+    hipLaunchKernelGGL(k_inject_nan<double>, dim3(1), dim3(64), 0, s, r, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject_nan(float* r, size_t idx, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_inject_nan<float>, dim3(1), dim3(64), 0, s, r, idx);
     return hipGetLastError();
 }
 
@@ -1635,7 +1697,7 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
     template hipError_t launch_update_p<T>(const LevelView&, const T*, const T*, T*, const double*, int, int, int,  \
                                            hipStream_t);                                                          \
     template hipError_t launch_update_xr<T>(const LevelView&, T*, T*, const T*, const T*, const double*, int, int, \
-                                            double*, hipStream_t, int*);                                          \
+                                            double*, hipStream_t, int*, int);                                     \
     template int flat_blocks<T>(const LevelView&);                                                                \
     template hipError_t launch_fill_zero<T>(T*, size_t, hipStream_t);
 INST(double)

@@ -162,26 +162,28 @@ static lasto_status read_scalars(lasto_grid g, int first, int n)
     return LASTO_OK;
 }
 
-// Inner FP32 multigrid on A e = r32 (the scaled residual): `cycles` V-cycles
-// in z32, the first from e = 0, each later one continuing from the current e
-// (a stationary iteration needs no residual of its own: the cycle computes
-// it after its pre-smoothing).
-static lasto_status mg32_inner(lasto_grid g, const lasto_solve_opts& o, int cycles, int* vcycles)
+// Inner FP32 multigrid on A e = r32 (the FP64 residual rounded to FP32):
+// `cycles` V-cycles in z32, the first from e = 0, each later one continuing
+// from the current e (a stationary iteration needs no residual of its own:
+// the cycle computes it after its pre-smoothing); then v += e.
+static lasto_status mg32_inner(lasto_grid g, const lasto_solve_opts& o, int cycles, int* vcycles, double* v)
 {
     for (int c = 0; c < cycles; ++c) {
         lasto_status st = vcycle_level<float>(g, 0, o.nu1, o.nu2, g->r32, g->z32, nullptr, nullptr, c == 0);
         if (st != LASTO_OK) return st;
         ++*vcycles;
     }
+    HIPCHK(launch_add32_nat(g->lev[0].view, v, g->z32, nullptr, g->scalars, 0, 0, g->stream));
     return LASTO_OK;
 }
 
-// Inner FP32 PCG on A e = r32 (the scaled residual) from e = 0, `iters` steps.
-static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int iters, int* vcycles)
+// Inner FP32 PCG on A e = r32 from e = 0, `iters` steps, then v += e. The
+// last step's update goes straight into v (e + alpha p): its residual is not
+// needed, since the refinement recomputes the true one in FP64.
+static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int iters, int* vcycles, double* v)
 {
     const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
-    HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
     float* rr = g->r32;   // working residual, updated in place
     for (int it = 0; it < iters; ++it) {
         int nd = 0;
@@ -196,8 +198,14 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
         int npq = 0;
         if (lasto_status e = apply_dot<float>(g, pn, g->q32, &npq); e != LASTO_OK) return e;
         if (lasto_status e = reduce_to(g, npq, S_PQ32); e != LASTO_OK) return e;
+        if (it + 1 == iters) {
+            if (it == 0) HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
+            HIPCHK(launch_add32_nat(V, v, g->e32, pn, g->scalars, srz, S_PQ32, s));
+            break;
+        }
         int nb_r = 0;
-        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s, &nb_r));
+        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s, &nb_r,
+                                       it == 0));
         if (lasto_status e = reduce_to(g, nb_r, S_RR32); e != LASTO_OK) return e;
     }
     return LASTO_OK;
@@ -300,7 +308,10 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     // reference norm ||b - A v_bc||_W and initial residual r (split)
     HIPCHK(launch_residual_nat(V, v, rho, fourpi, nullptr, g->partials, 1, s));
     if (lasto_status e = reduce_to(g, nb_i, S_R0); e != LASTO_OK) return e;
-    HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
+    // (the mixed form keeps only the FP32 rounding of r, which is all its
+    // inner solve reads)
+    if (o.precision == 1) HIPCHK(launch_residual_nat32(V, v, rho, fourpi, g->r32, g->partials, s));
+    else HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
     if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
     if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
     const double r0sq = g->h_scalars[S_R0];
@@ -329,20 +340,22 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     if (cg) HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
   for (;;) {
     while (rel > target && it < o.max_iters) {
-        if (o.debug_nan_iter == it)
-            HIPCHK(launch_inject_nan(g->r, sidx(V, V.nx / 2, V.ny / 2, V.nz / 2), s));
+        if (o.debug_nan_iter == it) {
+            const size_t at = sidx(V, V.nx / 2, V.ny / 2, V.nz / 2);
+            if (o.precision == 1) HIPCHK(launch_inject_nan(g->r32, at, s));
+            else HIPCHK(launch_inject_nan(g->r, at, s));
+        }
         if (o.precision == 1) {
-            // FP32 inner PCG on the scaled FP64 residual, then v += |r| e
-            HIPCHK(launch_scale_to32(V, g->r, g->r32, g->scalars, S_RR, s));
+            // FP32 inner solve on the FP32 rounding of the FP64 residual (the
+            // equation is linear, so the residual's scale does not matter
+            // while it stays far inside the FP32 range), then v += e in FP64
             const int inner = (inf.refinements == 0 && o.inner_first > 0) ? o.inner_first : o.inner_iters;
             if (o.method == 1) {
-                if (lasto_status e = mg32_inner(g, o, inner, &inf.vcycles); e != LASTO_OK) return e;
-                HIPCHK(launch_add_scaled32_nat(V, v, g->z32, g->scalars, S_RR, s));
+                if (lasto_status e = mg32_inner(g, o, inner, &inf.vcycles, v); e != LASTO_OK) return e;
             } else {
-                if (lasto_status e = pcg32_inner(g, o, inner, &inf.vcycles); e != LASTO_OK) return e;
-                HIPCHK(launch_add_scaled32_nat(V, v, g->e32, g->scalars, S_RR, s));
+                if (lasto_status e = pcg32_inner(g, o, inner, &inf.vcycles, v); e != LASTO_OK) return e;
             }
-            HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
+            HIPCHK(launch_residual_nat32(V, v, rho, fourpi, g->r32, g->partials, s));
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             inf.refinements++;
         } else if (o.method == 1) {
