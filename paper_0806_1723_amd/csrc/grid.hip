@@ -303,6 +303,7 @@ static void free_grid(lasto_grid g)
     (void)hipFree(g->stage);
     (void)hipFree(g->tail_dev);
     (void)hipFree(g->lds_tabs);
+    (void)hipFree(g->lds_plan_dev);
     for (double*& a : g->lscr) {
         (void)hipFree(a);
         a = nullptr;
@@ -398,6 +399,8 @@ static lasto_status build_lds_tail(lasto_grid g)
     P.total = o + P.ntab;
     LASTO_HIP(hipMalloc((void**)&g->lds_tabs, sizeof(float) * tab.size()));
     LASTO_HIP(hipMemcpy(g->lds_tabs, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
+    LASTO_HIP(hipMalloc((void**)&g->lds_plan_dev, sizeof(LdsPlan)));
+    LASTO_HIP(hipMemcpy(g->lds_plan_dev, &P, sizeof(LdsPlan), hipMemcpyHostToDevice));
     return LASTO_OK;
 }
 

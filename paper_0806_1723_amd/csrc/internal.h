@@ -229,6 +229,7 @@ struct lasto_grid_s {
     int tail32_top = -1;                   // first level of the FP32 LDS tail (-1: none)
     lasto::LdsPlan lds_plan{};
     float* lds_tabs = nullptr;             // device copy of the LDS tail's tables
+    lasto::LdsPlan* lds_plan_dev = nullptr;   // device copy of lds_plan
     lasto::TailLevel* tail_dev = nullptr;  // device [nlev]
     // fine-level Krylov vectors (FP64, split layout): residual, preconditioned
     // residual, search direction (ping-pong), A p
@@ -312,7 +313,7 @@ hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweep
 // the FP32 cycle from level P's first with every level in LDS: u, f that
 // level's correction and right-hand side (split), tabs the grid's table run
 hipError_t launch_tail_lds(float* u, const float* f, const float* tabs, int nu1, int nu2, int csweeps, int top_zero,
-                           const LdsPlan& P, hipStream_t s);
+                           const LdsPlan& P, const LdsPlan* P_dev, hipStream_t s);
 int tail_lds_limit();   // bytes of LDS one workgroup may use (0 if unknown)
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s);

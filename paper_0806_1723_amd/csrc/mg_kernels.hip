@@ -180,9 +180,16 @@ __device__ __forceinline__ T prolong_at(const LevelView& C, const T* __restrict_
 // rows share an L2. Ids past the last tile only contribute a zero partial.
 __device__ __forceinline__ int xcd_tile(int id, int per) { return (id & 7) * per + (id >> 3); }
 
-template <typename T> struct Vec2;
-template <> struct Vec2<float> { using type = float2; };
-template <> struct Vec2<double> { using type = double2; };
+// 16 bytes of one colour row: VEC consecutive entries (4 FP32, 2 FP64)
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    static constexpr int N = 4;
+};
+template <> struct Vec16<double> {
+    typedef double V __attribute__((ext_vector_type(2)));
+    static constexpr int N = 2;
+};
 
 template <typename T> __device__ __forceinline__ const T* tab_am(const Axis& a);
 template <typename T> __device__ __forceinline__ const T* tab_ap(const Axis& a);
@@ -208,36 +215,59 @@ __device__ __forceinline__ double recip(double d)
 
 enum HalfMode { HM_GS = 0, HM_RESID = 1, HM_APPLY = 2 };
 
-// Over the nodes of colour c (two neighbouring entries m, m+1 of a colour
-// row per thread, loaded as one 8- or 16-byte vector):
+// Over the nodes of colour c (VEC neighbouring entries m0 .. m0+VEC-1 of a
+// colour row per thread, 16 bytes, loaded as one vector):
 //   HM_GS    out_n = (sum_d am_d u_{n-e_d} + ap_d u_{n+e_d} - bscale f_n) / sum_d (am_d + ap_d)
 //            (the Gauss-Seidel update of a red-black half-sweep; dot += vol f out)
 //   HM_RESID out_n = bscale f_n - (A u)_n
 //   HM_APPLY out_n = (A u)_n                                     (dot += vol u out)
 // The neighbours all have the other colour: entry m of the other colour on
 // planes k-1 and k+1 holds the z neighbours, entries m-1+o and m+o the x
-// neighbours (o = (c+j+k) & 1), rows j-1 and j+1 the y neighbours. A thread
-// marches over a chunk of planes keeping the z neighbours in a register queue
-// and loading plane k+1's operands while it computes plane k. `uo` (other
-// colour), `fc`, `ucen` and `out` (this colour) are distinct arrays, so the
-// loads may run ahead of the stores.
-constexpr int H2_X = 64, H2_Y = 4, H2_NT = H2_X * H2_Y, H2_KC_MAX = 16, H2_BLOCKS = 2048;
+// neighbours (o = (c+j+k) & 1), rows j-1 and j+1 the y neighbours; the x
+// neighbours of a group are its own vector of the other colour plus one
+// entry past its left (o = 0) or right (o = 1) end. A thread marches over a
+// chunk of planes keeping the z neighbours in a register queue and loading
+// plane k+1's operands while it computes plane k. `uo` (other colour), `fc`,
+// `ucen` and `out` (this colour) are distinct arrays, so the loads may run
+// ahead of the stores. A workgroup is 32 groups (a 512-byte run of a row)
+// by 8 rows.
+constexpr int H2_X = 32, H2_Y = 8, H2_NT = H2_X * H2_Y, H2_KC_MAX = 16, H2_BLOCKS = 2048;
 
 struct HalfShape {
     int nbx, nby, nbz, nb, per, grid, kc;
 };
 
-// Planes per thread: as many as keep about H2_BLOCKS workgroups (the march
-// saves re-reads, but its planes form a serial chain, so small levels march
-// one plane per thread).
-static HalfShape half_shape(const LevelView& L)
+// Planes per thread (kc): the march saves re-reads, but a workgroup's
+// planes form a serial chain and its first planes are start-up, so the
+// cost of a launch is about rounds x (kc + 2), rounds being how many tiles
+// the busiest of the cap resident workgroups takes. kc minimises that (the
+// smaller on a tie).
+static int chunk_planes(long tiles, int planes, int cap, int kmax)
+{
+    int best = 1;
+    long best_cost = -1;
+    for (int k = 1; k <= kmax; ++k) {
+        const long nb = tiles * ((planes + k - 1) / k);
+        const long rounds = (nb + cap - 1) / cap;
+        const long cost = rounds * (k + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = k;
+        }
+    }
+    return best;
+}
+
+static HalfShape half_shape(const LevelView& L, int vec, int cap = H2_BLOCKS)
 {
     HalfShape h;
-    const int npairs = ((L.nx - 2) / 2) / 2 + 1;   // pairs (m, m+1), m even, m <= (nx-2)/2
-    h.nbx = (npairs + H2_X - 1) / H2_X;
+    // groups of VEC entries m0 = VEC g with m0 <= (nx-2)/2 (the last entry
+    // that can hold an interior node)
+    const int ngroups = ((L.nx - 2) / 2) / vec + 1;
+    h.nbx = (ngroups + H2_X - 1) / H2_X;
     h.nby = (L.ny - 2 + H2_Y - 1) / H2_Y;
     const long tiles = (long)h.nbx * h.nby;
-    h.kc = (int)std::min<long>(H2_KC_MAX, std::max<long>(1, (long)(L.nz - 2) * tiles / H2_BLOCKS));
+    h.kc = chunk_planes(tiles, L.nz - 2, std::max(cap, 8), H2_KC_MAX);
     h.nbz = (L.nz - 2 + h.kc - 1) / h.kc;
     h.nb = h.nbx * h.nby * h.nbz;
     h.per = (h.nb + 7) / 8;
@@ -245,11 +275,11 @@ static HalfShape half_shape(const LevelView& L)
     return h;
 }
 
-int half_blocks(const LevelView& L) { return half_shape(L).grid; }
+int half_blocks(const LevelView& L) { return half_shape(L, 2).grid; }
 
 template <typename T> struct HalfOps {
-    typename Vec2<T>::type ym, yp, fv, cv;   // y neighbours, f and centre of a pair
-    T xe;                                    // the x neighbour outside the z queue
+    typename Vec16<T>::V ym, yp, fv, cv;   // y neighbours, f and centre of a group
+    T xe;                                  // the x neighbour outside the z queue
 };
 
 // TOP marks finest-level launches; it changes no code, only the kernel's name,
@@ -259,7 +289,8 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                                                  const T* __restrict__ ucen, T* __restrict__ out, int c, T bscale,
                                                  double* __restrict__ dotp, int nbx, int nby, int nb, int per, int kc)
 {
-    using V2 = typename Vec2<T>::type;
+    typedef typename Vec16<T>::V VT;
+    constexpr int VEC = Vec16<T>::N;
     __shared__ double red[H2_NT / 64];
     constexpr bool NEED_U = !ZERO_IN || MODE != HM_GS;
     double dot = 0.0;
@@ -273,114 +304,111 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
     // XCD it runs on).
     for (int id = blockIdx.x; id < 8 * per; id += gridDim.x) {
         const int t = xcd_tile(id, per);
-        const int m = 2 * ((t % nbx) * H2_X + (threadIdx.x & (H2_X - 1)));
-        const int j = 1 + ((t / nbx) % nby) * H2_Y + (threadIdx.x >> 6);
-        if (!(t < nb && j <= L.ny - 2 && m <= (nx - 2) / 2)) continue;
+        const int m0 = VEC * ((t % nbx) * H2_X + (threadIdx.x & (H2_X - 1)));
+        const int j = 1 + ((t / nbx) % nby) * H2_Y + (threadIdx.x / H2_X);
+        if (!(t < nb && j <= L.ny - 2 && m0 <= (nx - 2) / 2)) continue;
         const int k0 = 1 + (t / (nbx * nby)) * kc;
         const int k1 = min(k0 + kc, nz - 1);
-        const size_t row = (size_t)j * W + m;
+        const size_t row = (size_t)j * W + m0;
         // both parities' x coefficients, picked per plane by select (named
         // values, not an array indexed at run time, so they stay in registers)
-        const V2 axm0 = *(const V2*)(xp + (size_t)0 * W + m), axm1 = *(const V2*)(xp + (size_t)3 * W + m);
-        const V2 axp0 = *(const V2*)(xp + (size_t)1 * W + m), axp1 = *(const V2*)(xp + (size_t)4 * W + m);
-        V2 axv0{}, axv1{};
+        const VT axm0 = *(const VT*)(xp + (size_t)0 * W + m0), axm1 = *(const VT*)(xp + (size_t)3 * W + m0);
+        const VT axp0 = *(const VT*)(xp + (size_t)1 * W + m0), axp1 = *(const VT*)(xp + (size_t)4 * W + m0);
+        VT axv0 = VT(T(0)), axv1 = VT(T(0));
         if (DOT) {
-            axv0 = *(const V2*)(xp + (size_t)2 * W + m);
-            axv1 = *(const V2*)(xp + (size_t)5 * W + m);
+            axv0 = *(const VT*)(xp + (size_t)2 * W + m0);
+            axv1 = *(const VT*)(xp + (size_t)5 * W + m0);
         }
         const T cym = tab_am<T>(L.ax[1])[j], cyp = tab_ap<T>(L.ax[1])[j];
         const double vy = DOT ? L.ax[1].m[j] : 0.0;
-        // the x neighbour not in the z queue: entry m+2 (o = 1) or m-1 (o = 0; m = 0 has no interior node)
-        const int xoff1 = 2, xoff0 = m > 0 ? -1 : 0;
+        // the x neighbour not in the z queue: entry m0+VEC (o = 1) or m0-1
+        // (o = 0; m0 = 0 has no interior node there)
+        const int xoff1 = VEC, xoff0 = m0 > 0 ? -1 : 0;
         auto load_plane = [&](int k, HalfOps<T>& q) {
             const size_t at = (size_t)k * plane + row;
             const int o = (c + j + k) & 1;
-            if (MODE != HM_APPLY) q.fv = *(const V2*)(fc + at);
-            if (MODE != HM_GS) q.cv = *(const V2*)(ucen + at);
+            if (MODE != HM_APPLY) q.fv = *(const VT*)(fc + at);
+            if (MODE != HM_GS) q.cv = *(const VT*)(ucen + at);
             if (NEED_U) {
-                q.ym = *(const V2*)(uo + at - W);
-                q.yp = *(const V2*)(uo + at + W);
+                q.ym = *(const VT*)(uo + at - W);
+                q.yp = *(const VT*)(uo + at + W);
                 q.xe = uo[at + (o ? xoff1 : xoff0)];
             }
         };
-        auto load_z = [&](int k) -> V2 {
-            V2 z{};
-            if (NEED_U) z = *(const V2*)(uo + (size_t)k * plane + row);
+        auto load_z = [&](int k) -> VT {
+            VT z = VT(T(0));
+            if (NEED_U) z = *(const VT*)(uo + (size_t)k * plane + row);
             return z;
         };
         // plane k from its operands and the z neighbours (zm, zc, zp)
-        auto compute = [&](int k, const HalfOps<T>& q, const V2& zm, const V2& zc, const V2& zp) {
+        auto compute = [&](int k, const HalfOps<T>& q, const VT& zm, const VT& zc, const VT& zp) {
             const int o = (c + j + k) & 1;
-            const int i0 = o + 2 * m;
+            const int i0 = o + 2 * m0;
             const bool okz = L.zint[k];   // planes next to another copy of a batch are faces
-            const bool ok0 = okz && i0 >= 1 && i0 <= nx - 2;
-            const bool ok1 = okz && i0 + 2 <= nx - 2;
-            const V2 cxm = o ? axm1 : axm0, cxp = o ? axp1 : axp0;
+            const VT cxm = o ? axm1 : axm0, cxp = o ? axp1 : axp0;
             const T czm = amz[k], czp = apz[k];
-            // x neighbours of the pair: o = 1: (zc.x, zc.y), (zc.y, xe); o = 0: (xe, zc.x), (zc.x, zc.y)
-            const T xl0 = o ? zc.x : q.xe, xr0 = o ? zc.y : zc.x;
-            const T xl1 = o ? zc.y : zc.x, xr1 = o ? q.xe : zc.y;
-            T r0, r1;
-            if (MODE == HM_GS) {
-                const T cyz = cym + cyp + czm + czp;
-                const T d0 = cxm.x + cxp.x + cyz, d1 = cxm.y + cxp.y + cyz;
-                T s0 = T(0), s1 = T(0);
-                if (NEED_U) {
-                    s0 = cxm.x * xl0 + cxp.x * xr0;
-                    s1 = cxm.y * xl1 + cxp.y * xr1;
-                    s0 += cym * q.ym.x + cyp * q.yp.x;
-                    s1 += cym * q.ym.y + cyp * q.yp.y;
-                    s0 += czm * zm.x + czp * zp.x;
-                    s1 += czm * zm.y + czp * zp.y;
+            VT r;
+            bool ok[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                ok[e] = okz && i0 + 2 * e >= 1 && i0 + 2 * e <= nx - 2;
+                // x neighbours of entry e: o = 1: (zc[e], zc[e+1] or xe); o = 0: (zc[e-1] or xe, zc[e])
+                const T xl = o ? zc[e] : (e > 0 ? zc[e > 0 ? e - 1 : 0] : q.xe);
+                const T xr = o ? (e + 1 < VEC ? zc[e + 1 < VEC ? e + 1 : e] : q.xe) : zc[e];
+                if (MODE == HM_GS) {
+                    const T d = cxm[e] + cxp[e] + cym + cyp + czm + czp;
+                    T sum = T(0);
+                    if (NEED_U) {
+                        sum = cxm[e] * xl + cxp[e] * xr;
+                        sum += cym * q.ym[e] + cyp * q.yp[e];
+                        sum += czm * zm[e] + czp * zp[e];
+                    }
+                    r[e] = (sum - bscale * q.fv[e]) * recip(d);
+                } else {
+                    // (A u) in difference form, which keeps FP32 free of cancellation
+                    const T c0 = q.cv[e];
+                    T a = cxm[e] * (xl - c0) + cxp[e] * (xr - c0);
+                    a += cym * (q.ym[e] - c0) + cyp * (q.yp[e] - c0);
+                    a += czm * (zm[e] - c0) + czp * (zp[e] - c0);
+                    r[e] = MODE == HM_RESID ? bscale * q.fv[e] - a : a;
                 }
-                r0 = (s0 - bscale * q.fv.x) * recip(d0);
-                r1 = (s1 - bscale * q.fv.y) * recip(d1);
-            } else {
-                // (A u) in difference form, which keeps FP32 free of cancellation
-                const T c0 = q.cv.x, c1 = q.cv.y;
-                T a0 = cxm.x * (xl0 - c0) + cxp.x * (xr0 - c0);
-                T a1 = cxm.y * (xl1 - c1) + cxp.y * (xr1 - c1);
-                a0 += cym * (q.ym.x - c0) + cyp * (q.yp.x - c0);
-                a1 += cym * (q.ym.y - c1) + cyp * (q.yp.y - c1);
-                a0 += czm * (zm.x - c0) + czp * (zp.x - c0);
-                a1 += czm * (zm.y - c1) + czp * (zp.y - c1);
-                r0 = MODE == HM_RESID ? bscale * q.fv.x - a0 : a0;
-                r1 = MODE == HM_RESID ? bscale * q.fv.y - a1 : a1;
             }
             const size_t at = (size_t)k * plane + row;
             if (ZERO_FACES) {
                 // face and padding entries of this array are zero: store the
-                // pair unconditionally, with zero where a node is not interior
-                V2 w;
-                w.x = ok0 ? r0 : T(0);
-                w.y = ok1 ? r1 : T(0);
-                *(V2*)(out + at) = w;
+                // group unconditionally, with zero where a node is not interior
+                VT w;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) w[e] = ok[e] ? r[e] : T(0);
+                *(VT*)(out + at) = w;
             } else {
-                if (ok0) out[at] = r0;
-                if (ok1) out[at + 1] = r1;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    if (ok[e]) out[at + e] = r[e];
             }
             if (DOT) {
                 const double vz = okz ? vy * L.ax[2].m[k] : 0.0;
-                const T a0 = MODE == HM_APPLY ? q.cv.x : q.fv.x;
-                const T a1 = MODE == HM_APPLY ? q.cv.y : q.fv.y;
-                const V2 av = o ? axv1 : axv0;   // zero off the interior
-                dot += (double)av.x * vz * (double)a0 * (double)r0;
-                dot += (double)av.y * vz * (double)a1 * (double)r1;
+                const VT av = o ? axv1 : axv0;   // zero off the interior
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const T a = MODE == HM_APPLY ? q.cv[e] : q.fv[e];
+                    dot += (double)av[e] * vz * (double)a * (double)(ok[e] ? r[e] : T(0));
+                }
             }
         };
         // two planes per step with alternating operand sets (A: even steps,
         // B: odd), so the next plane's loads are in flight while one plane is
         // computed and no register copies wait on them
         HalfOps<T> A{}, B{};
-        V2 z0 = load_z(k0 - 1), z1 = load_z(k0), z2 = load_z(k0 + 1);
+        VT z0 = load_z(k0 - 1), z1 = load_z(k0), z2 = load_z(k0 + 1);
         load_plane(k0, A);
         for (int k = k0; k < k1; k += 2) {
             load_plane(min(k + 1, k1 - 1), B);
-            const V2 z3 = load_z(min(k + 2, nz - 1));
+            const VT z3 = load_z(min(k + 2, nz - 1));
             compute(k, A, z0, z1, z2);
             if (k + 1 < k1) {
                 load_plane(min(k + 2, k1 - 1), A);
-                const V2 z4 = load_z(min(k + 3, nz - 1));
+                const VT z4 = load_z(min(k + 3, nz - 1));
                 compute(k + 1, B, z1, z2, z3);
                 z0 = z2;
                 z1 = z3;
@@ -419,8 +447,9 @@ static hipError_t launch_half2(const LevelView& L, const T* u, const T* f, T* ou
                                double* dotp, hipStream_t s, int* nparts, hipEvent_t ev0 = nullptr,
                                hipEvent_t ev1 = nullptr)
 {
-    const HalfShape h = half_shape(L);
-    const int G = std::min(h.grid, half_cap<T, MODE, ZERO_IN, DOT, ZERO_FACES, TOP>());
+    const int cap = half_cap<T, MODE, ZERO_IN, DOT, ZERO_FACES, TOP>();
+    const HalfShape h = half_shape(L, Vec16<T>::N, cap);
+    const int G = std::min(h.grid, cap);
     const size_t own = (size_t)colour * L.cs, other = (size_t)(1 - colour) * L.cs;
     const T* fo = f ? f + own : (const T*)nullptr;
     if (ev0 && ev1)
@@ -503,9 +532,36 @@ static PtShape pt_shape(const LevelView& L)
     return p;
 }
 
+// Resident workgroups of 256 threads on the device when each takes at most
+// 64 VGPRs (eight per compute unit), at least 8
+static int resident_256()
+{
+    static const int cap = [] {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 8;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 8;
+        return std::max(8, 8 * cus);
+    }();
+    return cap;
+}
+
+static int chunk_planes(long tiles, int planes, int cap, int kmax);
+
+// The residual kernels march up their planes (z-queue, one plane of loads
+// ahead): their chunk follows the same cost model as the half-sweeps.
+static PtShape residual_shape(const LevelView& L)
+{
+    PtShape p;
+    const int gx = (L.nx - 2 + PT_X - 1) / PT_X, gy = (L.ny - 2 + PT_Y - 1) / PT_Y;
+    p.kp = chunk_planes((long)gx * gy, L.nz - 2, resident_256(), PT_KP_MAX);
+    p.grid = dim3(gx, gy, (L.nz - 2 + p.kp - 1) / p.kp);
+    return p;
+}
+
+// partials of a residual norm (one per workgroup of residual_shape)
 int interior_blocks(const LevelView& L)
 {
-    const dim3 g = pt_shape(L).grid;
+    const dim3 g = residual_shape(L).grid;
     return (int)(g.x * g.y * g.z);
 }
 
@@ -524,51 +580,14 @@ int interior_blocks(const LevelView& L)
         hipLaunchKernelGGL(kernel, ps_.grid, dim3(PT_NT), 0, s, L, ps_.kp, __VA_ARGS__);      \
     } while (0)
 
-// Fine level, natural v and rho: r = bscale rho - A v (r in the split layout
-// when given) and partials of ||r||_W^2. interior_zero: the interior of v is
-// read as zero (the reference residual of the face data alone).
-__global__ __launch_bounds__(PT_NT) void k_residual_nat(LevelView L, int kp, const double* __restrict__ v,
-                                                        const double* __restrict__ rho, double bscale,
-                                                        double* __restrict__ r, double* __restrict__ part,
-                                                        int interior_zero)
-{
-    __shared__ double red[PT_NT / 64];
-    double acc = 0.0;
-    INTERIOR_LOOP
-    {
-        if (!inside || !L.zint[k]) continue;
-        const int nx = L.nx, ny = L.ny;
-        const size_t sxy = (size_t)nx * ny;
-        const size_t idx = (size_t)k * sxy + (size_t)j * nx + i;
-        double a;
-        if (!interior_zero) {
-            const double c = v[idx];
-            a = L.ax[0].am[i] * (v[idx - 1] - c) + L.ax[0].ap[i] * (v[idx + 1] - c);
-            a += L.ax[1].am[j] * (v[idx - nx] - c) + L.ax[1].ap[j] * (v[idx + nx] - c);
-            a += L.ax[2].am[k] * (v[idx - sxy] - c) + L.ax[2].ap[k] * (v[idx + sxy] - c);
-        } else {
-            a = 0.0;
-            if (i == 1) a += L.ax[0].am[i] * v[idx - 1];
-            if (i == nx - 2) a += L.ax[0].ap[i] * v[idx + 1];
-            if (j == 1) a += L.ax[1].am[j] * v[idx - nx];
-            if (j == ny - 2) a += L.ax[1].ap[j] * v[idx + nx];
-            if (!L.zint[k - 1]) a += L.ax[2].am[k] * v[idx - sxy];
-            if (!L.zint[k + 1]) a += L.ax[2].ap[k] * v[idx + sxy];
-        }
-        const double res = bscale * rho[idx] - a;
-        if (r) r[sidx(L, i, j, k)] = res;
-        acc += vol_at(L, i, j, k) * res * res;
-    }
-    const double t = block_sum<PT_NT>(acc, red);
-    if (threadIdx.x == 0) part[block_linear()] = t;
-}
-
-// The same residual of the iterate itself (interior read), marching each
-// thread's (i, j) column up its chunk of planes: the centre values of planes
-// k-1, k, k+1 stay in registers, and plane k+1's x and y neighbours and rho
-// are loaded before plane k is computed, so two planes' loads are in flight.
-// r (split, FP64 or FP32; optional) and partials of ||r||_W^2.
-template <typename TO>
+// Fine level, natural v and rho: r = bscale rho - A v (r in the split
+// layout, FP64 or FP32, when given) and partials of ||r||_W^2. IZ: the
+// interior of v is read as zero (the reference residual of the face data
+// alone). Each thread marches its (i, j) column up its chunk of planes: the
+// centre values of planes k-1, k, k+1 stay in registers, and plane k+1's x
+// and y neighbours and rho are loaded before plane k is computed, so two
+// planes' loads are in flight.
+template <typename TO, bool IZ>
 __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, const double* __restrict__ v,
                                                           const double* __restrict__ rho, double bscale,
                                                           TO* __restrict__ r, double* __restrict__ part)
@@ -605,9 +624,17 @@ __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, c
             Ops B = A;
             if (k + 1 < ke) B = load(k + 1);
             if (L.zint[k]) {
-                double a = cxm * (A.xm - zc) + cxp * (A.xp - zc);
-                a += cym * (A.ym - zc) + cyp * (A.yp - zc);
-                a += L.ax[2].am[k] * (zm - zc) + L.ax[2].ap[k] * (zp - zc);
+                double a;
+                if (IZ) {
+                    // only neighbours on a face (of this copy) keep their values
+                    a = (i == 1 ? cxm * A.xm : 0.0) + (i == nx - 2 ? cxp * A.xp : 0.0);
+                    a += (j == 1 ? cym * A.ym : 0.0) + (j == L.ny - 2 ? cyp * A.yp : 0.0);
+                    a += (!L.zint[k - 1] ? L.ax[2].am[k] * zm : 0.0) + (!L.zint[k + 1] ? L.ax[2].ap[k] * zp : 0.0);
+                } else {
+                    a = cxm * (A.xm - zc) + cxp * (A.xp - zc);
+                    a += cym * (A.ym - zc) + cyp * (A.yp - zc);
+                    a += L.ax[2].am[k] * (zm - zc) + L.ax[2].ap[k] * (zp - zc);
+                }
                 const double res = bscale * A.b - a;
                 if (r) r[sidx(L, i, j, k)] = (TO)res;
                 acc += vxy * L.ax[2].m[k] * res * res;
@@ -624,15 +651,22 @@ __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, c
 hipError_t launch_residual_nat(const LevelView& L, const double* v, const double* rho, double bscale, double* r_split,
                                double* partials, int interior_zero, hipStream_t s)
 {
-    if (interior_zero) PT_LAUNCH(k_residual_nat, L, s, v, rho, bscale, r_split, partials, interior_zero);
-    else PT_LAUNCH(k_residual_march<double>, L, s, v, rho, bscale, r_split, partials);
+    const PtShape ps = residual_shape(L);
+    if (interior_zero)
+        hipLaunchKernelGGL((k_residual_march<double, true>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale,
+                           r_split, partials);
+    else
+        hipLaunchKernelGGL((k_residual_march<double, false>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale,
+                           r_split, partials);
     return hipGetLastError();
 }
 
 hipError_t launch_residual_nat32(const LevelView& L, const double* v, const double* rho, double bscale, float* r32,
                                  double* partials, hipStream_t s)
 {
-    PT_LAUNCH(k_residual_march<float>, L, s, v, rho, bscale, r32, partials);
+    const PtShape ps = residual_shape(L);
+    hipLaunchKernelGGL((k_residual_march<float, false>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale, r32,
+                       partials);
     return hipGetLastError();
 }
 
@@ -733,15 +767,6 @@ hipError_t launch_dot(const LevelView& L, const T* a, const T* b, double* partia
 // of interior (j, k) are updated whole, as every split kernel treats them;
 // face rows and planes of other copies' faces are left alone. The norm
 // partials use one fixed workgroup count per array size (deterministic).
-template <typename T> struct Vec16;
-template <> struct Vec16<float> {
-    typedef float V __attribute__((ext_vector_type(4)));
-    static constexpr int N = 4;
-};
-template <> struct Vec16<double> {
-    typedef double V __attribute__((ext_vector_type(2)));
-    static constexpr int N = 2;
-};
 
 constexpr int FL_NT = 256, FL_U = 4, FL_MAX_BLOCKS = 2048;
 
@@ -770,11 +795,34 @@ static unsigned flat_vectors(const LevelView& L)
     return (unsigned)(2 * L.cs / Vec16<T>::N);
 }
 
+// Workgroups of a flat launch: as many passes (iters) per thread as the
+// kernel's resident workgroups (cap) need to cover the array, then the
+// fewest workgroups that cover it in that many passes, so every workgroup
+// is resident from the start and all take the same number of passes.
+static int flat_grid(unsigned nvec, int cap)
+{
+    const unsigned per = FL_NT * FL_U;
+    const unsigned c = (unsigned)std::max(1, std::min(cap, FL_MAX_BLOCKS));
+    const unsigned iters = std::max(1u, (nvec + c * per - 1) / (c * per));
+    return (int)std::max(1u, std::min<unsigned>(c, (nvec + per * iters - 1) / (per * iters)));
+}
+
+template <typename KernelPtr>
+static int kernel_cap(KernelPtr k)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 8;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 8;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, FL_NT, 0) != hipSuccess) return 8;
+    return std::max(8, per_cu * cus);
+}
+
+// an upper bound of the partials of any flat launch
 template <typename T>
 int flat_blocks(const LevelView& L)
 {
-    const unsigned per = FL_NT * FL_U;
-    return (int)std::max(1u, std::min<unsigned>(FL_MAX_BLOCKS, (flat_vectors<T>(L) + per - 1) / per));
+    (void)L;
+    return FL_MAX_BLOCKS;
 }
 
 // pnew = z + beta pold, beta = scal[i_num]/scal[i_den] (0 on the first step)
@@ -811,8 +859,9 @@ template <typename T>
 hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pnew, const double* scal, int i_num,
                            int i_den, int first, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update_p<T>, dim3(flat_blocks<T>(L)), dim3(FL_NT), 0, s, L, flat_vectors<T>(L), z, pold,
-                       pnew, scal, i_num, i_den, first);
+    static const int cap = kernel_cap(k_update_p<T>);
+    hipLaunchKernelGGL(k_update_p<T>, dim3(flat_grid(flat_vectors<T>(L), cap)), dim3(FL_NT), 0, s, L,
+                       flat_vectors<T>(L), z, pold, pnew, scal, i_num, i_den, first);
     return hipGetLastError();
 }
 
@@ -882,7 +931,8 @@ template <typename T>
 hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
                             int i_den, double* partials, hipStream_t s, int* nparts, int first)
 {
-    const int nb = flat_blocks<T>(L);
+    static const int cap = kernel_cap(k_update_xr<T>);
+    const int nb = flat_grid(flat_vectors<T>(L), cap);
     hipLaunchKernelGGL(k_update_xr<T>, dim3(nb), dim3(FL_NT), 0, s, L, flat_vectors<T>(L), x, r, p, q, scal, i_num,
                        i_den, partials, first);
     if (nparts) *nparts = nb;
@@ -1408,22 +1458,22 @@ struct LhLevel {
     LdsTab t;
 };
 
-__device__ __forceinline__ LhLevel lh_level(float* lds, const LdsPlan& P, int q)
+__device__ __forceinline__ LhLevel lh_level(float* lds, const LdsPlan* __restrict__ P, int q)
 {
     LhLevel L;
-    L.nx = P.dims[q][0];
-    L.ny = P.dims[q][1];
-    L.nz = P.dims[q][2];
-    L.W = P.dims[q][3];
-    L.cs = P.dims[q][4];
+    L.nx = P->dims[q][0];
+    L.ny = P->dims[q][1];
+    L.nz = P->dims[q][2];
+    L.W = P->dims[q][3];
+    L.cs = P->dims[q][4];
     L.P = L.ny * L.W;
-    const int* fd = q > 0 ? P.dims[q - 1] : P.dims[q];
-    L.t = lds_tab(lds + P.off[q][2], L.nx, L.ny, L.nz, fd[0], fd[1], fd[2], q > 0);
+    const int f = q > 0 ? q - 1 : q;
+    L.t = lds_tab(lds + P->off[q][2], L.nx, L.ny, L.nz, P->dims[f][0], P->dims[f][1], P->dims[f][2], q > 0);
     return L;
 }
 
 // half-sweep of colour c (zero_in: the other colour is read as zero)
-__device__ void lh_half(const LhLevel& L, float* u, const float* f, int c, bool zero_in)
+__device__ __forceinline__ void lh_half(const LhLevel& L, float* u, const float* f, int c, bool zero_in)
 {
     const int mc = (L.nx - 2) / 2 + 1, ry = L.ny - 2;
     const int total = mc * ry * (L.nz - 2);
@@ -1469,7 +1519,7 @@ __device__ __forceinline__ float lh_resid_red(const LhLevel& L, const float* u, 
 
 // fc = R r, r = f - A u of the fine level on its red nodes (black residuals
 // vanish after the black half-sweep that ends the pre-smoothing)
-__device__ void lh_restrict(const LhLevel& F, const float* u, const float* f, const LhLevel& C, float* fcoarse)
+__device__ __forceinline__ void lh_restrict(const LhLevel& F, const float* u, const float* f, const LhLevel& C, float* fcoarse)
 {
     const int rx = C.nx - 2, ry = C.ny - 2;
     const int total = rx * ry * (C.nz - 2);
@@ -1505,7 +1555,7 @@ __device__ void lh_restrict(const LhLevel& F, const float* u, const float* f, co
 }
 
 // u += P e on the fine nodes of colour c (P: trilinear in the coordinates)
-__device__ void lh_prolong(const LhLevel& F, float* u, const LhLevel& C, const float* e, int c)
+__device__ __forceinline__ void lh_prolong(const LhLevel& F, float* u, const LhLevel& C, const float* e, int c)
 {
     const int mc = (F.nx - 2) / 2 + 1, ry = F.ny - 2;
     const int total = mc * ry * (F.nz - 2);
@@ -1542,65 +1592,70 @@ __device__ void lh_prolong(const LhLevel& F, float* u, const LhLevel& C, const f
 
 __global__ __launch_bounds__(TL_NT) void k_tail_lds(float* __restrict__ utop, const float* __restrict__ ftop,
                                                     const float* __restrict__ tabs, int nu1, int nu2, int csweeps,
-                                                    int top_zero, LdsPlan P)
+                                                    int top_zero, const LdsPlan* __restrict__ P)
 {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
-    const int nl = P.nl;
+    const int nl = P->nl;
     // every correction to zero (faces and padding stay zero), the tables in,
     // the top level's right-hand side (and correction) in: 16-byte accesses,
     // four in flight per thread
     for (int q = 0; q < nl; ++q) {
-        float4* u4 = reinterpret_cast<float4*>(lds + P.off[q][0]);
-        const int n4 = P.dims[q][4] / 2;   // 2 cs / 4
+        float4* u4 = reinterpret_cast<float4*>(lds + P->off[q][0]);
+        const int n4 = P->dims[q][4] / 2;   // 2 cs / 4
         for (int e = threadIdx.x; e < n4; e += TL_NT) u4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     {
-        const int n4 = P.dims[0][4] / 2;
+        const int n4 = P->dims[0][4] / 2;
         const float4* f4 = reinterpret_cast<const float4*>(ftop);
         const float4* g4 = reinterpret_cast<const float4*>(utop);
-        float4* lf = reinterpret_cast<float4*>(lds + P.off[0][1]);
-        float4* lu = reinterpret_cast<float4*>(lds + P.off[0][0]);
+        float4* lf = reinterpret_cast<float4*>(lds + P->off[0][1]);
+        float4* lu = reinterpret_cast<float4*>(lds + P->off[0][0]);
         for (int e0 = threadIdx.x; e0 < n4; e0 += 4 * TL_NT) {
-            float4 vf[4], vu[4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int e = e0 + b * TL_NT;
-                if (e < n4) {
-                    vf[b] = f4[e];
-                    if (!top_zero) vu[b] = g4[e];
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int e = e0 + b * TL_NT;
-                if (e < n4) {
-                    lf[e] = vf[b];
-                    if (!top_zero) lu[e] = vu[b];
-                }
+            const int e1 = e0 + TL_NT, e2 = e0 + 2 * TL_NT, e3 = e0 + 3 * TL_NT;
+            const float4 f0 = f4[e0];
+            const float4 f1 = f4[min(e1, n4 - 1)];   // clamped: in bounds, stored only below n4
+            const float4 f2 = f4[min(e2, n4 - 1)];
+            const float4 f3 = f4[min(e3, n4 - 1)];
+            lf[e0] = f0;
+            if (e1 < n4) lf[e1] = f1;
+            if (e2 < n4) lf[e2] = f2;
+            if (e3 < n4) lf[e3] = f3;
+        }
+        if (!top_zero) {
+            for (int e0 = threadIdx.x; e0 < n4; e0 += 4 * TL_NT) {
+                const int e1 = e0 + TL_NT, e2 = e0 + 2 * TL_NT, e3 = e0 + 3 * TL_NT;
+                const float4 a0 = g4[e0];
+                const float4 a1 = g4[min(e1, n4 - 1)];   // clamped: in bounds, stored only below n4
+                const float4 a2 = g4[min(e2, n4 - 1)];
+                const float4 a3 = g4[min(e3, n4 - 1)];
+                lu[e0] = a0;
+                if (e1 < n4) lu[e1] = a1;
+                if (e2 < n4) lu[e2] = a2;
+                if (e3 < n4) lu[e3] = a3;
             }
         }
-        for (int e = threadIdx.x; e < P.ntab; e += TL_NT) lds[P.tab0 + e] = tabs[e];
+        for (int e = threadIdx.x; e < P->ntab; e += TL_NT) lds[P->tab0 + e] = tabs[e];
     }
     __syncthreads();
     for (int q = 0; q + 1 < nl; ++q) {
         const LhLevel L = lh_level(lds, P, q);
-        float* u = lds + P.off[q][0];
-        const float* f = lds + P.off[q][1];
+        float* u = lds + P->off[q][0];
+        const float* f = lds + P->off[q][1];
         for (int s = 0; s < nu1; ++s) {
             lh_half(L, u, f, 0, s == 0 && (q > 0 || top_zero));
             __syncthreads();
             lh_half(L, u, f, 1, false);
             __syncthreads();
         }
-        lh_restrict(L, u, f, lh_level(lds, P, q + 1), lds + P.off[q + 1][1]);
+        lh_restrict(L, u, f, lh_level(lds, P, q + 1), lds + P->off[q + 1][1]);
         __syncthreads();
     }
     {
         // coarsest: csweeps sweeps (red, black), then csweeps (black, red)
         const LhLevel L = lh_level(lds, P, nl - 1);
-        float* u = lds + P.off[nl - 1][0];
-        const float* f = lds + P.off[nl - 1][1];
+        float* u = lds + P->off[nl - 1][0];
+        const float* f = lds + P->off[nl - 1][1];
         for (int pass = 0; pass < 2 * csweeps; ++pass) {
             for (int h = 0; h < 2; ++h) {
                 const int colour = (pass < csweeps) ? h : 1 - h;
@@ -1611,11 +1666,11 @@ __global__ __launch_bounds__(TL_NT) void k_tail_lds(float* __restrict__ utop, co
     }
     for (int q = nl - 2; q >= 0; --q) {
         const LhLevel L = lh_level(lds, P, q), C = lh_level(lds, P, q + 1);
-        float* u = lds + P.off[q][0];
-        const float* f = lds + P.off[q][1];
+        float* u = lds + P->off[q][0];
+        const float* f = lds + P->off[q][1];
         // only red nodes take the correction when a black half-sweep follows
-        lh_prolong(L, u, C, lds + P.off[q + 1][0], 0);
-        if (nu2 == 0) lh_prolong(L, u, C, lds + P.off[q + 1][0], 1);
+        lh_prolong(L, u, C, lds + P->off[q + 1][0], 0);
+        if (nu2 == 0) lh_prolong(L, u, C, lds + P->off[q + 1][0], 1);
         __syncthreads();
         for (int s = 0; s < nu2; ++s) {
             lh_half(L, u, f, 1, false);
@@ -1625,18 +1680,18 @@ __global__ __launch_bounds__(TL_NT) void k_tail_lds(float* __restrict__ utop, co
         }
     }
     {
-        const int n4 = P.dims[0][4] / 2;
+        const int n4 = P->dims[0][4] / 2;
         float4* g4 = reinterpret_cast<float4*>(utop);
-        const float4* lu = reinterpret_cast<const float4*>(lds + P.off[0][0]);
+        const float4* lu = reinterpret_cast<const float4*>(lds + P->off[0][0]);
         for (int e = threadIdx.x; e < n4; e += TL_NT) g4[e] = lu[e];
     }
 }
 
 hipError_t launch_tail_lds(float* u, const float* f, const float* tabs, int nu1, int nu2, int csweeps, int top_zero,
-                           const LdsPlan& P, hipStream_t s)
+                           const LdsPlan& P, const LdsPlan* P_dev, hipStream_t s)
 {
     hipLaunchKernelGGL(k_tail_lds, dim3(1), dim3(TL_NT), sizeof(float) * (size_t)P.total, s, u, f, tabs, nu1, nu2,
-                       csweeps, top_zero, P);
+                       csweeps, top_zero, P_dev);
     return hipGetLastError();
 }
 

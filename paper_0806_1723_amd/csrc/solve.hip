@@ -82,7 +82,7 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     if (sizeof(T) == 4 && l == g->tail32_top) {
         // the rest of the FP32 cycle in one workgroup, all levels in LDS
         HIPCHK(launch_tail_lds((float*)u, (const float*)f, g->lds_tabs, nu1, nu2, kCoarseSweeps, zero_start ? 1 : 0,
-                               g->lds_plan, s));
+                               g->lds_plan, g->lds_plan_dev, s));
         if (dotp) {
             HIPCHK(launch_dot<T>(V, f, u, dotp, s));
             *ndot = row_blocks(V);
