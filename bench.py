@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # Summary: profiles/k_half2_fp32_finest_257_traffic.md. The figure belongs to
 # the kernel source it was measured on and to the same solve form; `traffic`
 # is reported as null when either differs.
-COUNTER_TRAFFIC = {"kernel_sha256_16": "819d3f239d9dcf0a", "form": (1, 0, 6, 0, 2, 2), "bytes_per_launch": 107.70e6}
+COUNTER_TRAFFIC = {"kernel_sha256_16": "191803d67b975fc8", "form": (1, 0, 6, 5, 2, 2), "bytes_per_launch": 114.85e6}
 
 
 def half_sweep_source_digest():
