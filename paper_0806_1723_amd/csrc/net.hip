@@ -326,7 +326,9 @@ extern "C" lasto_status lasto_net_get_grads(lasto_net n, float* host, long long 
 namespace lasto {
 
 // forward pass on the net's stream; y (device, nvox[0] FP32) receives the output
-lasto_status net_forward_async(lasto_net n, const uint16_t* x, float* y)
+// keep_acts: store every activation the backward pass reads (training);
+// otherwise the last up-sampling and the head are fused (inference)
+lasto_status net_forward_async(lasto_net n, const uint16_t* x, float* y, bool keep_acts)
 {
     const int* c = n->c;
     auto conv = [&](int i, const uint16_t* in, uint16_t* out) -> hipError_t {
@@ -348,6 +350,12 @@ lasto_status net_forward_async(lasto_net n, const uint16_t* x, float* y)
     NCHK(conv(6, n->u[2], n->d[1]));
     NCHK(launch_upsample_add(n->d[1], D[6], D[7], D[8], n->e[1], n->u[1], D[3], D[4], D[5], c[1], n->stream));
     NCHK(conv(7, n->u[1], n->d[0]));
+    if (!keep_acts) {
+        NCHK(launch_upsample_head(n->d[0], D[3], D[4], D[5], n->e[0], D[0], D[1], D[2], c[0], n->w + n->head_off,
+                                  y ? y : n->y, n->stream));
+        n->fwd_done = false;
+        return LASTO_OK;
+    }
     NCHK(launch_upsample_add(n->d[0], D[3], D[4], D[5], n->e[0], n->u[0], D[0], D[1], D[2], c[0], n->stream));
     NCHK(launch_head(n->u[0], n->nvox[0], c[0], n->w + n->head_off, y ? y : n->y, n->stream));
     n->fwd_done = true;
@@ -360,23 +368,23 @@ lasto_status net_forward_async(lasto_net n, const uint16_t* x, float* y)
 //   1..3: log(m_d / h_ref), m_d the dual width along axis d
 //   4: v * pot_scale (an initial guess inside, the Dirichlet data on faces)
 //   5: 1 on faces, 0 inside;  6, 7: 0
-__global__ void k_features(LevelView L, const double* __restrict__ rho, const double* __restrict__ v, double s_rho,
-                           double s_pot, double h_ref, uint16_t* __restrict__ x)
+__global__ __launch_bounds__(128) void k_features(LevelView L, const double* __restrict__ rho,
+                                                  const double* __restrict__ v, double s_rho, double s_pot,
+                                                  float h_ref, uint16_t* __restrict__ x)
 {
-    const long n = (long)L.nx * L.ny * L.nz;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        const int i = (int)(e % L.nx), j = (int)((e / L.nx) % L.ny), k = (int)(e / ((long)L.nx * L.ny));
-        const bool face = i == 0 || j == 0 || k == 0 || i == L.nx - 1 || j == L.ny - 1 || k == L.nz - 1;
-        uint16_t* o = x + (size_t)e * 8;
-        o[0] = f2bf((float)(rho[e] * s_rho));
-        o[1] = f2bf((float)log(L.ax[0].m[i] / h_ref));
-        o[2] = f2bf((float)log(L.ax[1].m[j] / h_ref));
-        o[3] = f2bf((float)log(L.ax[2].m[k] / h_ref));
-        o[4] = f2bf((float)(v[e] * s_pot));
-        o[5] = f2bf(face ? 1.0f : 0.0f);
-        o[6] = 0;
-        o[7] = 0;
-    }
+    const int i = blockIdx.x * 128 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i >= L.nx) return;
+    const size_t e = ((size_t)k * L.ny + j) * L.nx + i;
+    const bool face = i == 0 || j == 0 || k == 0 || i == L.nx - 1 || j == L.ny - 1 || k == L.nz - 1;
+    // the width channels are rounded to BF16 (8 significant bits), so FP32
+    // logarithms carry more than enough precision
+    const float inv = 1.0f / h_ref;
+    uint4 o;
+    o.x = (uint32_t)f2bf((float)(rho[e] * s_rho)) | ((uint32_t)f2bf(logf((float)L.ax[0].m[i] * inv)) << 16);
+    o.y = (uint32_t)f2bf(logf((float)L.ax[1].m[j] * inv)) | ((uint32_t)f2bf(logf((float)L.ax[2].m[k] * inv)) << 16);
+    o.z = (uint32_t)f2bf((float)(v[e] * s_pot)) | ((uint32_t)f2bf(face ? 1.0f : 0.0f) << 16);
+    o.w = 0;
+    *(uint4*)(x + e * 8) = o;
 }
 
 lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x,
@@ -385,9 +393,8 @@ lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, co
     const LevelView& L = g->lev[0].view;
     if (L.nx != n->dim[0][0] || L.ny != n->dim[0][1] || L.nz != n->dim[0][2])
         return fail(LASTO_ERR_ARG, "lasto_net: the net's grid does not match the grid's finest level");
-    const long nv = (long)L.nx * L.ny * L.nz;
-    hipLaunchKernelGGL(k_features, dim3((unsigned)std::min<long>((nv + 255) / 256, 16384)), dim3(256), 0, g->stream, L,
-                       rho, v, n->cfg.rho_scale * rho_mul, n->cfg.pot_scale, n->cfg.h_ref, x);
+    hipLaunchKernelGGL(k_features, dim3((L.nx + 127) / 128, L.ny, L.nz), dim3(128), 0, g->stream, L, rho, v,
+                       n->cfg.rho_scale * rho_mul, n->cfg.pot_scale, (float)n->cfg.h_ref, x);
     NCHK(hipGetLastError());
     return LASTO_OK;
 }
@@ -404,7 +411,7 @@ lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, con
     if (lasto_status st = net_features_async(g, n, rho, v, n->xin, rho_mul); st != LASTO_OK) return st;
     hipStream_t keep = n->stream;
     n->stream = g->stream;
-    lasto_status st = net_forward_async(n, n->xin, n->y);
+    lasto_status st = net_forward_async(n, n->xin, n->y, false);
     n->stream = keep;
     if (st != LASTO_OK) return st;
     *y = n->y;
@@ -425,7 +432,7 @@ extern "C" lasto_status lasto_net_features(lasto_grid g, lasto_net n, const doub
 extern "C" lasto_status lasto_net_forward(lasto_net n, const uint16_t* x, float* y)
 {
     if (!n || !x || !y) return net_fail(LASTO_ERR_ARG, "lasto_net_forward: NULL argument");
-    lasto_status st = lasto::net_forward_async(n, x, y);
+    lasto_status st = lasto::net_forward_async(n, x, y, true);
     if (st != LASTO_OK) return st;
     NCHK(hipMemcpyAsync(n->y, y, sizeof(float) * n->nvox[0], hipMemcpyDeviceToDevice, n->stream));
     NCHK(hipStreamSynchronize(n->stream));
@@ -524,7 +531,7 @@ extern "C" lasto_status lasto_net_train_step(lasto_net n, const uint16_t* x, con
                                              float lr, double* loss)
 {
     if (!n || !x) return net_fail(LASTO_ERR_ARG, "lasto_net_train_step: NULL argument");
-    lasto_status st = lasto::net_forward_async(n, x, n->y);
+    lasto_status st = lasto::net_forward_async(n, x, n->y, true);
     if (st != LASTO_OK) return st;
     st = lasto_net_backward(n, x, target, weight, loss);
     if (st != LASTO_OK) return st;

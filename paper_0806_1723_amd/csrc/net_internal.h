@@ -57,6 +57,9 @@ hipError_t launch_upsample_add(const uint16_t* coarse, int cx, int cy, int cz, c
                                int nx, int ny, int nz, int c, hipStream_t s);
 hipError_t launch_upsample_adj(const uint16_t* fine, int nx, int ny, int nz, uint16_t* out, int cx, int cy, int cz, int c,
                                const uint16_t* act, hipStream_t s);
+// inference: y = w . BF16(up(coarse) + skip) + b without storing the sum
+hipError_t launch_upsample_head(const uint16_t* coarse, int cx, int cy, int cz, const uint16_t* skip, int nx, int ny,
+                                int nz, int c, const float* w, float* y, hipStream_t s);
 hipError_t launch_head(const uint16_t* a, long nvox, int c, const float* w, float* y, hipStream_t s);
 hipError_t launch_head_loss_bwd(const uint16_t* a, long nvox, int c, const float* w, const float* y, const float* tgt,
                                 const float* wt, uint16_t* da, double* lossp, float* pw, int splits, hipStream_t s);

@@ -164,6 +164,125 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeom g, const uint16_t* __rest
     }
 }
 
+// Stride-1 convolution through LDS: a workgroup owns a 16 (x) x 4 (y) x 4
+// (z) brick of output nodes (wave w: plane z0 + w; its MT = 4 tiles: rows
+// y0 .. y0+3; lane m: x0 + m) and first copies the 18 x 6 x 6 input box
+// with its halo into LDS, 16 bytes (8 channels) per load, zero outside the
+// grid. The A operands then come from LDS; K order, MFMA order and the
+// epilogue are those of k_conv, so the results are the same bit for bit.
+constexpr int CL_BX = 16, CL_BY = 4, CL_BZ = 4;
+constexpr int CL_HX = CL_BX + 2, CL_HY = CL_BY + 2, CL_HZ = CL_BZ + 2;
+constexpr int CL_CMAX = 32;   // input channels the largest box holds
+
+// CM: input channels the box holds (8, 16 or 32: 10, 21 or 41 KB of LDS)
+template <int NT, int CM>
+__global__ __launch_bounds__(256) void k_conv_same_lds(ConvGeom g, const uint16_t* __restrict__ in,
+                                                       const uint16_t* __restrict__ wp, ConvEpilogue ep)
+{
+    constexpr int MT = CL_BY;
+    __shared__ __align__(16) uint16_t box[CL_HZ * CL_HY * CL_HX * CM];
+    const int nbx = (g.nx + CL_BX - 1) / CL_BX, nby = (g.ny + CL_BY - 1) / CL_BY;
+    const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+    const int x0 = bx * CL_BX, y0 = by * CL_BY, z0 = bz * CL_BZ;
+    const int cq = g.cin / 8;   // 16-byte chunks per node
+    {
+        // fill: box node (hx, hy, hz) <- input (x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz)
+        constexpr int B = 8;
+        const int n = CL_HZ * CL_HY * CL_HX * cq;
+        for (int e0 = threadIdx.x; e0 < n; e0 += B * 256) {
+            uint4 v[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int e = e0 + u * 256;
+                const int c = e % cq, node = e / cq;
+                const int hx = node % CL_HX, hy = (node / CL_HX) % CL_HY, hz = node / (CL_HX * CL_HY);
+                const int xi = x0 - 1 + hx, yi = y0 - 1 + hy, zi = z0 - 1 + hz;
+                v[u] = make_uint4(0, 0, 0, 0);
+                if (e < n && xi >= 0 && yi >= 0 && zi >= 0 && xi < g.ix && yi < g.iy && zi < g.iz)
+                    v[u] = *(const uint4*)(in + (((size_t)zi * g.iy + yi) * g.ix + xi) * g.cin + 8 * c);
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int e = e0 + u * 256;
+                if (e < n) *(uint4*)(box + (size_t)e * 8) = v[u];
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int z = z0 + w;
+    const int K = 27 * g.cin;
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int u = 0; u < MT; ++u)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[u][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int t = (8 * kq) / g.cin, ci = 8 * kq - t * g.cin;   // this lane's tap and channel at chunk 0
+    for (int kc = 0; kc < g.kpad; kc += 32) {
+        const int k = kc + 8 * kq;
+        uint4 b[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) b[j] = *(const uint4*)(wp + (size_t)(j * 16 + m) * g.kpad + k);
+        uint4 a[MT];
+        if (k < K) {
+            const Off o = tap_off(t);
+            // box node of output (x0 + m, y0 + u, z) plus the tap offset
+            const int base = ((w + 1 + o.dz) * CL_HY + 1 + o.dy) * CL_HX + m + 1 + o.dx;
+#pragma unroll
+            for (int u = 0; u < MT; ++u) a[u] = *(const uint4*)(box + (size_t)(base + u * CL_HX) * g.cin + ci);
+        } else {
+#pragma unroll
+            for (int u = 0; u < MT; ++u) a[u] = make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < MT; ++u) {
+            const bf16x8 av = as_bf16x8(a[u]);
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf16x8(b[j]), acc[u][j], 0, 0, 0);
+        }
+        ci += 32;
+        while (ci >= g.cin) {
+            ci -= g.cin;
+            ++t;
+        }
+    }
+    if (z >= g.nz) return;
+    // epilogue: C[m' = 4 kq + i][n = lane % 16] of tile (u, j) is node
+    // (x0 + m', y0 + u, z), channel 16 j + n
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = j * 16 + m;
+        const float bias = ep.bias ? ep.bias[co] : 0.f;
+#pragma unroll
+        for (int u = 0; u < MT; ++u) {
+            const int y = y0 + u;
+            if (y >= g.ny) continue;
+            uint16_t add[4] = {0, 0, 0, 0}, msk[4] = {0, 0, 0, 0};
+            const size_t rowv = ((size_t)z * g.ny + y) * g.nx;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = min(x0 + 4 * kq + i, g.nx - 1);
+                if (ep.addend) add[i] = ep.addend[(rowv + x) * g.cout + co];
+                if (ep.mask) msk[i] = ep.mask[(rowv + x) * g.cout + co];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 4 * kq + i;
+                if (x >= g.nx) continue;
+                const size_t at = (rowv + x) * g.cout + co;
+                float val = acc[u][j][i] + bias;
+                if (ep.relu) val = fmaxf(val, 0.f);
+                if (ep.addend) val += bf2f(add[i]);
+                if (ep.mask && !(bf2f(msk[i]) > 0.f)) val = 0.f;
+                if (ep.out_f32) ep.out_f32[at] = val;
+                if (ep.out_bf16) ep.out_bf16[at] = f2bf(val);
+            }
+        }
+    }
+}
+
 template <int MODE>
 static hipError_t launch_conv_mode(const ConvGeom& g, const uint16_t* in, const uint16_t* wp, const ConvEpilogue& ep,
                                    hipStream_t s)
@@ -191,6 +310,24 @@ hipError_t launch_conv(const ConvGeom& g, const uint16_t* in, const uint16_t* wp
                        hipStream_t s)
 {
     if (g.cin % 8 || g.cout % 16 || g.cout > 64 || g.kpad % 32 || g.kpad < 27 * g.cin) return hipErrorInvalidValue;
+    if (g.mode == CONV_SAME && g.cin <= CL_CMAX && g.ix == g.nx && g.iy == g.ny && g.iz == g.nz) {
+        const unsigned nb = (unsigned)(((g.nx + CL_BX - 1) / CL_BX) * ((g.ny + CL_BY - 1) / CL_BY) *
+                                       ((g.nz + CL_BZ - 1) / CL_BZ));
+        const int cm = g.cin <= 8 ? 8 : (g.cin <= 16 ? 16 : 32);
+#define CL_CASE(nt, cmv)                                                                                  \
+    case (nt) * 64 + (cmv):                                                                               \
+        hipLaunchKernelGGL((k_conv_same_lds<nt, cmv>), dim3(nb), dim3(256), 0, s, g, in, wp, ep);       \
+        break;
+        switch ((g.cout / 16) * 64 + cm) {
+            CL_CASE(1, 8) CL_CASE(1, 16) CL_CASE(1, 32)
+            CL_CASE(2, 8) CL_CASE(2, 16) CL_CASE(2, 32)
+            CL_CASE(3, 8) CL_CASE(3, 16) CL_CASE(3, 32)
+            CL_CASE(4, 8) CL_CASE(4, 16) CL_CASE(4, 32)
+            default: return hipErrorInvalidValue;
+        }
+#undef CL_CASE
+        return hipGetLastError();
+    }
     switch (g.mode) {
         case CONV_SAME: return launch_conv_mode<CONV_SAME>(g, in, wp, ep, s);
         case CONV_DOWN: return launch_conv_mode<CONV_DOWN>(g, in, wp, ep, s);
@@ -415,6 +552,54 @@ hipError_t launch_upsample_add(const uint16_t* coarse, int cx, int cy, int cz, c
     const long per_row = (long)((nx + 63) / 64) * 64 * (c / 8);
     const dim3 grid((unsigned)((per_row + 255) / 256), (unsigned)ny, (unsigned)nz);
     hipLaunchKernelGGL(k_upsample_add, grid, dim3(256), 0, s, coarse, cx, cy, cz, skip, out, nx, ny, nz, c);
+    return hipGetLastError();
+}
+
+// The net's last two steps for inference, fused: u0 = BF16(up(coarse) +
+// skip) and y = w . u0 + b at each fine node, without storing u0. The
+// arithmetic (tap order, BF16 rounding of u0, the head's summation order) is
+// that of k_upsample_add followed by k_head, so y is the same bit for bit.
+__global__ __launch_bounds__(256) void k_upsample_head(const uint16_t* __restrict__ coarse, int cx, int cy, int cz,
+                                                       const uint16_t* __restrict__ skip, int nx, int ny, int nz,
+                                                       int c, const float* __restrict__ w, float* __restrict__ y)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, yq = blockIdx.y, z = blockIdx.z;
+    if (x >= nx) return;
+    int xa, xb, ya, yb, za, zb;
+    float wxa, wxb, wya, wyb, wza, wzb;
+    up_taps(x, cx, xa, xb, wxa, wxb);
+    up_taps(yq, cy, ya, yb, wya, wyb);
+    up_taps(z, cz, za, zb, wza, wzb);
+    const int zz[2] = {za, zb}, yy[2] = {ya, yb}, xx[2] = {xa, xb};
+    const float wz[2] = {wza, wzb}, wy[2] = {wya, wyb}, wx[2] = {wxa, wxb};
+    const size_t node = ((size_t)z * ny + yq) * nx + x;
+    float s = w[c];
+    for (int q0 = 0; q0 < c; q0 += 8) {
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int cz2 = 0; cz2 < 2; ++cz2)
+#pragma unroll
+            for (int cy2 = 0; cy2 < 2; ++cy2)
+#pragma unroll
+                for (int cx2 = 0; cx2 < 2; ++cx2) {
+                    const float wt = wz[cz2] * wy[cy2] * wx[cx2];
+                    const uint4 q =
+                        *(const uint4*)(coarse + (((size_t)zz[cz2] * cy + yy[cy2]) * cx + xx[cx2]) * c + q0);
+                    add8(acc, q, wt);
+                }
+        add8(acc, *(const uint4*)(skip + node * c + q0), 1.f);
+#pragma unroll
+        for (int h = 0; h < 8; ++h) s += w[q0 + h] * bf2f(f2bf(acc[h]));
+    }
+    y[node] = s;
+}
+
+hipError_t launch_upsample_head(const uint16_t* coarse, int cx, int cy, int cz, const uint16_t* skip, int nx, int ny,
+                                int nz, int c, const float* w, float* y, hipStream_t s)
+{
+    if (c % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_upsample_head, dim3((unsigned)((nx + 255) / 256), (unsigned)ny, (unsigned)nz), dim3(256), 0,
+                       s, coarse, cx, cy, cz, skip, nx, ny, nz, c, w, y);
     return hipGetLastError();
 }
 

@@ -280,14 +280,22 @@ __global__ __launch_bounds__(256) void k_guess(LevelView L, const AtomDev* __res
             const AtomDev& A = atoms[a];
             const double dx = px - A.c[0], dy = py - A.c[1], dz = pz - A.c[2];
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double r = sqrt(r2);
+            // 1/r from the hardware estimate and two Newton steps (the far
+            // field -q/r of most node-atom pairs needs neither a square root
+            // nor a division)
+            double ri = __builtin_amdgcn_rsq(r2);
+            ri = ri * fma(-0.5 * r2, ri * ri, 1.5);
+            ri = ri * fma(-0.5 * r2, ri * ri, 1.5);
             if (A.kind == 0) {
-                if (r < 6.0 * A.w)
+                const double lim = 6.0 * A.w;
+                if (r2 < lim * lim) {
+                    const double r = sqrt(r2);
                     acc -= r > 1e-12 * A.w ? A.q * erf(r / A.w) / r : 2.0 * A.q / (sqrt(kPi) * A.w);
-                else
-                    acc -= A.q / r;
+                } else {
+                    acc -= A.q * ri;
+                }
             } else {
-                acc -= r < A.R ? A.q * (3.0 * A.R * A.R - r2) / (2.0 * A.R * A.R * A.R) : A.q / r;
+                acc -= r2 < A.R * A.R ? A.q * (3.0 * A.R * A.R - r2) / (2.0 * A.R * A.R * A.R) : A.q * ri;
             }
         }
         v[((size_t)k * ny + j) * nx + i] = acc;

@@ -178,3 +178,44 @@ def test_learned_correction_saves_cycles(torch, L):
         assert corr["cycles"] <= plain["cycles"] - 2
         assert corr["accepted"] >= corr["cycles"] // 2
     net.close()
+
+
+def test_net_features_match_their_definition(torch, L, R):
+    """lasto_net_features: channel 0 rho * rho_scale, 1..3 log(m_d / h_ref)
+    of the dual widths, 4 v * pot_scale, 5 the face flag, 6 and 7 zero, each
+    rounded to BF16 (the width channels within one BF16 step, or 1e-6 where
+    the logarithm is near zero: the kernel takes them in FP32)."""
+    rng = np.random.default_rng(21)
+    xs = [np.concatenate([[0.0], np.cumsum(rng.uniform(0.1, 0.9, n - 1))]) for n in (23, 17, 19)]
+    g = L.Grid(*xs)
+    shape = (19, 17, 23)
+    net = L.Net(shape, ch=(16, 16, 16, 16), seed=5, rho_scale=0.3, pot_scale=0.02, h_ref=0.25)
+    rho_h = rng.normal(size=shape) * 4.0
+    v_h = rng.normal(size=shape) * 50.0
+    rho = torch.from_numpy(rho_h).to("cuda")
+    v = torch.from_numpy(v_h).to("cuda")
+    got = R.bf16_bits_to_float(net.features(g, rho, v).cpu().numpy())
+    m = []
+    for x in xs:
+        d = np.zeros_like(x)
+        d[1:-1] = 0.5 * (x[2:] - x[:-2])
+        d[0] = 0.5 * (x[1] - x[0])
+        d[-1] = 0.5 * (x[-1] - x[-2])
+        m.append(d)
+    Z, Y, X = np.meshgrid(np.arange(shape[0]), np.arange(shape[1]), np.arange(shape[2]), indexing="ij")
+    face = (X == 0) | (Y == 0) | (Z == 0) | (X == shape[2] - 1) | (Y == shape[1] - 1) | (Z == shape[0] - 1)
+    want = np.zeros(shape + (8,))
+    want[..., 0] = rho_h * 0.3
+    want[..., 1] = np.log(m[0][X] / 0.25)
+    want[..., 2] = np.log(m[1][Y] / 0.25)
+    want[..., 3] = np.log(m[2][Z] / 0.25)
+    want[..., 4] = v_h * 0.02
+    want[..., 5] = face.astype(float)
+    exact = R.round_bf16(want)
+    for c in (0, 4, 5, 6, 7):
+        assert np.array_equal(got[..., c], exact[..., c]), c
+    for c in (1, 2, 3):
+        # one BF16 step, or the FP32 rounding of m / h_ref where the log is near 0
+        step = np.abs(exact[..., c]) * 2.0 ** -7 + 1e-6
+        assert (np.abs(got[..., c] - exact[..., c]) <= step).all(), c
+    g.close()

@@ -259,6 +259,44 @@ def test_batched_operator_and_sweep_match_oracle(torch, L, oracle_mod):
     g.close()
 
 
+def test_analytic_guess_matches_closed_form(torch, L):
+    """lasto_analytic_guess: the monopole field of every atom at each
+    interior node (Gaussian: -q erf(r/w)/r, with its r -> 0 limit; quartic:
+    the uniform ball of radius R), faces untouched."""
+    from scipy.special import erf
+    rng = np.random.default_rng(11)
+    xs = [graded(rng, n) for n in (37, 29, 33)]
+    g = L.Grid(*xs)
+    node = np.array([xs[0][18], xs[1][14], xs[2][16]])   # an atom exactly on a node
+    atoms = [I.Atom(center=node, q=9.0, width=0.6),
+             I.Atom(center=np.array([1.3, -2.2, 0.7]), q=10.5, width=0.85),
+             I.Atom(center=np.array([-4.0, 3.1, -1.9]), q=8.0, width=0.5),
+             I.Atom(center=np.array([2.9, 2.4, -3.3]), q=11.0, radius=1.7, kind=1),
+             I.Atom(center=np.array([-2.5, -3.6, 3.8]), q=7.5, radius=2.1, kind=1)]
+    v0 = rng.standard_normal((33, 29, 37))
+    v = to_dev(torch, v0)
+    g.analytic_guess(atoms, v)
+    got = v.cpu().numpy()
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    want = np.zeros_like(v0)
+    for a in atoms:
+        r = np.sqrt((X - a.center[0]) ** 2 + (Y - a.center[1]) ** 2 + (Z - a.center[2]) ** 2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            if a.kind == 0:
+                f = np.where(r > 1e-12 * a.width, erf(r / a.width) / r, 2.0 / (math.sqrt(math.pi) * a.width))
+            else:
+                R = a.radius
+                f = np.where(r < R, (3 * R * R - r * r) / (2 * R ** 3), 1.0 / r)
+        want -= a.q * f
+    faces = np.ones(v0.shape, bool)
+    faces[1:-1, 1:-1, 1:-1] = False
+    assert np.array_equal(got[faces], v0[faces])
+    err = np.abs(got - want)[~faces].max() / np.abs(want[~faces]).max()
+    say("  analytic guess max rel error %.2e" % err)
+    assert err <= 1e-13
+    g.close()
+
+
 def test_levels_match_oracle_hierarchy(torch, L, oracle_mod):
     w = I.config(3)
     xs = oracle_mod.mesh_for(w.axes)
