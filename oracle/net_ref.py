@@ -103,11 +103,14 @@ def up_matrix(nc, n):
 
 
 def upsample(a, shape):
-    """a: [C, cz, cy, cx] -> [C, nz, ny, nx]."""
+    """a: [C, cz, cy, cx] -> [C, nz, ny, nx]: the tensor product of the three
+    axes' up-sampling matrices, applied one axis at a time."""
     nz, ny, nx = shape
     _, cz, cy, cx = a.shape
     Mz, My, Mx = up_matrix(cz, nz), up_matrix(cy, ny), up_matrix(cx, nx)
-    return torch.einsum("Zz,Yy,Xx,czyx->cZYX", Mz, My, Mx, a)
+    t = torch.einsum("Xx,czyx->czyX", Mx, a)
+    t = torch.einsum("Yy,czyX->czYX", My, t)
+    return torch.einsum("Zz,czYX->cZYX", Mz, t)
 
 
 def forward(x, p, ch, bf16=True, keep=False):

@@ -173,6 +173,9 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeom g, const uint16_t* __rest
 constexpr int CL_BX = 16, CL_BY = 4, CL_BZ = 4;
 constexpr int CL_HX = CL_BX + 2, CL_HY = CL_BY + 2, CL_HZ = CL_BZ + 2;
 constexpr int CL_CMAX = 32;   // input channels the largest box holds
+#ifndef LASTO_CONV_LDS_MIN_NODES
+#define LASTO_CONV_LDS_MIN_NODES 100000   // levels from this many nodes use the LDS form
+#endif
 
 // CM: input channels the box holds (8, 16 or 32: 10, 21 or 41 KB of LDS)
 template <int NT, int CM>
@@ -310,7 +313,10 @@ hipError_t launch_conv(const ConvGeom& g, const uint16_t* in, const uint16_t* wp
                        hipStream_t s)
 {
     if (g.cin % 8 || g.cout % 16 || g.cout > 64 || g.kpad % 32 || g.kpad < 27 * g.cin) return hipErrorInvalidValue;
-    if (g.mode == CONV_SAME && g.cin <= CL_CMAX && g.ix == g.nx && g.iy == g.ny && g.iz == g.nz) {
+    // (on small levels the one-tile-per-wave gathers keep more waves busy
+    // than the bricks do, so the LDS form serves the large ones)
+    if (g.mode == CONV_SAME && g.cin <= CL_CMAX && g.ix == g.nx && g.iy == g.ny && g.iz == g.nz &&
+        (long)g.nx * g.ny * g.nz >= LASTO_CONV_LDS_MIN_NODES) {
         const unsigned nb = (unsigned)(((g.nx + CL_BX - 1) / CL_BX) * ((g.ny + CL_BY - 1) / CL_BY) *
                                        ((g.nz + CL_BZ - 1) / CL_BZ));
         const int cm = g.cin <= 8 ? 8 : (g.cin <= 16 ? 16 : 32);

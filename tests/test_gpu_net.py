@@ -59,19 +59,29 @@ def _net_with_biases(L, rng, shape, ch=CH, seed=3):
     return net, net.params().astype(np.float64)
 
 
-@pytest.mark.parametrize("shape", [(20, 27, 37), (9, 16, 8)])
-def test_net_forward_matches_reference(torch, L, R, shape):
-    say("net forward %s" % (shape,))
+# (93, 94, 95): levels of 0.83 M and 0.11 M nodes, where the stride-1
+# convolutions take their LDS-staged form (8 and 32 input channels)
+@pytest.mark.parametrize("shape,ch", [((20, 27, 37), CH), ((9, 16, 8), CH), ((93, 94, 95), (16, 32, 16, 16))])
+def test_net_forward_matches_reference(torch, L, R, shape, ch):
+    say("net forward %s ch %s" % (shape, ch))
     rng = np.random.default_rng(21)
-    net, p = _net_with_biases(L, rng, shape)
+    net, p = _net_with_biases(L, rng, shape, ch=ch)
     x_bits, x = _features(torch, rng, shape)
     y = net.forward(x_bits).cpu().numpy().astype(np.float64)
-    want = R.forward(x, p, CH, bf16=True).numpy()
+    want = R.forward(x, p, ch, bf16=True).numpy()
     err = np.linalg.norm(y - want) / np.linalg.norm(want)
-    exact = R.forward(x, p, CH, bf16=False).numpy()
-    say("  rel L2 %.3e, max %.3e of %.3e (vs unrounded FP64: %.3e)" % (
-        err, np.abs(y - want).max(), np.abs(want).max(), np.linalg.norm(y - exact) / np.linalg.norm(exact)))
-    assert err <= 2e-3
+    exact = R.forward(x, p, ch, bf16=False).numpy()
+    rounding = np.linalg.norm(want - exact) / np.linalg.norm(exact)
+    say("  rel L2 %.3e, max %.3e of %.3e (rounded reference vs unrounded FP64: %.3e)" % (
+        err, np.abs(y - want).max(), np.abs(want).max(), rounding))
+    # Both sides round every activation to BF16, the GPU from FP32
+    # accumulators and the reference from FP64: where the two pre-rounding
+    # values straddle a rounding boundary they round apart, and such
+    # differences cascade through the net's eleven rounded stages. The GPU
+    # then stays closer to the rounded reference than that reference is to
+    # unrounded arithmetic (0.6x at every shape measured).
+    assert err <= 0.75 * rounding + 1e-6
+    assert err <= 5e-3
     assert np.abs(y - want).max() <= 2e-2 * np.abs(want).max()
     net.close()
 
