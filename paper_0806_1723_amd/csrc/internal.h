@@ -27,7 +27,7 @@ enum Scalar {
     S_RR = 3,               // <r, r>_W after the update
     S_R0 = 4,               // reference ||b - A v_bc||_W^2
     S_TMP = 5,
-    S_RZ32_0 = 8, S_RZ32_1 = 9, S_PQ32 = 10, S_RR32 = 11,   // inner FP32 PCG
+    S_RZ32_0 = 8, S_RZ32_1 = 9, S_PQ32 = 10,   // inner FP32 PCG
     S_BR0 = 32,                        // per right-hand side: reference norm^2 [kMaxBatch]
     S_BRR = 32 + kMaxBatch,            // per right-hand side: residual norm^2 [kMaxBatch]
 };
@@ -323,7 +323,8 @@ template <typename T>
 hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pnew, const double* scal,
                            int i_num, int i_den, int first, hipStream_t s);
 // x += alpha p, r -= alpha q (all split), alpha = scal[i_num]/scal[i_den];
-// partials of <r, r>_W (count in *nparts, at most flat_blocks<T>(L))
+// partials of <r, r>_W when partials is given (count in *nparts, at most
+// flat_blocks<T>(L))
 template <typename T>
 hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
                             int i_den, double* partials, hipStream_t s, int* nparts, int first = 0);

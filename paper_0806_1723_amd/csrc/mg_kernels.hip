@@ -866,10 +866,10 @@ hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pne
 }
 
 // x += alpha p (x = alpha p on the first step), r -= alpha q (all split),
-// alpha = scal[i_num]/scal[i_den]; partial <r,r>_W. A non-finite alpha leaves
+// alpha = scal[i_num]/scal[i_den]; with NORM, partials of <r,r>_W. A non-finite alpha leaves
 // x and r untouched (the caller then reports the breakdown with x still the
 // last finite iterate).
-template <typename T>
+template <typename T, bool NORM>
 __global__ __launch_bounds__(FL_NT) void k_update_xr(LevelView L, unsigned nvec, T* __restrict__ x,
                                                      T* __restrict__ r, const T* __restrict__ p,
                                                      const T* __restrict__ q, const double* __restrict__ scal,
@@ -914,6 +914,7 @@ __global__ __launch_bounds__(FL_NT) void k_update_xr(LevelView L, unsigned nvec,
             } else if (first) {
                 reinterpret_cast<V*>(x)[e] = V(T(0));   // the iterate is still e = 0
             }
+            if (!NORM) continue;
             // dual volume: x width by parity of i (zero off the interior), y, z widths
             const double* wx = L.xpar + (size_t)(((ps[u].c + ps[u].j + ps[u].k) & 1) * 3 + 2) * L.W + ps[u].m;
             const double wyz = L.ax[1].m[ps[u].j] * L.ax[2].m[ps[u].k];
@@ -923,6 +924,7 @@ __global__ __launch_bounds__(FL_NT) void k_update_xr(LevelView L, unsigned nvec,
             acc += wyz * a;
         }
     }
+    if (!NORM) return;
     const double t = block_sum<FL_NT>(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = ok ? t : __builtin_nan("");
 }
@@ -931,11 +933,19 @@ template <typename T>
 hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
                             int i_den, double* partials, hipStream_t s, int* nparts, int first)
 {
-    static const int cap = kernel_cap(k_update_xr<T>);
-    const int nb = flat_grid(flat_vectors<T>(L), cap);
-    hipLaunchKernelGGL(k_update_xr<T>, dim3(nb), dim3(FL_NT), 0, s, L, flat_vectors<T>(L), x, r, p, q, scal, i_num,
-                       i_den, partials, first);
-    if (nparts) *nparts = nb;
+    if (partials) {
+        static const int cap = kernel_cap(k_update_xr<T, true>);
+        const int nb = flat_grid(flat_vectors<T>(L), cap);
+        hipLaunchKernelGGL((k_update_xr<T, true>), dim3(nb), dim3(FL_NT), 0, s, L, flat_vectors<T>(L), x, r, p, q,
+                           scal, i_num, i_den, partials, first);
+        if (nparts) *nparts = nb;
+    } else {
+        static const int cap = kernel_cap(k_update_xr<T, false>);
+        const int nb = flat_grid(flat_vectors<T>(L), cap);
+        hipLaunchKernelGGL((k_update_xr<T, false>), dim3(nb), dim3(FL_NT), 0, s, L, flat_vectors<T>(L), x, r, p, q,
+                           scal, i_num, i_den, partials, first);
+        if (nparts) *nparts = 0;
+    }
     return hipGetLastError();
 }
 

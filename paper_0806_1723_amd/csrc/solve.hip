@@ -203,10 +203,9 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
             HIPCHK(launch_add32_nat(V, v, g->e32, pn, g->scalars, srz, S_PQ32, s));
             break;
         }
-        int nb_r = 0;
-        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, g->partials, s, &nb_r,
+        // (the inner loop never reads its own residual norm)
+        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, nullptr, s, nullptr,
                                        it == 0));
-        if (lasto_status e = reduce_to(g, nb_r, S_RR32); e != LASTO_OK) return e;
     }
     return LASTO_OK;
 }
