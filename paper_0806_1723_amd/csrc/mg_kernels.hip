@@ -1088,11 +1088,20 @@ hipError_t launch_inject_nan(float* r, size_t idx, hipStream_t s)
 // one L2. A thread takes KU consecutive planes and issues every gather of all
 // of them before it sums any (their table lookups first, then the values),
 // so it waits on memory twice rather than twice per plane.
-template <typename T> struct TransferUnroll { static constexpr int KU = 4; };
+template <typename T> struct TransferUnroll { static constexpr int KU = 2; };
 template <> struct TransferUnroll<double> { static constexpr int KU = 2; };
 
 struct TileShape {
     int nbx, nby, nb, per;
+};
+
+// two consecutive elements, aligned to one (a pair starting at any entry)
+template <typename T> struct Pair;
+template <> struct Pair<float> {
+    typedef float P __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <> struct Pair<double> {
+    typedef double P __attribute__((ext_vector_type(2), aligned(8)));
 };
 
 static TileShape tile_shape(int cols_x, int rows_y, int planes, int ku)
@@ -1132,7 +1141,8 @@ __global__ __launch_bounds__(PT_NT) void k_restrict_red(LevelView F, LevelView C
 #pragma unroll
         for (int c = 0; c < 3; ++c) wz[u][c] = (T)C.ax[2].rw[3 * K + c];
     }
-    // the gathers: two red entries of each of the 3 x 3 fine rows per plane
+    // the gathers: two consecutive red entries of each of the 3 x 3 fine rows
+    // per plane, as one load (aligned to one element only)
     T g0[KU][3][3], g1[KU][3][3];
 #pragma unroll
     for (int u = 0; u < KU; ++u)
@@ -1141,8 +1151,9 @@ __global__ __launch_bounds__(PT_NT) void k_restrict_red(LevelView F, LevelView C
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const T* row = r + ((size_t)(fk[u] - 1 + c) * F.ny + (fj - 1 + b)) * F.W + x.m0;
-                g0[u][c][b] = row[0];
-                g1[u][c][b] = row[1];
+                const typename Pair<T>::P q = *(const typename Pair<T>::P*)row;
+                g0[u][c][b] = q.x;
+                g1[u][c][b] = q.y;
             }
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
@@ -1172,72 +1183,109 @@ hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* 
 }
 
 // u += P e on the red nodes only: when a black half-sweep follows, it
-// overwrites every black value, so correcting them would be wasted work. One
-// red entry m of a row per thread, KU planes; its fine node is i = o + 2m
-// with the row parity o = (j + k) & 1, so the taps of both parities are
-// prepared once.
+// overwrites every black value, so correcting them would be wasted work. Two
+// consecutive red entries m, m+1 of a row per thread (fine nodes i0 = o + 2m
+// and i1 = i0 + 2, o = (j + k) & 1), KU planes. Their coarse nodes lie in
+// Ix0 .. Ix0 + 3 (Ix0 = pc(i0); a coarse step spans at most two fine steps),
+// which in each coarse row are two consecutive entries of each colour: two
+// pair loads per row serve both fine nodes.
 template <typename T>
 __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C, const T* __restrict__ e,
                                                        T* __restrict__ u, int nbx, int nby, int nb, int per)
 {
+    typedef typename Pair<T>::P P2;
     constexpr int KU = TransferUnroll<T>::KU;
     const int t = xcd_tile(blockIdx.x, per);
-    const int m = (t % nbx) * PT_X + (threadIdx.x & (PT_X - 1));
+    const int m = 2 * ((t % nbx) * PT_X + (threadIdx.x & (PT_X - 1)));
     const int j = 1 + ((t / nbx) % nby) * PT_Y + (threadIdx.x >> 6);
-    if (t >= nb || j > F.ny - 2) return;
-    const bool mok = m <= (F.nx - 2) / 2;
-    const int mm = mok ? m : (F.nx - 2) / 2;   // clamped entry for the loads
-    const int i0 = 2 * mm, i1 = 2 * mm + 1;
-    const bool ok0 = mok && i0 >= 1 && i0 <= F.nx - 2;
-    const bool ok1 = mok && i1 <= F.nx - 2;
-    const PTaps<T> x0 = prolong_taps<T>(C.ax[0], min(max(i0, 1), F.nx - 2));
-    const PTaps<T> x1 = prolong_taps<T>(C.ax[0], min(i1, F.nx - 2));
+    if (t >= nb || j > F.ny - 2 || m > (F.nx - 2) / 2) return;
+    const int mlast = (F.nx - 2) / 2;
+    // taps of both nodes for both row parities (o = 0: i = 2m, 2m + 2; o = 1: 2m + 1, 2m + 3)
+    PTaps<T> xa[2], xb[2];
+    bool oka[2], okb[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        const int i0 = o + 2 * m, i1 = i0 + 2;
+        oka[o] = i0 >= 1 && i0 <= F.nx - 2;
+        okb[o] = m + 1 <= mlast && i1 <= F.nx - 2;
+        xa[o] = prolong_taps<T>(C.ax[0], min(max(i0, 1), F.nx - 2));
+        xb[o] = prolong_taps<T>(C.ax[0], min(max(i1, 1), F.nx - 2));
+    }
     const PTaps<T> y = prolong_taps<T>(C.ax[1], j);
     const int k0 = 1 + (t / (nbx * nby)) * KU;
     PTaps<T> z[KU];
 #pragma unroll
     for (int q = 0; q < KU; ++q) z[q] = prolong_taps<T>(C.ax[2], min(k0 + q, F.nz - 2));
     const size_t plane = (size_t)F.ny * F.W;
-    const size_t row = (size_t)j * F.W + mm;
-    T va[KU][2][2], vb[KU][2][2], uo[KU];
+    const size_t row = (size_t)j * F.W + m;
+    // per plane and coarse row (b, c): the coarse values at Ix0 .. Ix0 + 3
+    T cv[KU][2][2][4];
+    P2 uo[KU];
 #pragma unroll
     for (int q = 0; q < KU; ++q) {
         const int k = min(k0 + q, F.nz - 2);
-        const PTaps<T>& x = ((j + k) & 1) ? x1 : x0;
-        const int ma = x.I >> 1, mb = (x.I + 1) >> 1;
+        const int o = (j + k) & 1;
+        const int I0 = o ? xa[1].I : xa[0].I;
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int Jb = y.I + b, Kc = z[q].I + c;
                 const size_t crow = ((size_t)Kc * C.ny + Jb) * C.W;
-                const int ca = (x.I + Jb + Kc) & 1;
-                va[q][c][b] = e[(size_t)ca * C.cs + crow + ma];
-                vb[q][c][b] = e[(size_t)(ca ^ 1) * C.cs + crow + mb];
+                const int c0 = (I0 + Jb + Kc) & 1;   // colour of I0 (and I0 + 2); I0 + 1, I0 + 3 have the other
+                const P2 p0 = *(const P2*)(e + (size_t)c0 * C.cs + crow + (I0 >> 1));
+                const P2 p1 = *(const P2*)(e + (size_t)(c0 ^ 1) * C.cs + crow + ((I0 + 1) >> 1));
+                cv[q][c][b][0] = p0.x;
+                cv[q][c][b][1] = p1.x;
+                cv[q][c][b][2] = p0.y;
+                cv[q][c][b][3] = p1.y;
             }
-        uo[q] = u[(size_t)k * plane + row];
+        uo[q] = *(const P2*)(u + (size_t)k * plane + row);
     }
 #pragma unroll
     for (int q = 0; q < KU; ++q) {
         const int k = k0 + q;
-        const bool odd = (j + k) & 1;
-        const T w0 = odd ? x1.w0 : x0.w0, w1 = odd ? x1.w1 : x0.w1;
-        T acc = T(0);
+        if (k > F.nz - 2 || !F.zint[k]) continue;
+        const int o = (j + k) & 1;
+        const PTaps<T>& A = o ? xa[1] : xa[0];
+        const PTaps<T>& B = o ? xb[1] : xb[0];
+        const int d = B.I - A.I;   // 0, 1 or 2
+        T acc0 = T(0), acc1 = T(0);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            T sacc = T(0);
+            T s0 = T(0), s1 = T(0);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) sacc += (b ? y.w1 : y.w0) * (w0 * va[q][c][b] + w1 * vb[q][c][b]);
-            acc += (c ? z[q].w1 : z[q].w0) * sacc;
+            for (int b = 0; b < 2; ++b) {
+                const T* v = cv[q][c][b];
+                const T wyb = b ? y.w1 : y.w0;
+                s0 += wyb * (A.w0 * v[0] + A.w1 * v[1]);
+                const T b0 = d == 0 ? v[0] : (d == 1 ? v[1] : v[2]);
+                const T b1 = d == 0 ? v[1] : (d == 1 ? v[2] : v[3]);
+                s1 += wyb * (B.w0 * b0 + B.w1 * b1);
+            }
+            const T wzc = c ? z[q].w1 : z[q].w0;
+            acc0 += wzc * s0;
+            acc1 += wzc * s1;
         }
-        if (k <= F.nz - 2 && F.zint[k] && (odd ? ok1 : ok0)) u[(size_t)k * plane + row] = uo[q] + acc;
+        const bool s_a = o ? oka[1] : oka[0], s_b = o ? okb[1] : okb[0];
+        T* out = u + (size_t)k * plane + row;
+        if (s_a && s_b) {
+            P2 w;
+            w.x = uo[q].x + acc0;
+            w.y = uo[q].y + acc1;
+            *(P2*)out = w;
+        } else {
+            if (s_a) out[0] = uo[q].x + acc0;
+            if (s_b) out[1] = uo[q].y + acc1;
+        }
     }
 }
 
 template <typename T>
 hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s)
 {
-    const TileShape ts = tile_shape((F.nx - 2) / 2 + 1, F.ny - 2, F.nz - 2, TransferUnroll<T>::KU);
+    // pairs of red entries m = 0, 2, ... <= (nx - 2) / 2
+    const TileShape ts = tile_shape(((F.nx - 2) / 2) / 2 + 1, F.ny - 2, F.nz - 2, TransferUnroll<T>::KU);
     hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, e, u, ts.nbx, ts.nby, ts.nb,
                        ts.per);
     return hipGetLastError();
