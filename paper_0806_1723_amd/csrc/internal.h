@@ -271,7 +271,7 @@ namespace lasto {
 // ----------------------------------------------------------------- kernels
 // Block counts of the reducing launches (each writes one partial per block).
 int half_blocks(const LevelView& L);       // one half-sweep
-int interior_blocks(const LevelView& L);   // pointwise interior launches
+int interior_blocks(const LevelView& L);   // partials of a residual-norm launch (launch_residual_nat*)
 size_t split_elems(const LevelView& L);
 
 // Red-black half-sweep on A u = bscale f, in place in the split layout:
