@@ -1,6 +1,6 @@
 """CPU oracle for the LASTO Hartree step -- TEST INFRASTRUCTURE ONLY.
 
-Plain FP64 C (``oracle.c``) behind ctypes. Only ``tests/``, the smoke check
+Plain FP64 C (``oracle.c``, ``sphere.c``) behind ctypes. Only ``tests/``, the smoke check
 and the benchmark's CPU-baseline leg may import this package. The GPU path
 (``paper_0806_1723_amd``) never imports it and shares no code with it.
 
@@ -16,7 +16,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "sphere.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PI = np.pi
@@ -26,7 +26,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle library in place; returns its path."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -37,7 +37,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
             build(force=True)
         L = C.CDLL(_LIB)
         d, i = C.c_double, C.c_int
@@ -64,6 +64,18 @@ def lib():
         L.oracle_rb_sweep.restype = None
         L.oracle_hierarchy_sizes.argtypes = [P, i, P, i, P, i, d, i, P, i]
         L.oracle_hierarchy_sizes.restype = i
+        L.oracle_sphere_rule.argtypes = [i, i, P, P]
+        L.oracle_sphere_rule.restype = i
+        L.oracle_sphere_project.argtypes = [i, i, i, P, P]
+        L.oracle_sphere_project.restype = i
+        L.oracle_radial_node.argtypes = [d, d, i, i]
+        L.oracle_radial_node.restype = d
+        L.oracle_sphere_radial.argtypes = [i, P, P, i, d, P, P, P]
+        L.oracle_sphere_radial.restype = i
+        L.oracle_sphere_energy.argtypes = [i, P, i, d, P, P, P]
+        L.oracle_sphere_energy.restype = i
+        L.oracle_energy_grid.argtypes = [P, i, P, i, P, i, P, P, i, P, P]
+        L.oracle_energy_grid.restype = d
         _lib = L
     return _lib
 
@@ -219,3 +231,63 @@ def hartree_step(xs, atoms_arr, dirs, bc_mode=1, lmax_bc=4, rtol=1e-12, max_cycl
     pts = sphere_points(atoms_arr["centers"], atoms_arr["radius"], dirs)
     vs = interp(xs, v, pts).reshape(len(atoms_arr["q"]), -1)
     return dict(rho=rho, Q=Q, v=v, cycles=cyc, rel=rel, hist=hist, sphere=vs, center=center)
+
+
+# ------------------------------------------------------- inside the spheres
+NLM = 25
+
+
+def sphere_rule(n_theta, n_phi):
+    """Directions [n_theta*n_phi][3] and weights of the product rule on the
+    unit sphere used for eq. (3.6) (sphere.c)."""
+    np_ = n_theta * n_phi
+    d = np.zeros((np_, 3))
+    w = np.zeros(np_)
+    if lib().oracle_sphere_rule(n_theta, n_phi, _p(d), _p(w)) != 0:
+        raise ValueError("bad sphere rule")
+    return d, w
+
+
+def sphere_project(values, n_theta, n_phi):
+    """eq. (3.6): values [n_atoms][n_theta*n_phi] -> V_LM(R) [n_atoms][25]."""
+    v = _f64(values).reshape(-1, n_theta * n_phi)
+    out = np.zeros((len(v), NLM))
+    if lib().oracle_sphere_project(len(v), n_theta, n_phi, _p(v), _p(out)) != 0:
+        raise ValueError("bad sphere rule")
+    return out
+
+
+def radial_mesh(R, r_min, n):
+    """Atom mesh r_k, k = 0..n-1 (sphere.c)."""
+    return np.array([lib().oracle_radial_node(float(R), float(r_min), int(n), k) for k in range(n)])
+
+
+def sphere_radial(radii, Z, r_min, vlm_R, rho_lm):
+    """Interior solution of eq. (3.4): vlm_R [n_atoms][25], rho_lm
+    [n_atoms][25][n_rad] -> V_LM(r_k) [n_atoms][25][n_rad]."""
+    rho_lm = _f64(rho_lm)
+    na, _, n = rho_lm.shape
+    out = np.zeros_like(rho_lm)
+    rc = lib().oracle_sphere_radial(na, _p(_f64(radii)), _p(_f64(Z)), n, float(r_min), _p(_f64(vlm_R)),
+                                    _p(rho_lm), _p(out))
+    if rc != 0:
+        raise ValueError("oracle_sphere_radial needs n_rad >= 4")
+    return out
+
+
+def sphere_energy(radii, r_min, vlm, rho_lm):
+    """Per atom sum_LM int_0^R V_LM rho_LM r^2 dr."""
+    vlm, rho_lm = _f64(vlm), _f64(rho_lm)
+    na, _, n = rho_lm.shape
+    out = np.zeros(na)
+    if lib().oracle_sphere_energy(na, _p(_f64(radii)), n, float(r_min), _p(vlm), _p(rho_lm), _p(out)) != 0:
+        raise ValueError("oracle_sphere_energy needs n_rad >= 4")
+    return out
+
+
+def energy_grid(xs, v, rho, centers, radii):
+    """sum over nodes outside every sphere of vol_n v_n rho_n."""
+    x, y, z = (_f64(a) for a in xs)
+    centers = _f64(centers).reshape(-1, 3)
+    return lib().oracle_energy_grid(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(_f64(v)), _p(_f64(rho)),
+                                    len(centers), _p(centers), _p(_f64(radii)))
