@@ -190,6 +190,8 @@ def main():
                      "launches": launches, "events_on": "timed step 1 of %d" % args.steps},
     }
 
+    out["spheres"] = bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii)
+
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, xs, (rho[0] if nb > 1 else rho).cpu().numpy(), args.cpu_seconds)
         if nb > 1:
@@ -197,6 +199,80 @@ def main():
             out["cpu_baseline"]["sample"] += "; times %d right-hand sides" % nb
     g.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii):
+    """Inside the spheres, on the solved field: projection onto y_LM
+    (eq. (3.6), 8 x 9 rule), the radial solve of eq. (3.4) on 429-point log
+    meshes, and the energy integral (grid part over every node, sphere parts),
+    each call timed with events on the grid's stream; the median of the
+    timed repetitions. With the CPU leg on, the oracle's same three steps
+    once each."""
+    import numpy as np
+    import torch
+    nb = g.n_batch
+    atoms_b = w.batch_atoms if nb > 1 else [w.atoms]
+    rho_lm = np.stack([I.sphere_density(a) for a in atoms_b])
+    if nb == 1:
+        rho_lm = rho_lm[0]
+    Z = np.full(len(radii), I.PD_Z)
+    S = lasto.Spheres(g, centers, radii, Z=Z, n_theta=8, n_phi=9, n_rad=I.N_RAD, r_min=I.R_MIN)
+    rl = torch.from_numpy(rho_lm).to("cuda")
+    vR = S.project(v)
+    v_lm = S.radial(vR, rl)
+    S.energy(v, rho, v_lm, rl)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_proj, t_rad, t_en, t_all = [], [], [], []
+    for _ in range(max(args.steps, 5)):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev[0].record()
+        S.project(v, vR)
+        ev[1].record()
+        S.radial(vR, rl, v_lm)
+        ev[2].record()
+        e = S.energy(v, rho, v_lm, rl)
+        ev[3].record()
+        torch.cuda.synchronize()
+        t_all.append((time.perf_counter() - w0) * 1e6)
+        t_proj.append(ev[0].elapsed_time(ev[1]) * 1e3)
+        t_rad.append(ev[1].elapsed_time(ev[2]) * 1e3)
+        t_en.append(ev[2].elapsed_time(ev[3]) * 1e3)
+    med = statistics.median
+    nodes = int(np.prod(g.shape))
+    grid_bytes = 16 * nodes
+    e = np.atleast_2d(e)
+    log("bench: spheres: project %.1f us, radial %.1f us, energy %.1f us (grid part reads %.1f MB), "
+        "whole %.1f us; E_H/2 parts %s" % (med(t_proj), med(t_rad), med(t_en), grid_bytes / 1e6, med(t_all),
+                                          (0.5 * e[0]).tolist()))
+    out = {"atoms": len(radii), "rule": "8 x 9", "n_rad": I.N_RAD, "right_hand_sides": nb,
+           "project_us": round(med(t_proj), 2), "radial_us": round(med(t_rad), 2),
+           "energy_us": round(med(t_en), 2), "whole_us": round(med(t_all), 2),
+           "energy_grid_bytes": grid_bytes,
+           "energy_gbs_lower_bound": round(grid_bytes / (med(t_en) * 1e-6) / 1e9, 1),
+           "integral_v_rho": [round(float(x), 9) for x in e.sum(axis=1)]}
+    if not args.no_cpu:
+        import oracle
+        oracle.lib()
+        v_h = (v[0] if nb > 1 else v).cpu().numpy()
+        rho_h = (rho[0] if nb > 1 else rho).cpu().numpy()
+        rl_h = rho_lm[0] if nb > 1 else rho_lm
+        t0 = time.perf_counter()
+        d, _ = oracle.sphere_rule(8, 9)
+        vals = oracle.interp(xs, v_h, oracle.sphere_points(centers, radii, d)).reshape(len(radii), -1)
+        wR = oracle.sphere_project(vals, 8, 9)
+        t1 = time.perf_counter()
+        wl = oracle.sphere_radial(radii, Z, I.R_MIN, wR, rl_h)
+        t2 = time.perf_counter()
+        oracle.energy_grid(xs, v_h, rho_h, centers, radii)
+        oracle.sphere_energy(radii, I.R_MIN, wl, rl_h)
+        t3 = time.perf_counter()
+        out["cpu_oracle_ms"] = {"project": round((t1 - t0) * 1e3, 2), "radial": round((t2 - t1) * 1e3, 2),
+                                "energy": round((t3 - t2) * 1e3, 2), "cores": 1,
+                                "sample": "one right-hand side, once each"}
+        log("bench: spheres on the oracle: %s" % out["cpu_oracle_ms"])
+    S.close()
+    return out
 
 
 def cpu_baseline(w, xs, rho, min_seconds):

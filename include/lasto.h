@@ -221,6 +221,91 @@ lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, double* v,
 lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n_atoms, const double* centers,
                                  const double* radii, int n_dir, const double* dirs, double* out);
 
+/* ------------------------------------------------------------------------
+ * Inside the muffin-tin spheres (Section 3, eq. (3.4)-(3.7)) and the energy
+ * integral of Section 4. The grid solution gives V_C on each sphere boundary;
+ * its projection onto the real orthonormal harmonics y_LM (L <= 4, index
+ * L*L + L + M, no Condon-Shortley phase) is the Dirichlet datum of the radial
+ * equation (3.4) inside, whose solution with the sphere's own density
+ * rho_LM(r) and nuclear charge Z is
+ *   V_LM(r) = V_LM(R) (r/R)^L
+ *           - 4 pi/(2L+1) [ r^-(L+1) P(r) + r^L Q(r) - r^L P(R)/R^(2L+1) ]
+ *           + (L = 0) sqrt(4 pi) Z (1/r - 1/R),
+ *   P(r) = int_0^r rho_LM r'^(L+2) dr',  Q(r) = int_r^R rho_LM r'^(1-L) dr'
+ * (the printed integrands read as rho r'^(L+2) and rho r'^(1-L); the sign is
+ * that of eq. (3.2) as written, Laplacian V = +4 pi (rho - Z delta), the
+ * printed formula having the opposite overall sign).
+ *
+ * Radial mesh (Section 4: logarithmic, 429 points in the paper): atom a uses
+ *   r_k = R_a exp((k - (n_rad - 1)) D_a), D_a = ln(R_a / r_min) / (n_rad - 1),
+ * k = 0..n_rad-1, so r_0 = r_min and r_(n_rad-1) = R_a. Radial integrals are
+ * taken in t = ln r interval by interval, each as the integral of the cubic
+ * through four consecutive samples (fourth order); the piece [0, r_0] as
+ * rho(r_0) r_0^(L+3)/(2L+3) (rho_LM ~ r^L there) and, for the energy,
+ * V(r_0) rho(r_0) r_0^3 / 3.
+ *
+ * Angular rule of eq. (3.6): n_theta Gauss-Legendre nodes t_a in cos(theta)
+ * (ascending) times n_phi azimuths 2 pi (b + 1/2)/n_phi, point p = a n_phi + b,
+ * direction (sin cos, sin sin, cos), weight w_a 2 pi / n_phi. With
+ * n_theta >= 5 and n_phi >= 9 it integrates every product y_LM y_L'M' with
+ * L, L' <= 4 exactly.
+ *
+ * Batches: arrays of a batched grid carry a leading [n_batch] dimension; the
+ * geometry is the same for every copy.
+ */
+typedef struct lasto_spheres_s* lasto_spheres;
+
+/*
+ * A set of non-overlapping spheres on grid g: device tables of the atoms,
+ * the angular rule and the reduction scratch (owned by the set; destroy it
+ * before its grid).
+ *   centers: host [n_atoms][3]; radii, Z: host [n_atoms] (Z may be NULL: 0).
+ *   Each sphere lies inside the box; |C_a - C_b| >= R_a + R_b.
+ *   n_theta in 5..64, n_phi in 9..1024 (n_theta * n_phi <= 8192),
+ *   n_rad in 8..1024, 0 < r_min < min R_a.
+ * Errors: LASTO_ERR_ARG, LASTO_ERR_ALLOC, LASTO_ERR_HIP.
+ */
+lasto_status lasto_spheres_create(lasto_grid g, int n_atoms, const double* centers, const double* radii,
+                                  const double* Z, int n_theta, int n_phi, int n_rad, double r_min,
+                                  lasto_spheres* out);
+lasto_status lasto_spheres_destroy(lasto_spheres s);
+
+/*
+ * eq. (3.6): vlm_R[a][LM] = sum_p w_p V(C_a + R_a d_p) y_LM(d_p), V(x) by
+ * tricubic Lagrange interpolation of the grid values (as lasto_sphere_interp).
+ *   v: device grid values [nz][ny][nx]. vlm_R: device [n_atoms][25].
+ * Enqueued on the grid's stream; returns without waiting.
+ * Errors: LASTO_ERR_ARG (NULL), LASTO_ERR_HIP.
+ */
+lasto_status lasto_sphere_project(lasto_spheres s, const double* v, double* vlm_R);
+
+/*
+ * Interior solution of eq. (3.4) (formula above) in every sphere.
+ *   vlm_R: device [n_atoms][25] the Dirichlet data (lasto_sphere_project).
+ *   rho_lm: device [n_atoms][25][n_rad] rho_LM(r_k) of the density inside
+ *     sphere a on its mesh (the electron density; the nucleus enters by Z).
+ *   v_lm: device [n_atoms][25][n_rad] out, V_LM(r_k); v_lm[.][.][n_rad-1] = vlm_R.
+ * Enqueued on the grid's stream; returns without waiting.
+ * Errors: LASTO_ERR_ARG (NULL, v_lm aliasing an input), LASTO_ERR_HIP.
+ */
+lasto_status lasto_sphere_radial(lasto_spheres s, const double* vlm_R, const double* rho_lm, double* v_lm);
+
+/*
+ * The integral of V against the density over the domain (Section 4: half of
+ * it is the Hartree term of eq. (4.1) when V is the Hartree potential):
+ *   e_out[0] = sum over grid nodes outside every sphere (|x_n - C_a|^2 >= R_a^2,
+ *              squares and sums rounded as written) of vol_n v_n rho_n,
+ *              vol_n the product of the dual widths;
+ *   e_out[1] = sum over atoms and LM of int_0^R_a V_LM rho_LM r^2 dr on the
+ *              radial mesh (orthonormal y_LM turn the angular integral into
+ *              the sum over LM).
+ *   v, rho: device grid arrays; v_lm, rho_lm: device [n_atoms][25][n_rad].
+ *   e_out: host [2] ([n_batch][2] for a batch). Waits for the result.
+ * Errors: LASTO_ERR_ARG (NULL), LASTO_ERR_HIP.
+ */
+lasto_status lasto_sphere_energy(lasto_spheres s, const double* v, const double* rho, const double* v_lm,
+                                 const double* rho_lm, double* e_out);
+
 /*
  * The discrete operator of eq. (3.2) on the finest level: Au[n] = (A u)_n at
  * interior nodes (the three-point nonuniform second difference per axis, as

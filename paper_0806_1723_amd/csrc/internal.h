@@ -385,6 +385,26 @@ lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, co
                                 double rho_mul);
 hipError_t launch_interp(lasto_grid g, const double* v, const double* pts, int npts, double* out);
 
+// inside the spheres: one entry per atom (device table of a lasto_spheres)
+struct SphereAtom {
+    double c[3];   // centre
+    double R;      // sphere radius
+    double Z;      // nuclear charge
+    double D;      // log step of the radial mesh, ln(R / r_min) / (n_rad - 1)
+    double pad[2];
+};
+hipError_t launch_sphere_project(lasto_grid g, const double* v, const SphereAtom* atoms, int n_atoms,
+                                 const double4* rule, int npts, double* vlmR);
+hipError_t launch_radial_solve(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* vlmR,
+                               const double* rho_lm, double* v_lm);
+hipError_t launch_sphere_energy(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* v_lm,
+                                const double* rho_lm, double* e_atom);
+int energy_grid_blocks(const LevelView& L);   // partials per copy of launch_energy_grid
+hipError_t launch_energy_grid(lasto_grid g, const double* v, const double* rho, const SphereAtom* atoms, int n_atoms,
+                              double* partials);
+hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_atom, int n_atoms,
+                               double* out);
+
 // device table block builder
 lasto_status build_level_tables(lasto_grid g, int l);
 

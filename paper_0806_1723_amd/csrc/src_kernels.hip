@@ -436,12 +436,10 @@ __device__ __forceinline__ void lagrange_weights(const double* x, int i0, double
     w[3] = (d0 * d1 * d2) / ((x3 - x0) * (x3 - x1) * (x3 - x2));
 }
 
-__global__ __launch_bounds__(64) void k_interp(LevelView L, const double* __restrict__ v, const double* __restrict__ pts,
-                                               int npts, double* __restrict__ out)
+// tricubic Lagrange value of grid field v (one copy) at point p
+__device__ __forceinline__ double interp_point(const LevelView& L, const double* __restrict__ v, double px,
+                                              double py, double pz)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= npts) return;
-    const double px = pts[3 * t], py = pts[3 * t + 1], pz = pts[3 * t + 2];
     const int i0 = window_start(L.ax[0].x, L.nx, px);
     const int j0 = window_start(L.ax[1].x, L.ny, py);
     const int k0 = window_start(L.ax[2].x, L.nz, pz);
@@ -458,13 +456,406 @@ __global__ __launch_bounds__(64) void k_interp(LevelView L, const double* __rest
         }
         s += wz[c] * sy;
     }
-    out[t] = s;
+    return s;
+}
+
+__global__ __launch_bounds__(64) void k_interp(LevelView L, const double* __restrict__ v, const double* __restrict__ pts,
+                                               int npts, double* __restrict__ out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npts) return;
+    out[t] = interp_point(L, v, pts[3 * t], pts[3 * t + 1], pts[3 * t + 2]);
 }
 
 hipError_t launch_interp(lasto_grid g, const double* v, const double* pts, int npts, double* out)
 {
     const LevelView& L = g->cview;   // one right-hand side of a batch
     hipLaunchKernelGGL(k_interp, dim3((npts + 63) / 64), dim3(64), 0, g->stream, L, v, pts, npts, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ inside the spheres
+// eq. (3.6): V_LM(R) = int V(C + R d) y_LM(d) dOmega by a product rule
+// (rule[p] = direction, weight); eq. (3.4): the radial Green's-function
+// solution on each atom's logarithmic mesh; and the two parts of the
+// integral of V rho over the domain (grid nodes outside every sphere, radial
+// quadrature inside).
+
+// C + R d, rounded as written (no fused multiply-add), so the sphere points
+// are the products and sums of their definition
+__device__ __forceinline__ double axpy_exact(double c, double R, double d)
+{
+#pragma clang fp contract(off)
+    return c + R * d;
+}
+
+// |p - C|^2 with each square and sum rounded as written
+__device__ __forceinline__ double dist2_exact(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return dx * dx + dy * dy + dz * dz;
+}
+
+constexpr int SP_NT = 128;
+
+// one workgroup per (atom, right-hand side): every thread takes points
+// p = tid, tid + SP_NT, ..., accumulates w_p V_p y_LM(d_p) for the 25 LM,
+// then waves reduce in a fixed order
+__global__ __launch_bounds__(SP_NT) void k_sphere_project(LevelView L, const double* __restrict__ v, size_t copy_stride,
+                                                          const SphereAtom* __restrict__ atoms, int n_atoms,
+                                                          const double4* __restrict__ rule, int npts,
+                                                          double* __restrict__ vlmR)
+{
+    __shared__ double part[SP_NT / 64][25];
+    const int a = blockIdx.x, b = blockIdx.y;
+    const SphereAtom A = atoms[a];
+    const double* vb = v + (size_t)b * copy_stride;
+    double acc[25];
+    for (int t = 0; t < 25; ++t) acc[t] = 0.0;
+    for (int p = threadIdx.x; p < npts; p += SP_NT) {
+        const double4 d = rule[p];
+        const double val = d.w * interp_point(L, vb, axpy_exact(A.c[0], A.R, d.x), axpy_exact(A.c[1], A.R, d.y),
+                                              axpy_exact(A.c[2], A.R, d.z));
+        double S[25];
+        solid_harmonics(d.x, d.y, d.z, 4, S);   // |d| = 1: r^L y_LM(d) = y_LM(d)
+        for (int t = 0; t < 25; ++t) acc[t] += val * S[t];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int t = 0; t < 25; ++t) {
+        double s = acc[t];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+        if (lane == 0) part[wid][t] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 25) {
+        double s = 0.0;
+        for (int w = 0; w < SP_NT / 64; ++w) s += part[w][threadIdx.x];
+        vlmR[((size_t)b * n_atoms + a) * 25 + threadIdx.x] = s;
+    }
+}
+
+hipError_t launch_sphere_project(lasto_grid g, const double* v, const SphereAtom* atoms, int n_atoms,
+                                 const double4* rule, int npts, double* vlmR)
+{
+    const LevelView& L = g->cview;
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_sphere_project, dim3(n_atoms, g->n_batch), dim3(SP_NT), 0, g->stream, L, v, N, atoms, n_atoms,
+                       rule, npts, vlmR);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ int lm_degree(int lm)
+{
+    return lm < 1 ? 0 : lm < 4 ? 1 : lm < 9 ? 2 : lm < 16 ? 3 : 4;
+}
+
+__device__ __forceinline__ double ipow(double r, int e)
+{
+    double p = 1.0;
+    for (int t = 0; t < e; ++t) p *= r;
+    return p;
+}
+
+// integral over [t_k, t_k+1] of the cubic through four samples of g (uniform
+// step D in t = ln r): samples k-1..k+2 inside, 0..3 on the first interval,
+// n-4..n-1 on the last
+__device__ __forceinline__ double cubic_interval(const double* g, int n, int k, double D)
+{
+    double s;
+    if (k == 0)
+        s = 9.0 * g[0] + 19.0 * g[1] - 5.0 * g[2] + g[3];
+    else if (k == n - 2)
+        s = g[n - 4] - 5.0 * g[n - 3] + 19.0 * g[n - 2] + 9.0 * g[n - 1];
+    else
+        s = -g[k - 1] + 13.0 * g[k] + 13.0 * g[k + 1] - g[k + 2];
+    return D / 24.0 * s;
+}
+
+__device__ __forceinline__ double wave_prefix(double x, int lane)
+{
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(x, off);
+        if (lane >= off) x += t;
+    }
+    return x;
+}
+
+__device__ __forceinline__ double wave_suffix(double x, int lane)
+{
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_down(x, off);
+        if (lane + off < 64) x += t;
+    }
+    return x;
+}
+
+// Atom a's mesh: r_k = R exp((k - (n-1)) D), k = 0..n-1 (r_0 = r_min, r_(n-1) = R).
+__device__ __forceinline__ double radial_node(const SphereAtom& A, int n, int k)
+{
+    return A.R * exp((double)(k - (n - 1)) * A.D);
+}
+
+// One wave per (LM, atom, right-hand side). Interior solution of eq. (3.4):
+//   V(r) = V(R) (r/R)^L - 4 pi/(2L+1) [r^-(L+1) P(r) + r^L Q(r) - r^L P(R)/R^(2L+1)]
+//          + (L = 0) sqrt(4 pi) Z (1/r - 1/R),
+//   P(r) = int_0^r rho r'^(L+2) dr',  Q(r) = int_r^R rho r'^(1-L) dr'.
+// In t = ln r the integrands are g1 = rho r^(L+3) and g2 = rho r^(2-L);
+// P(r_k) = g1(r_0)/(2L+3) + sum_(j<k) I_j(g1), Q(r_k) = sum_(j>=k) I_j(g2).
+// Lane l owns points [l c, l c + c) and the intervals that start there; a
+// wave prefix sum of the lanes' P-increments and a suffix sum of their
+// Q-increments give each lane its starting values.
+__global__ __launch_bounds__(64) void k_radial_solve(const SphereAtom* __restrict__ atoms, int n_atoms, int n,
+                                                     const double* __restrict__ vlmR, const double* __restrict__ rho_lm,
+                                                     double* __restrict__ v_lm)
+{
+    extern __shared__ double rs_lds[];   // r, g1, g2, P: n each
+    double* r = rs_lds;
+    double* g1 = r + n;
+    double* g2 = g1 + n;
+    double* P = g2 + n;
+    const int lm = blockIdx.x, a = blockIdx.y, b = blockIdx.z, lane = threadIdx.x;
+    const int L = lm_degree(lm);
+    const SphereAtom A = atoms[a];
+    const size_t row = ((size_t)b * n_atoms + a) * 25 + lm;
+    const double* rho = rho_lm + row * n;
+    for (int k = lane; k < n; k += 64) {
+        const double rk = radial_node(A, n, k);
+        const double rl = ipow(rk, L);
+        r[k] = rk;
+        g1[k] = rho[k] * (rl * rk * rk * rk);
+        g2[k] = rho[k] * (rk * rk / rl);
+    }
+    __syncthreads();
+    const int c = (n + 63) / 64;
+    const int lo = min(n, lane * c), hi = min(n, lo + c), ihi = min(hi, n - 1);
+    double sI = 0.0, sJ = 0.0;
+    for (int k = lo; k < ihi; ++k) {
+        sI += cubic_interval(g1, n, k, A.D);
+        sJ += cubic_interval(g2, n, k, A.D);
+    }
+    const double head = g1[0] / (2 * L + 3);
+    const double inI = wave_prefix(sI, lane);
+    double exI = __shfl_up(inI, 1);
+    if (lane == 0) exI = 0.0;
+    const double PR = head + __shfl(inI, 63);
+    const double inJ = wave_suffix(sJ, lane);
+    double exJ = __shfl_down(inJ, 1);
+    if (lane == 63) exJ = 0.0;
+    double p = head + exI;
+    for (int k = lo; k < hi; ++k) {
+        P[k] = p;
+        if (k < n - 1) p += cubic_interval(g1, n, k, A.D);
+    }
+    const double cL = 4.0 * kPi / (2 * L + 1);
+    const double vR = vlmR[row];
+    const double R = A.R;
+    const double PRn = PR / ipow(R, 2 * L + 1);
+    const double zt = L == 0 ? sqrt(4.0 * kPi) * A.Z : 0.0;
+    double q = exJ;
+    double* out = v_lm + row * n;
+    for (int k = hi - 1; k >= lo; --k) {
+        if (k < n - 1) q += cubic_interval(g2, n, k, A.D);
+        const double rk = r[k];
+        const double rl = ipow(rk, L);
+        out[k] = vR * ipow(rk / R, L) - cL * (P[k] / (rl * rk) + rl * q - rl * PRn) + zt * (1.0 / rk - 1.0 / R);
+    }
+}
+
+hipError_t launch_radial_solve(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* vlmR,
+                               const double* rho_lm, double* v_lm)
+{
+    hipLaunchKernelGGL(k_radial_solve, dim3(25, n_atoms, g->n_batch), dim3(64), sizeof(double) * 4 * n_rad, g->stream,
+                       atoms, n_atoms, n_rad, vlmR, rho_lm, v_lm);
+    return hipGetLastError();
+}
+
+constexpr int SE_NT = 256;
+
+// One workgroup per (atom, right-hand side): sum_LM int_0^R V_LM rho_LM r^2 dr,
+// in t: g = V rho r^3, the piece [0, r_0] as g(r_0)/3, then the intervals.
+// Waves take LM = w, w + 4, ... (uniform trip count: 7 rounds of 4).
+__global__ __launch_bounds__(SE_NT) void k_sphere_energy(const SphereAtom* __restrict__ atoms, int n_atoms, int n,
+                                                         const double* __restrict__ v_lm,
+                                                         const double* __restrict__ rho_lm, double* __restrict__ e_atom)
+{
+    extern __shared__ double se_lds[];   // [SE_NT / 64][n]
+    __shared__ double per_lm[28];
+    const int a = blockIdx.x, b = blockIdx.y, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const SphereAtom A = atoms[a];
+    double* g = se_lds + (size_t)wid * n;
+    for (int base = 0; base < 28; base += SE_NT / 64) {
+        const int lm = base + wid;
+        if (lm < 25) {
+            const size_t row = (((size_t)b * n_atoms + a) * 25 + lm) * n;
+            for (int k = lane; k < n; k += 64) {
+                const double rk = radial_node(A, n, k);
+                g[k] = v_lm[row + k] * rho_lm[row + k] * (rk * rk * rk);
+            }
+        }
+        __syncthreads();
+        if (lm < 25) {
+            double s = 0.0;
+            for (int k = lane; k < n - 1; k += 64) s += cubic_interval(g, n, k, A.D);
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+            if (lane == 0) per_lm[lm] = g[0] / 3.0 + s;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int t = 0; t < 25; ++t) s += per_lm[t];
+        e_atom[(size_t)b * n_atoms + a] = s;
+    }
+}
+
+hipError_t launch_sphere_energy(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* v_lm,
+                                const double* rho_lm, double* e_atom)
+{
+    hipLaunchKernelGGL(k_sphere_energy, dim3(n_atoms, g->n_batch), dim3(SE_NT), sizeof(double) * (SE_NT / 64) * n_rad,
+                       g->stream, atoms, n_atoms, n_rad, v_lm, rho_lm, e_atom);
+    return hipGetLastError();
+}
+
+// Grid part: sum over nodes outside every sphere of vol_n v_n rho_n. A
+// workgroup takes EG_NT * EG_PER consecutive nodes of one copy (each wave
+// reads 64 consecutive doubles per load); the atoms whose sphere meets the
+// bounding box of those nodes are listed first (the box test can only
+// under-estimate a node's distance, so no node inside a sphere is missed).
+// One partial per workgroup.
+constexpr int EG_NT = 256;
+constexpr int EG_PER = 8;
+constexpr int EG_LIST = 512;
+
+int energy_grid_blocks(const LevelView& L)
+{
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    return (int)((N + (size_t)EG_NT * EG_PER - 1) / ((size_t)EG_NT * EG_PER));
+}
+
+__global__ __launch_bounds__(EG_NT) void k_energy_grid(LevelView L, const double* __restrict__ v,
+                                                       const double* __restrict__ rho, const SphereAtom* __restrict__ atoms,
+                                                       int n_atoms, double* __restrict__ partials)
+{
+    __shared__ int list[EG_LIST];
+    __shared__ int wcount[EG_NT / 64];
+    __shared__ double wsum[EG_NT / 64];
+    __shared__ double box[6];
+    const int b = blockIdx.y;
+    const unsigned nx = L.nx, ny = L.ny, nz = L.nz, plane = nx * ny, N = plane * nz;
+    const unsigned first = blockIdx.x * (unsigned)(EG_NT * EG_PER);
+    const unsigned last = min(first + (unsigned)(EG_NT * EG_PER), N) - 1u;
+    const double* X = L.ax[0].x;
+    const double* Y = L.ax[1].x;
+    const double* Zc = L.ax[2].x;
+    if (threadIdx.x == 0) {
+        const unsigned kf = first / plane, kl = last / plane;
+        const unsigned jf = (first - kf * plane) / nx, jl = (last - kl * plane) / nx;
+        const unsigned i_f = first - kf * plane - jf * nx, il = last - kl * plane - jl * nx;
+        const bool one_plane = kf == kl, one_row = one_plane && jf == jl;
+        box[0] = one_row ? X[i_f] : X[0];
+        box[1] = one_row ? X[il] : X[nx - 1];
+        box[2] = one_plane ? Y[jf] : Y[0];
+        box[3] = one_plane ? Y[jl] : Y[ny - 1];
+        box[4] = Zc[kf];
+        box[5] = Zc[kl];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int count = 0;
+    bool all = false;
+    for (int a0 = 0; a0 < n_atoms; a0 += EG_NT) {
+        const int a = a0 + threadIdx.x;
+        bool hit = false;
+        if (a < n_atoms) {
+            const SphereAtom& A = atoms[a];
+            const double ex = fmax(fmax(box[0] - A.c[0], A.c[0] - box[1]), 0.0);
+            const double ey = fmax(fmax(box[2] - A.c[1], A.c[1] - box[3]), 0.0);
+            const double ez = fmax(fmax(box[4] - A.c[2], A.c[2] - box[5]), 0.0);
+            hit = dist2_exact(ex, ey, ez) < A.R * A.R;
+        }
+        const unsigned long long mask = __ballot(hit);
+        if (lane == 0) wcount[wid] = __popcll(mask);
+        __syncthreads();
+        int off = count;
+        for (int w = 0; w < wid; ++w) off += wcount[w];
+        if (hit && off + __popcll(mask & ((1ull << lane) - 1ull)) < EG_LIST)
+            list[off + __popcll(mask & ((1ull << lane) - 1ull))] = a;
+        for (int w = 0; w < EG_NT / 64; ++w) count += wcount[w];
+        __syncthreads();
+    }
+    if (count > EG_LIST) all = true;
+    const int na = all ? n_atoms : count;
+    const double* vb = v + (size_t)b * N;
+    const double* rb = rho + (size_t)b * N;
+    double vv[EG_PER], rr[EG_PER];
+#pragma unroll
+    for (int s = 0; s < EG_PER; ++s) {
+        const unsigned n = first + threadIdx.x + s * EG_NT;
+        vv[s] = n < N ? vb[n] : 0.0;
+        rr[s] = n < N ? rb[n] : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < EG_PER; ++s) {
+        const unsigned n = first + threadIdx.x + s * EG_NT;
+        if (n >= N) continue;
+        const unsigned k = n / plane, j = (n - k * plane) / nx, i = n - k * plane - j * nx;
+        const double px = X[i], py = Y[j], pz = Zc[k];
+        bool outside = true;
+        for (int t = 0; t < na; ++t) {
+            const SphereAtom& A = atoms[all ? t : list[t]];
+            if (dist2_exact(px - A.c[0], py - A.c[1], pz - A.c[2]) < A.R * A.R) outside = false;
+        }
+        if (outside) acc += L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * vv[s] * rr[s];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+    if (lane == 0) wsum[wid] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < EG_NT / 64; ++w) s += wsum[w];
+        partials[(size_t)b * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+hipError_t launch_energy_grid(lasto_grid g, const double* v, const double* rho, const SphereAtom* atoms, int n_atoms,
+                              double* partials)
+{
+    const LevelView& L = g->cview;
+    hipLaunchKernelGGL(k_energy_grid, dim3(energy_grid_blocks(L), g->n_batch), dim3(EG_NT), 0, g->stream, L, v, rho,
+                       atoms, n_atoms, partials);
+    return hipGetLastError();
+}
+
+// out[b][0] = sum of the grid partials of copy b, out[b][1] = sum over atoms
+// of the sphere parts (fixed orders: strided per thread, then a tree).
+__global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ partials, int nparts,
+                                                      const double* __restrict__ e_atom, int n_atoms,
+                                                      double* __restrict__ out)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nparts; t += 256) s += partials[(size_t)b * nparts + t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int a = 0; a < n_atoms; ++a) e += e_atom[(size_t)b * n_atoms + a];
+        out[2 * b] = red[0];
+        out[2 * b + 1] = e;
+    }
+}
+
+hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_atom, int n_atoms,
+                               double* out)
+{
+    hipLaunchKernelGGL(k_energy_final, dim3(g->n_batch), dim3(256), 0, g->stream, partials, nparts, e_atom, n_atoms,
+                       out);
     return hipGetLastError();
 }
 

@@ -28,6 +28,10 @@ GAUSS_WIDTH = 0.5        # w in exp(-r^2/w^2) of the monopole pseudo-density
 ALPHA = 1.0              # radial factor r^l exp(-alpha r^2) of the l >= 1 terms
 SPHERE_RADIUS = 2.5      # muffin-tin radius used for the interpolation points
 NN_DIST = 5.2            # nearest-neighbour distance of the Pd-like clusters
+PD_Z = 46.0              # nuclear charge of the sphere densities (palladium)
+CORE_ZETA = 46.0         # exponent of their hydrogen-like core, exp(-2 zeta r)
+N_RAD = 429              # radial points per sphere (Section 4)
+R_MIN = 1e-5             # first radial point (bohr)
 
 
 @dataclass
@@ -288,3 +292,33 @@ def atom_arrays(atoms: List[Atom], lmax_pad: int = 4):
         rho_R=np.array([a.rho_R for a in atoms], dtype=np.float64),
         drho_R=np.array([a.drho_R for a in atoms], dtype=np.float64),
     )
+
+
+# ------------------------------------------------------- sphere densities
+def radial_points(R: float, n: int = N_RAD, r_min: float = R_MIN) -> np.ndarray:
+    """Where a sphere's radial density is sampled: r_k = R exp((k - (n-1)) D),
+    D = ln(R / r_min)/(n - 1) (logarithmic, Section 4)."""
+    D = np.log(R / r_min) / (n - 1)
+    return R * np.exp((np.arange(n) - (n - 1)) * D)
+
+
+def sphere_density(atoms: List[Atom], n: int = N_RAD, r_min: float = R_MIN, Z: float = PD_Z,
+                   zeta: float = CORE_ZETA) -> np.ndarray:
+    """Synthetic all-electron density inside each sphere as rho_LM(r_k)
+    [n_atoms][25][n] (real orthonormal y_LM, index L*L + L + M): a
+    hydrogen-like core of Z electrons, Z (zeta^3/pi) exp(-2 zeta r), plus the
+    atom's Gaussian of q electrons (its pseudo-density's monopole) on
+    y_00 = 1/sqrt(4 pi); for L >= 1 the atom's own c_lm r^l exp(-alpha r^2).
+    With a nucleus of charge Z the core is neutral, so the sphere's net
+    monopole is q like the pseudo-density's."""
+    out = np.zeros((len(atoms), 25, n))
+    for a, at in enumerate(atoms):
+        r = radial_points(at.radius, n, r_min)
+        core = Z * zeta ** 3 / np.pi * np.exp(-2.0 * zeta * r)
+        gauss = at.q * (np.pi * at.width ** 2) ** -1.5 * np.exp(-(r / at.width) ** 2)
+        out[a, 0] = np.sqrt(4.0 * np.pi) * (core + gauss)
+        for t in range(len(at.clm)):
+            lm = t + 1
+            l = int(np.sqrt(lm))
+            out[a, lm] = at.clm[t] * r ** l * np.exp(-at.alpha * r * r)
+    return out

@@ -88,8 +88,10 @@ class SolveInfo(C.Structure):
 SYMBOLS = [
     "lasto_status_string", "lasto_last_error", "lasto_mesh_graded_1d", "lasto_grid_create",
     "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
-    "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp", "lasto_apply",
-    "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess", "lasto_net_create", "lasto_net_destroy",
+    "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp",
+    "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_project", "lasto_sphere_radial",
+    "lasto_sphere_energy", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
+    "lasto_net_create", "lasto_net_destroy",
     "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
     "lasto_net_features", "lasto_net_forward", "lasto_net_backward", "lasto_net_adam_step",
     "lasto_net_train_step", "lasto_learned_guess", "lasto_learned_correction", "lasto_net_correction_features",
@@ -144,6 +146,16 @@ def load():
     L.lasto_poisson_solve.restype = i
     L.lasto_sphere_interp.argtypes = [P, P, i, P, P, i, P, P]
     L.lasto_sphere_interp.restype = i
+    L.lasto_spheres_create.argtypes = [P, i, P, P, P, i, i, i, d, C.POINTER(P)]
+    L.lasto_spheres_create.restype = i
+    L.lasto_spheres_destroy.argtypes = [P]
+    L.lasto_spheres_destroy.restype = i
+    L.lasto_sphere_project.argtypes = [P, P, P]
+    L.lasto_sphere_project.restype = i
+    L.lasto_sphere_radial.argtypes = [P, P, P, P]
+    L.lasto_sphere_radial.restype = i
+    L.lasto_sphere_energy.argtypes = [P, P, P, P, P, P]
+    L.lasto_sphere_energy.restype = i
     L.lasto_apply.argtypes = [P, P, P]
     L.lasto_apply.restype = i
     L.lasto_rb_sweep.argtypes = [P, P, P, P, i]
@@ -366,6 +378,60 @@ class Grid:
 
     def learned_correction(self, net: "Net", rho, v):
         return _learned_call(load().lasto_learned_correction, self, net, rho, v)
+
+
+class Spheres:
+    """A set of muffin-tin spheres on a grid: projection of V onto y_LM on
+    each boundary (eq. (3.6)), the interior radial solve (eq. (3.4)) and the
+    energy integral of V rho (Section 4). Arrays carry a leading batch
+    dimension on a batched grid."""
+
+    def __init__(self, grid: Grid, centers, radii, Z=None, n_theta: int = 8, n_phi: int = 9, n_rad: int = 429,
+                 r_min: float = 1e-5):
+        self.grid = grid
+        c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        r = np.ascontiguousarray(radii, dtype=np.float64).ravel()
+        z = None if Z is None else np.ascontiguousarray(Z, dtype=np.float64).ravel()
+        self.n_atoms, self.n_rad = len(c), n_rad
+        h = C.c_void_p()
+        _check(load().lasto_spheres_create(grid.h, len(c), _np_ptr(c), _np_ptr(r), None if z is None else _np_ptr(z),
+                                           n_theta, n_phi, n_rad, r_min, C.byref(h)))
+        self.h = h
+        lead = () if grid.n_batch == 1 else (grid.n_batch,)
+        self.vlm_R_shape = lead + (self.n_atoms, 25)
+        self.radial_shape = lead + (self.n_atoms, 25, n_rad)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lasto_spheres_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def project(self, v, vlm_R=None):
+        import torch
+        if vlm_R is None:
+            vlm_R = torch.empty(self.vlm_R_shape, dtype=torch.float64, device="cuda")
+        _check(load().lasto_sphere_project(self.h, _dev_ptr(v), _dev_ptr(vlm_R)))
+        return vlm_R
+
+    def radial(self, vlm_R, rho_lm, v_lm=None):
+        import torch
+        if v_lm is None:
+            v_lm = torch.empty(self.radial_shape, dtype=torch.float64, device="cuda")
+        _check(load().lasto_sphere_radial(self.h, _dev_ptr(vlm_R), _dev_ptr(rho_lm), _dev_ptr(v_lm)))
+        return v_lm
+
+    def energy(self, v, rho, v_lm, rho_lm) -> np.ndarray:
+        """[grid part, sphere part] of int V rho dV ([n_batch][2] for a batch)."""
+        e = np.zeros((self.grid.n_batch, 2))
+        _check(load().lasto_sphere_energy(self.h, _dev_ptr(v), _dev_ptr(rho), _dev_ptr(v_lm), _dev_ptr(rho_lm),
+                                          _np_ptr(e)))
+        return e[0] if self.grid.n_batch == 1 else e
 
 
 def _learned_call(fn, grid, net, rho, v):
