@@ -1,6 +1,6 @@
 """CPU oracle for the LASTO Hartree step -- TEST INFRASTRUCTURE ONLY.
 
-Plain FP64 C (``oracle.c``, ``sphere.c``) behind ctypes. Only ``tests/``, the smoke check
+Plain FP64 C (``oracle.c``, ``sphere.c``, ``basis.c``) behind ctypes. Only ``tests/``, the smoke check
 and the benchmark's CPU-baseline leg may import this package. The GPU path
 (``paper_0806_1723_amd``) never imports it and shares no code with it.
 
@@ -16,7 +16,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "sphere.c")]
+_SRCS = [os.path.join(_HERE, f) for f in ("oracle.c", "sphere.c", "basis.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PI = np.pi
@@ -76,6 +76,10 @@ def lib():
         L.oracle_sphere_energy.restype = i
         L.oracle_energy_grid.argtypes = [P, i, P, i, P, i, P, P, i, P, P]
         L.oracle_energy_grid.restype = d
+        L.oracle_density_points.argtypes = [i, P, i, P, P, P, i, P, P, i, P, P]
+        L.oracle_density_points.restype = i
+        L.oracle_interstitial_density.argtypes = [P, i, P, i, P, i, i, P, P, i, P, P, P, i, P, P, P]
+        L.oracle_interstitial_density.restype = i
         _lib = L
     return _lib
 
@@ -291,3 +295,43 @@ def energy_grid(xs, v, rho, centers, radii):
     centers = _f64(centers).reshape(-1, 3)
     return lib().oracle_energy_grid(_p(x), len(x), _p(y), len(y), _p(z), len(z), _p(_f64(v)), _p(_f64(rho)),
                                     len(centers), _p(centers), _p(_f64(radii)))
+
+
+# ------------------------------------------------ interstitial output density
+def _shells(shells):
+    n = np.ascontiguousarray([s[0] for s in shells], dtype=np.int32)
+    l = np.ascontiguousarray([s[1] for s in shells], dtype=np.int32)
+    z = _f64([s[2] for s in shells])
+    return n, l, z
+
+
+def density_points(centers, shells, coef, occ, pts):
+    """rho_out = sum_k f_k psi_k^2 at points [npts][3] (basis.c); shells =
+    [(n, l, zeta), ...] on every atom; coef [n_basis][n_occ]."""
+    centers = _f64(centers).reshape(-1, 3)
+    n, l, z = _shells(shells)
+    coef = _f64(coef)
+    occ = _f64(occ)
+    pts = _f64(pts).reshape(-1, 3)
+    out = np.zeros(len(pts))
+    rc = lib().oracle_density_points(len(centers), _p(centers), len(n), _p(n), _p(l), _p(z), len(occ), _p(coef),
+                                     _p(occ), len(pts), _p(pts), _p(out))
+    if rc != 0:
+        raise ValueError("bad shells")
+    return out
+
+
+def interstitial_density(xs, centers, radii, shells, coef, occ):
+    """rho_out on the grid nodes [nz][ny][nx], zero inside the spheres."""
+    x, y, zz = (_f64(a) for a in xs)
+    centers = _f64(centers).reshape(-1, 3)
+    n, l, z = _shells(shells)
+    coef = _f64(coef)
+    occ = _f64(occ)
+    out = np.zeros((len(zz), len(y), len(x)))
+    rc = lib().oracle_interstitial_density(_p(x), len(x), _p(y), len(y), _p(zz), len(zz), len(centers), _p(centers),
+                                           _p(_f64(radii)), len(n), _p(n), _p(l), _p(z), len(occ), _p(coef),
+                                           _p(occ), _p(out))
+    if rc != 0:
+        raise ValueError("bad shells")
+    return out
