@@ -191,6 +191,7 @@ def main():
     }
 
     out["spheres"] = bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii)
+    out["interstitial_density"] = bench_interstitial(args, lasto, I, g, w, xs, centers, radii)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, xs, (rho[0] if nb > 1 else rho).cpu().numpy(), args.cpu_seconds)
@@ -273,6 +274,61 @@ def bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii):
         log("bench: spheres on the oracle: %s" % out["cpu_oracle_ms"])
     S.close()
     return out
+
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def bench_interstitial(args, lasto, I, g, w, xs, centers, radii):
+    """The output density at every node outside the spheres: the Table 1
+    basis (25 functions per atom), 5 doubly occupied states per atom, seeded
+    coefficients. Algorithmic flops 2 * nodes * n_basis * n_states (the
+    contraction) per call, over the event-timed call; the median of the
+    timed repetitions. With the CPU leg on, the oracle's value at a sample of
+    nodes, scaled to the whole grid."""
+    import numpy as np
+    import torch
+    nodes = int(np.prod(g.copy_shape))
+    n_basis = len(radii) * sum(2 * l + 1 for _, l, _ in I.LASTO_SHELLS)
+    if 2.0 * nodes * n_basis * I.STATES_PER_ATOM * len(radii) > 40e12:
+        return {"skipped": "over 40 TFLOP per call at this size"}
+    coef, occ = I.basis_coefficients(len(radii), seed=7)
+    cd = torch.from_numpy(coef).to("cuda")
+    out_t = torch.empty(g.copy_shape, dtype=torch.float64, device="cuda")
+    g.interstitial_density(centers, radii, I.LASTO_SHELLS, cd, occ, rho_out=out_t)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(max(2, min(args.steps, 3))):
+        torch.cuda.synchronize()
+        e0.record()
+        g.interstitial_density(centers, radii, I.LASTO_SHELLS, cd, occ, rho_out=out_t)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = statistics.median(ts)
+    nb, n_occ = coef.shape
+    flops = 2.0 * nodes * nb * n_occ
+    tf = flops / (ms * 1e-3) / 1e12
+    log("bench: interstitial density %.2f ms, %d functions x %d states over %d nodes: %.1f TFLOP/s (%.3f of the "
+        "FP64 matrix peak)" % (ms, nb, n_occ, nodes, tf, tf / FP64_MFMA_PEAK_TFLOPS))
+    res = {"ms": round(ms, 3), "basis": nb, "states": n_occ, "nodes": nodes, "algorithmic_tflop": round(flops / 1e12, 3),
+           "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4),
+                        "kernel": "k_interstitial<10> and <8> (FP64 16x16x4 matrix cores)"}}
+    if not args.no_cpu:
+        import oracle
+        oracle.lib()
+        rng = np.random.default_rng(8)
+        m = 400
+        idx = rng.integers(0, len(xs[0]), size=(m, 3))
+        pts = np.stack([xs[0][idx[:, 0]], xs[1][idx[:, 1]], xs[2][idx[:, 2]]], axis=1)
+        t0 = time.perf_counter()
+        oracle.density_points(centers, I.LASTO_SHELLS, coef, occ, pts)
+        dt = time.perf_counter() - t0
+        res["cpu_oracle_ms"] = {"value": round(dt / m * nodes * 1e3, 1), "cores": 1,
+                                "sample": "%d nodes in %.2f s, scaled to %d nodes" % (m, dt, nodes)}
+        log("bench: interstitial density on the oracle: %s" % res["cpu_oracle_ms"])
+    return res
 
 
 def cpu_baseline(w, xs, rho, min_seconds):

@@ -306,6 +306,39 @@ lasto_status lasto_sphere_radial(lasto_spheres s, const double* vlm_R, const dou
 lasto_status lasto_sphere_energy(lasto_spheres s, const double* v, const double* rho, const double* v_lm,
                                  const double* rho_lm, double* e_out);
 
+/* ------------------------------------------------------------------------
+ * The output density in the interstitial region (Section 3, the density
+ * update after the eigenproblem H c = e S c): at the grid nodes outside every
+ * sphere
+ *   rho_out(x) = sum_k f_k psi_k(x)^2,  psi_k(x) = sum_mu c(mu, k) phi_mu(x),
+ * over the basis of eq. (3.13), phi_(i n l m)(x) = r_i^(n-1) exp(-zeta r_i)
+ * y_lm(r_i / |r_i|), r_i = x - C_i, the same shells on every atom; zero at
+ * nodes inside a sphere (|x - C_i|^2 < R_i^2). The paper sums |psi_k|^2 over
+ * the states below the Fermi level; f_k carries their occupations (2 for a
+ * doubly occupied state). Computed on the FP64 matrix cores (the contraction
+ * of nodes x basis with basis x states), then squared and summed.
+ */
+typedef struct {
+    int n;          /* principal quantum number, l + 1 <= n <= 16 */
+    int l;          /* 0..4; the shell holds 2l + 1 functions, m = -l..l */
+    double zeta;    /* exponent > 0 */
+} lasto_shell;
+
+/*
+ *   centers: host [n_atoms][3]; radii: host [n_atoms] (0: no sphere), or NULL.
+ *   shells: host [n_shells], at most 64 functions per atom; basis function
+ *     index mu = atom * (functions per atom) + (shell offset) + (m + l).
+ *   coef: device [n_basis][n_occ] (a function's coefficients over the states
+ *     contiguous). occ: host [n_occ].
+ *   rho_out: device [nz][ny][nx], one copy of a batched grid per call.
+ * Enqueued on the grid's stream; returns once the small tables are on the
+ * device, without waiting for the result.
+ * Errors: LASTO_ERR_ARG, LASTO_ERR_ALLOC, LASTO_ERR_HIP.
+ */
+lasto_status lasto_interstitial_density(lasto_grid g, int n_atoms, const double* centers, const double* radii,
+                                        int n_shells, const lasto_shell* shells, int n_occ, const double* coef,
+                                        const double* occ, double* rho_out);
+
 /*
  * The discrete operator of eq. (3.2) on the finest level: Au[n] = (A u)_n at
  * interior nodes (the three-point nonuniform second difference per axis, as

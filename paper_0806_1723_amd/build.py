@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblasto.so")
-SOURCES = ["api.hip", "grid.hip", "solve.hip", "mg_kernels.hip", "src_kernels.hip", "sphere.hip", "net.hip",
-           "net_kernels.hip"]
+SOURCES = ["api.hip", "grid.hip", "solve.hip", "mg_kernels.hip", "src_kernels.hip", "sphere.hip", "basis.hip",
+           "net.hip", "net_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

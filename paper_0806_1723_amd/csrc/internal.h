@@ -402,6 +402,11 @@ hipError_t launch_sphere_energy(lasto_grid g, const SphereAtom* atoms, int n_ato
 int energy_grid_blocks(const LevelView& L);   // partials per copy of launch_energy_grid
 hipError_t launch_energy_grid(lasto_grid g, const double* v, const double* rho, const SphereAtom* atoms, int n_atoms,
                               double* partials);
+// interstitial output density: atoms [n][4] (centre, sphere radius), shells
+// [n_shells][4] (n, l, offset within the atom's basis, zeta), coef
+// [n_atoms * nbpa][n_occ], occ [n_occ] (device)
+hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells, int n_shells,
+                               int nbpa, const double* coef, int n_occ, const double* occ, double* rho);
 hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_atom, int n_atoms,
                                double* out);
 

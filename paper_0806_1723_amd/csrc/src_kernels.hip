@@ -7,6 +7,8 @@
 //   k_bc        : multipole field of Q on the six faces (zero: eq. (3.3))
 //   k_interp    : tricubic Lagrange values at the sphere points
 //                 (eq. (3.5)-(3.6) take V_C on the sphere boundaries)
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lasto {
@@ -857,6 +859,156 @@ hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts,
     hipLaunchKernelGGL(k_energy_final, dim3(g->n_batch), dim3(256), 0, g->stream, partials, nparts, e_atom, n_atoms,
                        out);
     return hipGetLastError();
+}
+
+// -------------------------------------------- interstitial output density
+// rho_out(x) = sum_k f_k psi_k(x)^2, psi_k = sum_mu c_(mu,k) phi_mu(x), the
+// Slater-type basis phi = r^(n-1) exp(-zeta r) y_lm = r^(n-1-l) exp(-zeta r)
+// S_lm(x - C) of eq. (3.13), at the nodes outside every sphere (zero inside).
+// psi for 64 nodes x 16 NT states per workgroup is a dense contraction
+// (nodes x basis) . (basis x states) on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: A 16 x 4 from lane (row = lane % 16, k = lane / 16),
+// B 4 x 16 from lane (k = lane / 16, col = lane % 16), D 16 x 16 with lane
+// holding rows 4 (lane / 16) + j, j = 0..3, of column lane % 16). Per atom the
+// workgroup stages that atom's coefficient rows in LDS and each wave writes the
+// basis values of its 16 nodes to LDS; the squares are summed in registers.
+constexpr int ID_NT = 256;
+constexpr int ID_PTS = 64;    // nodes per workgroup, 16 per wave
+
+typedef double dbl4v __attribute__((ext_vector_type(4)));
+
+size_t interstitial_lds_bytes(int nt, int kpa)
+{
+    return sizeof(double) * ((size_t)kpa * 16 * nt + (size_t)(ID_NT / 64) * 16 * kpa);
+}
+
+template <int NT>
+__global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const double4* __restrict__ atoms, int n_atoms,
+                                                        const double4* __restrict__ shells, int n_shells, int nbpa,
+                                                        int kpa, const double* __restrict__ coef, int n_occ, int c0,
+                                                        const double* __restrict__ occ, int accumulate,
+                                                        double* __restrict__ rho)
+{
+    constexpr int NC = 16 * NT;
+    extern __shared__ double id_lds[];
+    double* Bs = id_lds;                          // [kpa][NC] coefficient rows of one atom
+    double* Ph = id_lds + (size_t)kpa * NC;       // [waves][16 nodes][kpa] basis values
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int p16 = lane & 15, grp = lane >> 4;
+    const unsigned nx = L.nx, ny = L.ny, plane = nx * ny, N = plane * L.nz;
+    const unsigned node0 = blockIdx.x * ID_PTS + wid * 16;
+    const unsigned me = min(node0 + p16, N - 1u);
+    const unsigned mk = me / plane, mj = (me - mk * plane) / nx, mi = me - mk * plane - mj * nx;
+    const double px = L.ax[0].x[mi], py = L.ax[1].x[mj], pz = L.ax[2].x[mk];
+    dbl4v acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = dbl4v{0.0, 0.0, 0.0, 0.0};
+    double* ph = Ph + ((size_t)wid * 16 + p16) * kpa;
+    const double* phw = Ph + (size_t)wid * 16 * kpa;
+    for (int a = 0; a < n_atoms; ++a) {
+        __syncthreads();   // the previous atom's products are done with Bs and Ph
+        const double* crow = coef + (size_t)a * nbpa * n_occ;
+        for (int e = threadIdx.x; e < kpa * NC; e += ID_NT) {
+            const int r = e / NC, c = e - r * NC, col = c0 + c;
+            Bs[e] = (r < nbpa && col < n_occ) ? crow[(size_t)r * n_occ + col] : 0.0;
+        }
+        const double4 A = atoms[a];
+        const double dx = px - A.x, dy = py - A.y, dz = pz - A.z;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double S[25];
+        solid_harmonics(dx, dy, dz, 4, S);
+        for (int s = grp; s < n_shells; s += 4) {
+            const double4 sh = shells[s];   // n, l, offset within the atom, zeta
+            const int n = (int)sh.x, l = (int)sh.y, off = (int)sh.z;
+            const double radial = ipow(r, n - 1 - l) * exp(-sh.w * r);
+#pragma unroll
+            for (int ll = 0; ll <= 4; ++ll)
+                if (ll == l) {
+#pragma unroll
+                    for (int m = 0; m <= 2 * ll; ++m) ph[off + m] = radial * S[ll * ll + m];
+                }
+        }
+        if (grp == 0)
+            for (int q = nbpa; q < kpa; ++q) ph[q] = 0.0;
+        __syncthreads();
+        for (int ks = 0; ks < kpa; ks += 4) {
+            const double av = phw[p16 * kpa + ks + grp];
+            const double* brow = Bs + (size_t)(ks + grp) * NC + p16;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[16 * t], acc[t], 0, 0, 0);
+        }
+    }
+    // rows 4 grp + j of this wave's 16 nodes, state c0 + 16 t + p16
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int col = c0 + 16 * t + p16;
+        const double f = col < n_occ ? occ[col] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[j] += f * (acc[t][j] * acc[t][j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        for (int o = 1; o < 16; o <<= 1) part[j] += __shfl_xor(part[j], o);
+    if (p16 < 4) {
+        const int j = p16;
+        const unsigned node = node0 + 4 * grp + j;
+        double val = j == 0 ? part[0] : j == 1 ? part[1] : j == 2 ? part[2] : part[3];
+        if (node < N) {
+            const unsigned k = node / plane, jj = (node - k * plane) / nx, i = node - k * plane - jj * nx;
+            const double qx = L.ax[0].x[i], qy = L.ax[1].x[jj], qz = L.ax[2].x[k];
+            for (int a = 0; a < n_atoms; ++a) {
+                const double4 A = atoms[a];
+                if (dist2_exact(qx - A.x, qy - A.y, qz - A.z) < A.w * A.w) val = 0.0;
+            }
+            rho[node] = accumulate ? rho[node] + val : val;
+        }
+    }
+}
+
+template <int NT>
+static hipError_t launch_interstitial_nt(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells,
+                                         int n_shells, int nbpa, int kpa, const double* coef, int n_occ, int c0,
+                                         const double* occ, int accumulate, double* rho)
+{
+    const LevelView& L = g->cview;
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    const size_t lds = interstitial_lds_bytes(NT, kpa);
+    if (lds > 65536)
+        if (hipError_t e = hipFuncSetAttribute((const void*)k_interstitial<NT>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            e != hipSuccess)
+            return e;
+    hipLaunchKernelGGL(k_interstitial<NT>, dim3((unsigned)((N + ID_PTS - 1) / ID_PTS)), dim3(ID_NT), lds, g->stream, L,
+                       atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, accumulate, rho);
+    return hipGetLastError();
+}
+
+// The states in chunks of at most 160 (10 column tiles per launch, so that
+// three workgroups share a CU's LDS); the first chunk writes rho, the others add.
+hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells, int n_shells,
+                               int nbpa, const double* coef, int n_occ, const double* occ, double* rho)
+{
+    const int kpa = (nbpa + 3) & ~3;
+    for (int c0 = 0; c0 < n_occ || c0 == 0; c0 += 160) {
+        const int tiles = std::min(10, (std::max(n_occ - c0, 1) + 15) / 16);
+        const int acc = c0 > 0;
+        hipError_t e;
+        switch (tiles) {
+        case 1: e = launch_interstitial_nt<1>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
+        case 2: e = launch_interstitial_nt<2>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
+        case 3:
+        case 4: e = launch_interstitial_nt<4>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
+        case 5:
+        case 6: e = launch_interstitial_nt<6>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
+        case 7:
+        case 8: e = launch_interstitial_nt<8>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
+        default: e = launch_interstitial_nt<10>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
+        }
+        if (e != hipSuccess) return e;
+        if (n_occ <= 0) break;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lasto

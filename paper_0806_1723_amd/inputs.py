@@ -32,6 +32,9 @@ PD_Z = 46.0              # nuclear charge of the sphere densities (palladium)
 CORE_ZETA = 46.0         # exponent of their hydrogen-like core, exp(-2 zeta r)
 N_RAD = 429              # radial points per sphere (Section 4)
 R_MIN = 1e-5             # first radial point (bohr)
+# the LASTO basis of Table 1 (n, l, zeta): 4d, 5d, 5s, 5p, 6s, 6p, 4f
+LASTO_SHELLS = [(4, 2, 2.2), (5, 2, 2.6), (5, 0, 1.0), (5, 1, 1.0), (6, 0, 2.0), (6, 1, 2.0), (4, 3, 1.6)]
+STATES_PER_ATOM = 5      # doubly occupied states per atom (10 valence electrons)
 
 
 @dataclass
@@ -322,3 +325,23 @@ def sphere_density(atoms: List[Atom], n: int = N_RAD, r_min: float = R_MIN, Z: f
             l = int(np.sqrt(lm))
             out[a, lm] = at.clm[t] * r ** l * np.exp(-at.alpha * r * r)
     return out
+
+
+# ------------------------------------------------------ basis coefficients
+def basis_coefficients(n_atoms: int, seed: int, shells=None, states_per_atom: int = STATES_PER_ATOM):
+    """Synthetic real coefficients of the occupied states, [n_basis][n_occ],
+    and their occupations (2 each). Each basis function's column of draws
+    N(0, 1/n_basis) is divided by its norm sqrt((2n)!/(2 zeta)^(2n+1)), so
+    every function contributes on a like scale (the paper's basis functions
+    are not normalised)."""
+    from math import factorial
+    shells = LASTO_SHELLS if shells is None else shells
+    rng = np.random.default_rng(seed)
+    scale = []
+    for n, l, z in shells:
+        nrm = np.sqrt(factorial(2 * n) / (2.0 * z) ** (2 * n + 1))
+        scale += [1.0 / nrm] * (2 * l + 1)
+    scale = np.tile(np.array(scale), n_atoms)
+    n_occ = states_per_atom * n_atoms
+    coef = rng.normal(0.0, 1.0 / np.sqrt(len(scale)), size=(len(scale), n_occ)) * scale[:, None]
+    return coef, np.full(n_occ, 2.0)

@@ -39,6 +39,10 @@ class Atom(C.Structure):
     ]
 
 
+class Shell(C.Structure):
+    _fields_ = [("n", C.c_int), ("l", C.c_int), ("zeta", C.c_double)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [
         ("rtol", C.c_double),
@@ -90,7 +94,7 @@ SYMBOLS = [
     "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
     "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp",
     "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_project", "lasto_sphere_radial",
-    "lasto_sphere_energy", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
+    "lasto_sphere_energy", "lasto_interstitial_density", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
     "lasto_net_create", "lasto_net_destroy",
     "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
     "lasto_net_features", "lasto_net_forward", "lasto_net_backward", "lasto_net_adam_step",
@@ -156,6 +160,8 @@ def load():
     L.lasto_sphere_radial.restype = i
     L.lasto_sphere_energy.argtypes = [P, P, P, P, P, P]
     L.lasto_sphere_energy.restype = i
+    L.lasto_interstitial_density.argtypes = [P, i, P, P, i, P, i, P, P, P]
+    L.lasto_interstitial_density.restype = i
     L.lasto_apply.argtypes = [P, P, P]
     L.lasto_apply.restype = i
     L.lasto_rb_sweep.argtypes = [P, P, P, P, i]
@@ -372,6 +378,24 @@ class Grid:
         arr, na = self._atom_table(atoms)
         _check(load().lasto_analytic_guess(self.h, na, C.cast(arr, C.c_void_p), _dev_ptr(v)))
         return v
+
+    def interstitial_density(self, centers, radii, shells, coef, occ, rho_out=None):
+        """rho_out = sum_k f_k psi_k^2 at the nodes outside every sphere (zero
+        inside); shells = [(n, l, zeta), ...] on every atom, coef a device
+        [n_basis][n_occ] float64 tensor, occ host [n_occ]. One copy of the grid."""
+        import torch
+        c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        r = None if radii is None else np.ascontiguousarray(radii, dtype=np.float64).ravel()
+        sh = (Shell * len(shells))()
+        for k, (n, l, z) in enumerate(shells):
+            sh[k].n, sh[k].l, sh[k].zeta = int(n), int(l), float(z)
+        f = np.ascontiguousarray(occ, dtype=np.float64).ravel()
+        if rho_out is None:
+            rho_out = torch.empty(self.copy_shape, dtype=torch.float64, device="cuda")
+        _check(load().lasto_interstitial_density(self.h, len(c), _np_ptr(c), None if r is None else _np_ptr(r),
+                                                 len(shells), C.cast(sh, C.c_void_p), len(f), _dev_ptr(coef),
+                                                 _np_ptr(f), _dev_ptr(rho_out)))
+        return rho_out
 
     def learned_guess(self, net: "Net", rho, v):
         return _learned_call(load().lasto_learned_guess, self, net, rho, v)
