@@ -80,6 +80,10 @@ def lib():
         L.oracle_density_points.restype = i
         L.oracle_interstitial_density.argtypes = [P, i, P, i, P, i, i, P, P, i, P, P, P, i, P, P, P]
         L.oracle_interstitial_density.restype = i
+        L.oracle_basis_points.argtypes = [i, P, i, P, P, P, i, P, P, P, P]
+        L.oracle_basis_points.restype = i
+        L.oracle_matrix_elements.argtypes = [P, i, P, i, P, i, P, i, P, P, i, P, P, P, P, P]
+        L.oracle_matrix_elements.restype = i
         _lib = L
     return _lib
 
@@ -335,3 +339,34 @@ def interstitial_density(xs, centers, radii, shells, coef, occ):
     if rc != 0:
         raise ValueError("bad shells")
     return out
+
+
+def basis_points(centers, shells, pts, vpts=None):
+    """phi and (-1/2 Laplacian + V) phi at points: two [npts][n_basis] arrays."""
+    centers = _f64(centers).reshape(-1, 3)
+    n, l, z = _shells(shells)
+    pts = _f64(pts).reshape(-1, 3)
+    vp = np.zeros(len(pts)) if vpts is None else _f64(vpts).ravel()
+    nb = len(centers) * int(sum(2 * q + 1 for q in l))
+    phi = np.zeros((len(pts), nb))
+    tphi = np.zeros((len(pts), nb))
+    rc = lib().oracle_basis_points(len(centers), _p(centers), len(n), _p(n), _p(l), _p(z), len(pts), _p(pts), _p(vp),
+                                   _p(phi), _p(tphi))
+    if rc != 0:
+        raise ValueError("bad shells")
+    return phi, tphi
+
+
+def matrix_elements(xs, v, centers, radii, shells):
+    """Interstitial S and H by grid quadrature (basis.c): two [n_basis][n_basis]."""
+    x, y, zz = (_f64(a) for a in xs)
+    centers = _f64(centers).reshape(-1, 3)
+    n, l, z = _shells(shells)
+    nb = len(centers) * int(sum(2 * q + 1 for q in l))
+    S = np.zeros((nb, nb))
+    H = np.zeros((nb, nb))
+    rc = lib().oracle_matrix_elements(_p(x), len(x), _p(y), len(y), _p(zz), len(zz), _p(_f64(v)), len(centers),
+                                      _p(centers), _p(_f64(radii)), len(n), _p(n), _p(l), _p(z), _p(S), _p(H))
+    if rc != 0:
+        raise ValueError("bad shells")
+    return S, H
