@@ -340,6 +340,29 @@ lasto_status lasto_interstitial_density(lasto_grid g, int n_atoms, const double*
                                         const double* occ, double* rho_out);
 
 /*
+ * The interstitial parts of the overlap and Hamiltonian matrices by grid
+ * quadrature (Section 3, eq. (3.11)-(3.12) in the nodal form under
+ * eq. (3.14), with the nodes of this grid and their dual volumes vol_P):
+ *   S[mu][nu] = sum_P vol_P phi_mu(P) phi_nu(P),
+ *   H[mu][nu] = 1/2 sum_P vol_P (phi_mu(P) tphi_nu(P) + tphi_mu(P) phi_nu(P)),
+ * over the nodes P outside every sphere, tphi = (-1/2 Laplacian + V) phi with
+ * the kinetic term in closed form, eq. (3.14):
+ *   -1/2 Laplacian phi = 1/2 [(l(l+1) - n(n-1)) r^(n-3) + 2 zeta n r^(n-2)
+ *                             - zeta^2 r^(n-1)] exp(-zeta r) y_lm.
+ * Basis as for lasto_interstitial_density.
+ *   v: device [nz][ny][nx] the potential V at the nodes (one copy).
+ *   centers: host [n_atoms][3]; radii: host [n_atoms], every radius > 0 (the
+ *     kinetic term is singular at a centre, which a sphere must cover).
+ *   S, H: device [n_basis][n_basis] (both triangles written), n_basis <= 32768.
+ * Computed on the FP64 matrix cores in 64 x 64 blocks (upper triangle) over
+ * node chunks, the chunks summed in a fixed order. Allocates its scratch
+ * (a node weight per node, the partial blocks) and waits for the result.
+ * Errors: LASTO_ERR_ARG, LASTO_ERR_ALLOC, LASTO_ERR_HIP.
+ */
+lasto_status lasto_matrix_elements(lasto_grid g, const double* v, int n_atoms, const double* centers,
+                                   const double* radii, int n_shells, const lasto_shell* shells, double* S, double* H);
+
+/*
  * The discrete operator of eq. (3.2) on the finest level: Au[n] = (A u)_n at
  * interior nodes (the three-point nonuniform second difference per axis, as
  * in lasto_poisson_solve); faces of Au are left untouched.

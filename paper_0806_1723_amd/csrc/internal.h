@@ -407,6 +407,14 @@ hipError_t launch_energy_grid(lasto_grid g, const double* v, const double* rho, 
 // [n_atoms * nbpa][n_occ], occ [n_occ] (device)
 hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells, int n_shells,
                                int nbpa, const double* coef, int n_occ, const double* occ, double* rho);
+// interstitial matrix elements: node weights vol * (outside every sphere),
+// then the 64 x 64 blocks (r <= c) of S and H over n_chunks node chunks
+hipError_t launch_node_weights(lasto_grid g, const double4* atoms, int n_atoms, double* w);
+int matrix_block_count(int n_basis);
+size_t matrix_partial_doubles(int n_pairs, int n_chunks);
+hipError_t launch_matrix_elements(lasto_grid g, const double* w, const double* v, const double4* atoms, int n_atoms,
+                                  const double4* shells, int n_shells, int nbpa, int n_basis, const int2* pairs,
+                                  int n_pairs, int n_chunks, double* partials, double* S, double* H);
 hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_atom, int n_atoms,
                                double* out);
 

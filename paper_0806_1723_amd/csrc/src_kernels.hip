@@ -1011,4 +1011,224 @@ hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, 
     return hipSuccess;
 }
 
+// ------------------------------------------ interstitial matrix elements
+// S[mu][nu] = sum_P w_P phi_mu phi_nu, H[mu][nu] = 1/2 sum_P w_P (phi_mu tphi_nu
+// + tphi_mu phi_nu), w_P = vol_P at nodes outside every sphere (0 inside),
+// tphi = (-1/2 Laplacian + V) phi with the kinetic term in closed form
+// (eq. (3.14)). A workgroup owns one 64 x 64 block (rows r0.., columns c0..,
+// r0 <= c0) and one chunk of nodes; per batch of 32 nodes it writes w phi and
+// w tphi of its rows and phi and tphi of its columns to LDS (one task per
+// (node, atom) evaluates that atom's harmonics once), then each wave runs
+// its 2 x 2 tiles of 16 x 16 through v_mfma_f64_16x16x4f64 (S: one product;
+// H: two into one accumulator). One partial block per workgroup, summed over
+// the chunks in a fixed order afterwards.
+constexpr int ME_NT = 256;
+constexpr int ME_B = 64;     // block of basis functions
+constexpr int ME_K = 32;     // nodes per batch
+constexpr int ME_LD = ME_B + 1;   // padded LDS row (doubles)
+
+__global__ __launch_bounds__(256) void k_node_weights(LevelView L, const double4* __restrict__ atoms, int n_atoms,
+                                                      double* __restrict__ w)
+{
+    const unsigned nx = L.nx, ny = L.ny, plane = nx * ny, N = plane * L.nz;
+    const unsigned node = blockIdx.x * 256u + threadIdx.x;
+    if (node >= N) return;
+    const unsigned k = node / plane, j = (node - k * plane) / nx, i = node - k * plane - j * nx;
+    const double px = L.ax[0].x[i], py = L.ax[1].x[j], pz = L.ax[2].x[k];
+    bool outside = true;
+    for (int a = 0; a < n_atoms; ++a) {
+        const double4 A = atoms[a];
+        if (dist2_exact(px - A.x, py - A.y, pz - A.z) < A.w * A.w) outside = false;
+    }
+    w[node] = outside ? L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] : 0.0;
+}
+
+hipError_t launch_node_weights(lasto_grid g, const double4* atoms, int n_atoms, double* w)
+{
+    const LevelView& L = g->cview;
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_node_weights, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, g->stream, L, atoms, n_atoms, w);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double rpow(double r, int e)
+{
+    return e >= 0 ? ipow(r, e) : 1.0 / ipow(r, -e);
+}
+
+// -1/2 Laplacian of r^(n-1) exp(-zeta r) y_lm, over S_lm = r^l y_lm (eq. (3.14)):
+// 1/2 [(l(l+1) - n(n-1)) r^(n-3-l) + 2 zeta n r^(n-2-l) - zeta^2 r^(n-1-l)] e;
+// the first term vanishes for n = l + 1, so no power below -1 appears
+__device__ __forceinline__ double kinetic_radial(int n, int l, double zeta, double r, double e)
+{
+    double t = -zeta * zeta * rpow(r, n - 1 - l) + 2.0 * zeta * n * rpow(r, n - 2 - l);
+    if (n != l + 1) t += (double)(l * (l + 1) - n * (n - 1)) * rpow(r, n - 3 - l);
+    return 0.5 * t * e;
+}
+
+__global__ __launch_bounds__(ME_NT) void k_matrix_elements(LevelView L, const double* __restrict__ w,
+                                                           const double* __restrict__ v,
+                                                           const double4* __restrict__ atoms, int n_atoms,
+                                                           const double4* __restrict__ shells, int n_shells, int nbpa,
+                                                           int n_basis, const int2* __restrict__ pairs, int n_chunks,
+                                                           unsigned chunk_nodes, double* __restrict__ partials)
+{
+    __shared__ double WPR[ME_K * ME_LD], WTR[ME_K * ME_LD], PC[ME_K * ME_LD], TC[ME_K * ME_LD];
+    const int pair = blockIdx.x / n_chunks, chunk = blockIdx.x - pair * n_chunks;
+    const int r0 = pairs[pair].x * ME_B, c0 = pairs[pair].y * ME_B;
+    const unsigned nx = L.nx, ny = L.ny, plane = nx * ny, N = plane * L.nz;
+    const unsigned n_begin = chunk * chunk_nodes, n_end = min(N, n_begin + chunk_nodes);
+    // atoms touching the row and the column block
+    const int ra0 = r0 / nbpa, ra1 = min(n_atoms - 1, (r0 + ME_B - 1) / nbpa);
+    const int ca0 = c0 / nbpa, ca1 = min(n_atoms - 1, (c0 + ME_B - 1) / nbpa);
+    const int nra = ra1 - ra0 + 1, nta = nra + (ca1 - ca0 + 1);
+    for (int e = threadIdx.x; e < ME_K * ME_LD; e += ME_NT) {
+        WPR[e] = 0.0;
+        WTR[e] = 0.0;
+        PC[e] = 0.0;
+        TC[e] = 0.0;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int p16 = lane & 15, grp = lane >> 4;
+    const int wr = (wid >> 1) * 32, wc = (wid & 1) * 32;   // this wave's 32 x 32 quarter
+    dbl4v accS[2][2], accH[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            accS[a][b] = dbl4v{0.0, 0.0, 0.0, 0.0};
+            accH[a][b] = dbl4v{0.0, 0.0, 0.0, 0.0};
+        }
+    for (unsigned base = n_begin; base < n_end; base += ME_K) {
+        __syncthreads();   // the previous batch's products are done with the tables
+        for (int task = threadIdx.x; task < ME_K * nta; task += ME_NT) {
+            const int t = task % ME_K, ti = task / ME_K;
+            const bool row = ti < nra;
+            const int a = row ? ra0 + ti : ca0 + (ti - nra);
+            const int lo = row ? r0 : c0;
+            const unsigned node = min(base + t, N - 1u);
+            const double wt = base + t < n_end ? w[node] : 0.0;
+            double* P1 = row ? WPR : PC;
+            double* P2 = row ? WTR : TC;
+            const unsigned k = node / plane, j = (node - k * plane) / nx, i = node - k * plane - j * nx;
+            const double4 A = atoms[a];
+            const double dx = L.ax[0].x[i] - A.x, dy = L.ax[1].x[j] - A.y, dz = L.ax[2].x[k] - A.z;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double vp = v[node];
+            double S[25];
+            solid_harmonics(dx, dy, dz, 4, S);
+            for (int s = 0; s < n_shells; ++s) {
+                const double4 sh = shells[s];
+                const int n = (int)sh.x, l = (int)sh.y;
+                const int mu0 = a * nbpa + (int)sh.z;
+                if (mu0 + 2 * l < lo || mu0 >= lo + ME_B) continue;
+                // nodes of zero weight (inside a sphere, past the chunk) get zeros
+                // on both sides, so no singular column value meets a zero weight
+                double phr = 0.0, kr = 0.0;
+                if (wt != 0.0) {
+                    const double e = exp(-sh.w * r);
+                    phr = ipow(r, n - 1 - l) * e;
+                    kr = kinetic_radial(n, l, sh.w, r, e);
+                }
+                const double f = row ? wt : 1.0;
+#pragma unroll
+                for (int ll = 0; ll <= 4; ++ll)
+                    if (ll == l) {
+#pragma unroll
+                        for (int m = 0; m <= 2 * ll; ++m) {
+                            const int col = mu0 + m - lo;
+                            if (col >= 0 && col < ME_B) {
+                                const double ph = phr * S[ll * ll + m];
+                                P1[t * ME_LD + col] = wt != 0.0 ? f * ph : 0.0;
+                                P2[t * ME_LD + col] = wt != 0.0 ? f * (kr * S[ll * ll + m] + vp * ph) : 0.0;
+                            }
+                        }
+                    }
+            }
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int ks = 0; ks < ME_K; ks += 4) {
+            const int kn = ks + grp;
+            double aP[2], aT[2], bP[2], bT[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                aP[q] = WPR[kn * ME_LD + wr + 16 * q + p16];
+                aT[q] = WTR[kn * ME_LD + wr + 16 * q + p16];
+                bP[q] = PC[kn * ME_LD + wc + 16 * q + p16];
+                bT[q] = TC[kn * ME_LD + wc + 16 * q + p16];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    accS[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aP[a], bP[b], accS[a][b], 0, 0, 0);
+                    accH[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aP[a], bT[b], accH[a][b], 0, 0, 0);
+                    accH[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aT[a], bP[b], accH[a][b], 0, 0, 0);
+                }
+        }
+    }
+    // partial block: [2][64][64] (S, then H), row-major
+    double* out = partials + (size_t)blockIdx.x * 2 * ME_B * ME_B;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int rr = wr + 16 * a + 4 * grp + j, cc = wc + 16 * b + p16;
+                out[rr * ME_B + cc] = accS[a][b][j];
+                out[ME_B * ME_B + rr * ME_B + cc] = 0.5 * accH[a][b][j];
+            }
+}
+
+// S and H [n_basis][n_basis] (both triangles) from the partial blocks
+__global__ __launch_bounds__(256) void k_matrix_reduce(const double* __restrict__ partials, const int2* __restrict__ pairs,
+                                                       int n_chunks, int n_basis, double* __restrict__ S,
+                                                       double* __restrict__ H)
+{
+    const int pair = blockIdx.x;
+    const int r0 = pairs[pair].x * ME_B, c0 = pairs[pair].y * ME_B;
+    for (int e = threadIdx.x; e < ME_B * ME_B; e += 256) {
+        const int rr = e / ME_B, cc = e - rr * ME_B;
+        const int mu = r0 + rr, nu = c0 + cc;
+        if (mu >= n_basis || nu >= n_basis || (r0 == c0 && rr > cc)) continue;   // a diagonal block: its upper half
+        double s = 0.0, h = 0.0;
+        for (int c = 0; c < n_chunks; ++c) {
+            const double* p = partials + ((size_t)pair * n_chunks + c) * 2 * ME_B * ME_B;
+            s += p[e];
+            h += p[ME_B * ME_B + e];
+        }
+        S[(size_t)mu * n_basis + nu] = s;
+        S[(size_t)nu * n_basis + mu] = s;
+        H[(size_t)mu * n_basis + nu] = h;
+        H[(size_t)nu * n_basis + mu] = h;
+    }
+}
+
+int matrix_block_count(int n_basis)
+{
+    const int nblk = (n_basis + ME_B - 1) / ME_B;
+    return nblk * (nblk + 1) / 2;
+}
+
+size_t matrix_partial_doubles(int n_pairs, int n_chunks)
+{
+    return (size_t)n_pairs * n_chunks * 2 * ME_B * ME_B;
+}
+
+hipError_t launch_matrix_elements(lasto_grid g, const double* w, const double* v, const double4* atoms, int n_atoms,
+                                  const double4* shells, int n_shells, int nbpa, int n_basis, const int2* pairs,
+                                  int n_pairs, int n_chunks, double* partials, double* S, double* H)
+{
+    const LevelView& L = g->cview;
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    const unsigned chunk = (unsigned)((N + n_chunks - 1) / n_chunks);
+    hipLaunchKernelGGL(k_matrix_elements, dim3((unsigned)(n_pairs * n_chunks)), dim3(ME_NT), 0, g->stream, L, w, v,
+                       atoms, n_atoms, shells, n_shells, nbpa, n_basis, pairs, n_chunks, chunk, partials);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_matrix_reduce, dim3(n_pairs), dim3(256), 0, g->stream, partials, pairs, n_chunks, n_basis, S, H);
+    return hipGetLastError();
+}
+
 }  // namespace lasto

@@ -94,7 +94,7 @@ SYMBOLS = [
     "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
     "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp",
     "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_project", "lasto_sphere_radial",
-    "lasto_sphere_energy", "lasto_interstitial_density", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
+    "lasto_sphere_energy", "lasto_interstitial_density", "lasto_matrix_elements", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
     "lasto_net_create", "lasto_net_destroy",
     "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
     "lasto_net_features", "lasto_net_forward", "lasto_net_backward", "lasto_net_adam_step",
@@ -162,6 +162,8 @@ def load():
     L.lasto_sphere_energy.restype = i
     L.lasto_interstitial_density.argtypes = [P, i, P, P, i, P, i, P, P, P]
     L.lasto_interstitial_density.restype = i
+    L.lasto_matrix_elements.argtypes = [P, P, i, P, P, i, P, P, P]
+    L.lasto_matrix_elements.restype = i
     L.lasto_apply.argtypes = [P, P, P]
     L.lasto_apply.restype = i
     L.lasto_rb_sweep.argtypes = [P, P, P, P, i]
@@ -396,6 +398,22 @@ class Grid:
                                                  len(shells), C.cast(sh, C.c_void_p), len(f), _dev_ptr(coef),
                                                  _np_ptr(f), _dev_ptr(rho_out)))
         return rho_out
+
+    def matrix_elements(self, v, centers, radii, shells):
+        """Interstitial S and H (device [n_basis][n_basis] float64 tensors) by
+        grid quadrature at the nodes outside every sphere, potential v."""
+        import torch
+        c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        r = np.ascontiguousarray(radii, dtype=np.float64).ravel()
+        sh = (Shell * len(shells))()
+        for k, (n, l, z) in enumerate(shells):
+            sh[k].n, sh[k].l, sh[k].zeta = int(n), int(l), float(z)
+        nb = len(c) * sum(2 * int(l) + 1 for _, l, _ in shells)
+        S = torch.empty((nb, nb), dtype=torch.float64, device="cuda")
+        H = torch.empty((nb, nb), dtype=torch.float64, device="cuda")
+        _check(load().lasto_matrix_elements(self.h, _dev_ptr(v), len(c), _np_ptr(c), _np_ptr(r), len(shells),
+                                            C.cast(sh, C.c_void_p), _dev_ptr(S), _dev_ptr(H)))
+        return S, H
 
     def learned_guess(self, net: "Net", rho, v):
         return _learned_call(load().lasto_learned_guess, self, net, rho, v)
