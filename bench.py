@@ -213,7 +213,8 @@ def bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii):
     import torch
     nb = g.n_batch
     atoms_b = w.batch_atoms if nb > 1 else [w.atoms]
-    rho_lm = np.stack([I.sphere_density(a) for a in atoms_b])
+    radii = I.muffin_tin_radii(w.atoms)
+    rho_lm = np.stack([I.sphere_density(a, radii=radii) for a in atoms_b])
     if nb == 1:
         rho_lm = rho_lm[0]
     Z = np.full(len(radii), I.PD_Z)

@@ -869,7 +869,8 @@ hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts,
 // (nodes x basis) . (basis x states) on the FP64 matrix cores
 // (v_mfma_f64_16x16x4: A 16 x 4 from lane (row = lane % 16, k = lane / 16),
 // B 4 x 16 from lane (k = lane / 16, col = lane % 16), D 16 x 16 with lane
-// holding rows 4 (lane / 16) + j, j = 0..3, of column lane % 16). Per atom the
+// holding rows lane / 16 + 4 j, j = 0..3, of column lane % 16, as measured on
+// gfx950). Per atom the
 // workgroup stages that atom's coefficient rows in LDS and each wave writes the
 // basis values of its 16 nodes to LDS; the squares are summed in registers.
 constexpr int ID_NT = 256;
@@ -938,7 +939,7 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
             for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[16 * t], acc[t], 0, 0, 0);
         }
     }
-    // rows 4 grp + j of this wave's 16 nodes, state c0 + 16 t + p16
+    // rows grp + 4 j of this wave's 16 nodes, state c0 + 16 t + p16
     double part[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -952,7 +953,7 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
         for (int o = 1; o < 16; o <<= 1) part[j] += __shfl_xor(part[j], o);
     if (p16 < 4) {
         const int j = p16;
-        const unsigned node = node0 + 4 * grp + j;
+        const unsigned node = node0 + grp + 4 * j;
         double val = j == 0 ? part[0] : j == 1 ? part[1] : j == 2 ? part[2] : part[3];
         if (node < N) {
             const unsigned k = node / plane, jj = (node - k * plane) / nx, i = node - k * plane - jj * nx;
@@ -1176,7 +1177,7 @@ __global__ __launch_bounds__(ME_NT) void k_matrix_elements(LevelView L, const do
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int rr = wr + 16 * a + 4 * grp + j, cc = wc + 16 * b + p16;
+                const int rr = wr + 16 * a + grp + 4 * j, cc = wc + 16 * b + p16;
                 out[rr * ME_B + cc] = accS[a][b][j];
                 out[ME_B * ME_B + rr * ME_B + cc] = 0.5 * accH[a][b][j];
             }

@@ -305,18 +305,32 @@ def radial_points(R: float, n: int = N_RAD, r_min: float = R_MIN) -> np.ndarray:
     return R * np.exp((np.arange(n) - (n - 1)) * D)
 
 
+def muffin_tin_radii(atoms: List[Atom]) -> np.ndarray:
+    """Sphere radii for the interior solve: each atom's radius, cut to just
+    under half its nearest-neighbour distance so that no two spheres overlap
+    (the jittered clusters bring some pairs below 2 x 2.5 bohr)."""
+    c = np.array([a.center for a in atoms], dtype=np.float64).reshape(-1, 3)
+    R = np.array([a.radius for a in atoms], dtype=np.float64)
+    if len(c) > 1:
+        d = np.sqrt(((c[:, None, :] - c[None, :, :]) ** 2).sum(-1))
+        np.fill_diagonal(d, np.inf)
+        R = np.minimum(R, 0.5 * d.min(axis=1) * (1.0 - 1e-9))
+    return R
+
+
 def sphere_density(atoms: List[Atom], n: int = N_RAD, r_min: float = R_MIN, Z: float = PD_Z,
-                   zeta: float = CORE_ZETA) -> np.ndarray:
+                   zeta: float = CORE_ZETA, radii=None) -> np.ndarray:
     """Synthetic all-electron density inside each sphere as rho_LM(r_k)
     [n_atoms][25][n] (real orthonormal y_LM, index L*L + L + M): a
     hydrogen-like core of Z electrons, Z (zeta^3/pi) exp(-2 zeta r), plus the
     atom's Gaussian of q electrons (its pseudo-density's monopole) on
     y_00 = 1/sqrt(4 pi); for L >= 1 the atom's own c_lm r^l exp(-alpha r^2).
     With a nucleus of charge Z the core is neutral, so the sphere's net
-    monopole is q like the pseudo-density's."""
+    monopole is q like the pseudo-density's. radii: the spheres' radii
+    (default each atom's own)."""
     out = np.zeros((len(atoms), 25, n))
     for a, at in enumerate(atoms):
-        r = radial_points(at.radius, n, r_min)
+        r = radial_points(at.radius if radii is None else radii[a], n, r_min)
         core = Z * zeta ** 3 / np.pi * np.exp(-2.0 * zeta * r)
         gauss = at.q * (np.pi * at.width ** 2) ** -1.5 * np.exp(-(r / at.width) ** 2)
         out[a, 0] = np.sqrt(4.0 * np.pi) * (core + gauss)

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -294,6 +295,10 @@ class Grid:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone; the process
+        # releases the device memory itself
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -449,6 +454,10 @@ class Spheres:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone; the process
+        # releases the device memory itself
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -514,6 +523,10 @@ class Net:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone; the process
+        # releases the device memory itself
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

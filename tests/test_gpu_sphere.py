@@ -258,9 +258,10 @@ def test_full_size_257_energy_and_spheres(torch, L, oracle_mod):
     v = smooth_field(xs, rng) * 10.0
     rho = smooth_field(xs, rng)
     A = I.atom_arrays(w.atoms)
-    c, r = A["centers"], A["radius"]
+    c, r = A["centers"], I.muffin_tin_radii(w.atoms)
+    assert r.min() > 2.4
     Z = np.full(len(r), I.PD_Z)
-    rho_lm = I.sphere_density(w.atoms)
+    rho_lm = I.sphere_density(w.atoms, radii=r)
     g = L.Grid(*xs)
     S = L.Spheres(g, c, r, Z=Z)
     rl = dev(torch, rho_lm)
@@ -274,11 +275,17 @@ def test_full_size_257_energy_and_spheres(torch, L, oracle_mod):
     wR = oracle_mod.sphere_project(vals, 8, 9)
     assert np.abs(vR - wR).max() <= 1e-13 * np.abs(vals).max()
     wl = oracle_mod.sphere_radial(r, Z, I.R_MIN, wR, rho_lm)
-    assert (np.abs(v_lm - wl) / np.abs(wl).max(axis=2, keepdims=True)).max() <= 1e-12
+    # the radial stage on identical Dirichlet data (rows whose only source
+    # is V_LM(R) (r/R)^L inherit the projection's last-digit differences)
+    v_lm_o = S.radial(dev(torch, wR), rl).cpu().numpy()
+    assert (np.abs(v_lm_o - wl) / np.abs(wl).max(axis=2, keepdims=True)).max() <= 1e-12
+    assert np.abs(v_lm - wl).max() <= 1e-12 * np.abs(wl).max()
     eg = oracle_mod.energy_grid(xs, v, rho, c, r)
     tg = oracle_mod.energy_grid(xs, np.abs(v), np.abs(rho), c, r)
     say("  grid part %.15e vs oracle %.15e" % (e[0], eg))
-    assert abs(e[0] - eg) <= 1e-13 * tg
+    # the oracle adds 17 M terms one after another: its rounding walks like
+    # sqrt(N) 2^-53 of the sum of |terms| (4.6e-13 here); 20 times that
+    assert abs(e[0] - eg) <= 20 * np.sqrt(v.size) * 2.0 ** -53 * tg
     es = oracle_mod.sphere_energy(r, I.R_MIN, wl, rho_lm).sum()
     ts = oracle_mod.sphere_energy(r, I.R_MIN, np.abs(wl), np.abs(rho_lm)).sum()
     say("  sphere part %.15e vs oracle %.15e" % (e[1], es))
