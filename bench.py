@@ -192,6 +192,7 @@ def main():
 
     out["spheres"] = bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii)
     out["interstitial_density"] = bench_interstitial(args, lasto, I, g, w, xs, centers, radii)
+    out["matrix_elements"] = bench_matrix_elements(args, lasto, I)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, xs, (rho[0] if nb > 1 else rho).cpu().numpy(), args.cpu_seconds)
@@ -330,6 +331,46 @@ def bench_interstitial(args, lasto, I, g, w, xs, centers, radii):
                                 "sample": "%d nodes in %.2f s, scaled to %d nodes" % (m, dt, nodes)}
         log("bench: interstitial density on the oracle: %s" % res["cpu_oracle_ms"])
     return res
+
+
+def bench_matrix_elements(args, lasto, I):
+    """The interstitial S and H of the 13-atom icosahedron at 129^3 (2.1 M
+    nodes; the 55-atom 257^3 case is 100 TFLOP) with the Table 1 basis (325
+    functions) and a smooth potential: event-timed calls, the median.
+    Algorithmic flops: 3 products x 2 flops per node per entry of the upper
+    triangle (diagonal included), as the kernel forms them."""
+    import numpy as np
+    import torch
+    w = I.config(2)
+    xs = lasto.mesh_for(w.axes)
+    g = lasto.Grid(*xs)
+    c = np.array([a.center for a in w.atoms])
+    r = np.array([a.radius for a in w.atoms])
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    v = torch.from_numpy(-3.0 / np.sqrt(1.0 + X * X + Y * Y + Z * Z)).to("cuda")
+    g.matrix_elements(v, c, r, I.LASTO_SHELLS)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        e0.record()
+        g.matrix_elements(v, c, r, I.LASTO_SHELLS)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = statistics.median(ts)
+    nodes = int(np.prod(g.copy_shape))
+    nb = len(c) * sum(2 * l + 1 for _, l, _ in I.LASTO_SHELLS)
+    flops = 3 * 2.0 * nodes * nb * (nb + 1) / 2
+    tf = flops / (ms * 1e-3) / 1e12
+    log("bench: interstitial S and H, %s, %d functions: %.2f ms, %.1f TFLOP/s (%.3f of the FP64 matrix peak)"
+        % (w.name, nb, ms, tf, tf / FP64_MFMA_PEAK_TFLOPS))
+    g.close()
+    return {"workload": w.name, "basis": nb, "nodes": nodes, "ms": round(ms, 3),
+            "algorithmic_tflop": round(flops / 1e12, 3),
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4),
+                         "kernel": "k_matrix_elements (FP64 16x16x4 matrix cores), with its weights and reduce"}}
 
 
 def cpu_baseline(w, xs, rho, min_seconds):
