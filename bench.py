@@ -148,6 +148,18 @@ def main():
     log("bench: fp64 solve %.3f ms, iters %d, smoother %.1f GB/s (avg %.1f us)"
         % (fp64_ms, fp64[-1]["iters"], fp64_gbs, f_ms * 1e3 / max(f_l, 1)))
 
+    # the direct solve by fast diagonalisation on the same problem (six FP64
+    # GEMMs along the axes; the first call builds the 1-D decompositions)
+    fdm = []
+    for _ in range(max(3, args.steps)):
+        v.zero_()
+        fdm.append(g.fdm_solve(rho, v))
+    fdm_ms = statistics.median(i["ms_total"] for i in fdm[1:])
+    m3 = [len(x) - 2 for x in xs]
+    fdm_flops = 4.0 * nb * float(np.prod(m3)) * sum(m3)
+    log("bench: fdm direct solve %.3f ms (first call %.1f ms), rel %.2e, %.1f TFLOP/s in its GEMMs' flops over the "
+        "whole call" % (fdm_ms, fdm[0]["ms_total"], fdm[-1]["rel_resid"], fdm_flops / (fdm_ms * 1e-3) / 1e12))
+
     # algorithmic bytes of one launch (a half-sweep), per interior node of the
     # grid: 12 B (FP64) or 6 B (FP32) for a half-sweep that reads the other
     # colour, f and writes its own colour (24 / 12 B per full sweep)
@@ -181,6 +193,9 @@ def main():
         "fp64_iters": fp64[-1]["iters"],
         "fp64_smoother_gbs": round(fp64_gbs, 1),
         "fp64_smoother_frac": round(fp64_gbs / HBM_PEAK_GBS, 4),
+        "fdm_direct_solve": {"ms": round(fdm_ms, 4), "first_call_ms": round(fdm[0]["ms_total"], 2),
+                             "rel_resid": fdm[-1]["rel_resid"], "gemm_tflop": round(fdm_flops / 1e12, 4),
+                             "note": "fast diagonalisation (six FP64 GEMMs), beside the multigrid headline"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": round(sm_bytes / launches) if launches else 0,

@@ -363,6 +363,35 @@ lasto_status lasto_matrix_elements(lasto_grid g, const double* v, int n_atoms, c
                                    const double* radii, int n_shells, const lasto_shell* shells, double* S, double* H);
 
 /*
+ * A direct solve of the discrete eq. (3.2) by fast diagonalisation (Lynch,
+ * Rice and Thomas, 1964), beside the multigrid of lasto_poisson_solve: the
+ * 7-point operator on a tensor-product mesh is the Kronecker sum of three
+ * 1-D operators A_d = M_d^-1 T_d, each diagonalised once per grid as
+ * S_d L_d S_d^-1 (S_d = M_d^-1/2 Q_d from the symmetric tridiagonal
+ * M_d^-1/2 T_d M_d^-1/2 = Q_d L_d Q_d^T), so that the interior solution is
+ *   u = (S_z x S_y x S_x) [ (S_z^-1 x S_y^-1 x S_x^-1) b / (l_z + l_y + l_x) ],
+ * b = 4 pi rho - A v_bc: six dense contractions along the axes on the FP64
+ * matrix cores (rocBLAS GEMMs). Exact up to rounding; no iteration.
+ *   rho, v: as lasto_poisson_solve (v's faces are set from bc/lmax_bc, its
+ *     interior overwritten; a batched grid solves every copy).
+ *   info (may be NULL): iters = 1, rel_resid = max over copies of
+ *     ||4 pi rho - A v||_W / ||4 pi rho - A v_bc||_W, batch_rel_resid, moments,
+ *     ms_total.
+ * The first call on a grid builds the 1-D decompositions on the host (O(n^3)
+ * per axis) and allocates two work arrays of the interior's size, kept until
+ * lasto_grid_destroy. Waits for the result.
+ * Errors: LASTO_ERR_ARG, LASTO_ERR_ALLOC, LASTO_ERR_HIP, LASTO_ERR_STATE (no
+ * convergence of a 1-D decomposition), LASTO_ERR_DIVERGED (non-finite result).
+ */
+lasto_status lasto_fdm_solve(lasto_grid g, const double* rho, double* v, int bc, int lmax_bc,
+                             lasto_solve_info* info);
+/* The 1-D decomposition on its own (host only, no device work): for
+ * coordinates x[0..n-1] (increasing, n >= 3) and the interior operator
+ * (A u)_i = am_i (u_(i-1) - u_i) + ap_i (u_(i+1) - u_i), i = 1..n-2, fills
+ * lam[n-2] and S, Sinv [n-2][n-2] (row-major) with A = S diag(lam) Sinv. */
+lasto_status lasto_fdm_axis(const double* x, int n, double* lam, double* S, double* Sinv);
+
+/*
  * The discrete operator of eq. (3.2) on the finest level: Au[n] = (A u)_n at
  * interior nodes (the three-point nonuniform second difference per axis, as
  * in lasto_poisson_solve); faces of Au are left untouched.

@@ -1,0 +1,333 @@
+// Fast diagonalisation: a direct solve of the discrete eq. (3.2) on the
+// tensor-product mesh.
+//
+// The 7-point operator is a Kronecker sum A = A_z (+) A_y (+) A_x of 1-D
+// three-point operators A_d = M_d^-1 T_d (T_d symmetric tridiagonal with
+// off-diagonals 1/h, M_d the dual widths). Each A_d = S_d L_d S_d^-1 with
+// S_d = M_d^-1/2 Q_d, S_d^-1 = Q_d^T M_d^1/2, where Q_d L_d Q_d^T is the
+// eigen-decomposition of the symmetric M_d^-1/2 T_d M_d^-1/2. The interior
+// solution of A u = b is then
+//   u = (S_z x S_y x S_x) [ (S_z^-1 x S_y^-1 x S_x^-1) b / (l_z + l_y + l_x) ],
+// three dense contractions along the axes, a division, three more: about
+// 12 n^4 flops on the FP64 matrix cores (rocBLAS GEMMs) where a multigrid
+// cycle is bandwidth-bound, and exact up to rounding. b is the residual of
+// the face data, 4 pi rho - A v_bc; the result fills the interior of v.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace lasto {
+
+struct FdmState {
+    int m[3] = {0, 0, 0};                          // interior nodes per axis (one copy)
+    double* S[3] = {nullptr, nullptr, nullptr};    // device [m][m] row-major
+    double* Si[3] = {nullptr, nullptr, nullptr};   // device inverses
+    double* lam[3] = {nullptr, nullptr, nullptr};  // device eigenvalues
+    double* buf[2] = {nullptr, nullptr};           // device [mz][my][mx]
+    rocblas_handle blas = nullptr;
+};
+
+void free_fdm(lasto_grid g)
+{
+    FdmState* f = g->fdm;
+    if (!f) return;
+    for (int d = 0; d < 3; ++d) {
+        (void)hipFree(f->S[d]);
+        (void)hipFree(f->Si[d]);
+        (void)hipFree(f->lam[d]);
+    }
+    (void)hipFree(f->buf[0]);
+    (void)hipFree(f->buf[1]);
+    if (f->blas) (void)rocblas_destroy_handle(f->blas);
+    delete f;
+    g->fdm = nullptr;
+}
+
+// Eigen-decomposition of a symmetric tridiagonal matrix (diagonal d[0..n-1],
+// off-diagonal e[i] between i and i+1) by the QL algorithm with implicit
+// Wilkinson shifts (Bowdler, Martin, Reinsch and Wilkinson, 1968). z starts
+// as the identity and accumulates the rotations: column k of z (z[i * n + k])
+// is the eigenvector of eigenvalue d[k]. Returns false if an eigenvalue takes
+// more than 60 sweeps.
+static bool tridiagonal_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& z)
+{
+    e.resize(n);
+    e[n - 1] = 0.0;
+    z.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) z[(size_t)i * n + i] = 1.0;
+    for (int l = 0; l < n; ++l) {
+        int sweeps = 0;
+        while (true) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= DBL_EPSILON * dd) break;
+            }
+            if (m == l) break;
+            if (++sweeps > 60) return false;
+            // shift: the eigenvalue of the leading 2 x 2 block nearer d[l]
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool deflated = false;
+            for (int i = m - 1; i >= l; --i) {
+                double f = s * e[i];
+                const double b = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {   // an off-diagonal vanished: split and restart
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    deflated = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                for (int k = 0; k < n; ++k) {
+                    double* zk = &z[(size_t)k * n];
+                    f = zk[i + 1];
+                    zk[i + 1] = s * zk[i] + c * f;
+                    zk[i] = c * zk[i] - s * f;
+                }
+            }
+            if (deflated) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    return true;
+}
+
+// 1-D operator of the interior nodes of coordinates x[0..n-1]:
+// (A u)_i = am_i (u_i-1 - u_i) + ap_i (u_i+1 - u_i), am = 1/(h_i-1 m_i),
+// ap = 1/(h_i m_i). Fills lam[n-2], S and Si [n-2][n-2] row-major.
+static bool axis_decomposition(const double* x, int n, double* lam, double* S, double* Si)
+{
+    const int m = n - 2;
+    std::vector<double> w(m), d(m), e(m), z;
+    for (int t = 0; t < m; ++t) {
+        const int i = t + 1;
+        const double hm = x[i] - x[i - 1], hp = x[i + 1] - x[i];
+        w[t] = 0.5 * (hm + hp);
+        d[t] = -(1.0 / (hm * w[t]) + 1.0 / (hp * w[t]));
+    }
+    for (int t = 0; t + 1 < m; ++t) e[t] = 1.0 / ((x[t + 2] - x[t + 1]) * std::sqrt(w[t] * w[t + 1]));
+    if (!tridiagonal_ql(m, d, e, z)) return false;
+    for (int t = 0; t < m; ++t) lam[t] = d[t];
+    for (int i = 0; i < m; ++i) {
+        const double sq = std::sqrt(w[i]);
+        for (int k = 0; k < m; ++k) {
+            S[(size_t)i * m + k] = z[(size_t)i * m + k] / sq;    // M^-1/2 Q
+            Si[(size_t)k * m + i] = z[(size_t)i * m + k] * sq;   // Q^T M^1/2
+        }
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ kernels
+// b = bscale rho - A v_bc at the interior nodes, packed [mz][my][mx]: with a
+// zero interior only face neighbours contribute
+__global__ __launch_bounds__(256) void k_fdm_rhs(LevelView L, const double* __restrict__ v,
+                                                 const double* __restrict__ rho, double bscale, double* __restrict__ b)
+{
+    const int mx = L.nx - 2, my = L.ny - 2, mz = L.nz - 2;
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)mx * my * mz) return;
+    const int i = (int)(t % mx) + 1;
+    const size_t rest = t / mx;
+    const int j = (int)(rest % my) + 1, k = (int)(rest / my) + 1;
+    const size_t plane = (size_t)L.nx * L.ny;
+    const size_t at = (size_t)k * plane + (size_t)j * L.nx + i;
+    double s = bscale * rho[at];
+    if (i == 1) s -= L.ax[0].am[i] * v[at - 1];
+    if (i == L.nx - 2) s -= L.ax[0].ap[i] * v[at + 1];
+    if (j == 1) s -= L.ax[1].am[j] * v[at - L.nx];
+    if (j == L.ny - 2) s -= L.ax[1].ap[j] * v[at + L.nx];
+    if (k == 1) s -= L.ax[2].am[k] * v[at - plane];
+    if (k == L.nz - 2) s -= L.ax[2].ap[k] * v[at + plane];
+    b[t] = s;
+}
+
+// u /= l_z[k] + l_y[j] + l_x[i] in the eigenbasis
+__global__ __launch_bounds__(256) void k_fdm_divide(double* __restrict__ u, const double* __restrict__ lx,
+                                                    const double* __restrict__ ly, const double* __restrict__ lz,
+                                                    int mx, int my, int mz)
+{
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)mx * my * mz) return;
+    const int i = (int)(t % mx);
+    const size_t rest = t / mx;
+    const int j = (int)(rest % my), k = (int)(rest / my);
+    u[t] = u[t] / (lz[k] + ly[j] + lx[i]);
+}
+
+// interior of v from the packed solution
+__global__ __launch_bounds__(256) void k_fdm_unpack(LevelView L, const double* __restrict__ u, double* __restrict__ v)
+{
+    const int mx = L.nx - 2, my = L.ny - 2, mz = L.nz - 2;
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)mx * my * mz) return;
+    const int i = (int)(t % mx) + 1;
+    const size_t rest = t / mx;
+    const int j = (int)(rest % my) + 1, k = (int)(rest / my) + 1;
+    v[((size_t)k * L.ny + j) * L.nx + i] = u[t];
+}
+
+static lasto_status fdm_init(lasto_grid g)
+{
+    if (g->fdm) return LASTO_OK;
+    const LevelView& V = g->cview;
+    const int n[3] = {V.nx, V.ny, V.nz};
+    FdmState* f = new FdmState;
+    g->fdm = f;
+    for (int d = 0; d < 3; ++d) {
+        const int m = n[d] - 2;
+        f->m[d] = m;
+        std::vector<double> lam(m), S((size_t)m * m), Si((size_t)m * m);
+        if (!axis_decomposition(g->lev[0].hx[d].data(), n[d], lam.data(), S.data(), Si.data())) {
+            free_fdm(g);
+            return fail(LASTO_ERR_STATE, "lasto_fdm_solve: the 1-D eigen-decomposition did not converge");
+        }
+        if (hipMalloc(&f->S[d], sizeof(double) * m * m) != hipSuccess ||
+            hipMalloc(&f->Si[d], sizeof(double) * m * m) != hipSuccess ||
+            hipMalloc(&f->lam[d], sizeof(double) * m) != hipSuccess) {
+            free_fdm(g);
+            return fail(LASTO_ERR_ALLOC, "lasto_fdm_solve: tables");
+        }
+        hipError_t e = hipMemcpy(f->S[d], S.data(), sizeof(double) * m * m, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(f->Si[d], Si.data(), sizeof(double) * m * m, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(f->lam[d], lam.data(), sizeof(double) * m, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_fdm(g);
+            return fail(LASTO_ERR_HIP, std::string("lasto_fdm_solve: ") + hipGetErrorString(e));
+        }
+    }
+    const size_t cells = (size_t)f->m[0] * f->m[1] * f->m[2];
+    if (hipMalloc(&f->buf[0], sizeof(double) * cells) != hipSuccess ||
+        hipMalloc(&f->buf[1], sizeof(double) * cells) != hipSuccess) {
+        free_fdm(g);
+        return fail(LASTO_ERR_ALLOC, "lasto_fdm_solve: work arrays");
+    }
+    if (rocblas_create_handle(&f->blas) != rocblas_status_success ||
+        rocblas_set_stream(f->blas, g->stream) != rocblas_status_success) {
+        free_fdm(g);
+        return fail(LASTO_ERR_HIP, "lasto_fdm_solve: rocBLAS handle");
+    }
+    return LASTO_OK;
+}
+
+// out = (P along axis d) in, for row-major [mz][my][mx] data (rocBLAS is
+// column-major: the array is an mx x (my mz) matrix, a stack of mz
+// mx x my matrices, or an (mx my) x mz matrix)
+static rocblas_status contract(FdmState* f, int d, const double* P, const double* in, double* out)
+{
+    const int mx = f->m[0], my = f->m[1], mz = f->m[2];
+    const double one = 1.0, zero = 0.0;
+    if (d == 0)
+        return rocblas_dgemm(f->blas, rocblas_operation_transpose, rocblas_operation_none, mx, my * mz, mx, &one, P, mx,
+                             in, mx, &zero, out, mx);
+    if (d == 1)
+        return rocblas_dgemm_strided_batched(f->blas, rocblas_operation_none, rocblas_operation_none, mx, my, my, &one,
+                                             in, mx, (rocblas_stride)mx * my, P, my, 0, &zero, out, mx,
+                                             (rocblas_stride)mx * my, mz);
+    return rocblas_dgemm(f->blas, rocblas_operation_none, rocblas_operation_none, mx * my, mz, mz, &one, in, mx * my, P,
+                         mz, &zero, out, mx * my);
+}
+
+}  // namespace lasto
+
+using namespace lasto;
+
+extern "C" lasto_status lasto_fdm_axis(const double* x, int n, double* lam, double* S, double* Sinv)
+{
+    if (!x || !lam || !S || !Sinv || n < 3) return fail(LASTO_ERR_ARG, "lasto_fdm_axis: NULL argument or n < 3");
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(x[i + 1] > x[i])) return fail(LASTO_ERR_ARG, "lasto_fdm_axis: coordinates must increase");
+    if (!axis_decomposition(x, n, lam, S, Sinv)) return fail(LASTO_ERR_STATE, "lasto_fdm_axis: no convergence");
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_fdm_solve(lasto_grid g, const double* rho, double* v, int bc, int lmax_bc,
+                                        lasto_solve_info* info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!g || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_fdm_solve: NULL argument");
+    if (bc < 0 || bc > 1 || lmax_bc < 0 || lmax_bc > 4) return fail(LASTO_ERR_ARG, "lasto_fdm_solve: bad bc/lmax_bc");
+    const LevelView& V = g->cview;
+    if (V.nx < 3 || V.ny < 3 || V.nz < 3) return fail(LASTO_ERR_ARG, "lasto_fdm_solve: needs 3 nodes per axis");
+    if (lasto_status st = fdm_init(g); st != LASTO_OK) return st;
+    FdmState* f = g->fdm;
+    const size_t N = (size_t)V.nx * V.ny * V.nz;
+    const size_t cells = (size_t)f->m[0] * f->m[1] * f->m[2];
+    const unsigned blocks = (unsigned)((cells + 255) / 256);
+    hipStream_t s = g->stream;
+    for (int b = 0; b < g->n_batch; ++b) {
+        const double* rb = rho + b * N;
+        double* vb = v + b * N;
+        if (bc == 1) {
+            LASTO_HIP(launch_moments(g, rb, g->moments + 25 * b));
+            LASTO_HIP(launch_bc(g, 1, g->moments + 25 * b, lmax_bc, vb));
+        } else {
+            LASTO_HIP(launch_bc(g, 0, g->moments, 0, vb));
+        }
+        hipLaunchKernelGGL(k_fdm_rhs, dim3(blocks), dim3(256), 0, s, V, vb, rb, 4.0 * kPi, f->buf[0]);
+        LASTO_LAUNCH_CHECK("k_fdm_rhs");
+        rocblas_status e = contract(f, 0, f->Si[0], f->buf[0], f->buf[1]);
+        if (e == rocblas_status_success) e = contract(f, 1, f->Si[1], f->buf[1], f->buf[0]);
+        if (e == rocblas_status_success) e = contract(f, 2, f->Si[2], f->buf[0], f->buf[1]);
+        if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_fdm_solve: rocBLAS GEMM");
+        hipLaunchKernelGGL(k_fdm_divide, dim3(blocks), dim3(256), 0, s, f->buf[1], f->lam[0], f->lam[1], f->lam[2],
+                           f->m[0], f->m[1], f->m[2]);
+        LASTO_LAUNCH_CHECK("k_fdm_divide");
+        e = contract(f, 2, f->S[2], f->buf[1], f->buf[0]);
+        if (e == rocblas_status_success) e = contract(f, 1, f->S[1], f->buf[0], f->buf[1]);
+        if (e == rocblas_status_success) e = contract(f, 0, f->S[0], f->buf[1], f->buf[0]);
+        if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_fdm_solve: rocBLAS GEMM");
+        hipLaunchKernelGGL(k_fdm_unpack, dim3(blocks), dim3(256), 0, s, V, f->buf[0], vb);
+        LASTO_LAUNCH_CHECK("k_fdm_unpack");
+    }
+    // ||4 pi rho - A v||_W against the face data's, per right-hand side
+    const int nparts = interior_blocks(V);
+    for (int b = 0; b < g->n_batch; ++b) {
+        for (int zero = 1; zero >= 0; --zero) {
+            LASTO_HIP(launch_residual_nat(V, v + b * N, rho + b * N, 4.0 * kPi, nullptr, g->partials, zero, s));
+            LASTO_HIP(launch_reduce(g->partials, 1, nparts, g->scalars + (zero ? S_BR0 : S_BRR) + b, s));
+        }
+    }
+    LASTO_HIP(hipMemcpyAsync(g->h_scalars, g->scalars, sizeof(double) * kNumScalars, hipMemcpyDeviceToHost, s));
+    LASTO_HIP(hipStreamSynchronize(s));
+    double worst = 0.0;
+    if (info) std::memset(info, 0, sizeof(*info));
+    for (int b = 0; b < g->n_batch; ++b) {
+        const double r0 = g->h_scalars[S_BR0 + b], rr = g->h_scalars[S_BRR + b];
+        const double rel = r0 > 0.0 ? std::sqrt(rr / r0) : std::sqrt(rr);
+        worst = std::max(worst, rel);
+        if (info && b < kMaxBatch) info->batch_rel_resid[b] = rel;
+    }
+    if (info) {
+        info->iters = 1;
+        info->rel_resid = worst;
+        info->resid_hist[0] = worst;
+        info->n_batch = g->n_batch;
+        if (bc == 1) {
+            LASTO_HIP(hipMemcpy(info->moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost));
+        }
+        info->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!std::isfinite(worst)) return fail(LASTO_ERR_DIVERGED, "lasto_fdm_solve: non-finite residual");
+    return LASTO_OK;
+}

@@ -271,6 +271,7 @@ static lasto_status alloc_zero(lasto_grid g, void** p, size_t bytes)
 
 static void free_grid(lasto_grid g)
 {
+    free_fdm(g);
     for (int l = 0; l < g->nlev; ++l) {
         Level& L = g->lev[l];
         (void)hipFree(L.dtab);

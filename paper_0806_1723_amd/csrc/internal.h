@@ -219,6 +219,10 @@ __host__ __device__ __forceinline__ LdsTab lds_tab(P* b, int nx, int ny, int nz,
 
 }  // namespace lasto
 
+namespace lasto {
+struct FdmState;   // fast-diagonalisation tables and work arrays (fdm.hip)
+}
+
 struct lasto_grid_s {
     int nlev = 0;
     int n_batch = 1;
@@ -258,6 +262,7 @@ struct lasto_grid_s {
     double* stage = nullptr;
     size_t stage_bytes = 0;
     double box_center[3] = {0, 0, 0};
+    lasto::FdmState* fdm = nullptr;   // built on the first lasto_fdm_solve
     // optional event timing of the finest-level sweeps (solve opts.profile)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;   // start/stop pairs
@@ -415,6 +420,7 @@ size_t matrix_partial_doubles(int n_pairs, int n_chunks);
 hipError_t launch_matrix_elements(lasto_grid g, const double* w, const double* v, const double4* atoms, int n_atoms,
                                   const double4* shells, int n_shells, int nbpa, int n_basis, const int2* pairs,
                                   int n_pairs, int n_chunks, double* partials, double* S, double* H);
+void free_fdm(lasto_grid g);
 hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_atom, int n_atoms,
                                double* out);
 

@@ -797,18 +797,29 @@ __global__ __launch_bounds__(EG_NT) void k_energy_grid(LevelView L, const double
         rr[s] = n < N ? rb[n] : 0.0;
     }
     double acc = 0.0;
+    // the thread's first node decoded once, then stepped by EG_NT with carries
+    unsigned n = first + threadIdx.x;
+    unsigned k = n / plane, j = (n - k * plane) / nx, i = n - k * plane - j * nx;
 #pragma unroll
     for (int s = 0; s < EG_PER; ++s) {
-        const unsigned n = first + threadIdx.x + s * EG_NT;
-        if (n >= N) continue;
-        const unsigned k = n / plane, j = (n - k * plane) / nx, i = n - k * plane - j * nx;
-        const double px = X[i], py = Y[j], pz = Zc[k];
-        bool outside = true;
-        for (int t = 0; t < na; ++t) {
-            const SphereAtom& A = atoms[all ? t : list[t]];
-            if (dist2_exact(px - A.c[0], py - A.c[1], pz - A.c[2]) < A.R * A.R) outside = false;
+        if (n < N) {
+            const double px = X[i], py = Y[j], pz = Zc[k];
+            bool outside = true;
+            for (int t = 0; t < na; ++t) {
+                const SphereAtom& A = atoms[all ? t : list[t]];
+                if (dist2_exact(px - A.c[0], py - A.c[1], pz - A.c[2]) < A.R * A.R) outside = false;
+            }
+            if (outside) acc += L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * vv[s] * rr[s];
         }
-        if (outside) acc += L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * vv[s] * rr[s];
+        n += EG_NT;
+        i += EG_NT;
+        while (i >= nx) {
+            i -= nx;
+            if (++j == ny) {
+                j = 0;
+                ++k;
+            }
+        }
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
     if (lane == 0) wsum[wid] = acc;
@@ -878,9 +889,16 @@ constexpr int ID_PTS = 64;    // nodes per workgroup, 16 per wave
 
 typedef double dbl4v __attribute__((ext_vector_type(4)));
 
+// LDS row of the staged coefficients: 16 NT doubles, plus 16 when NT is even,
+// so that the four k-rows one matrix-core operand reads start 32 banks apart
+__host__ __device__ constexpr int id_ldb(int nt)
+{
+    return 16 * nt + ((nt & 1) ? 0 : 16);
+}
+
 size_t interstitial_lds_bytes(int nt, int kpa)
 {
-    return sizeof(double) * ((size_t)kpa * 16 * nt + (size_t)(ID_NT / 64) * 16 * kpa);
+    return sizeof(double) * ((size_t)kpa * id_ldb(nt) + (size_t)(ID_NT / 64) * 16 * kpa);
 }
 
 template <int NT>
@@ -891,9 +909,10 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
                                                         double* __restrict__ rho)
 {
     constexpr int NC = 16 * NT;
+    constexpr int LDB = id_ldb(NT);
     extern __shared__ double id_lds[];
-    double* Bs = id_lds;                          // [kpa][NC] coefficient rows of one atom
-    double* Ph = id_lds + (size_t)kpa * NC;       // [waves][16 nodes][kpa] basis values
+    double* Bs = id_lds;                          // [kpa][LDB] coefficient rows of one atom
+    double* Ph = id_lds + (size_t)kpa * LDB;      // [waves][16 nodes][kpa] basis values
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int p16 = lane & 15, grp = lane >> 4;
     const unsigned nx = L.nx, ny = L.ny, plane = nx * ny, N = plane * L.nz;
@@ -911,7 +930,7 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
         const double* crow = coef + (size_t)a * nbpa * n_occ;
         for (int e = threadIdx.x; e < kpa * NC; e += ID_NT) {
             const int r = e / NC, c = e - r * NC, col = c0 + c;
-            Bs[e] = (r < nbpa && col < n_occ) ? crow[(size_t)r * n_occ + col] : 0.0;
+            Bs[r * LDB + c] = (r < nbpa && col < n_occ) ? crow[(size_t)r * n_occ + col] : 0.0;
         }
         const double4 A = atoms[a];
         const double dx = px - A.x, dy = py - A.y, dz = pz - A.z;
@@ -934,7 +953,7 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
         __syncthreads();
         for (int ks = 0; ks < kpa; ks += 4) {
             const double av = phw[p16 * kpa + ks + grp];
-            const double* brow = Bs + (size_t)(ks + grp) * NC + p16;
+            const double* brow = Bs + (size_t)(ks + grp) * LDB + p16;
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[16 * t], acc[t], 0, 0, 0);
         }
@@ -985,29 +1004,37 @@ static hipError_t launch_interstitial_nt(lasto_grid g, const double4* atoms, int
     return hipGetLastError();
 }
 
-// The states in chunks of at most 160 (10 column tiles per launch, so that
-// three workgroups share a CU's LDS); the first chunk writes rho, the others add.
+// The states in chunks of at most LASTO_ID_CHUNK (160: ten column tiles, two
+// waves per SIMD and three workgroups' LDS per CU at 25 functions per atom;
+// longer chunks need more than 128 registers per lane); the first chunk
+// writes rho, the others add.
+#ifndef LASTO_ID_CHUNK
+#define LASTO_ID_CHUNK 160
+#endif
 hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells, int n_shells,
                                int nbpa, const double* coef, int n_occ, const double* occ, double* rho)
 {
     const int kpa = (nbpa + 3) & ~3;
-    for (int c0 = 0; c0 < n_occ || c0 == 0; c0 += 160) {
-        const int tiles = std::min(10, (std::max(n_occ - c0, 1) + 15) / 16);
+    constexpr int CHUNK = LASTO_ID_CHUNK;
+    static_assert(CHUNK % 16 == 0 && CHUNK <= 288, "state chunk: a multiple of 16, at most 288");
+    for (int c0 = 0; c0 < n_occ; c0 += CHUNK) {
+        const int tiles = std::min(CHUNK / 16, (n_occ - c0 + 15) / 16);
         const int acc = c0 > 0;
         hipError_t e;
-        switch (tiles) {
-        case 1: e = launch_interstitial_nt<1>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
-        case 2: e = launch_interstitial_nt<2>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
-        case 3:
-        case 4: e = launch_interstitial_nt<4>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
-        case 5:
-        case 6: e = launch_interstitial_nt<6>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
-        case 7:
-        case 8: e = launch_interstitial_nt<8>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
-        default: e = launch_interstitial_nt<10>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho); break;
-        }
+#define LASTO_ID_CASE(T) \
+    e = launch_interstitial_nt<T>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho)
+        if (tiles <= 1) LASTO_ID_CASE(1);
+        else if (tiles <= 2) LASTO_ID_CASE(2);
+        else if (tiles <= 4) LASTO_ID_CASE(4);
+        else if (tiles <= 6) LASTO_ID_CASE(6);
+        else if (tiles <= 8) LASTO_ID_CASE(8);
+        else if (tiles <= 10) LASTO_ID_CASE(10);
+        else if (tiles <= 12) LASTO_ID_CASE(12);
+        else if (tiles <= 14) LASTO_ID_CASE(14);
+        else if (tiles <= 16) LASTO_ID_CASE(16);
+        else LASTO_ID_CASE(18);
+#undef LASTO_ID_CASE
         if (e != hipSuccess) return e;
-        if (n_occ <= 0) break;
     }
     return hipSuccess;
 }
@@ -1159,14 +1186,20 @@ __global__ __launch_bounds__(ME_NT) void k_matrix_elements(LevelView L, const do
                 bP[q] = PC[kn * ME_LD + wc + 16 * q + p16];
                 bT[q] = TC[kn * ME_LD + wc + 16 * q + p16];
             }
+            // the two H products of a tile are seven instructions apart, so
+            // no product waits on the one before it
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     accS[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aP[a], bP[b], accS[a][b], 0, 0, 0);
                     accH[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aP[a], bT[b], accH[a][b], 0, 0, 0);
-                    accH[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aT[a], bP[b], accH[a][b], 0, 0, 0);
                 }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    accH[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aT[a], bP[b], accH[a][b], 0, 0, 0);
         }
     }
     // partial block: [2][64][64] (S, then H), row-major

@@ -95,7 +95,8 @@ SYMBOLS = [
     "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
     "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp",
     "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_project", "lasto_sphere_radial",
-    "lasto_sphere_energy", "lasto_interstitial_density", "lasto_matrix_elements", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
+    "lasto_sphere_energy", "lasto_interstitial_density", "lasto_matrix_elements", "lasto_fdm_solve",
+    "lasto_fdm_axis", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
     "lasto_net_create", "lasto_net_destroy",
     "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
     "lasto_net_features", "lasto_net_forward", "lasto_net_backward", "lasto_net_adam_step",
@@ -165,6 +166,10 @@ def load():
     L.lasto_interstitial_density.restype = i
     L.lasto_matrix_elements.argtypes = [P, P, i, P, P, i, P, P, P]
     L.lasto_matrix_elements.restype = i
+    L.lasto_fdm_solve.argtypes = [P, P, P, i, i, C.POINTER(SolveInfo)]
+    L.lasto_fdm_solve.restype = i
+    L.lasto_fdm_axis.argtypes = [P, i, P, P, P]
+    L.lasto_fdm_axis.restype = i
     L.lasto_apply.argtypes = [P, P, P]
     L.lasto_apply.restype = i
     L.lasto_rb_sweep.argtypes = [P, P, P, P, i]
@@ -240,6 +245,18 @@ def mesh_for(axes) -> List[np.ndarray]:
     return [mesh_graded_1d(a.lo, a.hi, a.n, a.planes, a.hmin, a.hmax, a.gmax, a.hmin_step)[0] for a in axes]
 
 
+def fdm_axis(x):
+    """Host decomposition of the 1-D interior operator: (lam, S, Sinv) with
+    A = S diag(lam) Sinv."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    m = len(x) - 2
+    lam = np.zeros(m)
+    S = np.zeros((m, m))
+    Si = np.zeros((m, m))
+    _check(load().lasto_fdm_axis(_np_ptr(x), len(x), _np_ptr(lam), _np_ptr(S), _np_ptr(Si)))
+    return lam, S, Si
+
+
 def make_atoms(atoms: Sequence) -> C.Array:
     """lasto_atom array from objects with the fields of inputs.Atom."""
     arr = (Atom * max(len(atoms), 1))()
@@ -294,10 +311,10 @@ class Grid:
             load().lasto_grid_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the HIP runtime may already be gone; the process
         # releases the device memory itself
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
@@ -404,6 +421,13 @@ class Grid:
                                                  _np_ptr(f), _dev_ptr(rho_out)))
         return rho_out
 
+    def fdm_solve(self, rho, v, bc: int = 1, lmax_bc: int = 4) -> dict:
+        """Direct solve by fast diagonalisation (v's faces set, interior
+        overwritten); returns the solve info as a dict."""
+        info = SolveInfo()
+        _check(load().lasto_fdm_solve(self.h, _dev_ptr(rho), _dev_ptr(v), bc, lmax_bc, C.byref(info)))
+        return info.as_dict()
+
     def matrix_elements(self, v, centers, radii, shells):
         """Interstitial S and H (device [n_basis][n_basis] float64 tensors) by
         grid quadrature at the nodes outside every sphere, potential v."""
@@ -453,10 +477,10 @@ class Spheres:
             load().lasto_spheres_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the HIP runtime may already be gone; the process
         # releases the device memory itself
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
@@ -522,10 +546,10 @@ class Net:
             load().lasto_net_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the HIP runtime may already be gone; the process
         # releases the device memory itself
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
