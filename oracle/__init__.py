@@ -76,6 +76,8 @@ def lib():
         L.oracle_sphere_energy.restype = i
         L.oracle_energy_grid.argtypes = [P, i, P, i, P, i, P, P, i, P, P]
         L.oracle_energy_grid.restype = d
+        L.oracle_sphere_density_terms.argtypes = [P, i, P, i, P, i, i, P, P, i, d, P, i, P]
+        L.oracle_sphere_density_terms.restype = i
         L.oracle_density_points.argtypes = [i, P, i, P, P, P, i, P, P, i, P, P]
         L.oracle_density_points.restype = i
         L.oracle_interstitial_density.argtypes = [P, i, P, i, P, i, i, P, P, i, P, P, P, i, P, P, P]
@@ -370,3 +372,17 @@ def matrix_elements(xs, v, centers, radii, shells):
     if rc != 0:
         raise ValueError("bad shells")
     return S, H
+
+
+def sphere_density_terms(xs, centers, radii, r_min, rho_lm, lmin, rho):
+    """Adds sum_(L >= lmin) rho_LM(r) y_LM inside each sphere to rho (in place)."""
+    x, y, z = (_f64(a) for a in xs)
+    centers = _f64(centers).reshape(-1, 3)
+    rho_lm = _f64(rho_lm)
+    assert rho.dtype == np.float64 and rho.flags.c_contiguous
+    rc = lib().oracle_sphere_density_terms(_p(x), len(x), _p(y), len(y), _p(z), len(z), len(centers), _p(centers),
+                                           _p(_f64(radii)), rho_lm.shape[2], float(r_min), _p(rho_lm), int(lmin),
+                                           _p(rho))
+    if rc != 0:
+        raise ValueError("bad n_rad or lmin")
+    return rho

@@ -11,6 +11,9 @@
  *   - the interior solution of the radial equation (3.4) with that
  *     projection as Dirichlet data, written as the radial Green's function
  *     integrals under (3.4)-(3.5);
+ *   - the tabulated non-spherical density put on the grid inside each sphere
+ *     (the paper places the non-spherical terms directly on the grid; here
+ *     from the same radial tables the interior solve uses);
  *   - the bilinear integral of V against the density over the whole domain:
  *     grid quadrature at nodes outside every sphere plus radial quadrature
  *     of sum_LM V_LM rho_LM inside each sphere (orthonormal y_LM turn the
@@ -262,4 +265,62 @@ double oracle_energy_grid(const double* x, int nx, const double* y, int ny, cons
         }
     }
     return s;
+}
+
+/* ------------------------------------------- tabulated density on the grid */
+
+/* The paper puts the non-spherical part of the sphere density directly on
+ * the grid. Here it is read from the radial tables: at each node inside
+ * sphere a (|x - C|^2 < R^2),
+ *   rho += sum_(LM, L >= lmin) rho_LM(r) y_LM(x - C),
+ * with rho_LM(r) the cubic Lagrange interpolant in t = ln r through the four
+ * mesh samples around t (window start clamp(floor((t - t_0)/D) - 1, 0, n - 4),
+ * t_k = ln R + (k - (n-1)) D), and below r_0, rho_LM(r_0) (r / r_0)^L (the
+ * r^L behaviour at the centre). y_LM(x - C) = S_LM(x - C) / r^L.
+ * rho_lm [n_atoms][25][n_rad]; rho [nz][ny][nx] is added to. */
+int oracle_sphere_density_terms(const double* x, int nx, const double* y, int ny, const double* z, int nz,
+                                int n_atoms, const double* centers, const double* radii, int n_rad, double r_min,
+                                const double* rho_lm, int lmin, double* rho)
+{
+    if (n_rad < 4 || lmin < 0 || lmin > 4) return 1;
+    int n = n_rad;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                for (int a = 0; a < n_atoms; ++a) {
+                    double dx = x[i] - centers[3 * a], dy = y[j] - centers[3 * a + 1], dz = z[k] - centers[3 * a + 2];
+                    volatile double sx = dx * dx, sy = dy * dy, sz = dz * dz;   /* no contraction */
+                    double R = radii[a];
+                    if (!(sx + sy + sz < R * R)) continue;
+                    double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    double S[25];
+                    oracle_solid_harmonics(dx, dy, dz, S);
+                    double D = log(R / r_min) / (n - 1);
+                    double r0 = oracle_radial_node(R, r_min, n, 0);
+                    double add = 0.0;
+                    for (int lm = lmin * lmin; lm < NLM; ++lm) {
+                        int L = lm_degree(lm);
+                        const double* tab = rho_lm + ((size_t)a * NLM + lm) * n;
+                        double val;
+                        if (r < r0) {
+                            val = tab[0] * S[lm] / pow(r0, L);   /* rho(r_0) (r/r_0)^L y_LM, y_LM = S / r^L */
+                        } else {
+                            double t = log(r);
+                            double t0 = log(R) - (n - 1) * D;
+                            double u0 = (t - t0) / D;
+                            int i0 = (int)floor(u0) - 1;
+                            if (i0 < 0) i0 = 0;
+                            if (i0 > n - 4) i0 = n - 4;
+                            double u = u0 - i0;
+                            double w[4] = {-(u - 1) * (u - 2) * (u - 3) / 6.0, u * (u - 2) * (u - 3) / 2.0,
+                                           -u * (u - 1) * (u - 3) / 2.0, u * (u - 1) * (u - 2) / 6.0};
+                            double f = w[0] * tab[i0] + w[1] * tab[i0 + 1] + w[2] * tab[i0 + 2] + w[3] * tab[i0 + 3];
+                            val = f * S[lm] / pow(r, L);
+                        }
+                        add += val;
+                    }
+                    rho[((size_t)k * ny + j) * nx + i] += add;
+                    break;   /* spheres do not overlap */
+                }
+    return 0;
 }

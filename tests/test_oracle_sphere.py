@@ -272,3 +272,98 @@ def test_grid_energy_leaves_lattice_ball_to_sphere():
     c2 = np.array([[1.25, 1.25, 1.25]])
     e2 = O.energy_grid(xs, one, one, c2, np.array([1.5 * h]))
     assert abs((full - e2) / h ** 3 - 8) < 1e-12
+
+
+# ------------------------------------------------- tabulated density terms
+def _real_sph(L, M, d):
+    th = np.arccos(np.clip(d[:, 2], -1, 1))
+    ph = np.arctan2(d[:, 1], d[:, 0])
+    Y = sp.sph_harm_y(L, abs(M), th, ph) * (-1) ** abs(M)
+    if M == 0:
+        return Y.real
+    return math.sqrt(2) * (Y.real if M > 0 else Y.imag)
+
+
+def test_density_terms_exact_for_cubics_in_log_r():
+    """rho_LM(r) = p_LM(ln r), p cubic: the four-point Lagrange interpolant in
+    ln r reproduces it, so the grid term is sum_LM p_LM(ln r) y_LM (scipy's
+    harmonics) at every node inside the sphere with r >= r_0; below r_0 it is
+    rho_LM(r_0) (r/r_0)^L y_LM; nodes outside are untouched; lmin drops L < lmin"""
+    rng = np.random.default_rng(91)
+    x = np.linspace(-3, 3, 25) + 0.013
+    xs = [x, x + 0.007, x - 0.011]
+    c = np.array([[0.0, 0.0, 0.0]])
+    R, r_min, n = 2.2, 0.3, 40
+    coef = rng.normal(size=(25, 4))
+    r = O.radial_mesh(R, r_min, n)
+    t = np.log(r)
+    tab = np.zeros((1, 25, n))
+    for lm in range(25):
+        tab[0, lm] = coef[lm, 0] + coef[lm, 1] * t + coef[lm, 2] * t * t + coef[lm, 3] * t ** 3
+    base = rng.normal(size=(25, 25, 25))
+    for lmin in (0, 1, 2):
+        rho = base.copy()
+        O.sphere_density_terms(xs, c, [R], r_min, tab, lmin, rho)
+        Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+        d2 = X * X + Y * Y + Z * Z
+        inside = d2 < R * R
+        assert np.array_equal(rho[~inside], base[~inside])
+        pts = np.stack([X[inside], Y[inside], Z[inside]], axis=1)
+        rr = np.sqrt((pts ** 2).sum(1))
+        dirs = pts / rr[:, None]
+        want = np.zeros(len(pts))
+        for L in range(lmin, 5):
+            for M in range(-L, L + 1):
+                lm = L * L + L + M
+                p = coef[lm, 0] + coef[lm, 1] * np.log(rr) + coef[lm, 2] * np.log(rr) ** 2 + coef[lm, 3] * np.log(rr) ** 3
+                below = rr < r[0]
+                p[below] = tab[0, lm, 0] * (rr[below] / r[0]) ** L
+                want += p * _real_sph(L, M, dirs)
+        got = rho[inside] - base[inside]
+        assert (rr < r[0]).any() and (rr >= r[0]).any()
+        assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
+
+
+def test_density_terms_match_gaussian_multipoles():
+    """the synthetic sphere densities' l-terms c r^l exp(-r^2), tabulated on
+    429 points and put back on the grid, agree with the analytic
+    c S_lm exp(-r^2) to the interpolation error (for r^4 the samples grow
+    like exp(4 t): (4 D)^4 / 24 with D = 0.029, about 2e-5)"""
+    rng = np.random.default_rng(92)
+    x = np.linspace(-3, 3, 31)
+    c = np.array([[0.05, -0.02, 0.03]])
+    R, r_min, n = 2.5, 1e-5, 429
+    r = O.radial_mesh(R, r_min, n)
+    cl = rng.normal(size=24) * 0.3
+    tab = np.zeros((1, 25, n))
+    for lm in range(1, 25):
+        L = int(math.isqrt(lm))
+        tab[0, lm] = cl[lm - 1] * r ** L * np.exp(-r * r)
+    rho = np.zeros((31, 31, 31))
+    O.sphere_density_terms([x, x, x], c, [R], r_min, tab, 1, rho)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    want = np.zeros_like(rho)
+    for idx in np.ndindex(rho.shape):
+        dx, dy, dz = X[idx] - c[0, 0], Y[idx] - c[0, 1], Z[idx] - c[0, 2]
+        if dx * dx + dy * dy + dz * dz < R * R:
+            S = O.solid_harmonics(dx, dy, dz)
+            want[idx] = (cl * S[1:]).sum() * math.exp(-(dx * dx + dy * dy + dz * dz))
+    assert np.abs(rho - want).max() <= 3e-5 * np.abs(want).max()
+
+
+def test_density_terms_window_is_centred():
+    """a table that is 1 at one mesh index k and 0 elsewhere: at a node half
+    way between r_k and r_(k+1) the interpolant uses the window k-1..k+2 and
+    returns the Lagrange weight of its second node at u = 1.5, 9/16 (a window
+    starting at k would give 5/16)"""
+    R, r_min, n, k = 2.0, 0.1, 30, 12
+    r = O.radial_mesh(R, r_min, n)
+    rk = math.sqrt(r[k] * r[k + 1])   # t half way
+    x = np.array([-2.5, -1.0, 0.0, rk, 2.5])
+    xs = [x, np.array([-2.5, -1.0, 0.0, 1.0, 2.5]), np.array([-2.5, -1.0, 0.0, 1.0, 2.5])]
+    tab = np.zeros((1, 25, n))
+    tab[0, 0, k] = 1.0
+    rho = np.zeros((5, 5, 5))
+    O.sphere_density_terms(xs, np.zeros((1, 3)), [R], r_min, tab, 0, rho)
+    y00 = 0.5 / math.sqrt(math.pi)
+    assert abs(rho[2, 2, 3] - 9.0 / 16.0 * y00) <= 1e-12
