@@ -271,6 +271,22 @@ lasto_status lasto_spheres_create(lasto_grid g, int n_atoms, const double* cente
 lasto_status lasto_spheres_destroy(lasto_spheres s);
 
 /*
+ * The non-spherical density put on the grid inside the spheres (Section 1
+ * places the non-spherical terms of the sphere densities directly on the
+ * grid; here from the radial tables the interior solve uses): at every node
+ * inside sphere a (|x - C_a|^2 < R_a^2),
+ *   rho += sum_(LM, L >= lmin) rho_LM(r) y_LM(x - C_a),
+ * rho_LM(r) the cubic in t = ln r through the four mesh samples around t
+ * (window start clamp(floor((t - t_0)/D) - 1, 0, n_rad - 4)); below r_0,
+ * rho_LM(r_0) (r / r_0)^L. With kind-1 atoms of lmax 0 in
+ * lasto_pseudo_density, lmin = 1 here and the interstitial density outside,
+ * this is the paper-mode source.
+ *   rho_lm: device [n_atoms][25][n_rad]; rho: device grid array, added to.
+ * Enqueued on the grid's stream. Errors: LASTO_ERR_ARG, LASTO_ERR_HIP.
+ */
+lasto_status lasto_sphere_density_terms(lasto_spheres s, const double* rho_lm, int lmin, double* rho);
+
+/*
  * eq. (3.6): vlm_R[a][LM] = sum_p w_p V(C_a + R_a d_p) y_LM(d_p), V(x) by
  * tricubic Lagrange interpolation of the grid values (as lasto_sphere_interp).
  *   v: device grid values [nz][ny][nx]. vlm_R: device [n_atoms][25].

@@ -405,6 +405,8 @@ hipError_t launch_radial_solve(lasto_grid g, const SphereAtom* atoms, int n_atom
 hipError_t launch_sphere_energy(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* v_lm,
                                 const double* rho_lm, double* e_atom);
 int energy_grid_blocks(const LevelView& L);   // partials per copy of launch_energy_grid
+hipError_t launch_sphere_terms(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* rho_lm,
+                               int lmin, double* rho);
 hipError_t launch_energy_grid(lasto_grid g, const double* v, const double* rho, const SphereAtom* atoms, int n_atoms,
                               double* partials);
 // interstitial output density: atoms [n][4] (centre, sphere radius), shells

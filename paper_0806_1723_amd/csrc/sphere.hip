@@ -194,3 +194,11 @@ extern "C" lasto_status lasto_sphere_energy(lasto_spheres s, const double* v, co
     std::copy(s->e_host, s->e_host + 2 * nb, e_out);
     return LASTO_OK;
 }
+
+extern "C" lasto_status lasto_sphere_density_terms(lasto_spheres s, const double* rho_lm, int lmin, double* rho)
+{
+    if (!s || !rho_lm || !rho) return fail(LASTO_ERR_ARG, "lasto_sphere_density_terms: NULL argument");
+    if (lmin < 0 || lmin > 4) return fail(LASTO_ERR_ARG, "lasto_sphere_density_terms: lmin must be 0..4");
+    LASTO_HIP(launch_sphere_terms(s->g, s->atoms, s->n_atoms, s->n_rad, rho_lm, lmin, rho));
+    return LASTO_OK;
+}

@@ -840,6 +840,144 @@ hipError_t launch_energy_grid(lasto_grid g, const double* v, const double* rho, 
     return hipGetLastError();
 }
 
+// The tabulated non-spherical density on the grid: at every node inside a
+// sphere, rho += sum_(L >= lmin) rho_LM(r) y_LM, rho_LM by the cubic in
+// t = ln r through the four radial samples around t (window start
+// clamp(floor((t - t_0)/D) - 1, 0, n - 4)); below r_0, rho_LM(r_0) (r/r_0)^L.
+// Workgroups take EG_NT * EG_PER consecutive nodes and the spheres meeting
+// their box, as for the energy's grid part.
+__global__ __launch_bounds__(EG_NT) void k_sphere_terms(LevelView L, const SphereAtom* __restrict__ atoms, int n_atoms,
+                                                        int n, const double* __restrict__ rho_lm, int lmin,
+                                                        double* __restrict__ rho)
+{
+    __shared__ int list[EG_LIST];
+    __shared__ int wcount[EG_NT / 64];
+    __shared__ double box[6];
+    const int b = blockIdx.y;
+    const unsigned nx = L.nx, ny = L.ny, nz = L.nz, plane = nx * ny, N = plane * nz;
+    const unsigned first = blockIdx.x * (unsigned)(EG_NT * EG_PER);
+    const unsigned last = min(first + (unsigned)(EG_NT * EG_PER), N) - 1u;
+    const double* X = L.ax[0].x;
+    const double* Y = L.ax[1].x;
+    const double* Zc = L.ax[2].x;
+    if (threadIdx.x == 0) {
+        const unsigned kf = first / plane, kl = last / plane;
+        const unsigned jf = (first - kf * plane) / nx, jl = (last - kl * plane) / nx;
+        const unsigned i_f = first - kf * plane - jf * nx, il = last - kl * plane - jl * nx;
+        const bool one_plane = kf == kl, one_row = one_plane && jf == jl;
+        box[0] = one_row ? X[i_f] : X[0];
+        box[1] = one_row ? X[il] : X[nx - 1];
+        box[2] = one_plane ? Y[jf] : Y[0];
+        box[3] = one_plane ? Y[jl] : Y[ny - 1];
+        box[4] = Zc[kf];
+        box[5] = Zc[kl];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int count = 0;
+    for (int a0 = 0; a0 < n_atoms; a0 += EG_NT) {
+        const int a = a0 + threadIdx.x;
+        bool hit = false;
+        if (a < n_atoms) {
+            const SphereAtom& A = atoms[a];
+            const double ex = fmax(fmax(box[0] - A.c[0], A.c[0] - box[1]), 0.0);
+            const double ey = fmax(fmax(box[2] - A.c[1], A.c[1] - box[3]), 0.0);
+            const double ez = fmax(fmax(box[4] - A.c[2], A.c[2] - box[5]), 0.0);
+            hit = dist2_exact(ex, ey, ez) < A.R * A.R;
+        }
+        const unsigned long long mask = __ballot(hit);
+        if (lane == 0) wcount[wid] = __popcll(mask);
+        __syncthreads();
+        int off = count;
+        for (int w = 0; w < wid; ++w) off += wcount[w];
+        if (hit && off + __popcll(mask & ((1ull << lane) - 1ull)) < EG_LIST)
+            list[off + __popcll(mask & ((1ull << lane) - 1ull))] = a;
+        for (int w = 0; w < EG_NT / 64; ++w) count += wcount[w];
+        __syncthreads();
+    }
+    if (count == 0) return;
+    const bool all = count > EG_LIST;
+    const int na = all ? n_atoms : count;
+    double* rb = rho + (size_t)b * N;
+    unsigned node = first + threadIdx.x;
+    unsigned k = node / plane, j = (node - k * plane) / nx, i = node - k * plane - j * nx;
+    for (int s = 0; s < EG_PER; ++s) {
+        if (node < N) {
+            const double px = X[i], py = Y[j], pz = Zc[k];
+            int hit_a = -1;
+            double dx = 0.0, dy = 0.0, dz = 0.0, d2 = 0.0;
+            for (int t = 0; t < na && hit_a < 0; ++t) {
+                const int a = all ? t : list[t];
+                const SphereAtom& A = atoms[a];
+                const double ex = px - A.c[0], ey = py - A.c[1], ez = pz - A.c[2];
+                const double q = dist2_exact(ex, ey, ez);
+                if (q < A.R * A.R) {
+                    hit_a = a;
+                    dx = ex;
+                    dy = ey;
+                    dz = ez;
+                    d2 = q;
+                }
+            }
+            if (hit_a >= 0) {
+                const SphereAtom& A = atoms[hit_a];
+                const double r = sqrt(d2);
+                double S[25];
+                solid_harmonics(dx, dy, dz, 4, S);
+                const double r0 = radial_node(A, n, 0);
+                const double* tab = rho_lm + ((size_t)b * n_atoms + hit_a) * 25 * n;
+                double add = 0.0;
+                if (r < r0) {
+                    double ir0[5] = {1.0, 1.0 / r0, 0.0, 0.0, 0.0};
+                    ir0[2] = ir0[1] * ir0[1];
+                    ir0[3] = ir0[2] * ir0[1];
+                    ir0[4] = ir0[3] * ir0[1];
+#pragma unroll
+                    for (int lm = 0; lm < 25; ++lm)
+                        if (lm >= lmin * lmin) add += tab[(size_t)lm * n] * S[lm] * ir0[lm_degree(lm)];
+                } else {
+                    const double t0 = log(A.R) - (n - 1) * A.D;
+                    const double u0 = (log(r) - t0) / A.D;
+                    int i0 = (int)floor(u0) - 1;
+                    i0 = i0 < 0 ? 0 : (i0 > n - 4 ? n - 4 : i0);
+                    const double u = u0 - i0;
+                    const double w0 = -(u - 1) * (u - 2) * (u - 3) / 6.0, w1 = u * (u - 2) * (u - 3) / 2.0;
+                    const double w2 = -u * (u - 1) * (u - 3) / 2.0, w3 = u * (u - 1) * (u - 2) / 6.0;
+                    double ir[5] = {1.0, 1.0 / r, 0.0, 0.0, 0.0};
+                    ir[2] = ir[1] * ir[1];
+                    ir[3] = ir[2] * ir[1];
+                    ir[4] = ir[3] * ir[1];
+#pragma unroll
+                    for (int lm = 0; lm < 25; ++lm)
+                        if (lm >= lmin * lmin) {
+                            const double* tl = tab + (size_t)lm * n + i0;
+                            add += (w0 * tl[0] + w1 * tl[1] + w2 * tl[2] + w3 * tl[3]) * S[lm] * ir[lm_degree(lm)];
+                        }
+                }
+                rb[node] += add;
+            }
+        }
+        node += EG_NT;
+        i += EG_NT;
+        while (i >= nx) {
+            i -= nx;
+            if (++j == ny) {
+                j = 0;
+                ++k;
+            }
+        }
+    }
+}
+
+hipError_t launch_sphere_terms(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* rho_lm,
+                               int lmin, double* rho)
+{
+    const LevelView& L = g->cview;
+    hipLaunchKernelGGL(k_sphere_terms, dim3(energy_grid_blocks(L), g->n_batch), dim3(EG_NT), 0, g->stream, L, atoms,
+                       n_atoms, n_rad, rho_lm, lmin, rho);
+    return hipGetLastError();
+}
+
 // out[b][0] = sum of the grid partials of copy b, out[b][1] = sum over atoms
 // of the sphere parts (fixed orders: strided per thread, then a tree).
 __global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ partials, int nparts,

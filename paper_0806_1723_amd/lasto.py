@@ -94,7 +94,7 @@ SYMBOLS = [
     "lasto_status_string", "lasto_last_error", "lasto_mesh_graded_1d", "lasto_grid_create",
     "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
     "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp",
-    "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_project", "lasto_sphere_radial",
+    "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_density_terms", "lasto_sphere_project", "lasto_sphere_radial",
     "lasto_sphere_energy", "lasto_interstitial_density", "lasto_matrix_elements", "lasto_fdm_solve",
     "lasto_fdm_axis", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
     "lasto_net_create", "lasto_net_destroy",
@@ -156,6 +156,8 @@ def load():
     L.lasto_spheres_create.restype = i
     L.lasto_spheres_destroy.argtypes = [P]
     L.lasto_spheres_destroy.restype = i
+    L.lasto_sphere_density_terms.argtypes = [P, P, i, P]
+    L.lasto_sphere_density_terms.restype = i
     L.lasto_sphere_project.argtypes = [P, P, P]
     L.lasto_sphere_project.restype = i
     L.lasto_sphere_radial.argtypes = [P, P, P, P]
@@ -486,6 +488,11 @@ class Spheres:
             self.close()
         except Exception:
             pass
+
+    def density_terms(self, rho_lm, rho, lmin: int = 1):
+        """rho += sum_(L >= lmin) rho_LM(r) y_LM inside each sphere (in place)."""
+        _check(load().lasto_sphere_density_terms(self.h, _dev_ptr(rho_lm), lmin, _dev_ptr(rho)))
+        return rho
 
     def project(self, v, vlm_R=None):
         import torch

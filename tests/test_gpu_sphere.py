@@ -319,3 +319,67 @@ def test_sphere_argument_errors(torch, L):
         S.radial(buf[:, :, 0].contiguous(), buf, buf)                 # output aliases the input
     S.close()
     g.close()
+
+
+@pytest.mark.parametrize("lmin,n,r_min", [(1, 429, 1e-5), (0, 40, 0.3), (2, 1024, 1e-6)])
+def test_density_terms_match_oracle(torch, L, oracle_mod, lmin, n, r_min):
+    say("sphere density terms lmin=%d n_rad=%d r_min=%g" % (lmin, n, r_min))
+    rng = np.random.default_rng(36 + lmin)
+    xs = [graded(rng, m) for m in (41, 37, 35)]
+    c, r = SPHERES
+    tab, _ = radial_inputs(rng, r, n, r_min)
+    base = smooth_field(xs, rng)
+    g = L.Grid(*xs)
+    S = L.Spheres(g, c, r, n_rad=n, r_min=r_min)
+    got = S.density_terms(dev(torch, tab), dev(torch, base), lmin=lmin).cpu().numpy()
+    want = base.copy()
+    oracle_mod.sphere_density_terms(xs, c, r, r_min, tab, lmin, want)
+    err = np.abs(got - want).max()
+    say("  max err %.2e of %.2e (changed nodes %d)" % (err, np.abs(want - base).max(), (want != base).sum()))
+    assert err <= 1e-13 * np.abs(want - base).max() + 1e-15 * np.abs(base).max()
+    assert np.array_equal(got == base, want == base)
+    S.close()
+    g.close()
+
+
+def test_paper_mode_source_full_size_257(torch, L, oracle_mod):
+    """The paper-mode source at the 55-atom 257^3 workload: kind-1 quartic
+    monopoles (no analytic l-terms), the tabulated l >= 1 density inside the
+    spheres, the interstitial density outside; every node against the oracle,
+    then the solve to 1e-10 from it"""
+    say("paper-mode source, 257^3 config 3")
+    w = I.config(3)
+    xs = oracle_mod.mesh_for(w.axes)
+    r = I.muffin_tin_radii(w.atoms)
+    for a, ra in zip(w.atoms, r):
+        a.kind, a.rho_R, a.drho_R, a.radius, a.lmax, a.clm = 1, 0.035, -0.089, ra, 0, np.zeros(0)
+    A = I.atom_arrays(w.atoms)
+    c = A["centers"]
+    tab = I.sphere_density(I.config(3).atoms, radii=r)
+    coef, occ = I.basis_coefficients(len(r), seed=37)
+    g = L.Grid(*xs)
+    S = L.Spheres(g, c, r)
+    ri = g.interstitial_density(c, r, I.LASTO_SHELLS, dev(torch, coef), occ)
+    rho = g.pseudo_density(w.atoms, rho_interstitial=ri)
+    S.density_terms(dev(torch, tab), rho, lmin=1)
+    got = rho.cpu().numpy()
+    # the oracle: the interstitial density at sampled nodes (its full grid
+    # would take hours), the pseudo-density and the terms at every node
+    want_q = oracle_mod.pseudo_density(xs, A)
+    oracle_mod.sphere_density_terms(xs, c, r, I.R_MIN, tab, 1, want_q)
+    ri_h = ri.cpu().numpy()
+    assert np.abs((got - ri_h) - want_q).max() <= 1e-12 * np.abs(want_q).max()
+    rng = np.random.default_rng(38)
+    idx = rng.integers(0, len(xs[0]), size=(200, 3))
+    pts = np.stack([xs[0][idx[:, 0]], xs[1][idx[:, 1]], xs[2][idx[:, 2]]], axis=1)
+    inside = (((pts[:, None, :] - c[None]) ** 2).sum(-1) < r[None] ** 2).any(axis=1)
+    want_i = oracle_mod.density_points(c, I.LASTO_SHELLS, coef, occ, pts[~inside])
+    got_i = ri_h[idx[:, 2], idx[:, 1], idx[:, 0]]
+    assert np.all(got_i[inside] == 0.0)
+    assert np.abs(got_i[~inside] - want_i).max() <= 1e-10 * np.abs(want_i).max()
+    v = g.empty()
+    info = g.poisson_solve(rho, v, rtol=1e-10, precision=1)
+    say("  solve from the paper-mode source: rel %.2e, %d refinements" % (info["rel_resid"], info["refinements"]))
+    assert info["rel_resid"] <= 1e-10
+    S.close()
+    g.close()
