@@ -1039,7 +1039,9 @@ size_t interstitial_lds_bytes(int nt, int kpa)
     return sizeof(double) * ((size_t)kpa * id_ldb(nt) + (size_t)(ID_NT / 64) * 16 * kpa);
 }
 
-template <int NT>
+// PF > 0: the next atom's coefficient rows are fetched into PF registers per
+// thread while the current atom's products run (kpa * 16 NT <= PF * ID_NT)
+template <int NT, int PF>
 __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const double4* __restrict__ atoms, int n_atoms,
                                                         const double4* __restrict__ shells, int n_shells, int nbpa,
                                                         int kpa, const double* __restrict__ coef, int n_occ, int c0,
@@ -1063,12 +1065,33 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
     for (int t = 0; t < NT; ++t) acc[t] = dbl4v{0.0, 0.0, 0.0, 0.0};
     double* ph = Ph + ((size_t)wid * 16 + p16) * kpa;
     const double* phw = Ph + (size_t)wid * 16 * kpa;
+    double pre[PF > 0 ? PF : 1];
+    auto fetch = [&](int a) {
+        const double* crow = coef + (size_t)a * nbpa * n_occ;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e = threadIdx.x + q * ID_NT;
+            const int r = e / NC, c = e - r * NC, col = c0 + c;
+            pre[q] = (r < nbpa && col < n_occ) ? crow[(size_t)r * n_occ + col] : 0.0;
+        }
+    };
+    if (PF > 0) fetch(0);
     for (int a = 0; a < n_atoms; ++a) {
         __syncthreads();   // the previous atom's products are done with Bs and Ph
-        const double* crow = coef + (size_t)a * nbpa * n_occ;
-        for (int e = threadIdx.x; e < kpa * NC; e += ID_NT) {
-            const int r = e / NC, c = e - r * NC, col = c0 + c;
-            Bs[r * LDB + c] = (r < nbpa && col < n_occ) ? crow[(size_t)r * n_occ + col] : 0.0;
+        if (PF > 0) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int e = threadIdx.x + q * ID_NT;
+                const int r = e / NC, c = e - r * NC;
+                if (r < kpa) Bs[r * LDB + c] = pre[q];
+            }
+            if (a + 1 < n_atoms) fetch(a + 1);   // in flight during this atom's work
+        } else {
+            const double* crow = coef + (size_t)a * nbpa * n_occ;
+            for (int e = threadIdx.x; e < kpa * NC; e += ID_NT) {
+                const int r = e / NC, c = e - r * NC, col = c0 + c;
+                Bs[r * LDB + c] = (r < nbpa && col < n_occ) ? crow[(size_t)r * n_occ + col] : 0.0;
+            }
         }
         const double4 A = atoms[a];
         const double dx = px - A.x, dy = py - A.y, dz = pz - A.z;
@@ -1124,28 +1147,44 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
     }
 }
 
-template <int NT>
-static hipError_t launch_interstitial_nt(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells,
-                                         int n_shells, int nbpa, int kpa, const double* coef, int n_occ, int c0,
-                                         const double* occ, int accumulate, double* rho)
+template <int NT, int PF>
+static hipError_t launch_interstitial_kernel(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells,
+                                             int n_shells, int nbpa, int kpa, const double* coef, int n_occ, int c0,
+                                             const double* occ, int accumulate, double* rho)
 {
     const LevelView& L = g->cview;
     const size_t N = (size_t)L.nx * L.ny * L.nz;
     const size_t lds = interstitial_lds_bytes(NT, kpa);
     if (lds > 65536)
-        if (hipError_t e = hipFuncSetAttribute((const void*)k_interstitial<NT>,
+        if (hipError_t e = hipFuncSetAttribute((const void*)k_interstitial<NT, PF>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             e != hipSuccess)
             return e;
-    hipLaunchKernelGGL(k_interstitial<NT>, dim3((unsigned)((N + ID_PTS - 1) / ID_PTS)), dim3(ID_NT), lds, g->stream, L,
-                       atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, accumulate, rho);
+    hipLaunchKernelGGL((k_interstitial<NT, PF>), dim3((unsigned)((N + ID_PTS - 1) / ID_PTS)), dim3(ID_NT), lds,
+                       g->stream, L, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, accumulate,
+                       rho);
     return hipGetLastError();
 }
 
+// up to 32 functions per atom (kpa <= 32) the next atom's rows are
+// prefetched into registers; more take the plain staging
+template <int NT>
+static hipError_t launch_interstitial_nt(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells,
+                                         int n_shells, int nbpa, int kpa, const double* coef, int n_occ, int c0,
+                                         const double* occ, int accumulate, double* rho)
+{
+    // (more than eight tiles with the prefetch exceed 256 registers per lane)
+    constexpr int PF = NT <= 8 ? (32 * 16 * NT + ID_NT - 1) / ID_NT : 0;
+    if (PF > 0 && kpa <= 32)
+        return launch_interstitial_kernel<NT, PF>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ,
+                                                  accumulate, rho);
+    return launch_interstitial_kernel<NT, 0>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ,
+                                             accumulate, rho);
+}
+
 // The states in chunks of at most LASTO_ID_CHUNK (160: ten column tiles, two
-// waves per SIMD and three workgroups' LDS per CU at 25 functions per atom;
-// longer chunks need more than 128 registers per lane); the first chunk
-// writes rho, the others add.
+// waves per SIMD; launches of at most eight tiles also prefetch the next
+// atom's rows); the first chunk writes rho, the others add.
 #ifndef LASTO_ID_CHUNK
 #define LASTO_ID_CHUNK 160
 #endif
