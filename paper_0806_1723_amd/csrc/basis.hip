@@ -16,9 +16,10 @@ extern "C" lasto_status lasto_interstitial_density(lasto_grid g, int n_atoms, co
         return fail(LASTO_ERR_ARG, "lasto_interstitial_density: NULL argument or empty basis");
     if (n_shells > 64) return fail(LASTO_ERR_ARG, "lasto_interstitial_density: at most 64 shells");
     std::vector<double4> sh(n_shells);
-    int nbpa = 0;
+    int nbpa = 0, lmax = 0;
     for (int s = 0; s < n_shells; ++s) {
         const lasto_shell& S = shells[s];
+        lmax = std::max(lmax, S.l);
         if (S.l < 0 || S.l > 4 || S.n < S.l + 1 || S.n > 16 || !(S.zeta > 0.0) || !std::isfinite(S.zeta))
             return fail(LASTO_ERR_ARG, "lasto_interstitial_density: shells need 0 <= l <= 4, l + 1 <= n <= 16, "
                                        "zeta > 0");
@@ -55,7 +56,7 @@ extern "C" lasto_status lasto_interstitial_density(lasto_grid g, int n_atoms, co
     LASTO_HIP(hipMemcpyAsync(d_sh, sh.data(), sizeof(double4) * n_shells, hipMemcpyHostToDevice, g->stream));
     LASTO_HIP(hipMemcpyAsync(d_occ, occ, sizeof(double) * n_occ, hipMemcpyHostToDevice, g->stream));
     LASTO_HIP(hipStreamSynchronize(g->stream));   // the host tables may go once copied
-    LASTO_HIP(launch_interstitial(g, d_at, n_atoms, d_sh, n_shells, nbpa, coef, n_occ, d_occ, rho_out));
+    LASTO_HIP(launch_interstitial(g, d_at, n_atoms, d_sh, n_shells, lmax, nbpa, coef, n_occ, d_occ, rho_out));
     return LASTO_OK;
 }
 

@@ -413,7 +413,7 @@ hipError_t launch_energy_grid(lasto_grid g, const double* v, const double* rho, 
 // [n_shells][4] (n, l, offset within the atom's basis, zeta), coef
 // [n_atoms * nbpa][n_occ], occ [n_occ] (device)
 hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells, int n_shells,
-                               int nbpa, const double* coef, int n_occ, const double* occ, double* rho);
+                               int lmax, int nbpa, const double* coef, int n_occ, const double* occ, double* rho);
 // interstitial matrix elements: node weights vol * (outside every sphere),
 // then the 64 x 64 blocks (r <= c) of S and H over n_chunks node chunks
 hipError_t launch_node_weights(lasto_grid g, const double4* atoms, int n_atoms, double* w);

@@ -1041,7 +1041,7 @@ size_t interstitial_lds_bytes(int nt, int kpa)
 
 // PF > 0: the next atom's coefficient rows are fetched into PF registers per
 // thread while the current atom's products run (kpa * 16 NT <= PF * ID_NT)
-template <int NT, int PF>
+template <int NT, int PF, int LMAX>
 __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const double4* __restrict__ atoms, int n_atoms,
                                                         const double4* __restrict__ shells, int n_shells, int nbpa,
                                                         int kpa, const double* __restrict__ coef, int n_occ, int c0,
@@ -1065,14 +1065,16 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
     for (int t = 0; t < NT; ++t) acc[t] = dbl4v{0.0, 0.0, 0.0, 0.0};
     double* ph = Ph + ((size_t)wid * 16 + p16) * kpa;
     const double* phw = Ph + (size_t)wid * 16 * kpa;
+    // staging: wave w takes rows w, w + 4, ..., each lane columns lane,
+    // lane + 64, ... (NC is a multiple of 16, so the last pass may be partial)
+    constexpr int CPL = (NC + 63) / 64;   // column passes per row
     double pre[PF > 0 ? PF : 1];
     auto fetch = [&](int a) {
-        const double* crow = coef + (size_t)a * nbpa * n_occ;
+        const double* crow = coef + (size_t)a * nbpa * n_occ + c0;
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int e = threadIdx.x + q * ID_NT;
-            const int r = e / NC, c = e - r * NC, col = c0 + c;
-            pre[q] = (r < nbpa && col < n_occ) ? crow[(size_t)r * n_occ + col] : 0.0;
+            const int r = wid + 4 * (q / CPL), c = lane + 64 * (q % CPL);
+            pre[q] = (r < nbpa && c < NC && c0 + c < n_occ) ? crow[(size_t)r * n_occ + c] : 0.0;
         }
     };
     if (PF > 0) fetch(0);
@@ -1081,29 +1083,30 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
         if (PF > 0) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                const int e = threadIdx.x + q * ID_NT;
-                const int r = e / NC, c = e - r * NC;
-                if (r < kpa) Bs[r * LDB + c] = pre[q];
+                const int r = wid + 4 * (q / CPL), c = lane + 64 * (q % CPL);
+                if (r < kpa && c < NC) Bs[r * LDB + c] = pre[q];
             }
             if (a + 1 < n_atoms) fetch(a + 1);   // in flight during this atom's work
         } else {
-            const double* crow = coef + (size_t)a * nbpa * n_occ;
-            for (int e = threadIdx.x; e < kpa * NC; e += ID_NT) {
-                const int r = e / NC, c = e - r * NC, col = c0 + c;
-                Bs[r * LDB + c] = (r < nbpa && col < n_occ) ? crow[(size_t)r * n_occ + col] : 0.0;
-            }
+            const double* crow = coef + (size_t)a * nbpa * n_occ + c0;
+            for (int r = wid; r < kpa; r += 4)
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    const int c = lane + 64 * q;
+                    if (c < NC) Bs[r * LDB + c] = (r < nbpa && c0 + c < n_occ) ? crow[(size_t)r * n_occ + c] : 0.0;
+                }
         }
         const double4 A = atoms[a];
         const double dx = px - A.x, dy = py - A.y, dz = pz - A.z;
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
         double S[25];
-        solid_harmonics(dx, dy, dz, 4, S);
+        solid_harmonics(dx, dy, dz, LMAX, S);   // the shells' largest l is LMAX
         for (int s = grp; s < n_shells; s += 4) {
             const double4 sh = shells[s];   // n, l, offset within the atom, zeta
             const int n = (int)sh.x, l = (int)sh.y, off = (int)sh.z;
             const double radial = ipow(r, n - 1 - l) * exp(-sh.w * r);
 #pragma unroll
-            for (int ll = 0; ll <= 4; ++ll)
+            for (int ll = 0; ll <= LMAX; ++ll)
                 if (ll == l) {
 #pragma unroll
                     for (int m = 0; m <= 2 * ll; ++m) ph[off + m] = radial * S[ll * ll + m];
@@ -1147,7 +1150,7 @@ __global__ __launch_bounds__(ID_NT) void k_interstitial(LevelView L, const doubl
     }
 }
 
-template <int NT, int PF>
+template <int NT, int PF, int LMAX>
 static hipError_t launch_interstitial_kernel(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells,
                                              int n_shells, int nbpa, int kpa, const double* coef, int n_occ, int c0,
                                              const double* occ, int accumulate, double* rho)
@@ -1156,11 +1159,11 @@ static hipError_t launch_interstitial_kernel(lasto_grid g, const double4* atoms,
     const size_t N = (size_t)L.nx * L.ny * L.nz;
     const size_t lds = interstitial_lds_bytes(NT, kpa);
     if (lds > 65536)
-        if (hipError_t e = hipFuncSetAttribute((const void*)k_interstitial<NT, PF>,
+        if (hipError_t e = hipFuncSetAttribute((const void*)k_interstitial<NT, PF, LMAX>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             e != hipSuccess)
             return e;
-    hipLaunchKernelGGL((k_interstitial<NT, PF>), dim3((unsigned)((N + ID_PTS - 1) / ID_PTS)), dim3(ID_NT), lds,
+    hipLaunchKernelGGL((k_interstitial<NT, PF, LMAX>), dim3((unsigned)((N + ID_PTS - 1) / ID_PTS)), dim3(ID_NT), lds,
                        g->stream, L, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, accumulate,
                        rho);
     return hipGetLastError();
@@ -1168,18 +1171,19 @@ static hipError_t launch_interstitial_kernel(lasto_grid g, const double4* atoms,
 
 // up to 32 functions per atom (kpa <= 32) the next atom's rows are
 // prefetched into registers; more take the plain staging
-template <int NT>
+template <int NT, int LMAX>
 static hipError_t launch_interstitial_nt(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells,
                                          int n_shells, int nbpa, int kpa, const double* coef, int n_occ, int c0,
                                          const double* occ, int accumulate, double* rho)
 {
     // (more than eight tiles with the prefetch exceed 256 registers per lane)
-    constexpr int PF = NT <= 8 ? (32 * 16 * NT + ID_NT - 1) / ID_NT : 0;
+    // rows per wave (kpa <= 32: 8) times column passes per row
+    constexpr int PF = NT <= 8 ? 8 * ((16 * NT + 63) / 64) : 0;
     if (PF > 0 && kpa <= 32)
-        return launch_interstitial_kernel<NT, PF>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ,
-                                                  accumulate, rho);
-    return launch_interstitial_kernel<NT, 0>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ,
-                                             accumulate, rho);
+        return launch_interstitial_kernel<NT, PF, LMAX>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0,
+                                                        occ, accumulate, rho);
+    return launch_interstitial_kernel<NT, 0, LMAX>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0,
+                                                   occ, accumulate, rho);
 }
 
 // The states in chunks of at most LASTO_ID_CHUNK (160: ten column tiles, two
@@ -1188,8 +1192,10 @@ static hipError_t launch_interstitial_nt(lasto_grid g, const double4* atoms, int
 #ifndef LASTO_ID_CHUNK
 #define LASTO_ID_CHUNK 160
 #endif
-hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells, int n_shells,
-                               int nbpa, const double* coef, int n_occ, const double* occ, double* rho)
+template <int LMAX>
+static hipError_t launch_interstitial_l(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells,
+                                        int n_shells, int nbpa, const double* coef, int n_occ, const double* occ,
+                                        double* rho)
 {
     const int kpa = (nbpa + 3) & ~3;
     constexpr int CHUNK = LASTO_ID_CHUNK;
@@ -1199,7 +1205,7 @@ hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, 
         const int acc = c0 > 0;
         hipError_t e;
 #define LASTO_ID_CASE(T) \
-    e = launch_interstitial_nt<T>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho)
+    e = launch_interstitial_nt<T, LMAX>(g, atoms, n_atoms, shells, n_shells, nbpa, kpa, coef, n_occ, c0, occ, acc, rho)
         if (tiles <= 1) LASTO_ID_CASE(1);
         else if (tiles <= 2) LASTO_ID_CASE(2);
         else if (tiles <= 4) LASTO_ID_CASE(4);
@@ -1214,6 +1220,14 @@ hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, 
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// harmonics up to l = 3 when no shell goes higher (the Table 1 basis), else 4
+hipError_t launch_interstitial(lasto_grid g, const double4* atoms, int n_atoms, const double4* shells, int n_shells,
+                               int lmax, int nbpa, const double* coef, int n_occ, const double* occ, double* rho)
+{
+    if (lmax <= 3) return launch_interstitial_l<3>(g, atoms, n_atoms, shells, n_shells, nbpa, coef, n_occ, occ, rho);
+    return launch_interstitial_l<4>(g, atoms, n_atoms, shells, n_shells, nbpa, coef, n_occ, occ, rho);
 }
 
 // ------------------------------------------ interstitial matrix elements
