@@ -68,9 +68,10 @@ extern "C" lasto_status lasto_matrix_elements(lasto_grid g, const double* v, int
         return fail(LASTO_ERR_ARG, "lasto_matrix_elements: NULL argument or empty basis");
     if (n_shells > 64) return fail(LASTO_ERR_ARG, "lasto_matrix_elements: at most 64 shells");
     std::vector<double4> sh(n_shells);
-    int nbpa = 0;
+    int nbpa = 0, lmax = 0;
     for (int s = 0; s < n_shells; ++s) {
         const lasto_shell& Q = shells[s];
+        lmax = std::max(lmax, Q.l);
         if (Q.l < 0 || Q.l > 4 || Q.n < Q.l + 1 || Q.n > 16 || !(Q.zeta > 0.0) || !std::isfinite(Q.zeta))
             return fail(LASTO_ERR_ARG, "lasto_matrix_elements: shells need 0 <= l <= 4, l + 1 <= n <= 16, zeta > 0");
         sh[s] = double4{(double)Q.n, (double)Q.l, (double)nbpa, Q.zeta};
@@ -122,8 +123,8 @@ extern "C" lasto_status lasto_matrix_elements(lasto_grid g, const double* v, int
     if (e == hipSuccess) e = hipMemcpyAsync(d_pr, pr.data(), sizeof(int2) * n_pairs, hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess) e = launch_node_weights(g, d_at, n_atoms, w);
     if (e == hipSuccess)
-        e = launch_matrix_elements(g, w, v, d_at, n_atoms, d_sh, n_shells, nbpa, n_basis, d_pr, n_pairs, n_chunks,
-                                   partials, S, H);
+        e = launch_matrix_elements(g, w, v, d_at, n_atoms, d_sh, n_shells, lmax, nbpa, n_basis, d_pr, n_pairs,
+                                   n_chunks, partials, S, H);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     release();
     if (e != hipSuccess) return fail(LASTO_ERR_HIP, std::string("lasto_matrix_elements: ") + hipGetErrorString(e));

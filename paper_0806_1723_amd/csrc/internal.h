@@ -420,8 +420,8 @@ hipError_t launch_node_weights(lasto_grid g, const double4* atoms, int n_atoms, 
 int matrix_block_count(int n_basis);
 size_t matrix_partial_doubles(int n_pairs, int n_chunks);
 hipError_t launch_matrix_elements(lasto_grid g, const double* w, const double* v, const double4* atoms, int n_atoms,
-                                  const double4* shells, int n_shells, int nbpa, int n_basis, const int2* pairs,
-                                  int n_pairs, int n_chunks, double* partials, double* S, double* H);
+                                  const double4* shells, int n_shells, int lmax, int nbpa, int n_basis,
+                                  const int2* pairs, int n_pairs, int n_chunks, double* partials, double* S, double* H);
 void free_fdm(lasto_grid g);
 hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_atom, int n_atoms,
                                double* out);

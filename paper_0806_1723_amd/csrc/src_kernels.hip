@@ -1285,6 +1285,7 @@ __device__ __forceinline__ double kinetic_radial(int n, int l, double zeta, doub
     return 0.5 * t * e;
 }
 
+template <int LMAX>
 __global__ __launch_bounds__(ME_NT) void k_matrix_elements(LevelView L, const double* __restrict__ w,
                                                            const double* __restrict__ v,
                                                            const double4* __restrict__ atoms, int n_atoms,
@@ -1335,7 +1336,7 @@ __global__ __launch_bounds__(ME_NT) void k_matrix_elements(LevelView L, const do
             const double r = sqrt(dx * dx + dy * dy + dz * dz);
             const double vp = v[node];
             double S[25];
-            solid_harmonics(dx, dy, dz, 4, S);
+            solid_harmonics(dx, dy, dz, LMAX, S);   // the shells' largest l is LMAX
             for (int s = 0; s < n_shells; ++s) {
                 const double4 sh = shells[s];
                 const int n = (int)sh.x, l = (int)sh.y;
@@ -1351,7 +1352,7 @@ __global__ __launch_bounds__(ME_NT) void k_matrix_elements(LevelView L, const do
                 }
                 const double f = row ? wt : 1.0;
 #pragma unroll
-                for (int ll = 0; ll <= 4; ++ll)
+                for (int ll = 0; ll <= LMAX; ++ll)
                     if (ll == l) {
 #pragma unroll
                         for (int m = 0; m <= 2 * ll; ++m) {
@@ -1443,14 +1444,18 @@ size_t matrix_partial_doubles(int n_pairs, int n_chunks)
 }
 
 hipError_t launch_matrix_elements(lasto_grid g, const double* w, const double* v, const double4* atoms, int n_atoms,
-                                  const double4* shells, int n_shells, int nbpa, int n_basis, const int2* pairs,
-                                  int n_pairs, int n_chunks, double* partials, double* S, double* H)
+                                  const double4* shells, int n_shells, int lmax, int nbpa, int n_basis,
+                                  const int2* pairs, int n_pairs, int n_chunks, double* partials, double* S, double* H)
 {
     const LevelView& L = g->cview;
     const size_t N = (size_t)L.nx * L.ny * L.nz;
     const unsigned chunk = (unsigned)((N + n_chunks - 1) / n_chunks);
-    hipLaunchKernelGGL(k_matrix_elements, dim3((unsigned)(n_pairs * n_chunks)), dim3(ME_NT), 0, g->stream, L, w, v,
-                       atoms, n_atoms, shells, n_shells, nbpa, n_basis, pairs, n_chunks, chunk, partials);
+    if (lmax <= 3)
+        hipLaunchKernelGGL(k_matrix_elements<3>, dim3((unsigned)(n_pairs * n_chunks)), dim3(ME_NT), 0, g->stream, L, w,
+                           v, atoms, n_atoms, shells, n_shells, nbpa, n_basis, pairs, n_chunks, chunk, partials);
+    else
+        hipLaunchKernelGGL(k_matrix_elements<4>, dim3((unsigned)(n_pairs * n_chunks)), dim3(ME_NT), 0, g->stream, L, w,
+                           v, atoms, n_atoms, shells, n_shells, nbpa, n_basis, pairs, n_chunks, chunk, partials);
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     hipLaunchKernelGGL(k_matrix_reduce, dim3(n_pairs), dim3(256), 0, g->stream, partials, pairs, n_chunks, n_basis, S, H);
     return hipGetLastError();
