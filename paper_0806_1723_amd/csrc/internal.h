@@ -402,8 +402,9 @@ hipError_t launch_sphere_project(lasto_grid g, const double* v, const SphereAtom
                                  const double4* rule, int npts, double* vlmR);
 hipError_t launch_radial_solve(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* vlmR,
                                const double* rho_lm, double* v_lm);
+// per (atom, LM) row of each copy: int_0^R V_LM rho_LM r^2 dr into e_row [n_batch][n_atoms][25]
 hipError_t launch_sphere_energy(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* v_lm,
-                                const double* rho_lm, double* e_atom);
+                                const double* rho_lm, double* e_row);
 int energy_grid_blocks(const LevelView& L);   // partials per copy of launch_energy_grid
 hipError_t launch_sphere_terms(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* rho_lm,
                                int lmin, double* rho);
@@ -423,7 +424,7 @@ hipError_t launch_matrix_elements(lasto_grid g, const double* w, const double* v
                                   const double4* shells, int n_shells, int lmax, int nbpa, int n_basis,
                                   const int2* pairs, int n_pairs, int n_chunks, double* partials, double* S, double* H);
 void free_fdm(lasto_grid g);
-hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_atom, int n_atoms,
+hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_row, int nrows,
                                double* out);
 
 // device table block builder

@@ -17,7 +17,7 @@ struct lasto_spheres_s {
     double4* rule = nullptr;       // device [npts]: direction, weight
     int nparts = 0;                // grid partials per copy
     double* partials = nullptr;    // device [n_batch][nparts]
-    double* e_atom = nullptr;      // device [n_batch][n_atoms]
+    double* e_row = nullptr;       // device [n_batch][n_atoms][25]
     double* e_dev = nullptr;       // device [n_batch][2]
     double* e_host = nullptr;      // pinned [n_batch][2]
 };
@@ -63,7 +63,7 @@ void free_spheres(lasto_spheres s)
     (void)hipFree(s->atoms);
     (void)hipFree(s->rule);
     (void)hipFree(s->partials);
-    (void)hipFree(s->e_atom);
+    (void)hipFree(s->e_row);
     (void)hipFree(s->e_dev);
     if (s->e_host) (void)hipHostFree(s->e_host);
     delete s;
@@ -130,7 +130,7 @@ extern "C" lasto_status lasto_spheres_create(lasto_grid g, int n_atoms, const do
     if (e == hipSuccess) e = hipMalloc(&s->atoms, sizeof(SphereAtom) * n_atoms);
     if (e == hipSuccess) e = hipMalloc(&s->rule, sizeof(double4) * rule.size());
     if (e == hipSuccess) e = hipMalloc(&s->partials, sizeof(double) * (size_t)nb * s->nparts);
-    if (e == hipSuccess) e = hipMalloc(&s->e_atom, sizeof(double) * (size_t)nb * n_atoms);
+    if (e == hipSuccess) e = hipMalloc(&s->e_row, sizeof(double) * (size_t)nb * n_atoms * 25);
     if (e == hipSuccess) e = hipMalloc(&s->e_dev, sizeof(double) * 2 * nb);
     if (e == hipSuccess) e = hipHostMalloc(&s->e_host, sizeof(double) * 2 * nb, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -187,8 +187,8 @@ extern "C" lasto_status lasto_sphere_energy(lasto_spheres s, const double* v, co
     lasto_grid g = s->g;
     const int nb = g->n_batch;
     LASTO_HIP(launch_energy_grid(g, v, rho, s->atoms, s->n_atoms, s->partials));
-    LASTO_HIP(launch_sphere_energy(g, s->atoms, s->n_atoms, s->n_rad, v_lm, rho_lm, s->e_atom));
-    LASTO_HIP(launch_energy_final(g, s->partials, s->nparts, s->e_atom, s->n_atoms, s->e_dev));
+    LASTO_HIP(launch_sphere_energy(g, s->atoms, s->n_atoms, s->n_rad, v_lm, rho_lm, s->e_row));
+    LASTO_HIP(launch_energy_final(g, s->partials, s->nparts, s->e_row, s->n_atoms * 25, s->e_dev));
     LASTO_HIP(hipMemcpyAsync(s->e_host, s->e_dev, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, g->stream));
     LASTO_HIP(hipStreamSynchronize(g->stream));
     std::copy(s->e_host, s->e_host + 2 * nb, e_out);

@@ -671,50 +671,36 @@ hipError_t launch_radial_solve(lasto_grid g, const SphereAtom* atoms, int n_atom
     return hipGetLastError();
 }
 
-constexpr int SE_NT = 256;
-
-// One workgroup per (atom, right-hand side): sum_LM int_0^R V_LM rho_LM r^2 dr,
-// in t: g = V rho r^3, the piece [0, r_0] as g(r_0)/3, then the intervals.
-// Waves take LM = w, w + 4, ... (uniform trip count: 7 rounds of 4).
-__global__ __launch_bounds__(SE_NT) void k_sphere_energy(const SphereAtom* __restrict__ atoms, int n_atoms, int n,
-                                                         const double* __restrict__ v_lm,
-                                                         const double* __restrict__ rho_lm, double* __restrict__ e_atom)
+// One wave per (LM, atom, right-hand side): int_0^R V_LM rho_LM r^2 dr, in
+// t: g = V rho r^3, the piece [0, r_0] as g(r_0)/3, then the intervals
+// (each lane sums its strided intervals, the wave adds the lanes in a fixed
+// tree). e_row [n_batch][n_atoms][25].
+__global__ __launch_bounds__(64) void k_sphere_energy(const SphereAtom* __restrict__ atoms, int n_atoms, int n,
+                                                      const double* __restrict__ v_lm,
+                                                      const double* __restrict__ rho_lm, double* __restrict__ e_row)
 {
-    extern __shared__ double se_lds[];   // [SE_NT / 64][n]
-    __shared__ double per_lm[28];
-    const int a = blockIdx.x, b = blockIdx.y, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    extern __shared__ double se_lds[];   // [n]
+    const int lm = blockIdx.x, a = blockIdx.y, b = blockIdx.z, lane = threadIdx.x;
     const SphereAtom A = atoms[a];
-    double* g = se_lds + (size_t)wid * n;
-    for (int base = 0; base < 28; base += SE_NT / 64) {
-        const int lm = base + wid;
-        if (lm < 25) {
-            const size_t row = (((size_t)b * n_atoms + a) * 25 + lm) * n;
-            for (int k = lane; k < n; k += 64) {
-                const double rk = radial_node(A, n, k);
-                g[k] = v_lm[row + k] * rho_lm[row + k] * (rk * rk * rk);
-            }
-        }
-        __syncthreads();
-        if (lm < 25) {
-            double s = 0.0;
-            for (int k = lane; k < n - 1; k += 64) s += cubic_interval(g, n, k, A.D);
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
-            if (lane == 0) per_lm[lm] = g[0] / 3.0 + s;
-        }
-        __syncthreads();
+    const size_t row = ((size_t)b * n_atoms + a) * 25 + lm;
+    const double* v = v_lm + row * n;
+    const double* rho = rho_lm + row * n;
+    for (int k = lane; k < n; k += 64) {
+        const double rk = radial_node(A, n, k);
+        se_lds[k] = v[k] * rho[k] * (rk * rk * rk);
     }
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int t = 0; t < 25; ++t) s += per_lm[t];
-        e_atom[(size_t)b * n_atoms + a] = s;
-    }
+    __syncthreads();
+    double s = 0.0;
+    for (int k = lane; k < n - 1; k += 64) s += cubic_interval(se_lds, n, k, A.D);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+    if (lane == 0) e_row[row] = se_lds[0] / 3.0 + s;
 }
 
 hipError_t launch_sphere_energy(lasto_grid g, const SphereAtom* atoms, int n_atoms, int n_rad, const double* v_lm,
-                                const double* rho_lm, double* e_atom)
+                                const double* rho_lm, double* e_row)
 {
-    hipLaunchKernelGGL(k_sphere_energy, dim3(n_atoms, g->n_batch), dim3(SE_NT), sizeof(double) * (SE_NT / 64) * n_rad,
-                       g->stream, atoms, n_atoms, n_rad, v_lm, rho_lm, e_atom);
+    hipLaunchKernelGGL(k_sphere_energy, dim3(25, n_atoms, g->n_batch), dim3(64), sizeof(double) * n_rad, g->stream,
+                       atoms, n_atoms, n_rad, v_lm, rho_lm, e_row);
     return hipGetLastError();
 }
 
@@ -978,35 +964,37 @@ hipError_t launch_sphere_terms(lasto_grid g, const SphereAtom* atoms, int n_atom
     return hipGetLastError();
 }
 
-// out[b][0] = sum of the grid partials of copy b, out[b][1] = sum over atoms
-// of the sphere parts (fixed orders: strided per thread, then a tree).
+// out[b][0] = sum of the grid partials of copy b, out[b][1] = sum of the
+// sphere rows of copy b (fixed orders: strided per thread, then a tree).
 __global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ partials, int nparts,
-                                                      const double* __restrict__ e_atom, int n_atoms,
+                                                      const double* __restrict__ e_row, int nrows,
                                                       double* __restrict__ out)
 {
-    __shared__ double red[256];
+    __shared__ double red[2][256];
     const int b = blockIdx.x;
-    double s = 0.0;
+    double s = 0.0, e = 0.0;
     for (int t = threadIdx.x; t < nparts; t += 256) s += partials[(size_t)b * nparts + t];
-    red[threadIdx.x] = s;
+    for (int t = threadIdx.x; t < nrows; t += 256) e += e_row[(size_t)b * nrows + t];
+    red[0][threadIdx.x] = s;
+    red[1][threadIdx.x] = e;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double e = 0.0;
-        for (int a = 0; a < n_atoms; ++a) e += e_atom[(size_t)b * n_atoms + a];
-        out[2 * b] = red[0];
-        out[2 * b + 1] = e;
+        out[2 * b] = red[0][0];
+        out[2 * b + 1] = red[1][0];
     }
 }
 
-hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_atom, int n_atoms,
+hipError_t launch_energy_final(lasto_grid g, const double* partials, int nparts, const double* e_row, int nrows,
                                double* out)
 {
-    hipLaunchKernelGGL(k_energy_final, dim3(g->n_batch), dim3(256), 0, g->stream, partials, nparts, e_atom, n_atoms,
-                       out);
+    hipLaunchKernelGGL(k_energy_final, dim3(g->n_batch), dim3(256), 0, g->stream, partials, nparts, e_row, nrows, out);
     return hipGetLastError();
 }
 
