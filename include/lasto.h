@@ -388,8 +388,9 @@ lasto_status lasto_matrix_elements(lasto_grid g, const double* v, int n_atoms, c
  *   u = (S_z x S_y x S_x) [ (S_z^-1 x S_y^-1 x S_x^-1) b / (l_z + l_y + l_x) ],
  * b = 4 pi rho - A v_bc: six dense contractions along the axes on the FP64
  * matrix cores (rocBLAS GEMMs). Exact up to rounding; no iteration.
- *   rho, v: as lasto_poisson_solve (v's faces are set from bc/lmax_bc, its
- *     interior overwritten; a batched grid solves every copy).
+ *   rho, v: as lasto_poisson_solve (v's faces are set from bc/lmax_bc as
+ *     there: 0 zero, 1 multipole, 2 the faces of v as given; its interior is
+ *     overwritten; a batched grid solves every copy).
  *   info (may be NULL): iters = 1, rel_resid = max over copies of
  *     ||4 pi rho - A v||_W / ||4 pi rho - A v_bc||_W, batch_rel_resid, moments,
  *     ms_total.

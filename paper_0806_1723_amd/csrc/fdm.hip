@@ -266,7 +266,7 @@ extern "C" lasto_status lasto_fdm_solve(lasto_grid g, const double* rho, double*
 {
     const auto t0 = std::chrono::steady_clock::now();
     if (!g || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_fdm_solve: NULL argument");
-    if (bc < 0 || bc > 1 || lmax_bc < 0 || lmax_bc > 4) return fail(LASTO_ERR_ARG, "lasto_fdm_solve: bad bc/lmax_bc");
+    if (bc < 0 || bc > 2 || lmax_bc < 0 || lmax_bc > 4) return fail(LASTO_ERR_ARG, "lasto_fdm_solve: bad bc/lmax_bc");
     const LevelView& V = g->cview;
     if (V.nx < 3 || V.ny < 3 || V.nz < 3) return fail(LASTO_ERR_ARG, "lasto_fdm_solve: needs 3 nodes per axis");
     if (lasto_status st = fdm_init(g); st != LASTO_OK) return st;
@@ -281,9 +281,9 @@ extern "C" lasto_status lasto_fdm_solve(lasto_grid g, const double* rho, double*
         if (bc == 1) {
             LASTO_HIP(launch_moments(g, rb, g->moments + 25 * b));
             LASTO_HIP(launch_bc(g, 1, g->moments + 25 * b, lmax_bc, vb));
-        } else {
+        } else if (bc == 0) {
             LASTO_HIP(launch_bc(g, 0, g->moments, 0, vb));
-        }
+        }   // bc 2: the faces of v as given
         hipLaunchKernelGGL(k_fdm_rhs, dim3(blocks), dim3(256), 0, s, V, vb, rb, 4.0 * kPi, f->buf[0]);
         LASTO_LAUNCH_CHECK("k_fdm_rhs");
         rocblas_status e = contract(f, 0, f->Si[0], f->buf[0], f->buf[1]);

@@ -149,3 +149,15 @@ def test_paper_mode_pseudo_density_with_interstitial_density(torch, L, oracle_mo
     want = oracle_mod.pseudo_density(xs, I.atom_arrays(atoms), rho_inter=ri_o)
     assert np.abs(rho - want).max() <= 1e-12 * np.abs(want).max()
     g.close()
+
+
+def test_interstitial_density_argument_errors(torch, L):
+    x = np.linspace(-4, 4, 9)
+    g = L.Grid(x, x, x)
+    coef = torch.zeros((9, 2), dtype=torch.float64, device="cuda")
+    for shells in ([(1, 1, 1.0)], [(2, 0, 0.0)], [(6, 5, 1.0)], [(5, 4, 1.0)] * 8):
+        with pytest.raises(L.LastoError):
+            g.interstitial_density([[0, 0, 0]], [1.0], shells, coef, [2.0, 2.0])
+    with pytest.raises(L.LastoError):
+        g.interstitial_density([[0, 0, 0]], [-1.0], [(2, 0, 1.0)], coef, [2.0, 2.0])
+    g.close()

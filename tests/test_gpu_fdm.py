@@ -108,3 +108,24 @@ def test_fdm_full_size_257(torch, L, oracle_mod):
     say("  max rel diff to the FP64 multigrid solve at 1e-12: %.2e" % d)
     assert d <= 1e-9
     g.close()
+
+
+def test_fdm_faces_as_given_and_errors(torch, L, oracle_mod):
+    """bc = 2 keeps the caller's faces (here the multipole faces of a first
+    solve, and the interior of v is ignored); bad arguments are refused"""
+    say("fdm solve bc=2, errors")
+    w = I.config(2, n_override=65)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    v1 = g.empty()
+    g.fdm_solve(rho, v1, bc=1)
+    v2 = v1.clone()
+    v2[1:-1, 1:-1, 1:-1] = 123.0
+    info = g.fdm_solve(rho, v2, bc=2)
+    assert info["rel_resid"] <= 1e-12
+    assert (v2 - v1).abs().max().item() <= 1e-12 * v1.abs().max().item()
+    for kw in (dict(bc=3), dict(bc=1, lmax_bc=5)):
+        with pytest.raises(L.LastoError):
+            g.fdm_solve(rho, v2, **kw)
+    g.close()
