@@ -1258,18 +1258,14 @@ hipError_t launch_node_weights(lasto_grid g, const double4* atoms, int n_atoms, 
     return hipGetLastError();
 }
 
-__device__ __forceinline__ double rpow(double r, int e)
-{
-    return e >= 0 ? ipow(r, e) : 1.0 / ipow(r, -e);
-}
-
 // -1/2 Laplacian of r^(n-1) exp(-zeta r) y_lm, over S_lm = r^l y_lm (eq. (3.14)):
-// 1/2 [(l(l+1) - n(n-1)) r^(n-3-l) + 2 zeta n r^(n-2-l) - zeta^2 r^(n-1-l)] e;
-// the first term vanishes for n = l + 1, so no power below -1 appears
-__device__ __forceinline__ double kinetic_radial(int n, int l, double zeta, double r, double e)
+// 1/2 [(l(l+1) - n(n-1)) r^(n-3-l) + 2 zeta n r^(n-2-l) - zeta^2 r^(n-1-l)] e,
+// from p = r^(n-1-l) and ir = 1/r (the first term vanishes for n = l + 1, so
+// no power below -1 of r appears)
+__device__ __forceinline__ double kinetic_radial(int n, int l, double zeta, double p, double ir, double e)
 {
-    double t = -zeta * zeta * rpow(r, n - 1 - l) + 2.0 * zeta * n * rpow(r, n - 2 - l);
-    if (n != l + 1) t += (double)(l * (l + 1) - n * (n - 1)) * rpow(r, n - 3 - l);
+    double t = (-zeta * zeta + 2.0 * zeta * n * ir) * p;
+    if (n != l + 1) t += (double)(l * (l + 1) - n * (n - 1)) * p * ir * ir;
     return 0.5 * t * e;
 }
 
@@ -1325,6 +1321,8 @@ __global__ __launch_bounds__(ME_NT) void k_matrix_elements(LevelView L, const do
             const double vp = v[node];
             double S[25];
             solid_harmonics(dx, dy, dz, LMAX, S);   // the shells' largest l is LMAX
+            const double ir = wt != 0.0 ? 1.0 / r : 0.0;
+            double zeta_prev = -1.0, e = 0.0;   // consecutive shells of one exponent share exp
             for (int s = 0; s < n_shells; ++s) {
                 const double4 sh = shells[s];
                 const int n = (int)sh.x, l = (int)sh.y;
@@ -1334,9 +1332,13 @@ __global__ __launch_bounds__(ME_NT) void k_matrix_elements(LevelView L, const do
                 // on both sides, so no singular column value meets a zero weight
                 double phr = 0.0, kr = 0.0;
                 if (wt != 0.0) {
-                    const double e = exp(-sh.w * r);
-                    phr = ipow(r, n - 1 - l) * e;
-                    kr = kinetic_radial(n, l, sh.w, r, e);
+                    if (sh.w != zeta_prev) {
+                        e = exp(-sh.w * r);
+                        zeta_prev = sh.w;
+                    }
+                    const double p = ipow(r, n - 1 - l);
+                    phr = p * e;
+                    kr = kinetic_radial(n, l, sh.w, p, ir, e);
                 }
                 const double f = row ? wt : 1.0;
 #pragma unroll
