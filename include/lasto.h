@@ -161,6 +161,10 @@ typedef struct {
     int profile;        /* 1: time every finest-level smoother launch with HIP events (default 0) */
     int inner_first;    /* precision 1: inner steps of the first refinement, 0 = inner_iters (default 0);
                            its reduction is bounded by FP32 rounding of the operator sooner than later ones */
+    int coarse;         /* coarsest solve of the cycle: 0 (default) exact, by fast diagonalisation of the
+                           first level with at most 16384 nodes (each axis at most 34 nodes, the level below
+                           the finest, its block in one workgroup's LDS), else as 1; 1 red-black sweeps on
+                           every level down to the coarsest */
 } lasto_solve_opts;
 
 typedef struct {
@@ -178,6 +182,7 @@ typedef struct {
     int smooth_fp32;        /* launches among them that ran in FP32 */
     int n_batch;            /* right-hand sides solved (the grid's n_batch) */
     double batch_rel_resid[16]; /* rel_resid of each right-hand side (rel_resid is their maximum) */
+    int coarse_level;       /* level the cycle solved exactly by fast diagonalisation, -1 if none */
 } lasto_solve_info;
 
 void lasto_solve_opts_default(lasto_solve_opts* o);

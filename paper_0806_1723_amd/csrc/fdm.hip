@@ -248,6 +248,269 @@ static rocblas_status contract(FdmState* f, int d, const double* P, const double
                          mz, &zero, out, mx * my);
 }
 
+// ---------------------------------------------- coarsest solve of the cycle
+// The multigrid cycle's correction equation A e = f (zero faces) at one small
+// level, solved exactly by the same diagonalisation in one workgroup. The
+// level's interior is copied from the split layout into a dense
+// [copy][z][y][x] block in LDS, with the axis tables beside it (copied in
+// once per call: the large sweeps between calls evict them from the caches).
+// Each contraction step gives one thread one grid line, held in registers,
+// which it replaces by the line times an axis matrix, two rows at a time
+// (each pair read into registers by 16-byte LDS reads before its products);
+// every lane of a wave reads the same matrix entry, an LDS broadcast. Rows are
+// padded with zeros to MX entries. All six contractions run through one
+// rolled loop over the same code, so a call fetches a few KB of instructions
+// rather than a fully unrolled pass each (the code runs once per call, from a
+// cold instruction cache). A batched level solves each copy on its own
+// planes with the same z tables.
+// lanes of the workgroup (a line and two matrix rows in registers need more
+// than the 128 registers per lane that 1024 lanes allow)
+constexpr int CF_NT = 512;
+
+// element offsets of each axis's blocks in the table: S^-1 [m][MX],
+// S [m][MX], eigenvalues [m], each block starting on a multiple of 4
+struct CfTab {
+    int si[3], s[3], lam[3];
+    int total;
+};
+
+static CfTab cf_layout(const int m[3], int MX)
+{
+    CfTab t{};
+    int o = 0;
+    auto take = [&](int n) {
+        const int at = o;
+        o += (n + 3) & ~3;
+        return at;
+    };
+    for (int d = 0; d < 3; ++d) {
+        t.si[d] = take(m[d] * MX);
+        t.s[d] = take(m[d] * MX);
+        t.lam[d] = take(m[d]);
+    }
+    t.total = o;
+    return t;
+}
+
+template <typename T> struct CfVec;
+template <> struct CfVec<float> { using type = float4; };
+template <> struct CfVec<double> { using type = double2; };
+
+// row[0..MX) into registers by 16-byte LDS reads, all issued before use
+template <typename T, int MX>
+__device__ __forceinline__ void cf_load_row(const T* row, T (&a)[MX])
+{
+    using V = typename CfVec<T>::type;
+    constexpr int E = 16 / sizeof(T);
+#pragma unroll
+    for (int i = 0; i < MX; i += E) *reinterpret_cast<V*>(&a[i]) = *reinterpret_cast<const V*>(row + i);
+}
+
+// rows r and r + 1 of a matrix (row points at row r) times the register line v
+template <typename T, int MX>
+__device__ __forceinline__ void cf_rows2(const T* row, const T (&v)[MX], T& y0, T& y1)
+{
+    T a[MX], b[MX];
+    cf_load_row<T, MX>(row, a);
+    cf_load_row<T, MX>(row + MX, b);
+    T a0 = T(0), a1 = T(0), b0 = T(0), b1 = T(0);
+#pragma unroll
+    for (int i = 0; i < MX; i += 2) {
+        a0 = fma(a[i], v[i], a0);
+        a1 = fma(a[i + 1], v[i + 1], a1);
+        b0 = fma(b[i], v[i], b0);
+        b1 = fma(b[i + 1], v[i + 1], b1);
+    }
+    y0 = a0 + a1;
+    y1 = b0 + b1;
+}
+
+template <typename T, int MX>
+__device__ __forceinline__ T cf_row(const T* row, const T (&v)[MX])
+{
+    T a[MX];
+    cf_load_row<T, MX>(row, a);
+    T a0 = T(0), a1 = T(0);
+#pragma unroll
+    for (int i = 0; i < MX; i += 2) {
+        a0 = fma(a[i], v[i], a0);
+        a1 = fma(a[i + 1], v[i + 1], a1);
+    }
+    return a0 + a1;
+}
+
+// dense block index t (x fastest, copies stacked in z) -> split-layout index
+__device__ __forceinline__ size_t cf_split(const LevelView& V, int t, int mx, int my, int mz)
+{
+    const int i = t % mx, r = t / mx;
+    const int j = r % my, kb = r / my;
+    return sidx(V, i + 1, j + 1, (kb / mz) * V.nzc + 1 + kb % mz);
+}
+
+template <typename T, int MX>
+__global__ __launch_bounds__(CF_NT) void k_coarse_fdm(LevelView V, const T* __restrict__ f, T* __restrict__ u,
+                                                      const T* __restrict__ tab, CfTab tl)
+{
+    extern __shared__ unsigned char cf_smem[];
+    const int mx = V.nx - 2, my = V.ny - 2, mz = V.nzc - 2, nb = V.nz / V.nzc;
+    const int pxy = mx * my, pc = pxy * mz;   // nodes of a plane, of a copy
+    const int n = pc * nb;
+    T* w = reinterpret_cast<T*>(cf_smem);
+    T* tb = w + ((n + 3) & ~3);
+    // tables and f into LDS, eight loads in flight per lane
+    for (int t0 = 0; t0 < tl.total; t0 += 8 * CF_NT) {
+        T tmp[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int t = t0 + b * CF_NT + (int)threadIdx.x;
+            tmp[b] = t < tl.total ? tab[t] : T(0);
+        }
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int t = t0 + b * CF_NT + (int)threadIdx.x;
+            if (t < tl.total) tb[t] = tmp[b];
+        }
+    }
+    for (int t0 = 0; t0 < n; t0 += 8 * CF_NT) {
+        T tmp[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int t = t0 + b * CF_NT + (int)threadIdx.x;
+            tmp[b] = t < n ? f[cf_split(V, t, mx, my, mz)] : T(0);
+        }
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int t = t0 + b * CF_NT + (int)threadIdx.x;
+            if (t < n) w[t] = tmp[b];
+        }
+    }
+    __syncthreads();
+    // Seven steps on the block: S_x^-1, S_y^-1, S_z^-1, the division, S_z,
+    // S_y, S_x. A line of axis d starts at (line / A) B + (line % A) C with
+    // stride st: x lines (A, B, C, st) = (my, pxy, mx, 1), y lines
+    // (mx, pxy, 1, mx), z lines (pxy, pc, 1, pxy). A lane owns its line
+    // for the step, so it may overwrite it in place.
+    T v[MX];
+    for (int step = 0; step < 7; ++step) {
+        if (step == 3) {
+            for (int t = threadIdx.x; t < n; t += CF_NT) {
+                const int i = t % mx, r = t / mx;
+                w[t] = w[t] / (tb[tl.lam[0] + i] + tb[tl.lam[1] + r % my] + tb[tl.lam[2] + (r / my) % mz]);
+            }
+        } else {
+            const int d = step < 3 ? step : 6 - step;
+            const T* M = tb + (step < 3 ? tl.si[d] : tl.s[d]);
+            const int m = d == 0 ? mx : d == 1 ? my : mz;
+            const int A = d == 0 ? my : d == 1 ? mx : pxy;
+            const int B = d == 2 ? pc : pxy;
+            const int C = d == 0 ? mx : 1;
+            const int st = d == 0 ? 1 : d == 1 ? mx : pxy;
+            for (int line = threadIdx.x; line < n / m; line += CF_NT) {
+                T* base = w + (line / A) * B + (line % A) * C;
+#pragma unroll
+                for (int k = 0; k < MX; ++k) v[k] = k < m ? base[k * st] : T(0);
+                int r = 0;
+                for (; r + 1 < m; r += 2) {
+                    T y0, y1;
+                    cf_rows2<T, MX>(M + r * MX, v, y0, y1);
+                    base[r * st] = y0;
+                    base[(r + 1) * st] = y1;
+                }
+                if (r < m) base[r * st] = cf_row<T, MX>(M + r * MX, v);
+            }
+        }
+        __syncthreads();
+    }
+    // the block into e
+    for (int t = threadIdx.x; t < n; t += CF_NT) u[cf_split(V, t, mx, my, mz)] = w[t];
+}
+
+template <typename T, int MX>
+static hipError_t cf_allow_lds(int bytes)
+{
+    return hipFuncSetAttribute((const void*)k_coarse_fdm<T, MX>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+static size_t cf_lds_bytes(size_t elem, const int m[3], int nb, const CfTab& tl)
+{
+    const size_t cells = ((size_t)m[0] * m[1] * m[2] * nb + 3) & ~(size_t)3;
+    return elem * (cells + tl.total);
+}
+
+lasto_status build_coarse_fdm(lasto_grid g)
+{
+    g->cfdm_level = -1;
+    const int t = g->tail_top;
+    if (t < 1) return LASTO_OK;   // at the finest level the cycle would be the direct solve itself
+    const Level& L = g->lev[t];
+    int m[3], mmax = 0;
+    for (int d = 0; d < 3; ++d) {
+        m[d] = L.n[d] - 2;
+        if (m[d] < 1) return LASTO_OK;
+        mmax = std::max(mmax, m[d]);
+    }
+    if (mmax > 32) return LASTO_OK;   // (a line of at most 32 in registers)
+    const int MX = mmax <= 16 ? 16 : 32;
+    const CfTab tl = cf_layout(m, MX);
+    const int lim = tail_lds_limit();
+    if (lim <= 0 || cf_lds_bytes(sizeof(double), m, g->n_batch, tl) > (size_t)lim) return LASTO_OK;
+    std::vector<double> tab((size_t)tl.total, 0.0);
+    for (int d = 0; d < 3; ++d) {
+        const int n = m[d];
+        std::vector<double> lam(n), S((size_t)n * n), Si((size_t)n * n);
+        if (!axis_decomposition(L.hx[d].data(), L.n[d], lam.data(), S.data(), Si.data()))
+            return fail(LASTO_ERR_STATE, "lasto_grid_create: coarse-level eigen-decomposition did not converge");
+        for (int r = 0; r < n; ++r) {
+            for (int c = 0; c < n; ++c) {
+                tab[tl.si[d] + (size_t)r * MX + c] = Si[(size_t)r * n + c];
+                tab[tl.s[d] + (size_t)r * MX + c] = S[(size_t)r * n + c];
+            }
+            tab[tl.lam[d] + r] = lam[r];
+        }
+    }
+    std::vector<float> tabf(tab.begin(), tab.end());
+    hipError_t e = hipSuccess;
+    switch (MX) {
+        case 16: e = cf_allow_lds<double, 16>(lim); if (e == hipSuccess) e = cf_allow_lds<float, 16>(lim); break;
+        default: e = cf_allow_lds<double, 32>(lim); if (e == hipSuccess) e = cf_allow_lds<float, 32>(lim); break;
+    }
+    if (e == hipSuccess) e = hipMalloc(&g->cfdm_tab64, sizeof(double) * tab.size());
+    if (e == hipSuccess) e = hipMalloc(&g->cfdm_tab32, sizeof(float) * tabf.size());
+    if (e == hipSuccess) e = hipMemcpy(g->cfdm_tab64, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->cfdm_tab32, tabf.data(), sizeof(float) * tabf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(LASTO_ERR_HIP, std::string("lasto_grid_create: coarse tables: ") + hipGetErrorString(e));
+    g->cfdm_level = t;
+    g->cfdm_mx = MX;
+    return LASTO_OK;
+}
+
+void free_coarse_fdm(lasto_grid g)
+{
+    (void)hipFree(g->cfdm_tab64);
+    (void)hipFree(g->cfdm_tab32);
+    g->cfdm_tab64 = nullptr;
+    g->cfdm_tab32 = nullptr;
+    g->cfdm_level = -1;
+}
+
+template <typename T>
+hipError_t launch_coarse_fdm(lasto_grid g, const T* f, T* u, hipStream_t s)
+{
+    const Level& L = g->lev[g->cfdm_level];
+    const LevelView& V = L.view;
+    const T* tab = sizeof(T) == 8 ? (const T*)g->cfdm_tab64 : (const T*)g->cfdm_tab32;
+    const int m[3] = {L.n[0] - 2, L.n[1] - 2, L.n[2] - 2};
+    const CfTab tl = cf_layout(m, g->cfdm_mx);
+    const size_t lds = cf_lds_bytes(sizeof(T), m, g->n_batch, tl);
+    switch (g->cfdm_mx) {
+        case 16: hipLaunchKernelGGL((k_coarse_fdm<T, 16>), dim3(1), dim3(CF_NT), lds, s, V, f, u, tab, tl); break;
+        default: hipLaunchKernelGGL((k_coarse_fdm<T, 32>), dim3(1), dim3(CF_NT), lds, s, V, f, u, tab, tl); break;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_coarse_fdm<double>(lasto_grid, const double*, double*, hipStream_t);
+template hipError_t launch_coarse_fdm<float>(lasto_grid, const float*, float*, hipStream_t);
+
 }  // namespace lasto
 
 using namespace lasto;
@@ -323,6 +586,7 @@ extern "C" lasto_status lasto_fdm_solve(lasto_grid g, const double* rho, double*
         info->rel_resid = worst;
         info->resid_hist[0] = worst;
         info->n_batch = g->n_batch;
+        info->coarse_level = -1;
         if (bc == 1) {
             LASTO_HIP(hipMemcpy(info->moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost));
         }

@@ -272,6 +272,7 @@ static lasto_status alloc_zero(lasto_grid g, void** p, size_t bytes)
 static void free_grid(lasto_grid g)
 {
     free_fdm(g);
+    free_coarse_fdm(g);
     for (int l = 0; l < g->nlev; ++l) {
         Level& L = g->lev[l];
         (void)hipFree(L.dtab);
@@ -537,6 +538,7 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
                 break;
             }
         st = build_lds_tail(g);
+        if (st == LASTO_OK) st = build_coarse_fdm(g);
     }
     if (st == LASTO_OK) {
         std::vector<TailLevel> tl(g->nlev);

@@ -263,6 +263,13 @@ struct lasto_grid_s {
     size_t stage_bytes = 0;
     double box_center[3] = {0, 0, 0};
     lasto::FdmState* fdm = nullptr;   // built on the first lasto_fdm_solve
+    // coarsest solve of the cycle by fast diagonalisation (cfdm_level -1: the
+    // level does not allow it, and the red-black tail runs instead)
+    int cfdm_level = -1;
+    int cfdm_mx = 0;                  // padded row length of its axis tables
+    double* cfdm_tab64 = nullptr;     // device: per axis S^-1, S, eigenvalues
+    float* cfdm_tab32 = nullptr;
+    bool coarse_direct = true;        // the current solve's choice (opts.coarse == 0)
     // optional event timing of the finest-level sweeps (solve opts.profile)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;   // start/stop pairs
@@ -320,6 +327,11 @@ hipError_t launch_tail(const TailLevel* lv, int nl, int nu1, int nu2, int csweep
 hipError_t launch_tail_lds(float* u, const float* f, const float* tabs, int nu1, int nu2, int csweeps, int top_zero,
                            const LdsPlan& P, const LdsPlan* P_dev, hipStream_t s);
 int tail_lds_limit();   // bytes of LDS one workgroup may use (0 if unknown)
+// exact solve of A e = f (zero faces) at level g->cfdm_level, split layout
+template <typename T>
+hipError_t launch_coarse_fdm(lasto_grid g, const T* f, T* e, hipStream_t s);
+lasto_status build_coarse_fdm(lasto_grid g);   // tables of the tail's top level, if it qualifies
+void free_coarse_fdm(lasto_grid g);
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s);
 template <typename T>

@@ -79,6 +79,15 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     Level& L = g->lev[l];
     const LevelView& V = L.view;
     hipStream_t s = g->stream;
+    if (g->coarse_direct && l == g->cfdm_level) {
+        // exact coarsest solve (its result does not depend on a start)
+        HIPCHK(launch_coarse_fdm<T>(g, f, u, s));
+        if (dotp) {
+            HIPCHK(launch_dot<T>(V, f, u, dotp, s));
+            *ndot = row_blocks(V);
+        }
+        return LASTO_OK;
+    }
     if (sizeof(T) == 4 && l == g->tail32_top) {
         // the rest of the FP32 cycle in one workgroup, all levels in LDS
         HIPCHK(launch_tail_lds((float*)u, (const float*)f, g->lds_tabs, nu1, nu2, kCoarseSweeps, zero_start ? 1 : 0,
@@ -275,12 +284,16 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad rtol/max_iters/nu1/nu2");
     if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
         o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 1 || (o.precision == 1 && o.inner_iters < 1) ||
-        o.inner_first < 0)
-        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters");
+        o.inner_first < 0 || o.coarse < 0 || o.coarse > 1)
+        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters/coarse");
     lasto_solve_info inf;
     std::memset(&inf, 0, sizeof(inf));
     hipStream_t s = g->stream;
     g->prof_on = (o.profile == 1);
+    g->coarse_direct = (o.coarse == 0);
+    // the FP32 cycle reaches the exact solve unless its LDS tail starts above it
+    const bool lds_first = o.precision == 1 && g->tail32_top >= 0 && g->tail32_top < g->cfdm_level;
+    inf.coarse_level = (g->coarse_direct && !lds_first) ? g->cfdm_level : -1;
     g->prof_used = 0;
     g->prof_bytes = 0.0;
     g->prof_fp32 = 0;

@@ -59,6 +59,7 @@ class SolveOpts(C.Structure):
         ("debug_nan_iter", C.c_int),
         ("profile", C.c_int),
         ("inner_first", C.c_int),
+        ("coarse", C.c_int),
     ]
 
 
@@ -77,6 +78,7 @@ class SolveInfo(C.Structure):
         ("smooth_fp32", C.c_int),
         ("n_batch", C.c_int),
         ("batch_rel_resid", C.c_double * 16),
+        ("coarse_level", C.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -86,7 +88,8 @@ class SolveInfo(C.Structure):
                     moments=list(self.moments), ms_total=self.ms_total,
                     smooth_launches=self.smooth_launches, smooth_ms=self.smooth_ms,
                     smooth_bytes=self.smooth_bytes, smooth_fp32=self.smooth_fp32,
-                    batch_rel_resid=list(self.batch_rel_resid[:max(self.n_batch, 1)]))
+                    batch_rel_resid=list(self.batch_rel_resid[:max(self.n_batch, 1)]),
+                    coarse_level=self.coarse_level)
 
 
 # exported names, in header order

@@ -157,6 +157,10 @@ SOLVE_CASES = [
     (2, 129, dict(precision=1, method=1)),
     (4, 65, dict()),
     (4, 65, dict(precision=1, method=1)),
+    # the red-black tail instead of the exact coarsest solve
+    (1, 33, dict(coarse=1)),
+    (2, 65, dict(coarse=1)),
+    (2, 129, dict(precision=1, coarse=1)),
 ]
 
 
@@ -183,6 +187,38 @@ def test_solve_matches_oracle(torch, L, oracle_mod, cid, n, opts):
     g.close()
 
 
+@pytest.mark.parametrize("cid,n", [(2, 129), (3, 129), (1, 33)])
+def test_exact_coarsest_solve_engaged_and_no_slower_to_converge(torch, L, oracle_mod, cid, n):
+    """the cycle's exact coarsest solve runs where the first level of at most
+    16384 nodes lies below the finest, and takes no more iterations than the
+    red-black tail it replaces (both to the same tolerance)"""
+    say("coarsest solve config %d n=%d" % (cid, n))
+    w = I.config(cid, n_override=n)
+    xs = oracle_mod.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    top = next(l for l, s in enumerate(g.levels()) if s[0] * s[1] * s[2] <= 16384)
+    assert top >= 1
+    out = {}
+    for prec in (0, 1):
+        for coarse in (0, 1):
+            v = g.empty()
+            info = g.poisson_solve(rho, v, rtol=1e-10, precision=prec, coarse=coarse)
+            out[prec, coarse] = (info, v)
+            say("  precision %d coarse %d: iters %d vcycles %d level %d" % (
+                prec, coarse, info["iters"], info["vcycles"], info["coarse_level"]))
+        a, va = out[prec, 0]
+        b, vb = out[prec, 1]
+        # (an FP32 cycle whose LDS tail starts above that level keeps the tail)
+        assert a["coarse_level"] == top or (prec == 1 and a["coarse_level"] == -1)
+        assert b["coarse_level"] == -1
+        assert a["rel_resid"] <= 1e-10 and b["rel_resid"] <= 1e-10
+        assert a["vcycles"] <= b["vcycles"]
+        d = (va - vb).cpu().numpy()
+        assert wnorm(xs, d) <= 1e-8 * wnorm(xs, vb.cpu().numpy())
+    g.close()
+
+
 def test_solve_ragged_noncubic_zero_faces(torch, L, oracle_mod):
     say("solve ragged 70x45x97, bc=0")
     rng = np.random.default_rng(14)
@@ -202,7 +238,8 @@ def test_solve_ragged_noncubic_zero_faces(torch, L, oracle_mod):
 
 
 # -------------------------------------------------------------- batches
-BATCH_OPTS = [dict(), dict(precision=1), dict(method=1), dict(precision=1, method=1)]
+BATCH_OPTS = [dict(), dict(precision=1), dict(method=1), dict(precision=1, method=1), dict(coarse=1),
+              dict(precision=1, coarse=1)]
 
 
 @pytest.mark.parametrize("opts", BATCH_OPTS)
