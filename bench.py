@@ -472,16 +472,23 @@ def bench_learned(args):
     fwd_ms = e0.elapsed_time(e1) / 10
     flops = conv_flops((n, n, n), ch)
     rows = []
+    mixed = []
     for p in test_p:
         for _ in range(2):   # second pass timed warm
             r = learned.compare(net, p, rtol=1e-10)
+            rm = learned.compare(net, p, rtol=1e-10, precision=1)
         a = learned.corrected_cycles(p, None)
         b = learned.corrected_cycles(p, net_c)
         rows.append((r, a, b))
+        mixed.append(rm)
         log("bench: %s zero %d/%.2f ms analytic %d/%.2f ms learned %d/%.2f ms (accepted %s) | stationary plain %d/%.2f ms"
             " corrected %d/%.2f ms" % (p.name[:28], r["zero"]["iters"], r["zero"]["ms"], r["analytic"]["iters"],
                                        r["analytic"]["ms"], r["learned"]["iters"], r["learned"]["ms"],
                                        r["learned"]["accepted"], a["cycles"], a["ms"], b["cycles"], b["ms"]))
+        log("bench:   mixed precision: zero %d/%.2f ms analytic %d/%.2f ms learned %d/%.2f ms (accepted %s),"
+            " error vs label %.2e" % (rm["zero"]["vcycles"], rm["zero"]["ms"], rm["analytic"]["vcycles"],
+                                      rm["analytic"]["ms"], rm["learned"]["vcycles"], rm["learned"]["ms"],
+                                      rm["learned"]["accepted"], rm["err_vs_label"]))
     med = lambda v: round(float(statistics.median(v)), 3)
     out = {
         "metric": "time-to-1e-10-residual per Poisson solve: learned guess vs plain multigrid (V-cycles saved)",
@@ -501,6 +508,10 @@ def bench_learned(args):
                    "analytic": med([r["analytic"]["ms"] for r, _, _ in rows]),
                    "learned": med([r["learned"]["ms"] for r, _, _ in rows])},
         "learned_guess_accepted": [bool(r["learned"]["accepted"]) for r, _, _ in rows],
+        # the same three starts with FP32 cycles inside FP64 refinement (V-cycles counted)
+        "mixed_vcycles": {k: [rm[k]["vcycles"] for rm in mixed] for k in ("zero", "analytic", "learned")},
+        "mixed_ms": {k: med([rm[k]["ms"] for rm in mixed]) for k in ("zero", "analytic", "learned")},
+        "mixed_err_vs_label": max(rm["err_vs_label"] for rm in mixed),
         "stationary_cycles": {"plain": [a["cycles"] for _, a, _ in rows],
                               "learned_correction": [b["cycles"] for _, _, b in rows]},
         "stationary_ms": {"plain": med([a["ms"] for _, a, _ in rows]),
