@@ -511,6 +511,233 @@ hipError_t launch_coarse_fdm(lasto_grid g, const T* f, T* u, hipStream_t s)
 template hipError_t launch_coarse_fdm<double>(lasto_grid, const double*, double*, hipStream_t);
 template hipError_t launch_coarse_fdm<float>(lasto_grid, const float*, float*, hipStream_t);
 
+// ------------------------------------ coarsest solve by GEMMs (a larger level)
+// The same exact solve on a level of up to kGemmCoarseMaxPts nodes per copy
+// (90^3 under the 257^3 mesh), where the block no longer fits in LDS: the
+// level's interior is packed into a dense [copy][z][y][x] array, contracted
+// along x, y, z by rocBLAS GEMMs in the cycle's precision (the same three
+// shapes as the direct solver, z batched over copies), divided by the
+// eigenvalue sums, contracted back and unpacked. Below that level nothing
+// runs, so the launch-bound sweeps and transfers of the small levels are
+// replaced by nine launches. rocBLAS runs with atomics off (fixed summation
+// order, so repeated solves give the same bits).
+struct CoarseGemm {
+    int m[3] = {0, 0, 0};
+    int nb = 1;
+    double* S64[3] = {nullptr, nullptr, nullptr};
+    double* Si64[3] = {nullptr, nullptr, nullptr};
+    double* lam64[3] = {nullptr, nullptr, nullptr};
+    float* S32[3] = {nullptr, nullptr, nullptr};
+    float* Si32[3] = {nullptr, nullptr, nullptr};
+    float* lam32[3] = {nullptr, nullptr, nullptr};
+    double* buf64[2] = {nullptr, nullptr};
+    float* buf32[2] = {nullptr, nullptr};
+    rocblas_handle blas = nullptr;
+};
+
+void free_coarse_gemm(lasto_grid g)
+{
+    CoarseGemm* c = g->cg;
+    if (!c) return;
+    for (int d = 0; d < 3; ++d) {
+        (void)hipFree(c->S64[d]);
+        (void)hipFree(c->Si64[d]);
+        (void)hipFree(c->lam64[d]);
+        (void)hipFree(c->S32[d]);
+        (void)hipFree(c->Si32[d]);
+        (void)hipFree(c->lam32[d]);
+    }
+    for (int b = 0; b < 2; ++b) {
+        (void)hipFree(c->buf64[b]);
+        (void)hipFree(c->buf32[b]);
+    }
+    if (c->blas) (void)rocblas_destroy_handle(c->blas);
+    delete c;
+    g->cg = nullptr;
+}
+
+// the level the GEMM solve would take (set at grid creation; -1: none). It
+// must lie below the finest level and above the LDS solve's level.
+void choose_coarse_gemm_level(lasto_grid g)
+{
+    g->cg_level = -1;
+    for (int l = 1; l < g->nlev; ++l) {
+        const Level& L = g->lev[l];
+        const size_t per_copy = (size_t)L.n[0] * L.n[1] * L.n[2];
+        if (per_copy > kGemmCoarseMaxPts) continue;
+        if (L.npts > kTailMaxPts && L.n[0] >= 3 && L.n[1] >= 3 && L.n[2] >= 3) g->cg_level = l;
+        return;
+    }
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<double>& src)
+{
+    std::vector<T> h(src.begin(), src.end());
+    hipError_t e = hipMalloc(dst, sizeof(T) * h.size());
+    if (e == hipSuccess) e = hipMemcpy(*dst, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+lasto_status coarse_gemm_init(lasto_grid g)
+{
+    if (g->cg || g->cg_level < 0) return LASTO_OK;
+    const Level& L = g->lev[g->cg_level];
+    CoarseGemm* c = new CoarseGemm;
+    g->cg = c;
+    c->nb = g->n_batch;
+    hipError_t e = hipSuccess;
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+        const int m = L.n[d] - 2;
+        c->m[d] = m;
+        std::vector<double> lam(m), S((size_t)m * m), Si((size_t)m * m);
+        if (!axis_decomposition(L.hx[d].data(), L.n[d], lam.data(), S.data(), Si.data())) {
+            free_coarse_gemm(g);
+            return fail(LASTO_ERR_STATE, "lasto_poisson_solve: coarse-level eigen-decomposition did not converge");
+        }
+        e = upload(&c->S64[d], S);
+        if (e == hipSuccess) e = upload(&c->Si64[d], Si);
+        if (e == hipSuccess) e = upload(&c->lam64[d], lam);
+        if (e == hipSuccess) e = upload(&c->S32[d], S);
+        if (e == hipSuccess) e = upload(&c->Si32[d], Si);
+        if (e == hipSuccess) e = upload(&c->lam32[d], lam);
+    }
+    const size_t cells = (size_t)c->m[0] * c->m[1] * c->m[2] * c->nb;
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipMalloc(&c->buf64[b], sizeof(double) * cells);
+        if (e == hipSuccess) e = hipMalloc(&c->buf32[b], sizeof(float) * cells);
+    }
+    if (e != hipSuccess) {
+        free_coarse_gemm(g);
+        return fail(LASTO_ERR_ALLOC, std::string("lasto_poisson_solve: coarse-level tables: ") + hipGetErrorString(e));
+    }
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
+        rocblas_set_stream(c->blas, g->stream) != rocblas_status_success ||
+        rocblas_set_atomics_mode(c->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
+        free_coarse_gemm(g);
+        return fail(LASTO_ERR_HIP, "lasto_poisson_solve: rocBLAS handle");
+    }
+    return LASTO_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_split_to_dense(LevelView V, const T* __restrict__ a, T* __restrict__ d)
+{
+    const int mx = V.nx - 2, my = V.ny - 2, mz = V.nzc - 2;
+    const int n = mx * my * mz * (V.nz / V.nzc);
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < n) d[t] = a[cf_split(V, t, mx, my, mz)];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_to_split(LevelView V, const T* __restrict__ d, T* __restrict__ a)
+{
+    const int mx = V.nx - 2, my = V.ny - 2, mz = V.nzc - 2;
+    const int n = mx * my * mz * (V.nz / V.nzc);
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < n) a[cf_split(V, t, mx, my, mz)] = d[t];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_divide_dense(T* __restrict__ d, const T* __restrict__ lx,
+                                                      const T* __restrict__ ly, const T* __restrict__ lz, int mx,
+                                                      int my, int mz, int n)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    const int i = t % mx, r = t / mx;
+    d[t] = d[t] / (lx[i] + ly[r % my] + lz[(r / my) % mz]);
+}
+
+static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, int m, int n, int k, const double* A, int lda,
+                           const double* B, int ldb, double* C, int ldc)
+{
+    const double one = 1.0, zero = 0.0;
+    return rocblas_dgemm(h, ta, rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &zero, C, ldc);
+}
+static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, int m, int n, int k, const float* A, int lda,
+                           const float* B, int ldb, float* C, int ldc)
+{
+    const float one = 1.0f, zero = 0.0f;
+    return rocblas_sgemm(h, ta, rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &zero, C, ldc);
+}
+static rocblas_status gemm_sb(rocblas_handle h, int m, int n, int k, const double* A, int lda, rocblas_stride sa,
+                              const double* B, int ldb, rocblas_stride sb, double* C, int ldc, rocblas_stride sc,
+                              int batch)
+{
+    const double one = 1.0, zero = 0.0;
+    return rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda,
+                                         sa, B, ldb, sb, &zero, C, ldc, sc, batch);
+}
+static rocblas_status gemm_sb(rocblas_handle h, int m, int n, int k, const float* A, int lda, rocblas_stride sa,
+                              const float* B, int ldb, rocblas_stride sb, float* C, int ldc, rocblas_stride sc,
+                              int batch)
+{
+    const float one = 1.0f, zero = 0.0f;
+    return rocblas_sgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda,
+                                         sa, B, ldb, sb, &zero, C, ldc, sc, batch);
+}
+
+// out = (P along axis d) in on the dense [copy][z][y][x] block (column-major
+// views as in the direct solver; z batched over copies)
+template <typename T>
+static rocblas_status contract_c(const CoarseGemm* c, int d, const T* P, const T* in, T* out)
+{
+    const int mx = c->m[0], my = c->m[1], mz = c->m[2], nb = c->nb;
+    if (d == 0) return gemm(c->blas, rocblas_operation_transpose, mx, my * mz * nb, mx, P, mx, in, mx, out, mx);
+    if (d == 1)
+        return gemm_sb(c->blas, mx, my, my, in, mx, (rocblas_stride)mx * my, P, my, 0, out, mx,
+                       (rocblas_stride)mx * my, mz * nb);
+    const rocblas_stride cs = (rocblas_stride)mx * my * mz;
+    return gemm_sb(c->blas, mx * my, mz, mz, in, mx * my, cs, P, mz, 0, out, mx * my, cs, nb);
+}
+
+template <typename T> struct CgTab;
+template <> struct CgTab<double> {
+    static double* const* S(const CoarseGemm* c) { return c->S64; }
+    static double* const* Si(const CoarseGemm* c) { return c->Si64; }
+    static double* const* lam(const CoarseGemm* c) { return c->lam64; }
+    static double* buf(const CoarseGemm* c, int b) { return c->buf64[b]; }
+};
+template <> struct CgTab<float> {
+    static float* const* S(const CoarseGemm* c) { return c->S32; }
+    static float* const* Si(const CoarseGemm* c) { return c->Si32; }
+    static float* const* lam(const CoarseGemm* c) { return c->lam32; }
+    static float* buf(const CoarseGemm* c, int b) { return c->buf32[b]; }
+};
+
+template <typename T>
+lasto_status coarse_gemm_solve(lasto_grid g, const T* f, T* u, hipStream_t s)
+{
+    const CoarseGemm* c = g->cg;
+    const LevelView& V = g->lev[g->cg_level].view;
+    const int n = c->m[0] * c->m[1] * c->m[2] * c->nb;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    T* b0 = CgTab<T>::buf(c, 0);
+    T* b1 = CgTab<T>::buf(c, 1);
+    auto Si = CgTab<T>::Si(c);
+    auto S = CgTab<T>::S(c);
+    auto lam = CgTab<T>::lam(c);
+    hipLaunchKernelGGL(k_split_to_dense<T>, dim3(blocks), dim3(256), 0, s, V, f, b0);
+    LASTO_LAUNCH_CHECK("k_split_to_dense");
+    rocblas_status e = contract_c<T>(c, 0, Si[0], b0, b1);
+    if (e == rocblas_status_success) e = contract_c<T>(c, 1, Si[1], b1, b0);
+    if (e == rocblas_status_success) e = contract_c<T>(c, 2, Si[2], b0, b1);
+    if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_poisson_solve: coarse-level GEMM");
+    hipLaunchKernelGGL(k_divide_dense<T>, dim3(blocks), dim3(256), 0, s, b1, lam[0], lam[1], lam[2], c->m[0],
+                       c->m[1], c->m[2], n);
+    LASTO_LAUNCH_CHECK("k_divide_dense");
+    e = contract_c<T>(c, 2, S[2], b1, b0);
+    if (e == rocblas_status_success) e = contract_c<T>(c, 1, S[1], b0, b1);
+    if (e == rocblas_status_success) e = contract_c<T>(c, 0, S[0], b1, b0);
+    if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_poisson_solve: coarse-level GEMM");
+    hipLaunchKernelGGL(k_dense_to_split<T>, dim3(blocks), dim3(256), 0, s, V, b0, u);
+    LASTO_LAUNCH_CHECK("k_dense_to_split");
+    return LASTO_OK;
+}
+template lasto_status coarse_gemm_solve<double>(lasto_grid, const double*, double*, hipStream_t);
+template lasto_status coarse_gemm_solve<float>(lasto_grid, const float*, float*, hipStream_t);
+
 }  // namespace lasto
 
 using namespace lasto;

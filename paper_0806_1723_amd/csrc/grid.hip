@@ -273,6 +273,7 @@ static void free_grid(lasto_grid g)
 {
     free_fdm(g);
     free_coarse_fdm(g);
+    free_coarse_gemm(g);
     for (int l = 0; l < g->nlev; ++l) {
         Level& L = g->lev[l];
         (void)hipFree(L.dtab);
@@ -539,6 +540,7 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
             }
         st = build_lds_tail(g);
         if (st == LASTO_OK) st = build_coarse_fdm(g);
+        if (st == LASTO_OK) choose_coarse_gemm_level(g);
     }
     if (st == LASTO_OK) {
         std::vector<TailLevel> tl(g->nlev);

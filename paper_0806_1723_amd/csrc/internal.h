@@ -155,6 +155,7 @@ template <> struct TailBuf<float> {
 };
 
 constexpr size_t kTailMaxPts = 16384;   // levels at or below this size run in the tail kernel
+constexpr size_t kGemmCoarseMaxPts = 1200000;   // per copy: the largest level the GEMM coarsest solve takes
 
 // LDS layout of the FP32 tail. Per level q (0 = the first level it takes):
 // dims nx, ny, nz, W, cs; offsets (floats) of its correction and right-hand
@@ -220,7 +221,8 @@ __host__ __device__ __forceinline__ LdsTab lds_tab(P* b, int nx, int ny, int nz,
 }  // namespace lasto
 
 namespace lasto {
-struct FdmState;   // fast-diagonalisation tables and work arrays (fdm.hip)
+struct FdmState;     // fast-diagonalisation tables and work arrays (fdm.hip)
+struct CoarseGemm;   // the same for the cycle's coarsest level (fdm.hip)
 }
 
 struct lasto_grid_s {
@@ -269,7 +271,11 @@ struct lasto_grid_s {
     int cfdm_mx = 0;                  // padded row length of its axis tables
     double* cfdm_tab64 = nullptr;     // device: per axis S^-1, S, eigenvalues
     float* cfdm_tab32 = nullptr;
-    bool coarse_direct = true;        // the current solve's choice (opts.coarse == 0)
+    int coarse_mode = 0;              // the current solve's opts.coarse
+    // the exact coarsest solve by GEMMs on a larger level (tables built on
+    // first use; cg_level -1: no level qualifies)
+    int cg_level = -1;
+    lasto::CoarseGemm* cg = nullptr;
     // optional event timing of the finest-level sweeps (solve opts.profile)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;   // start/stop pairs
@@ -332,6 +338,12 @@ template <typename T>
 hipError_t launch_coarse_fdm(lasto_grid g, const T* f, T* e, hipStream_t s);
 lasto_status build_coarse_fdm(lasto_grid g);   // tables of the tail's top level, if it qualifies
 void free_coarse_fdm(lasto_grid g);
+// exact solve of A e = f (zero faces) at level g->cg_level by GEMMs, split layout
+void choose_coarse_gemm_level(lasto_grid g);
+lasto_status coarse_gemm_init(lasto_grid g);    // tables, buffers and rocBLAS handle on first use
+template <typename T>
+lasto_status coarse_gemm_solve(lasto_grid g, const T* f, T* e, hipStream_t s);
+void free_coarse_gemm(lasto_grid g);
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s);
 template <typename T>

@@ -79,7 +79,16 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     Level& L = g->lev[l];
     const LevelView& V = L.view;
     hipStream_t s = g->stream;
-    if (g->coarse_direct && l == g->cfdm_level) {
+    if (g->coarse_mode == 0 && g->cg && l == g->cg_level) {
+        // exact coarsest solve by GEMMs (nothing below this level runs)
+        if (lasto_status e = coarse_gemm_solve<T>(g, f, u, s); e != LASTO_OK) return e;
+        if (dotp) {
+            HIPCHK(launch_dot<T>(V, f, u, dotp, s));
+            *ndot = row_blocks(V);
+        }
+        return LASTO_OK;
+    }
+    if (g->coarse_mode != 1 && l == g->cfdm_level) {
         // exact coarsest solve (its result does not depend on a start)
         HIPCHK(launch_coarse_fdm<T>(g, f, u, s));
         if (dotp) {
@@ -284,16 +293,23 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad rtol/max_iters/nu1/nu2");
     if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
         o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 1 || (o.precision == 1 && o.inner_iters < 1) ||
-        o.inner_first < 0 || o.coarse < 0 || o.coarse > 1)
+        o.inner_first < 0 || o.coarse < 0 || o.coarse > 2)
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters/coarse");
     lasto_solve_info inf;
     std::memset(&inf, 0, sizeof(inf));
     hipStream_t s = g->stream;
     g->prof_on = (o.profile == 1);
-    g->coarse_direct = (o.coarse == 0);
-    // the FP32 cycle reaches the exact solve unless its LDS tail starts above it
-    const bool lds_first = o.precision == 1 && g->tail32_top >= 0 && g->tail32_top < g->cfdm_level;
-    inf.coarse_level = (g->coarse_direct && !lds_first) ? g->cfdm_level : -1;
+    g->coarse_mode = o.coarse;
+    if (o.coarse == 0) {
+        if (lasto_status e = coarse_gemm_init(g); e != LASTO_OK) return e;
+    }
+    if (o.coarse == 0 && g->cg) {
+        inf.coarse_level = g->cg_level;
+    } else {
+        // the FP32 cycle reaches the LDS solve unless its LDS tail starts above it
+        const bool lds_first = o.precision == 1 && g->tail32_top >= 0 && g->tail32_top < g->cfdm_level;
+        inf.coarse_level = (o.coarse != 1 && !lds_first) ? g->cfdm_level : -1;
+    }
     g->prof_used = 0;
     g->prof_bytes = 0.0;
     g->prof_fp32 = 0;

@@ -161,6 +161,10 @@ SOLVE_CASES = [
     (1, 33, dict(coarse=1)),
     (2, 65, dict(coarse=1)),
     (2, 129, dict(precision=1, coarse=1)),
+    # the exact solve at the level of at most 16384 nodes, in LDS
+    (2, 65, dict(coarse=2)),
+    (2, 129, dict(coarse=2)),
+    (2, 129, dict(precision=1, coarse=2)),
 ]
 
 
@@ -187,35 +191,43 @@ def test_solve_matches_oracle(torch, L, oracle_mod, cid, n, opts):
     g.close()
 
 
-@pytest.mark.parametrize("cid,n", [(2, 129), (3, 129), (1, 33)])
+@pytest.mark.parametrize("cid,n", [(2, 129), (3, 129), (1, 33), (3, 257)])
 def test_exact_coarsest_solve_engaged_and_no_slower_to_converge(torch, L, oracle_mod, cid, n):
-    """the cycle's exact coarsest solve runs where the first level of at most
-    16384 nodes lies below the finest, and takes no more iterations than the
-    red-black tail it replaces (both to the same tolerance)"""
+    """the cycle's exact coarsest solve runs on the level the options name:
+    by GEMMs on the first level below the finest with at most 1.2e6 nodes
+    (when that level is larger than 16384 nodes), in LDS on the first level
+    of at most 16384 nodes; either takes no more V-cycles than the red-black
+    tail it replaces, to the same tolerance and solution"""
     say("coarsest solve config %d n=%d" % (cid, n))
     w = I.config(cid, n_override=n)
     xs = oracle_mod.mesh_for(w.axes)
     g = L.Grid(*xs)
     rho = g.pseudo_density(w.atoms)
-    top = next(l for l, s in enumerate(g.levels()) if s[0] * s[1] * s[2] <= 16384)
+    sizes = [s[0] * s[1] * s[2] for s in g.levels()]
+    top = next(l for l, s in enumerate(sizes) if s <= 16384)
+    gemm = next(l for l, s in enumerate(sizes) if l >= 1 and s <= 1200000)
+    gemm = gemm if sizes[gemm] > 16384 else top
     assert top >= 1
     out = {}
     for prec in (0, 1):
-        for coarse in (0, 1):
+        for coarse in (0, 2, 1):
             v = g.empty()
             info = g.poisson_solve(rho, v, rtol=1e-10, precision=prec, coarse=coarse)
             out[prec, coarse] = (info, v)
             say("  precision %d coarse %d: iters %d vcycles %d level %d" % (
                 prec, coarse, info["iters"], info["vcycles"], info["coarse_level"]))
-        a, va = out[prec, 0]
-        b, vb = out[prec, 1]
-        # (an FP32 cycle whose LDS tail starts above that level keeps the tail)
-        assert a["coarse_level"] == top or (prec == 1 and a["coarse_level"] == -1)
-        assert b["coarse_level"] == -1
-        assert a["rel_resid"] <= 1e-10 and b["rel_resid"] <= 1e-10
-        assert a["vcycles"] <= b["vcycles"]
-        d = (va - vb).cpu().numpy()
-        assert wnorm(xs, d) <= 1e-8 * wnorm(xs, vb.cpu().numpy())
+        ref, vref = out[prec, 1]
+        assert ref["coarse_level"] == -1 and ref["rel_resid"] <= 1e-10
+        # (an FP32 cycle whose LDS tail starts above the LDS level keeps the tail)
+        assert out[prec, 0][0]["coarse_level"] == gemm or (gemm == top and prec == 1 and
+                                                           out[prec, 0][0]["coarse_level"] == -1)
+        assert out[prec, 2][0]["coarse_level"] == top or (prec == 1 and out[prec, 2][0]["coarse_level"] == -1)
+        for coarse in (0, 2):
+            info, v = out[prec, coarse]
+            assert info["rel_resid"] <= 1e-10
+            assert info["vcycles"] <= ref["vcycles"]
+            d = (v - vref).cpu().numpy()
+            assert wnorm(xs, d) <= 1e-8 * wnorm(xs, vref.cpu().numpy())
     g.close()
 
 
@@ -239,7 +251,7 @@ def test_solve_ragged_noncubic_zero_faces(torch, L, oracle_mod):
 
 # -------------------------------------------------------------- batches
 BATCH_OPTS = [dict(), dict(precision=1), dict(method=1), dict(precision=1, method=1), dict(coarse=1),
-              dict(precision=1, coarse=1)]
+              dict(precision=1, coarse=1), dict(coarse=2), dict(precision=1, coarse=2)]
 
 
 @pytest.mark.parametrize("opts", BATCH_OPTS)
