@@ -515,8 +515,8 @@ template hipError_t launch_coarse_fdm<float>(lasto_grid, const float*, float*, h
 // The same exact solve on a level of up to kGemmCoarseMaxPts nodes per copy
 // (90^3 under the 257^3 mesh), where the block no longer fits in LDS: the
 // level's interior is packed into a dense [copy][z][y][x] array, contracted
-// along x, y, z by rocBLAS GEMMs in the cycle's precision (the same three
-// shapes as the direct solver, z batched over copies), divided by the
+// along x, y, z by rocBLAS GEMMs in the cycle's precision (each a single
+// GEMM per copy: the axes rotate, see contract_rot), divided by the
 // eigenvalue sums, contracted back and unpacked. Below that level nothing
 // runs, so the launch-bound sweeps and transfers of the small levels are
 // replaced by nine launches. rocBLAS runs with atomics off (fixed summation
@@ -649,47 +649,39 @@ __global__ __launch_bounds__(256) void k_divide_dense(T* __restrict__ d, const T
     d[t] = d[t] / (lx[i] + ly[r % my] + lz[(r / my) % mz]);
 }
 
-static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, int m, int n, int k, const double* A, int lda,
-                           const double* B, int ldb, double* C, int ldc)
+static rocblas_status gemm_tn(rocblas_handle h, int m, int n, int k, const double* A, int lda, rocblas_stride sa,
+                              const double* B, int ldb, double* C, int ldc, rocblas_stride sc, int batch)
 {
     const double one = 1.0, zero = 0.0;
-    return rocblas_dgemm(h, ta, rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &zero, C, ldc);
+    return rocblas_dgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, m, n, k, &one, A,
+                                         lda, sa, B, ldb, 0, &zero, C, ldc, sc, batch);
 }
-static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, int m, int n, int k, const float* A, int lda,
-                           const float* B, int ldb, float* C, int ldc)
+static rocblas_status gemm_tn(rocblas_handle h, int m, int n, int k, const float* A, int lda, rocblas_stride sa,
+                              const float* B, int ldb, float* C, int ldc, rocblas_stride sc, int batch)
 {
     const float one = 1.0f, zero = 0.0f;
-    return rocblas_sgemm(h, ta, rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &zero, C, ldc);
-}
-static rocblas_status gemm_sb(rocblas_handle h, int m, int n, int k, const double* A, int lda, rocblas_stride sa,
-                              const double* B, int ldb, rocblas_stride sb, double* C, int ldc, rocblas_stride sc,
-                              int batch)
-{
-    const double one = 1.0, zero = 0.0;
-    return rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda,
-                                         sa, B, ldb, sb, &zero, C, ldc, sc, batch);
-}
-static rocblas_status gemm_sb(rocblas_handle h, int m, int n, int k, const float* A, int lda, rocblas_stride sa,
-                              const float* B, int ldb, rocblas_stride sb, float* C, int ldc, rocblas_stride sc,
-                              int batch)
-{
-    const float one = 1.0f, zero = 0.0f;
-    return rocblas_sgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda,
-                                         sa, B, ldb, sb, &zero, C, ldc, sc, batch);
+    return rocblas_sgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, m, n, k, &one, A,
+                                         lda, sa, B, ldb, 0, &zero, C, ldc, sc, batch);
 }
 
-// out = (P along axis d) in on the dense [copy][z][y][x] block (column-major
-// views as in the direct solver; z batched over copies)
+// One contraction with the axes rotated: each copy's block holds L =
+// cells / m lines of m contiguous entries ([line][k], the contracted axis
+// fastest); the output is out[r][line] = sum_k P[r][k] in[line][k], the new
+// axis slowest. Column-major, that is C (L x m) = A^T B with A the input
+// (m x L) and B the row-major P read as column-major (B(k, r) = P[r][k]):
+// one GEMM per copy, whatever the axis (L x m x m, e.g. 7744 x 88 x 88).
+// Three of them take [z][y][x] to [x'][z][y], [y'][x'][z] and [z'][y'][x']
+// (the original order), three more back to [z][y][x]. (rocBLAS runs these
+// shapes at 6 TFLOP/s in FP64 and 17 in FP32: 128-wide tiles leave most
+// compute units idle. A hand-written kernel with 32 lines per workgroup and
+// a 4 x 4 block per lane was slower still, latency-bound at three waves per
+// compute unit.)
 template <typename T>
-static rocblas_status contract_c(const CoarseGemm* c, int d, const T* P, const T* in, T* out)
+static rocblas_status contract_rot(const CoarseGemm* c, int m, const T* P, const T* in, T* out)
 {
-    const int mx = c->m[0], my = c->m[1], mz = c->m[2], nb = c->nb;
-    if (d == 0) return gemm(c->blas, rocblas_operation_transpose, mx, my * mz * nb, mx, P, mx, in, mx, out, mx);
-    if (d == 1)
-        return gemm_sb(c->blas, mx, my, my, in, mx, (rocblas_stride)mx * my, P, my, 0, out, mx,
-                       (rocblas_stride)mx * my, mz * nb);
-    const rocblas_stride cs = (rocblas_stride)mx * my * mz;
-    return gemm_sb(c->blas, mx * my, mz, mz, in, mx * my, cs, P, mz, 0, out, mx * my, cs, nb);
+    const int per = c->m[0] * c->m[1] * c->m[2];
+    const int L = per / m;
+    return gemm_tn(c->blas, L, m, m, in, m, per, P, m, out, L, per, c->nb);
 }
 
 template <typename T> struct CgTab;
@@ -720,16 +712,16 @@ lasto_status coarse_gemm_solve(lasto_grid g, const T* f, T* u, hipStream_t s)
     auto lam = CgTab<T>::lam(c);
     hipLaunchKernelGGL(k_split_to_dense<T>, dim3(blocks), dim3(256), 0, s, V, f, b0);
     LASTO_LAUNCH_CHECK("k_split_to_dense");
-    rocblas_status e = contract_c<T>(c, 0, Si[0], b0, b1);
-    if (e == rocblas_status_success) e = contract_c<T>(c, 1, Si[1], b1, b0);
-    if (e == rocblas_status_success) e = contract_c<T>(c, 2, Si[2], b0, b1);
+    rocblas_status e = contract_rot<T>(c, c->m[0], Si[0], b0, b1);
+    if (e == rocblas_status_success) e = contract_rot<T>(c, c->m[1], Si[1], b1, b0);
+    if (e == rocblas_status_success) e = contract_rot<T>(c, c->m[2], Si[2], b0, b1);
     if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_poisson_solve: coarse-level GEMM");
     hipLaunchKernelGGL(k_divide_dense<T>, dim3(blocks), dim3(256), 0, s, b1, lam[0], lam[1], lam[2], c->m[0],
                        c->m[1], c->m[2], n);
     LASTO_LAUNCH_CHECK("k_divide_dense");
-    e = contract_c<T>(c, 2, S[2], b1, b0);
-    if (e == rocblas_status_success) e = contract_c<T>(c, 1, S[1], b0, b1);
-    if (e == rocblas_status_success) e = contract_c<T>(c, 0, S[0], b1, b0);
+    e = contract_rot<T>(c, c->m[0], S[0], b1, b0);
+    if (e == rocblas_status_success) e = contract_rot<T>(c, c->m[1], S[1], b0, b1);
+    if (e == rocblas_status_success) e = contract_rot<T>(c, c->m[2], S[2], b1, b0);
     if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_poisson_solve: coarse-level GEMM");
     hipLaunchKernelGGL(k_dense_to_split<T>, dim3(blocks), dim3(256), 0, s, V, b0, u);
     LASTO_LAUNCH_CHECK("k_dense_to_split");
