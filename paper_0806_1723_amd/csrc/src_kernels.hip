@@ -324,13 +324,26 @@ __global__ __launch_bounds__(MO_NT) void k_moments(LevelView L, const double* __
     double acc[25];
     for (int c = 0; c < 25; ++c) acc[c] = 0.0;
     double S[25];
-    for (size_t t = (size_t)blockIdx.x * MO_NT + threadIdx.x; t < n; t += (size_t)gridDim.x * MO_NT) {
+    // the node index is decoded once and then advanced by the grid stride
+    // with carries (a 64-bit division per node cost more than the node)
+    size_t t = (size_t)blockIdx.x * MO_NT + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * MO_NT;
+    int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((size_t)nx * ny));
+    const int di = (int)(stride % nx), dj = (int)((stride / nx) % ny), dk = (int)(stride / ((size_t)nx * ny));
+    for (; t < n; t += stride) {
         const double f = rho[t];
-        if (f == 0.0) continue;
-        const int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((size_t)nx * ny));
-        const double w = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * f;
-        solid_harmonics(L.ax[0].x[i] - cx, L.ax[1].x[j] - cy, L.ax[2].x[k] - cz, 4, S);
-        for (int c = 0; c < 25; ++c) acc[c] += w * S[c];
+        if (f != 0.0) {
+            const double w = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * f;
+            solid_harmonics(L.ax[0].x[i] - cx, L.ax[1].x[j] - cy, L.ax[2].x[k] - cz, 4, S);
+            for (int c = 0; c < 25; ++c) acc[c] += w * S[c];
+        }
+        i += di;
+        int carry = i >= nx;
+        i -= carry * nx;
+        j += dj + carry;
+        carry = j >= ny;
+        j -= carry * ny;
+        k += dk + carry;
     }
     for (int c = 0; c < 25; ++c) {
         double v = acc[c];
