@@ -188,7 +188,11 @@ def main():
                    "parallelism": "single GPU"},
         "solve": {"iters": last["iters"], "vcycles": last["vcycles"], "refinements": last["refinements"],
                   "rel_resid": last["rel_resid"], "per_rhs_rel_resid": last["batch_rel_resid"],
-                  "ms_per_rhs": round(solve_ms / nb, 4)},
+                  "ms_per_rhs": round(solve_ms / nb, 4),
+                  # the level the cycle solves exactly by fast diagonalisation (its coarsest)
+                  "coarsest_exact_level": last["coarse_level"],
+                  "coarsest_exact_shape": (list(g.levels()[last["coarse_level"]])
+                                           if last["coarse_level"] >= 0 else None)},
         "fp64_solve_ms": round(fp64_ms, 4),
         "fp64_iters": fp64[-1]["iters"],
         "fp64_smoother_gbs": round(fp64_gbs, 1),
