@@ -230,22 +230,19 @@ static lasto_status fdm_init(lasto_grid g)
     return LASTO_OK;
 }
 
-// out = (P along axis d) in, for row-major [mz][my][mx] data (rocBLAS is
-// column-major: the array is an mx x (my mz) matrix, a stack of mz
-// mx x my matrices, or an (mx my) x mz matrix)
+// out[r][line] = sum_k P[r][k] in[line][k] for the m = f->m[d] entries of
+// each line of the packed interior (axis d fastest): the new axis is written
+// slowest, so column-major this is one GEMM, C (L x m) = A^T B, with A the
+// input (m x L) and B the row-major P read as column-major. Contracting x, y,
+// z in turn takes [z][y][x] to [x'][z][y], [y'][x'][z] and [z'][y'][x'] (the
+// original order); the same three steps take it back.
 static rocblas_status contract(FdmState* f, int d, const double* P, const double* in, double* out)
 {
-    const int mx = f->m[0], my = f->m[1], mz = f->m[2];
+    const int m = f->m[d];
+    const int L = f->m[0] * f->m[1] * f->m[2] / m;
     const double one = 1.0, zero = 0.0;
-    if (d == 0)
-        return rocblas_dgemm(f->blas, rocblas_operation_transpose, rocblas_operation_none, mx, my * mz, mx, &one, P, mx,
-                             in, mx, &zero, out, mx);
-    if (d == 1)
-        return rocblas_dgemm_strided_batched(f->blas, rocblas_operation_none, rocblas_operation_none, mx, my, my, &one,
-                                             in, mx, (rocblas_stride)mx * my, P, my, 0, &zero, out, mx,
-                                             (rocblas_stride)mx * my, mz);
-    return rocblas_dgemm(f->blas, rocblas_operation_none, rocblas_operation_none, mx * my, mz, mz, &one, in, mx * my, P,
-                         mz, &zero, out, mx * my);
+    return rocblas_dgemm(f->blas, rocblas_operation_transpose, rocblas_operation_none, L, m, m, &one, in, m, P, m,
+                         &zero, out, L);
 }
 
 // ---------------------------------------------- coarsest solve of the cycle
@@ -775,9 +772,9 @@ extern "C" lasto_status lasto_fdm_solve(lasto_grid g, const double* rho, double*
         hipLaunchKernelGGL(k_fdm_divide, dim3(blocks), dim3(256), 0, s, f->buf[1], f->lam[0], f->lam[1], f->lam[2],
                            f->m[0], f->m[1], f->m[2]);
         LASTO_LAUNCH_CHECK("k_fdm_divide");
-        e = contract(f, 2, f->S[2], f->buf[1], f->buf[0]);
+        e = contract(f, 0, f->S[0], f->buf[1], f->buf[0]);
         if (e == rocblas_status_success) e = contract(f, 1, f->S[1], f->buf[0], f->buf[1]);
-        if (e == rocblas_status_success) e = contract(f, 0, f->S[0], f->buf[1], f->buf[0]);
+        if (e == rocblas_status_success) e = contract(f, 2, f->S[2], f->buf[1], f->buf[0]);
         if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_fdm_solve: rocBLAS GEMM");
         hipLaunchKernelGGL(k_fdm_unpack, dim3(blocks), dim3(256), 0, s, V, f->buf[0], vb);
         LASTO_LAUNCH_CHECK("k_fdm_unpack");
