@@ -131,6 +131,9 @@ def main():
     achieved = sm_bytes / (sm_ms * 1e-3) / 1e9 if sm_ms > 0 else 0.0
     avg_launch_us = sm_ms * 1e3 / max(launches, 1)
     last = infos[-1]
+    # the solutions of the timed forms (first right-hand side), for their
+    # error against the oracle's solve of the same problem
+    kept = {"mixed" if mixed else "fp64": (v[0] if nb > 1 else v).cpu().numpy()}
     log("bench: solve %.3f ms (median), step %.3f ms, iters %d, vcycles %d, refinements %d, rel %.2e"
         % (solve_ms, ms_per_step, last["iters"], last["vcycles"], last["refinements"], last["rel_resid"]))
     log("bench: smoother %d launches, avg %.1f us, %.1f GB/s" % (launches, avg_launch_us, achieved))
@@ -141,6 +144,7 @@ def main():
         v.zero_()
         fp64.append(g.poisson_solve(rho, v, rtol=w.rtol, precision=0, profile=1 if si == 1 else 0))
     fp64_ms = statistics.median(i["ms_total"] for i in fp64[2:])
+    kept["fp64"] = (v[0] if nb > 1 else v).cpu().numpy()
     f_ms = fp64[1]["smooth_ms"]
     f_b = fp64[1]["smooth_bytes"]
     f_l = fp64[1]["smooth_launches"]
@@ -155,6 +159,7 @@ def main():
         v.zero_()
         fdm.append(g.fdm_solve(rho, v))
     fdm_ms = statistics.median(i["ms_total"] for i in fdm[1:])
+    kept["fdm_direct"] = (v[0] if nb > 1 else v).cpu().numpy()
     m3 = [len(x) - 2 for x in xs]
     fdm_flops = 4.0 * nb * float(np.prod(m3)) * sum(m3)
     log("bench: fdm direct solve %.3f ms (first call %.1f ms), rel %.2e, %.1f TFLOP/s in its GEMMs' flops over the "
@@ -214,7 +219,18 @@ def main():
     out["matrix_elements"] = bench_matrix_elements(args, lasto, I)
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, xs, (rho[0] if nb > 1 else rho).cpu().numpy(), args.cpu_seconds)
+        out["cpu_baseline"], v_oracle = cpu_baseline(w, xs, (rho[0] if nb > 1 else rho).cpu().numpy(),
+                                                     args.cpu_seconds)
+        # relative W-norm (dual-volume) difference over the interior
+        vol = np.einsum("k,j,i->kji", *[dual_widths(x) for x in (xs[2], xs[1], xs[0])])[1:-1, 1:-1, 1:-1]
+        inner = (slice(1, -1),) * 3
+        ref = float(np.sqrt((vol * v_oracle[inner] ** 2).sum()))
+        out["err_vs_oracle"] = {k: float(np.sqrt((vol * (a[inner] - v_oracle[inner]) ** 2).sum())) / ref
+                                for k, a in kept.items()}
+        out["err_vs_oracle"]["norm"] = ("relative W-norm of the difference over the interior, against the "
+                                        "oracle's solve to the same tolerance (first right-hand side)")
+        log("bench: error against the oracle's solution: %s" % {k: "%.2e" % e for k, e in out["err_vs_oracle"].items()
+                                                                  if k != "norm"})
         if nb > 1:
             out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"] * nb, 1)
             out["cpu_baseline"]["sample"] += "; times %d right-hand sides" % nb
@@ -417,7 +433,17 @@ def cpu_baseline(w, xs, rho, min_seconds):
         % (len(times), total, cores, cyc, rel, ms))
     return {"value": round(ms, 1), "unit": "ms", "cores": cores, "kind": "oracle",
             "sample": "%d whole FP64 solves of the %d^3 problem to %.0e (%d V(2,2) cycles each, %.1f s in "
-                      "all); median per solve" % (len(times), len(xs[0]), w.rtol, cyc, total)}
+                      "all); median per solve" % (len(times), len(xs[0]), w.rtol, cyc, total)}, v
+
+
+def dual_widths(x):
+    """Dual-cell widths of one axis (half cells at the ends)."""
+    import numpy as np
+    m = np.empty_like(x)
+    m[1:-1] = 0.5 * (x[2:] - x[:-2])
+    m[0] = 0.5 * (x[1] - x[0])
+    m[-1] = 0.5 * (x[-1] - x[-2])
+    return m
 
 
 def conv_flops(shape, ch):
