@@ -354,6 +354,14 @@ hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pne
 // x += alpha p, r -= alpha q (all split), alpha = scal[i_num]/scal[i_den];
 // partials of <r, r>_W when partials is given (count in *nparts, at most
 // flat_blocks<T>(L))
+// the inner FP32 PCG's deferred form: pnew = z + beta pold with x = (or +=,
+// accumulate) alpha_prev pold in the same pass; then r -= alpha q
+template <typename T>
+hipError_t launch_update_px(const LevelView& L, const T* z, const T* pold, T* pnew, T* x, const double* scal,
+                            int i_num, int i_den, int i_anum, int i_aden, int accumulate, hipStream_t s);
+template <typename T>
+hipError_t launch_update_r(const LevelView& L, T* r, const T* q, const double* scal, int i_num, int i_den,
+                           hipStream_t s);
 template <typename T>
 hipError_t launch_update_xr(const LevelView& L, T* x, T* r, const T* p, const T* q, const double* scal, int i_num,
                             int i_den, double* partials, hipStream_t s, int* nparts, int first = 0);

@@ -865,6 +865,107 @@ hipError_t launch_update_p(const LevelView& L, const T* z, const T* pold, T* pne
     return hipGetLastError();
 }
 
+// The inner FP32 PCG defers x += alpha p by one step into the next p update,
+// which reads the old p anyway (8 array passes a step instead of 9):
+// pnew = z + beta pold, beta = scal[i_num]/scal[i_den], and with XM 1
+// x = alpha pold, with XM 2 x += alpha pold, alpha = scal[i_anum]/scal[i_aden]
+// (the previous step's); a non-finite alpha leaves x untouched.
+template <typename T, int XM>
+__global__ __launch_bounds__(FL_NT) void k_update_px(LevelView L, unsigned nvec, const T* __restrict__ z,
+                                                     const T* __restrict__ pold, T* __restrict__ pnew,
+                                                     T* __restrict__ x, const double* __restrict__ scal, int i_num,
+                                                     int i_den, int i_anum, int i_aden)
+{
+    typedef typename Vec16<T>::V V;
+    constexpr int N = Vec16<T>::N;
+    const T beta = (T)(scal[i_num] / scal[i_den]);
+    const double ad = scal[i_anum] / scal[i_aden];
+    const bool ok = isfinite(ad);
+    const T alpha = (T)ad;
+    const unsigned stride = gridDim.x * FL_NT;
+    for (unsigned e0 = blockIdx.x * FL_NT + threadIdx.x; e0 < nvec; e0 += stride * FL_U) {
+        V zv[FL_U], pv[FL_U], xv[FL_U];
+        bool lv[FL_U];
+#pragma unroll
+        for (int u = 0; u < FL_U; ++u) {
+            const unsigned e = e0 + u * stride;
+            lv[u] = e < nvec && row_pos(L, e * N).live;
+            zv[u] = pv[u] = xv[u] = V(T(0));
+            if (lv[u]) {
+                zv[u] = reinterpret_cast<const V*>(z)[e];
+                pv[u] = reinterpret_cast<const V*>(pold)[e];
+                if (XM == 2 && ok) xv[u] = reinterpret_cast<const V*>(x)[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < FL_U; ++u) {
+            if (!lv[u]) continue;
+            const unsigned e = e0 + u * stride;
+            reinterpret_cast<V*>(pnew)[e] = zv[u] + beta * pv[u];
+            if (ok) reinterpret_cast<V*>(x)[e] = xv[u] + alpha * pv[u];
+            else if (XM == 1) reinterpret_cast<V*>(x)[e] = V(T(0));
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_update_px(const LevelView& L, const T* z, const T* pold, T* pnew, T* x, const double* scal,
+                            int i_num, int i_den, int i_anum, int i_aden, int accumulate, hipStream_t s)
+{
+    if (accumulate) {
+        static const int cap = kernel_cap(k_update_px<T, 2>);
+        hipLaunchKernelGGL((k_update_px<T, 2>), dim3(flat_grid(flat_vectors<T>(L), cap)), dim3(FL_NT), 0, s, L,
+                           flat_vectors<T>(L), z, pold, pnew, x, scal, i_num, i_den, i_anum, i_aden);
+    } else {
+        static const int cap = kernel_cap(k_update_px<T, 1>);
+        hipLaunchKernelGGL((k_update_px<T, 1>), dim3(flat_grid(flat_vectors<T>(L), cap)), dim3(FL_NT), 0, s, L,
+                           flat_vectors<T>(L), z, pold, pnew, x, scal, i_num, i_den, i_anum, i_aden);
+    }
+    return hipGetLastError();
+}
+
+// r -= alpha q (split), alpha = scal[i_num]/scal[i_den]; a non-finite alpha
+// leaves r untouched
+template <typename T>
+__global__ __launch_bounds__(FL_NT) void k_update_r(LevelView L, unsigned nvec, T* __restrict__ r,
+                                                    const T* __restrict__ q, const double* __restrict__ scal,
+                                                    int i_num, int i_den)
+{
+    typedef typename Vec16<T>::V V;
+    constexpr int N = Vec16<T>::N;
+    const double ad = scal[i_num] / scal[i_den];
+    if (!isfinite(ad)) return;
+    const T alpha = (T)ad;
+    const unsigned stride = gridDim.x * FL_NT;
+    for (unsigned e0 = blockIdx.x * FL_NT + threadIdx.x; e0 < nvec; e0 += stride * FL_U) {
+        V rv[FL_U], qv[FL_U];
+        bool lv[FL_U];
+#pragma unroll
+        for (int u = 0; u < FL_U; ++u) {
+            const unsigned e = e0 + u * stride;
+            lv[u] = e < nvec && row_pos(L, e * N).live;
+            rv[u] = qv[u] = V(T(0));
+            if (lv[u]) {
+                rv[u] = reinterpret_cast<const V*>(r)[e];
+                qv[u] = reinterpret_cast<const V*>(q)[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < FL_U; ++u)
+            if (lv[u]) reinterpret_cast<V*>(r)[e0 + u * stride] = rv[u] - alpha * qv[u];
+    }
+}
+
+template <typename T>
+hipError_t launch_update_r(const LevelView& L, T* r, const T* q, const double* scal, int i_num, int i_den,
+                           hipStream_t s)
+{
+    static const int cap = kernel_cap(k_update_r<T>);
+    hipLaunchKernelGGL(k_update_r<T>, dim3(flat_grid(flat_vectors<T>(L), cap)), dim3(FL_NT), 0, s, L,
+                       flat_vectors<T>(L), r, q, scal, i_num, i_den);
+    return hipGetLastError();
+}
+
 // x += alpha p (x = alpha p on the first step), r -= alpha q (all split),
 // alpha = scal[i_num]/scal[i_den]; with NORM, partials of <r,r>_W. A non-finite alpha leaves
 // x and r untouched (the caller then reports the breakdown with x still the
@@ -1809,6 +1910,9 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
     template hipError_t launch_dot<T>(const LevelView&, const T*, const T*, double*, hipStream_t);                 \
     template hipError_t launch_update_p<T>(const LevelView&, const T*, const T*, T*, const double*, int, int, int,  \
                                            hipStream_t);                                                          \
+    template hipError_t launch_update_px<T>(const LevelView&, const T*, const T*, T*, T*, const double*, int, int, \
+                                            int, int, int, hipStream_t);                                       \
+    template hipError_t launch_update_r<T>(const LevelView&, T*, const T*, const double*, int, int, hipStream_t); \
     template hipError_t launch_update_xr<T>(const LevelView&, T*, T*, const T*, const T*, const double*, int, int, \
                                             double*, hipStream_t, int*, int);                                     \
     template int flat_blocks<T>(const LevelView&);                                                                \

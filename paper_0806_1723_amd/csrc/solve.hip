@@ -196,8 +196,10 @@ static lasto_status mg32_inner(lasto_grid g, const lasto_solve_opts& o, int cycl
 }
 
 // Inner FP32 PCG on A e = r32 from e = 0, `iters` steps, then v += e. The
-// last step's update goes straight into v (e + alpha p): its residual is not
-// needed, since the refinement recomputes the true one in FP64.
+// update e += alpha p of each step is deferred into the next step's update
+// of p (which reads the old p anyway); the last step's goes straight into v
+// (v += e + alpha p): its residual is not needed, since the refinement
+// recomputes the true one in FP64.
 static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int iters, int* vcycles, double* v)
 {
     const LevelView& V = g->lev[0].view;
@@ -212,7 +214,13 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
         if (lasto_status e = reduce_to(g, nd, srz); e != LASTO_OK) return e;
         float* pn = g->p32[it & 1];
         float* po = g->p32[(it + 1) & 1];
-        HIPCHK(launch_update_p<float>(V, g->z32, po, pn, g->scalars, srz, srz_old, it == 0, s));
+        if (it == 0) {
+            HIPCHK(launch_update_p<float>(V, g->z32, po, pn, g->scalars, srz, srz_old, 1, s));
+        } else {
+            // e (=, then +=) alpha_prev p_old, alpha_prev = (r,z) / (p,q) of the previous step
+            HIPCHK(launch_update_px<float>(V, g->z32, po, pn, g->e32, g->scalars, srz, srz_old, srz_old, S_PQ32,
+                                           it >= 2, s));
+        }
         int npq = 0;
         if (lasto_status e = apply_dot<float>(g, pn, g->q32, &npq); e != LASTO_OK) return e;
         if (lasto_status e = reduce_to(g, npq, S_PQ32); e != LASTO_OK) return e;
@@ -222,8 +230,7 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
             break;
         }
         // (the inner loop never reads its own residual norm)
-        HIPCHK(launch_update_xr<float>(V, g->e32, rr, pn, g->q32, g->scalars, srz, S_PQ32, nullptr, s, nullptr,
-                                       it == 0));
+        HIPCHK(launch_update_r<float>(V, rr, g->q32, g->scalars, srz, S_PQ32, s));
     }
     return LASTO_OK;
 }
