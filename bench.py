@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # Summary: profiles/k_half2_fp32_finest_257_traffic.md. The figure belongs to
 # the kernel source it was measured on and to the same solve form; `traffic`
 # is reported as null when either differs.
-COUNTER_TRAFFIC = {"kernel_sha256_16": "191803d67b975fc8", "form": (1, 0, 6, 5, 2, 2), "bytes_per_launch": 114.85e6}
+COUNTER_TRAFFIC = {"kernel_sha256_16": "191803d67b975fc8", "form": (1, 0, 5, 4, 3, 3), "bytes_per_launch": 116.99e6}
 
 
 def half_sweep_source_digest():
@@ -98,8 +98,10 @@ def main():
     centers = np.array([a.center for a in w.atoms])
     radii = np.array([a.radius for a in w.atoms])
 
-    # the first refinement's reduction is bounded by FP32 rounding after 5 PCG steps
-    form = dict(precision=mixed, method=0, inner_iters=6, inner_first=5 if mixed else 0, nu1=2, nu2=2)
+    # V(3,3) cycles (with the exact coarsest solve, fewer cycles than V(2,2)
+    # for less time in both forms); in the mixed form four FP32 PCG steps per
+    # refinement reach the FP32 rounding floor, and two refinements 1e-10
+    form = dict(precision=mixed, method=0, inner_iters=5, inner_first=4 if mixed else 0, nu1=3, nu2=3)
 
     def step(profile, precision):
         g.pseudo_density(atoms, rho_out=rho)
@@ -142,7 +144,8 @@ def main():
     fp64 = []
     for si in range(max(3, args.steps)):
         v.zero_()
-        fp64.append(g.poisson_solve(rho, v, rtol=w.rtol, precision=0, profile=1 if si == 1 else 0))
+        fp64.append(g.poisson_solve(rho, v, rtol=w.rtol, precision=0, nu1=form["nu1"], nu2=form["nu2"],
+                                    profile=1 if si == 1 else 0))
     fp64_ms = statistics.median(i["ms_total"] for i in fp64[2:])
     kept["fp64"] = (v[0] if nb > 1 else v).cpu().numpy()
     f_ms = fp64[1]["smooth_ms"]
