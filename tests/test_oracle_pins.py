@@ -427,3 +427,68 @@ def test_interp_exact_on_cubics(oracle_mod):
     # at a node: exactly that node's value
     g = oracle_mod.interp(xs, v, np.array([[xs[0][3], xs[1][5], xs[2][7]]]))
     assert g[0] == v[7, 5, 3]
+
+
+# ------------------------------------------------------- smoother sweep
+@pytest.mark.parametrize("first", [0, 1])
+def test_rb_sweep_solves_each_colour_in_turn(oracle_mod, first):
+    """One red-black Gauss-Seidel sweep, checked through the (separately
+    pinned) operator: after the sweep every node of the colour updated last
+    satisfies its own equation exactly with the final neighbours, and every
+    node of the colour updated first satisfies its equation with its own new
+    value and the other colour's values from before the sweep. A damped or
+    over-relaxed update, a swapped colour order, a dropped coefficient or a
+    wrong parity test leaves a residual at one of the two colours; faces and
+    the colour order of the input are untouched."""
+    rng = np.random.default_rng(21)
+    xs = [random_graded(rng, n) for n in (10, 9, 11)]
+    nz, ny, nx = 11, 9, 10
+    u = rng.normal(size=(nz, ny, nx))
+    rho = rng.normal(size=(nz, ny, nx))
+    out = oracle_mod.rb_sweep(xs, u, rho, first)
+    K, J, Ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    colour = (Ii + J + K) % 2
+    inner = np.zeros_like(u, bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    b = 4 * np.pi * rho
+    scale = np.abs(b[inner]).max() + np.abs(oracle_mod.apply(xs, u)[inner]).max()
+    last = inner & (colour == 1 - first)
+    r_last = oracle_mod.apply(xs, out) - b
+    assert np.abs(r_last[last]).max() < 1e-12 * scale
+    mixed = np.where(colour == first, out, u)
+    r_first = oracle_mod.apply(xs, mixed) - b
+    one = inner & (colour == first)
+    assert np.abs(r_first[one]).max() < 1e-12 * scale
+    # the first colour's new values are not already solutions with the final
+    # neighbours (the sweep is not a Jacobi step in disguise)
+    assert np.abs(r_last[one]).max() > 1e-3 * scale
+    assert np.array_equal(out[~inner], u[~inner])
+
+
+# ------------------------------------------- interstitial density mask
+def test_interstitial_density_added_outside_spheres_only(oracle_mod):
+    """rho_inter is added at nodes with |x - C|^2 >= R^2 for every sphere and
+    nowhere else. On a unit lattice, a sphere of radius 2 about a node holds
+    27 lattice points strictly inside (|n|^2 in {0, 1, 2, 3}); the node at
+    distance exactly 2 keeps the density, and a second sphere of radius 1.5
+    about a cell centre removes its 8 corners. The atoms carry no charge of
+    their own, so only the interstitial term shows."""
+    x = np.arange(-6.0, 7.0)
+    xs = [x, x, x]
+    n = len(x)
+    centers = np.array([[-2.0, 0.0, 0.0], [3.5, 3.5, 3.5]])
+    atoms = [I.Atom(center=c, q=0.0, radius=r, lmax=0) for c, r in zip(centers, (2.0, 1.5))]
+    A = I.atom_arrays(atoms)
+    rng = np.random.default_rng(22)
+    inter = rng.uniform(1.0, 2.0, size=(n, n, n))
+    rho = oracle_mod.pseudo_density(xs, A, rho_inter=inter)
+    removed = rho == 0.0
+    assert removed.sum() == 27 + 8
+    assert np.array_equal(rho[~removed], inter[~removed])
+    ix = lambda c: int(round(c + 6.0))
+    # exactly on the first sphere (distance 2) and one lattice step beyond the corners
+    assert rho[ix(0), ix(0), ix(0)] == inter[ix(0), ix(0), ix(0)]
+    assert rho[ix(0), ix(0), ix(-4)] == inter[ix(0), ix(0), ix(-4)]
+    assert rho[ix(0), ix(0), ix(-2)] == 0.0 and rho[ix(1), ix(1), ix(-1)] == 0.0
+    assert rho[ix(3), ix(3), ix(3)] == 0.0 and rho[ix(4), ix(4), ix(4)] == 0.0
+    assert rho[ix(5), ix(4), ix(4)] == inter[ix(5), ix(4), ix(4)]
