@@ -368,6 +368,17 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     }
     double target = o.rtol;
     if (!std::isfinite(r0) || !std::isfinite(rel)) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: non-finite rho or v");
+    if (r0 == 0.0) {
+        // the face data alone satisfy every interior equation exactly (for
+        // instance rho = 0 with zero faces): the solution is the zero interior
+        HIPCHK(launch_fill_zero<double>(g->q, split_elems(V), s));
+        HIPCHK(launch_split_to_nat(V, g->q, v, s));
+        HIPCHK(hipStreamSynchronize(s));
+        inf.n_batch = nbat;
+        inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        if (info) *info = inf;
+        return LASTO_OK;
+    }
 
     lasto_status result = LASTO_OK;
     double best = rel;

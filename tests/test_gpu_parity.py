@@ -165,7 +165,14 @@ SOLVE_CASES = [
     (2, 65, dict(coarse=2)),
     (2, 129, dict(coarse=2)),
     (2, 129, dict(precision=1, coarse=2)),
+    # the benchmark's forms on the 55-atom cluster: V(3,3), FP32 PCG with 4
+    # then 5 steps per FP64 refinement, and the FP64 PCG
+    (3, 129, dict(precision=1, method=0, inner_iters=5, inner_first=4, nu1=3, nu2=3)),
+    (3, 129, dict(nu1=3, nu2=3)),
 ]
+
+# the benchmark's two timed forms (mixed, FP64)
+BENCH_FORMS = [dict(precision=1, method=0, inner_iters=5, inner_first=4, nu1=3, nu2=3), dict(nu1=3, nu2=3)]
 
 
 @pytest.mark.parametrize("cid,n,opts", SOLVE_CASES)
@@ -188,6 +195,30 @@ def test_solve_matches_oracle(torch, L, oracle_mod, cid, n, opts):
     assert err <= 1e-9
     # the oracle's own operator confirms the residual
     assert oracle_mod.rel_residual(xs, rho_o, got) <= 2e-12
+    g.close()
+
+
+@pytest.mark.parametrize("form", BENCH_FORMS)
+def test_bench_form_at_the_headline_tolerance_matches_oracle(torch, L, oracle_mod, form):
+    """The benchmark's forms stopped at its tolerance (1e-10) on the
+    55-atom cluster at 129^3: the solution matches the oracle's (solved to
+    1e-12) to 1e-9 in the relative W-norm, and the oracle's own operator
+    confirms the residual."""
+    say("bench form at 1e-10, config 3 n=129 %s" % form)
+    w = I.config(3, n_override=129)
+    xs = oracle_mod.mesh_for(w.axes)
+    rho_o, v_o = oracle_solution(oracle_mod, xs, w.atoms)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    v = g.empty()
+    info = g.poisson_solve(rho, v, rtol=1e-10, **form)
+    got = v.cpu().numpy()
+    err = wnorm(xs, got - v_o) / wnorm(xs, v_o)
+    say("  iters %d vcycles %d refinements %d rel %.2e, error vs oracle %.3e" % (
+        info["iters"], info["vcycles"], info["refinements"], info["rel_resid"], err))
+    assert info["rel_resid"] <= 1e-10
+    assert err <= 1e-9
+    assert oracle_mod.rel_residual(xs, rho_o, got) <= 1.05e-10
     g.close()
 
 
@@ -286,6 +317,39 @@ def test_batched_solve_matches_oracle_per_copy(torch, L, oracle_mod, opts):
     pts = oracle_mod.sphere_points(centers, radii, I.default_directions())
     for b in range(3):
         want = oracle_mod.interp(xs, got[b], pts).reshape(13, 64)
+        assert np.abs(sph[b] - want).max() <= 1e-13 * np.abs(want).max()
+    g.close()
+
+
+def test_mackay_cluster_batch_matches_oracle_per_copy(torch, L, oracle_mod):
+    """The 309-atom Mackay icosahedron with its 8 SCF-like perturbations
+    (1 % multiplicative noise on q and c_lm) on one batched grid, at 65^3 per
+    copy, in the benchmark's mixed form: each copy's source, moments and
+    solution match the oracle's run of that copy, and the sphere values are
+    each copy's own."""
+    say("batched solve, 8 x config 5 (309 atoms) n=65, bench mixed form")
+    w = I.config(5, n_override=65)
+    xs = oracle_mod.mesh_for(w.axes)
+    assert len(w.atoms) == 309 and len(w.batch_atoms) == 8
+    g = L.Grid(*xs, n_batch=8)
+    rho, Q = g.pseudo_density(w.batch_atoms, moments=True)
+    v = g.empty()
+    info = g.poisson_solve(rho, v, rtol=1e-12, **BENCH_FORMS[0])
+    say("  iters %d vcycles %d per-copy rel %s" % (info["iters"], info["vcycles"], info["batch_rel_resid"]))
+    assert max(info["batch_rel_resid"]) <= 1e-12
+    got = v.cpu().numpy()
+    centers = np.array([a.center for a in w.atoms])
+    radii = np.array([a.radius for a in w.atoms])
+    sph = g.sphere_interp(v, centers, radii)
+    pts = oracle_mod.sphere_points(centers, radii, I.default_directions())
+    for b, atoms in enumerate(w.batch_atoms):
+        rho_o, v_o = oracle_solution(oracle_mod, xs, atoms)
+        assert np.abs(rho[b].cpu().numpy() - rho_o).max() <= 1e-12 * np.abs(rho_o).max()
+        assert np.abs(Q[b] - oracle_mod.moments(xs, rho_o, 4)).max() <= 1e-11 * np.abs(Q[b]).max()
+        err = wnorm(xs, got[b] - v_o) / wnorm(xs, v_o)
+        say("  copy %d: rel W-norm error vs oracle %.3e" % (b, err))
+        assert err <= 1e-9
+        want = oracle_mod.interp(xs, got[b], pts).reshape(309, 64)
         assert np.abs(sph[b] - want).max() <= 1e-13 * np.abs(want).max()
     g.close()
 
@@ -472,6 +536,15 @@ def test_failure_paths(torch, L, oracle_mod):
     v2 = g.empty()
     g.poisson_solve(rho, v2, rtol=1e-12)
     assert float((v1 - v2).abs().max()) <= 1e-9 * float(v2.abs().max())
+    # a problem the faces alone solve (rho = 0, zero faces): OK, the zero
+    # interior, no iteration, in every form
+    zero = torch.zeros_like(rho)
+    for opts in (dict(), dict(precision=1), dict(method=1)):
+        v3 = g.empty()
+        v3.fill_(3.0)
+        info = g.poisson_solve(zero, v3, bc=0, **opts)
+        assert info["rel_resid"] == 0.0 and info["iters"] == 0
+        assert float(v3.abs().max()) == 0.0
     g.close()
 
 
