@@ -228,6 +228,26 @@ lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, double* v,
 lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n_atoms, const double* centers,
                                  const double* radii, int n_dir, const double* dirs, double* out);
 
+/*
+ * lasto_sphere_interp for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same values, bit for bit, with no hipMalloc or hipFree. Its
+ * staging (the points, the device values, and copies of the directions,
+ * centres and radii) lives in a static device array of the library, sized for
+ * LASTO_NOALLOC_MAX_POINTS points (11 doubles per point, 2.75 MiB), which each
+ * GPU the library runs on holds until the process ends; its device address is
+ * looked up once per device, on the first call there.
+ *   Arguments, layout and ownership as lasto_sphere_interp.
+ *   n_atoms * n_dir > LASTO_NOALLOC_MAX_POINTS -> LASTO_ERR_ARG (nothing runs).
+ * Every call on one GPU shares that array: calls that overlap on one GPU (from
+ * two host threads, or on two streams) race; serialise them. Each call writes
+ * every part of the array it reads, so no clearing is needed between calls.
+ * Errors: as lasto_sphere_interp.
+ */
+#define LASTO_NOALLOC_MAX_POINTS 32768
+lasto_status lasto_sphere_interp_noalloc(lasto_grid g, const double* v, int n_atoms, const double* centers,
+                                         const double* radii, int n_dir, const double* dirs, double* out);
+
 /* ------------------------------------------------------------------------
  * Inside the muffin-tin spheres (Section 3, eq. (3.4)-(3.7)) and the energy
  * integral of Section 4. The grid solution gives V_C on each sphere boundary;

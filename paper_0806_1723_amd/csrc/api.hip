@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -252,6 +254,62 @@ extern "C" lasto_status lasto_analytic_guess(lasto_grid g, int n_atoms, const la
     return LASTO_OK;
 }
 
+// The 64 default directions of the sphere values: 8 Gauss-Legendre nodes in
+// cos(theta) (roots of P_8 by Newton, ascending) times 8 azimuths
+// 2 pi (b + 1/2)/8, theta-major; d[3 k + c].
+static void default_directions(double* d)
+{
+    double t[8];
+    for (int a = 0; a < 8; ++a) {
+        double xx = std::cos(kPi * (a + 0.75) / 8.5);
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = xx;
+            for (int k = 2; k <= 8; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * xx * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = 8.0 * (xx * p1 - p0) / (xx * xx - 1.0);
+            const double dx = p1 / dp;
+            xx -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        t[a] = xx;
+    }
+    std::sort(t, t + 8);
+    for (int a = 0; a < 8; ++a) {
+        const double st = std::sqrt(std::max(0.0, 1.0 - t[a] * t[a]));
+        for (int b = 0; b < 8; ++b) {
+            const double ph = 2.0 * kPi * (b + 0.5) / 8.0;
+            double* o = d + 3 * (8 * a + b);
+            o[0] = st * std::cos(ph);
+            o[1] = st * std::sin(ph);
+            o[2] = t[a];
+        }
+    }
+}
+
+// sphere point C_a + R_a d_k, component c (the product rounded, then the sum)
+static inline double sphere_point(const double* centers, const double* radii, const double* d, int a, int k, int c)
+{
+    return centers[3 * a + c] + radii[a] * d[3 * k + c];
+}
+
+// every sphere point inside the box of level 0
+static lasto_status check_sphere_points(lasto_grid g, int n_atoms, const double* centers, const double* radii,
+                                        int n_dir, const double* d, const char* who)
+{
+    const Level& L0 = g->lev[0];
+    for (int a = 0; a < n_atoms; ++a)
+        for (int k = 0; k < n_dir; ++k)
+            for (int c = 0; c < 3; ++c) {
+                const double p = sphere_point(centers, radii, d, a, k, c);
+                if (!std::isfinite(p) || p < L0.hx[c].front() || p > L0.hx[c].back())
+                    return fail(LASTO_ERR_ARG, std::string(who) + ": point outside the box");
+            }
+    return LASTO_OK;
+}
+
 extern "C" lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n_atoms, const double* centers,
                                             const double* radii, int n_dir, const double* dirs, double* out)
 {
@@ -263,48 +321,18 @@ extern "C" lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n
         d.assign(dirs, dirs + 3 * (size_t)n_dir);
     } else {
         if (n_dir != 64) return fail(LASTO_ERR_ARG, "lasto_sphere_interp: default directions need n_dir = 64");
-        // 8 Gauss-Legendre nodes in cos(theta) (roots of P_8 by Newton) x 8 azimuths
-        double t[8];
-        for (int a = 0; a < 8; ++a) {
-            double xx = std::cos(kPi * (a + 0.75) / 8.5);
-            for (int it = 0; it < 100; ++it) {
-                double p0 = 1.0, p1 = xx;
-                for (int k = 2; k <= 8; ++k) {
-                    const double p2 = ((2.0 * k - 1.0) * xx * p1 - (k - 1.0) * p0) / k;
-                    p0 = p1;
-                    p1 = p2;
-                }
-                const double dp = 8.0 * (xx * p1 - p0) / (xx * xx - 1.0);
-                const double dx = p1 / dp;
-                xx -= dx;
-                if (std::fabs(dx) < 1e-16) break;
-            }
-            t[a] = xx;
-        }
-        std::sort(t, t + 8);
-        for (int a = 0; a < 8; ++a) {
-            const double st = std::sqrt(std::max(0.0, 1.0 - t[a] * t[a]));
-            for (int b = 0; b < 8; ++b) {
-                const double ph = 2.0 * kPi * (b + 0.5) / 8.0;
-                d.push_back(st * std::cos(ph));
-                d.push_back(st * std::sin(ph));
-                d.push_back(t[a]);
-            }
-        }
+        d.resize(3 * 64);
+        default_directions(d.data());
     }
     const size_t np = (size_t)n_atoms * n_dir;
     if (np == 0) return LASTO_OK;
+    if (lasto_status e = check_sphere_points(g, n_atoms, centers, radii, n_dir, d.data(), "lasto_sphere_interp");
+        e != LASTO_OK)
+        return e;
     std::vector<double> pts(3 * np);
-    const Level& L0 = g->lev[0];
     for (int a = 0; a < n_atoms; ++a)
-        for (int k = 0; k < n_dir; ++k) {
-            for (int c = 0; c < 3; ++c) {
-                const double p = centers[3 * a + c] + radii[a] * d[3 * k + c];
-                if (!std::isfinite(p) || p < L0.hx[c].front() || p > L0.hx[c].back())
-                    return fail(LASTO_ERR_ARG, "lasto_sphere_interp: point outside the box");
-                pts[3 * ((size_t)a * n_dir + k) + c] = p;
-            }
-        }
+        for (int k = 0; k < n_dir; ++k)
+            for (int c = 0; c < 3; ++c) pts[3 * ((size_t)a * n_dir + k) + c] = sphere_point(centers, radii, d.data(), a, k, c);
     const size_t bytes = sizeof(double) * 4 * np;
     if (bytes > g->stage_bytes) {
         (void)hipStreamSynchronize(g->stream);
@@ -322,6 +350,99 @@ extern "C" lasto_status lasto_sphere_interp(lasto_grid g, const double* v, int n
         LASTO_HIP(launch_interp(g, v + b * N, dpts, (int)np, dout));
         LASTO_HIP(hipMemcpyAsync(out + b * np, dout, sizeof(double) * np, hipMemcpyDeviceToHost, g->stream));
         LASTO_HIP(hipStreamSynchronize(g->stream));
+    }
+    return LASTO_OK;
+}
+
+// ------------------------------------------- allocation-free sphere values
+// Staging of lasto_sphere_interp_noalloc in one static device array per GPU:
+// [points 3P][values P][directions 3P][centres 3P][radii P] doubles,
+// P = LASTO_NOALLOC_MAX_POINTS (n_dir <= P and n_atoms <= P, since both are at
+// least 1 and their product is at most P). Every region is written before it
+// is read, so nothing needs clearing between calls.
+constexpr size_t kNaPts = 0, kNaVals = 3 * (size_t)LASTO_NOALLOC_MAX_POINTS,
+                 kNaDirs = 4 * (size_t)LASTO_NOALLOC_MAX_POINTS, kNaCent = 7 * (size_t)LASTO_NOALLOC_MAX_POINTS,
+                 kNaRad = 10 * (size_t)LASTO_NOALLOC_MAX_POINTS, kNaTotal = 11 * (size_t)LASTO_NOALLOC_MAX_POINTS;
+static __device__ __align__(256) double scratch[kNaTotal];
+
+// The device address of `scratch` on each device, taken once per device with
+// that device current (the host-side name is not a device address).
+constexpr int kNaMaxDevices = 64;
+static std::mutex g_na_mutex;
+static double* g_na_ptr[kNaMaxDevices] = {};
+
+static lasto_status noalloc_scratch(int device, double** out)
+{
+    if (device < 0 || device >= kNaMaxDevices) return fail(LASTO_ERR_ARG, "noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (!g_na_ptr[device]) {
+        int cur = 0;
+        LASTO_HIP(hipGetDevice(&cur));
+        if (cur != device) LASTO_HIP(hipSetDevice(device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(LASTO_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_na_ptr[device] = (double*)p;
+    }
+    *out = g_na_ptr[device];
+    return LASTO_OK;
+}
+
+// p[3 t + c] = centre[3 a + c] + radius[a] dir[3 k + c], t = a n_dir + k: the
+// points the host path forms (product rounded, then the sum; no fused multiply-add)
+__global__ __launch_bounds__(64) void k_sphere_points(const double* __restrict__ cen, const double* __restrict__ rad,
+                                                      const double* __restrict__ dir, int n_dir, int np,
+                                                      double* __restrict__ pts)
+{
+#pragma clang fp contract(off)
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= np) return;
+    const int a = t / n_dir, k = t - a * n_dir;
+    for (int c = 0; c < 3; ++c) {
+        const double prod = rad[a] * dir[3 * k + c];
+        pts[3 * t + c] = cen[3 * a + c] + prod;
+    }
+}
+
+extern "C" lasto_status lasto_sphere_interp_noalloc(lasto_grid g, const double* v, int n_atoms, const double* centers,
+                                                    const double* radii, int n_dir, const double* dirs, double* out)
+{
+    const char* who = "lasto_sphere_interp_noalloc";
+    if (!g || !v || !out || n_atoms < 0 || (n_atoms > 0 && (!centers || !radii)))
+        return fail(LASTO_ERR_ARG, std::string(who) + ": NULL argument");
+    double dflt[3 * 64];
+    const double* d = dirs;
+    if (dirs) {
+        if (n_dir < 1) return fail(LASTO_ERR_ARG, std::string(who) + ": n_dir must be >= 1");
+    } else {
+        if (n_dir != 64) return fail(LASTO_ERR_ARG, std::string(who) + ": default directions need n_dir = 64");
+        default_directions(dflt);
+        d = dflt;
+    }
+    const long long np = (long long)n_atoms * n_dir;
+    if (np == 0) return LASTO_OK;
+    if (np > LASTO_NOALLOC_MAX_POINTS)
+        return fail(LASTO_ERR_ARG, std::string(who) + ": n_atoms * n_dir exceeds LASTO_NOALLOC_MAX_POINTS (" +
+                                       std::to_string(LASTO_NOALLOC_MAX_POINTS) + ")");
+    if (lasto_status e = check_sphere_points(g, n_atoms, centers, radii, n_dir, d, who); e != LASTO_OK) return e;
+    double* S = nullptr;
+    if (lasto_status e = noalloc_scratch(g->device, &S); e != LASTO_OK) return e;
+    hipStream_t s = g->stream;
+    LASTO_HIP(hipMemcpyAsync(S + kNaDirs, d, sizeof(double) * 3 * n_dir, hipMemcpyHostToDevice, s));
+    LASTO_HIP(hipMemcpyAsync(S + kNaCent, centers, sizeof(double) * 3 * n_atoms, hipMemcpyHostToDevice, s));
+    LASTO_HIP(hipMemcpyAsync(S + kNaRad, radii, sizeof(double) * n_atoms, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sphere_points, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, s, (const double*)(S + kNaCent),
+                       (const double*)(S + kNaRad), (const double*)(S + kNaDirs), n_dir, (int)np, S + kNaPts);
+    LASTO_HIP(hipGetLastError());
+    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    for (int b = 0; b < g->n_batch; ++b) {
+        LASTO_HIP(launch_interp(g, v + b * N, S + kNaPts, (int)np, S + kNaVals));
+        LASTO_HIP(hipMemcpyAsync(out + b * np, S + kNaVals, sizeof(double) * np, hipMemcpyDeviceToHost, s));
+        // the values region is reused by the next copy; the host inputs
+        // (default directions on this stack frame) stay alive until here
+        LASTO_HIP(hipStreamSynchronize(s));
     }
     return LASTO_OK;
 }

@@ -17,6 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblasto.so")
 
 OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_CONVERGED, ERR_DIVERGED, ERR_STATE = range(7)
+# points one call of lasto_sphere_interp_noalloc may take (LASTO_NOALLOC_MAX_POINTS)
+NOALLOC_MAX_POINTS = 32768
 
 
 class LastoError(RuntimeError):
@@ -96,7 +98,7 @@ class SolveInfo(C.Structure):
 SYMBOLS = [
     "lasto_status_string", "lasto_last_error", "lasto_mesh_graded_1d", "lasto_grid_create",
     "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
-    "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp",
+    "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp", "lasto_sphere_interp_noalloc",
     "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_density_terms", "lasto_sphere_project", "lasto_sphere_radial",
     "lasto_sphere_energy", "lasto_interstitial_density", "lasto_matrix_elements", "lasto_fdm_solve",
     "lasto_fdm_axis", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
@@ -155,6 +157,8 @@ def load():
     L.lasto_poisson_solve.restype = i
     L.lasto_sphere_interp.argtypes = [P, P, i, P, P, i, P, P]
     L.lasto_sphere_interp.restype = i
+    L.lasto_sphere_interp_noalloc.argtypes = [P, P, i, P, P, i, P, P]
+    L.lasto_sphere_interp_noalloc.restype = i
     L.lasto_spheres_create.argtypes = [P, i, P, P, P, i, i, i, d, C.POINTER(P)]
     L.lasto_spheres_create.restype = i
     L.lasto_spheres_destroy.argtypes = [P]
@@ -370,7 +374,8 @@ class Grid:
             _check(st)
         return d
 
-    def sphere_interp(self, v, centers, radii, dirs=None) -> np.ndarray:
+    def sphere_interp(self, v, centers, radii, dirs=None, noalloc: bool = False) -> np.ndarray:
+        """V at C_a + R_a d_k (lasto_sphere_interp; noalloc: lasto_sphere_interp_noalloc)."""
         centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
         radii = np.ascontiguousarray(radii, dtype=np.float64).ravel()
         na = len(centers)
@@ -382,8 +387,8 @@ class Grid:
             nd = len(dirs)
             dp = _np_ptr(dirs)
         out = np.zeros((self.n_batch, na, nd))
-        _check(load().lasto_sphere_interp(self.h, _dev_ptr(v), na, _np_ptr(centers), _np_ptr(radii), nd, dp,
-                                          _np_ptr(out)))
+        fn = load().lasto_sphere_interp_noalloc if noalloc else load().lasto_sphere_interp
+        _check(fn(self.h, _dev_ptr(v), na, _np_ptr(centers), _np_ptr(radii), nd, dp, _np_ptr(out)))
         return out[0] if self.n_batch == 1 else out
 
     def apply(self, u, Au=None):

@@ -81,3 +81,9 @@ def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):
         L._dev_ptr(torch.zeros(3, dtype=torch.float64))
+
+
+def test_noalloc_limit_matches_the_header():
+    src = open(HEADER).read()
+    m = re.search(r"#define LASTO_NOALLOC_MAX_POINTS (\d+)", src)
+    assert m and int(m.group(1)) == L.NOALLOC_MAX_POINTS
