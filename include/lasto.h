@@ -41,6 +41,8 @@ extern "C" {
 #endif
 
 typedef struct lasto_grid_s* lasto_grid;
+/* a learned-form network (see lasto_net_create) */
+typedef struct lasto_net_s* lasto_net;
 
 typedef enum {
     LASTO_OK = 0,
@@ -154,7 +156,10 @@ typedef struct {
                            precision 1 it selects the inner FP32 solver the same way */
     int precision;      /* 0 FP64 throughout (default); 1 FP32 V-cycles inside FP64 refinement */
     int inner_iters;    /* precision 1: FP32 PCG steps or V-cycles per FP64 refinement (default 6) */
-    int guess;          /* 0 use the interior of v as given (default), 1 zero interior */
+    int guess;          /* interior start: 0 v as given (default), 1 zero, 2 the analytic superposition of
+                           the atoms' monopole fields (lasto_analytic_guess), 3 that plus the learned
+                           correction of guess_net, judged as lasto_learned_guess (the analytic start is
+                           kept when the learned one is no better: info->fallback_used bit 0) */
     int bc;             /* 0 zero faces (eq. (3.3)), 1 multipole faces (default), 2 faces of v as given */
     int lmax_bc;        /* multipole order of the face values, 0..4 (default 4) */
     int debug_nan_iter; /* >= 0: inject a NaN into the residual at that iteration (tests only); default -1 */
@@ -167,6 +172,16 @@ typedef struct {
                            (by GEMMs), else as 2; 2 on the first level with at most 16384 nodes (each axis
                            at most 34 nodes, the level below the finest, its block in one workgroup's LDS),
                            else as 1; 1 red-black sweeps on every level down to the coarsest */
+    int fallback;       /* precision 1: 1 (default) when the FP32 inner solve breaks down (a non-finite
+                           correction, which is never added to v), the residual keeps growing, or max_iters
+                           pass, the solve restarts as FP64 MG-PCG from the current iterate with max_iters
+                           more iterations (info->fallback_used bit 1); 0 returns the failure */
+    int n_atoms;        /* guess 2, 3: atoms per right-hand side in `atoms` */
+    const lasto_atom* atoms;   /* guess 2, 3: host atom tables as for lasto_pseudo_density */
+    lasto_net guess_net;       /* guess 3: the learned-guess net (its grid: one copy of the finest level) */
+    lasto_net coarse_net;      /* learned coarse correction (NULL: none): a net trained to map a coarse
+                                  level's restricted residual to its correction; see lasto_poisson_solve */
+    int coarse_net_level;      /* the level it acts on (>= 1, above the exact coarsest solve) */
 } lasto_solve_opts;
 
 typedef struct {
@@ -185,6 +200,15 @@ typedef struct {
     int n_batch;            /* right-hand sides solved (the grid's n_batch) */
     double batch_rel_resid[16]; /* rel_resid of each right-hand side (rel_resid is their maximum) */
     int coarse_level;       /* level the cycle solved exactly by fast diagonalisation, -1 if none */
+    int fallback_used;      /* bit 0: guess 3 kept the analytic start; bit 1: FP64 finished a failed mixed solve */
+    int guess_accepted;     /* guess 3: right-hand sides whose learned start was kept */
+    int coarse_applied;     /* learned coarse corrections proposed (one per visit of coarse_net_level) */
+    int coarse_accepted;    /* ... and accepted by the coarse residual test */
+    double ms_bc;           /* moments and face values (HIP events on the grid's stream), ms */
+    double ms_guess;        /* the initial guess (analytic superposition, net and judge), ms */
+    double ms_cycles;       /* the iteration to the exit residual, ms */
+    double alg_bytes;       /* algorithmic HBM bytes of the iteration's finest-level launches (each launch's
+                               compulsory reads and writes of whole arrays) */
 } lasto_solve_info;
 
 void lasto_solve_opts_default(lasto_solve_opts* o);
@@ -206,6 +230,17 @@ void lasto_solve_opts_default(lasto_solve_opts* o);
  * coefficients for the stacked system, i.e. CG on the block-diagonal
  * operator) until every copy meets rtol against its own reference norm
  * (info->batch_rel_resid); each copy's faces come from its own moments.
+ * Learned coarse correction (opts->coarse_net, one right-hand side): each
+ * time a cycle reaches level c = coarse_net_level, the net reads that level's
+ * restricted residual f_c at unit RMS s (s = ||f_c||_W / sqrt(sum of the
+ * interior dual volumes)) with the level's spacings, and proposes
+ * e^ = s out_scale net(f_c / s) for A_c e = f_c; e^ starts the level's cycle
+ * if ||f_c - A_c e^||_W < ||f_c||_W, otherwise it starts from zero as without
+ * the net (the test runs on the device; info->coarse_applied / _accepted
+ * count the proposals). The preconditioner then varies from step to step, so
+ * the CG forms take the flexible (Polak-Ribiere) beta. Level c must lie above
+ * the cycle's exact coarsest solve or one-workgroup tail (coarse = 2 or 1
+ * make room) and fit the net's creation size.
  * Returns LASTO_OK, or LASTO_ERR_NOT_CONVERGED / LASTO_ERR_DIVERGED with v
  * and info filled, or LASTO_ERR_ARG / LASTO_ERR_HIP.
  */
@@ -447,7 +482,10 @@ lasto_status lasto_apply(lasto_grid g, const double* u, double* Au);
 /*
  * One red-black Gauss-Seidel sweep on A u = 4 pi rho at the finest level,
  * out of place: u_out = S(u_in). Nodes with (i+j+k) % 2 == first_colour are
- * updated first from u_in, the other colour then from those new values.
+ * updated first from u_in, the other colour then from those new values. On a
+ * batched grid k counts planes of the stacked copies (copy b starts at plane
+ * b nz), so with an odd nz the copies at odd b take the colours in the other
+ * order (every solve form converges to the same solution either way).
  * Faces of u_out are left untouched (copy them from u_in when needed).
  * This is the smoother of the multigrid solve, exposed for testing.
  *   u_in, rho, u_out: device [nz][ny][nx]; u_out must not alias u_in.
@@ -484,8 +522,6 @@ lasto_status lasto_analytic_guess(lasto_grid g, int n_atoms, const lasto_atom* a
  * kernels. Plain multigrid stays the judge: lasto_learned_guess keeps the
  * correction only if it lowers the residual.
  */
-typedef struct lasto_net_s* lasto_net;
-
 typedef struct {
     int nx, ny, nz;              /* node grid the net runs on (the grid's finest level); each >= 8 */
     int ch[4];                   /* channels per level: ch[0] = 16, the others 16, 32, 48 or 64 */
@@ -500,6 +536,10 @@ typedef struct {
  * LASTO_ERR_ALLOC, LASTO_ERR_HIP. The net owns all its device memory. */
 lasto_status lasto_net_create(const lasto_net_config* cfg, void* hip_stream, lasto_net* out);
 lasto_status lasto_net_destroy(lasto_net n);
+/* Run the net on a node grid of nx * ny * nz (each 8 .. its creation size; every
+ * buffer was allocated for the creation size): the learned coarse correction
+ * meets a different coarse-level shape on each graded mesh. Errors: LASTO_ERR_ARG. */
+lasto_status lasto_net_set_grid(lasto_net n, int nx, int ny, int nz);
 /* Flat FP32 parameter vector: per convolution W[27][cin][cout] then b[cout]
  * (8 convolutions in forward order), then the head w[16] and its bias. */
 lasto_status lasto_net_param_count(lasto_net n, long long* count);
@@ -507,6 +547,39 @@ lasto_status lasto_net_get_params(lasto_net n, float* host, long long count);
 lasto_status lasto_net_set_params(lasto_net n, const float* host, long long count);
 /* gradients of the last lasto_net_backward, same layout */
 lasto_status lasto_net_get_grads(lasto_net n, float* host, long long count);
+/*
+ * Checkpoint and resume of training: the file holds the FP32 masters, Adam's
+ * first and second moments and step count, the seed and the feature and
+ * output scales (not the grid size, which is the loading net's own). A net
+ * loaded from a checkpoint continues training with the same bits as the net
+ * that wrote it, given the same data and learning rates (every reduction of
+ * the forward and backward kernels runs in a fixed order).
+ *   path: host file name; lasto_net_save writes "<path>.tmp" and renames it.
+ * Errors: LASTO_ERR_ARG (NULL, unreadable or foreign file, channel counts
+ * that differ from the net's), LASTO_ERR_STATE (a write failed), LASTO_ERR_HIP.
+ */
+lasto_status lasto_net_save(lasto_net n, const char* path);
+lasto_status lasto_net_load(lasto_net n, const char* path);
+/* the net's configuration (its scales and seed as loaded) and Adam step count (step may be NULL) */
+lasto_status lasto_net_get_config(lasto_net n, lasto_net_config* cfg, long long* step);
+/*
+ * Read access to the net's stored BF16 tensors, for checking each kernel on
+ * the operands it read: after lasto_net_forward the activations e_l (level l,
+ * ch[l] channels), m_3 (level 3, ch[3]), d_l (conv output on level l + 1,
+ * ch[l]) and u_l = up(d_l) + e_l (level l, ch[l]); after lasto_net_backward
+ * the gradient of each convolution's pre-activation output (G0..G7, on its
+ * output level with its output channels) and of u_l (DU0..DU2).
+ *   out: device [nz_l][ny_l][nx_l][c] BF16 bit patterns, count its length, or
+ *   NULL to query the shape; dims: host [4] out: nx_l, ny_l, nz_l, c.
+ * Errors: LASTO_ERR_ARG (NULL dims, unknown tensor, count mismatch), LASTO_ERR_HIP.
+ */
+enum {
+    LASTO_NET_E0 = 0, LASTO_NET_E1, LASTO_NET_E2, LASTO_NET_E3, LASTO_NET_M3,
+    LASTO_NET_D2, LASTO_NET_D1, LASTO_NET_D0, LASTO_NET_U2, LASTO_NET_U1, LASTO_NET_U0,
+    LASTO_NET_G0, LASTO_NET_G1, LASTO_NET_G2, LASTO_NET_G3, LASTO_NET_G4, LASTO_NET_G5, LASTO_NET_G6, LASTO_NET_G7,
+    LASTO_NET_DU0, LASTO_NET_DU1, LASTO_NET_DU2
+};
+lasto_status lasto_net_tensor(lasto_net n, int which, uint16_t* out, long long count, int* dims);
 
 /*
  * Net input features from a source and a potential on grid g (whose finest
@@ -533,11 +606,15 @@ lasto_status lasto_net_train_step(lasto_net n, const uint16_t* x, const float* t
  * are formed: v and v + out_scale * net(features(rho, v)); each gets one
  * red-black sweep of eq. (3.2)'s discrete form (red, then black; faces kept),
  * and the one with the smaller relative residual
- * ||4 pi rho - A v||_W / ||4 pi rho - A v_bc||_W is returned in v.
- *   rel: host [2] or NULL: that residual for the plain and the learned candidate.
- *   accepted: host, may be NULL: 1 if the learned candidate was kept.
+ * ||4 pi rho - A v||_W / ||4 pi rho - A v_bc||_W is returned in v. On a
+ * batched grid every right-hand side is judged on its own (the net runs per
+ * copy; the sweeps and norms of all copies share launches), with the same
+ * bits as a grid holding that copy alone.
+ *   rel: host [2 n_batch] or NULL: per copy, that residual for the plain and
+ *     the learned candidate.
+ *   accepted: host, may be NULL: how many copies kept the learned candidate.
  * Uses the grid's solver scratch (not to be called during a solve on the same grid).
- * Errors: LASTO_ERR_ARG (grid and net sizes differ), LASTO_ERR_HIP.
+ * Errors: LASTO_ERR_ARG (the net's grid differs from one copy of the finest level), LASTO_ERR_HIP.
  */
 lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
                                  int* accepted);
@@ -556,6 +633,21 @@ lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const double* rho, d
  */
 lasto_status lasto_learned_correction(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
                                       int* accepted);
+/*
+ * A training pair of the learned coarse correction for iterate v (one
+ * right-hand side): the restricted residual f_c that a cycle's descent
+ * produces at level c (nu1 red-black pre-smoothing sweeps from zero on each
+ * finer level, the red residual, the restriction), as the net's features
+ * (x: device [nz_c][ny_c][nx_c][8] BF16, as the solve forms them), and the
+ * target e_c / (s out_scale) (target: device FP32 [nz_c][ny_c][nx_c], zero
+ * on faces), e_c the solution of A_c e = f_c by 40 V-cycles of level c.
+ *   r_scale: host out s; dims: host [3] out nx_c, ny_c, nz_c.
+ * Uses the grid's solver vectors (zero again on return).
+ * Errors: LASTO_ERR_ARG (level outside 1 .. levels - 1, a level that does not
+ * fit the net, a zero residual), LASTO_ERR_HIP.
+ */
+lasto_status lasto_coarse_pair(lasto_grid g, lasto_net n, const double* rho, const double* v, int level, int nu1,
+                               uint16_t* x, float* target, double* r_scale, int* dims);
 /* the correction net's features for iterate v (x as for lasto_net_features);
  * *r_scale (host) receives s. Errors: LASTO_ERR_ARG (zero residual), LASTO_ERR_HIP. */
 lasto_status lasto_net_correction_features(lasto_grid g, lasto_net n, const double* rho, const double* v,

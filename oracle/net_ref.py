@@ -189,3 +189,36 @@ def round_bf16(a):
     """Nearest-even BF16 values of a (float64 array)."""
     return torch.as_tensor(np.asarray(a, dtype=np.float64)).to(torch.float32).to(torch.bfloat16).to(
         torch.float64).numpy()
+
+
+# ------------------------------------------------- one stage at a time
+# Each stage of the network on given operands (the values the GPU stored), in
+# float64, so that every kernel is checked on exactly the inputs it read.
+def conv_pre(inp, W, b, stride):
+    """One convolution before its ReLU: inp [C, nz, ny, nx], W [co, ci, 3, 3,
+    3], b [co] (or None) -> [co, ...]; stride 1 or 2, zero padding 1."""
+    out = F.conv3d(torch.as_tensor(inp)[None], torch.as_tensor(W), None if b is None else torch.as_tensor(b),
+                   stride=stride, padding=1)
+    return out[0]
+
+
+def conv_adjoint(gout, W, stride, in_shape):
+    """The adjoint of conv_pre (no bias) with respect to its input: the
+    vector-Jacobian product of the convolution, by autograd."""
+    x = torch.zeros((1,) + tuple(in_shape), dtype=torch.float64, requires_grad=True)
+    out = F.conv3d(x, torch.as_tensor(W), None, stride=stride, padding=1)
+    (g,) = torch.autograd.grad(out, x, torch.as_tensor(gout)[None])
+    return g[0]
+
+
+def upsample_adjoint(fine, coarse_shape):
+    """The adjoint of upsample: [C, nz, ny, nx] -> [C, cz, cy, cx]."""
+    c = torch.zeros((fine.shape[0],) + tuple(coarse_shape), dtype=torch.float64, requires_grad=True)
+    out = upsample(c, tuple(fine.shape[1:]))
+    (g,) = torch.autograd.grad(out, c, torch.as_tensor(fine))
+    return g
+
+
+def head(u0, hw, hb):
+    """y = w . u0 + b per node: u0 [c0, nz, ny, nx]."""
+    return torch.einsum("c,czyx->zyx", torch.as_tensor(hw), torch.as_tensor(u0)) + hb

@@ -172,8 +172,8 @@ extern "C" lasto_status lasto_mesh_graded_1d(double lo, double hi, int n, const 
 // Validate an atom table, copy it to the grid's staging buffer and derive the
 // per-atom constants on the device (k_atom_prep). The staging buffer is reused
 // by the next call, so callers finish their kernels before returning.
-static lasto_status stage_atoms(lasto_grid g, int n_atoms, const lasto_atom* atoms, int renormalize, const char* who,
-                                AtomDev** out)
+lasto_status lasto::stage_atoms(lasto_grid g, int n_atoms, const lasto_atom* atoms, int renormalize, const char* who,
+                         AtomDev** out)
 {
     std::vector<AtomDev> hv((size_t)std::max(n_atoms, 1));
     const std::string w(who);

@@ -313,6 +313,8 @@ static void free_grid(lasto_grid g)
     }
     if (g->h_scalars) (void)hipHostFree(g->h_scalars);
     for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : g->ph_ev)
+        if (e) (void)hipEventDestroy(e);
     g->prof_ev.clear();
 }
 

@@ -18,7 +18,7 @@ constexpr int kCoarseMax = 5;         // coarsening stops when every axis has <=
 constexpr double kCoarsenTheta = 4.0; // merge cell pairs up to theta * (smallest spacing)
 constexpr int kReduceBlocks = 1024;   // fixed partial count of every reduction (determinism)
 constexpr int kMaxBatch = 16;          // right-hand sides of one batched grid
-constexpr int kNumScalars = 32 + 2 * kMaxBatch;
+constexpr int kNumScalars = 32 + 3 * kMaxBatch;
 
 // scalar slots of the device scalar array
 enum Scalar {
@@ -27,9 +27,16 @@ enum Scalar {
     S_RR = 3,               // <r, r>_W after the update
     S_R0 = 4,               // reference ||b - A v_bc||_W^2
     S_TMP = 5,
+    S_BAD = 6,              // nonzero once an FP32 correction held a non-finite value (not added to v)
     S_RZ32_0 = 8, S_RZ32_1 = 9, S_PQ32 = 10,   // inner FP32 PCG
+    S_LC_R = 12, S_LC_E = 13,  // learned coarse correction: ||f_c||_W^2 and ||f_c - A_c e||_W^2
+    S_LC_ACC = 14,          // learned coarse corrections accepted in this solve
+    S_LC_SCALE = 15,        // (spare)
+    S_ZQ = 16, S_FNUM = 17,     // flexible CG: <z_new, q_old>_W and its beta numerator (FP64)
+    S_ZQ32 = 18, S_FNUM32 = 19, // the same in the inner FP32 PCG
     S_BR0 = 32,                        // per right-hand side: reference norm^2 [kMaxBatch]
     S_BRR = 32 + kMaxBatch,            // per right-hand side: residual norm^2 [kMaxBatch]
+    S_BJ = 32 + 2 * kMaxBatch,         // per right-hand side: a second residual norm^2 [kMaxBatch]
 };
 
 void set_error(const std::string& msg);
@@ -282,6 +289,14 @@ struct lasto_grid_s {
     int prof_used = 0;
     double prof_bytes = 0.0;
     int prof_fp32 = 0;
+    // algorithmic bytes of the current solve's finest-level launches
+    double alg_bytes = 0.0;
+    // phase stamps of a solve (start, faces done, guess done, end)
+    hipEvent_t ph_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // the current solve's learned coarse correction (lc_net NULL: none)
+    lasto_net lc_net = nullptr;
+    int lc_level = -1;
+    int lc_applied = 0;
 };
 
 namespace lasto {
@@ -376,9 +391,10 @@ hipError_t launch_add_nat(const LevelView& L, double* v, const double* e_split, 
 // r32 = bscale rho - A v in FP32 (split), partials of ||r||_W^2 (FP64)
 hipError_t launch_residual_nat32(const LevelView& L, const double* v, const double* rho, double bscale, float* r32,
                                  double* partials, hipStream_t s);
-// v (natural) += e32 (+ alpha p32 when p32 is given, alpha = scal[i_num]/scal[i_den])
-hipError_t launch_add32_nat(const LevelView& L, double* v, const float* e32, const float* p32, const double* scal,
-                            int i_num, int i_den, hipStream_t s);
+// v (natural) += e32 (+ alpha p32 when p32 is given, alpha = scal[i_num]/scal[i_den]); a node
+// whose new value would not be finite keeps its value and sets scal[S_BAD] (bad = true)
+hipError_t launch_add32_nat(const LevelView& L, double* v, const float* e32, const float* p32, double* scal,
+                            int i_num, int i_den, hipStream_t s, bool flag_bad = false);
 hipError_t launch_nat_to_split(const LevelView& L, const double* a, double* s_out, hipStream_t s);
 hipError_t launch_split_to_nat(const LevelView& L, const double* s_in, double* a, hipStream_t s);
 template <typename T>
@@ -412,6 +428,9 @@ hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const 
 hipError_t launch_moments(lasto_grid g, const double* rho, double* Q);
 hipError_t launch_bc(lasto_grid g, int mode, const double* Q, int lmax_bc, double* v);
 hipError_t launch_guess(lasto_grid g, const AtomDev* atoms, int n_atoms, double* v);
+// validate an atom table, copy it to the grid's staging buffer and prepare it on the device
+lasto_status stage_atoms(lasto_grid g, int n_atoms, const lasto_atom* atoms, int renormalize, const char* who,
+                         AtomDev** out);
 // v (natural, interior) += s * y (FP32, natural)
 hipError_t launch_add_f32_nat(const LevelView& L, double* v, const float* y, double s, hipStream_t st);
 // learned guess: features of (rho, v) and the net's forward pass on the grid's
@@ -420,6 +439,18 @@ lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, con
                                double* out_scale, double rho_mul = 1.0);
 lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x,
                                 double rho_mul);
+// learned coarse correction at level l of a cycle: u = the net's proposal for
+// A_l u = f if it lowers the residual, else 0 (r: the level's residual scratch,
+// zero again on return); g->lc_net must be set
+template <typename T>
+lasto_status learned_coarse_start(lasto_grid g, int l, const T* f, T* u, T* r);
+// `cycles` FP64 V-cycles of level c on A_c u = f from zero (no learned correction)
+lasto_status coarse_cycles(lasto_grid g, int c, int cycles, const double* f, double* u);
+// the node grid a net was created for (its largest), out[3] = nx, ny, nz
+lasto_status net_capacity(lasto_net n, int* out);
+lasto_status coarse_pair(lasto_grid g, lasto_net n, const double* rho, const double* v, int c, int nu1, int cycles,
+                         uint16_t* x, float* t, double* r_scale);
+hipError_t launch_flex_beta(double* scal, int i_rz_old, int i_pq, int i_zq, int i_out, hipStream_t s);
 hipError_t launch_interp(lasto_grid g, const double* v, const double* pts, int npts, double* out);
 
 // inside the spheres: one entry per atom (device table of a lasto_spheres)

@@ -309,6 +309,12 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
         if (!(t < nb && j <= L.ny - 2 && m0 <= (nx - 2) / 2)) continue;
         const int k0 = 1 + (t / (nbx * nby)) * kc;
         const int k1 = min(k0 + kc, nz - 1);
+        // Mirrored march: even plane chunks walk up (D = 1), odd ones down, so
+        // the plane two neighbouring chunks both read (the halo of one, the
+        // last or first plane of the other) is read by both at the same time,
+        // at the start or at the end of both marches, and the second read
+        // finds it in the L2.
+        const int D = ((t / (nbx * nby)) & 1) ? -1 : 1;
         const size_t row = (size_t)j * W + m0;
         // both parities' x coefficients, picked per plane by select (named
         // values, not an array indexed at run time, so they stay in registers)
@@ -340,13 +346,15 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
             if (NEED_U) z = *(const VT*)(uo + (size_t)k * plane + row);
             return z;
         };
-        // plane k from its operands and the z neighbours (zm, zc, zp)
-        auto compute = [&](int k, const HalfOps<T>& q, const VT& zm, const VT& zc, const VT& zp) {
+        // plane k from its operands and the z neighbours: zb behind the
+        // march (plane k - D), zc, za ahead of it (plane k + D)
+        auto compute = [&](int k, const HalfOps<T>& q, const VT& zb, const VT& zc, const VT& za) {
             const int o = (c + j + k) & 1;
             const int i0 = o + 2 * m0;
             const bool okz = L.zint[k];   // planes next to another copy of a batch are faces
             const VT cxm = o ? axm1 : axm0, cxp = o ? axp1 : axp0;
             const T czm = amz[k], czp = apz[k];
+            const T czb = D > 0 ? czm : czp, cza = D > 0 ? czp : czm;
             VT r;
             bool ok[VEC];
 #pragma unroll
@@ -361,7 +369,7 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                     if (NEED_U) {
                         sum = cxm[e] * xl + cxp[e] * xr;
                         sum += cym * q.ym[e] + cyp * q.yp[e];
-                        sum += czm * zm[e] + czp * zp[e];
+                        sum += czb * zb[e] + cza * za[e];
                     }
                     r[e] = (sum - bscale * q.fv[e]) * recip(d);
                 } else {
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                     const T c0 = q.cv[e];
                     T a = cxm[e] * (xl - c0) + cxp[e] * (xr - c0);
                     a += cym * (q.ym[e] - c0) + cyp * (q.yp[e] - c0);
-                    a += czm * (zm[e] - c0) + czp * (zp[e] - c0);
+                    a += czb * (zb[e] - c0) + cza * (za[e] - c0);
                     r[e] = MODE == HM_RESID ? bscale * q.fv[e] - a : a;
                 }
             }
@@ -396,20 +404,29 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                 }
             }
         };
-        // two planes per step with alternating operand sets (A: even steps,
+        // Two planes per step with alternating operand sets (A: even steps,
         // B: odd), so the next plane's loads are in flight while one plane is
-        // computed and no register copies wait on them
+        // computed and no register copies wait on them. Mirrored march: even
+        // plane chunks walk up, odd ones down, so the plane two neighbouring
+        // chunks both read (the halo of one, the last or first plane of the
+        // other) is read by both at the same time, at the start or at the end
+        // of both marches, and the second read finds it in the L2.
+        const int ks = D > 0 ? k0 : k1 - 1;
+        // a plane inside the chunk (loads past its end are not used)
+        auto inchunk = [&](int k) { return min(max(k, k0), k1 - 1); };
+        auto clampz = [&](int k) { return min(max(k, 0), nz - 1); };
         HalfOps<T> A{}, B{};
-        VT z0 = load_z(k0 - 1), z1 = load_z(k0), z2 = load_z(k0 + 1);
-        load_plane(k0, A);
-        for (int k = k0; k < k1; k += 2) {
-            load_plane(min(k + 1, k1 - 1), B);
-            const VT z3 = load_z(min(k + 2, nz - 1));
+        // queue: z0 = plane k - D, z1 = plane k, z2 = plane k + D
+        VT z0 = load_z(ks - D), z1 = load_z(ks), z2 = load_z(ks + D);
+        load_plane(ks, A);
+        for (int k = ks; D > 0 ? k < k1 : k >= k0; k += 2 * D) {
+            load_plane(inchunk(k + D), B);
+            const VT z3 = load_z(clampz(k + 2 * D));
             compute(k, A, z0, z1, z2);
-            if (k + 1 < k1) {
-                load_plane(min(k + 2, k1 - 1), A);
-                const VT z4 = load_z(min(k + 3, nz - 1));
-                compute(k + 1, B, z1, z2, z3);
+            if (D > 0 ? k + 1 < k1 : k - 1 >= k0) {
+                load_plane(inchunk(k + 2 * D), A);
+                const VT z4 = load_z(clampz(k + 3 * D));
+                compute(k + D, B, z1, z2, z3);
                 z0 = z2;
                 z1 = z3;
                 z2 = z4;
@@ -1088,9 +1105,10 @@ hipError_t launch_add_f32_nat(const LevelView& L, double* v, const float* y, dou
 // v (natural) += e (FP32, split) and, with p given, + alpha p, alpha =
 // scal[i_num]/scal[i_den] (the last step of an inner PCG folded into v; a
 // non-finite alpha adds e alone), interior
+template <bool FLAG>
 __global__ __launch_bounds__(PT_NT) void k_add32_nat(LevelView L, int kp, double* __restrict__ v,
                                                      const float* __restrict__ e, const float* __restrict__ p,
-                                                     const double* __restrict__ scal, int i_num, int i_den)
+                                                     double* __restrict__ scal, int i_num, int i_den)
 {
     float alpha = 0.0f;
     if (p) {
@@ -1102,14 +1120,24 @@ __global__ __launch_bounds__(PT_NT) void k_add32_nat(LevelView L, int kp, double
         if (!inside || !L.zint[k]) continue;
         const size_t at = sidx(L, i, j, k);
         const float d = p ? e[at] + alpha * p[at] : e[at];
-        v[((size_t)k * L.ny + j) * L.nx + i] += (double)d;
+        double& vv = v[((size_t)k * L.ny + j) * L.nx + i];
+        if (FLAG) {
+            // a broken-down FP32 correction never reaches v: the node keeps
+            // its value and the solve is told (every writer stores the same 1)
+            const double nv = vv + (double)d;
+            if (isfinite(nv)) vv = nv;
+            else scal[S_BAD] = 1.0;
+        } else {
+            vv += (double)d;
+        }
     }
 }
 
-hipError_t launch_add32_nat(const LevelView& L, double* v, const float* e32, const float* p32, const double* scal,
-                            int i_num, int i_den, hipStream_t s)
+hipError_t launch_add32_nat(const LevelView& L, double* v, const float* e32, const float* p32, double* scal,
+                            int i_num, int i_den, hipStream_t s, bool flag_bad)
 {
-    PT_LAUNCH(k_add32_nat, L, s, v, e32, p32, scal, i_num, i_den);
+    if (flag_bad) PT_LAUNCH(k_add32_nat<true>, L, s, v, e32, p32, scal, i_num, i_den);
+    else PT_LAUNCH(k_add32_nat<false>, L, s, v, e32, p32, scal, i_num, i_den);
     return hipGetLastError();
 }
 
@@ -1921,5 +1949,28 @@ INST(double)
 INST(float)
 #undef INST
 template hipError_t launch_fill_zero<unsigned char>(unsigned char*, size_t, hipStream_t);
+
+}  // namespace lasto
+
+namespace lasto {
+
+// Flexible (Polak-Ribiere) CG with a preconditioner that changes from step
+// to step: beta = <z_new, r_new - r_old> / <z_old, r_old>, where
+// r_new - r_old = -alpha_old q_old, so its numerator is
+// -alpha_old <z_new, q_old>, alpha_old = <z_old, r_old> / <p_old, q_old> (with
+// a fixed symmetric preconditioner <z_new, r_old> = 0 and this is <z_new, r_new>).
+__global__ void k_flex_beta(double* scal, int i_rz_old, int i_pq, int i_zq, int i_out)
+{
+    if (threadIdx.x == 0) {
+        const double alpha = scal[i_rz_old] / scal[i_pq];
+        scal[i_out] = -alpha * scal[i_zq];
+    }
+}
+
+hipError_t launch_flex_beta(double* scal, int i_rz_old, int i_pq, int i_zq, int i_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flex_beta, dim3(1), dim3(64), 0, s, scal, i_rz_old, i_pq, i_zq, i_out);
+    return hipGetLastError();
+}
 
 }  // namespace lasto

@@ -18,6 +18,7 @@
 // W[27][cin][cout] then b[cout]; then the head w[c0], b); Adam updates them and
 // re-packs the BF16 copies the matrix-core kernels read.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -105,6 +106,20 @@ lasto_status nalloc(lasto_net n, T** p, size_t count)
     return LASTO_OK;
 }
 
+// the node grid the net runs on (at most its creation size per axis, for
+// which every buffer is allocated): level l + 1 has (n + 1) / 2 nodes per axis
+void set_dims(lasto_net n, int nx, int ny, int nz)
+{
+    int nn[3] = {nx, ny, nz};
+    for (int l = 0; l < 4; ++l) {
+        for (int d = 0; d < 3; ++d) {
+            n->dim[l][d] = nn[d];
+            nn[d] = (nn[d] + 1) / 2;
+        }
+        n->nvox[l] = (long)n->dim[l][0] * n->dim[l][1] * n->dim[l][2];
+    }
+}
+
 ConvGeom fwd_geom(const lasto_net_s* n, const Layer& L)
 {
     ConvGeom g;
@@ -186,15 +201,8 @@ extern "C" lasto_status lasto_net_create(const lasto_net_config* cfg, void* hip_
     lasto_net n = new lasto_net_s();
     n->cfg = *cfg;
     n->stream = (hipStream_t)hip_stream;
-    int nn[3] = {cfg->nx, cfg->ny, cfg->nz};
-    for (int l = 0; l < 4; ++l) {
-        for (int d = 0; d < 3; ++d) {
-            n->dim[l][d] = nn[d];
-            nn[d] = (nn[d] + 1) / 2;
-        }
-        n->nvox[l] = (long)n->dim[l][0] * n->dim[l][1] * n->dim[l][2];
-        n->c[l] = cfg->ch[l];
-    }
+    set_dims(n, cfg->nx, cfg->ny, cfg->nz);
+    for (int l = 0; l < 4; ++l) n->c[l] = cfg->ch[l];
     const int* c = n->c;
     // (cin, cout, mode, lin, lout)
     const int spec[8][5] = {{kInFeatures, c[0], CONV_SAME, 0, 0}, {c[0], c[1], CONV_DOWN, 0, 1},
@@ -390,7 +398,7 @@ __global__ __launch_bounds__(128) void k_features(LevelView L, const double* __r
 lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x,
                                 double rho_mul)
 {
-    const LevelView& L = g->lev[0].view;
+    const LevelView& L = g->cview;   // one right-hand side of a batch
     if (L.nx != n->dim[0][0] || L.ny != n->dim[0][1] || L.nz != n->dim[0][2])
         return fail(LASTO_ERR_ARG, "lasto_net: the net's grid does not match the grid's finest level");
     hipLaunchKernelGGL(k_features, dim3((L.nx + 127) / 128, L.ny, L.nz), dim3(128), 0, g->stream, L, rho, v,
@@ -405,7 +413,8 @@ lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, con
                                double* out_scale, double rho_mul)
 {
     if (!n->xin) {
-        if (lasto_status st = nalloc(n, &n->xin, (size_t)n->nvox[0] * kInFeatures); st != LASTO_OK) return st;
+        const size_t cap = (size_t)n->cfg.nx * n->cfg.ny * n->cfg.nz;
+        if (lasto_status st = nalloc(n, &n->xin, cap * kInFeatures); st != LASTO_OK) return st;
     }
     NCHK(hipStreamSynchronize(n->stream));
     if (lasto_status st = net_features_async(g, n, rho, v, n->xin, rho_mul); st != LASTO_OK) return st;
@@ -536,4 +545,400 @@ extern "C" lasto_status lasto_net_train_step(lasto_net n, const uint16_t* x, con
     st = lasto_net_backward(n, x, target, weight, loss);
     if (st != LASTO_OK) return st;
     return lasto_net_adam_step(n, lr);
+}
+
+// ------------------------------------------------------------ checkpoints
+// File layout (little-endian): "LASTONET" | u32 version (1) | i32 ch[4] |
+// u64 seed | f64 rho_scale, pot_scale, h_ref, out_scale | i32 nx, ny, nz |
+// i64 step | u64 nparam | f32 w[nparam] | f32 m[nparam] | f32 v[nparam].
+// The masters w and Adam's moments m, v and step count are all the state a
+// training step reads besides its data, so a net loaded from a checkpoint
+// continues training with the same bits as the net that wrote it.
+namespace {
+
+constexpr char kNetMagic[8] = {'L', 'A', 'S', 'T', 'O', 'N', 'E', 'T'};
+constexpr uint32_t kNetVersion = 1;
+
+struct NetFileHead {
+    char magic[8];
+    uint32_t version;
+    int32_t ch[4];
+    uint64_t seed;
+    double rho_scale, pot_scale, h_ref, out_scale;
+    int32_t nx, ny, nz;
+    int64_t step;
+    uint64_t nparam;
+};
+
+struct FileCloser {
+    FILE* f;
+    ~FileCloser()
+    {
+        if (f) fclose(f);
+    }
+};
+
+}  // namespace
+
+extern "C" lasto_status lasto_net_save(lasto_net n, const char* path)
+{
+    if (!n || !path) return net_fail(LASTO_ERR_ARG, "lasto_net_save: NULL argument");
+    NCHK(hipStreamSynchronize(n->stream));
+    NetFileHead h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, kNetMagic, 8);
+    h.version = kNetVersion;
+    for (int l = 0; l < 4; ++l) h.ch[l] = n->cfg.ch[l];
+    h.seed = n->cfg.seed;
+    h.rho_scale = n->cfg.rho_scale;
+    h.pot_scale = n->cfg.pot_scale;
+    h.h_ref = n->cfg.h_ref;
+    h.out_scale = n->cfg.out_scale;
+    h.nx = n->cfg.nx;
+    h.ny = n->cfg.ny;
+    h.nz = n->cfg.nz;
+    h.step = n->step;
+    h.nparam = n->nparam;
+    std::vector<float> buf(3 * n->nparam);
+    NCHK(hipMemcpy(buf.data(), n->w, sizeof(float) * n->nparam, hipMemcpyDeviceToHost));
+    NCHK(hipMemcpy(buf.data() + n->nparam, n->m, sizeof(float) * n->nparam, hipMemcpyDeviceToHost));
+    NCHK(hipMemcpy(buf.data() + 2 * n->nparam, n->v, sizeof(float) * n->nparam, hipMemcpyDeviceToHost));
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        FileCloser fc{fopen(tmp.c_str(), "wb")};
+        if (!fc.f) return net_fail(LASTO_ERR_ARG, "lasto_net_save: cannot open " + tmp);
+        if (fwrite(&h, sizeof(h), 1, fc.f) != 1 || fwrite(buf.data(), sizeof(float), buf.size(), fc.f) != buf.size())
+            return net_fail(LASTO_ERR_STATE, "lasto_net_save: write failed");
+        if (fclose(fc.f) != 0) {
+            fc.f = nullptr;
+            return net_fail(LASTO_ERR_STATE, "lasto_net_save: write failed");
+        }
+        fc.f = nullptr;
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return net_fail(LASTO_ERR_STATE, "lasto_net_save: rename failed");
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_load(lasto_net n, const char* path)
+{
+    if (!n || !path) return net_fail(LASTO_ERR_ARG, "lasto_net_load: NULL argument");
+    FileCloser fc{fopen(path, "rb")};
+    if (!fc.f) return net_fail(LASTO_ERR_ARG, std::string("lasto_net_load: cannot open ") + path);
+    NetFileHead h;
+    if (fread(&h, sizeof(h), 1, fc.f) != 1 || std::memcmp(h.magic, kNetMagic, 8) != 0 || h.version != kNetVersion)
+        return net_fail(LASTO_ERR_ARG, "lasto_net_load: not a net checkpoint of this version");
+    for (int l = 0; l < 4; ++l)
+        if (h.ch[l] != n->cfg.ch[l]) return net_fail(LASTO_ERR_ARG, "lasto_net_load: channel counts differ");
+    if (h.nparam != n->nparam) return net_fail(LASTO_ERR_ARG, "lasto_net_load: parameter count differs");
+    if (!(h.rho_scale > 0.0) || !(h.pot_scale > 0.0) || !(h.h_ref > 0.0) || !(h.out_scale > 0.0) || h.step < 0)
+        return net_fail(LASTO_ERR_ARG, "lasto_net_load: corrupt header");
+    std::vector<float> buf(3 * n->nparam);
+    if (fread(buf.data(), sizeof(float), buf.size(), fc.f) != buf.size())
+        return net_fail(LASTO_ERR_ARG, "lasto_net_load: truncated file");
+    char extra;
+    if (fread(&extra, 1, 1, fc.f) != 0) return net_fail(LASTO_ERR_ARG, "lasto_net_load: trailing bytes");
+    NCHK(hipStreamSynchronize(n->stream));
+    NCHK(hipMemcpy(n->w, buf.data(), sizeof(float) * n->nparam, hipMemcpyHostToDevice));
+    NCHK(hipMemcpy(n->m, buf.data() + n->nparam, sizeof(float) * n->nparam, hipMemcpyHostToDevice));
+    NCHK(hipMemcpy(n->v, buf.data() + 2 * n->nparam, sizeof(float) * n->nparam, hipMemcpyHostToDevice));
+    // the grid size the net runs on is the caller's; the weights, moments,
+    // step, seed and feature scales are the checkpoint's
+    n->cfg.seed = h.seed;
+    n->cfg.rho_scale = h.rho_scale;
+    n->cfg.pot_scale = h.pot_scale;
+    n->cfg.h_ref = h.h_ref;
+    n->cfg.out_scale = h.out_scale;
+    n->step = (int)h.step;
+    if (lasto_status e = pack_all(n); e != LASTO_OK) return e;
+    NCHK(hipStreamSynchronize(n->stream));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_get_config(lasto_net n, lasto_net_config* cfg, long long* step)
+{
+    if (!n || !cfg) return net_fail(LASTO_ERR_ARG, "lasto_net_get_config: NULL argument");
+    *cfg = n->cfg;
+    if (step) *step = n->step;
+    return LASTO_OK;
+}
+
+// ------------------------------------------------------------ test access
+// The stored BF16 tensors of the last forward (with activations kept) and
+// backward pass, for checking each kernel on exactly the operands it read.
+extern "C" lasto_status lasto_net_tensor(lasto_net n, int which, uint16_t* out, long long count, int* dims)
+{
+    if (!n || !dims) return net_fail(LASTO_ERR_ARG, "lasto_net_tensor: NULL argument");
+    const uint16_t* src = nullptr;
+    int level = 0, ch = 0;
+    if (which >= LASTO_NET_E0 && which <= LASTO_NET_E3) {
+        level = which - LASTO_NET_E0;
+        ch = n->c[level];
+        src = n->e[level];
+    } else if (which == LASTO_NET_M3) {
+        level = 3;
+        ch = n->c[3];
+        src = n->m3;
+    } else if (which >= LASTO_NET_D2 && which <= LASTO_NET_D0) {
+        const int l = 2 - (which - LASTO_NET_D2);   // d_l lives on level l + 1 with ch[l] channels
+        level = l + 1;
+        ch = n->c[l];
+        src = n->d[l];
+    } else if (which >= LASTO_NET_U2 && which <= LASTO_NET_U0) {
+        const int l = 2 - (which - LASTO_NET_U2);
+        level = l;
+        ch = n->c[l];
+        src = n->u[l];
+    } else if (which >= LASTO_NET_G0 && which <= LASTO_NET_G7) {
+        const Layer& L = n->layers[which - LASTO_NET_G0];
+        level = L.lout;
+        ch = L.cout;
+        src = n->gg[which - LASTO_NET_G0];
+    } else if (which >= LASTO_NET_DU0 && which <= LASTO_NET_DU2) {
+        level = which - LASTO_NET_DU0;
+        ch = n->c[level];
+        src = n->du[level];
+    } else {
+        return net_fail(LASTO_ERR_ARG, "lasto_net_tensor: unknown tensor");
+    }
+    dims[0] = n->dim[level][0];
+    dims[1] = n->dim[level][1];
+    dims[2] = n->dim[level][2];
+    dims[3] = ch;
+    const long long size = (long long)n->nvox[level] * ch;
+    if (!out) return LASTO_OK;   // dims only
+    if (count != size) return net_fail(LASTO_ERR_ARG, "lasto_net_tensor: count != the tensor's size");
+    NCHK(hipMemcpyAsync(out, src, sizeof(uint16_t) * size, hipMemcpyDeviceToDevice, n->stream));
+    NCHK(hipStreamSynchronize(n->stream));
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_net_set_grid(lasto_net n, int nx, int ny, int nz)
+{
+    if (!n) return net_fail(LASTO_ERR_ARG, "lasto_net_set_grid: NULL net");
+    if (nx < 8 || ny < 8 || nz < 8 || nx > n->cfg.nx || ny > n->cfg.ny || nz > n->cfg.nz)
+        return net_fail(LASTO_ERR_ARG, "lasto_net_set_grid: each axis must be 8 .. the net's creation size");
+    NCHK(hipStreamSynchronize(n->stream));
+    set_dims(n, nx, ny, nz);
+    n->fwd_done = false;
+    return LASTO_OK;
+}
+
+// -------------------------------------------- learned coarse correction
+// Inside a V-cycle, at one coarse level c: the net reads the restricted
+// residual f_c (scaled to unit RMS s = ||f_c||_W / sqrt(sum vol)) and the
+// level's spacings, and proposes the correction e^ = s out_scale net(f_c / s)
+// of A_c e = f_c. It becomes the start of the level's own cycle only if it
+// lowers the residual, ||f_c - A_c e^||_W < ||f_c||_W (the residual of the
+// zero start); otherwise the cycle starts from zero as without the net. The
+// test runs on the device (no host read inside the cycle).
+namespace lasto {
+
+template <typename T>
+__global__ __launch_bounds__(128) void k_lc_features(LevelView L, const T* __restrict__ f,
+                                                     const double* __restrict__ scal, double inv_vol, double rho_scale,
+                                                     float h_ref, uint16_t* __restrict__ x)
+{
+    const int i = blockIdx.x * 128 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i >= L.nx) return;
+    const double sr = sqrt(scal[S_LC_R] * inv_vol);
+    const double mul = sr > 0.0 ? rho_scale / sr : 0.0;
+    const size_t e = ((size_t)k * L.ny + j) * L.nx + i;
+    const bool face = i == 0 || j == 0 || k == 0 || i == L.nx - 1 || j == L.ny - 1 || k == L.nz - 1;
+    const double fv = face ? 0.0 : (double)f[sidx(L, i, j, k)];
+    const float inv = 1.0f / h_ref;
+    uint4 o;
+    o.x = (uint32_t)f2bf((float)(fv * mul)) | ((uint32_t)f2bf(logf((float)L.ax[0].m[i] * inv)) << 16);
+    o.y = (uint32_t)f2bf(logf((float)L.ax[1].m[j] * inv)) | ((uint32_t)f2bf(logf((float)L.ax[2].m[k] * inv)) << 16);
+    o.z = (uint32_t)f2bf(face ? 1.0f : 0.0f) << 16;
+    o.w = 0;
+    *(uint4*)(x + e * 8) = o;
+}
+
+// u = s out_scale y at interior nodes, zero on faces (split layout)
+template <typename T>
+__global__ __launch_bounds__(128) void k_lc_candidate(LevelView L, const float* __restrict__ y,
+                                                      const double* __restrict__ scal, double inv_vol,
+                                                      double out_scale, T* __restrict__ u)
+{
+    const int i = blockIdx.x * 128 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i >= L.nx) return;
+    const bool face = i == 0 || j == 0 || k == 0 || i == L.nx - 1 || j == L.ny - 1 || k == L.nz - 1;
+    const double sr = sqrt(scal[S_LC_R] * inv_vol);
+    const double val = face ? 0.0 : sr * out_scale * (double)y[((size_t)k * L.ny + j) * L.nx + i];
+    u[sidx(L, i, j, k)] = (T)val;
+}
+
+// keep u if ||f - A u||_W < ||f||_W, else zero it; count acceptances
+template <typename T>
+__global__ __launch_bounds__(256) void k_lc_select(T* __restrict__ u, size_t n, double* __restrict__ scal)
+{
+    const double r = scal[S_LC_R], e = scal[S_LC_E];
+    const bool keep = e < r;   // false for NaN
+    if (blockIdx.x == 0 && threadIdx.x == 0 && keep) scal[S_LC_ACC] += 1.0;
+    if (keep) return;
+    for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (size_t)gridDim.x * 256) u[t] = T(0);
+}
+
+// sum of the dual volumes over the interior of a level
+static double interior_volume(const Level& L)
+{
+    double v = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        const std::vector<double>& x = L.hx[d];
+        v *= 0.5 * (x[x.size() - 1] + x[x.size() - 2]) - 0.5 * (x[0] + x[1]);
+    }
+    return v;
+}
+
+lasto_status net_capacity(lasto_net n, int* out)
+{
+    if (!n) return fail(LASTO_ERR_ARG, "lasto_net: NULL net");
+    out[0] = n->cfg.nx;
+    out[1] = n->cfg.ny;
+    out[2] = n->cfg.nz;
+    return LASTO_OK;
+}
+
+template <typename T>
+lasto_status learned_coarse_start(lasto_grid g, int l, const T* f, T* u, T* r)
+{
+    lasto_net n = g->lc_net;
+    Level& Lv = g->lev[l];
+    const LevelView& V = Lv.view;
+    hipStream_t s = g->stream;
+    const double inv_vol = 1.0 / interior_volume(Lv);
+    // ||f||_W^2
+    NCHK(launch_dot<T>(V, f, f, g->partials, s));
+    NCHK(launch_reduce(g->partials, 1, row_blocks(V), g->scalars + S_LC_R, s));
+    if (!n->xin) {
+        const size_t cap = (size_t)n->cfg.nx * n->cfg.ny * n->cfg.nz;
+        if (lasto_status st = nalloc(n, &n->xin, cap * kInFeatures); st != LASTO_OK) return st;
+    }
+    set_dims(n, V.nx, V.ny, V.nz);
+    const dim3 grid3((V.nx + 127) / 128, V.ny, V.nz);
+    hipLaunchKernelGGL(k_lc_features<T>, grid3, dim3(128), 0, s, V, f, (const double*)g->scalars, inv_vol,
+                       n->cfg.rho_scale, (float)n->cfg.h_ref, n->xin);
+    NCHK(hipGetLastError());
+    hipStream_t keep = n->stream;
+    n->stream = s;
+    lasto_status st = net_forward_async(n, n->xin, n->y, false);
+    n->stream = keep;
+    if (st != LASTO_OK) return st;
+    hipLaunchKernelGGL(k_lc_candidate<T>, grid3, dim3(128), 0, s, V, (const float*)n->y, (const double*)g->scalars,
+                       inv_vol, n->cfg.out_scale, u);
+    NCHK(hipGetLastError());
+    // ||f - A e^||_W^2 (r is the level's residual scratch: zero again afterwards)
+    NCHK(launch_residual_colour<T>(V, u, f, r, 0, s));
+    NCHK(launch_residual_colour<T>(V, u, f, r, 1, s));
+    NCHK(launch_dot<T>(V, r, r, g->partials, s));
+    NCHK(launch_reduce(g->partials, 1, row_blocks(V), g->scalars + S_LC_E, s));
+    NCHK(launch_fill_zero<T>(r, split_elems(V), s));
+    const size_t ne = split_elems(V);
+    const unsigned nbk = (unsigned)std::min<size_t>((ne + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_lc_select<T>, dim3(nbk), dim3(256), 0, s, u, ne, g->scalars);
+    NCHK(hipGetLastError());
+    g->lc_applied++;
+    return LASTO_OK;
+}
+
+template lasto_status learned_coarse_start<float>(lasto_grid, int, const float*, float*, float*);
+template lasto_status learned_coarse_start<double>(lasto_grid, int, const double*, double*, double*);
+
+// natural FP32 copy of a split FP64 level array (faces included)
+__global__ __launch_bounds__(128) void k_split_to_f32_nat(LevelView L, const double* __restrict__ a, float* __restrict__ t)
+{
+    const int i = blockIdx.x * 128 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i >= L.nx) return;
+    t[((size_t)k * L.ny + j) * L.nx + i] = (float)a[sidx(L, i, j, k)];
+}
+
+__global__ __launch_bounds__(256) void k_scale_f32(float* __restrict__ t, long n, double mul)
+{
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) t[e] = (float)(t[e] * mul);
+}
+
+static hipError_t launch_split_to_f32_nat(const LevelView& L, const double* a, float* t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_split_to_f32_nat, dim3((L.nx + 127) / 128, L.ny, L.nz), dim3(128), 0, s, L, a, t);
+    return hipGetLastError();
+}
+
+static hipError_t launch_scale_f32(float* t, long n, double mul, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_f32, dim3((unsigned)std::min<long>((n + 255) / 256, 4096)), dim3(256), 0, s, t, n, mul);
+    return hipGetLastError();
+}
+
+// Training pair of the coarse net at level c for iterate v: the restricted
+// residual the cycle's descent produces there (nu1 pre-smoothing sweeps from
+// zero on each finer level, red residual, restriction) and the solution of
+// A_c e = f_c by `cycles` V-cycles of level c (FP64).
+lasto_status coarse_pair(lasto_grid g, lasto_net n, const double* rho, const double* v, int c, int nu1, int cycles,
+                         uint16_t* x, float* t, double* r_scale)
+{
+    hipStream_t s = g->stream;
+    const LevelView& V0 = g->lev[0].view;
+    NCHK(launch_residual_nat(V0, v, rho, 4.0 * kPi, g->r, g->partials, 0, s));
+    const double* f = g->r;
+    for (int l = 0; l < c; ++l) {
+        const LevelView& V = g->lev[l].view;
+        double* u = l == 0 ? g->z : g->lev[l].u64;
+        for (int k = 0; k < nu1; ++k) {
+            NCHK(launch_half<double>(V, u, f, 0, k == 0, 1.0, nullptr, s, nullptr, 0));
+            NCHK(launch_half<double>(V, u, f, 1, 0, 1.0, nullptr, s, nullptr, 0));
+        }
+        NCHK(launch_residual_colour<double>(V, u, f, g->lev[l].r64, 0, s));
+        NCHK(launch_restrict_red<double>(V, g->lev[l + 1].view, g->lev[l].r64, g->lev[l + 1].f64, s));
+        f = g->lev[l + 1].f64;
+    }
+    Level& Lc = g->lev[c];
+    const LevelView& Vc = Lc.view;
+    if (lasto_status e = coarse_cycles(g, c, cycles, Lc.f64, Lc.u64); e != LASTO_OK) return e;
+    NCHK(launch_dot<double>(Vc, Lc.f64, Lc.f64, g->partials, s));
+    NCHK(launch_reduce(g->partials, 1, row_blocks(Vc), g->scalars + S_LC_R, s));
+    const double inv_vol = 1.0 / interior_volume(Lc);
+    set_dims(n, Vc.nx, Vc.ny, Vc.nz);
+    const dim3 grid3((Vc.nx + 127) / 128, Vc.ny, Vc.nz);
+    hipLaunchKernelGGL(k_lc_features<double>, grid3, dim3(128), 0, s, Vc, (const double*)Lc.f64,
+                       (const double*)g->scalars, inv_vol, n->cfg.rho_scale, (float)n->cfg.h_ref, x);
+    NCHK(hipGetLastError());
+    // the target e_c / (s out_scale) in natural layout, zero on faces
+    NCHK(launch_split_to_f32_nat(Vc, Lc.u64, t, s));
+    double sr2 = 0.0;
+    NCHK(hipMemcpyAsync(&sr2, g->scalars + S_LC_R, sizeof(double), hipMemcpyDeviceToHost, s));
+    NCHK(hipStreamSynchronize(s));
+    const double sr = std::sqrt(sr2 * inv_vol);
+    if (!(sr > 0.0) || !std::isfinite(sr)) return fail(LASTO_ERR_ARG, "lasto_coarse_pair: zero residual");
+    NCHK(launch_scale_f32(t, (long)Vc.nx * Vc.ny * Vc.nz, 1.0 / (sr * n->cfg.out_scale), s));
+    // the solver's vectors go back with zero faces and padding (and zero)
+    for (int l = 0; l <= c; ++l) {
+        const LevelView& V = g->lev[l].view;
+        NCHK(launch_fill_zero<double>(l == 0 ? g->z : g->lev[l].u64, split_elems(V), s));
+        NCHK(launch_fill_zero<double>(g->lev[l].r64, split_elems(V), s));
+        if (l > 0) NCHK(launch_fill_zero<double>(g->lev[l].f64, split_elems(V), s));
+    }
+    NCHK(launch_fill_zero<double>(g->r, split_elems(V0), s));
+    NCHK(hipStreamSynchronize(s));
+    *r_scale = sr;
+    return LASTO_OK;
+}
+
+}  // namespace lasto
+
+extern "C" lasto_status lasto_coarse_pair(lasto_grid g, lasto_net n, const double* rho, const double* v, int level,
+                                          int nu1, uint16_t* x, float* target, double* r_scale, int* dims)
+{
+    if (!g || !n || !rho || !v || !x || !target || !r_scale || !dims)
+        return net_fail(LASTO_ERR_ARG, "lasto_coarse_pair: NULL argument");
+    if (g->n_batch != 1) return net_fail(LASTO_ERR_ARG, "lasto_coarse_pair: one right-hand side per grid");
+    if (level < 1 || level >= g->nlev || nu1 < 1 || nu1 > 16)
+        return net_fail(LASTO_ERR_ARG, "lasto_coarse_pair: level must be 1 .. levels - 1, nu1 1 .. 16");
+    const lasto::LevelView& Vc = g->lev[level].view;
+    if (Vc.nx < 8 || Vc.ny < 8 || Vc.nz < 8 || Vc.nx > n->cfg.nx || Vc.ny > n->cfg.ny || Vc.nz > n->cfg.nz)
+        return net_fail(LASTO_ERR_ARG, "lasto_coarse_pair: the level does not fit the net (8 .. its size per axis)");
+    NCHK(hipStreamSynchronize(n->stream));
+    dims[0] = Vc.nx;
+    dims[1] = Vc.ny;
+    dims[2] = Vc.nz;
+    return lasto::coarse_pair(g, n, rho, v, level, nu1, 40, x, target, r_scale);
 }

@@ -35,6 +35,18 @@ template <> struct Buf<float> {
         if (e_ != hipSuccess) return fail(LASTO_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// interior nodes of a level, all copies of a batch
+static double interior_pts(const LevelView& V)
+{
+    return (double)(V.nx - 2) * (V.ny - 2) * (V.nzc - 2) * (V.nz / V.nzc);
+}
+
+// algorithmic bytes of a finest-level launch: `per_node` bytes per interior node
+static void count(lasto_grid g, int l, double per_node)
+{
+    if (l == 0) g->alg_bytes += per_node * interior_pts(g->lev[0].view);
+}
+
 // A half-sweep at level l. With profiling on, each finest-level half-sweep
 // is launched with a pair of events that take the dispatch's own start and
 // end timestamps, so their difference is the kernel's execution time.
@@ -44,6 +56,9 @@ static hipError_t half(lasto_grid g, int l, T* u, const T* f, int colour, int ze
 {
     const LevelView& V = g->lev[l].view;
     const bool timed = g->prof_on && l == 0;
+    // half the interior nodes read f and (unless the other colour is zero)
+    // one other-colour value, and write their own value
+    count(g, l, 0.5 * sizeof(T) * (zero_in ? 2.0 : 3.0));
     if (!timed) return launch_half<T>(V, u, f, colour, zero_in, T(1), dotp, g->stream, nparts, l == 0);
     if ((size_t)(2 * g->prof_used + 2) > g->prof_ev.size()) {
         for (int k = 0; k < 64; ++k) {
@@ -119,6 +134,12 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
         }
         return LASTO_OK;
     }
+    if (g->lc_net && l == g->lc_level) {
+        // the learned coarse correction proposes this level's start (kept
+        // only if it lowers the level's residual, else zero)
+        if (lasto_status e = learned_coarse_start<T>(g, l, f, u, Buf<T>::r(L)); e != LASTO_OK) return e;
+        zero_start = false;
+    }
     for (int k = 0; k < nu1; ++k) {
         HIPCHK(half<T>(g, l, u, f, 0, k == 0 && zero_start, nullptr));
         HIPCHK(half<T>(g, l, u, f, 1, 0, nullptr));
@@ -130,12 +151,19 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     T* r = Buf<T>::r(L);
     HIPCHK(launch_residual_colour<T>(V, u, f, r, 0, s));
     HIPCHK(launch_restrict_red<T>(V, C.view, r, Buf<T>::f(C), s));
+    // red residual: read u (both colours) and f, write r at red nodes;
+    // restriction: read the red residual, write the coarse right-hand side
+    const double cfrac = l == 0 ? interior_pts(C.view) / interior_pts(V) : 0.0;
+    count(g, l, 0.5 * 4 * sizeof(T));
+    count(g, l, (0.5 + cfrac) * sizeof(T));
     lasto_status st = vcycle_level<T>(g, l + 1, nu1, nu2, Buf<T>::f(C), Buf<T>::u(C), nullptr, nullptr);
     if (st != LASTO_OK) return st;
     // a post-smoothing that starts with a black half-sweep recomputes every
     // black value, so only red nodes take the interpolated correction
     if (nu2 > 0) HIPCHK(launch_prolong_red<T>(V, C.view, Buf<T>::u(C), u, s));
     else HIPCHK(launch_prolong_add<T>(V, C.view, Buf<T>::u(C), u, s));
+    // read-modify-write of u at red (or all) nodes plus the coarse correction
+    count(g, l, (nu2 > 0 ? 0.5 : 1.0) * 2 * sizeof(T) + cfrac * sizeof(T));
     int nb1 = 0, nb2 = 0;
     for (int k = 0; k < nu2; ++k) {
         const bool last = (k == nu2 - 1) && dotp;
@@ -169,6 +197,8 @@ static lasto_status apply_dot(lasto_grid g, const T* p, T* q, int* count)
     HIPCHK(launch_apply_colour<T>(V, p, q, 0, g->partials, g->stream, &nb0));
     HIPCHK(launch_apply_colour<T>(V, p, q, 1, g->partials + nb0, g->stream, &nb1));
     *count = nb0 + nb1;
+    // each colour reads p's other colour and centre, writes q
+    lasto::count(g, 0, 3.0 * sizeof(T));
     return LASTO_OK;
 }
 
@@ -191,7 +221,8 @@ static lasto_status mg32_inner(lasto_grid g, const lasto_solve_opts& o, int cycl
         if (st != LASTO_OK) return st;
         ++*vcycles;
     }
-    HIPCHK(launch_add32_nat(g->lev[0].view, v, g->z32, nullptr, g->scalars, 0, 0, g->stream));
+    HIPCHK(launch_add32_nat(g->lev[0].view, v, g->z32, nullptr, g->scalars, 0, 0, g->stream, true));
+    count(g, 0, 4.0 + 16.0);
     return LASTO_OK;
 }
 
@@ -216,21 +247,37 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
         float* po = g->p32[(it + 1) & 1];
         if (it == 0) {
             HIPCHK(launch_update_p<float>(V, g->z32, po, pn, g->scalars, srz, srz_old, 1, s));
+            count(g, 0, 2 * 4.0);
         } else {
+            int beta_num = srz;
+            if (g->lc_net) {
+                // flexible (Polak-Ribiere) beta under the learned coarse correction
+                HIPCHK(launch_dot<float>(V, g->z32, g->q32, g->partials, s));
+                if (lasto_status e = reduce_to(g, row_blocks(V), S_ZQ32); e != LASTO_OK) return e;
+                HIPCHK(launch_flex_beta(g->scalars, srz_old, S_PQ32, S_ZQ32, S_FNUM32, s));
+                count(g, 0, 8.0);
+                beta_num = S_FNUM32;
+            }
             // e (=, then +=) alpha_prev p_old, alpha_prev = (r,z) / (p,q) of the previous step
-            HIPCHK(launch_update_px<float>(V, g->z32, po, pn, g->e32, g->scalars, srz, srz_old, srz_old, S_PQ32,
+            HIPCHK(launch_update_px<float>(V, g->z32, po, pn, g->e32, g->scalars, beta_num, srz_old, srz_old, S_PQ32,
                                            it >= 2, s));
+            count(g, 0, (it >= 2 ? 5 : 4) * 4.0);
         }
         int npq = 0;
         if (lasto_status e = apply_dot<float>(g, pn, g->q32, &npq); e != LASTO_OK) return e;
         if (lasto_status e = reduce_to(g, npq, S_PQ32); e != LASTO_OK) return e;
         if (it + 1 == iters) {
-            if (it == 0) HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
-            HIPCHK(launch_add32_nat(V, v, g->e32, pn, g->scalars, srz, S_PQ32, s));
+            if (it == 0) {
+                HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
+                count(g, 0, 4.0);
+            }
+            HIPCHK(launch_add32_nat(V, v, g->e32, pn, g->scalars, srz, S_PQ32, s, true));
+            count(g, 0, 8.0 + 16.0);
             break;
         }
         // (the inner loop never reads its own residual norm)
         HIPCHK(launch_update_r<float>(V, rr, g->q32, g->scalars, srz, S_PQ32, s));
+        count(g, 0, 3 * 4.0);
     }
     return LASTO_OK;
 }
@@ -255,16 +302,18 @@ static lasto_status set_faces(lasto_grid g, const double* rho, int bc, int lmax_
     return LASTO_OK;
 }
 
-// squared W-norm of 4 pi rho - A v for each right-hand side into
-// S_BR0 + b (interior_zero: of the face data alone) or S_BRR + b
-static lasto_status batch_norms(lasto_grid g, const double* rho, const double* v, int interior_zero)
+// squared W-norm of 4 pi rho - A v for each right-hand side into slot
+// base + b (default: S_BR0 + b with interior_zero, of the face data alone;
+// S_BRR + b otherwise)
+static lasto_status batch_norms(lasto_grid g, const double* rho, const double* v, int interior_zero, int base = -1)
 {
     const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
     const int nb = interior_blocks(g->cview);
+    if (base < 0) base = interior_zero ? S_BR0 : S_BRR;
     for (int b = 0; b < g->n_batch; ++b) {
         HIPCHK(launch_residual_nat(g->cview, v + b * N, rho + b * N, 4.0 * kPi, nullptr, g->partials, interior_zero,
                                    g->stream));
-        if (lasto_status e = reduce_to(g, nb, (interior_zero ? S_BR0 : S_BRR) + b); e != LASTO_OK) return e;
+        if (lasto_status e = reduce_to(g, nb, base + b); e != LASTO_OK) return e;
     }
     return LASTO_OK;
 }
@@ -285,6 +334,18 @@ extern "C" void lasto_solve_opts_default(lasto_solve_opts* o)
     o->lmax_bc = 4;
     o->debug_nan_iter = -1;
     o->profile = 0;
+    o->fallback = 1;
+}
+
+static lasto_status judge_batch(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel, int* accepted);
+static lasto_status coarse_net_check(lasto_grid g, const lasto_solve_opts& o);
+
+// milliseconds between two recorded events (0 if either is missing)
+static double event_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.0f;
+    if (!a || !b || hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return (double)ms;
 }
 
 extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, double* v, const lasto_solve_opts* opts,
@@ -299,9 +360,13 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     if (!(o.rtol > 0.0) || o.max_iters < 1 || o.nu1 < 1 || o.nu2 < 0 || o.nu1 > 16 || o.nu2 > 16)
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad rtol/max_iters/nu1/nu2");
     if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
-        o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 1 || (o.precision == 1 && o.inner_iters < 1) ||
-        o.inner_first < 0 || o.coarse < 0 || o.coarse > 2)
-        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters/coarse");
+        o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 3 || (o.precision == 1 && o.inner_iters < 1) ||
+        o.inner_first < 0 || o.coarse < 0 || o.coarse > 2 || o.fallback < 0 || o.fallback > 1)
+        return fail(LASTO_ERR_ARG,
+                    "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters/coarse/fallback");
+    if (o.guess >= 2 && (o.n_atoms < 1 || !o.atoms))
+        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: guess 2 and 3 need the atom tables");
+    if (o.guess == 3 && !o.guess_net) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: guess 3 needs guess_net");
     lasto_solve_info inf;
     std::memset(&inf, 0, sizeof(inf));
     hipStream_t s = g->stream;
@@ -317,28 +382,62 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         const bool lds_first = o.precision == 1 && g->tail32_top >= 0 && g->tail32_top < g->cfdm_level;
         inf.coarse_level = (o.coarse != 1 && !lds_first) ? g->cfdm_level : -1;
     }
+    if (o.coarse_net) {
+        if (lasto_status e = coarse_net_check(g, o); e != LASTO_OK) return e;
+    }
+    g->lc_net = o.coarse_net;
+    g->lc_level = o.coarse_net ? o.coarse_net_level : -1;
+    g->lc_applied = 0;
+    struct LcOff {
+        lasto_grid g;
+        ~LcOff()
+        {
+            g->lc_net = nullptr;
+            g->lc_level = -1;
+        }
+    } lc_off{g};
     g->prof_used = 0;
     g->prof_bytes = 0.0;
     g->prof_fp32 = 0;
+    g->alg_bytes = 0.0;
     struct ProfOff {
         lasto_grid g;
         ~ProfOff() { g->prof_on = false; }
     } prof_off{g};
+    for (hipEvent_t& e : g->ph_ev)
+        if (!e) HIPCHK(hipEventCreate(&e));
     Level& L0 = g->lev[0];
     const LevelView& V = L0.view;
     const int nb_i = interior_blocks(V);
     const double fourpi = 4.0 * kPi;
+    const int nbat = g->n_batch;
+    const size_t Ncopy = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    HIPCHK(hipEventRecord(g->ph_ev[0], s));
 
     // face values (every right-hand side of a batch from its own moments)
     if (o.bc == 0 || o.bc == 1) {
         if (lasto_status e = set_faces(g, rho, o.bc, o.lmax_bc, v); e != LASTO_OK) return e;
         if (o.bc == 1) HIPCHK(hipMemcpyAsync(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, s));
     }
+    HIPCHK(hipEventRecord(g->ph_ev[1], s));
+    // the start inside
     if (o.guess == 1) {
         // zero interior: copy an all-zero split array onto the interior of v
         HIPCHK(launch_fill_zero<double>(g->q, split_elems(V), s));
         HIPCHK(launch_split_to_nat(V, g->q, v, s));
+    } else if (o.guess >= 2) {
+        AtomDev* dat = nullptr;
+        if (lasto_status e = stage_atoms(g, nbat * o.n_atoms, o.atoms, 1, "lasto_poisson_solve", &dat); e != LASTO_OK)
+            return e;
+        for (int b = 0; b < nbat; ++b) HIPCHK(launch_guess(g, dat + (size_t)b * o.n_atoms, o.n_atoms, v + b * Ncopy));
+        if (o.guess == 3) {
+            int acc = 0;
+            if (lasto_status e = judge_batch(g, o.guess_net, rho, v, nullptr, &acc); e != LASTO_OK) return e;
+            inf.guess_accepted = acc;
+            if (acc < nbat) inf.fallback_used |= 1;
+        }
     }
+    HIPCHK(hipEventRecord(g->ph_ev[2], s));
 
     // reference norm ||b - A v_bc||_W and initial residual r (split)
     HIPCHK(launch_residual_nat(V, v, rho, fourpi, nullptr, g->partials, 1, s));
@@ -347,7 +446,10 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     // inner solve reads)
     if (o.precision == 1) HIPCHK(launch_residual_nat32(V, v, rho, fourpi, g->r32, g->partials, s));
     else HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
+    count(g, 0, 8.0 + (o.precision == 1 ? 20.0 : 24.0));
     if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
+    HIPCHK(launch_fill_zero<double>(g->scalars + S_BAD, 1, s));
+    HIPCHK(launch_fill_zero<double>(g->scalars + S_LC_ACC, 1, s));
     if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
     const double r0sq = g->h_scalars[S_R0];
     const double r0 = std::sqrt(r0sq);
@@ -359,7 +461,6 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     // A batch iterates on the stacked system (one norm, one set of CG
     // coefficients for all copies, which is CG on the block-diagonal system)
     // and then checks every copy against its own reference norm.
-    const int nbat = g->n_batch;
     double br0[kMaxBatch] = {0.0};
     if (nbat > 1) {
         if (lasto_status e = batch_norms(g, rho, v, 1); e != LASTO_OK) return e;
@@ -375,46 +476,58 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         HIPCHK(launch_split_to_nat(V, g->q, v, s));
         HIPCHK(hipStreamSynchronize(s));
         inf.n_batch = nbat;
+        inf.ms_bc = event_ms(g->ph_ev[0], g->ph_ev[1]);
+        inf.ms_guess = event_ms(g->ph_ev[1], g->ph_ev[2]);
         inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         if (info) *info = inf;
         return LASTO_OK;
     }
 
     lasto_status result = LASTO_OK;
+    const char* why = "";
     double best = rel;
     int grow = 0;
     int it = 0, cg_it = 0;
+    int max_it = o.max_iters;
+    // the form running now: the mixed form can hand over to FP64 MG-PCG
+    int prec = o.precision;
+    int method = o.method;
     // CG accumulates its correction in the split array x (zero now) and adds
     // it to v when it stops or restarts
-    const bool cg = (o.precision == 0 && o.method == 0);
-    if (cg) HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
+    bool cg = (prec == 0 && method == 0);
+    if (cg) {
+        HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
+        count(g, 0, 8.0);
+    }
   for (;;) {
-    while (rel > target && it < o.max_iters) {
+    while (rel > target && it < max_it) {
         if (o.debug_nan_iter == it) {
             const size_t at = sidx(V, V.nx / 2, V.ny / 2, V.nz / 2);
-            if (o.precision == 1) HIPCHK(launch_inject_nan(g->r32, at, s));
+            if (prec == 1) HIPCHK(launch_inject_nan(g->r32, at, s));
             else HIPCHK(launch_inject_nan(g->r, at, s));
         }
-        if (o.precision == 1) {
+        if (prec == 1) {
             // FP32 inner solve on the FP32 rounding of the FP64 residual (the
             // equation is linear, so the residual's scale does not matter
             // while it stays far inside the FP32 range), then v += e in FP64
             const int inner = (inf.refinements == 0 && o.inner_first > 0) ? o.inner_first : o.inner_iters;
-            if (o.method == 1) {
+            if (method == 1) {
                 if (lasto_status e = mg32_inner(g, o, inner, &inf.vcycles, v); e != LASTO_OK) return e;
             } else {
                 if (lasto_status e = pcg32_inner(g, o, inner, &inf.vcycles, v); e != LASTO_OK) return e;
             }
             HIPCHK(launch_residual_nat32(V, v, rho, fourpi, g->r32, g->partials, s));
+            count(g, 0, 20.0);
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             inf.refinements++;
-        } else if (o.method == 1) {
+        } else if (method == 1) {
             // plain V-cycle iteration: v += V(r), r = b - A v
             lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, nullptr, nullptr);
             if (st != LASTO_OK) return st;
             inf.vcycles++;
             HIPCHK(launch_add_nat(V, v, g->z, s));
             HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
+            count(g, 0, 24.0 + 24.0);
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
         } else {
             // one MG-preconditioned CG step
@@ -426,22 +539,41 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             if (lasto_status e = reduce_to(g, nd, srz); e != LASTO_OK) return e;
             double* pn = g->p[cg_it & 1];
             double* po = g->p[(cg_it + 1) & 1];
-            HIPCHK(launch_update_p<double>(V, g->z, po, pn, g->scalars, srz, srz_old, cg_it == 0, s));
+            int beta_num = srz;
+            if (g->lc_net && cg_it > 0) {
+                // the learned coarse correction makes the preconditioner vary
+                // from step to step: flexible (Polak-Ribiere) beta
+                HIPCHK(launch_dot<double>(V, g->z, g->q, g->partials, s));
+                if (lasto_status e = reduce_to(g, row_blocks(V), S_ZQ); e != LASTO_OK) return e;
+                HIPCHK(launch_flex_beta(g->scalars, srz_old, S_PQ, S_ZQ, S_FNUM, s));
+                count(g, 0, 16.0);
+                beta_num = S_FNUM;
+            }
+            HIPCHK(launch_update_p<double>(V, g->z, po, pn, g->scalars, beta_num, srz_old, cg_it == 0, s));
+            count(g, 0, (cg_it == 0 ? 2 : 3) * 8.0);
             int npq = 0;
             if (lasto_status e = apply_dot<double>(g, pn, g->q, &npq); e != LASTO_OK) return e;
             if (lasto_status e = reduce_to(g, npq, S_PQ); e != LASTO_OK) return e;
             int nb_r = 0;
             HIPCHK(launch_update_xr<double>(V, g->x, g->r, pn, g->q, g->scalars, srz, S_PQ, g->partials, s, &nb_r));
+            count(g, 0, 6 * 8.0);
             if (lasto_status e = reduce_to(g, nb_r, S_RR); e != LASTO_OK) return e;
             cg_it++;
         }
         true_resid = !cg;
-        if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;
+        // the residual norm, and (mixed form) whether an FP32 correction broke down
+        if (lasto_status e = read_scalars(g, S_RR, S_BAD - S_RR + 1); e != LASTO_OK) return e;
         rel = std::sqrt(g->h_scalars[S_RR]) / r0;
         if (it < 128) inf.resid_hist[it] = rel;
         ++it;
+        if (prec == 1 && g->h_scalars[S_BAD] != 0.0) {
+            result = LASTO_ERR_DIVERGED;
+            why = "lasto_poisson_solve: the FP32 inner solve produced non-finite values (v kept finite)";
+            break;
+        }
         if (!std::isfinite(rel)) {
             result = LASTO_ERR_DIVERGED;
+            why = "lasto_poisson_solve: residual not finite";
             break;
         }
         if (rel < best) {
@@ -449,6 +581,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             grow = 0;
         } else if (rel > 1e3 * best && ++grow >= 3) {
             result = LASTO_ERR_DIVERGED;
+            why = "lasto_poisson_solve: residual growing";
             break;
         }
         if (rel <= target && cg) {
@@ -458,6 +591,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             HIPCHK(launch_add_nat(V, v, g->x, s));
             HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
             HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
+            count(g, 0, 24.0 + 8.0 + 24.0);
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;
             rel = std::sqrt(g->h_scalars[S_RR]) / r0;
@@ -465,7 +599,39 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             cg_it = 0;
         }
     }
-    if (nbat > 1 && result == LASTO_OK && rel <= target && it < o.max_iters) {
+    if (result == LASTO_OK && rel > target && it >= max_it) {
+        result = LASTO_ERR_NOT_CONVERGED;
+        why = "lasto_poisson_solve: tolerance not reached within max_iters";
+    }
+    if (result != LASTO_OK && prec == 1 && o.fallback == 1) {
+        // the mixed form failed: finish as FP64 MG-PCG from the current
+        // iterate (finite: a broken-down correction never reaches v), with
+        // max_iters more iterations
+        inf.fallback_used |= 2;
+        prec = 0;
+        method = 0;
+        cg = true;
+        cg_it = 0;
+        grow = 0;
+        result = LASTO_OK;
+        why = "";
+        max_it = it + o.max_iters;
+        HIPCHK(launch_fill_zero<double>(g->x, split_elems(V), s));
+        HIPCHK(launch_residual_nat(V, v, rho, fourpi, g->r, g->partials, 0, s));
+        count(g, 0, 8.0 + 24.0);
+        if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
+        if (lasto_status e = read_scalars(g, S_RR, 1); e != LASTO_OK) return e;
+        rel = std::sqrt(g->h_scalars[S_RR]) / r0;
+        best = rel;
+        true_resid = true;
+        if (!std::isfinite(rel)) {
+            result = LASTO_ERR_DIVERGED;
+            why = "lasto_poisson_solve: residual not finite";
+            break;
+        }
+        continue;
+    }
+    if (nbat > 1 && result == LASTO_OK && rel <= target && it < max_it) {
         // every copy against its own reference norm; tighten the stacked
         // target while one of them is still above the tolerance
         if (lasto_status e = batch_norms(g, rho, v, 0); e != LASTO_OK) return e;
@@ -484,7 +650,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     // a breakdown; x holds the last finite correction), then the true
     // residual of the returned iterate, unless the loop ended on it (the same
     // kernel and launch shape: the same bits)
-    if (true_resid && r0 > 0.0) {
+    if (true_resid) {
         inf.rel_resid = rel;
     } else {
         if (cg) HIPCHK(launch_add_nat(V, v, g->x, s));
@@ -493,6 +659,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         if (lasto_status e = read_scalars(g, S_TMP, 1); e != LASTO_OK) return e;
         inf.rel_resid = std::sqrt(g->h_scalars[S_TMP]) / r0;
     }
+    HIPCHK(hipEventRecord(g->ph_ev[3], s));
     inf.iters = it;
     inf.n_batch = nbat;
     if (nbat > 1) {
@@ -507,8 +674,15 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     } else {
         inf.batch_rel_resid[0] = inf.rel_resid;
     }
+    // learned coarse corrections accepted on the device
+    if (g->lc_applied > 0) {
+        if (lasto_status e = read_scalars(g, S_LC_ACC, 1); e != LASTO_OK) return e;
+        inf.coarse_applied = g->lc_applied;
+        inf.coarse_accepted = (int)g->h_scalars[S_LC_ACC];
+    }
+    HIPCHK(hipStreamSynchronize(s));
     if (g->prof_on) {
-        // read_scalars synchronised the stream: every event has completed
+        // the stream is synchronised: every event has completed
         double ms = 0.0;
         for (int k = 0; k < g->prof_used; ++k) {
             float e = 0.0f;
@@ -520,13 +694,21 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         inf.smooth_bytes = g->prof_bytes;
         inf.smooth_fp32 = g->prof_fp32;
     }
-    if (result == LASTO_OK && !(inf.rel_resid <= o.rtol)) result = LASTO_ERR_NOT_CONVERGED;
-    if (!std::isfinite(inf.rel_resid)) result = LASTO_ERR_DIVERGED;
+    inf.ms_bc = event_ms(g->ph_ev[0], g->ph_ev[1]);
+    inf.ms_guess = event_ms(g->ph_ev[1], g->ph_ev[2]);
+    inf.ms_cycles = event_ms(g->ph_ev[2], g->ph_ev[3]);
+    inf.alg_bytes = g->alg_bytes;
+    if (result == LASTO_OK && !(inf.rel_resid <= o.rtol)) {
+        result = LASTO_ERR_NOT_CONVERGED;
+        why = "lasto_poisson_solve: tolerance not reached within max_iters";
+    }
+    if (!std::isfinite(inf.rel_resid)) {
+        result = LASTO_ERR_DIVERGED;
+        why = "lasto_poisson_solve: residual not finite";
+    }
     inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (info) *info = inf;
-    if (result == LASTO_ERR_NOT_CONVERGED)
-        return fail(result, "lasto_poisson_solve: tolerance not reached within max_iters");
-    if (result == LASTO_ERR_DIVERGED) return fail(result, "lasto_poisson_solve: residual not finite or growing");
+    if (result != LASTO_OK) return fail(result, why);
     return LASTO_OK;
 }
 
@@ -618,16 +800,103 @@ static lasto_status judge(lasto_grid g, const double* rho, double* v, const floa
     return LASTO_OK;
 }
 
+// The learned guess on every right-hand side of the grid: per copy the
+// net's correction of v (features of that copy's rho and v), then both
+// candidates of every copy get one red-black sweep (all copies in one
+// launch) and each copy keeps the one with the smaller residual relative to
+// its face data alone. rel (host [2 n_batch] or NULL): plain, learned per
+// copy; *accepted: copies that kept the learned candidate.
+static lasto_status judge_batch(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel, int* accepted)
+{
+    if (lasto_status e = learned_scratch(g); e != LASTO_OK) return e;
+    const int nb = g->n_batch;
+    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    hipStream_t s = g->stream;
+    double* keep_plain = g->lscr[LS_PLAIN];
+    double* keep_learned = g->lscr[LS_LEARNED];
+    if (lasto_status e = batch_norms(g, rho, v, 1, S_BR0); e != LASTO_OK) return e;
+    HIPCHK(hipMemcpyAsync(keep_plain, v, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
+    for (int b = 0; b < nb; ++b) {
+        const float* y = nullptr;
+        double out_scale = 0.0;
+        if (lasto_status e = net_guess_forward(g, n, rho + b * N, v + b * N, &y, &out_scale); e != LASTO_OK)
+            return e;
+        HIPCHK(launch_add_f32_nat(g->cview, v + b * N, y, out_scale, s));
+    }
+    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
+    if (lasto_status e = batch_norms(g, rho, v, 0, S_BRR); e != LASTO_OK) return e;
+    HIPCHK(hipMemcpyAsync(keep_learned, v, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(v, keep_plain, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
+    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
+    if (lasto_status e = batch_norms(g, rho, v, 0, S_BJ); e != LASTO_OK) return e;
+    if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
+    int acc = 0;
+    for (int b = 0; b < nb; ++b) {
+        const double r0 = std::sqrt(g->h_scalars[S_BR0 + b]);
+        const double plain = r0 > 0.0 ? std::sqrt(g->h_scalars[S_BJ + b]) / r0 : 0.0;
+        const double learned = r0 > 0.0 ? std::sqrt(g->h_scalars[S_BRR + b]) / r0 : 0.0;
+        if (rel) {
+            rel[2 * b] = plain;
+            rel[2 * b + 1] = learned;
+        }
+        if (std::isfinite(learned) && learned < plain) {
+            HIPCHK(hipMemcpyAsync(v + b * N, keep_learned + b * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            ++acc;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (accepted) *accepted = acc;
+    return LASTO_OK;
+}
+
+// The first level a cycle in precision T does not treat level by level (an
+// exact coarsest solve or a one-workgroup tail), under coarse mode `mode`.
+static int first_special_level(lasto_grid g, int mode, bool fp32)
+{
+    int lev = g->tail_top;
+    if (fp32 && g->tail32_top >= 0) lev = std::min(lev, g->tail32_top);
+    if (mode != 1 && g->cfdm_level >= 0) lev = std::min(lev, g->cfdm_level);
+    if (mode == 0 && g->cg) lev = std::min(lev, g->cg_level);
+    return lev;
+}
+
+static lasto_status coarse_net_check(lasto_grid g, const lasto_solve_opts& o)
+{
+    const int c = o.coarse_net_level;
+    if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: coarse_net needs one right-hand side");
+    if (c < 1 || c >= g->nlev) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: coarse_net_level out of range");
+    if (c >= first_special_level(g, o.coarse, false) || (o.precision == 1 && c >= first_special_level(g, o.coarse, true)))
+        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: coarse_net_level must lie above the cycle's exact coarsest "
+                                   "solve (choose a coarser exact solve with coarse = 2 or 1)");
+    const LevelView& V = g->lev[c].view;
+    int cap[3];
+    if (lasto_status e = net_capacity(o.coarse_net, cap); e != LASTO_OK) return e;
+    if (V.nx < 8 || V.ny < 8 || V.nz < 8 || V.nx > cap[0] || V.ny > cap[1] || V.nz > cap[2])
+        return fail(LASTO_ERR_ARG, "lasto_poisson_solve: coarse_net_level's grid does not fit the net");
+    return LASTO_OK;
+}
+
+// `cycles` FP64 V(2,2)-cycles of level c on A_c u = f, the first from zero
+// (the exact LDS solve below when the level allows it, else the tail)
+lasto_status lasto::coarse_cycles(lasto_grid g, int c, int cycles, const double* f, double* u)
+{
+    const int mode = g->coarse_mode;
+    lasto_net lc = g->lc_net;
+    g->coarse_mode = (g->cfdm_level > c) ? 2 : 1;
+    g->lc_net = nullptr;
+    lasto_status st = LASTO_OK;
+    for (int k = 0; k < cycles && st == LASTO_OK; ++k)
+        st = vcycle_level<double>(g, c, 2, 2, f, u, nullptr, nullptr, k == 0);
+    g->coarse_mode = mode;
+    g->lc_net = lc;
+    return st;
+}
+
 extern "C" lasto_status lasto_learned_guess(lasto_grid g, lasto_net n, const double* rho, double* v, double* rel,
                                             int* accepted)
 {
     if (!g || !n || !rho || !v) return fail(LASTO_ERR_ARG, "lasto_learned_guess: NULL argument");
-    if (g->n_batch != 1) return fail(LASTO_ERR_ARG, "lasto_learned_guess: one right-hand side per grid");
-    if (lasto_status e = learned_scratch(g); e != LASTO_OK) return e;
-    const float* y = nullptr;
-    double out_scale = 0.0;
-    if (lasto_status e = net_guess_forward(g, n, rho, v, &y, &out_scale); e != LASTO_OK) return e;
-    return judge(g, rho, v, y, out_scale, rel, accepted);
+    return judge_batch(g, n, rho, v, rel, accepted);
 }
 
 // The residual r = 4 pi rho - A v in natural layout (LS_R, faces zero) and

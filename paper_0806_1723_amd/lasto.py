@@ -62,6 +62,12 @@ class SolveOpts(C.Structure):
         ("profile", C.c_int),
         ("inner_first", C.c_int),
         ("coarse", C.c_int),
+        ("fallback", C.c_int),
+        ("n_atoms", C.c_int),
+        ("atoms", C.c_void_p),
+        ("guess_net", C.c_void_p),
+        ("coarse_net", C.c_void_p),
+        ("coarse_net_level", C.c_int),
     ]
 
 
@@ -81,6 +87,14 @@ class SolveInfo(C.Structure):
         ("n_batch", C.c_int),
         ("batch_rel_resid", C.c_double * 16),
         ("coarse_level", C.c_int),
+        ("fallback_used", C.c_int),
+        ("guess_accepted", C.c_int),
+        ("coarse_applied", C.c_int),
+        ("coarse_accepted", C.c_int),
+        ("ms_bc", C.c_double),
+        ("ms_guess", C.c_double),
+        ("ms_cycles", C.c_double),
+        ("alg_bytes", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -91,7 +105,10 @@ class SolveInfo(C.Structure):
                     smooth_launches=self.smooth_launches, smooth_ms=self.smooth_ms,
                     smooth_bytes=self.smooth_bytes, smooth_fp32=self.smooth_fp32,
                     batch_rel_resid=list(self.batch_rel_resid[:max(self.n_batch, 1)]),
-                    coarse_level=self.coarse_level)
+                    coarse_level=self.coarse_level, fallback_used=self.fallback_used,
+                    guess_accepted=self.guess_accepted, coarse_applied=self.coarse_applied,
+                    coarse_accepted=self.coarse_accepted, ms_bc=self.ms_bc, ms_guess=self.ms_guess,
+                    ms_cycles=self.ms_cycles, alg_bytes=self.alg_bytes)
 
 
 # exported names, in header order
@@ -102,10 +119,11 @@ SYMBOLS = [
     "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_density_terms", "lasto_sphere_project", "lasto_sphere_radial",
     "lasto_sphere_energy", "lasto_interstitial_density", "lasto_matrix_elements", "lasto_fdm_solve",
     "lasto_fdm_axis", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
-    "lasto_net_create", "lasto_net_destroy",
+    "lasto_net_create", "lasto_net_destroy", "lasto_net_set_grid",
     "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
+    "lasto_net_save", "lasto_net_load", "lasto_net_get_config", "lasto_net_tensor",
     "lasto_net_features", "lasto_net_forward", "lasto_net_backward", "lasto_net_adam_step",
-    "lasto_net_train_step", "lasto_learned_guess", "lasto_learned_correction", "lasto_net_correction_features",
+    "lasto_net_train_step", "lasto_learned_guess", "lasto_learned_correction", "lasto_coarse_pair", "lasto_net_correction_features",
 ]
 
 
@@ -196,6 +214,17 @@ def load():
     for name in ("lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads"):
         getattr(L, name).argtypes = [P, P, C.c_longlong]
         getattr(L, name).restype = i
+    for name in ("lasto_net_save", "lasto_net_load"):
+        getattr(L, name).argtypes = [P, C.c_char_p]
+        getattr(L, name).restype = i
+    L.lasto_net_get_config.argtypes = [P, C.POINTER(NetConfig), C.POINTER(C.c_longlong)]
+    L.lasto_net_get_config.restype = i
+    L.lasto_net_tensor.argtypes = [P, i, P, C.c_longlong, P]
+    L.lasto_net_tensor.restype = i
+    L.lasto_net_set_grid.argtypes = [P, i, i, i]
+    L.lasto_net_set_grid.restype = i
+    L.lasto_coarse_pair.argtypes = [P, P, P, P, i, i, P, P, C.POINTER(d), P]
+    L.lasto_coarse_pair.restype = i
     L.lasto_net_features.argtypes = [P, P, P, P, P]
     L.lasto_net_features.restype = i
     L.lasto_net_forward.argtypes = [P, P, P]
@@ -364,7 +393,19 @@ class Grid:
             Q = Q[0]
         return (rho_out, Q) if moments else rho_out
 
-    def poisson_solve(self, rho, v, allow_fail: bool = False, **opts):
+    def poisson_solve(self, rho, v, allow_fail: bool = False, atoms=None, guess_net=None, coarse_net=None,
+                      **opts):
+        """lasto_poisson_solve. atoms (guess 2, 3): as for pseudo_density;
+        guess_net, coarse_net: Net objects (or None)."""
+        keep = None
+        if atoms is not None:
+            keep, na = self._atom_table(atoms)
+            opts["n_atoms"] = na
+            opts["atoms"] = C.cast(keep, C.c_void_p).value
+        if guess_net is not None:
+            opts["guess_net"] = guess_net.h.value
+        if coarse_net is not None:
+            opts["coarse_net"] = coarse_net.h.value
         o = default_opts(**opts)
         info = SolveInfo()
         st = load().lasto_poisson_solve(self.h, _dev_ptr(rho), _dev_ptr(v), C.byref(o), C.byref(info))
@@ -525,10 +566,12 @@ class Spheres:
 
 
 def _learned_call(fn, grid, net, rho, v):
-    rel = np.zeros(2)
+    rel = np.zeros(2 * grid.n_batch)
     acc = C.c_int()
     _check(fn(grid.h, net.h, _dev_ptr(rho), _dev_ptr(v), _np_ptr(rel), C.byref(acc)))
-    return dict(rel_before=float(rel[0]), rel_after=float(rel[1]), accepted=bool(acc.value))
+    if grid.n_batch == 1:
+        return dict(rel_before=float(rel[0]), rel_after=float(rel[1]), accepted=bool(acc.value))
+    return dict(rel_before=rel[0::2].tolist(), rel_after=rel[1::2].tolist(), accepted=int(acc.value))
 
 
 class Net:
@@ -555,6 +598,55 @@ class Net:
         n = C.c_longlong()
         _check(load().lasto_net_param_count(h, C.byref(n)))
         self.nparam = n.value
+
+    def save(self, path: str):
+        """Checkpoint: masters, Adam moments and step, seed and scales (lasto_net_save)."""
+        _check(load().lasto_net_save(self.h, os.fsencode(path)))
+
+    def load_checkpoint(self, path: str):
+        """Resume from a checkpoint (lasto_net_load); the grid size stays this net's."""
+        _check(load().lasto_net_load(self.h, os.fsencode(path)))
+        _check(load().lasto_net_get_config(self.h, C.byref(self.cfg), None))
+
+    def coarse_pair(self, grid: "Grid", rho, v, level: int, nu1: int = 2):
+        """Training pair of the learned coarse correction at `level` for iterate v:
+        (features x, target t, residual scale s, level shape (nz, ny, nx))."""
+        import torch
+        nz, ny, nx = grid.levels()[level][::-1]
+        x = torch.zeros((nz, ny, nx, 8), dtype=torch.int16, device="cuda")
+        t = torch.zeros((nz, ny, nx), dtype=torch.float32, device="cuda")
+        s = C.c_double()
+        dims = np.zeros(3, dtype=np.int32)
+        _check(load().lasto_coarse_pair(grid.h, self.h, _dev_ptr(rho), _dev_ptr(v), level, nu1,
+                                        _dev_ptr(x, torch.int16), _dev_ptr(t, torch.float32), C.byref(s),
+                                        _np_ptr(dims)))
+        return x, t, s.value, (nz, ny, nx)
+
+    def set_grid(self, shape):
+        """Run on a grid of shape (nz, ny, nx), at most the creation size per axis."""
+        nz, ny, nx = shape
+        _check(load().lasto_net_set_grid(self.h, nx, ny, nz))
+        self.shape = (nz, ny, nx)
+
+    # stored tensors (lasto_net_tensor), in header order
+    TENSORS = ["e0", "e1", "e2", "e3", "m3", "d2", "d1", "d0", "u2", "u1", "u0",
+               "g0", "g1", "g2", "g3", "g4", "g5", "g6", "g7", "du0", "du1", "du2"]
+
+    def tensor(self, name: str):
+        """A stored BF16 tensor as int16 bit patterns on the device, [nz][ny][nx][c]."""
+        import torch
+        which = self.TENSORS.index(name)
+        dims = np.zeros(4, dtype=np.int32)
+        _check(load().lasto_net_tensor(self.h, which, None, 0, _np_ptr(dims)))
+        nx, ny, nz, c = (int(d) for d in dims)
+        out = torch.empty((nz, ny, nx, c), dtype=torch.int16, device="cuda")
+        _check(load().lasto_net_tensor(self.h, which, _dev_ptr(out, torch.int16), out.numel(), _np_ptr(dims)))
+        return out
+
+    def adam_steps(self) -> int:
+        cfg, st = NetConfig(), C.c_longlong()
+        _check(load().lasto_net_get_config(self.h, C.byref(cfg), C.byref(st)))
+        return st.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -178,3 +178,63 @@ def corrected_cycles(p: Problem, net_c, rtol: float = 1e-10, max_cycles: int = 6
             break
     torch.cuda.synchronize()
     return dict(cycles=c, accepted=acc, rel_resid=rel, ms=(time.perf_counter() - t0) * 1e3)
+
+
+# ------------------------------------------- learned coarse correction
+# The coarse net reads a coarse level's restricted residual at unit RMS and
+# returns the correction in units of out_scale times that RMS (smooth
+# corrections are ~ (L / pi)^2 / (4 pi) ~ 20 .. 200 times the residual).
+COARSE_SCALES = dict(rho_scale=1.0, pot_scale=0.01, h_ref=1.0, out_scale=100.0)
+
+
+def coarse_pairs(net: "lasto.Net", p: Problem, level: int, cycles=(0, 1, 2, 3), nu1: int = 2):
+    """Training pairs of the coarse net at `level` from the solver's own
+    iterates (k stationary V-cycles from the analytic guess): the restricted
+    residual the cycle's descent produces there and the exact correction of
+    that level (lasto_coarse_pair), with uniform weights over the level's
+    interior nodes."""
+    import torch
+    pairs = []
+    for k in cycles:
+        v = p.v_guess.clone()
+        if k:
+            p.grid.poisson_solve(p.rho, v, rtol=1e-14, bc=2, method=1, max_iters=k, allow_fail=True, coarse=2,
+                                 nu1=nu1)
+        x, t, _, shape = net.coarse_pair(p.grid, p.rho, v, level, nu1)
+        wt = torch.zeros_like(t)
+        wt[1:-1, 1:-1, 1:-1] = 1.0
+        wt /= wt.sum()
+        pairs.append((x, t, wt.contiguous(), shape))
+    return pairs
+
+
+def train_coarse(net: "lasto.Net", pairs, steps: int, lr: float = 2e-3):
+    """Adam over the pairs in turn, the net's grid set to each pair's level shape."""
+    hist = []
+    for s in range(steps):
+        x, t, wt, shape = pairs[s % len(pairs)]
+        net.set_grid(shape)
+        a = lr * 0.5 * (1.0 + np.cos(np.pi * s / max(steps, 1)))
+        hist.append(net.train_step(x, t, wt, max(a, lr * 1e-3)))
+    return hist
+
+
+def compare_coarse(net_c: "lasto.Net", p: Problem, level: int, rtol: float = 1e-10, **opts) -> dict:
+    """The same solve (faces and analytic guess as given, the exact coarsest
+    solve one level further down: coarse = 2) without and with the learned
+    coarse correction at `level`: iterations, V-cycles, time, proposals kept."""
+    import torch
+    out = {}
+    for kind in ("plain", "learned"):
+        for rep in range(2):   # the second pass timed warm
+            v = p.v_guess.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            kw = dict(coarse_net=net_c, coarse_net_level=level) if kind == "learned" else {}
+            info = p.grid.poisson_solve(p.rho, v, rtol=rtol, bc=2, coarse=2, **kw, **opts)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+        out[kind] = dict(iters=info["iters"], vcycles=info["vcycles"], ms=ms, rel_resid=info["rel_resid"],
+                         applied=info["coarse_applied"], accepted=info["coarse_accepted"],
+                         err_vs_label=float((v - p.v_star).abs().max() / p.v_star.abs().max()))
+    return out

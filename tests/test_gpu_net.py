@@ -135,6 +135,92 @@ def test_net_training_lowers_the_loss(torch, L):
     net2.close()
 
 
+def test_net_checkpoint_resumes_training_bit_for_bit(torch, L, tmp_path):
+    """lasto_net_save / lasto_net_load: five Adam steps, a checkpoint, five
+    more; a fresh net (other seed and scales) loaded from the checkpoint takes
+    the same five steps with the same losses and parameters bit for bit, and
+    has the checkpoint's step count and scales. Foreign files and other
+    channel counts are refused."""
+    shape = (17, 19, 18)
+    say("net checkpoint %s" % (shape,))
+    rng = np.random.default_rng(24)
+    ch = (16, 32, 16, 16)
+    x_bits, x = _features(torch, rng, shape)
+    t = torch.from_numpy(np.tanh(x[..., 0] - 0.3 * x[..., 4]).astype(np.float32)).cuda()
+    wt = torch.full(shape, 1.0 / np.prod(shape), dtype=torch.float32, device="cuda")
+    a = L.Net(shape, ch=ch, seed=11, rho_scale=0.2, pot_scale=0.03, h_ref=0.3, out_scale=2.0)
+    first = [a.train_step(x_bits, t, wt, 3e-3) for _ in range(5)]
+    path = str(tmp_path / "net.ckpt")
+    a.save(path)
+    rest = [a.train_step(x_bits, t, wt, 2e-3) for _ in range(5)]
+    pa = a.params()
+    b = L.Net(shape, ch=ch, seed=99)
+    b.load_checkpoint(path)
+    assert b.adam_steps() == 5
+    assert (b.cfg.seed, b.cfg.rho_scale, b.cfg.pot_scale, b.cfg.h_ref, b.cfg.out_scale) == (11, 0.2, 0.03, 0.3, 2.0)
+    rest_b = [b.train_step(x_bits, t, wt, 2e-3) for _ in range(5)]
+    assert rest_b == rest and all(np.isfinite(first))
+    assert np.array_equal(b.params(), pa) and b.adam_steps() == 10
+    # refused: other channel counts, a file that is not a checkpoint
+    c = L.Net(shape, ch=(16, 16, 16, 16), seed=1)
+    with pytest.raises(L.LastoError):
+        c.load_checkpoint(path)
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a checkpoint" * 8)
+    with pytest.raises(L.LastoError):
+        b.load_checkpoint(str(junk))
+    for n in (a, b, c):
+        n.close()
+
+
+def test_learned_guess_on_a_batch_matches_each_copy_alone(torch, L):
+    """The learned guess on a batched grid (three SCF-like perturbations of a
+    random config-4 cluster at 34^3) judges every copy on its own, with the
+    same bits as a grid holding that copy alone; the solve's guess = 3 runs
+    the same judge and reports how many learned starts it kept. (The node
+    colours of the stacked sweeps follow the stacked plane index, so with an
+    even plane count every copy sweeps red first, as a grid of its own does.)"""
+    from paper_0806_1723_amd import inputs as I
+    from paper_0806_1723_amd import learned
+    n = 34
+    say("learned guess on a batch, config 4 n=%d x 3" % n)
+    w = I.config(4, n_override=n, sample=3)
+    xs = L.mesh_for(w.axes)
+    batch = [w.atoms] + [I.perturb_atoms(w.atoms, 50 + b, rel=0.2) for b in range(2)]
+    net = L.Net((n, n, n), ch=(16, 16, 16, 16), seed=3, **learned.NET_SCALES)
+
+    def start(g, atoms):
+        rho = g.pseudo_density(atoms)
+        v = g.empty()
+        g.boundary_values(rho, v)
+        g.analytic_guess(atoms, v)
+        return rho, v
+
+    gb = L.Grid(*xs, n_batch=3)
+    rho_b, v_b = start(gb, batch)
+    rb = gb.learned_guess(net, rho_b, v_b)
+    acc = 0
+    for b in range(3):
+        g1 = L.Grid(*xs)
+        rho1, v1 = start(g1, batch[b])
+        r1 = g1.learned_guess(net, rho1, v1)
+        say("  copy %d: plain %.3e learned %.3e accepted %s" % (b, r1["rel_before"], r1["rel_after"], r1["accepted"]))
+        assert torch.equal(v1, v_b[b])
+        assert (r1["rel_before"], r1["rel_after"]) == (rb["rel_before"][b], rb["rel_after"][b])
+        acc += r1["accepted"]
+        g1.close()
+    assert rb["accepted"] == acc
+    v3 = gb.empty()
+    info = gb.poisson_solve(rho_b, v3, rtol=1e-10, guess=3, atoms=batch, guess_net=net)
+    assert info["guess_accepted"] == acc and bool(info["fallback_used"] & 1) == (acc < 3)
+    assert max(info["batch_rel_resid"]) <= 1e-10
+    v_b2 = v_b.clone()
+    gb.poisson_solve(rho_b, v_b2, rtol=1e-10)
+    assert float((v3 - v_b2).abs().max()) <= 1e-8 * float(v_b2.abs().max())
+    gb.close()
+    net.close()
+
+
 def test_learned_guess_lowers_the_residual_of_the_analytic_guess(torch, L):
     """Trained on config-4 problems (random clusters, 65^3 graded), the net's
     correction lowers the smoothed residual of the analytic guess on held-out
@@ -193,6 +279,52 @@ def test_learned_correction_saves_cycles(torch, L):
         assert corr["cycles"] <= plain["cycles"] - 2
         assert corr["accepted"] >= corr["cycles"] // 2
     net.close()
+
+
+def test_learned_coarse_correction_inside_the_cycle(torch, L):
+    """The learned coarse correction (config-4 clusters at 65^3, the net on
+    the first coarse level, the exact coarsest solve one level below): it is
+    proposed at every visit of its level, kept only where it lowers that
+    level's residual, and the flexible CG, the mixed form and the stationary
+    cycles reach the same solution (the label) with it. A net whose proposals
+    are far off is always refused, and the solve then takes the plain cycle's
+    course."""
+    from paper_0806_1723_amd import learned
+    n, level = 65, 1
+    say("learned coarse correction, config 4 at %d^3, level %d" % (n, level))
+    train_p = [learned.make_problem(4, s, n) for s in range(8)]
+    test_p = [learned.make_problem(4, 1000 + s, n) for s in range(2)]
+    cap = max(max(p.grid.levels()[level]) for p in train_p + test_p)
+    net = L.Net((cap, cap, cap), ch=(16, 32, 32, 32), seed=13, **learned.COARSE_SCALES)
+    pairs = [pp for p in train_p for pp in learned.coarse_pairs(net, p, level)]
+    hist = learned.train_coarse(net, pairs, steps=800, lr=2e-3)
+    k = len(pairs)
+    say("  %d pairs, training loss %.3e -> %.3e" % (k, np.mean(hist[:k]), np.mean(hist[-k:])))
+    assert np.mean(hist[-k:]) < 0.5 * np.mean(hist[:k])
+    for p in test_p:
+        for opts in (dict(), dict(precision=1), dict(method=1)):
+            r = learned.compare_coarse(net, p, level, **opts)
+            say("  %s %s: %s" % (p.name[:24], opts, r))
+            for kind in ("plain", "learned"):
+                assert r[kind]["rel_resid"] <= 1e-10 and r[kind]["err_vs_label"] <= 1e-8
+            assert r["plain"]["applied"] == 0
+            assert r["learned"]["applied"] >= r["learned"]["vcycles"] and r["learned"]["accepted"] >= 1
+            assert r["learned"]["accepted"] <= r["learned"]["applied"]
+    # far-off proposals are refused every time: the plain cycle's course
+    bad = L.Net((cap, cap, cap), ch=(16, 16, 16, 16), seed=2, rho_scale=1.0, pot_scale=0.01, h_ref=1.0,
+                out_scale=1e6)
+    p = test_p[0]
+    r = learned.compare_coarse(bad, p, level)
+    say("  refused net: %s" % r)
+    assert r["learned"]["accepted"] == 0 and r["learned"]["applied"] >= r["learned"]["vcycles"]
+    assert abs(r["learned"]["iters"] - r["plain"]["iters"]) <= 1 and r["learned"]["rel_resid"] <= 1e-10
+    # the level must lie above the exact coarsest solve
+    with pytest.raises(L.LastoError):
+        p.grid.poisson_solve(p.rho, p.v_guess.clone(), bc=2, coarse_net=net, coarse_net_level=level)
+    for q in train_p + test_p:
+        q.grid.close()
+    net.close()
+    bad.close()
 
 
 def test_net_features_match_their_definition(torch, L, R):

@@ -548,6 +548,78 @@ def test_failure_paths(torch, L, oracle_mod):
     g.close()
 
 
+def test_mixed_form_falls_back_to_fp64(torch, L, oracle_mod):
+    """The fallback of the mixed form, forced from the host: a NaN injected
+    into the FP32 inner solve's right-hand side (its correction never reaches
+    v), and a refinement budget too small for the tolerance. Both finish as
+    FP64 MG-PCG from the current iterate and match the oracle; with the
+    fallback off the first returns DIVERGED with a finite v."""
+    say("mixed-form fallback, config 2 n=65")
+    w = I.config(2, n_override=65)
+    xs = oracle_mod.mesh_for(w.axes)
+    rho_o, v_o = oracle_solution(oracle_mod, xs, w.atoms)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    for opts in (dict(debug_nan_iter=1), dict(max_iters=10, inner_iters=1), dict(debug_nan_iter=0, method=1)):
+        v = g.empty()
+        info = g.poisson_solve(rho, v, rtol=1e-12, precision=1, **opts)
+        err = wnorm(xs, v.cpu().numpy() - v_o) / wnorm(xs, v_o)
+        say("  %s: fallback %d iters %d refinements %d rel %.2e err %.2e" % (
+            opts, info["fallback_used"], info["iters"], info["refinements"], info["rel_resid"], err))
+        assert info["fallback_used"] & 2 and info["rel_resid"] <= 1e-12 and err <= 1e-9
+    v = g.empty()
+    info = g.poisson_solve(rho, v, rtol=1e-12, precision=1, debug_nan_iter=1, fallback=0, allow_fail=True)
+    assert info["status"] == L.ERR_DIVERGED and info["fallback_used"] == 0
+    assert torch.isfinite(v).all()
+    # without trouble the mixed form needs no fallback
+    info = g.poisson_solve(rho, g.empty(), rtol=1e-12, precision=1)
+    assert info["fallback_used"] == 0
+    g.close()
+
+
+@pytest.mark.parametrize("nb", [1, 2])
+def test_analytic_start_option_and_phase_report(torch, L, oracle_mod, nb):
+    """guess = 2 starts from the analytic superposition inside the solve:
+    the same iterate as lasto_analytic_guess followed by a solve of v as
+    given, fewer iterations than the zero start, the oracle's solution; the
+    info reports the phases and the finest level's algorithmic bytes."""
+    say("guess 2, config 2 n=65, %d copies" % nb)
+    w = I.config(2, n_override=65)
+    xs = oracle_mod.mesh_for(w.axes)
+    batch = [w.atoms] + [I.perturb_atoms(w.atoms, 900 + b) for b in range(nb - 1)]
+    atoms = batch if nb > 1 else w.atoms
+    g = L.Grid(*xs, n_batch=nb)
+    rho = g.pseudo_density(atoms)
+    v2 = g.empty()
+    i2 = g.poisson_solve(rho, v2, rtol=1e-12, guess=2, atoms=atoms)
+    v0 = g.empty()
+    g.boundary_values(rho, v0)
+    g.analytic_guess(atoms, v0)
+    i0 = g.poisson_solve(rho, v0, rtol=1e-12)
+    assert torch.equal(v0, v2) and i0["iters"] == i2["iters"]
+    iz = g.poisson_solve(rho, g.empty(), rtol=1e-12, guess=1)
+    say("  iters analytic %d zero %d; ms bc %.3f guess %.3f cycles %.3f total %.3f; %.0f B per node per V-cycle"
+        % (i2["iters"], iz["iters"], i2["ms_bc"], i2["ms_guess"], i2["ms_cycles"], i2["ms_total"],
+           i2["alg_bytes"] / (i2["vcycles"] * nb * 63 ** 3)))
+    assert i2["iters"] < iz["iters"]
+    assert i2["ms_bc"] > 0 and i2["ms_guess"] > 0 and i2["ms_cycles"] > 0
+    assert i2["ms_bc"] + i2["ms_guess"] + i2["ms_cycles"] <= i2["ms_total"]
+    # FP64 V(2,2) MG-PCG at the finest level, per node and iteration: the
+    # cycle (8 half-sweeps 92 B, red residual 16 B, restriction and
+    # prolongation 14 B plus the coarse level's share) and the Krylov streams
+    # (update of p, A p, update of x and r: 96 B), about 220 B
+    assert 190 <= i2["alg_bytes"] / (i2["vcycles"] * nb * 63 ** 3) <= 260
+    got = v2.cpu().numpy()
+    for b, a in enumerate(batch):
+        _, v_o = oracle_solution(oracle_mod, xs, a)
+        gb = got[b] if nb > 1 else got
+        assert wnorm(xs, gb - v_o) / wnorm(xs, v_o) <= 1e-9
+    # the atom tables are required
+    with pytest.raises(L.LastoError):
+        g.poisson_solve(rho, g.empty(), guess=2)
+    g.close()
+
+
 def test_scratch_users_leave_the_solver_clean(torch, L, oracle_mod):
     """lasto_rb_sweep borrows the solver's vectors: a solve after it on the
     same grid gives the same bits as before it."""
