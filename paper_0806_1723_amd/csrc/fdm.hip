@@ -50,63 +50,67 @@ void free_fdm(lasto_grid g)
     g->fdm = nullptr;
 }
 
-// Eigen-decomposition of a symmetric tridiagonal matrix (diagonal d[0..n-1],
-// off-diagonal e[i] between i and i+1) by the QL algorithm with implicit
-// Wilkinson shifts (Bowdler, Martin, Reinsch and Wilkinson, 1968). z starts
-// as the identity and accumulates the rotations: column k of z (z[i * n + k])
-// is the eigenvector of eigenvalue d[k]. Returns false if an eigenvalue takes
-// more than 60 sweeps.
-static bool tridiagonal_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& z)
+// Eigen-decomposition T = Q diag(a) Q^T of a symmetric tridiagonal matrix
+// (diagonal a[0..n-1], off-diagonal b[k] between k and k+1) by implicit
+// symmetric QR steps with the Wilkinson shift, as the bulge-chasing sweep of
+// Golub and Van Loan (Matrix Computations, Section 8.3): on the unreduced
+// block [lo, hi] ending at the bottom, a plane rotation on (lo, lo+1) set by
+// the first column of T - mu I starts a bulge, and rotations on (k, k+1) for
+// k = lo+1 .. hi-1 chase it down and out; the rotations are accumulated into
+// Q. An off-diagonal below eps (|a_k| + |a_k+1|) is set to zero, which splits
+// the matrix. On return a holds the eigenvalues and column k of Q
+// (q[i * n + k]) the eigenvector of a[k]. False if the iteration has not
+// converged after 40 n steps.
+static bool tridiagonal_eigen(int n, std::vector<double>& a, std::vector<double>& b, std::vector<double>& q)
 {
-    e.resize(n);
-    e[n - 1] = 0.0;
-    z.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) z[(size_t)i * n + i] = 1.0;
-    for (int l = 0; l < n; ++l) {
-        int sweeps = 0;
-        while (true) {
-            int m = l;
-            for (; m < n - 1; ++m) {
-                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= DBL_EPSILON * dd) break;
+    q.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) q[(size_t)i * n + i] = 1.0;
+    b.resize(std::max(n - 1, 0));
+    auto negligible = [&](int k) { return std::fabs(b[k]) <= DBL_EPSILON * (std::fabs(a[k]) + std::fabs(a[k + 1])); };
+    // plane rotation of columns k, k+1 of Q (Q <- Q R, R^T = [[c, s], [-s, c]])
+    auto rotate_q = [&](int k, double c, double s) {
+        for (int i = 0; i < n; ++i) {
+            double* row = &q[(size_t)i * n];
+            const double u = row[k], w = row[k + 1];
+            row[k] = c * u + s * w;
+            row[k + 1] = -s * u + c * w;
+        }
+    };
+    long steps = 0;
+    int hi = n - 1;
+    while (hi > 0) {
+        if (negligible(hi - 1)) {
+            b[hi - 1] = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && !negligible(lo - 1)) --lo;
+        if (++steps > 40L * n) return false;
+        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer a[hi]
+        const double dl = 0.5 * (a[hi - 1] - a[hi]);
+        const double bb = b[hi - 1];
+        const double mu = a[hi] - bb * bb / (dl + std::copysign(std::hypot(dl, bb), dl));
+        double x = a[lo] - mu, y = b[lo], bulge = 0.0;
+        for (int k = lo; k < hi; ++k) {
+            // rotation (c, s) with -s x + c y = 0: it zeroes the bulge (or, at
+            // k = lo, the second entry of the shifted first column)
+            const double r = std::hypot(x, y);
+            const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? y / r : 0.0;
+            if (k > lo) b[k - 1] = r;
+            // the 2 x 2 block on (k, k+1) under R^T . R
+            const double ak = a[k], ak1 = a[k + 1], bk = b[k];
+            a[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
+            a[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
+            b[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
+            // the entry below the block becomes the new bulge
+            if (k + 1 < hi) {
+                bulge = s * b[k + 1];
+                b[k + 1] = c * b[k + 1];
             }
-            if (m == l) break;
-            if (++sweeps > 60) return false;
-            // shift: the eigenvalue of the leading 2 x 2 block nearer d[l]
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = std::hypot(g, 1.0);
-            g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
-            double s = 1.0, c = 1.0, p = 0.0;
-            bool deflated = false;
-            for (int i = m - 1; i >= l; --i) {
-                double f = s * e[i];
-                const double b = c * e[i];
-                r = std::hypot(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) {   // an off-diagonal vanished: split and restart
-                    d[i + 1] -= p;
-                    e[m] = 0.0;
-                    deflated = true;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * b;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - b;
-                for (int k = 0; k < n; ++k) {
-                    double* zk = &z[(size_t)k * n];
-                    f = zk[i + 1];
-                    zk[i + 1] = s * zk[i] + c * f;
-                    zk[i] = c * zk[i] - s * f;
-                }
-            }
-            if (deflated) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0.0;
+            rotate_q(k, c, s);
+            x = b[k];
+            y = bulge;
         }
     }
     return true;
@@ -126,7 +130,7 @@ static bool axis_decomposition(const double* x, int n, double* lam, double* S, d
         d[t] = -(1.0 / (hm * w[t]) + 1.0 / (hp * w[t]));
     }
     for (int t = 0; t + 1 < m; ++t) e[t] = 1.0 / ((x[t + 2] - x[t + 1]) * std::sqrt(w[t] * w[t + 1]));
-    if (!tridiagonal_ql(m, d, e, z)) return false;
+    if (!tridiagonal_eigen(m, d, e, z)) return false;
     for (int t = 0; t < m; ++t) lam[t] = d[t];
     for (int i = 0; i < m; ++i) {
         const double sq = std::sqrt(w[i]);
@@ -524,12 +528,9 @@ struct CoarseGemm {
     double* S64[3] = {nullptr, nullptr, nullptr};
     double* Si64[3] = {nullptr, nullptr, nullptr};
     double* lam64[3] = {nullptr, nullptr, nullptr};
-    float* S32[3] = {nullptr, nullptr, nullptr};
-    float* Si32[3] = {nullptr, nullptr, nullptr};
     float* lam32[3] = {nullptr, nullptr, nullptr};
     double* buf64[2] = {nullptr, nullptr};
     float* buf32[2] = {nullptr, nullptr};
-    rocblas_handle blas = nullptr;
 };
 
 void free_coarse_gemm(lasto_grid g)
@@ -540,15 +541,12 @@ void free_coarse_gemm(lasto_grid g)
         (void)hipFree(c->S64[d]);
         (void)hipFree(c->Si64[d]);
         (void)hipFree(c->lam64[d]);
-        (void)hipFree(c->S32[d]);
-        (void)hipFree(c->Si32[d]);
         (void)hipFree(c->lam32[d]);
     }
     for (int b = 0; b < 2; ++b) {
         (void)hipFree(c->buf64[b]);
         (void)hipFree(c->buf32[b]);
     }
-    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     delete c;
     g->cg = nullptr;
 }
@@ -595,8 +593,6 @@ lasto_status coarse_gemm_init(lasto_grid g)
         e = upload(&c->S64[d], S);
         if (e == hipSuccess) e = upload(&c->Si64[d], Si);
         if (e == hipSuccess) e = upload(&c->lam64[d], lam);
-        if (e == hipSuccess) e = upload(&c->S32[d], S);
-        if (e == hipSuccess) e = upload(&c->Si32[d], Si);
         if (e == hipSuccess) e = upload(&c->lam32[d], lam);
     }
     const size_t cells = (size_t)c->m[0] * c->m[1] * c->m[2] * c->nb;
@@ -607,12 +603,6 @@ lasto_status coarse_gemm_init(lasto_grid g)
     if (e != hipSuccess) {
         free_coarse_gemm(g);
         return fail(LASTO_ERR_ALLOC, std::string("lasto_poisson_solve: coarse-level tables: ") + hipGetErrorString(e));
-    }
-    if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
-        rocblas_set_stream(c->blas, g->stream) != rocblas_status_success ||
-        rocblas_set_atomics_mode(c->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
-        free_coarse_gemm(g);
-        return fail(LASTO_ERR_HIP, "lasto_poisson_solve: rocBLAS handle");
     }
     return LASTO_OK;
 }
@@ -646,51 +636,90 @@ __global__ __launch_bounds__(256) void k_divide_dense(T* __restrict__ d, const T
     d[t] = d[t] / (lx[i] + ly[r % my] + lz[(r / my) % mz]);
 }
 
-static rocblas_status gemm_tn(rocblas_handle h, int m, int n, int k, const double* A, int lda, rocblas_stride sa,
-                              const double* B, int ldb, double* C, int ldc, rocblas_stride sc, int batch)
+// One contraction with the axes rotated, on the FP64 matrix cores: each
+// copy's block holds L = cells / m lines of m contiguous entries ([line][k],
+// the contracted axis fastest); the output is out[r][line] = sum_k P[r][k]
+// in[line][k], the new axis slowest. Three of them take [z][y][x] to
+// [x'][z][y], [y'][x'][z] and [z'][y'][x'] (the original order), three more
+// back to [z][y][x]. A workgroup computes 64 rows r by 32 lines as 4 x 2
+// tiles of v_mfma_f64_16x16x4f64 (A 16 x 4 from lane (row = lane % 16,
+// k = lane / 16), B 4 x 16 from lane (k = lane / 16, col = lane % 16), D with
+// lane holding rows lane / 16 + 4 j of column lane % 16), two tiles per wave,
+// over chunks of 64 k staged in LDS (P's rows and the block's lines read as
+// contiguous runs; rows padded to an odd length so the 16 rows a wave reads
+// fall on distinct banks). FP32 levels are read and written in FP32 and
+// contracted in FP64. The summation order is fixed: the same bits every time.
+constexpr int CT_RB = 64, CT_LB = 32, CT_KC = 64, CT_LD = CT_KC + 1, CT_NT = 256;
+typedef double ct_dbl4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(CT_NT) void k_contract(const double* __restrict__ P, const T* __restrict__ in,
+                                                    T* __restrict__ out, int m, int L, int row_blocks,
+                                                    int line_blocks)
 {
-    const double one = 1.0, zero = 0.0;
-    return rocblas_dgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, m, n, k, &one, A,
-                                         lda, sa, B, ldb, 0, &zero, C, ldc, sc, batch);
-}
-static rocblas_status gemm_tn(rocblas_handle h, int m, int n, int k, const float* A, int lda, rocblas_stride sa,
-                              const float* B, int ldb, float* C, int ldc, rocblas_stride sc, int batch)
-{
-    const float one = 1.0f, zero = 0.0f;
-    return rocblas_sgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, m, n, k, &one, A,
-                                         lda, sa, B, ldb, 0, &zero, C, ldc, sc, batch);
+    __shared__ double As[CT_RB * CT_LD];
+    __shared__ double Bs[CT_LB * CT_LD];
+    const int b = blockIdx.x;
+    const int copy = b / (row_blocks * line_blocks);
+    const int rb = (b / line_blocks) % row_blocks, lb = b % line_blocks;
+    const int r0 = rb * CT_RB, l0 = lb * CT_LB;
+    const size_t per = (size_t)m * L;
+    const T* __restrict__ inc = in + copy * per;
+    T* __restrict__ outc = out + copy * per;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p16 = lane & 15, grp = lane >> 4;
+    // this wave's two tiles: row tile `wave`, column tiles 0 and 1
+    ct_dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < m; k0 += CT_KC) {
+        const int kn = min(CT_KC, m - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < CT_RB * CT_KC; e += CT_NT) {
+            const int r = e / CT_KC, k = e % CT_KC;
+            As[r * CT_LD + k] = (r0 + r < m && k < kn) ? P[(size_t)(r0 + r) * m + k0 + k] : 0.0;
+        }
+        for (int e = threadIdx.x; e < CT_LB * CT_KC; e += CT_NT) {
+            const int l = e / CT_KC, k = e % CT_KC;
+            Bs[l * CT_LD + k] = (l0 + l < L && k < kn) ? (double)inc[(size_t)(l0 + l) * m + k0 + k] : 0.0;
+        }
+        __syncthreads();
+        const double* arow = As + (wave * 16 + p16) * CT_LD + grp;
+        const double* b0 = Bs + p16 * CT_LD + grp;
+        const double* b1 = Bs + (16 + p16) * CT_LD + grp;
+        for (int ks = 0; ks < kn; ks += 4) {
+            const double a = arow[ks];
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0[ks], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1[ks], acc1, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = r0 + wave * 16 + grp + 4 * j;
+        if (r >= m) continue;
+        const int la = l0 + p16, lb2 = l0 + 16 + p16;
+        if (la < L) outc[(size_t)r * L + la] = (T)acc0[j];
+        if (lb2 < L) outc[(size_t)r * L + lb2] = (T)acc1[j];
+    }
 }
 
-// One contraction with the axes rotated: each copy's block holds L =
-// cells / m lines of m contiguous entries ([line][k], the contracted axis
-// fastest); the output is out[r][line] = sum_k P[r][k] in[line][k], the new
-// axis slowest. Column-major, that is C (L x m) = A^T B with A the input
-// (m x L) and B the row-major P read as column-major (B(k, r) = P[r][k]):
-// one GEMM per copy, whatever the axis (L x m x m, e.g. 7744 x 88 x 88).
-// Three of them take [z][y][x] to [x'][z][y], [y'][x'][z] and [z'][y'][x']
-// (the original order), three more back to [z][y][x]. (rocBLAS runs these
-// shapes at 6 TFLOP/s in FP64 and 17 in FP32: 128-wide tiles leave most
-// compute units idle. A hand-written kernel with 32 lines per workgroup and
-// a 4 x 4 block per lane was slower still, latency-bound at three waves per
-// compute unit.)
 template <typename T>
-static rocblas_status contract_rot(const CoarseGemm* c, int m, const T* P, const T* in, T* out)
+static hipError_t contract_rot(const CoarseGemm* c, int m, const double* P, const T* in, T* out, hipStream_t s)
 {
     const int per = c->m[0] * c->m[1] * c->m[2];
     const int L = per / m;
-    return gemm_tn(c->blas, L, m, m, in, m, per, P, m, out, L, per, c->nb);
+    const int row_blocks = (m + CT_RB - 1) / CT_RB, line_blocks = (L + CT_LB - 1) / CT_LB;
+    hipLaunchKernelGGL(k_contract<T>, dim3((unsigned)(row_blocks * line_blocks * c->nb)), dim3(CT_NT), 0, s, P, in,
+                       out, m, L, row_blocks, line_blocks);
+    return hipGetLastError();
 }
 
+// (the axis tables are FP64 in both precisions; the eigenvalue sums of the
+// division are the cycle's precision)
 template <typename T> struct CgTab;
 template <> struct CgTab<double> {
-    static double* const* S(const CoarseGemm* c) { return c->S64; }
-    static double* const* Si(const CoarseGemm* c) { return c->Si64; }
     static double* const* lam(const CoarseGemm* c) { return c->lam64; }
     static double* buf(const CoarseGemm* c, int b) { return c->buf64[b]; }
 };
 template <> struct CgTab<float> {
-    static float* const* S(const CoarseGemm* c) { return c->S32; }
-    static float* const* Si(const CoarseGemm* c) { return c->Si32; }
     static float* const* lam(const CoarseGemm* c) { return c->lam32; }
     static float* buf(const CoarseGemm* c, int b) { return c->buf32[b]; }
 };
@@ -704,22 +733,18 @@ lasto_status coarse_gemm_solve(lasto_grid g, const T* f, T* u, hipStream_t s)
     const unsigned blocks = (unsigned)((n + 255) / 256);
     T* b0 = CgTab<T>::buf(c, 0);
     T* b1 = CgTab<T>::buf(c, 1);
-    auto Si = CgTab<T>::Si(c);
-    auto S = CgTab<T>::S(c);
     auto lam = CgTab<T>::lam(c);
     hipLaunchKernelGGL(k_split_to_dense<T>, dim3(blocks), dim3(256), 0, s, V, f, b0);
     LASTO_LAUNCH_CHECK("k_split_to_dense");
-    rocblas_status e = contract_rot<T>(c, c->m[0], Si[0], b0, b1);
-    if (e == rocblas_status_success) e = contract_rot<T>(c, c->m[1], Si[1], b1, b0);
-    if (e == rocblas_status_success) e = contract_rot<T>(c, c->m[2], Si[2], b0, b1);
-    if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_poisson_solve: coarse-level GEMM");
+    LASTO_HIP(contract_rot<T>(c, c->m[0], c->Si64[0], b0, b1, s));
+    LASTO_HIP(contract_rot<T>(c, c->m[1], c->Si64[1], b1, b0, s));
+    LASTO_HIP(contract_rot<T>(c, c->m[2], c->Si64[2], b0, b1, s));
     hipLaunchKernelGGL(k_divide_dense<T>, dim3(blocks), dim3(256), 0, s, b1, lam[0], lam[1], lam[2], c->m[0],
                        c->m[1], c->m[2], n);
     LASTO_LAUNCH_CHECK("k_divide_dense");
-    e = contract_rot<T>(c, c->m[0], S[0], b1, b0);
-    if (e == rocblas_status_success) e = contract_rot<T>(c, c->m[1], S[1], b0, b1);
-    if (e == rocblas_status_success) e = contract_rot<T>(c, c->m[2], S[2], b1, b0);
-    if (e != rocblas_status_success) return fail(LASTO_ERR_HIP, "lasto_poisson_solve: coarse-level GEMM");
+    LASTO_HIP(contract_rot<T>(c, c->m[0], c->S64[0], b1, b0, s));
+    LASTO_HIP(contract_rot<T>(c, c->m[1], c->S64[1], b0, b1, s));
+    LASTO_HIP(contract_rot<T>(c, c->m[2], c->S64[2], b1, b0, s));
     hipLaunchKernelGGL(k_dense_to_split<T>, dim3(blocks), dim3(256), 0, s, V, b0, u);
     LASTO_LAUNCH_CHECK("k_dense_to_split");
     return LASTO_OK;
