@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time over which the oracle baseline repeats whole solves")
+    ap.add_argument("--no-clean", action="store_true", help="skip the 513^3 MALL-free smoother roofline")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="report the solve alone (no sphere, interstitial-density or matrix-element objects)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -217,9 +220,27 @@ def main():
                      "launches": launches, "events_on": "timed step 1 of %d" % args.steps},
     }
 
-    out["spheres"] = bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii)
-    out["interstitial_density"] = bench_interstitial(args, lasto, I, g, w, xs, centers, radii)
-    out["matrix_elements"] = bench_matrix_elements(args, lasto, I)
+    # the whole iteration's algorithmic bytes at the finest level (every
+    # launch's compulsory reads and writes) over the event-timed iteration
+    out["solve_phases"] = {
+        name: {"ms_bc": round(inf["ms_bc"], 4), "ms_guess": round(inf["ms_guess"], 4),
+               "ms_cycles": round(inf["ms_cycles"], 4), "alg_bytes": inf["alg_bytes"],
+               "alg_gbs_over_cycles": round(inf["alg_bytes"] / (inf["ms_cycles"] * 1e-3) / 1e9, 1)
+               if inf["ms_cycles"] > 0 else None, "fallback_used": inf["fallback_used"]}
+        for name, inf in (("mixed" if mixed else "timed", last), ("fp64", fp64[-1]))}
+    log("bench: iteration bandwidth (finest-level algorithmic bytes / event-timed cycles): %s"
+        % {k: v["alg_gbs_over_cycles"] for k, v in out["solve_phases"].items()})
+    if args.config == 3 and not args.n and not args.no_clean:
+        out["roofline_clean"] = bench_clean_roofline(args, lasto, I, form)
+    out["roofline"]["mall_assisted"] = bool(n <= 257)
+    if n <= 257:
+        out["roofline"]["note"] = ("the finest level's FP32 arrays (u, f: ~150 MB with padding) fit the 256 MB "
+                                   "Infinity Cache; roofline_clean gives the same kernel at 513^3")
+
+    if not args.solve_only:
+        out["spheres"] = bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii)
+        out["interstitial_density"] = bench_interstitial(args, lasto, I, g, w, xs, centers, radii)
+        out["matrix_elements"] = bench_matrix_elements(args, lasto, I)
 
     if not args.no_cpu:
         out["cpu_baseline"], v_oracle = cpu_baseline(w, xs, (rho[0] if nb > 1 else rho).cpu().numpy(),
@@ -239,6 +260,74 @@ def main():
             out["cpu_baseline"]["sample"] += "; times %d right-hand sides" % nb
     g.close()
     print(json.dumps(out), flush=True)
+
+
+def copy_ceiling(gib=2.0, reps=10):
+    """Device-to-device copy of `gib` GiB (far beyond the 256 MB Infinity
+    Cache) with torch's copy kernel, event-timed: read + written bytes per
+    second, the streaming ceiling the stencil kernels are held to."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = statistics.median(ts)
+    gbs = 2.0 * n * 8 / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"gbs": round(gbs, 1), "bytes_per_copy": 2 * n * 8, "ms": round(ms, 4), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "kernel": "torch copy_ (float64), median of %d" % reps}
+
+
+def bench_clean_roofline(args, lasto, I, form):
+    """The dominant kernel where the Infinity Cache cannot hold its arrays:
+    one right-hand side of the 309-atom cluster on its graded 513^3 mesh
+    (FP32 u and f ~1.1 GB, FP64 ~2.2 GB), one mixed and one FP64 solve with
+    every finest-level half-sweep event-timed (12 or 8 B per updated node and
+    colour pass, as at 257^3), against 8 TB/s and against the measured copy
+    ceiling."""
+    import torch
+    cc = copy_ceiling()
+    log("bench: copy ceiling %.1f GB/s (%.3f of 8 TB/s)" % (cc["gbs"], cc["frac_of_peak"]))
+    w = I.config(5)
+    xs = lasto.mesh_for(w.axes)
+    g = lasto.Grid(*xs)
+    rho = g.pseudo_density(w.batch_atoms[0])
+    v = g.empty()
+    res = {"workload": "309-atom Mackay icosahedron, graded 513^3, L=80, one right-hand side", "copy_ceiling": cc}
+    for name, prec in (("fp32_in_mixed", 1), ("fp64", 0)):
+        for rep in range(2):   # the first also warms up
+            v.zero_()
+            opts = dict(form, precision=prec)
+            if prec == 0:
+                opts.update(inner_first=0)
+            info = g.poisson_solve(rho, v, rtol=1e-10, profile=1, **opts)
+        launches, ms, by = info["smooth_launches"], info["smooth_ms"], info["smooth_bytes"]
+        gbs = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        res[name] = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "frac_of_copy_ceiling": round(gbs / cc["gbs"], 4),
+                     "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
+                     "algorithmic_bytes_per_launch": round(by / max(launches, 1)),
+                     "solve_ms": round(info["ms_total"], 3), "iters": info["iters"], "vcycles": info["vcycles"],
+                     "rel_resid": info["rel_resid"],
+                     "iteration_alg_gbs": round(info["alg_bytes"] / (info["ms_cycles"] * 1e-3) / 1e9, 1)
+                     if info["ms_cycles"] > 0 else None}
+        log("bench: 513^3 %s: smoother %.1f GB/s (%.3f of 8 TB/s, %.3f of the copy ceiling), avg %.1f us; solve "
+            "%.2f ms, %d iters" % (name, gbs, gbs / HBM_PEAK_GBS, gbs / cc["gbs"], ms * 1e3 / max(launches, 1),
+                                   info["ms_total"], info["iters"]))
+    g.close()
+    del rho, v
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_spheres(args, lasto, I, g, w, xs, v, rho, centers, radii):
@@ -418,7 +507,8 @@ def cpu_baseline(w, xs, rho, min_seconds):
     import numpy as np
     import oracle
     oracle.lib()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the threads the oracle's OpenMP loops actually use
+    cores = oracle.max_threads()
     center = tuple(0.5 * (x[0] + x[-1]) for x in xs)
     Q = oracle.moments(xs, rho, 4, center)
     v0 = np.zeros_like(rho)
@@ -434,9 +524,33 @@ def cpu_baseline(w, xs, rho, min_seconds):
     ms = statistics.median(times) * 1e3
     log("bench: oracle %d solves in %.1f s (%d threads), %d cycles each, rel %.2e, median %.1f ms"
         % (len(times), total, cores, cyc, rel, ms))
-    return {"value": round(ms, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+    # one host thread: two V-cycles of the same solve, scaled to the cycles a
+    # whole solve takes (a bounded sample of a ~20 s single-thread solve)
+    oracle.set_threads(1)
+    vs = v0.copy()
+    t0 = time.perf_counter()
+    oracle.solve(xs, rho, vs, rtol=1e-300, max_cycles=2)
+    t1 = (time.perf_counter() - t0) / 2.0
+    oracle.set_threads(cores)
+    one = {"ms_per_solve": round(t1 * cyc * 1e3, 1), "ms_per_cycle": round(t1 * 1e3, 1), "cores": 1,
+           "sample": "2 V(2,2) cycles timed, times %d cycles" % cyc}
+    log("bench: oracle on one thread: %.1f ms per cycle, %.0f ms per solve" % (t1 * 1e3, t1 * cyc * 1e3))
+    return {"value": round(ms, 1), "unit": "ms", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(), "one_thread": one,
             "sample": "%d whole FP64 solves of the %d^3 problem to %.0e (%d V(2,2) cycles each, %.1f s in "
                       "all); median per solve" % (len(times), len(xs[0]), w.rtol, cyc, total)}, v
+
+
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def dual_widths(x):

@@ -86,6 +86,10 @@ def lib():
         L.oracle_basis_points.restype = i
         L.oracle_matrix_elements.argtypes = [P, i, P, i, P, i, P, i, P, P, i, P, P, P, P, P]
         L.oracle_matrix_elements.restype = i
+        L.oracle_set_threads.argtypes = [i]
+        L.oracle_set_threads.restype = None
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = i
         _lib = L
     return _lib
 
@@ -386,3 +390,12 @@ def sphere_density_terms(xs, centers, radii, r_min, rho_lm, lmin, rho):
     if rc != 0:
         raise ValueError("bad n_rad or lmin")
     return rho
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())

@@ -26,6 +26,7 @@
  * Array layout: [nz][ny][nx], x fastest, boundary nodes included.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -899,3 +900,7 @@ void oracle_rb_sweep(const double* x, int nx, const double* y, int ny, const dou
     free(b);
     level_free(&L);
 }
+
+/* Host threads of the OpenMP loops (for timing the oracle on n cores). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }
