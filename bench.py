@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time over which the oracle baseline repeats whole solves")
     ap.add_argument("--no-clean", action="store_true", help="skip the 513^3 MALL-free smoother roofline")
+    ap.add_argument("--train", type=int, default=200, help="config 4: training problems")
+    ap.add_argument("--train-steps", type=int, default=2400, help="config 4: Adam steps per net")
+    ap.add_argument("--validate", type=int, default=50, help="config 4: labels checked by the oracle")
     ap.add_argument("--solve-only", action="store_true",
                     help="report the solve alone (no sphere, interstitial-density or matrix-element objects)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -262,30 +265,42 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def copy_ceiling(gib=2.0, reps=10):
-    """Device-to-device copy of `gib` GiB (far beyond the 256 MB Infinity
-    Cache) with torch's copy kernel, event-timed: read + written bytes per
-    second, the streaming ceiling the stencil kernels are held to."""
+def copy_ceiling(lasto, gib=2.0, reps=10):
+    """The streaming ceiling, event-timed over arrays of `gib` GiB (far beyond
+    the 256 MB Infinity Cache): torch's device copy, and the library's stream
+    probe as a copy (one read, one write) and as a + b (two reads, one write:
+    the half-sweep's mix, the ceiling the smoother is held to). Bytes moved per
+    second, medians of `reps`."""
     import torch
     n = int(gib * (1 << 30)) // 8
     a = torch.rand(n, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(2):
-        b.copy_(a)
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    d = torch.empty_like(a)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ts = []
-    for _ in range(reps):
-        e0.record()
-        b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    ms = statistics.median(ts)
-    gbs = 2.0 * n * 8 / (ms * 1e-3) / 1e9
-    del a, b
+
+    def timed(fn, nbytes):
+        for _ in range(2):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = statistics.median(ts)
+        return round(nbytes / (ms * 1e-3) / 1e9, 1)
+
+    out = {"torch_copy_gbs": timed(lambda: d.copy_(a), 2 * n * 8),
+           "probe_copy_gbs": timed(lambda: lasto.stream_probe(a, d), 2 * n * 8),
+           "probe_two_reads_one_write_gbs": timed(lambda: lasto.stream_probe(a, d, b=b), 3 * n * 8),
+           "gib_per_array": gib}
+    assert torch.equal(d, a + b)
+    out["gbs"] = max(out["probe_two_reads_one_write_gbs"], out["probe_copy_gbs"], out["torch_copy_gbs"])
+    out["frac_of_peak"] = round(out["gbs"] / HBM_PEAK_GBS, 4)
+    del a, b, d
     torch.cuda.empty_cache()
-    return {"gbs": round(gbs, 1), "bytes_per_copy": 2 * n * 8, "ms": round(ms, 4), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "kernel": "torch copy_ (float64), median of %d" % reps}
+    return out
 
 
 def bench_clean_roofline(args, lasto, I, form):
@@ -296,8 +311,8 @@ def bench_clean_roofline(args, lasto, I, form):
     colour pass, as at 257^3), against 8 TB/s and against the measured copy
     ceiling."""
     import torch
-    cc = copy_ceiling()
-    log("bench: copy ceiling %.1f GB/s (%.3f of 8 TB/s)" % (cc["gbs"], cc["frac_of_peak"]))
+    cc = copy_ceiling(lasto)
+    log("bench: streaming ceiling %s" % cc)
     w = I.config(5)
     xs = lasto.mesh_for(w.axes)
     g = lasto.Grid(*xs)
@@ -576,38 +591,67 @@ def conv_flops(shape, ch):
 
 
 def bench_learned(args):
-    """Config 4: the learned initial guess and the learned correction against
-    plain multigrid on held-out random clusters at 129^3 (nets trained first,
-    on the GPU, by the library's own kernels)."""
+    """Config 4: the learned initial guess (net on a coarse level of each
+    graded mesh, its output interpolated to the finest) and the learned
+    coarse correction inside the cycle, against plain multigrid on held-out
+    random clusters at 129^3. The nets are trained first, on the GPU, by the
+    library's own kernels, on `--train` seeded problems whose labels are the
+    method's own FP64 solves; a sample of labels is validated by the oracle
+    (its own pseudo-density and its own operator's residual of the label)."""
     import numpy as np
     import torch
 
     from paper_0806_1723_amd import lasto, learned
     lasto.load()
     n = args.n or 129
-    ntrain, ntest = 16, 4
-    t0 = time.perf_counter()
-    train_p = [learned.make_problem(4, s, n) for s in range(ntrain)]
-    test_p = [learned.make_problem(4, 1000 + s, n) for s in range(ntest)]
-    log("bench: %d training and %d test problems at %d^3 in %.1f s" % (ntrain, ntest, n, time.perf_counter() - t0))
+    ntrain, ntest, nval = args.train, 8, min(args.validate, args.train)
+    glev, clev = 2, 1   # the guess net's level; the coarse correction's level (exact solve one below: coarse = 2)
     ch = (16, 32, 32, 32)
-    net = lasto.Net((n, n, n), ch=ch, seed=7, **learned.NET_SCALES)
+    cap = 96
+    net = lasto.Net((cap, cap, cap), ch=ch, seed=7, **learned.NET_SCALES)
+    net_c = lasto.Net((cap, cap, cap), ch=ch, seed=9, **learned.COARSE_SCALES)
     t0 = time.perf_counter()
-    hist = learned.train(net, train_p, steps=1600, lr=2e-3)
+    pairs, cpairs, val = [], [], []
+    for sidx in range(ntrain):
+        p = learned.make_problem(4, sidx, n)
+        pairs.append(learned.training_pair(net, p, level=glev))
+        cpairs += learned.coarse_pairs(net_c, p, clev, cycles=(0, 2))
+        if sidx < nval:
+            val.append((sidx, p.grid.coords, p.rho.cpu().numpy(), p.v_star.cpu().numpy(), p.atoms))
+        p.grid.close()
+        del p
+    t_data = time.perf_counter() - t0
+    log("bench: %d training problems at %d^3 (pairs on levels %d and %d) in %.1f s" % (ntrain, n, glev, clev, t_data))
+    # the labels against the oracle: its own pseudo-density of the same atoms
+    # and its own operator's relative residual of the label
+    import oracle
+    from paper_0806_1723_amd import inputs as I
+    oracle.lib()
+    t0 = time.perf_counter()
+    worst_rho, worst_res = 0.0, 0.0
+    for sidx, xs, rho, vstar, atoms in val:
+        rho_o = oracle.pseudo_density(xs, I.atom_arrays(atoms))
+        worst_rho = max(worst_rho, float(np.abs(rho - rho_o).max() / np.abs(rho_o).max()))
+        worst_res = max(worst_res, oracle.rel_residual(xs, rho_o, vstar))
+    log("bench: %d labels validated by the oracle in %.1f s: source max rel diff %.2e, label residual by the "
+        "oracle's operator <= %.2e" % (len(val), time.perf_counter() - t0, worst_rho, worst_res))
+    t0 = time.perf_counter()
+    hist = learned.train(net, [], steps=args.train_steps, lr=2e-3, pairs=pairs)
     torch.cuda.synchronize()
     t_guess = time.perf_counter() - t0
-    net_c = lasto.Net((n, n, n), ch=ch, seed=9, **learned.CORRECTION_SCALES)
-    pairs = [pp for p in train_p for pp in learned.correction_pairs(net_c, p, (1, 2, 3))]
     t0 = time.perf_counter()
-    hist_c = learned.train_pairs(net_c, pairs, steps=2400, lr=2e-3)
+    hist_c = learned.train_coarse(net_c, cpairs, steps=args.train_steps, lr=2e-3)
     torch.cuda.synchronize()
     t_corr = time.perf_counter() - t0
-    log("bench: trained guess net %.1f s (loss %.3e -> %.3e), correction net %.1f s (loss %.3e -> %.3e)" % (
-        t_guess, np.mean(hist[:ntrain]), np.mean(hist[-ntrain:]), t_corr, np.mean(hist_c[:len(pairs)]),
-        np.mean(hist_c[-len(pairs):])))
-    # forward-pass time and matrix-core rate of the net
+    k = len(pairs)
+    log("bench: trained guess net %.1f s (loss %.3e -> %.3e), coarse net %.1f s (loss %.3e -> %.3e)" % (
+        t_guess, np.mean(hist[:k]), np.mean(hist[-k:]), t_corr, np.mean(hist_c[:len(cpairs)]),
+        np.mean(hist_c[-len(cpairs):])))
+    test_p = [learned.make_problem(4, 1000 + s, n) for s in range(ntest)]
+    # forward-pass time of the guess net on its level of the first test problem
+    learned.use_level(net, test_p[0].grid, glev)
     x = net.features(test_p[0].grid, test_p[0].rho, test_p[0].v_guess)
-    y = torch.zeros((n, n, n), dtype=torch.float32, device="cuda")
+    y = torch.zeros(net.shape, dtype=torch.float32, device="cuda")
     for _ in range(3):
         net.forward(x, y)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -617,58 +661,56 @@ def bench_learned(args):
     e1.record()
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1) / 10
-    flops = conv_flops((n, n, n), ch)
-    rows = []
-    mixed = []
+    flops = conv_flops(net.shape, ch)
+    rows, mixed, coarse = [], [], []
     for p in test_p:
         for _ in range(2):   # second pass timed warm
-            r = learned.compare(net, p, rtol=1e-10)
-            rm = learned.compare(net, p, rtol=1e-10, precision=1)
-        a = learned.corrected_cycles(p, None)
-        b = learned.corrected_cycles(p, net_c)
-        rows.append((r, a, b))
+            r = learned.compare(net, p, rtol=1e-10, level=glev)
+            rm = learned.compare(net, p, rtol=1e-10, level=glev, precision=1, nu1=3, nu2=3, inner_iters=5,
+                                 inner_first=4)
+        rc = learned.compare_coarse(net_c, p, clev)
+        rows.append(r)
         mixed.append(rm)
-        log("bench: %s zero %d/%.2f ms analytic %d/%.2f ms learned %d/%.2f ms (accepted %s) | stationary plain %d/%.2f ms"
-            " corrected %d/%.2f ms" % (p.name[:28], r["zero"]["iters"], r["zero"]["ms"], r["analytic"]["iters"],
-                                       r["analytic"]["ms"], r["learned"]["iters"], r["learned"]["ms"],
-                                       r["learned"]["accepted"], a["cycles"], a["ms"], b["cycles"], b["ms"]))
-        log("bench:   mixed precision: zero %d/%.2f ms analytic %d/%.2f ms learned %d/%.2f ms (accepted %s),"
-            " error vs label %.2e" % (rm["zero"]["vcycles"], rm["zero"]["ms"], rm["analytic"]["vcycles"],
-                                      rm["analytic"]["ms"], rm["learned"]["vcycles"], rm["learned"]["ms"],
-                                      rm["learned"]["accepted"], rm["err_vs_label"]))
+        coarse.append(rc)
+        log("bench: %s FP64 zero %d/%.2f ms analytic %d/%.2f ms learned %d/%.2f ms (kept %s); mixed %d/%.2f %d/%.2f "
+            "%d/%.2f; coarse net %d/%.2f vs %d/%.2f ms (kept %d of %d)" % (
+                p.name[:26], r["zero"]["iters"], r["zero"]["ms"], r["analytic"]["iters"], r["analytic"]["ms"],
+                r["learned"]["iters"], r["learned"]["ms"], r["learned"]["accepted"], rm["zero"]["vcycles"],
+                rm["zero"]["ms"], rm["analytic"]["vcycles"], rm["analytic"]["ms"], rm["learned"]["vcycles"],
+                rm["learned"]["ms"], rc["learned"]["iters"], rc["learned"]["ms"], rc["plain"]["iters"],
+                rc["plain"]["ms"], rc["learned"]["accepted"], rc["learned"]["applied"]))
     med = lambda v: round(float(statistics.median(v)), 3)
     out = {
         "metric": "time-to-1e-10-residual per Poisson solve: learned guess vs plain multigrid (V-cycles saved)",
-        "value": med([r["learned"]["ms"] for r, _, _ in rows]),
+        "value": med([r["learned"]["ms"] for r in mixed]),
         "unit": "ms",
         "n_gpus": 1, "steps": ntest, "warmup": 1,
-        "ms_per_step": med([r["learned"]["ms"] for r, _, _ in rows]),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 net + f64 solve",
-        "data": "synthetic",
+        "ms_per_step": med([r["learned"]["ms"] for r in mixed]),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 net + f32/f64 solve", "data": "synthetic",
         "config": {"workload": "random 13-55-atom clusters (seeds 40000+s), graded %d^3, L=48" % n,
                    "train_problems": ntrain, "test_problems": ntest, "net_channels": list(ch),
-                   "parallelism": "single GPU"},
-        "pcg_iters": {"zero": [r["zero"]["iters"] for r, _, _ in rows],
-                      "analytic": [r["analytic"]["iters"] for r, _, _ in rows],
-                      "learned": [r["learned"]["iters"] for r, _, _ in rows]},
-        "pcg_ms": {"zero": med([r["zero"]["ms"] for r, _, _ in rows]),
-                   "analytic": med([r["analytic"]["ms"] for r, _, _ in rows]),
-                   "learned": med([r["learned"]["ms"] for r, _, _ in rows])},
-        "learned_guess_accepted": [bool(r["learned"]["accepted"]) for r, _, _ in rows],
-        # the same three starts with FP32 cycles inside FP64 refinement (V-cycles counted)
-        "mixed_vcycles": {k: [rm[k]["vcycles"] for rm in mixed] for k in ("zero", "analytic", "learned")},
-        "mixed_ms": {k: med([rm[k]["ms"] for rm in mixed]) for k in ("zero", "analytic", "learned")},
-        "mixed_err_vs_label": max(rm["err_vs_label"] for rm in mixed),
-        "stationary_cycles": {"plain": [a["cycles"] for _, a, _ in rows],
-                              "learned_correction": [b["cycles"] for _, _, b in rows]},
-        "stationary_ms": {"plain": med([a["ms"] for _, a, _ in rows]),
-                          "learned_correction": med([b["ms"] for _, _, b in rows])},
-        "training_s": {"guess_net": round(t_guess, 2), "correction_net": round(t_corr, 2)},
+                   "guess_net_level": glev, "coarse_net_level": clev, "parallelism": "single GPU"},
+        "labels_validated_by_oracle": {"problems": len(val), "source_max_rel_diff": worst_rho,
+                                       "label_residual_by_oracle_max": worst_res},
+        "fp64_pcg_iters": {k: [r[k]["iters"] for r in rows] for k in ("zero", "analytic", "learned")},
+        "fp64_pcg_ms": {k: med([r[k]["ms"] for r in rows]) for k in ("zero", "analytic", "learned")},
+        "learned_guess_kept": [bool(r["learned"]["accepted"]) for r in rows],
+        "mixed_vcycles": {k: [r[k]["vcycles"] for r in mixed] for k in ("zero", "analytic", "learned")},
+        "mixed_ms": {k: med([r[k]["ms"] for r in mixed]) for k in ("zero", "analytic", "learned")},
+        "mixed_err_vs_label": max(r["err_vs_label"] for r in mixed),
+        "coarse_net": {"iters": {k: [r[k]["iters"] for r in coarse] for k in ("plain", "learned")},
+                       "ms": {k: med([r[k]["ms"] for r in coarse]) for k in ("plain", "learned")},
+                       "kept_of_proposed": [[r["learned"]["accepted"], r["learned"]["applied"]] for r in coarse],
+                       "form": "FP64 MG-PCG (flexible with the net), exact coarsest solve by LDS (coarse = 2)"},
+        "training_s": {"data": round(t_data, 2), "guess_net": round(t_guess, 2), "coarse_net": round(t_corr, 2)},
         "roofline": {"bound": "mfma", "achieved": round(flops / (fwd_ms * 1e-3) / 1e12, 2), "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": round(flops / (fwd_ms * 1e-3) / 1e12 / 2500.0, 5), "traffic": None,
-                     "kernel": "net forward pass (k_conv<*> BF16 MFMA, all layers)", "gflop": round(flops / 1e9, 2),
-                     "forward_ms": round(fwd_ms, 3)},
+                     "kernel": "guess net forward pass on level %d (k_conv<*> BF16 MFMA, all layers)" % glev,
+                     "gflop": round(flops / 1e9, 3), "forward_ms": round(fwd_ms, 4), "grid": list(net.shape)},
     }
+    for p in test_p:
+        p.grid.close()
     print(json.dumps(out), flush=True)
 
 

@@ -104,6 +104,9 @@ lasto_status lasto_grid_destroy(lasto_grid g);
 /* Number of levels and the node counts of level l (out[3] = nx, ny, nz). */
 lasto_status lasto_grid_levels(lasto_grid g, int* n_levels);
 lasto_status lasto_grid_level_shape(lasto_grid g, int level, int* out3);
+/* The finest-level index of each node of level l per axis (every coarse node
+ * is a fine node): ix [nx_l], iy [ny_l], iz [nz_l], host. */
+lasto_status lasto_grid_level_nodes(lasto_grid g, int level, int* ix, int* iy, int* iz);
 
 /*
  * One atom of the pseudo-density (host struct, passed by pointer).
@@ -493,6 +496,16 @@ lasto_status lasto_apply(lasto_grid g, const double* u, double* Au);
 lasto_status lasto_rb_sweep(lasto_grid g, const double* u_in, const double* rho, double* u_out, int first_colour);
 
 /*
+ * Streaming ceiling (measurement, not part of the method): dst = a over
+ * `bytes` (b NULL) or dst = a + b elementwise in FP64 (two reads and one
+ * write, the red-black half-sweep's mix), 16-byte accesses, four per thread in
+ * flight. Enqueued on hip_stream (NULL: the default stream); returns without
+ * waiting. a, b, dst: device, bytes a multiple of 16.
+ * Errors: LASTO_ERR_ARG, LASTO_ERR_HIP.
+ */
+lasto_status lasto_stream_probe(const double* a, const double* b, double* dst, size_t bytes, void* hip_stream);
+
+/*
  * Dirichlet data on the six faces of v, the boundary step of
  * lasto_poisson_solve on its own (eq. (3.3) for bc = 0; bc = 1 the multipole
  * field of the grid moments, as documented at lasto_poisson_solve).
@@ -523,7 +536,9 @@ lasto_status lasto_analytic_guess(lasto_grid g, int n_atoms, const lasto_atom* a
  * correction only if it lowers the residual.
  */
 typedef struct {
-    int nx, ny, nz;              /* node grid the net runs on (the grid's finest level); each >= 8 */
+    int nx, ny, nz;              /* node grid the net runs on: the grid's finest level or, for the learned
+                                    guess, one of its coarse levels (features at that level's nodes, the
+                                    output interpolated linearly to the finest); each >= 8 */
     int ch[4];                   /* channels per level: ch[0] = 16, the others 16, 32, 48 or 64 */
     unsigned long long seed;     /* initial weights: He-normal from a splitmix64 / Box-Muller stream */
     double rho_scale;            /* feature 0 = rho * rho_scale */

@@ -1,4 +1,4 @@
-"""Build liblasto.so (gfx950) in place with hipcc."""
+"""Build liblasto.so (gfx950) in place with hipcc (``host.cpp`` is host-only C++)."""
 from __future__ import annotations
 
 import os
@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblasto.so")
 SOURCES = ["api.hip", "grid.hip", "solve.hip", "mg_kernels.hip", "src_kernels.hip", "sphere.hip", "basis.hip",
-           "fdm.hip", "net.hip", "net_kernels.hip"]
+           "fdm.hip", "net.hip", "net_kernels.hip", "host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -28,7 +28,7 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     """Compile every HIP source into liblasto.so (always recompiles)."""
-    objs = [os.path.join(CSRC, src.replace(".hip", ".o")) for src in SOURCES]
+    objs = [os.path.join(CSRC, os.path.splitext(src)[0] + ".o") for src in SOURCES]
     cmds = [[HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", os.path.join(CSRC, src), "-o", obj]
             for src, obj in zip(SOURCES, objs)]
     if verbose:

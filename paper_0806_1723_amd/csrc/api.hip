@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "host.h"
 #include "internal.h"
 
 namespace lasto {
@@ -19,70 +20,6 @@ lasto_status fail(lasto_status s, const std::string& msg)
 {
     set_error(msg);
     return s;
-}
-
-// ---------------------------------------------------------------- mesh
-// Spacing rule h(d) = min(hmax, hmin + (g-1) d), d = distance to the nearest
-// plane. Phi(d) = int_0^d dt/h(t) in closed form and its inverse.
-struct Spacing {
-    double g, hmin, hmax;
-    double dsat() const { return (hmax - hmin) / (g - 1.0); }
-    double phi(double d) const
-    {
-        if (g <= 1.0) return d / hmin;
-        const double ds = dsat();
-        if (d <= ds) return std::log1p((g - 1.0) * d / hmin) / (g - 1.0);
-        return std::log1p((g - 1.0) * ds / hmin) / (g - 1.0) + (d - ds) / hmax;
-    }
-    double phi_inv(double v) const
-    {
-        if (g <= 1.0) return v * hmin;
-        const double ds = dsat();
-        const double vs = std::log1p((g - 1.0) * ds / hmin) / (g - 1.0);
-        if (v <= vs) return hmin * std::expm1((g - 1.0) * v) / (g - 1.0);
-        return ds + (v - vs) * hmax;
-    }
-};
-
-// Pieces of [lo, hi] on which the distance to the nearest plane is linear:
-// breaks at planes and at midpoints between neighbouring planes.
-struct Piece {
-    double a, b, plane;
-};
-
-static std::vector<Piece> mesh_pieces(double lo, double hi, std::vector<double> planes)
-{
-    std::sort(planes.begin(), planes.end());
-    std::vector<double> br{lo};
-    for (size_t j = 0; j < planes.size(); ++j) {
-        if (j > 0) {
-            const double mid = 0.5 * (planes[j - 1] + planes[j]);
-            if (mid > br.back() && mid < hi) br.push_back(mid);
-        }
-        if (planes[j] > br.back() && planes[j] < hi) br.push_back(planes[j]);
-    }
-    br.push_back(hi);
-    std::vector<Piece> out;
-    for (size_t k = 0; k + 1 < br.size(); ++k) {
-        const double mid = 0.5 * (br[k] + br[k + 1]);
-        double best = planes[0];
-        for (double p : planes)
-            if (std::fabs(p - mid) < std::fabs(best - mid)) best = p;
-        out.push_back({br[k], br[k + 1], best});
-    }
-    return out;
-}
-
-static double piece_length(const Piece& P, const Spacing& S)
-{
-    return std::fabs(S.phi(std::fabs(P.b - P.plane)) - S.phi(std::fabs(P.a - P.plane)));
-}
-
-static double total_length(const std::vector<Piece>& pcs, const Spacing& S)
-{
-    double t = 0.0;
-    for (const Piece& P : pcs) t += piece_length(P, S);
-    return t;
 }
 
 }  // namespace lasto
@@ -109,64 +46,9 @@ extern "C" lasto_status lasto_mesh_graded_1d(double lo, double hi, int n, const 
                                              double hmin, double hmax, double gmax, double hmin_step, double* x_out,
                                              double* g_out, double* hmin_used)
 {
-    if (!x_out || n < 3 || !(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi) || n_planes < 0 ||
-        (n_planes > 0 && !planes))
-        return fail(LASTO_ERR_ARG, "lasto_mesh_graded_1d: bad n, range or arrays");
-    if (n_planes == 0) {
-        for (int i = 0; i < n; ++i) x_out[i] = lo + (hi - lo) * (double)i / (double)(n - 1);
-        x_out[0] = lo;
-        x_out[n - 1] = hi;
-        if (g_out) *g_out = 1.0;
-        if (hmin_used) *hmin_used = (hi - lo) / (double)(n - 1);
-        return LASTO_OK;
-    }
-    if (!(hmin > 0.0) || hmax < hmin || !(gmax > 1.0))
-        return fail(LASTO_ERR_ARG, "lasto_mesh_graded_1d: need hmin > 0, hmax >= hmin, gmax > 1");
-    std::vector<double> pl(planes, planes + n_planes);
-    for (double p : pl)
-        if (!std::isfinite(p)) return fail(LASTO_ERR_ARG, "lasto_mesh_graded_1d: non-finite plane");
-    const std::vector<Piece> pcs = mesh_pieces(lo, hi, pl);
-    const double cells = (double)(n - 1);
-    Spacing S{1.0, hmin, hmax};
-    for (;;) {
-        S.g = 1.0;
-        if (total_length(pcs, S) <= cells) break;
-        S.g = gmax;
-        if (total_length(pcs, S) <= cells) {
-            double a = 1.0, b = gmax;
-            for (int it = 0; it < 200; ++it) {
-                const double m = 0.5 * (a + b);
-                if (m <= a || m >= b) break;
-                S.g = m;
-                if (total_length(pcs, S) > cells) a = m;
-                else b = m;
-            }
-            S.g = b;
-            break;
-        }
-        if (hmin_step <= 0.0 || S.hmin + hmin_step > hmax)
-            return fail(LASTO_ERR_ARG, "lasto_mesh_graded_1d: no growth factor <= gmax fits n nodes");
-        S.hmin += hmin_step;
-    }
-    const double T = total_length(pcs, S);
-    std::vector<double> start(pcs.size() + 1, 0.0);
-    for (size_t k = 0; k < pcs.size(); ++k) start[k + 1] = start[k] + piece_length(pcs[k], S);
-    x_out[0] = lo;
-    x_out[n - 1] = hi;
-    size_t k = 0;
-    for (int i = 1; i < n - 1; ++i) {
-        const double t = T * (double)i / (double)(n - 1);
-        while (k + 1 < pcs.size() && start[k + 1] < t) ++k;
-        const Piece& P = pcs[k];
-        const double pa = S.phi(std::fabs(P.a - P.plane));
-        double x;
-        if (P.plane <= P.a) x = P.plane + S.phi_inv(pa + (t - start[k]));
-        else x = P.plane - S.phi_inv(pa - (t - start[k]));
-        x_out[i] = std::min(std::max(x, P.a), P.b);
-    }
-    if (g_out) *g_out = S.g;
-    if (hmin_used) *hmin_used = S.hmin;
-    return LASTO_OK;
+    const char* err = lasto::mesh_graded_1d(lo, hi, n, planes, n_planes, hmin, hmax, gmax, hmin_step, x_out, g_out,
+                                            hmin_used);
+    return err ? fail(LASTO_ERR_ARG, std::string("lasto_mesh_graded_1d: ") + err) : LASTO_OK;
 }
 
 // Validate an atom table, copy it to the grid's staging buffer and derive the

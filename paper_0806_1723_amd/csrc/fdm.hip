@@ -21,6 +21,7 @@
 #include <cstring>
 #include <vector>
 
+#include "host.h"
 #include "internal.h"
 
 namespace lasto {
@@ -48,98 +49,6 @@ void free_fdm(lasto_grid g)
     if (f->blas) (void)rocblas_destroy_handle(f->blas);
     delete f;
     g->fdm = nullptr;
-}
-
-// Eigen-decomposition T = Q diag(a) Q^T of a symmetric tridiagonal matrix
-// (diagonal a[0..n-1], off-diagonal b[k] between k and k+1) by implicit
-// symmetric QR steps with the Wilkinson shift, as the bulge-chasing sweep of
-// Golub and Van Loan (Matrix Computations, Section 8.3): on the unreduced
-// block [lo, hi] ending at the bottom, a plane rotation on (lo, lo+1) set by
-// the first column of T - mu I starts a bulge, and rotations on (k, k+1) for
-// k = lo+1 .. hi-1 chase it down and out; the rotations are accumulated into
-// Q. An off-diagonal below eps (|a_k| + |a_k+1|) is set to zero, which splits
-// the matrix. On return a holds the eigenvalues and column k of Q
-// (q[i * n + k]) the eigenvector of a[k]. False if the iteration has not
-// converged after 40 n steps.
-static bool tridiagonal_eigen(int n, std::vector<double>& a, std::vector<double>& b, std::vector<double>& q)
-{
-    q.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) q[(size_t)i * n + i] = 1.0;
-    b.resize(std::max(n - 1, 0));
-    auto negligible = [&](int k) { return std::fabs(b[k]) <= DBL_EPSILON * (std::fabs(a[k]) + std::fabs(a[k + 1])); };
-    // plane rotation of columns k, k+1 of Q (Q <- Q R, R^T = [[c, s], [-s, c]])
-    auto rotate_q = [&](int k, double c, double s) {
-        for (int i = 0; i < n; ++i) {
-            double* row = &q[(size_t)i * n];
-            const double u = row[k], w = row[k + 1];
-            row[k] = c * u + s * w;
-            row[k + 1] = -s * u + c * w;
-        }
-    };
-    long steps = 0;
-    int hi = n - 1;
-    while (hi > 0) {
-        if (negligible(hi - 1)) {
-            b[hi - 1] = 0.0;
-            --hi;
-            continue;
-        }
-        int lo = hi - 1;
-        while (lo > 0 && !negligible(lo - 1)) --lo;
-        if (++steps > 40L * n) return false;
-        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer a[hi]
-        const double dl = 0.5 * (a[hi - 1] - a[hi]);
-        const double bb = b[hi - 1];
-        const double mu = a[hi] - bb * bb / (dl + std::copysign(std::hypot(dl, bb), dl));
-        double x = a[lo] - mu, y = b[lo], bulge = 0.0;
-        for (int k = lo; k < hi; ++k) {
-            // rotation (c, s) with -s x + c y = 0: it zeroes the bulge (or, at
-            // k = lo, the second entry of the shifted first column)
-            const double r = std::hypot(x, y);
-            const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? y / r : 0.0;
-            if (k > lo) b[k - 1] = r;
-            // the 2 x 2 block on (k, k+1) under R^T . R
-            const double ak = a[k], ak1 = a[k + 1], bk = b[k];
-            a[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
-            a[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
-            b[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
-            // the entry below the block becomes the new bulge
-            if (k + 1 < hi) {
-                bulge = s * b[k + 1];
-                b[k + 1] = c * b[k + 1];
-            }
-            rotate_q(k, c, s);
-            x = b[k];
-            y = bulge;
-        }
-    }
-    return true;
-}
-
-// 1-D operator of the interior nodes of coordinates x[0..n-1]:
-// (A u)_i = am_i (u_i-1 - u_i) + ap_i (u_i+1 - u_i), am = 1/(h_i-1 m_i),
-// ap = 1/(h_i m_i). Fills lam[n-2], S and Si [n-2][n-2] row-major.
-static bool axis_decomposition(const double* x, int n, double* lam, double* S, double* Si)
-{
-    const int m = n - 2;
-    std::vector<double> w(m), d(m), e(m), z;
-    for (int t = 0; t < m; ++t) {
-        const int i = t + 1;
-        const double hm = x[i] - x[i - 1], hp = x[i + 1] - x[i];
-        w[t] = 0.5 * (hm + hp);
-        d[t] = -(1.0 / (hm * w[t]) + 1.0 / (hp * w[t]));
-    }
-    for (int t = 0; t + 1 < m; ++t) e[t] = 1.0 / ((x[t + 2] - x[t + 1]) * std::sqrt(w[t] * w[t + 1]));
-    if (!tridiagonal_eigen(m, d, e, z)) return false;
-    for (int t = 0; t < m; ++t) lam[t] = d[t];
-    for (int i = 0; i < m; ++i) {
-        const double sq = std::sqrt(w[i]);
-        for (int k = 0; k < m; ++k) {
-            S[(size_t)i * m + k] = z[(size_t)i * m + k] / sq;    // M^-1/2 Q
-            Si[(size_t)k * m + i] = z[(size_t)i * m + k] * sq;   // Q^T M^1/2
-        }
-    }
-    return true;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -528,9 +437,12 @@ struct CoarseGemm {
     double* S64[3] = {nullptr, nullptr, nullptr};
     double* Si64[3] = {nullptr, nullptr, nullptr};
     double* lam64[3] = {nullptr, nullptr, nullptr};
+    float* S32[3] = {nullptr, nullptr, nullptr};
+    float* Si32[3] = {nullptr, nullptr, nullptr};
     float* lam32[3] = {nullptr, nullptr, nullptr};
     double* buf64[2] = {nullptr, nullptr};
     float* buf32[2] = {nullptr, nullptr};
+    rocblas_handle blas = nullptr;   // the FP32 contractions
 };
 
 void free_coarse_gemm(lasto_grid g)
@@ -541,12 +453,15 @@ void free_coarse_gemm(lasto_grid g)
         (void)hipFree(c->S64[d]);
         (void)hipFree(c->Si64[d]);
         (void)hipFree(c->lam64[d]);
+        (void)hipFree(c->S32[d]);
+        (void)hipFree(c->Si32[d]);
         (void)hipFree(c->lam32[d]);
     }
     for (int b = 0; b < 2; ++b) {
         (void)hipFree(c->buf64[b]);
         (void)hipFree(c->buf32[b]);
     }
+    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     delete c;
     g->cg = nullptr;
 }
@@ -593,6 +508,8 @@ lasto_status coarse_gemm_init(lasto_grid g)
         e = upload(&c->S64[d], S);
         if (e == hipSuccess) e = upload(&c->Si64[d], Si);
         if (e == hipSuccess) e = upload(&c->lam64[d], lam);
+        if (e == hipSuccess) e = upload(&c->S32[d], S);
+        if (e == hipSuccess) e = upload(&c->Si32[d], Si);
         if (e == hipSuccess) e = upload(&c->lam32[d], lam);
     }
     const size_t cells = (size_t)c->m[0] * c->m[1] * c->m[2] * c->nb;
@@ -603,6 +520,12 @@ lasto_status coarse_gemm_init(lasto_grid g)
     if (e != hipSuccess) {
         free_coarse_gemm(g);
         return fail(LASTO_ERR_ALLOC, std::string("lasto_poisson_solve: coarse-level tables: ") + hipGetErrorString(e));
+    }
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
+        rocblas_set_stream(c->blas, g->stream) != rocblas_status_success ||
+        rocblas_set_atomics_mode(c->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
+        free_coarse_gemm(g);
+        return fail(LASTO_ERR_HIP, "lasto_poisson_solve: rocBLAS handle");
     }
     return LASTO_OK;
 }
@@ -641,85 +564,117 @@ __global__ __launch_bounds__(256) void k_divide_dense(T* __restrict__ d, const T
 // the contracted axis fastest); the output is out[r][line] = sum_k P[r][k]
 // in[line][k], the new axis slowest. Three of them take [z][y][x] to
 // [x'][z][y], [y'][x'][z] and [z'][y'][x'] (the original order), three more
-// back to [z][y][x]. A workgroup computes 64 rows r by 32 lines as 4 x 2
-// tiles of v_mfma_f64_16x16x4f64 (A 16 x 4 from lane (row = lane % 16,
+// back to [z][y][x]. Each wave computes one 16 x 16 tile (16 rows r by 16
+// lines) by v_mfma_f64_16x16x4f64 (A 16 x 4 from lane (row = lane % 16,
 // k = lane / 16), B 4 x 16 from lane (k = lane / 16, col = lane % 16), D with
-// lane holding rows lane / 16 + 4 j of column lane % 16), two tiles per wave,
-// over chunks of 64 k staged in LDS (P's rows and the block's lines read as
-// contiguous runs; rows padded to an odd length so the 16 rows a wave reads
-// fall on distinct banks). FP32 levels are read and written in FP32 and
-// contracted in FP64. The summation order is fixed: the same bits every time.
-constexpr int CT_RB = 64, CT_LB = 32, CT_KC = 64, CT_LD = CT_KC + 1, CT_NT = 256;
+// lane holding rows lane / 16 + 4 j of column lane % 16). The operands come
+// straight from memory (P, a few tens of KB, stays in the L2; each lane's
+// line is a contiguous run): a workgroup of small waves is latency-bound, so
+// for m <= 32 NCH every load of the whole k range is issued before the first
+// matrix-core step (NCH = 0: chunks of 32 k in turn). The summation order is
+// fixed: the same bits every time.
+constexpr int CT_NT = 256;
 typedef double ct_dbl4 __attribute__((ext_vector_type(4)));
 
-template <typename T>
+template <typename T, int NCH>
 __global__ __launch_bounds__(CT_NT) void k_contract(const double* __restrict__ P, const T* __restrict__ in,
-                                                    T* __restrict__ out, int m, int L, int row_blocks,
-                                                    int line_blocks)
+                                                    T* __restrict__ out, int m, int L, int rtiles, int ctiles)
 {
-    __shared__ double As[CT_RB * CT_LD];
-    __shared__ double Bs[CT_LB * CT_LD];
-    const int b = blockIdx.x;
-    const int copy = b / (row_blocks * line_blocks);
-    const int rb = (b / line_blocks) % row_blocks, lb = b % line_blocks;
-    const int r0 = rb * CT_RB, l0 = lb * CT_LB;
-    const size_t per = (size_t)m * L;
-    const T* __restrict__ inc = in + copy * per;
-    T* __restrict__ outc = out + copy * per;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int KS = 8;                          // k-steps of 4 per chunk
+    constexpr int NS = NCH > 0 ? NCH * KS : KS;    // steps held in registers at once
+    const int lane = threadIdx.x & 63;
+    const int task = blockIdx.x * (CT_NT / 64) + (threadIdx.x >> 6);   // (column tile, row tile) of copy blockIdx.y
+    if (task >= rtiles * ctiles) return;   // the last workgroup's spare waves
+    const int rt = task % rtiles, ct = task / rtiles;
     const int p16 = lane & 15, grp = lane >> 4;
-    // this wave's two tiles: row tile `wave`, column tiles 0 and 1
-    ct_dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < m; k0 += CT_KC) {
-        const int kn = min(CT_KC, m - k0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < CT_RB * CT_KC; e += CT_NT) {
-            const int r = e / CT_KC, k = e % CT_KC;
-            As[r * CT_LD + k] = (r0 + r < m && k < kn) ? P[(size_t)(r0 + r) * m + k0 + k] : 0.0;
+    const size_t per = (size_t)m * L;
+    const T* __restrict__ inc = in + blockIdx.y * per;
+    T* __restrict__ outc = out + blockIdx.y * per;
+    const int r = rt * 16 + p16, ln = ct * 16 + p16;
+    const bool rok = r < m, lok = ln < L;
+    const double* __restrict__ prow = P + (size_t)(rok ? r : 0) * m;
+    const T* __restrict__ il = inc + (size_t)(lok ? ln : 0) * m;
+    ct_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int kend = NCH > 0 ? 4 * NS : m;
+    for (int k0 = 0; k0 < kend; k0 += 4 * NS) {
+        double a[NS], bv[NS];
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const int k = k0 + 4 * st + grp;
+            const bool kok = k < m;
+            const int kk = kok ? k : 0;
+            a[st] = (rok && kok) ? prow[kk] : 0.0;
+            bv[st] = (lok && kok) ? (double)il[kk] : 0.0;
         }
-        for (int e = threadIdx.x; e < CT_LB * CT_KC; e += CT_NT) {
-            const int l = e / CT_KC, k = e % CT_KC;
-            Bs[l * CT_LD + k] = (l0 + l < L && k < kn) ? (double)inc[(size_t)(l0 + l) * m + k0 + k] : 0.0;
-        }
-        __syncthreads();
-        const double* arow = As + (wave * 16 + p16) * CT_LD + grp;
-        const double* b0 = Bs + p16 * CT_LD + grp;
-        const double* b1 = Bs + (16 + p16) * CT_LD + grp;
-        for (int ks = 0; ks < kn; ks += 4) {
-            const double a = arow[ks];
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0[ks], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1[ks], acc1, 0, 0, 0);
-        }
+#pragma unroll
+        for (int st = 0; st < NS; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], bv[st], acc, 0, 0, 0);
     }
+    if (!lok) return;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int r = r0 + wave * 16 + grp + 4 * j;
-        if (r >= m) continue;
-        const int la = l0 + p16, lb2 = l0 + 16 + p16;
-        if (la < L) outc[(size_t)r * L + la] = (T)acc0[j];
-        if (lb2 < L) outc[(size_t)r * L + lb2] = (T)acc1[j];
+        const int row = rt * 16 + grp + 4 * j;
+        if (row < m) outc[(size_t)row * L + ln] = (T)acc[j];
     }
 }
 
 template <typename T>
-static hipError_t contract_rot(const CoarseGemm* c, int m, const double* P, const T* in, T* out, hipStream_t s)
+static hipError_t contract_rot_mfma(const CoarseGemm* c, int m, const double* P, const T* in, T* out, hipStream_t s)
 {
     const int per = c->m[0] * c->m[1] * c->m[2];
     const int L = per / m;
-    const int row_blocks = (m + CT_RB - 1) / CT_RB, line_blocks = (L + CT_LB - 1) / CT_LB;
-    hipLaunchKernelGGL(k_contract<T>, dim3((unsigned)(row_blocks * line_blocks * c->nb)), dim3(CT_NT), 0, s, P, in,
-                       out, m, L, row_blocks, line_blocks);
+    const int rtiles = (m + 15) / 16, ctiles = (L + 15) / 16;
+    const int waves = rtiles * ctiles;   // per copy
+    const dim3 grid((unsigned)((waves + CT_NT / 64 - 1) / (CT_NT / 64)), (unsigned)c->nb);
+    const int nch = (m + 31) / 32;
+    switch (nch) {
+        case 1: hipLaunchKernelGGL((k_contract<T, 1>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 2: hipLaunchKernelGGL((k_contract<T, 2>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 3: hipLaunchKernelGGL((k_contract<T, 3>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 4: hipLaunchKernelGGL((k_contract<T, 4>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        default: hipLaunchKernelGGL((k_contract<T, 0>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+    }
     return hipGetLastError();
+}
+
+// Which contraction each precision takes (measured at 90^3, one right-hand
+// side, 7744 x 88 x 88 per contraction): FP64 on the matrix cores above,
+// 13.5 us against rocBLAS dgemm's 19.5 us; FP32 through rocBLAS sgemm
+// (strided batch over the copies, atomics off, so the bits repeat), 6.9 us
+// against 15.9 us for the same matrix-core kernel reading FP32 (its 16-row
+// by 16-line tiles gather each lane's operands from 16 lines and are bound by
+// the requests they issue, where sgemm's 128 x 128 LDS tiles are not).
+static hipError_t contract_rot(const CoarseGemm* c, int m, const double* const* P64, int d, const double* in,
+                               double* out, hipStream_t s)
+{
+    return contract_rot_mfma<double>(c, m, P64[d], in, out, s);
+}
+
+static hipError_t contract_rot(const CoarseGemm* c, int m, const float* const* P32, int d, const float* in, float* out,
+                               hipStream_t)
+{
+    const int per = c->m[0] * c->m[1] * c->m[2];
+    const int L = per / m;
+    const float one = 1.0f, zero = 0.0f;
+    // column-major C (L x m) = A^T B, A the input (m x L), B the row-major P
+    // read as column-major (B(k, r) = P[r][k]): out[r][line] = sum_k P[r][k] in[line][k]
+    const rocblas_status st = rocblas_sgemm_strided_batched(c->blas, rocblas_operation_transpose,
+                                                            rocblas_operation_none, L, m, m, &one, in, m, per, P32[d], m,
+                                                            0, &zero, out, L, per, c->nb);
+    return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
 }
 
 // (the axis tables are FP64 in both precisions; the eigenvalue sums of the
 // division are the cycle's precision)
 template <typename T> struct CgTab;
 template <> struct CgTab<double> {
+    static double* const* S(const CoarseGemm* c) { return c->S64; }
+    static double* const* Si(const CoarseGemm* c) { return c->Si64; }
     static double* const* lam(const CoarseGemm* c) { return c->lam64; }
     static double* buf(const CoarseGemm* c, int b) { return c->buf64[b]; }
 };
 template <> struct CgTab<float> {
+    static float* const* S(const CoarseGemm* c) { return c->S32; }
+    static float* const* Si(const CoarseGemm* c) { return c->Si32; }
     static float* const* lam(const CoarseGemm* c) { return c->lam32; }
     static float* buf(const CoarseGemm* c, int b) { return c->buf32[b]; }
 };
@@ -736,15 +691,17 @@ lasto_status coarse_gemm_solve(lasto_grid g, const T* f, T* u, hipStream_t s)
     auto lam = CgTab<T>::lam(c);
     hipLaunchKernelGGL(k_split_to_dense<T>, dim3(blocks), dim3(256), 0, s, V, f, b0);
     LASTO_LAUNCH_CHECK("k_split_to_dense");
-    LASTO_HIP(contract_rot<T>(c, c->m[0], c->Si64[0], b0, b1, s));
-    LASTO_HIP(contract_rot<T>(c, c->m[1], c->Si64[1], b1, b0, s));
-    LASTO_HIP(contract_rot<T>(c, c->m[2], c->Si64[2], b0, b1, s));
+    auto Si = CgTab<T>::Si(c);
+    auto S = CgTab<T>::S(c);
+    LASTO_HIP(contract_rot(c, c->m[0], Si, 0, b0, b1, s));
+    LASTO_HIP(contract_rot(c, c->m[1], Si, 1, b1, b0, s));
+    LASTO_HIP(contract_rot(c, c->m[2], Si, 2, b0, b1, s));
     hipLaunchKernelGGL(k_divide_dense<T>, dim3(blocks), dim3(256), 0, s, b1, lam[0], lam[1], lam[2], c->m[0],
                        c->m[1], c->m[2], n);
     LASTO_LAUNCH_CHECK("k_divide_dense");
-    LASTO_HIP(contract_rot<T>(c, c->m[0], c->S64[0], b1, b0, s));
-    LASTO_HIP(contract_rot<T>(c, c->m[1], c->S64[1], b0, b1, s));
-    LASTO_HIP(contract_rot<T>(c, c->m[2], c->S64[2], b1, b0, s));
+    LASTO_HIP(contract_rot(c, c->m[0], S, 0, b1, b0, s));
+    LASTO_HIP(contract_rot(c, c->m[1], S, 1, b0, b1, s));
+    LASTO_HIP(contract_rot(c, c->m[2], S, 2, b1, b0, s));
     hipLaunchKernelGGL(k_dense_to_split<T>, dim3(blocks), dim3(256), 0, s, V, b0, u);
     LASTO_LAUNCH_CHECK("k_dense_to_split");
     return LASTO_OK;

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "host.h"
 #include "internal.h"
 
 namespace lasto {
@@ -11,40 +12,6 @@ namespace lasto {
 hipError_t init_harmonic_constants();
 template <typename T>
 hipError_t launch_fill_zero(T* a, size_t n, hipStream_t s);
-
-// Pair-merging coarsening of one axis: walking up from node 0, the pair of
-// cells [x_i, x_{i+2}] merges (node i+1 dropped) when x_{i+2} - x_i <= tau.
-// An axis with at most 3 nodes is kept as it is.
-static std::vector<int> coarsen_axis(const std::vector<double>& x, double tau)
-{
-    const int n = (int)x.size();
-    std::vector<int> keep;
-    keep.push_back(0);
-    if (n <= 3) {
-        for (int t = 1; t < n; ++t) keep.push_back(t);
-        return keep;
-    }
-    int i = 0;
-    while (i < n - 1) {
-        if (i + 2 <= n - 1 && x[i + 2] - x[i] <= tau) {
-            keep.push_back(i + 2);
-            i += 2;
-        } else {
-            keep.push_back(i + 1);
-            i += 1;
-        }
-    }
-    return keep;
-}
-
-static void dual_widths(const std::vector<double>& x, std::vector<double>& m)
-{
-    const int n = (int)x.size();
-    m.assign(n, 0.0);
-    m[0] = 0.5 * (x[1] - x[0]);
-    m[n - 1] = 0.5 * (x[n - 1] - x[n - 2]);
-    for (int i = 1; i < n - 1; ++i) m[i] = 0.5 * (x[i + 1] - x[i - 1]);
-}
 
 // Per-axis tables of one copy: stencil coefficients, dual widths,
 // coordinates, restriction (rf, rw) and prolongation (pc, pw from the finer
@@ -315,6 +282,8 @@ static void free_grid(lasto_grid g)
     for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : g->ph_ev)
         if (e) (void)hipEventDestroy(e);
+    for (void* p : g->lg_alloc) (void)hipFree(p);
+    g->lg_alloc.clear();
     g->prof_ev.clear();
 }
 
@@ -594,5 +563,22 @@ extern "C" lasto_status lasto_grid_level_shape(lasto_grid g, int level, int* out
     if (!g || !out3) return fail(LASTO_ERR_ARG, "lasto_grid_level_shape: NULL argument");
     if (level < 0 || level >= g->nlev) return fail(LASTO_ERR_ARG, "lasto_grid_level_shape: level out of range");
     for (int d = 0; d < 3; ++d) out3[d] = g->lev[level].n[d];
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_grid_level_nodes(lasto_grid g, int level, int* ix, int* iy, int* iz)
+{
+    if (!g || !ix || !iy || !iz) return fail(LASTO_ERR_ARG, "lasto_grid_level_nodes: NULL argument");
+    if (level < 0 || level >= g->nlev) return fail(LASTO_ERR_ARG, "lasto_grid_level_nodes: level out of range");
+    int* out[3] = {ix, iy, iz};
+    for (int d = 0; d < 3; ++d) {
+        const std::vector<double>& xf = g->lev[0].hx[d];
+        const std::vector<double>& xc = g->lev[level].hx[d];
+        for (size_t I = 0; I < xc.size(); ++I) {
+            const auto it = std::lower_bound(xf.begin(), xf.end(), xc[I]);
+            if (it == xf.end() || *it != xc[I]) return fail(LASTO_ERR_STATE, "lasto_grid_level_nodes: not nested");
+            out[d][I] = (int)(it - xf.begin());
+        }
+    }
     return LASTO_OK;
 }

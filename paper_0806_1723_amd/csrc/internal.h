@@ -293,6 +293,12 @@ struct lasto_grid_s {
     double alg_bytes = 0.0;
     // phase stamps of a solve (start, faces done, guess done, end)
     hipEvent_t ph_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // tables of the learned guess on a coarse level (lg_level -1: none built)
+    int lg_level = -1;
+    const int* lg_idx[3] = {nullptr, nullptr, nullptr};     // fine index of each coarse node
+    const int* lg_pi[3] = {nullptr, nullptr, nullptr};      // coarse interval of each fine node
+    const double* lg_pw[3] = {nullptr, nullptr, nullptr};   // its linear weight
+    std::vector<void*> lg_alloc;
     // the current solve's learned coarse correction (lc_net NULL: none)
     lasto_net lc_net = nullptr;
     int lc_level = -1;
@@ -439,6 +445,9 @@ lasto_status net_guess_forward(lasto_grid g, lasto_net n, const double* rho, con
                                double* out_scale, double rho_mul = 1.0);
 lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x,
                                 double rho_mul);
+// v += the learned correction of one right-hand side (finest-level net, or a
+// net on a coarse level with its output interpolated to the finest)
+lasto_status net_guess_apply(lasto_grid g, lasto_net n, const double* rho, double* v);
 // learned coarse correction at level l of a cycle: u = the net's proposal for
 // A_l u = f if it lowers the residual, else 0 (r: the level's residual scratch,
 // zero again on return); g->lc_net must be set

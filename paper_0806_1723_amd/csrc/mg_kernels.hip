@@ -309,12 +309,6 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
         if (!(t < nb && j <= L.ny - 2 && m0 <= (nx - 2) / 2)) continue;
         const int k0 = 1 + (t / (nbx * nby)) * kc;
         const int k1 = min(k0 + kc, nz - 1);
-        // Mirrored march: even plane chunks walk up (D = 1), odd ones down, so
-        // the plane two neighbouring chunks both read (the halo of one, the
-        // last or first plane of the other) is read by both at the same time,
-        // at the start or at the end of both marches, and the second read
-        // finds it in the L2.
-        const int D = ((t / (nbx * nby)) & 1) ? -1 : 1;
         const size_t row = (size_t)j * W + m0;
         // both parities' x coefficients, picked per plane by select (named
         // values, not an array indexed at run time, so they stay in registers)
@@ -346,15 +340,13 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
             if (NEED_U) z = *(const VT*)(uo + (size_t)k * plane + row);
             return z;
         };
-        // plane k from its operands and the z neighbours: zb behind the
-        // march (plane k - D), zc, za ahead of it (plane k + D)
-        auto compute = [&](int k, const HalfOps<T>& q, const VT& zb, const VT& zc, const VT& za) {
+        // plane k from its operands and the z neighbours (zm, zc, zp)
+        auto compute = [&](int k, const HalfOps<T>& q, const VT& zm, const VT& zc, const VT& zp) {
             const int o = (c + j + k) & 1;
             const int i0 = o + 2 * m0;
             const bool okz = L.zint[k];   // planes next to another copy of a batch are faces
             const VT cxm = o ? axm1 : axm0, cxp = o ? axp1 : axp0;
             const T czm = amz[k], czp = apz[k];
-            const T czb = D > 0 ? czm : czp, cza = D > 0 ? czp : czm;
             VT r;
             bool ok[VEC];
 #pragma unroll
@@ -369,7 +361,7 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                     if (NEED_U) {
                         sum = cxm[e] * xl + cxp[e] * xr;
                         sum += cym * q.ym[e] + cyp * q.yp[e];
-                        sum += czb * zb[e] + cza * za[e];
+                        sum += czm * zm[e] + czp * zp[e];
                     }
                     r[e] = (sum - bscale * q.fv[e]) * recip(d);
                 } else {
@@ -377,7 +369,7 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                     const T c0 = q.cv[e];
                     T a = cxm[e] * (xl - c0) + cxp[e] * (xr - c0);
                     a += cym * (q.ym[e] - c0) + cyp * (q.yp[e] - c0);
-                    a += czb * (zb[e] - c0) + cza * (za[e] - c0);
+                    a += czm * (zm[e] - c0) + czp * (zp[e] - c0);
                     r[e] = MODE == HM_RESID ? bscale * q.fv[e] - a : a;
                 }
             }
@@ -404,29 +396,20 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                 }
             }
         };
-        // Two planes per step with alternating operand sets (A: even steps,
+        // two planes per step with alternating operand sets (A: even steps,
         // B: odd), so the next plane's loads are in flight while one plane is
-        // computed and no register copies wait on them. Mirrored march: even
-        // plane chunks walk up, odd ones down, so the plane two neighbouring
-        // chunks both read (the halo of one, the last or first plane of the
-        // other) is read by both at the same time, at the start or at the end
-        // of both marches, and the second read finds it in the L2.
-        const int ks = D > 0 ? k0 : k1 - 1;
-        // a plane inside the chunk (loads past its end are not used)
-        auto inchunk = [&](int k) { return min(max(k, k0), k1 - 1); };
-        auto clampz = [&](int k) { return min(max(k, 0), nz - 1); };
+        // computed and no register copies wait on them
         HalfOps<T> A{}, B{};
-        // queue: z0 = plane k - D, z1 = plane k, z2 = plane k + D
-        VT z0 = load_z(ks - D), z1 = load_z(ks), z2 = load_z(ks + D);
-        load_plane(ks, A);
-        for (int k = ks; D > 0 ? k < k1 : k >= k0; k += 2 * D) {
-            load_plane(inchunk(k + D), B);
-            const VT z3 = load_z(clampz(k + 2 * D));
+        VT z0 = load_z(k0 - 1), z1 = load_z(k0), z2 = load_z(k0 + 1);
+        load_plane(k0, A);
+        for (int k = k0; k < k1; k += 2) {
+            load_plane(min(k + 1, k1 - 1), B);
+            const VT z3 = load_z(min(k + 2, nz - 1));
             compute(k, A, z0, z1, z2);
-            if (D > 0 ? k + 1 < k1 : k - 1 >= k0) {
-                load_plane(inchunk(k + 2 * D), A);
-                const VT z4 = load_z(clampz(k + 3 * D));
-                compute(k + D, B, z1, z2, z3);
+            if (k + 1 < k1) {
+                load_plane(min(k + 2, k1 - 1), A);
+                const VT z4 = load_z(min(k + 3, nz - 1));
+                compute(k + 1, B, z1, z2, z3);
                 z0 = z2;
                 z1 = z3;
                 z2 = z4;
@@ -1974,3 +1957,55 @@ hipError_t launch_flex_beta(double* scal, int i_rz_old, int i_pq, int i_zq, int 
 }
 
 }  // namespace lasto
+
+// ------------------------------------------------- streaming ceiling probes
+// The rate a plain stream reaches on this device, the ceiling the stencils
+// are measured against: dst = src (one read, one write) or dst = a + b (two
+// reads, one write, the half-sweep's mix), 16-byte accesses, four per thread
+// in flight before any store, grid-stride over resident workgroups.
+namespace lasto {
+
+typedef double sp_dbl2 __attribute__((ext_vector_type(2)));
+
+template <int READS>
+__global__ __launch_bounds__(256) void k_stream(const sp_dbl2* __restrict__ a, const sp_dbl2* __restrict__ b,
+                                                sp_dbl2* __restrict__ d, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    for (; t + 3 * stride < n; t += 4 * stride) {
+        sp_dbl2 x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = a[t + u * stride];
+        if (READS == 2) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) y[u] = b[t + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[t + u * stride] = READS == 2 ? x[u] + y[u] : x[u];
+    }
+    for (; t < n; t += stride) d[t] = READS == 2 ? a[t] + b[t] : a[t];
+}
+
+}  // namespace lasto
+
+// dst = a (b NULL) or dst = a + b over `bytes` (a multiple of 16) of FP64 data
+extern "C" lasto_status lasto_stream_probe(const double* a, const double* b, double* dst, size_t bytes,
+                                           void* hip_stream)
+{
+    if (!a || !dst || bytes % 16 != 0) return lasto::fail(LASTO_ERR_ARG, "lasto_stream_probe: NULL or bytes % 16");
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return lasto::fail(LASTO_ERR_HIP, "lasto_stream_probe: device query");
+    const size_t n = bytes / 16;
+    const unsigned grid = (unsigned)std::max(8, cus * 8);
+    hipStream_t s = (hipStream_t)hip_stream;
+    typedef lasto::sp_dbl2 V;
+    if (b)
+        hipLaunchKernelGGL(lasto::k_stream<2>, dim3(grid), dim3(256), 0, s, (const V*)a, (const V*)b, (V*)dst, n);
+    else
+        hipLaunchKernelGGL(lasto::k_stream<1>, dim3(grid), dim3(256), 0, s, (const V*)a, (const V*)nullptr, (V*)dst, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return lasto::fail(LASTO_ERR_HIP, std::string("lasto_stream_probe: ") + hipGetErrorString(e));
+    return LASTO_OK;
+}

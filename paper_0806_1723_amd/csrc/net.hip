@@ -17,6 +17,7 @@
 // Parameters live as FP32 masters in one flat vector (per convolution
 // W[27][cin][cout] then b[cout]; then the head w[c0], b); Adam updates them and
 // re-packs the BF16 copies the matrix-core kernels read.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -395,15 +396,149 @@ __global__ __launch_bounds__(128) void k_features(LevelView L, const double* __r
     *(uint4*)(x + e * 8) = o;
 }
 
+// The learned guess on a coarse level l of the hierarchy: the features are
+// taken at that level's nodes (every coarse node is a fine node: injection of
+// rho and v, the level's own dual widths), and the net's output, a correction
+// at the coarse nodes, is brought to the finest level by linear
+// interpolation in physical coordinates along each axis (the multigrid's
+// prolongation composed down the levels). Tables per axis: the fine index of
+// each coarse node, and for each fine node its coarse interval and weight.
+__global__ __launch_bounds__(128) void k_features_inject(LevelView F, LevelView C, const int* __restrict__ ix,
+                                                         const int* __restrict__ iy, const int* __restrict__ iz,
+                                                         const double* __restrict__ rho, const double* __restrict__ v,
+                                                         double s_rho, double s_pot, float h_ref,
+                                                         uint16_t* __restrict__ x)
+{
+    const int I = blockIdx.x * 128 + threadIdx.x, J = blockIdx.y, K = blockIdx.z;
+    if (I >= C.nx) return;
+    const size_t e = ((size_t)K * C.ny + J) * C.nx + I;
+    const size_t f = ((size_t)iz[K] * F.ny + iy[J]) * F.nx + ix[I];
+    const bool face = I == 0 || J == 0 || K == 0 || I == C.nx - 1 || J == C.ny - 1 || K == C.nz - 1;
+    const float inv = 1.0f / h_ref;
+    uint4 o;
+    o.x = (uint32_t)f2bf((float)(rho[f] * s_rho)) | ((uint32_t)f2bf(logf((float)C.ax[0].m[I] * inv)) << 16);
+    o.y = (uint32_t)f2bf(logf((float)C.ax[1].m[J] * inv)) | ((uint32_t)f2bf(logf((float)C.ax[2].m[K] * inv)) << 16);
+    o.z = (uint32_t)f2bf((float)(v[f] * s_pot)) | ((uint32_t)f2bf(face ? 1.0f : 0.0f) << 16);
+    o.w = 0;
+    *(uint4*)(x + e * 8) = o;
+}
+
+// v += s * (linear interpolation of y from the coarse nodes), interior fine nodes
+__global__ __launch_bounds__(128) void k_prolong_add_nat(LevelView F, int cnx, int cny, const int* __restrict__ px,
+                                                         const double* __restrict__ wx, const int* __restrict__ py,
+                                                         const double* __restrict__ wy, const int* __restrict__ pz,
+                                                         const double* __restrict__ wz, const float* __restrict__ y,
+                                                         double s, double* __restrict__ v)
+{
+    const int i = blockIdx.x * 128 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i < 1 || i > F.nx - 2 || j < 1 || j > F.ny - 2 || k < 1 || k > F.nz - 2) return;
+    const int I = px[i], J = py[j], K = pz[k];
+    const double ax = wx[i], ay = wy[j], az = wz[k];
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const float* row = y + ((size_t)(K + c) * cny + (J + b)) * cnx + I;
+            const double w = (c ? az : 1.0 - az) * (b ? ay : 1.0 - ay);
+            acc += w * ((1.0 - ax) * (double)row[0] + ax * (double)row[1]);
+        }
+    v[((size_t)k * F.ny + j) * F.nx + i] += s * acc;
+}
+
+// the level whose node grid the net runs on (0: the finest), -1 if none
+static int net_level(lasto_grid g, lasto_net n)
+{
+    for (int l = 0; l < g->nlev; ++l) {
+        const Level& L = g->lev[l];
+        if (L.n[0] == n->dim[0][0] && L.n[1] == n->dim[0][1] && L.n[2] == n->dim[0][2]) return l;
+    }
+    return -1;
+}
+
+// device tables of level l against the finest level (built once per level)
+static lasto_status coarse_guess_tables(lasto_grid g, int l)
+{
+    if (g->lg_level == l) return LASTO_OK;
+    for (void* p : g->lg_alloc) (void)hipFree(p);
+    g->lg_alloc.clear();
+    g->lg_level = -1;
+    const Level& F = g->lev[0];
+    const Level& C = g->lev[l];
+    for (int d = 0; d < 3; ++d) {
+        const std::vector<double>& xf = F.hx[d];
+        const std::vector<double>& xc = C.hx[d];
+        const int nf = (int)xf.size(), nc = (int)xc.size();
+        std::vector<int> idx(nc), pi(nf);
+        std::vector<double> pw(nf);
+        for (int I = 0; I < nc; ++I) {
+            const auto it = std::lower_bound(xf.begin(), xf.end(), xc[I]);
+            if (it == xf.end() || *it != xc[I]) return fail(LASTO_ERR_STATE, "lasto_net: a coarse node is not a fine node");
+            idx[I] = (int)(it - xf.begin());
+        }
+        for (int i = 0, I = 0; i < nf; ++i) {
+            while (I + 2 < nc && xc[I + 1] <= xf[i]) ++I;
+            pi[i] = I;
+            pw[i] = (xf[i] - xc[I]) / (xc[I + 1] - xc[I]);
+        }
+        int* d_idx = nullptr;
+        int* d_pi = nullptr;
+        double* d_pw = nullptr;
+        if (hipMalloc(&d_idx, sizeof(int) * nc) != hipSuccess || hipMalloc(&d_pi, sizeof(int) * nf) != hipSuccess ||
+            hipMalloc(&d_pw, sizeof(double) * nf) != hipSuccess)
+            return fail(LASTO_ERR_ALLOC, "lasto_net: coarse guess tables");
+        g->lg_alloc.push_back(d_idx);
+        g->lg_alloc.push_back(d_pi);
+        g->lg_alloc.push_back(d_pw);
+        NCHK(hipMemcpy(d_idx, idx.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
+        NCHK(hipMemcpy(d_pi, pi.data(), sizeof(int) * nf, hipMemcpyHostToDevice));
+        NCHK(hipMemcpy(d_pw, pw.data(), sizeof(double) * nf, hipMemcpyHostToDevice));
+        g->lg_idx[d] = d_idx;
+        g->lg_pi[d] = d_pi;
+        g->lg_pw[d] = d_pw;
+    }
+    g->lg_level = l;
+    return LASTO_OK;
+}
+
 lasto_status net_features_async(lasto_grid g, lasto_net n, const double* rho, const double* v, uint16_t* x,
                                 double rho_mul)
 {
     const LevelView& L = g->cview;   // one right-hand side of a batch
-    if (L.nx != n->dim[0][0] || L.ny != n->dim[0][1] || L.nz != n->dim[0][2])
-        return fail(LASTO_ERR_ARG, "lasto_net: the net's grid does not match the grid's finest level");
-    hipLaunchKernelGGL(k_features, dim3((L.nx + 127) / 128, L.ny, L.nz), dim3(128), 0, g->stream, L, rho, v,
-                       n->cfg.rho_scale * rho_mul, n->cfg.pot_scale, (float)n->cfg.h_ref, x);
+    const int l = net_level(g, n);
+    if (l < 0) return fail(LASTO_ERR_ARG, "lasto_net: the net's grid matches no level of the grid");
+    if (l == 0) {
+        hipLaunchKernelGGL(k_features, dim3((L.nx + 127) / 128, L.ny, L.nz), dim3(128), 0, g->stream, L, rho, v,
+                           n->cfg.rho_scale * rho_mul, n->cfg.pot_scale, (float)n->cfg.h_ref, x);
+    } else {
+        if (lasto_status e = coarse_guess_tables(g, l); e != LASTO_OK) return e;
+        LevelView C = g->lev[l].view;
+        C.nz = C.nzc;   // one copy
+        hipLaunchKernelGGL(k_features_inject, dim3((C.nx + 127) / 128, C.ny, C.nz), dim3(128), 0, g->stream, L, C,
+                           g->lg_idx[0], g->lg_idx[1], g->lg_idx[2], rho, v, n->cfg.rho_scale * rho_mul,
+                           n->cfg.pot_scale, (float)n->cfg.h_ref, x);
+    }
     NCHK(hipGetLastError());
+    return LASTO_OK;
+}
+
+// the learned correction of one right-hand side: v += out_scale net(features(rho, v)),
+// on the finest level or, for a net on a coarse level, interpolated from it
+lasto_status net_guess_apply(lasto_grid g, lasto_net n, const double* rho, double* v)
+{
+    const float* y = nullptr;
+    double out_scale = 0.0;
+    if (lasto_status st = net_guess_forward(g, n, rho, v, &y, &out_scale); st != LASTO_OK) return st;
+    const LevelView& L = g->cview;
+    const int l = net_level(g, n);
+    if (l == 0) {
+        NCHK(launch_add_f32_nat(L, v, y, out_scale, g->stream));
+    } else {
+        hipLaunchKernelGGL(k_prolong_add_nat, dim3((L.nx + 127) / 128, L.ny, L.nz), dim3(128), 0, g->stream, L,
+                           n->dim[0][0], n->dim[0][1], g->lg_pi[0], g->lg_pw[0], g->lg_pi[1], g->lg_pw[1],
+                           g->lg_pi[2], g->lg_pw[2], y, out_scale, v);
+        NCHK(hipGetLastError());
+    }
     return LASTO_OK;
 }
 

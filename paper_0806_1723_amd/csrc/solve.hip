@@ -816,13 +816,8 @@ static lasto_status judge_batch(lasto_grid g, lasto_net n, const double* rho, do
     double* keep_learned = g->lscr[LS_LEARNED];
     if (lasto_status e = batch_norms(g, rho, v, 1, S_BR0); e != LASTO_OK) return e;
     HIPCHK(hipMemcpyAsync(keep_plain, v, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
-    for (int b = 0; b < nb; ++b) {
-        const float* y = nullptr;
-        double out_scale = 0.0;
-        if (lasto_status e = net_guess_forward(g, n, rho + b * N, v + b * N, &y, &out_scale); e != LASTO_OK)
-            return e;
-        HIPCHK(launch_add_f32_nat(g->cview, v + b * N, y, out_scale, s));
-    }
+    for (int b = 0; b < nb; ++b)
+        if (lasto_status e = net_guess_apply(g, n, rho + b * N, v + b * N); e != LASTO_OK) return e;
     if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
     if (lasto_status e = batch_norms(g, rho, v, 0, S_BRR); e != LASTO_OK) return e;
     HIPCHK(hipMemcpyAsync(keep_learned, v, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));

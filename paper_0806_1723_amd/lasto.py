@@ -114,11 +114,12 @@ class SolveInfo(C.Structure):
 # exported names, in header order
 SYMBOLS = [
     "lasto_status_string", "lasto_last_error", "lasto_mesh_graded_1d", "lasto_grid_create",
-    "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_pseudo_density",
+    "lasto_grid_destroy", "lasto_grid_levels", "lasto_grid_level_shape", "lasto_grid_level_nodes",
+    "lasto_pseudo_density",
     "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp", "lasto_sphere_interp_noalloc",
     "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_density_terms", "lasto_sphere_project", "lasto_sphere_radial",
     "lasto_sphere_energy", "lasto_interstitial_density", "lasto_matrix_elements", "lasto_fdm_solve",
-    "lasto_fdm_axis", "lasto_apply", "lasto_rb_sweep", "lasto_boundary_values", "lasto_analytic_guess",
+    "lasto_fdm_axis", "lasto_apply", "lasto_rb_sweep", "lasto_stream_probe", "lasto_boundary_values", "lasto_analytic_guess",
     "lasto_net_create", "lasto_net_destroy", "lasto_net_set_grid",
     "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
     "lasto_net_save", "lasto_net_load", "lasto_net_get_config", "lasto_net_tensor",
@@ -167,6 +168,8 @@ def load():
     L.lasto_grid_levels.restype = i
     L.lasto_grid_level_shape.argtypes = [P, i, P]
     L.lasto_grid_level_shape.restype = i
+    L.lasto_grid_level_nodes.argtypes = [P, i, P, P, P]
+    L.lasto_grid_level_nodes.restype = i
     L.lasto_pseudo_density.argtypes = [P, i, P, P, i, P, P]
     L.lasto_pseudo_density.restype = i
     L.lasto_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
@@ -199,6 +202,8 @@ def load():
     L.lasto_fdm_axis.restype = i
     L.lasto_apply.argtypes = [P, P, P]
     L.lasto_apply.restype = i
+    L.lasto_stream_probe.argtypes = [P, P, P, C.c_size_t, P]
+    L.lasto_stream_probe.restype = i
     L.lasto_rb_sweep.argtypes = [P, P, P, P, i]
     L.lasto_rb_sweep.restype = i
     L.lasto_boundary_values.argtypes = [P, P, i, i, P, P]
@@ -368,6 +373,13 @@ class Grid:
             _check(load().lasto_grid_level_shape(self.h, l, _np_ptr(s)))
             out.append(tuple(int(v) for v in s))
         return out
+
+    def level_nodes(self, level: int):
+        """Finest-level indices of level `level`'s nodes per axis: (ix, iy, iz)."""
+        nx, ny, nz = self.levels()[level]
+        out = [np.zeros(n, dtype=np.int32) for n in (nx, ny, nz)]
+        _check(load().lasto_grid_level_nodes(self.h, level, *[_np_ptr(a) for a in out]))
+        return tuple(out)
 
     def empty(self):
         import torch
@@ -730,3 +742,11 @@ def hartree_step(grid: Grid, atoms, rtol=1e-10, dirs=None, **opts):
     radii = np.array([a.radius for a in atoms])
     sph = grid.sphere_interp(v, centers, radii, dirs)
     return dict(rho=rho, v=v, info=info, sphere=sph)
+
+
+def stream_probe(a, dst, b=None, stream=None):
+    """dst = a (or a + b) by the library's streaming probe on the current stream."""
+    import torch
+    st = stream or torch.cuda.current_stream()
+    _check(load().lasto_stream_probe(_dev_ptr(a), None if b is None else _dev_ptr(b), _dev_ptr(dst),
+                                     a.numel() * 8, C.c_void_p(st.cuda_stream)))

@@ -53,18 +53,33 @@ def make_problem(cid: int, sample: int, n: int, rtol: float = 1e-10) -> Problem:
     return Problem(w.name, w.atoms, g, rho, v, v_star, info)
 
 
-def training_pair(net: "lasto.Net", p: Problem, weighting: str = "volume"):
+def use_level(net: "lasto.Net", grid: "lasto.Grid", level: int):
+    """Run the net on level `level` of the grid (0: the finest; a coarse level
+    for a learned guess whose output is interpolated to the finest)."""
+    nx, ny, nz = grid.levels()[level]
+    net.set_grid((nz, ny, nx))
+
+
+def training_pair(net: "lasto.Net", p: Problem, weighting: str = "volume", level: int = 0):
     """Features, target (the correction in units of out_scale) and weights
     over interior nodes (zero on faces): "volume" weighs each node by its
     dual-cell volume (the W-norm of the error, which the far field's smooth
-    error dominates), "uniform" weighs nodes alike."""
+    error dominates), "uniform" weighs nodes alike. A net on a coarse level
+    learns the correction at that level's nodes (each a fine node)."""
     import torch
+    lev = level
+    use_level(net, p.grid, lev)
     x = net.features(p.grid, p.rho, p.v_guess)
     t = ((p.v_star - p.v_guess) / net.cfg.out_scale).to(torch.float32)
+    coords = p.grid.coords
+    if lev > 0:
+        ix, iy, iz = (torch.from_numpy(a.astype(np.int64)).to(t.device) for a in p.grid.level_nodes(lev))
+        t = t.index_select(0, iz).index_select(1, iy).index_select(2, ix).contiguous()
+        coords = [c[idx.cpu().numpy()] for c, idx in zip(coords, (ix, iy, iz))]
     wt = torch.zeros_like(t)
     if weighting == "volume":
-        m = [np.zeros_like(c) for c in p.grid.coords]
-        for c, mm in zip(p.grid.coords, m):
+        m = [np.zeros_like(c) for c in coords]
+        for c, mm in zip(coords, m):
             mm[1:-1] = 0.5 * (c[2:] - c[:-2])
         vol = np.einsum("k,j,i->kji", m[2], m[1], m[0])
         wt.copy_(torch.from_numpy(vol.astype(np.float32)))
@@ -81,12 +96,14 @@ def training_pair(net: "lasto.Net", p: Problem, weighting: str = "volume"):
 
 
 def train(net: "lasto.Net", problems: List[Problem], steps: int, lr: float = 2e-3, log_every: int = 0,
-          weighting: str = "volume"):
-    """Adam over the problems in turn; returns the loss history."""
-    pairs = [training_pair(net, p, weighting) for p in problems]
+          weighting: str = "volume", level: int = 0, pairs=None):
+    """Adam over the problems (or the given pairs) in turn; returns the loss history."""
+    if pairs is None:
+        pairs = [training_pair(net, p, weighting, level) for p in problems]
     hist = []
     for s in range(steps):
         x, t, wt = pairs[s % len(pairs)]
+        net.set_grid(tuple(t.shape))
         a = lr * 0.5 * (1.0 + np.cos(np.pi * s / max(steps, 1)))   # cosine decay
         hist.append(net.train_step(x, t, wt, max(a, lr * 1e-3)))
         if log_every and (s + 1) % log_every == 0:
@@ -94,7 +111,7 @@ def train(net: "lasto.Net", problems: List[Problem], steps: int, lr: float = 2e-
     return hist
 
 
-def compare(net: "lasto.Net", p: Problem, rtol: float = 1e-10, **opts) -> dict:
+def compare(net: "lasto.Net", p: Problem, rtol: float = 1e-10, level: int = 0, **opts) -> dict:
     """Time-to-tolerance and iterations from the faces alone (zero guess), the
     analytic guess, and the learned guess, same solver and tolerance. Each
     timing covers the faces, the guess and the solve."""
@@ -111,6 +128,7 @@ def compare(net: "lasto.Net", p: Problem, rtol: float = 1e-10, **opts) -> dict:
         if kind != "zero":
             g.analytic_guess(p.atoms, v)
         if kind == "learned":
+            use_level(net, g, level)
             lg = g.learned_guess(net, rho, v)
         info = g.poisson_solve(rho, v, rtol=rtol, bc=2, **opts)
         torch.cuda.synchronize()

@@ -281,6 +281,71 @@ def test_learned_correction_saves_cycles(torch, L):
     net.close()
 
 
+def test_learned_guess_on_a_coarse_level(torch, L):
+    """A learned-guess net on a coarse level of the hierarchy: its features
+    are taken at that level's nodes and its output is interpolated linearly to
+    the finest level. A net whose output is a constant c (all weights zero,
+    head bias c) must propose the finest-level start v + out_scale c at every
+    interior node; its judged residual matches that candidate's, swept once,
+    computed here from lasto_rb_sweep and lasto_apply. A net trained on that
+    level then helps the solve from its start reach the tolerance."""
+    from paper_0806_1723_amd import learned
+    n, lev = 65, 2
+    say("learned guess on coarse level %d, config 4 at %d^3" % (lev, n))
+    p = learned.make_problem(4, 7, n)
+    g = p.grid
+    nx, ny, nz = g.levels()[lev]
+    net = L.Net((nz, ny, nx), ch=(16, 16, 16, 16), seed=5, **learned.NET_SCALES)
+    prm = np.zeros(net.nparam, dtype=np.float32)
+    prm[-1] = 0.7
+    net.set_params(prm)
+    v = p.v_guess.clone()
+    r = g.learned_guess(net, p.rho, v)
+    shift = learned.NET_SCALES["out_scale"] * float(np.float32(0.7))   # the net's output is FP32
+    shifted = p.v_guess.clone()
+    shifted[1:-1, 1:-1, 1:-1] += shift
+    cand = g.rb_sweep(shifted, p.rho)
+    plain = g.rb_sweep(p.v_guess, p.rho)
+    m = []
+    for c in g.coords:
+        mm = np.zeros_like(c)
+        mm[1:-1] = 0.5 * (c[2:] - c[:-2])
+        m.append(mm)
+    vol = np.einsum("k,j,i->kji", m[2], m[1], m[0])
+    b = 4 * np.pi * p.rho.cpu().numpy()
+    vbc = p.v_guess.clone()
+    vbc[1:-1, 1:-1, 1:-1] = 0.0
+
+    def wres(u):
+        rr = (b - g.apply(u).cpu().numpy())[1:-1, 1:-1, 1:-1]
+        return float(np.sqrt((vol[1:-1, 1:-1, 1:-1] * rr * rr).sum()))
+
+    r0 = wres(vbc)
+    rc, rp = wres(cand) / r0, wres(plain) / r0
+    say("  constant net: judged plain %.6e learned %.6e; host %.6e %.6e" % (r["rel_before"], r["rel_after"], rp, rc))
+    assert abs(r["rel_after"] - rc) <= 1e-9 * rc and abs(r["rel_before"] - rp) <= 1e-9 * rp
+    assert r["accepted"] == (rc < rp)
+    # (the interpolation weights of a constant sum to one up to rounding)
+    want = cand if r["accepted"] else plain
+    assert float((v - want).abs().max()) <= 1e-13 * float(want.abs().max())
+    # trained on the coarse level: the solve from its start reaches the tolerance
+    train_p = [learned.make_problem(4, s, n) for s in range(8)]
+    # (the first coarse level: at 65^3 about 43^3 nodes, the resolution the
+    # 129^3 benchmark's guess net has on its second)
+    net2 = L.Net((48, 48, 48), ch=(16, 32, 32, 32), seed=7, **learned.NET_SCALES)
+    hist = learned.train(net2, train_p, steps=600, lr=2e-3, level=1)
+    say("  coarse-level training loss %.3e -> %.3e" % (np.mean(hist[:8]), np.mean(hist[-8:])))
+    assert np.mean(hist[-8:]) < 0.8 * np.mean(hist[:8])
+    res = learned.compare(net2, p, rtol=1e-10, level=1)
+    say("  %s" % res)
+    assert res["learned"]["rel_resid"] <= 1e-10 and res["err_vs_label"] <= 1e-8
+    for q in train_p:
+        q.grid.close()
+    g.close()
+    net.close()
+    net2.close()
+
+
 def test_learned_coarse_correction_inside_the_cycle(torch, L):
     """The learned coarse correction (config-4 clusters at 65^3, the net on
     the first coarse level, the exact coarsest solve one level below): it is
