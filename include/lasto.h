@@ -185,6 +185,14 @@ typedef struct {
     lasto_net coarse_net;      /* learned coarse correction (NULL: none): a net trained to map a coarse
                                   level's restricted residual to its correction; see lasto_poisson_solve */
     int coarse_net_level;      /* the level it acts on (>= 1, above the exact coarsest solve) */
+    double inner_rate;  /* precision 1: 0 (default) fixed inner step counts (inner_first, inner_iters); in
+                           (0, 1) adaptive: each refinement takes just enough steps to reach 0.7 rtol from
+                           the current relative residual rel at a per-step reduction q,
+                           ceil(log(0.7 rtol / rel) / log(q)), at least 1 and at most inner_first (first
+                           refinement, when set) or inner_iters. q starts at inner_rate; after a refinement
+                           of two or more PCG steps it becomes that refinement's own per-step decrease of
+                           sqrt(<r, z>_W); after a later refinement that reduced the true residual by less
+                           than 1e-5 it rises to that reduction per step when slower */
 } lasto_solve_opts;
 
 typedef struct {
@@ -212,6 +220,8 @@ typedef struct {
     double ms_cycles;       /* the iteration to the exit residual, ms */
     double alg_bytes;       /* algorithmic HBM bytes of the iteration's finest-level launches (each launch's
                                compulsory reads and writes of whole arrays) */
+    double inner_rate;      /* precision 1 with opts->inner_rate > 0: the per-step reduction q the last
+                               refinement was planned with */
 } lasto_solve_info;
 
 void lasto_solve_opts_default(lasto_solve_opts* o);

@@ -18,7 +18,8 @@ constexpr int kCoarseMax = 5;         // coarsening stops when every axis has <=
 constexpr double kCoarsenTheta = 4.0; // merge cell pairs up to theta * (smallest spacing)
 constexpr int kReduceBlocks = 1024;   // fixed partial count of every reduction (determinism)
 constexpr int kMaxBatch = 16;          // right-hand sides of one batched grid
-constexpr int kNumScalars = 32 + 3 * kMaxBatch;
+constexpr int kInnerHist = 32;        // inner FP32 PCG steps whose <r, z>_W are kept (a ring)
+constexpr int kNumScalars = 32 + 3 * kMaxBatch + kInnerHist;
 
 // scalar slots of the device scalar array
 enum Scalar {
@@ -28,7 +29,7 @@ enum Scalar {
     S_R0 = 4,               // reference ||b - A v_bc||_W^2
     S_TMP = 5,
     S_BAD = 6,              // nonzero once an FP32 correction held a non-finite value (not added to v)
-    S_RZ32_0 = 8, S_RZ32_1 = 9, S_PQ32 = 10,   // inner FP32 PCG
+    S_PQ32 = 10,            // inner FP32 PCG: <p, A p>_W (its <r, z>_W are S_RZH + step)
     S_LC_R = 12, S_LC_E = 13,  // learned coarse correction: ||f_c||_W^2 and ||f_c - A_c e||_W^2
     S_LC_ACC = 14,          // learned coarse corrections accepted in this solve
     S_LC_SCALE = 15,        // (spare)
@@ -37,6 +38,7 @@ enum Scalar {
     S_BR0 = 32,                        // per right-hand side: reference norm^2 [kMaxBatch]
     S_BRR = 32 + kMaxBatch,            // per right-hand side: residual norm^2 [kMaxBatch]
     S_BJ = 32 + 2 * kMaxBatch,         // per right-hand side: a second residual norm^2 [kMaxBatch]
+    S_RZH = 32 + 3 * kMaxBatch,        // inner FP32 PCG: <r, z>_W of step k at S_RZH + k % kInnerHist
 };
 
 void set_error(const std::string& msg);

@@ -241,7 +241,9 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
         lasto_status st = vcycle_level<float>(g, 0, o.nu1, o.nu2, rr, g->z32, g->partials, &nd);
         if (st != LASTO_OK) return st;
         ++*vcycles;
-        const int srz = S_RZ32_0 + (it & 1), srz_old = S_RZ32_0 + ((it + 1) & 1);
+        // <r, z>_W of every step is kept (the refinement reads the inner
+        // solve's convergence from them)
+        const int srz = S_RZH + it % kInnerHist, srz_old = S_RZH + (it + kInnerHist - 1) % kInnerHist;
         if (lasto_status e = reduce_to(g, nd, srz); e != LASTO_OK) return e;
         float* pn = g->p32[it & 1];
         float* po = g->p32[(it + 1) & 1];
@@ -361,9 +363,11 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: bad rtol/max_iters/nu1/nu2");
     if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
         o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 3 || (o.precision == 1 && o.inner_iters < 1) ||
-        o.inner_first < 0 || o.coarse < 0 || o.coarse > 2 || o.fallback < 0 || o.fallback > 1)
+        o.inner_first < 0 || o.coarse < 0 || o.coarse > 2 || o.fallback < 0 || o.fallback > 1 ||
+        !(o.inner_rate >= 0.0 && o.inner_rate < 1.0))
         return fail(LASTO_ERR_ARG,
-                    "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters/coarse/fallback");
+                    "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters/coarse/fallback/"
+                    "inner_rate");
     if (o.guess >= 2 && (o.n_atoms < 1 || !o.atoms))
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: guess 2 and 3 need the atom tables");
     if (o.guess == 3 && !o.guess_net) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: guess 3 needs guess_net");
@@ -492,6 +496,16 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     // the form running now: the mixed form can hand over to FP64 MG-PCG
     int prec = o.precision;
     int method = o.method;
+    // adaptive inner step counts of the mixed form: q is the expected
+    // per-step reduction, first the option's, then the inner PCG's own
+    // (the decrease of sqrt(<r, z>_W) over a refinement's steps, which runs
+    // a little slower than the true residual's), raised to the true
+    // residual's per-step reduction over a later
+    // refinement when that is slower (a refinement reducing by 1e-5 or more
+    // may have stopped at FP32 rounding, so it does not count)
+    double q_rate = o.inner_rate;
+    int pending_rate = 0, rz_steps = 0;
+    double rate_from = 0.0;
     // CG accumulates its correction in the split array x (zero now) and adds
     // it to v when it stops or restarts
     bool cg = (prec == 0 && method == 0);
@@ -510,7 +524,16 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             // FP32 inner solve on the FP32 rounding of the FP64 residual (the
             // equation is linear, so the residual's scale does not matter
             // while it stays far inside the FP32 range), then v += e in FP64
-            const int inner = (inf.refinements == 0 && o.inner_first > 0) ? o.inner_first : o.inner_iters;
+            const int cap = (inf.refinements == 0 && o.inner_first > 0) ? o.inner_first : o.inner_iters;
+            int inner = cap;
+            if (o.inner_rate > 0.0 && rel > target) {
+                // just enough steps at the expected rate to reach the target
+                // (planned against 0.7 of it, so that a refinement that
+                // lands a hair above it does not cost another)
+                const double want = std::log(0.7 * target / rel) / std::log(q_rate);
+                inner = std::max(1, std::min(cap, (int)std::ceil(want - 1e-9)));
+            }
+            const double rel_before = rel;
             if (method == 1) {
                 if (lasto_status e = mg32_inner(g, o, inner, &inf.vcycles, v); e != LASTO_OK) return e;
             } else {
@@ -520,6 +543,10 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             count(g, 0, 20.0);
             if (lasto_status e = reduce_to(g, nb_i, S_RR); e != LASTO_OK) return e;
             inf.refinements++;
+            pending_rate = o.inner_rate > 0.0 && inf.refinements > 1 && inner > 1 ? inner : 0;
+            rate_from = rel_before;
+            inf.inner_rate = q_rate;
+            rz_steps = (o.inner_rate > 0.0 && method == 0) ? std::min(inner, kInnerHist) : 0;
         } else if (method == 1) {
             // plain V-cycle iteration: v += V(r), r = b - A v
             lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, nullptr, nullptr);
@@ -561,11 +588,26 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
             cg_it++;
         }
         true_resid = !cg;
-        // the residual norm, and (mixed form) whether an FP32 correction broke down
-        if (lasto_status e = read_scalars(g, S_RR, S_BAD - S_RR + 1); e != LASTO_OK) return e;
+        // the residual norm, and (mixed form) whether an FP32 correction broke
+        // down; with adaptive inner steps also the inner PCG's <r, z>_W
+        const int last_slot = rz_steps > 0 ? S_RZH + kInnerHist - 1 : S_BAD;
+        if (lasto_status e = read_scalars(g, S_RR, last_slot - S_RR + 1); e != LASTO_OK) return e;
         rel = std::sqrt(g->h_scalars[S_RR]) / r0;
         if (it < 128) inf.resid_hist[it] = rel;
         ++it;
+        if (rz_steps >= 2) {
+            // (A and the cycle are negative definite: <r, z>_W < 0)
+            const int last = rz_steps - 1;
+            const double a = std::fabs(g->h_scalars[S_RZH]), b = std::fabs(g->h_scalars[S_RZH + last]);
+            if (a > 0.0 && b > 0.0 && std::isfinite(a) && std::isfinite(b) && b < a)
+                q_rate = std::min(0.9, std::max(1e-3, std::pow(b / a, 0.5 / last)));
+        }
+        rz_steps = 0;
+        if (pending_rate > 0 && std::isfinite(rel) && rel > 0.0 && rate_from > 0.0) {
+            const double red = rel / rate_from;
+            if (red > 1e-5 && red < 1.0) q_rate = std::max(q_rate, std::pow(red, 1.0 / pending_rate));
+        }
+        pending_rate = 0;
         if (prec == 1 && g->h_scalars[S_BAD] != 0.0) {
             result = LASTO_ERR_DIVERGED;
             why = "lasto_poisson_solve: the FP32 inner solve produced non-finite values (v kept finite)";

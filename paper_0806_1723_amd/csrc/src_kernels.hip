@@ -268,47 +268,106 @@ hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const 
 // -2 q / (sqrt(pi) w) at r = 0 and erf taken as 1 beyond 6w; kind 1 (the
 // quartic inside R) the uniform ball, -q (3R^2 - r^2)/(2R^3) inside and -q/r
 // outside. Faces are left as they are.
-__global__ __launch_bounds__(256) void k_guess(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
-                                               double* __restrict__ v)
+//
+// A guess only starts the iteration, so the far field -q/r (every atom
+// beyond 6w, or beyond R for kind 1: almost every node-atom pair) is summed
+// in FP32: coordinates relative to the workgroup's first node (exact to
+// about 1e-7 bohr near it), the hardware reciprocal square root, FP32
+// partial sums over at most 32 atoms added in FP64; the near field (erf or
+// the ball) stays FP64. Every far term has the sign of its charge, so with
+// positive charges the sum is within about 32 * 2^-24 (plus a few ulp per
+// term) of the FP64 sum, relative: far below what the guess itself misses
+// (the l >= 1 terms, the discretisation).
+constexpr int GU_X = 64, GU_Y = 4, GU_Z = 4, GU_NT = GU_X * GU_Y, GU_CHUNK = 512, GU_PART = 32;
+
+__device__ __forceinline__ double guess_near(const AtomDev& A, double dx, double dy, double dz)
 {
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    if (A.kind == 0) return r > 1e-12 * A.w ? -A.q * erf(r / A.w) / r : -2.0 * A.q / (sqrt(kPi) * A.w);
+    return -A.q * (3.0 * A.R * A.R - r2) / (2.0 * A.R * A.R * A.R);
+}
+
+__global__ __launch_bounds__(GU_NT) void k_guess(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
+                                                 double* __restrict__ v)
+{
+    __shared__ float4 sc[GU_CHUNK];   // atom centre relative to the origin, and charge
+    __shared__ float sl[GU_CHUNK];    // squared radius of the atom's exact near field
     const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const int i = 1 + blockIdx.x * 64 + (threadIdx.x & 63), j = 1 + blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i > nx - 2 || j > ny - 2) return;
-    const double px = L.ax[0].x[i], py = L.ax[1].x[j];
-    for (int k = 1 + blockIdx.z * 4; k <= min(nz - 2, 4 + blockIdx.z * 4); ++k) {
-        const double pz = L.ax[2].x[k];
-        double acc = 0.0;
-        for (int a = 0; a < n_atoms; ++a) {
-            const AtomDev& A = atoms[a];
-            const double dx = px - A.c[0], dy = py - A.c[1], dz = pz - A.c[2];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            // 1/r from the hardware estimate and two Newton steps (the far
-            // field -q/r of most node-atom pairs needs neither a square root
-            // nor a division)
-            double ri = __builtin_amdgcn_rsq(r2);
-            ri = ri * fma(-0.5 * r2, ri * ri, 1.5);
-            ri = ri * fma(-0.5 * r2, ri * ri, 1.5);
-            if (A.kind == 0) {
-                const double lim = 6.0 * A.w;
-                if (r2 < lim * lim) {
-                    const double r = sqrt(r2);
-                    acc -= r > 1e-12 * A.w ? A.q * erf(r / A.w) / r : 2.0 * A.q / (sqrt(kPi) * A.w);
-                } else {
-                    acc -= A.q * ri;
-                }
-            } else {
-                acc -= r2 < A.R * A.R ? A.q * (3.0 * A.R * A.R - r2) / (2.0 * A.R * A.R * A.R) : A.q * ri;
-            }
-        }
-        v[((size_t)k * ny + j) * nx + i] = acc;
+    const int i0 = 1 + blockIdx.x * GU_X, j0 = 1 + blockIdx.y * GU_Y, k0 = 1 + blockIdx.z * GU_Z;
+    const int i = i0 + (threadIdx.x & (GU_X - 1)), j = j0 + (int)(threadIdx.x / GU_X);
+    const bool live = i <= nx - 2 && j <= ny - 2;
+    // origin: the workgroup's first node
+    const double ox = L.ax[0].x[i0], oy = L.ax[1].x[j0], oz = L.ax[2].x[k0];
+    const double px = L.ax[0].x[min(i, nx - 2)], py = L.ax[1].x[min(j, ny - 2)];
+    const float fx = (float)(px - ox), fy = (float)(py - oy);
+    double pz[GU_Z];
+    float fz[GU_Z];
+#pragma unroll
+    for (int t = 0; t < GU_Z; ++t) {
+        pz[t] = L.ax[2].x[min(k0 + t, nz - 2)];
+        fz[t] = (float)(pz[t] - oz);
     }
+    double near[GU_Z];
+    float far[GU_Z];
+#pragma unroll
+    for (int t = 0; t < GU_Z; ++t) {
+        near[t] = 0.0;
+        far[t] = 0.0f;
+    }
+    for (int a0 = 0; a0 < n_atoms; a0 += GU_CHUNK) {
+        const int na = min(GU_CHUNK, n_atoms - a0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < na; t += GU_NT) {
+            const AtomDev& A = atoms[a0 + t];
+            sc[t] = make_float4((float)(A.c[0] - ox), (float)(A.c[1] - oy), (float)(A.c[2] - oz), (float)A.q);
+            const double lim = A.kind == 0 ? 6.0 * A.w : A.R;
+            // a little above the FP64 limit: every pair the FP64 test calls
+            // near is near here too (the exact formula holds on both sides)
+            sl[t] = (float)(lim * lim) * 1.0001f;
+        }
+        __syncthreads();
+        // FP32 partial sums of at most GU_PART atoms, added in FP64
+        for (int a1 = 0; a1 < na; a1 += GU_PART) {
+#pragma unroll
+            for (int t = 0; t < GU_Z; ++t) far[t] = 0.0f;
+            const int a2 = min(a1 + GU_PART, na);
+            for (int a = a1; a < a2; ++a) {
+                const float4 c = sc[a];
+                const float lim2 = sl[a];
+                const float dx = fx - c.x, dy = fy - c.y;
+                const float dxy = fmaf(dx, dx, dy * dy);
+#pragma unroll
+                for (int t = 0; t < GU_Z; ++t) {
+                    const float dz = fz[t] - c.z;
+                    const float r2 = fmaf(dz, dz, dxy);
+                    if (r2 < lim2) {
+                        const AtomDev& A = atoms[a0 + a];
+                        const double ddx = px - A.c[0], ddy = py - A.c[1], ddz = pz[t] - A.c[2];
+                        const double r2d = ddx * ddx + ddy * ddy + ddz * ddz;
+                        const double limd = A.kind == 0 ? 6.0 * A.w : A.R;
+                        if (r2d < limd * limd) near[t] += guess_near(A, ddx, ddy, ddz);
+                        else near[t] -= A.q / sqrt(r2d);
+                    } else {
+                        far[t] = fmaf(-c.w, __builtin_amdgcn_rsqf(r2), far[t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < GU_Z; ++t) near[t] += (double)far[t];
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int t = 0; t < GU_Z; ++t)
+        if (k0 + t <= nz - 2) v[((size_t)(k0 + t) * ny + j) * nx + i] = near[t];
 }
 
 hipError_t launch_guess(lasto_grid g, const AtomDev* atoms, int n_atoms, double* v)
 {
     const LevelView& L = g->cview;   // one right-hand side of a batch
-    const dim3 grid((L.nx - 2 + 63) / 64, (L.ny - 2 + 3) / 4, (L.nz - 2 + 3) / 4);
-    hipLaunchKernelGGL(k_guess, grid, dim3(256), 0, g->stream, L, atoms, n_atoms, v);
+    const dim3 grid((L.nx - 2 + GU_X - 1) / GU_X, (L.ny - 2 + GU_Y - 1) / GU_Y, (L.nz - 2 + GU_Z - 1) / GU_Z);
+    hipLaunchKernelGGL(k_guess, grid, dim3(GU_NT), 0, g->stream, L, atoms, n_atoms, v);
     return hipGetLastError();
 }
 

@@ -68,6 +68,7 @@ class SolveOpts(C.Structure):
         ("guess_net", C.c_void_p),
         ("coarse_net", C.c_void_p),
         ("coarse_net_level", C.c_int),
+        ("inner_rate", C.c_double),
     ]
 
 
@@ -95,6 +96,7 @@ class SolveInfo(C.Structure):
         ("ms_guess", C.c_double),
         ("ms_cycles", C.c_double),
         ("alg_bytes", C.c_double),
+        ("inner_rate", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -108,7 +110,7 @@ class SolveInfo(C.Structure):
                     coarse_level=self.coarse_level, fallback_used=self.fallback_used,
                     guess_accepted=self.guess_accepted, coarse_applied=self.coarse_applied,
                     coarse_accepted=self.coarse_accepted, ms_bc=self.ms_bc, ms_guess=self.ms_guess,
-                    ms_cycles=self.ms_cycles, alg_bytes=self.alg_bytes)
+                    ms_cycles=self.ms_cycles, alg_bytes=self.alg_bytes, inner_rate=self.inner_rate)
 
 
 # exported names, in header order

@@ -171,8 +171,16 @@ SOLVE_CASES = [
     (3, 129, dict(nu1=3, nu2=3)),
 ]
 
-# the benchmark's two timed forms (mixed, FP64)
-BENCH_FORMS = [dict(precision=1, method=0, inner_iters=5, inner_first=4, nu1=3, nu2=3), dict(nu1=3, nu2=3)]
+# the benchmark's two timed forms (mixed with adaptive inner steps, FP64),
+# both from the analytic start, and the fixed-step mixed form from zero
+BENCH_FORMS = [dict(precision=1, method=0, nu1=3, nu2=3, inner_first=4, inner_iters=8, inner_rate=0.05, guess=2),
+               dict(nu1=3, nu2=3, guess=2),
+               dict(precision=1, method=0, inner_iters=5, inner_first=4, nu1=3, nu2=3)]
+
+
+def start_atoms(form, atoms):
+    """the atom tables a form's start needs (guess 2 and 3)"""
+    return dict(atoms=atoms) if form.get("guess", 0) >= 2 else {}
 
 
 @pytest.mark.parametrize("cid,n,opts", SOLVE_CASES)
@@ -211,7 +219,7 @@ def test_bench_form_at_the_headline_tolerance_matches_oracle(torch, L, oracle_mo
     g = L.Grid(*xs)
     rho = g.pseudo_density(w.atoms)
     v = g.empty()
-    info = g.poisson_solve(rho, v, rtol=1e-10, **form)
+    info = g.poisson_solve(rho, v, rtol=1e-10, **form, **start_atoms(form, w.atoms))
     got = v.cpu().numpy()
     err = wnorm(xs, got - v_o) / wnorm(xs, v_o)
     say("  iters %d vcycles %d refinements %d rel %.2e, error vs oracle %.3e" % (
@@ -219,6 +227,35 @@ def test_bench_form_at_the_headline_tolerance_matches_oracle(torch, L, oracle_mo
     assert info["rel_resid"] <= 1e-10
     assert err <= 1e-9
     assert oracle_mod.rel_residual(xs, rho_o, got) <= 1.05e-10
+    g.close()
+
+
+def test_adaptive_inner_steps_take_fewer_cycles(torch, L):
+    """inner_rate > 0: each refinement plans its FP32 step count from the
+    current residual and the inner solve's measured convergence. From the
+    analytic start the mixed solve then needs fewer V-cycles than the fixed
+    4 + 5 steps from zero, and at least one fewer than the fixed steps from
+    the same start; every form reaches 1e-10."""
+    say("adaptive inner steps, config 3 n=129")
+    w = I.config(3, n_override=129)
+    xs = L.mesh_for(w.axes)
+    g = L.Grid(*xs)
+    rho = g.pseudo_density(w.atoms)
+    base = dict(precision=1, method=0, nu1=3, nu2=3)
+    fixed0 = g.poisson_solve(rho, g.empty(), rtol=1e-10, guess=1, inner_first=4, inner_iters=5, **base)
+    fixed2 = g.poisson_solve(rho, g.empty(), rtol=1e-10, guess=2, atoms=w.atoms, inner_first=4, inner_iters=5,
+                             **base)
+    adapt2 = g.poisson_solve(rho, g.empty(), rtol=1e-10, guess=2, atoms=w.atoms, inner_first=4, inner_iters=8,
+                             inner_rate=0.05, **base)
+    for name, i in (("fixed, zero start", fixed0), ("fixed, analytic start", fixed2),
+                    ("adaptive, analytic start", adapt2)):
+        say("  %s: %d V-cycles, %d refinements, rel %.2e, q %.3f" % (name, i["vcycles"], i["refinements"],
+                                                                    i["rel_resid"], i["inner_rate"]))
+        assert i["rel_resid"] <= 1e-10
+    assert adapt2["vcycles"] < fixed0["vcycles"] and adapt2["vcycles"] < fixed2["vcycles"]
+    assert 0.0 < adapt2["inner_rate"] < 1.0
+    with pytest.raises(L.LastoError):
+        g.poisson_solve(rho, g.empty(), precision=1, inner_rate=1.0)
     g.close()
 
 
@@ -334,7 +371,7 @@ def test_mackay_cluster_batch_matches_oracle_per_copy(torch, L, oracle_mod):
     g = L.Grid(*xs, n_batch=8)
     rho, Q = g.pseudo_density(w.batch_atoms, moments=True)
     v = g.empty()
-    info = g.poisson_solve(rho, v, rtol=1e-12, **BENCH_FORMS[0])
+    info = g.poisson_solve(rho, v, rtol=1e-12, **BENCH_FORMS[0], **start_atoms(BENCH_FORMS[0], w.batch_atoms))
     say("  iters %d vcycles %d per-copy rel %s" % (info["iters"], info["vcycles"], info["batch_rel_resid"]))
     assert max(info["batch_rel_resid"]) <= 1e-12
     got = v.cpu().numpy()
@@ -406,7 +443,39 @@ def test_analytic_guess_matches_closed_form(torch, L):
     assert np.array_equal(got[faces], v0[faces])
     err = np.abs(got - want)[~faces].max() / np.abs(want[~faces]).max()
     say("  analytic guess max rel error %.2e" % err)
-    assert err <= 1e-13
+    # the far field (-q/r beyond 6w or R) is summed in FP32 partial sums of
+    # at most 32 atoms, near fields in FP64: the guess only starts the
+    # iteration, and its own distance from the discrete solution (no l >= 1
+    # terms, no discretisation) is ~1e-3
+    assert err <= 40 * 2.0 ** -24
+    g.close()
+
+
+def test_analytic_guess_many_atoms_matches_closed_form(torch, L):
+    """More atoms than one staging chunk of the guess kernel (512): 700
+    Gaussian atoms scattered over the box, some of them off the mesh."""
+    from scipy.special import erf
+    rng = np.random.default_rng(12)
+    xs = [graded(rng, n) for n in (35, 27, 31)]
+    g = L.Grid(*xs)
+    lo = np.array([x[0] for x in xs]) - 1.0
+    hi = np.array([x[-1] for x in xs]) + 1.0
+    atoms = [I.Atom(center=lo + (hi - lo) * rng.random(3), q=float(rng.uniform(0.5, 2.0)),
+                    width=float(rng.uniform(0.3, 0.7))) for _ in range(700)]
+    v = to_dev(torch, np.zeros((31, 27, 35)))
+    g.analytic_guess(atoms, v)
+    got = v.cpu().numpy()[1:-1, 1:-1, 1:-1]
+    Z, Y, X = np.meshgrid(xs[2][1:-1], xs[1][1:-1], xs[0][1:-1], indexing="ij")
+    want = np.zeros_like(got)
+    for a in atoms:
+        r = np.sqrt((X - a.center[0]) ** 2 + (Y - a.center[1]) ** 2 + (Z - a.center[2]) ** 2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            f = np.where(r > 1e-12 * a.width, erf(r / a.width) / r, 2.0 / (math.sqrt(math.pi) * a.width))
+        want -= a.q * f
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say("  analytic guess, 700 atoms: max rel error %.2e" % err)
+    # FP32 partial sums of 32 same-sign terms: (32 + a few ulp per term) * 2^-24
+    assert err <= 40 * 2.0 ** -24
     g.close()
 
 
