@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time over which the oracle baseline repeats whole solves")
     ap.add_argument("--no-clean", action="store_true", help="skip the 513^3 MALL-free smoother roofline")
+    ap.add_argument("--clean-only", action="store_true",
+                    help="only the 513^3 MALL-free smoother roofline (one JSON object), for kernel traces")
     ap.add_argument("--train", type=int, default=200, help="config 4: training problems")
     ap.add_argument("--train-steps", type=int, default=2400, help="config 4: Adam steps per net")
     ap.add_argument("--validate", type=int, default=50, help="config 4: labels checked by the oracle")
@@ -118,6 +120,10 @@ def main():
     form = dict(precision=mixed, method=0, nu1=3, nu2=3, inner_first=4 if mixed else 0,
                 inner_iters=8 if mixed else 5, inner_rate=0.05 if mixed else 0.0)
     start = dict(guess=2, atoms=atoms)
+    if args.clean_only:
+        g.close()
+        print(json.dumps(bench_clean_roofline(args, lasto, I, form)), flush=True)
+        return
 
     def step(profile, precision):
         g.pseudo_density(atoms, rho_out=rho)

@@ -269,98 +269,84 @@ hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const 
 // quartic inside R) the uniform ball, -q (3R^2 - r^2)/(2R^3) inside and -q/r
 // outside. Faces are left as they are.
 //
-// A guess only starts the iteration, so the far field -q/r (every atom
-// beyond 6w, or beyond R for kind 1: almost every node-atom pair) is summed
-// in FP32: coordinates relative to the workgroup's first node (exact to
-// about 1e-7 bohr near it), the hardware reciprocal square root, FP32
-// partial sums over at most 32 atoms added in FP64; the near field (erf or
-// the ball) stays FP64. Every far term has the sign of its charge, so with
-// positive charges the sum is within about 32 * 2^-24 (plus a few ulp per
-// term) of the FP64 sum, relative: far below what the guess itself misses
-// (the l >= 1 terms, the discretisation).
+// A guess only starts the iteration, so it is summed in FP32: coordinates
+// relative to the workgroup's first node (exact to about 1e-7 bohr near
+// it), the far field -q/r (beyond 6w, or R for kind 1: most node-atom pairs)
+// by the hardware reciprocal square root, the near field (erf, the ball) by
+// FP32 formulas, in partial sums over at most 32 atoms added in FP64. Every
+// term has the sign of its charge, so with positive charges the result is
+// within about 32 * 2^-24 (plus a few ulp per term) of the FP64 sum,
+// relative: far below what the guess itself misses (the l >= 1 terms, the
+// discretisation).
 constexpr int GU_X = 64, GU_Y = 4, GU_Z = 4, GU_NT = GU_X * GU_Y, GU_CHUNK = 512, GU_PART = 32;
-
-__device__ __forceinline__ double guess_near(const AtomDev& A, double dx, double dy, double dz)
-{
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
-    if (A.kind == 0) return r > 1e-12 * A.w ? -A.q * erf(r / A.w) / r : -2.0 * A.q / (sqrt(kPi) * A.w);
-    return -A.q * (3.0 * A.R * A.R - r2) / (2.0 * A.R * A.R * A.R);
-}
 
 __global__ __launch_bounds__(GU_NT) void k_guess(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
                                                  double* __restrict__ v)
 {
     __shared__ float4 sc[GU_CHUNK];   // atom centre relative to the origin, and charge
-    __shared__ float sl[GU_CHUNK];    // squared radius of the atom's exact near field
+    __shared__ float4 sp[GU_CHUNK];   // near-field radius^2, 1/w (kind 0) or 0, R^2 and 1/(2 R^3) (kind 1)
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int i0 = 1 + blockIdx.x * GU_X, j0 = 1 + blockIdx.y * GU_Y, k0 = 1 + blockIdx.z * GU_Z;
     const int i = i0 + (threadIdx.x & (GU_X - 1)), j = j0 + (int)(threadIdx.x / GU_X);
     const bool live = i <= nx - 2 && j <= ny - 2;
     // origin: the workgroup's first node
     const double ox = L.ax[0].x[i0], oy = L.ax[1].x[j0], oz = L.ax[2].x[k0];
-    const double px = L.ax[0].x[min(i, nx - 2)], py = L.ax[1].x[min(j, ny - 2)];
-    const float fx = (float)(px - ox), fy = (float)(py - oy);
-    double pz[GU_Z];
+    const float fx = (float)(L.ax[0].x[min(i, nx - 2)] - ox), fy = (float)(L.ax[1].x[min(j, ny - 2)] - oy);
     float fz[GU_Z];
 #pragma unroll
-    for (int t = 0; t < GU_Z; ++t) {
-        pz[t] = L.ax[2].x[min(k0 + t, nz - 2)];
-        fz[t] = (float)(pz[t] - oz);
-    }
-    double near[GU_Z];
-    float far[GU_Z];
+    for (int t = 0; t < GU_Z; ++t) fz[t] = (float)(L.ax[2].x[min(k0 + t, nz - 2)] - oz);
+    double acc[GU_Z];
 #pragma unroll
-    for (int t = 0; t < GU_Z; ++t) {
-        near[t] = 0.0;
-        far[t] = 0.0f;
-    }
+    for (int t = 0; t < GU_Z; ++t) acc[t] = 0.0;
+    constexpr float kTwoOverSqrtPi = 1.12837916709551257f;
     for (int a0 = 0; a0 < n_atoms; a0 += GU_CHUNK) {
         const int na = min(GU_CHUNK, n_atoms - a0);
         __syncthreads();
         for (int t = threadIdx.x; t < na; t += GU_NT) {
             const AtomDev& A = atoms[a0 + t];
             sc[t] = make_float4((float)(A.c[0] - ox), (float)(A.c[1] - oy), (float)(A.c[2] - oz), (float)A.q);
-            const double lim = A.kind == 0 ? 6.0 * A.w : A.R;
-            // a little above the FP64 limit: every pair the FP64 test calls
-            // near is near here too (the exact formula holds on both sides)
-            sl[t] = (float)(lim * lim) * 1.0001f;
+            if (A.kind == 0)
+                sp[t] = make_float4((float)(36.0 * A.w * A.w), (float)(1.0 / A.w), 0.0f, 0.0f);
+            else
+                sp[t] = make_float4((float)(A.R * A.R), 0.0f, (float)(3.0 * A.R * A.R),
+                                    (float)(0.5 / (A.R * A.R * A.R)));
         }
         __syncthreads();
-        // FP32 partial sums of at most GU_PART atoms, added in FP64
         for (int a1 = 0; a1 < na; a1 += GU_PART) {
+            float part[GU_Z];
 #pragma unroll
-            for (int t = 0; t < GU_Z; ++t) far[t] = 0.0f;
+            for (int t = 0; t < GU_Z; ++t) part[t] = 0.0f;
             const int a2 = min(a1 + GU_PART, na);
             for (int a = a1; a < a2; ++a) {
                 const float4 c = sc[a];
-                const float lim2 = sl[a];
+                const float4 p = sp[a];
                 const float dx = fx - c.x, dy = fy - c.y;
                 const float dxy = fmaf(dx, dx, dy * dy);
 #pragma unroll
                 for (int t = 0; t < GU_Z; ++t) {
                     const float dz = fz[t] - c.z;
                     const float r2 = fmaf(dz, dz, dxy);
-                    if (r2 < lim2) {
-                        const AtomDev& A = atoms[a0 + a];
-                        const double ddx = px - A.c[0], ddy = py - A.c[1], ddz = pz[t] - A.c[2];
-                        const double r2d = ddx * ddx + ddy * ddy + ddz * ddz;
-                        const double limd = A.kind == 0 ? 6.0 * A.w : A.R;
-                        if (r2d < limd * limd) near[t] += guess_near(A, ddx, ddy, ddz);
-                        else near[t] -= A.q / sqrt(r2d);
+                    float f;
+                    if (r2 >= p.x) {
+                        f = __builtin_amdgcn_rsqf(r2);   // -q/r
+                    } else if (p.y > 0.0f) {
+                        // Gaussian: erf(r/w)/r, 2/(sqrt(pi) w) at r = 0
+                        const float r = sqrtf(r2);
+                        f = r > 1e-6f / p.y ? erff(r * p.y) / r : kTwoOverSqrtPi * p.y;
                     } else {
-                        far[t] = fmaf(-c.w, __builtin_amdgcn_rsqf(r2), far[t]);
+                        f = (p.z - r2) * p.w;   // uniform ball: (3R^2 - r^2)/(2R^3)
                     }
+                    part[t] = fmaf(-c.w, f, part[t]);
                 }
             }
 #pragma unroll
-            for (int t = 0; t < GU_Z; ++t) near[t] += (double)far[t];
+            for (int t = 0; t < GU_Z; ++t) acc[t] += (double)part[t];
         }
     }
     if (!live) return;
 #pragma unroll
     for (int t = 0; t < GU_Z; ++t)
-        if (k0 + t <= nz - 2) v[((size_t)(k0 + t) * ny + j) * nx + i] = near[t];
+        if (k0 + t <= nz - 2) v[((size_t)(k0 + t) * ny + j) * nx + i] = acc[t];
 }
 
 hipError_t launch_guess(lasto_grid g, const AtomDev* atoms, int n_atoms, double* v)

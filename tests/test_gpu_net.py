@@ -333,7 +333,7 @@ def test_learned_guess_on_a_coarse_level(torch, L):
     # (the first coarse level: at 65^3 about 43^3 nodes, the resolution the
     # 129^3 benchmark's guess net has on its second)
     net2 = L.Net((48, 48, 48), ch=(16, 32, 32, 32), seed=7, **learned.NET_SCALES)
-    hist = learned.train(net2, train_p, steps=600, lr=2e-3, level=1)
+    hist = learned.train(net2, train_p, steps=1500, lr=2e-3, level=1)
     say("  coarse-level training loss %.3e -> %.3e" % (np.mean(hist[:8]), np.mean(hist[-8:])))
     assert np.mean(hist[-8:]) < 0.8 * np.mean(hist[:8])
     res = learned.compare(net2, p, rtol=1e-10, level=1)
