@@ -28,14 +28,16 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel (finest-level FP32 half-sweep,
-# launch mix of one mixed solve), from two rocprofv3 --pmc runs of
-# `bench.py --steps 1 --warmup 0 --no-cpu` (FETCH_SIZE, then WRITE_SIZE), each
-# counter scaled by what it reads for a 512 MiB device copy
-# (`bench.py --copy-calibration 512`: FETCH_SIZE x2.000, WRITE_SIZE x1.000).
-# Summary: profiles/k_half2_fp32_finest_257_traffic.md. The figure belongs to
-# the kernel source it was measured on and to the same solve form; `traffic`
-# is reported as null when either differs.
-COUNTER_TRAFFIC = {"kernel_sha256_16": "191803d67b975fc8", "form": (1, 0, 5, 4, 3, 3), "bytes_per_launch": 116.99e6}
+# launch mix of one headline solve: 54 plain, 12 with partials, 6 from zero),
+# from two rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu
+# --no-clean --solve-only` (FETCH_SIZE, then WRITE_SIZE; per-variant means
+# over all its FP32 solves), each counter scaled by what it reads for a
+# 512 MiB device copy (`bench.py --copy-calibration 512`: FETCH_SIZE x2.000,
+# WRITE_SIZE x1.000). Summary: profiles/k_half2_fp32_finest_257_traffic.md.
+# The figure belongs to the kernel source it was measured on and to the same
+# solve form and start; `traffic` is reported as null when either differs.
+COUNTER_TRAFFIC = {"kernel_sha256_16": "191803d67b975fc8", "form": (1, 0, 8, 4, 3, 3, 0.05, 2),
+                   "bytes_per_launch": 116.69e6}
 
 
 def half_sweep_source_digest():
@@ -697,8 +699,8 @@ def bench_learned(args):
     for p in test_p:
         for _ in range(2):   # second pass timed warm
             r = learned.compare(net, p, rtol=1e-10, level=glev)
-            rm = learned.compare(net, p, rtol=1e-10, level=glev, precision=1, nu1=3, nu2=3, inner_iters=5,
-                                 inner_first=4)
+            rm = learned.compare(net, p, rtol=1e-10, level=glev, precision=1, nu1=3, nu2=3, inner_iters=8,
+                                 inner_first=4, inner_rate=0.05)
         rc = learned.compare_coarse(net_c, p, clev)
         rows.append(r)
         mixed.append(rm)
@@ -823,10 +825,12 @@ def bench_batched(args):
                          refinements=last["refinements"], ms_guess=round(last["ms_guess"], 3),
                          ms_cycles=round(last["ms_cycles"], 3), rel_resid=last["rel_resid"],
                          per_rhs_rel_resid=last["batch_rel_resid"], guess_accepted=last["guess_accepted"],
+                         rel_start=last["rel_start"], resid_hist=last["resid_hist"],
                          smoother=(timed[0]["smooth_bytes"], timed[0]["smooth_ms"], timed[0]["smooth_launches"]))
         log("bench: 8 x %d^3 mixed from the %s start: %.2f ms (%.2f per right-hand side), %d V-cycles, %d "
-            "refinements, guess %.2f ms, rel %.2e%s" % (
-                n, name, ms, ms / nb, last["vcycles"], last["refinements"], last["ms_guess"], last["rel_resid"],
+            "refinements, guess %.2f ms, start rel %.2e, after each refinement %s%s" % (
+                n, name, ms, ms / nb, last["vcycles"], last["refinements"], last["ms_guess"], last["rel_start"],
+                ["%.1e" % x for x in last["resid_hist"]],
                 (", learned start kept on %d of %d" % (last["guess_accepted"], nb)) if name == "learned" else ""))
     # plain FP64 MG-PCG on the same batch, zero and analytic starts
     fp64 = {}

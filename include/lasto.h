@@ -222,6 +222,7 @@ typedef struct {
                                compulsory reads and writes of whole arrays) */
     double inner_rate;      /* precision 1 with opts->inner_rate > 0: the per-step reduction q the last
                                refinement was planned with */
+    double rel_start;       /* relative residual of the start (after the guess), as rel_resid */
 } lasto_solve_info;
 
 void lasto_solve_opts_default(lasto_solve_opts* o);

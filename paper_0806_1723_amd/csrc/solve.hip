@@ -458,6 +458,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     const double r0sq = g->h_scalars[S_R0];
     const double r0 = std::sqrt(r0sq);
     double rel = (r0 > 0.0) ? std::sqrt(g->h_scalars[S_RR]) / r0 : 0.0;
+    inf.rel_start = rel;
     // rel is the true residual of v with no CG correction pending (the mixed
     // form and the stationary cycles recompute it every step; CG only when it
     // folds its correction into v), so the exit need not compute it again

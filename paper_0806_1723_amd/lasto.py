@@ -97,6 +97,7 @@ class SolveInfo(C.Structure):
         ("ms_cycles", C.c_double),
         ("alg_bytes", C.c_double),
         ("inner_rate", C.c_double),
+        ("rel_start", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -110,7 +111,8 @@ class SolveInfo(C.Structure):
                     coarse_level=self.coarse_level, fallback_used=self.fallback_used,
                     guess_accepted=self.guess_accepted, coarse_applied=self.coarse_applied,
                     coarse_accepted=self.coarse_accepted, ms_bc=self.ms_bc, ms_guess=self.ms_guess,
-                    ms_cycles=self.ms_cycles, alg_bytes=self.alg_bytes, inner_rate=self.inner_rate)
+                    ms_cycles=self.ms_cycles, alg_bytes=self.alg_bytes, inner_rate=self.inner_rate,
+                    rel_start=self.rel_start)
 
 
 # exported names, in header order
