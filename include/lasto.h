@@ -193,6 +193,11 @@ typedef struct {
                            of two or more PCG steps it becomes that refinement's own per-step decrease of
                            sqrt(<r, z>_W); after a later refinement that reduced the true residual by less
                            than 1e-5 it rises to that reduction per step when slower */
+    int eager;          /* 0 (default): the finest-level V-cycle of the CG forms is captured into a HIP graph
+                           at its second use on a grid (per precision, nu1, nu2 and coarse mode; on a stream
+                           of the library's own) and replayed after, one host call in place of every level's
+                           launches; same kernels in the same order, so the same bits. 1: every launch from
+                           the host. (profile = 1 and a learned coarse correction always launch eagerly) */
 } lasto_solve_opts;
 
 typedef struct {

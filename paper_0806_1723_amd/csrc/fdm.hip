@@ -679,6 +679,12 @@ template <> struct CgTab<float> {
     static float* buf(const CoarseGemm* c, int b) { return c->buf32[b]; }
 };
 
+// the stream the FP32 contractions (rocBLAS) are issued on
+void coarse_gemm_set_stream(lasto_grid g, hipStream_t s)
+{
+    if (g->cg && g->cg->blas) (void)rocblas_set_stream(g->cg->blas, s);
+}
+
 template <typename T>
 lasto_status coarse_gemm_solve(lasto_grid g, const T* f, T* u, hipStream_t s)
 {

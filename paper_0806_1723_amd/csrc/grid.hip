@@ -238,6 +238,11 @@ static lasto_status alloc_zero(lasto_grid g, void** p, size_t bytes)
 
 static void free_grid(lasto_grid g)
 {
+    for (auto& e : g->vgraphs)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    g->vgraphs.clear();
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    g->cap_stream = nullptr;
     free_fdm(g);
     free_coarse_fdm(g);
     free_coarse_gemm(g);

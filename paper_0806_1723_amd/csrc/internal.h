@@ -288,6 +288,21 @@ struct lasto_grid_s {
     // optional event timing of the finest-level sweeps (solve opts.profile)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;   // start/stop pairs
+    // finest-level V-cycles captured into HIP graphs (replayed in place of
+    // every level's launches), keyed by precision, sweeps and coarse mode;
+    // captured on a stream of the library's own at their second use
+    struct VGraph {
+        int key[4];
+        const void* f;
+        void* u;
+        double* dotp;
+        int uses = 0;
+        hipGraphExec_t exec = nullptr;
+        int ndot = 0;
+        double bytes = 0.0;
+    };
+    std::vector<VGraph> vgraphs;
+    hipStream_t cap_stream = nullptr;
     int prof_used = 0;
     double prof_bytes = 0.0;
     int prof_fp32 = 0;
@@ -364,6 +379,7 @@ void free_coarse_fdm(lasto_grid g);
 // exact solve of A e = f (zero faces) at level g->cg_level by GEMMs, split layout
 void choose_coarse_gemm_level(lasto_grid g);
 lasto_status coarse_gemm_init(lasto_grid g);    // tables, buffers and rocBLAS handle on first use
+void coarse_gemm_set_stream(lasto_grid g, hipStream_t s);   // the stream of its rocBLAS calls
 template <typename T>
 lasto_status coarse_gemm_solve(lasto_grid g, const T* f, T* e, hipStream_t s);
 void free_coarse_gemm(lasto_grid g);

@@ -6,6 +6,7 @@
 // reduced on the device into a scalar array that later kernels read (so CG's
 // alpha and beta never travel to the host). The host reads one 8-byte norm
 // per outer iteration to decide convergence.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -182,6 +183,65 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     return LASTO_OK;
 }
 
+// The finest-level V-cycle of the CG forms (fixed operands every step),
+// replayed from a HIP graph unless `eager`: the first use on a grid for a
+// key launches eagerly (lazy tables, library workspaces and static launch
+// shapes are set up outside any capture), the second captures the cycle on
+// the library's own stream and replays it, and later uses replay. Algorithmic
+// bytes and partial counts are those the capture recorded.
+template <typename T>
+static lasto_status vcycle0(lasto_grid g, const lasto_solve_opts& o, const T* f, T* u, double* dotp, int* ndot)
+{
+    if (o.eager || g->prof_on || g->lc_net) return vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, ndot);
+    const int key[4] = {(int)sizeof(T), o.nu1, o.nu2, g->coarse_mode};
+    lasto_grid_s::VGraph* e = nullptr;
+    for (auto& v : g->vgraphs)
+        if (std::equal(key, key + 4, v.key) && v.f == f && v.u == u && v.dotp == dotp) e = &v;
+    if (!e) {
+        lasto_grid_s::VGraph v;
+        std::copy(key, key + 4, v.key);
+        v.f = f;
+        v.u = u;
+        v.dotp = dotp;
+        g->vgraphs.push_back(v);
+        e = &g->vgraphs.back();
+    }
+    if (e->exec) {
+        HIPCHK(hipGraphLaunch(e->exec, g->stream));
+        g->alg_bytes += e->bytes;
+        if (ndot) *ndot = e->ndot;
+        return LASTO_OK;
+    }
+    if (e->uses++ == 0) return vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, ndot);
+    if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    hipStream_t keep = g->stream;
+    const double b0 = g->alg_bytes;
+    HIPCHK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+    g->stream = g->cap_stream;
+    coarse_gemm_set_stream(g, g->cap_stream);
+    int nd = 0;
+    const lasto_status st = vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, &nd);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g->cap_stream, &graph);
+    g->stream = keep;
+    coarse_gemm_set_stream(g, keep);
+    if (st != LASTO_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (st != LASTO_OK) return st;
+        return fail(LASTO_ERR_HIP, std::string("vcycle capture: ") + hipGetErrorString(ec));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(LASTO_ERR_HIP, std::string("vcycle graph: ") + hipGetErrorString(ei));
+    e->exec = exec;
+    e->ndot = nd;
+    e->bytes = g->alg_bytes - b0;   // counted while capturing: this use's share
+    HIPCHK(hipGraphLaunch(exec, g->stream));
+    if (ndot) *ndot = nd;
+    return LASTO_OK;
+}
+
 static lasto_status reduce_to(lasto_grid g, int count, int slot)
 {
     HIPCHK(launch_reduce(g->partials, 1, count, g->scalars + slot, g->stream));
@@ -238,7 +298,7 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
     float* rr = g->r32;   // working residual, updated in place
     for (int it = 0; it < iters; ++it) {
         int nd = 0;
-        lasto_status st = vcycle_level<float>(g, 0, o.nu1, o.nu2, rr, g->z32, g->partials, &nd);
+        lasto_status st = vcycle0<float>(g, o, rr, g->z32, g->partials, &nd);
         if (st != LASTO_OK) return st;
         ++*vcycles;
         // <r, z>_W of every step is kept (the refinement reads the inner
@@ -560,7 +620,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         } else {
             // one MG-preconditioned CG step
             int nd = 0;
-            lasto_status st = vcycle_level<double>(g, 0, o.nu1, o.nu2, g->r, g->z, g->partials, &nd);
+            lasto_status st = vcycle0<double>(g, o, g->r, g->z, g->partials, &nd);
             if (st != LASTO_OK) return st;
             inf.vcycles++;
             const int srz = S_RZ0 + (cg_it & 1), srz_old = S_RZ0 + ((cg_it + 1) & 1);
