@@ -130,8 +130,7 @@ extern "C" lasto_status lasto_analytic_guess(lasto_grid g, int n_atoms, const la
     AtomDev* dat = nullptr;
     if (lasto_status st = stage_atoms(g, nb * n_atoms, atoms, 1, "lasto_analytic_guess", &dat); st != LASTO_OK)
         return st;
-    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
-    for (int b = 0; b < nb; ++b) LASTO_HIP(launch_guess(g, dat + (size_t)b * n_atoms, n_atoms, v + b * N));
+    LASTO_HIP(launch_guess_all(g, dat, atoms, n_atoms, v));
     LASTO_HIP(hipStreamSynchronize(g->stream));
     return LASTO_OK;
 }

@@ -452,6 +452,9 @@ hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const 
 hipError_t launch_moments(lasto_grid g, const double* rho, double* Q);
 hipError_t launch_bc(lasto_grid g, int mode, const double* Q, int lmax_bc, double* v);
 hipError_t launch_guess(lasto_grid g, const AtomDev* atoms, int n_atoms, double* v);
+// every right-hand side's guess (one pass for copies that share their geometry)
+hipError_t launch_guess_all(lasto_grid g, const AtomDev* dev_atoms, const lasto_atom* host_atoms, int n_atoms,
+                            double* v);
 // validate an atom table, copy it to the grid's staging buffer and prepare it on the device
 lasto_status stage_atoms(lasto_grid g, int n_atoms, const lasto_atom* atoms, int renormalize, const char* who,
                          AtomDev** out);

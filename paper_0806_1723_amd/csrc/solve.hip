@@ -475,7 +475,6 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     const int nb_i = interior_blocks(V);
     const double fourpi = 4.0 * kPi;
     const int nbat = g->n_batch;
-    const size_t Ncopy = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
     HIPCHK(hipEventRecord(g->ph_ev[0], s));
 
     // face values (every right-hand side of a batch from its own moments)
@@ -493,7 +492,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         AtomDev* dat = nullptr;
         if (lasto_status e = stage_atoms(g, nbat * o.n_atoms, o.atoms, 1, "lasto_poisson_solve", &dat); e != LASTO_OK)
             return e;
-        for (int b = 0; b < nbat; ++b) HIPCHK(launch_guess(g, dat + (size_t)b * o.n_atoms, o.n_atoms, v + b * Ncopy));
+        HIPCHK(launch_guess_all(g, dat, o.atoms, o.n_atoms, v));
         if (o.guess == 3) {
             int acc = 0;
             if (lasto_status e = judge_batch(g, o.guess_net, rho, v, nullptr, &acc); e != LASTO_OK) return e;
@@ -851,15 +850,21 @@ static lasto_status learned_scratch(lasto_grid g)
     return LASTO_OK;
 }
 
+// rho in the split layout in the learned scratch, for smooth_nat
+static lasto_status stage_rho_split(lasto_grid g, const double* rho)
+{
+    HIPCHK(launch_nat_to_split(g->lev[0].view, rho, g->lscr[LS_SF], g->stream));
+    return LASTO_OK;
+}
+
 // one red-black sweep on A v = 4 pi rho in place on natural v (faces kept),
-// through the split layout in the learned scratch
-static lasto_status smooth_nat(lasto_grid g, const double* rho, double* v)
+// through the split layout in the learned scratch (rho staged there first)
+static lasto_status smooth_nat(lasto_grid g, double* v)
 {
     const LevelView& V = g->lev[0].view;
     double* su = g->lscr[LS_SU];
     double* sf = g->lscr[LS_SF];
     HIPCHK(launch_nat_to_split(V, v, su, g->stream));
-    HIPCHK(launch_nat_to_split(V, rho, sf, g->stream));
     HIPCHK(launch_half_keep_faces<double>(V, su, sf, 0, 4.0 * kPi, g->stream));
     HIPCHK(launch_half_keep_faces<double>(V, su, sf, 1, 4.0 * kPi, g->stream));
     HIPCHK(launch_split_to_nat(V, su, v, g->stream));
@@ -877,23 +882,23 @@ static lasto_status judge(lasto_grid g, const double* rho, double* v, const floa
     const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
     const size_t nn = (size_t)V.nx * V.ny * V.nz;
+    // the plain candidate is swept in a copy, the learned one in v itself,
+    // and the plain one goes back to v only if it wins
     double* keep_plain = g->lscr[LS_PLAIN];
-    double* keep_learned = g->lscr[LS_LEARNED];
     if (lasto_status e = resid_norm2(g, rho, v, 1, S_R0); e != LASTO_OK) return e;
     HIPCHK(hipMemcpyAsync(keep_plain, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    if (lasto_status e = stage_rho_split(g, rho); e != LASTO_OK) return e;
     if (y) HIPCHK(launch_add_f32_nat(V, v, y, cscale, s));
-    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
+    if (lasto_status e = smooth_nat(g, v); e != LASTO_OK) return e;
     if (lasto_status e = resid_norm2(g, rho, v, 0, S_TMP); e != LASTO_OK) return e;
-    HIPCHK(hipMemcpyAsync(keep_learned, v, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(v, keep_plain, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
-    if (lasto_status e = resid_norm2(g, rho, v, 0, S_RR); e != LASTO_OK) return e;
+    if (lasto_status e = smooth_nat(g, keep_plain); e != LASTO_OK) return e;
+    if (lasto_status e = resid_norm2(g, rho, keep_plain, 0, S_RR); e != LASTO_OK) return e;
     if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
     const double r0 = std::sqrt(g->h_scalars[S_R0]);
     const double plain = r0 > 0.0 ? std::sqrt(g->h_scalars[S_RR]) / r0 : 0.0;
     const double learned = r0 > 0.0 ? std::sqrt(g->h_scalars[S_TMP]) / r0 : 0.0;
     const bool keep = y && std::isfinite(learned) && learned < plain;
-    if (keep) HIPCHK(hipMemcpyAsync(v, keep_learned, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    if (!keep) HIPCHK(hipMemcpyAsync(v, keep_plain, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     if (rel) {
         rel[0] = plain;
@@ -915,18 +920,18 @@ static lasto_status judge_batch(lasto_grid g, lasto_net n, const double* rho, do
     const int nb = g->n_batch;
     const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
     hipStream_t s = g->stream;
+    // the plain candidates are swept in a copy, the learned ones in v
+    // itself, and a plain one goes back to v only where it wins
     double* keep_plain = g->lscr[LS_PLAIN];
-    double* keep_learned = g->lscr[LS_LEARNED];
     if (lasto_status e = batch_norms(g, rho, v, 1, S_BR0); e != LASTO_OK) return e;
     HIPCHK(hipMemcpyAsync(keep_plain, v, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
+    if (lasto_status e = stage_rho_split(g, rho); e != LASTO_OK) return e;
     for (int b = 0; b < nb; ++b)
         if (lasto_status e = net_guess_apply(g, n, rho + b * N, v + b * N); e != LASTO_OK) return e;
-    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
+    if (lasto_status e = smooth_nat(g, v); e != LASTO_OK) return e;
     if (lasto_status e = batch_norms(g, rho, v, 0, S_BRR); e != LASTO_OK) return e;
-    HIPCHK(hipMemcpyAsync(keep_learned, v, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(v, keep_plain, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
-    if (lasto_status e = smooth_nat(g, rho, v); e != LASTO_OK) return e;
-    if (lasto_status e = batch_norms(g, rho, v, 0, S_BJ); e != LASTO_OK) return e;
+    if (lasto_status e = smooth_nat(g, keep_plain); e != LASTO_OK) return e;
+    if (lasto_status e = batch_norms(g, rho, keep_plain, 0, S_BJ); e != LASTO_OK) return e;
     if (lasto_status e = read_scalars(g, 0, kNumScalars); e != LASTO_OK) return e;
     int acc = 0;
     for (int b = 0; b < nb; ++b) {
@@ -937,10 +942,8 @@ static lasto_status judge_batch(lasto_grid g, lasto_net n, const double* rho, do
             rel[2 * b] = plain;
             rel[2 * b + 1] = learned;
         }
-        if (std::isfinite(learned) && learned < plain) {
-            HIPCHK(hipMemcpyAsync(v + b * N, keep_learned + b * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-            ++acc;
-        }
+        if (std::isfinite(learned) && learned < plain) ++acc;
+        else HIPCHK(hipMemcpyAsync(v + b * N, keep_plain + b * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     if (accepted) *accepted = acc;

@@ -357,6 +357,152 @@ hipError_t launch_guess(lasto_grid g, const AtomDev* atoms, int n_atoms, double*
     return hipGetLastError();
 }
 
+// The same guess for NB right-hand sides whose atoms share every centre,
+// width, radius and kind and differ only in charge (the perturbations of one
+// structure): each node-atom pair's potential shape is evaluated once and
+// scaled by the NB charges, the same FP32 operations per copy as k_guess in
+// the same order from the same origins (so the same bits). atoms:
+// [NB][n_atoms] (copy-major);
+// copy b of v at v + b * N.
+constexpr int GB_Z = 2;
+
+template <int NB>
+__global__ __launch_bounds__(GU_NT) void k_guess_shared(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
+                                                        size_t N, double* __restrict__ v)
+{
+    __shared__ float4 sc[GU_CHUNK];     // atom centre relative to the origin; w unused
+    __shared__ float4 sp[GU_CHUNK];     // as in k_guess
+    __shared__ float sq[GU_CHUNK][NB];  // the charge of the atom in each copy
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int i0 = 1 + blockIdx.x * GU_X, j0 = 1 + blockIdx.y * GU_Y, k0 = 1 + blockIdx.z * GB_Z;
+    const int i = i0 + (threadIdx.x & (GU_X - 1)), j = j0 + (int)(threadIdx.x / GU_X);
+    const bool live = i <= nx - 2 && j <= ny - 2;
+    // the origin of k_guess's workgroup holding these planes (same roundings)
+    static_assert(GU_Z % GB_Z == 0, "a guess workgroup's planes split evenly");
+    const int ko = 1 + (blockIdx.z / (GU_Z / GB_Z)) * GU_Z;
+    const double ox = L.ax[0].x[i0], oy = L.ax[1].x[j0], oz = L.ax[2].x[ko];
+    const float fx = (float)(L.ax[0].x[min(i, nx - 2)] - ox), fy = (float)(L.ax[1].x[min(j, ny - 2)] - oy);
+    float fz[GB_Z];
+#pragma unroll
+    for (int t = 0; t < GB_Z; ++t) fz[t] = (float)(L.ax[2].x[min(k0 + t, nz - 2)] - oz);
+    double acc[GB_Z][NB];
+#pragma unroll
+    for (int t = 0; t < GB_Z; ++t)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[t][b] = 0.0;
+    constexpr float kTwoOverSqrtPi = 1.12837916709551257f;
+    for (int a0 = 0; a0 < n_atoms; a0 += GU_CHUNK) {
+        const int na = min(GU_CHUNK, n_atoms - a0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < na; t += GU_NT) {
+            const AtomDev& A = atoms[a0 + t];
+            sc[t] = make_float4((float)(A.c[0] - ox), (float)(A.c[1] - oy), (float)(A.c[2] - oz), 0.0f);
+            if (A.kind == 0)
+                sp[t] = make_float4((float)(36.0 * A.w * A.w), (float)(1.0 / A.w), 0.0f, 0.0f);
+            else
+                sp[t] = make_float4((float)(A.R * A.R), 0.0f, (float)(3.0 * A.R * A.R),
+                                    (float)(0.5 / (A.R * A.R * A.R)));
+#pragma unroll
+            for (int b = 0; b < NB; ++b) sq[t][b] = (float)atoms[(size_t)b * n_atoms + a0 + t].q;
+        }
+        __syncthreads();
+        for (int a1 = 0; a1 < na; a1 += GU_PART) {
+            float part[GB_Z][NB];
+#pragma unroll
+            for (int t = 0; t < GB_Z; ++t)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) part[t][b] = 0.0f;
+            const int a2 = min(a1 + GU_PART, na);
+            for (int a = a1; a < a2; ++a) {
+                const float4 c = sc[a];
+                const float4 p = sp[a];
+                const float dx = fx - c.x, dy = fy - c.y;
+                const float dxy = fmaf(dx, dx, dy * dy);
+#pragma unroll
+                for (int t = 0; t < GB_Z; ++t) {
+                    const float dz = fz[t] - c.z;
+                    const float r2 = fmaf(dz, dz, dxy);
+                    float f;
+                    if (r2 >= p.x) {
+                        f = __builtin_amdgcn_rsqf(r2);
+                    } else if (p.y > 0.0f) {
+                        const float r = sqrtf(r2);
+                        f = r > 1e-6f / p.y ? erff(r * p.y) / r : kTwoOverSqrtPi * p.y;
+                    } else {
+                        f = (p.z - r2) * p.w;
+                    }
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) part[t][b] = fmaf(-sq[a][b], f, part[t][b]);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < GB_Z; ++t)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[t][b] += (double)part[t][b];
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int t = 0; t < GB_Z; ++t)
+        if (k0 + t <= nz - 2) {
+            const size_t at = ((size_t)(k0 + t) * ny + j) * nx + i;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) v[(size_t)b * N + at] = acc[t][b];
+        }
+}
+
+template <int NB>
+static hipError_t launch_guess_shared(lasto_grid g, const AtomDev* atoms, int n_atoms, double* v)
+{
+    const LevelView& L = g->cview;
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    const dim3 grid((L.nx - 2 + GU_X - 1) / GU_X, (L.ny - 2 + GU_Y - 1) / GU_Y, (L.nz - 2 + GB_Z - 1) / GB_Z);
+    hipLaunchKernelGGL(k_guess_shared<NB>, grid, dim3(GU_NT), 0, g->stream, L, atoms, n_atoms, N, v);
+    return hipGetLastError();
+}
+
+// the guess of every right-hand side of the grid: copies whose atoms share
+// their geometry with copy 0 of their group of up to 8 go through one pass
+hipError_t launch_guess_all(lasto_grid g, const AtomDev* dev_atoms, const lasto_atom* host_atoms, int n_atoms,
+                            double* v)
+{
+    const int nb = g->n_batch;
+    const size_t N = (size_t)g->cview.nx * g->cview.ny * g->cview.nz;
+    auto same_geometry = [&](int b) {
+        for (int a = 0; a < n_atoms; ++a) {
+            const lasto_atom& x = host_atoms[(size_t)b * n_atoms + a];
+            const lasto_atom& y = host_atoms[a];
+            if (x.center[0] != y.center[0] || x.center[1] != y.center[1] || x.center[2] != y.center[2] ||
+                x.kind != y.kind || x.width != y.width || x.radius != y.radius)
+                return false;
+        }
+        return true;
+    };
+    bool shared = nb > 1;
+    for (int b = 1; b < nb && shared; ++b) shared = same_geometry(b);
+    int b = 0;
+    if (shared) {
+        for (; b + 8 <= nb; b += 8) {
+            hipError_t e = launch_guess_shared<8>(g, dev_atoms + (size_t)b * n_atoms, n_atoms, v + b * N);
+            if (e != hipSuccess) return e;
+        }
+        for (; b + 4 <= nb; b += 4) {
+            hipError_t e = launch_guess_shared<4>(g, dev_atoms + (size_t)b * n_atoms, n_atoms, v + b * N);
+            if (e != hipSuccess) return e;
+        }
+        for (; b + 2 <= nb; b += 2) {
+            hipError_t e = launch_guess_shared<2>(g, dev_atoms + (size_t)b * n_atoms, n_atoms, v + b * N);
+            if (e != hipSuccess) return e;
+        }
+    }
+    for (; b < nb; ++b) {
+        hipError_t e = launch_guess(g, dev_atoms + (size_t)b * n_atoms, n_atoms, v + b * N);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+
 // --------------------------------------------------------------- moments
 // Q_lm = sum_n vol_n rho_n S_lm(x_n - c), l <= 4, by rows: along a row (j, k)
 // dy and dz are fixed and S_lm(dx, dy, dz) is a polynomial of degree <= l in

@@ -2,6 +2,7 @@
 same seeded inputs, element by element at sizes the oracle finishes in
 seconds (spanning several tiles, with ragged tails), and through properties
 at the full 257^3 size."""
+import dataclasses
 import math
 import sys
 
@@ -480,6 +481,29 @@ def test_analytic_guess_matches_closed_form(torch, L):
     # terms, no discretisation) is ~1e-3
     assert err <= 40 * 2.0 ** -24
     g.close()
+
+
+@pytest.mark.parametrize("nb,shared", [(8, True), (3, True), (2, False)])
+def test_batched_analytic_guess_matches_each_copy(torch, L, nb, shared):
+    """Copies whose atoms differ only in charge share one pass over the
+    node-atom pairs (groups of 8, 4, 2, then single copies); every copy's
+    guess equals, bit for bit, the guess of a grid holding that copy alone,
+    and so does a batch whose copies differ in geometry."""
+    say("batched analytic guess, %d copies, shared geometry %s" % (nb, shared))
+    w = I.config(2, n_override=57)
+    xs = L.mesh_for(w.axes)
+    if shared:
+        batch = [I.perturb_atoms(w.atoms, 90 + b, rel=0.05) for b in range(nb)]
+    else:
+        batch = [w.atoms, [dataclasses.replace(a, center=a.center + 0.3) for a in w.atoms]]
+    gb = L.Grid(*xs, n_batch=nb)
+    vb = gb.analytic_guess(batch, gb.empty())
+    g1 = L.Grid(*xs)
+    for b in range(nb):
+        v1 = g1.analytic_guess(batch[b], g1.empty())
+        assert torch.equal(v1, vb[b]), b
+    g1.close()
+    gb.close()
 
 
 def test_analytic_guess_many_atoms_matches_closed_form(torch, L):
