@@ -583,66 +583,92 @@ int interior_blocks(const LevelView& L)
 // Fine level, natural v and rho: r = bscale rho - A v (r in the split
 // layout, FP64 or FP32, when given) and partials of ||r||_W^2. IZ: the
 // interior of v is read as zero (the reference residual of the face data
-// alone). Each thread marches its (i, j) column up its chunk of planes: the
-// centre values of planes k-1, k, k+1 stay in registers, and plane k+1's x
-// and y neighbours and rho are loaded before plane k is computed, so two
-// planes' loads are in flight.
+// alone: only rho and the face values next to a node are read). Each thread
+// marches its (i, j) column up its chunk of planes: the centre values of
+// planes k-1, k, k+1 stay in registers, a wave covers 64 consecutive nodes
+// of a row, so the x neighbours are the adjacent lanes' centres (a lane at
+// either end of the wave loads its outer neighbour), and plane k+1's y
+// neighbours and rho are loaded before plane k is computed.
 template <typename TO, bool IZ>
 __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, const double* __restrict__ v,
                                                           const double* __restrict__ rho, double bscale,
                                                           TO* __restrict__ r, double* __restrict__ part)
 {
+    static_assert(PT_X == 64, "a wave covers one row segment");
     __shared__ double red[PT_NT / 64];
     double acc = 0.0;
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);
+    const int lane = threadIdx.x % PT_X;
+    const int i = 1 + blockIdx.x * PT_X + lane;
     const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
     const int kb = 1 + blockIdx.z * kp;
     const int ke = min(kb + kp, L.nz - 1);
-    if (i <= L.nx - 2 && j <= L.ny - 2) {
-        const int nx = L.nx;
-        const size_t sxy = (size_t)nx * L.ny;
-        const size_t col = (size_t)j * nx + i;
-        const double cxm = L.ax[0].am[i], cxp = L.ax[0].ap[i], cym = L.ax[1].am[j], cyp = L.ax[1].ap[j];
-        const double vxy = L.ax[0].m[i] * L.ax[1].m[j];
-        struct Ops {
-            double xm, xp, ym, yp, b;
-        };
-        auto load = [&](int k) {
-            Ops o;
-            const size_t idx = (size_t)k * sxy + col;
-            o.xm = v[idx - 1];
-            o.xp = v[idx + 1];
-            o.ym = v[idx - nx];
-            o.yp = v[idx + nx];
-            o.b = rho[idx];
-            return o;
-        };
-        double zm = v[(size_t)(kb - 1) * sxy + col], zc = v[(size_t)kb * sxy + col];
-        Ops A = load(kb);
-        for (int k = kb; k < ke; ++k) {
-            const double zp = v[(size_t)(k + 1) * sxy + col];
-            Ops B = A;
-            if (k + 1 < ke) B = load(k + 1);
-            if (L.zint[k]) {
-                double a;
-                if (IZ) {
-                    // only neighbours on a face (of this copy) keep their values
-                    a = (i == 1 ? cxm * A.xm : 0.0) + (i == nx - 2 ? cxp * A.xp : 0.0);
-                    a += (j == 1 ? cym * A.ym : 0.0) + (j == L.ny - 2 ? cyp * A.yp : 0.0);
-                    a += (!L.zint[k - 1] ? L.ax[2].am[k] * zm : 0.0) + (!L.zint[k + 1] ? L.ax[2].ap[k] * zp : 0.0);
-                } else {
-                    a = cxm * (A.xm - zc) + cxp * (A.xp - zc);
-                    a += cym * (A.ym - zc) + cyp * (A.yp - zc);
-                    a += L.ax[2].am[k] * (zm - zc) + L.ax[2].ap[k] * (zp - zc);
-                }
-                const double res = bscale * A.b - a;
-                if (r) r[sidx(L, i, j, k)] = (TO)res;
-                acc += vxy * L.ax[2].m[k] * res * res;
-            }
-            zm = zc;
-            zc = zp;
-            A = B;
+    const int nx = L.nx;
+    // every lane of a row that exists takes part in the shuffles: lanes past
+    // the row's last interior node hold the face value (or a clamped copy)
+    const bool row_ok = j <= L.ny - 2;
+    const bool inside = row_ok && i <= nx - 2;
+    const int ic = min(i, nx - 1);
+    const size_t sxy = (size_t)nx * L.ny;
+    const size_t col = (size_t)min(j, L.ny - 1) * nx + ic;
+    const double cxm = L.ax[0].am[min(i, nx - 2)], cxp = L.ax[0].ap[min(i, nx - 2)];
+    const double cym = L.ax[1].am[min(j, L.ny - 2)], cyp = L.ax[1].ap[min(j, L.ny - 2)];
+    const double vxy = L.ax[0].m[min(i, nx - 2)] * L.ax[1].m[min(j, L.ny - 2)];
+    const bool first = lane == 0, last = lane == PT_X - 1;
+    struct Ops {
+        double ym, yp, b, xo;   // xo: the outer x neighbour of an end lane
+    };
+    auto load = [&](int k) {
+        Ops o;
+        const size_t idx = (size_t)k * sxy + col;
+        o.b = inside ? rho[idx] : 0.0;
+        if (IZ) {
+            o.ym = (inside && j == 1) ? v[idx - nx] : 0.0;
+            o.yp = (inside && j == L.ny - 2) ? v[idx + nx] : 0.0;
+            o.xo = (inside && ((first && i == 1) || (last && i == nx - 2))) ? v[first ? idx - 1 : idx + 1] : 0.0;
+        } else {
+            o.ym = inside ? v[idx - nx] : 0.0;
+            o.yp = inside ? v[idx + nx] : 0.0;
+            o.xo = (inside && (first || last)) ? v[first ? idx - 1 : idx + 1] : 0.0;
         }
+        return o;
+    };
+    // centres of planes k-1, k, k+1 (IZ: only face planes are not zero)
+    auto centre = [&](int k) -> double {
+        if (!row_ok) return 0.0;
+        if (IZ) {
+            const bool face_x = ic == 0 || ic == nx - 1;
+            if (!face_x && L.zint[k]) return 0.0;
+        }
+        return v[(size_t)k * sxy + col];
+    };
+    double zm = centre(kb - 1), zc = centre(kb);
+    Ops A = load(kb);
+    for (int k = kb; k < ke; ++k) {
+        const double zp = centre(k + 1);
+        Ops B = A;
+        if (k + 1 < ke) B = load(k + 1);
+        // x neighbours from the adjacent lanes' centres
+        const double sl = __shfl_up(zc, 1, 64), sr = __shfl_down(zc, 1, 64);
+        const double xm = first ? A.xo : sl, xp = last ? A.xo : sr;
+        if (inside && L.zint[k]) {
+            double a;
+            if (IZ) {
+                // only neighbours on a face (of this copy) keep their values
+                a = (i == 1 ? cxm * xm : 0.0) + (i == nx - 2 ? cxp * xp : 0.0);
+                a += (j == 1 ? cym * A.ym : 0.0) + (j == L.ny - 2 ? cyp * A.yp : 0.0);
+                a += (!L.zint[k - 1] ? L.ax[2].am[k] * zm : 0.0) + (!L.zint[k + 1] ? L.ax[2].ap[k] * zp : 0.0);
+            } else {
+                a = cxm * (xm - zc) + cxp * (xp - zc);
+                a += cym * (A.ym - zc) + cyp * (A.yp - zc);
+                a += L.ax[2].am[k] * (zm - zc) + L.ax[2].ap[k] * (zp - zc);
+            }
+            const double res = bscale * A.b - a;
+            if (r) r[sidx(L, i, j, k)] = (TO)res;
+            acc += vxy * L.ax[2].m[k] * res * res;
+        }
+        zm = zc;
+        zc = zp;
+        A = B;
     }
     const double t = block_sum<PT_NT>(acc, red);
     if (threadIdx.x == 0) part[block_linear()] = t;
