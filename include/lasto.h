@@ -198,6 +198,8 @@ typedef struct {
                            of the library's own) and replayed after, one host call in place of every level's
                            launches; same kernels in the same order, so the same bits. 1: every launch from
                            the host. (profile = 1 and a learned coarse correction always launch eagerly) */
+    int nu_coarse;      /* > 0: red-black sweeps before and after the coarse correction on every level below
+                           the finest (the finest keeps nu1, nu2); 0 (default): nu1, nu2 on every level */
 } lasto_solve_opts;
 
 typedef struct {

@@ -281,6 +281,7 @@ struct lasto_grid_s {
     double* cfdm_tab64 = nullptr;     // device: per axis S^-1, S, eigenvalues
     float* cfdm_tab32 = nullptr;
     int coarse_mode = 0;              // the current solve's opts.coarse
+    int nu_coarse = 0;                // the current solve's opts.nu_coarse
     // the exact coarsest solve by GEMMs on a larger level (tables built on
     // first use; cg_level -1: no level qualifies)
     int cg_level = -1;
@@ -292,7 +293,7 @@ struct lasto_grid_s {
     // every level's launches), keyed by precision, sweeps and coarse mode;
     // captured on a stream of the library's own at their second use
     struct VGraph {
-        int key[4];
+        int key[5];
         const void* f;
         void* u;
         double* dotp;

@@ -157,7 +157,9 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     const double cfrac = l == 0 ? interior_pts(C.view) / interior_pts(V) : 0.0;
     count(g, l, 0.5 * 4 * sizeof(T));
     count(g, l, (0.5 + cfrac) * sizeof(T));
-    lasto_status st = vcycle_level<T>(g, l + 1, nu1, nu2, Buf<T>::f(C), Buf<T>::u(C), nullptr, nullptr);
+    // levels below the finest take nu_coarse sweeps each way when it is set
+    const int nc1 = g->nu_coarse > 0 ? g->nu_coarse : nu1, nc2 = g->nu_coarse > 0 ? g->nu_coarse : nu2;
+    lasto_status st = vcycle_level<T>(g, l + 1, nc1, nc2, Buf<T>::f(C), Buf<T>::u(C), nullptr, nullptr);
     if (st != LASTO_OK) return st;
     // a post-smoothing that starts with a black half-sweep recomputes every
     // black value, so only red nodes take the interpolated correction
@@ -193,13 +195,13 @@ template <typename T>
 static lasto_status vcycle0(lasto_grid g, const lasto_solve_opts& o, const T* f, T* u, double* dotp, int* ndot)
 {
     if (o.eager || g->prof_on || g->lc_net) return vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, ndot);
-    const int key[4] = {(int)sizeof(T), o.nu1, o.nu2, g->coarse_mode};
+    const int key[5] = {(int)sizeof(T), o.nu1, o.nu2, g->coarse_mode, g->nu_coarse};
     lasto_grid_s::VGraph* e = nullptr;
     for (auto& v : g->vgraphs)
-        if (std::equal(key, key + 4, v.key) && v.f == f && v.u == u && v.dotp == dotp) e = &v;
+        if (std::equal(key, key + 5, v.key) && v.f == f && v.u == u && v.dotp == dotp) e = &v;
     if (!e) {
         lasto_grid_s::VGraph v;
-        std::copy(key, key + 4, v.key);
+        std::copy(key, key + 5, v.key);
         v.f = f;
         v.u = u;
         v.dotp = dotp;
@@ -424,10 +426,10 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
         o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 3 || (o.precision == 1 && o.inner_iters < 1) ||
         o.inner_first < 0 || o.coarse < 0 || o.coarse > 2 || o.fallback < 0 || o.fallback > 1 ||
-        !(o.inner_rate >= 0.0 && o.inner_rate < 1.0))
+        !(o.inner_rate >= 0.0 && o.inner_rate < 1.0) || o.nu_coarse < 0)
         return fail(LASTO_ERR_ARG,
                     "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters/coarse/fallback/"
-                    "inner_rate");
+                    "inner_rate/nu_coarse");
     if (o.guess >= 2 && (o.n_atoms < 1 || !o.atoms))
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: guess 2 and 3 need the atom tables");
     if (o.guess == 3 && !o.guess_net) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: guess 3 needs guess_net");
@@ -466,8 +468,13 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     g->alg_bytes = 0.0;
     struct ProfOff {
         lasto_grid g;
-        ~ProfOff() { g->prof_on = false; }
+        ~ProfOff()
+        {
+            g->prof_on = false;
+            g->nu_coarse = 0;
+        }
     } prof_off{g};
+    g->nu_coarse = o.nu_coarse;
     for (hipEvent_t& e : g->ph_ev)
         if (!e) HIPCHK(hipEventCreate(&e));
     Level& L0 = g->lev[0];
@@ -981,14 +988,16 @@ static lasto_status coarse_net_check(lasto_grid g, const lasto_solve_opts& o)
 // (the exact LDS solve below when the level allows it, else the tail)
 lasto_status lasto::coarse_cycles(lasto_grid g, int c, int cycles, const double* f, double* u)
 {
-    const int mode = g->coarse_mode;
+    const int mode = g->coarse_mode, nuc = g->nu_coarse;
     lasto_net lc = g->lc_net;
     g->coarse_mode = (g->cfdm_level > c) ? 2 : 1;
     g->lc_net = nullptr;
+    g->nu_coarse = 0;
     lasto_status st = LASTO_OK;
     for (int k = 0; k < cycles && st == LASTO_OK; ++k)
         st = vcycle_level<double>(g, c, 2, 2, f, u, nullptr, nullptr, k == 0);
     g->coarse_mode = mode;
+    g->nu_coarse = nuc;
     g->lc_net = lc;
     return st;
 }

@@ -70,6 +70,7 @@ class SolveOpts(C.Structure):
         ("coarse_net_level", C.c_int),
         ("inner_rate", C.c_double),
         ("eager", C.c_int),
+        ("nu_coarse", C.c_int),
     ]
 
 

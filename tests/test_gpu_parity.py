@@ -156,6 +156,10 @@ SOLVE_CASES = [
     (2, 129, dict()),
     (2, 129, dict(precision=1)),
     (2, 129, dict(precision=1, method=1)),
+    # more sweeps below the finest level than on it (coarse = 2 keeps levels
+    # between the finest and the exact solve, where nu_coarse applies)
+    (3, 129, dict(precision=1, nu1=3, nu2=3, nu_coarse=4, inner_first=4, inner_iters=8, inner_rate=0.05, coarse=2)),
+    (3, 129, dict(nu1=2, nu2=2, nu_coarse=3, coarse=2)),
     (4, 65, dict()),
     (4, 65, dict(precision=1, method=1)),
     # the red-black tail instead of the exact coarsest solve
