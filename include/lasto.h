@@ -193,11 +193,13 @@ typedef struct {
                            of two or more PCG steps it becomes that refinement's own per-step decrease of
                            sqrt(<r, z>_W); after a later refinement that reduced the true residual by less
                            than 1e-5 it rises to that reduction per step when slower */
-    int eager;          /* 0 (default): the finest-level V-cycle of the CG forms is captured into a HIP graph
-                           at its second use on a grid (per precision, nu1, nu2 and coarse mode; on a stream
-                           of the library's own) and replayed after, one host call in place of every level's
-                           launches; same kernels in the same order, so the same bits. 1: every launch from
-                           the host. (profile = 1 and a learned coarse correction always launch eagerly) */
+    int graphs;         /* 1: the inner FP32 PCG's steps (their V-cycle, reductions and updates) and the FP64
+                           CG's finest-level V-cycle are captured into HIP graphs at their second use on a
+                           grid (keyed by what they launch; on a stream of the library's own) and replayed
+                           after, one host call in place of each sequence's launches; same kernels in the same
+                           order, so the same bits. 0 (default): every launch from the host, which measured as
+                           fast or faster at 257^3 and 513^3 (the GPU, not the host, bounds these solves).
+                           profile = 1 and a learned coarse correction always launch from the host */
     int nu_coarse;      /* > 0: red-black sweeps before and after the coarse correction on every level below
                            the finest (the finest keeps nu1, nu2); 0 (default): nu1, nu2 on every level */
 } lasto_solve_opts;

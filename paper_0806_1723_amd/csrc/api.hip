@@ -90,8 +90,20 @@ lasto_status lasto::stage_atoms(lasto_grid g, int n_atoms, const lasto_atom* ato
         LASTO_HIP(hipMalloc(&g->stage, bytes));
         g->stage_bytes = bytes;
     }
+    // the upload goes from pinned memory, so it does not wait for the
+    // stream's earlier work (the previous call finished before returning, so
+    // the pinned copy is free)
+    if (bytes > g->stage_host_bytes) {
+        (void)hipStreamSynchronize(g->stream);
+        if (g->stage_host) (void)hipHostFree(g->stage_host);
+        g->stage_host = nullptr;
+        g->stage_host_bytes = 0;
+        LASTO_HIP(hipHostMalloc(&g->stage_host, std::max(bytes, (size_t)1 << 16)));
+        g->stage_host_bytes = std::max(bytes, (size_t)1 << 16);
+    }
+    std::memcpy(g->stage_host, hv.data(), bytes);
     AtomDev* dat = (AtomDev*)g->stage;
-    LASTO_HIP(hipMemcpyAsync(dat, hv.data(), bytes, hipMemcpyHostToDevice, g->stream));
+    LASTO_HIP(hipMemcpyAsync(dat, g->stage_host, bytes, hipMemcpyHostToDevice, g->stream));
     if (n_atoms > 0) LASTO_HIP(launch_atom_prep(g, dat, n_atoms, renormalize));
     *out = dat;
     return LASTO_OK;

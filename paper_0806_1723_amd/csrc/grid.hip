@@ -284,6 +284,8 @@ static void free_grid(lasto_grid g)
         a = nullptr;
     }
     if (g->h_scalars) (void)hipHostFree(g->h_scalars);
+    if (g->stage_host) (void)hipHostFree(g->stage_host);
+    g->stage_host = nullptr;
     for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : g->ph_ev)
         if (e) (void)hipEventDestroy(e);

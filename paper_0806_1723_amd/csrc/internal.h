@@ -272,6 +272,8 @@ struct lasto_grid_s {
     // interpolation / atom staging
     double* stage = nullptr;
     size_t stage_bytes = 0;
+    void* stage_host = nullptr;       // pinned host copy of the staged atom table (an async upload)
+    size_t stage_host_bytes = 0;
     double box_center[3] = {0, 0, 0};
     lasto::FdmState* fdm = nullptr;   // built on the first lasto_fdm_solve
     // coarsest solve of the cycle by fast diagonalisation (cfdm_level -1: the
@@ -289,18 +291,17 @@ struct lasto_grid_s {
     // optional event timing of the finest-level sweeps (solve opts.profile)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;   // start/stop pairs
-    // finest-level V-cycles captured into HIP graphs (replayed in place of
-    // every level's launches), keyed by precision, sweeps and coarse mode;
-    // captured on a stream of the library's own at their second use
+    // launch sequences captured into HIP graphs (the finest-level V-cycle,
+    // a step of the inner FP32 PCG) and replayed in place of their launches,
+    // keyed by what they do and the arrays they touch; captured on a stream
+    // of the library's own at their second use
     struct VGraph {
-        int key[5];
-        const void* f;
-        void* u;
-        double* dotp;
+        int key[8];
+        const void* ptr[4];
         int uses = 0;
         hipGraphExec_t exec = nullptr;
-        int ndot = 0;
-        double bytes = 0.0;
+        int aux = 0;          // an int the sequence reports (the V-cycle's partial count)
+        double bytes = 0.0;   // algorithmic bytes it counts
     };
     std::vector<VGraph> vgraphs;
     hipStream_t cap_stream = nullptr;

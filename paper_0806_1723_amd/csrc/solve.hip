@@ -185,44 +185,42 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     return LASTO_OK;
 }
 
-// The finest-level V-cycle of the CG forms (fixed operands every step),
-// replayed from a HIP graph unless `eager`: the first use on a grid for a
-// key launches eagerly (lazy tables, library workspaces and static launch
-// shapes are set up outside any capture), the second captures the cycle on
-// the library's own stream and replays it, and later uses replay. Algorithmic
-// bytes and partial counts are those the capture recorded.
-template <typename T>
-static lasto_status vcycle0(lasto_grid g, const lasto_solve_opts& o, const T* f, T* u, double* dotp, int* ndot)
+// A launch sequence `body` (launches on g->stream only, no host reads)
+// replayed from a HIP graph: the first use for a key runs eagerly (lazy
+// tables, library workspaces and static launch shapes are set up outside any
+// capture), the second captures the sequence on the library's own stream and
+// replays it, and later uses replay. The int the body reports and the
+// algorithmic bytes it counts are those of the capture.
+template <typename Body>
+static lasto_status graphed(lasto_grid g, const int (&key)[8], const void* const (&ptr)[4], Body body, int* aux)
 {
-    if (o.eager || g->prof_on || g->lc_net) return vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, ndot);
-    const int key[5] = {(int)sizeof(T), o.nu1, o.nu2, g->coarse_mode, g->nu_coarse};
     lasto_grid_s::VGraph* e = nullptr;
     for (auto& v : g->vgraphs)
-        if (std::equal(key, key + 5, v.key) && v.f == f && v.u == u && v.dotp == dotp) e = &v;
+        if (std::equal(key, key + 8, v.key) && std::equal(ptr, ptr + 4, v.ptr)) e = &v;
     if (!e) {
         lasto_grid_s::VGraph v;
-        std::copy(key, key + 5, v.key);
-        v.f = f;
-        v.u = u;
-        v.dotp = dotp;
+        std::copy(key, key + 8, v.key);
+        std::copy(ptr, ptr + 4, v.ptr);
         g->vgraphs.push_back(v);
         e = &g->vgraphs.back();
     }
+    int tmp = 0;
+    if (!aux) aux = &tmp;
     if (e->exec) {
         HIPCHK(hipGraphLaunch(e->exec, g->stream));
         g->alg_bytes += e->bytes;
-        if (ndot) *ndot = e->ndot;
+        *aux = e->aux;
         return LASTO_OK;
     }
-    if (e->uses++ == 0) return vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, ndot);
+    if (e->uses++ == 0) return body(aux);
     if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
     hipStream_t keep = g->stream;
     const double b0 = g->alg_bytes;
     HIPCHK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
     g->stream = g->cap_stream;
     coarse_gemm_set_stream(g, g->cap_stream);
-    int nd = 0;
-    const lasto_status st = vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, &nd);
+    int got = 0;
+    const lasto_status st = body(&got);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(g->cap_stream, &graph);
     g->stream = keep;
@@ -230,18 +228,33 @@ static lasto_status vcycle0(lasto_grid g, const lasto_solve_opts& o, const T* f,
     if (st != LASTO_OK || ec != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
         if (st != LASTO_OK) return st;
-        return fail(LASTO_ERR_HIP, std::string("vcycle capture: ") + hipGetErrorString(ec));
+        return fail(LASTO_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
     }
     hipGraphExec_t exec = nullptr;
     const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    if (ei != hipSuccess) return fail(LASTO_ERR_HIP, std::string("vcycle graph: ") + hipGetErrorString(ei));
+    if (ei != hipSuccess) return fail(LASTO_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
     e->exec = exec;
-    e->ndot = nd;
+    e->aux = got;
     e->bytes = g->alg_bytes - b0;   // counted while capturing: this use's share
     HIPCHK(hipGraphLaunch(exec, g->stream));
-    if (ndot) *ndot = nd;
+    *aux = got;
     return LASTO_OK;
+}
+
+// whether launch sequences may go through graphs in this solve
+static bool graphs_on(lasto_grid g, const lasto_solve_opts& o) { return o.graphs && !g->prof_on && !g->lc_net; }
+
+// The finest-level V-cycle of the CG forms (fixed operands every step),
+// through a graph when `graphs` is set
+template <typename T>
+static lasto_status vcycle0(lasto_grid g, const lasto_solve_opts& o, const T* f, T* u, double* dotp, int* ndot)
+{
+    auto body = [&](int* nd) { return vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, nd); };
+    if (!graphs_on(g, o)) return body(ndot);
+    const int key[8] = {1, (int)sizeof(T), o.nu1, o.nu2, g->coarse_mode, g->nu_coarse, 0, 0};
+    const void* const ptr[4] = {f, u, dotp, nullptr};
+    return graphed(g, key, ptr, body, ndot);
 }
 
 static lasto_status reduce_to(lasto_grid g, int count, int slot)
@@ -288,60 +301,80 @@ static lasto_status mg32_inner(lasto_grid g, const lasto_solve_opts& o, int cycl
     return LASTO_OK;
 }
 
-// Inner FP32 PCG on A e = r32 from e = 0, `iters` steps, then v += e. The
-// update e += alpha p of each step is deferred into the next step's update
-// of p (which reads the old p anyway); the last step's goes straight into v
-// (v += e + alpha p): its residual is not needed, since the refinement
-// recomputes the true one in FP64.
-static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int iters, int* vcycles, double* v)
+// one step `it` of the inner FP32 PCG (the last when it + 1 == iters)
+static lasto_status pcg32_step(lasto_grid g, const lasto_solve_opts& o, int it, int iters, double* v)
 {
     const LevelView& V = g->lev[0].view;
     hipStream_t s = g->stream;
     float* rr = g->r32;   // working residual, updated in place
+    int nd = 0;
+    lasto_status st = vcycle_level<float>(g, 0, o.nu1, o.nu2, rr, g->z32, g->partials, &nd);
+    if (st != LASTO_OK) return st;
+    // <r, z>_W of every step is kept (the refinement reads the inner
+    // solve's convergence from them)
+    const int srz = S_RZH + it % kInnerHist, srz_old = S_RZH + (it + kInnerHist - 1) % kInnerHist;
+    if (lasto_status e = reduce_to(g, nd, srz); e != LASTO_OK) return e;
+    float* pn = g->p32[it & 1];
+    float* po = g->p32[(it + 1) & 1];
+    if (it == 0) {
+        HIPCHK(launch_update_p<float>(V, g->z32, po, pn, g->scalars, srz, srz_old, 1, s));
+        count(g, 0, 2 * 4.0);
+    } else {
+        int beta_num = srz;
+        if (g->lc_net) {
+            // flexible (Polak-Ribiere) beta under the learned coarse correction
+            HIPCHK(launch_dot<float>(V, g->z32, g->q32, g->partials, s));
+            if (lasto_status e = reduce_to(g, row_blocks(V), S_ZQ32); e != LASTO_OK) return e;
+            HIPCHK(launch_flex_beta(g->scalars, srz_old, S_PQ32, S_ZQ32, S_FNUM32, s));
+            count(g, 0, 8.0);
+            beta_num = S_FNUM32;
+        }
+        // e (=, then +=) alpha_prev p_old, alpha_prev = (r,z) / (p,q) of the previous step
+        HIPCHK(launch_update_px<float>(V, g->z32, po, pn, g->e32, g->scalars, beta_num, srz_old, srz_old, S_PQ32,
+                                       it >= 2, s));
+        count(g, 0, (it >= 2 ? 5 : 4) * 4.0);
+    }
+    int npq = 0;
+    if (lasto_status e = apply_dot<float>(g, pn, g->q32, &npq); e != LASTO_OK) return e;
+    if (lasto_status e = reduce_to(g, npq, S_PQ32); e != LASTO_OK) return e;
+    if (it + 1 == iters) {
+        if (it == 0) {
+            HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
+            count(g, 0, 4.0);
+        }
+        HIPCHK(launch_add32_nat(V, v, g->e32, pn, g->scalars, srz, S_PQ32, s, true));
+        count(g, 0, 8.0 + 16.0);
+        return LASTO_OK;
+    }
+    // (the inner loop never reads its own residual norm)
+    HIPCHK(launch_update_r<float>(V, rr, g->q32, g->scalars, srz, S_PQ32, s));
+    count(g, 0, 3 * 4.0);
+    return LASTO_OK;
+}
+
+// Inner FP32 PCG on A e = r32 from e = 0, `iters` steps, then v += e. The
+// update e += alpha p of each step is deferred into the next step's update
+// of p (which reads the old p anyway); the last step's goes straight into v
+// (v += e + alpha p): its residual is not needed, since the refinement
+// recomputes the true one in FP64. Each step (its V-cycle, reductions and
+// updates) goes through a graph keyed by its index and whether it is the
+// last, when `graphs` is set.
+static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int iters, int* vcycles, double* v)
+{
     for (int it = 0; it < iters; ++it) {
-        int nd = 0;
-        lasto_status st = vcycle0<float>(g, o, rr, g->z32, g->partials, &nd);
+        const bool last = it + 1 == iters;
+        auto body = [&](int*) { return pcg32_step(g, o, it, iters, v); };
+        lasto_status st;
+        if (graphs_on(g, o)) {
+            const int key[8] = {2, it % kInnerHist, last ? 1 : 0, o.nu1, o.nu2, g->coarse_mode, g->nu_coarse,
+                                it >= 2 ? 2 : it};
+            const void* const ptr[4] = {v, g->r32, g->z32, nullptr};
+            st = graphed(g, key, ptr, body, nullptr);
+        } else {
+            st = body(nullptr);
+        }
         if (st != LASTO_OK) return st;
         ++*vcycles;
-        // <r, z>_W of every step is kept (the refinement reads the inner
-        // solve's convergence from them)
-        const int srz = S_RZH + it % kInnerHist, srz_old = S_RZH + (it + kInnerHist - 1) % kInnerHist;
-        if (lasto_status e = reduce_to(g, nd, srz); e != LASTO_OK) return e;
-        float* pn = g->p32[it & 1];
-        float* po = g->p32[(it + 1) & 1];
-        if (it == 0) {
-            HIPCHK(launch_update_p<float>(V, g->z32, po, pn, g->scalars, srz, srz_old, 1, s));
-            count(g, 0, 2 * 4.0);
-        } else {
-            int beta_num = srz;
-            if (g->lc_net) {
-                // flexible (Polak-Ribiere) beta under the learned coarse correction
-                HIPCHK(launch_dot<float>(V, g->z32, g->q32, g->partials, s));
-                if (lasto_status e = reduce_to(g, row_blocks(V), S_ZQ32); e != LASTO_OK) return e;
-                HIPCHK(launch_flex_beta(g->scalars, srz_old, S_PQ32, S_ZQ32, S_FNUM32, s));
-                count(g, 0, 8.0);
-                beta_num = S_FNUM32;
-            }
-            // e (=, then +=) alpha_prev p_old, alpha_prev = (r,z) / (p,q) of the previous step
-            HIPCHK(launch_update_px<float>(V, g->z32, po, pn, g->e32, g->scalars, beta_num, srz_old, srz_old, S_PQ32,
-                                           it >= 2, s));
-            count(g, 0, (it >= 2 ? 5 : 4) * 4.0);
-        }
-        int npq = 0;
-        if (lasto_status e = apply_dot<float>(g, pn, g->q32, &npq); e != LASTO_OK) return e;
-        if (lasto_status e = reduce_to(g, npq, S_PQ32); e != LASTO_OK) return e;
-        if (it + 1 == iters) {
-            if (it == 0) {
-                HIPCHK(launch_fill_zero<float>(g->e32, split_elems(V), s));
-                count(g, 0, 4.0);
-            }
-            HIPCHK(launch_add32_nat(V, v, g->e32, pn, g->scalars, srz, S_PQ32, s, true));
-            count(g, 0, 8.0 + 16.0);
-            break;
-        }
-        // (the inner loop never reads its own residual norm)
-        HIPCHK(launch_update_r<float>(V, rr, g->q32, g->scalars, srz, S_PQ32, s));
-        count(g, 0, 3 * 4.0);
     }
     return LASTO_OK;
 }
@@ -487,7 +520,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     // face values (every right-hand side of a batch from its own moments)
     if (o.bc == 0 || o.bc == 1) {
         if (lasto_status e = set_faces(g, rho, o.bc, o.lmax_bc, v); e != LASTO_OK) return e;
-        if (o.bc == 1) HIPCHK(hipMemcpyAsync(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost, s));
+        // (the moments reach info at the end, when the solve has synchronised)
     }
     HIPCHK(hipEventRecord(g->ph_ev[1], s));
     // the start inside
@@ -549,6 +582,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         inf.n_batch = nbat;
         inf.ms_bc = event_ms(g->ph_ev[0], g->ph_ev[1]);
         inf.ms_guess = event_ms(g->ph_ev[1], g->ph_ev[2]);
+        if (o.bc == 1) HIPCHK(hipMemcpy(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost));
         inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         if (info) *info = inf;
         return LASTO_OK;
@@ -815,6 +849,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         result = LASTO_ERR_DIVERGED;
         why = "lasto_poisson_solve: residual not finite";
     }
+    if (o.bc == 1) HIPCHK(hipMemcpy(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost));
     inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (info) *info = inf;
     if (result != LASTO_OK) return fail(result, why);

@@ -69,7 +69,7 @@ class SolveOpts(C.Structure):
         ("coarse_net", C.c_void_p),
         ("coarse_net_level", C.c_int),
         ("inner_rate", C.c_double),
-        ("eager", C.c_int),
+        ("graphs", C.c_int),
         ("nu_coarse", C.c_int),
     ]
 

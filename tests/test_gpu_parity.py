@@ -237,11 +237,12 @@ def test_bench_form_at_the_headline_tolerance_matches_oracle(torch, L, oracle_mo
 
 @pytest.mark.parametrize("batch", [1, 2])
 def test_graph_replays_match_eager_launches(torch, L, batch):
-    """The finest-level V-cycle captured into a HIP graph and replayed gives
-    the same bits as launching every kernel from the host: the mixed and the
-    FP64 CG forms, solved five times in a row on one grid (the first use
-    eager, the second capturing, then replays), with eager work of the
-    program's own between the solves, each compared with an eager solve."""
+    """With graphs = 1 the inner FP32 PCG steps and the FP64 CG's V-cycles
+    are captured into HIP graphs and replayed: the same bits as launching
+    every kernel from the host, for the mixed and the FP64 CG forms solved
+    five times in a row on one grid (the first use eager, the second
+    capturing, then replays), with eager work of the program's own between
+    the solves, each compared with a solve launched from the host."""
     say("graph replays vs eager launches, config 3 n=%d x %d" % (65 if batch > 1 else 129, batch))
     n = 65 if batch > 1 else 129
     w = I.config(3, n_override=n)
@@ -251,10 +252,10 @@ def test_graph_replays_match_eager_launches(torch, L, batch):
     rho = g.pseudo_density(atoms)
     for form in BENCH_FORMS[:2]:
         ref = g.empty()
-        iref = g.poisson_solve(rho, ref, rtol=1e-10, eager=1, **form, **start_atoms(form, atoms))
+        iref = g.poisson_solve(rho, ref, rtol=1e-10, **form, **start_atoms(form, atoms))
         for rep in range(5):
             v = g.empty()
-            info = g.poisson_solve(rho, v, rtol=1e-10, **form, **start_atoms(form, atoms))
+            info = g.poisson_solve(rho, v, rtol=1e-10, graphs=1, **form, **start_atoms(form, atoms))
             assert torch.equal(v, ref), (form, rep)
             assert (info["iters"], info["vcycles"], info["rel_resid"]) == \
                 (iref["iters"], iref["vcycles"], iref["rel_resid"])
