@@ -559,90 +559,142 @@ __global__ __launch_bounds__(256) void k_divide_dense(T* __restrict__ d, const T
     d[t] = d[t] / (lx[i] + ly[r % my] + lz[(r / my) % mz]);
 }
 
-// One contraction with the axes rotated, on the FP64 matrix cores: each
-// copy's block holds L = cells / m lines of m contiguous entries ([line][k],
-// the contracted axis fastest); the output is out[r][line] = sum_k P[r][k]
+// One contraction with the axes rotated, on the matrix cores: each copy's
+// block holds L = cells / m lines of m contiguous entries ([line][k], the
+// contracted axis fastest); the output is out[r][line] = sum_k P[r][k]
 // in[line][k], the new axis slowest. Three of them take [z][y][x] to
 // [x'][z][y], [y'][x'][z] and [z'][y'][x'] (the original order), three more
 // back to [z][y][x]. Each wave computes one 16 x 16 tile (16 rows r by 16
-// lines) by v_mfma_f64_16x16x4f64 (A 16 x 4 from lane (row = lane % 16,
-// k = lane / 16), B 4 x 16 from lane (k = lane / 16, col = lane % 16), D with
-// lane holding rows lane / 16 + 4 j of column lane % 16). The operands come
-// straight from memory (P, a few tens of KB, stays in the L2; each lane's
-// line is a contiguous run): a workgroup of small waves is latency-bound, so
-// for m <= 32 NCH every load of the whole k range is issued before the first
-// matrix-core step (NCH = 0: chunks of 32 k in turn). The summation order is
-// fixed: the same bits every time.
+// lines) by 16 x 16 x 4 matrix-core steps in the cycle's precision
+// (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32): A 16 x 4 from lane
+// (row = lane % 16, k-slot = lane / 16), B 4 x 16 from lane (k-slot =
+// lane / 16, col = lane % 16). The k axis is taken in chunks of 16 in a
+// permuted order so that each lane reads four consecutive entries of its row
+// of P and of its line at once: in chunk c, step s, lane group g holds
+// k = 16 c + 4 g + s (the four steps of a chunk cover its 16 k once, A and B
+// alike). Both operands come straight from memory (P stays in the L2; each
+// lane's line is a contiguous run); for m <= 16 NCH every load of the whole
+// k range is issued before the first matrix-core step. The summation order
+// is fixed: the same bits every time.
 constexpr int CT_NT = 256;
 typedef double ct_dbl4 __attribute__((ext_vector_type(4)));
+typedef float ct_flt4 __attribute__((ext_vector_type(4)));
 
-template <typename T, int NCH>
-__global__ __launch_bounds__(CT_NT) void k_contract(const double* __restrict__ P, const T* __restrict__ in,
+template <typename T> struct CtMfma;
+template <> struct CtMfma<double> {
+    typedef ct_dbl4 Acc;
+    static __device__ __forceinline__ Acc step(double a, double b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // lane l holds rows l / 16 + 4 j of column l % 16
+    static __device__ __forceinline__ int row(int grp, int j) { return grp + 4 * j; }
+};
+template <> struct CtMfma<float> {
+    typedef ct_flt4 Acc;
+    static __device__ __forceinline__ Acc step(float a, float b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // lane l holds rows 4 (l / 16) + j of column l % 16
+    static __device__ __forceinline__ int row(int grp, int j) { return 4 * grp + j; }
+};
+
+// four consecutive entries p[k .. k + 3] (zero past n), one load when all are in range
+template <typename T>
+__device__ __forceinline__ void ct_load4(const T* __restrict__ p, int k, int n, bool ok, T* v)
+{
+    if (ok && k + 3 < n) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = p[k + s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = (ok && k + s < n) ? p[k + s] : T(0);
+    }
+}
+
+template <typename T, int NCH, int RT>
+__global__ __launch_bounds__(CT_NT) void k_contract(const T* __restrict__ P, const T* __restrict__ in,
                                                     T* __restrict__ out, int m, int L, int rtiles, int ctiles)
 {
-    constexpr int KS = 8;                          // k-steps of 4 per chunk
-    constexpr int NS = NCH > 0 ? NCH * KS : KS;    // steps held in registers at once
+    typedef typename CtMfma<T>::Acc Acc;
+    constexpr int NC = NCH > 0 ? NCH : 2;   // 16-k chunks held in registers at once
     const int lane = threadIdx.x & 63;
-    const int task = blockIdx.x * (CT_NT / 64) + (threadIdx.x >> 6);   // (column tile, row tile) of copy blockIdx.y
-    if (task >= rtiles * ctiles) return;   // the last workgroup's spare waves
-    const int rt = task % rtiles, ct = task / rtiles;
+    // (column tile, group of RT row tiles) of copy blockIdx.y: the wave's
+    // line operands are loaded once for its RT row tiles
+    const int task = blockIdx.x * (CT_NT / 64) + (threadIdx.x >> 6);
+    const int rgroups = (rtiles + RT - 1) / RT;
+    if (task >= rgroups * ctiles) return;   // the last workgroup's spare waves
+    const int rg = task % rgroups, ct = task / rgroups;
     const int p16 = lane & 15, grp = lane >> 4;
     const size_t per = (size_t)m * L;
     const T* __restrict__ inc = in + blockIdx.y * per;
     T* __restrict__ outc = out + blockIdx.y * per;
-    const int r = rt * 16 + p16, ln = ct * 16 + p16;
-    const bool rok = r < m, lok = ln < L;
-    const double* __restrict__ prow = P + (size_t)(rok ? r : 0) * m;
+    const int ln = ct * 16 + p16;
+    const bool lok = ln < L;
     const T* __restrict__ il = inc + (size_t)(lok ? ln : 0) * m;
-    ct_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    const int kend = NCH > 0 ? 4 * NS : m;
-    for (int k0 = 0; k0 < kend; k0 += 4 * NS) {
-        double a[NS], bv[NS];
+    Acc acc[RT];
 #pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const int k = k0 + 4 * st + grp;
-            const bool kok = k < m;
-            const int kk = kok ? k : 0;
-            a[st] = (rok && kok) ? prow[kk] : 0.0;
-            bv[st] = (lok && kok) ? (double)il[kk] : 0.0;
+    for (int q = 0; q < RT; ++q) acc[q] = Acc{T(0), T(0), T(0), T(0)};
+    const int kend = NCH > 0 ? 16 * NC : m;
+    for (int k0 = 0; k0 < kend; k0 += 16 * NC) {
+        T bv[NC][4];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ct_load4(il, k0 + 16 * c + 4 * grp, m, lok, bv[c]);
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const int r = (rg * RT + q) * 16 + p16;
+            const bool rok = r < m;
+            const T* __restrict__ prow = P + (size_t)(rok ? r : 0) * m;
+            T a[NC][4];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ct_load4(prow, k0 + 16 * c + 4 * grp, m, rok, a[c]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int st = 0; st < 4; ++st) acc[q] = CtMfma<T>::step(a[c][st], bv[c][st], acc[q]);
         }
-#pragma unroll
-        for (int st = 0; st < NS; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], bv[st], acc, 0, 0, 0);
     }
     if (!lok) return;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int row = rt * 16 + grp + 4 * j;
-        if (row < m) outc[(size_t)row * L + ln] = (T)acc[j];
-    }
+    for (int q = 0; q < RT; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = (rg * RT + q) * 16 + CtMfma<T>::row(grp, j);
+            if (row < m) outc[(size_t)row * L + ln] = acc[q][j];
+        }
 }
 
 template <typename T>
-static hipError_t contract_rot_mfma(const CoarseGemm* c, int m, const double* P, const T* in, T* out, hipStream_t s)
+static hipError_t contract_rot_mfma(const CoarseGemm* c, int m, const T* P, const T* in, T* out, hipStream_t s)
 {
+    // one row tile per wave (two, sharing the line loads, measured slower:
+    // 10.9 against 9.7 us FP32, 14.5 against 13.5 us FP64 at 90^3, fewer
+    // waves to hide the loads' latency)
+    constexpr int RT = 1;
     const int per = c->m[0] * c->m[1] * c->m[2];
     const int L = per / m;
     const int rtiles = (m + 15) / 16, ctiles = (L + 15) / 16;
-    const int waves = rtiles * ctiles;   // per copy
+    const int waves = ((rtiles + RT - 1) / RT) * ctiles;   // per copy
     const dim3 grid((unsigned)((waves + CT_NT / 64 - 1) / (CT_NT / 64)), (unsigned)c->nb);
-    const int nch = (m + 31) / 32;
+    const int nch = (m + 15) / 16;
     switch (nch) {
-        case 1: hipLaunchKernelGGL((k_contract<T, 1>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
-        case 2: hipLaunchKernelGGL((k_contract<T, 2>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
-        case 3: hipLaunchKernelGGL((k_contract<T, 3>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
-        case 4: hipLaunchKernelGGL((k_contract<T, 4>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
-        default: hipLaunchKernelGGL((k_contract<T, 0>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 1: hipLaunchKernelGGL((k_contract<T, 1, RT>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 2: hipLaunchKernelGGL((k_contract<T, 2, RT>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 3: hipLaunchKernelGGL((k_contract<T, 3, RT>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 4: hipLaunchKernelGGL((k_contract<T, 4, RT>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 5: hipLaunchKernelGGL((k_contract<T, 5, RT>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        case 6: hipLaunchKernelGGL((k_contract<T, 6, RT>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
+        default: hipLaunchKernelGGL((k_contract<T, 0, RT>), grid, dim3(CT_NT), 0, s, P, in, out, m, L, rtiles, ctiles); break;
     }
     return hipGetLastError();
 }
 
 // Which contraction each precision takes (measured at 90^3, one right-hand
-// side, 7744 x 88 x 88 per contraction): FP64 on the matrix cores above,
-// 13.5 us against rocBLAS dgemm's 19.5 us; FP32 through rocBLAS sgemm
-// (strided batch over the copies, atomics off, so the bits repeat), 6.9 us
-// against 15.9 us for the same matrix-core kernel reading FP32 (its 16-row
-// by 16-line tiles gather each lane's operands from 16 lines and are bound by
-// the requests they issue, where sgemm's 128 x 128 LDS tiles are not).
+// side, 7744 x 88 x 88 per contraction): FP64 on the matrix cores above
+// (rocBLAS dgemm takes 19.5 us); FP32 through rocBLAS sgemm (strided batch
+// over the copies, atomics off, so the bits repeat), 6.9 us against 9.7 us
+// for the kernel above on the FP32 matrix cores.
 static hipError_t contract_rot(const CoarseGemm* c, int m, const double* const* P64, int d, const double* in,
                                double* out, hipStream_t s)
 {
