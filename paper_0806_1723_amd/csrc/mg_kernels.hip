@@ -1909,27 +1909,35 @@ int tail_lds_limit()
 // out[c] = sum_b partials[b * stride + c], c < stride, in a fixed order
 // (thread t takes t, t+1024, ..., then a fixed tree): a given launch shape
 // always gives the same bits.
-__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part, int stride, int count,
-                                                 double* __restrict__ out)
+// Sums of partials in a fixed order: thread t adds entries t, t + 256, ...
+// of each column, each wave combines its lanes by a butterfly, and thread 0
+// adds the four wave sums in order. One workgroup of 256 (a launch of this
+// size is latency-bound: fewer threads and no tree of barriers).
+constexpr int RD_NT = 256;
+
+__global__ __launch_bounds__(RD_NT) void k_reduce(const double* __restrict__ part, int stride, int count,
+                                                  double* __restrict__ out)
 {
-    __shared__ double sh[1024];
+    __shared__ double sh[RD_NT / 64];
     for (int c = 0; c < stride; ++c) {
         double a = 0.0;
-        for (int t = threadIdx.x; t < count; t += 1024) a += part[(size_t)t * stride + c];
-        sh[threadIdx.x] = a;
+        for (int t = threadIdx.x; t < count; t += RD_NT) a += part[(size_t)t * stride + c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
         __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < RD_NT / 64; ++w) t += sh[w];
+            out[c] = t;
         }
-        if (threadIdx.x == 0) out[c] = sh[0];
         __syncthreads();
     }
 }
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partials, stride, count, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RD_NT), 0, s, partials, stride, count, out);
     return hipGetLastError();
 }
 

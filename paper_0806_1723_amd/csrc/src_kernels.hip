@@ -504,109 +504,49 @@ hipError_t launch_guess_all(lasto_grid g, const AtomDev* dev_atoms, const lasto_
 
 
 // --------------------------------------------------------------- moments
-// Q_lm = sum_n vol_n rho_n S_lm(x_n - c), l <= 4, by rows: along a row (j, k)
-// dy and dz are fixed and S_lm(dx, dy, dz) is a polynomial of degree <= l in
-// dx, sum_a p_lm,a(dy, dz) dx^a, so the row contributes
-// vol_y vol_z sum_a p_lm,a R_a with R_a = sum_i vol_x,i rho_ijk dx_i^a. A wave
-// takes whole rows: its lanes stride over i for the five sums R_0..R_4
-// (one pass over rho, four multiplies and five adds per node), the wave
-// reduces them, and lane c < 25 then builds p_lm,a of its own (l, m) by the
-// harmonics' recurrence run on polynomials in dx and adds its row term.
-// Rows go to waves in a fixed order and every sum has a fixed order.
 constexpr int MO_NT = 256;
-
-// coefficients (in dx, degree <= 4) of S_lm(dx, dy, dz) for index c = l*l + l + m
-__device__ __forceinline__ void harmonic_poly(int c, double y, double z, double* p)
-{
-    int l = 0;
-    while ((l + 1) * (l + 1) <= c) ++l;
-    const int m = c - l * l - l, am = m < 0 ? -m : m;
-    // Q_am^am = (2 am - 1)!! (x + i y)^am as polynomials in x
-    double re[5] = {1.0, 0.0, 0.0, 0.0, 0.0}, im[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int t = 1; t <= am; ++t) {
-        double nre[5], nim[5];
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            const double xre = a > 0 ? re[a - 1] : 0.0, xim = a > 0 ? im[a - 1] : 0.0;
-            nre[a] = (xre - y * im[a]) * (2.0 * t - 1.0);
-            nim[a] = (y * re[a] + xim) * (2.0 * t - 1.0);
-        }
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            re[a] = nre[a];
-            im[a] = nim[a];
-        }
-    }
-    // up the recurrence in l: Q_l = a z Q_{l-1} - b r^2 Q_{l-2}, r^2 = x^2 + (y^2 + z^2)
-    const double yz2 = y * y + z * z;
-    double pre[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, pim[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int ll = am + 1; ll <= l; ++ll) {
-        const double ca = (2.0 * (ll - 1) + 1.0) / (double)(ll - am);
-        const double cb = (double)(ll - 1 + am) / (double)(ll - am);
-        double nre[5], nim[5];
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            const double r2re = (a >= 2 ? pre[a - 2] : 0.0) + yz2 * pre[a];
-            const double r2im = (a >= 2 ? pim[a - 2] : 0.0) + yz2 * pim[a];
-            nre[a] = ca * z * re[a] - cb * r2re;
-            nim[a] = ca * z * im[a] - cb * r2im;
-        }
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            pre[a] = re[a];
-            pim[a] = im[a];
-            re[a] = nre[a];
-            im[a] = nim[a];
-        }
-    }
-    const double nrm = c_ynorm[c];
-#pragma unroll
-    for (int a = 0; a < 5; ++a) p[a] = nrm * (m >= 0 ? re[a] : im[a]);
-}
 
 __global__ __launch_bounds__(MO_NT) void k_moments(LevelView L, const double* __restrict__ rho, double cx, double cy,
                                                    double cz, double* __restrict__ part)
 {
-    __shared__ double sh[MO_NT / 64][25];
+    __shared__ double sh[MO_NT / 64];
     const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int waves = gridDim.x * (MO_NT / 64);
-    const long rows = (long)ny * nz;
-    double acc = 0.0;   // lane c < 25: this wave's sum of Q_c
-    for (long row = (long)blockIdx.x * (MO_NT / 64) + wid; row < rows; row += waves) {
-        const int j = (int)(row % ny), k = (int)(row / ny);
-        const double* __restrict__ r = rho + (size_t)row * nx;
-        double R0 = 0.0, R1 = 0.0, R2 = 0.0, R3 = 0.0, R4 = 0.0;
-        for (int i = lane; i < nx; i += 64) {
-            const double f = r[i] * L.ax[0].m[i], t = L.ax[0].x[i] - cx;
-            const double f1 = f * t, f2 = f1 * t, f3 = f2 * t;
-            R0 += f;
-            R1 += f1;
-            R2 += f2;
-            R3 += f3;
-            R4 += f3 * t;
+    const size_t n = (size_t)nx * ny * nz;
+    double acc[25];
+    for (int c = 0; c < 25; ++c) acc[c] = 0.0;
+    double S[25];
+    // the node index is decoded once and then advanced by the grid stride
+    // with carries (a 64-bit division per node cost more than the node)
+    size_t t = (size_t)blockIdx.x * MO_NT + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * MO_NT;
+    int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((size_t)nx * ny));
+    const int di = (int)(stride % nx), dj = (int)((stride / nx) % ny), dk = (int)(stride / ((size_t)nx * ny));
+    for (; t < n; t += stride) {
+        const double f = rho[t];
+        if (f != 0.0) {
+            const double w = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * f;
+            solid_harmonics(L.ax[0].x[i] - cx, L.ax[1].x[j] - cy, L.ax[2].x[k] - cz, 4, S);
+            for (int c = 0; c < 25; ++c) acc[c] += w * S[c];
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            R0 += __shfl_xor(R0, off, 64);
-            R1 += __shfl_xor(R1, off, 64);
-            R2 += __shfl_xor(R2, off, 64);
-            R3 += __shfl_xor(R3, off, 64);
-            R4 += __shfl_xor(R4, off, 64);
-        }
-        if (lane < 25) {
-            double p[5];
-            harmonic_poly(lane, L.ax[1].x[j] - cy, L.ax[2].x[k] - cz, p);
-            const double vyz = L.ax[1].m[j] * L.ax[2].m[k];
-            acc += vyz * ((((p[4] * R4 + p[3] * R3) + p[2] * R2) + p[1] * R1) + p[0] * R0);
-        }
+        i += di;
+        int carry = i >= nx;
+        i -= carry * nx;
+        j += dj + carry;
+        carry = j >= ny;
+        j -= carry * ny;
+        k += dk + carry;
     }
-    if (lane < 25) sh[wid][lane] = acc;
-    __syncthreads();
-    if (threadIdx.x < 25) {
-        double s = 0.0;
-        for (int w = 0; w < MO_NT / 64; ++w) s += sh[w][threadIdx.x];
-        part[(size_t)blockIdx.x * 25 + threadIdx.x] = s;
+    for (int c = 0; c < 25; ++c) {
+        double v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < MO_NT / 64; ++w) s += sh[w];
+            part[(size_t)blockIdx.x * 25 + c] = s;
+        }
     }
 }
 
