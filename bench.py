@@ -50,6 +50,14 @@ def half_sweep_source_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
+def smoother_label(t, form):
+    """The finest-level smoother kernel a solve form times (profile = 1)."""
+    if form.get("fused_sweeps", 0) <= 1:
+        return "k_half2<%s, GS, *, *, true, true> (red-black half-sweep, finest level)" % t
+    return ("k_gs_block<%s, S, *, *, true> (S red-black half-sweeps in one pass, finest level: the pre-smoothing "
+            "from zero and the post-smoothing)" % t)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -71,6 +79,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=2400, help="config 4: Adam steps per net")
     ap.add_argument("--validate", type=int, default=50, help="config 4: labels checked by the oracle")
     ap.add_argument("--train5", type=int, default=32, help="config 5: perturbed copies the guess net trains on")
+    ap.add_argument("--fused-sweeps", type=int, default=None,
+                    help="opts.fused_sweeps for every solve (default: the library's)")
     ap.add_argument("--solve-only", action="store_true",
                     help="report the solve alone (no sphere, interstitial-density or matrix-element objects)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -121,6 +131,8 @@ def main():
     # inside the timed solve (guess = 2); the zero start is reported beside.
     form = dict(precision=mixed, method=0, nu1=3, nu2=3, inner_first=4 if mixed else 0,
                 inner_iters=8 if mixed else 5, inner_rate=0.05 if mixed else 0.0)
+    if args.fused_sweeps is not None:
+        form["fused_sweeps"] = args.fused_sweeps
     start = dict(guess=2, atoms=atoms)
     if args.clean_only:
         g.close()
@@ -169,7 +181,7 @@ def main():
     for si in range(max(3, args.steps)):
         v.zero_()
         fp64.append(g.poisson_solve(rho, v, rtol=w.rtol, precision=0, nu1=form["nu1"], nu2=form["nu2"],
-                                    profile=1 if si == 1 else 0, **start))
+                                    fused_sweeps=form.get("fused_sweeps", 0), profile=1 if si == 1 else 0, **start))
     fp64_ms = statistics.median(i["ms_total"] for i in fp64[2:])
     kept["fp64"] = (v[0] if nb > 1 else v).cpu().numpy()
     f_ms = fp64[1]["smooth_ms"]
@@ -212,7 +224,7 @@ def main():
     traffic = None
     form_key = (form["precision"], form["method"], form["inner_iters"], form["inner_first"], form["nu1"], form["nu2"],
                 form["inner_rate"], start["guess"])
-    if (n == 257 and args.config == 3 and form_key == COUNTER_TRAFFIC["form"]
+    if (n == 257 and args.config == 3 and form_key == COUNTER_TRAFFIC["form"] and form.get("fused_sweeps", 0) <= 1
             and half_sweep_source_digest() == COUNTER_TRAFFIC["kernel_sha256_16"]):
         traffic = COUNTER_TRAFFIC["bytes_per_launch"]
     out = {
@@ -250,8 +262,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": round(sm_bytes / launches) if launches else 0,
-                     "kernel": "k_half2<%s, GS, *, *, true, true> (red-black half-sweep, finest level)"
-                               % ("float" if mixed else "double"),
+                     "kernel": smoother_label("float" if mixed else "double", form),
                      "bytes_per_point_per_launch": round(sm_bpp, 3), "avg_launch_us": round(avg_launch_us, 2),
                      "launches": launches, "events_on": "timed step 1 of %d" % args.steps},
     }
@@ -811,6 +822,8 @@ def bench_batched(args):
     # at 513^3 the finest level dominates a cycle: V(3,3) with 4 sweeps each
     # way on the levels below takes 5 cycles where plain V(3,3) takes 6
     form = dict(precision=1, method=0, nu1=3, nu2=3, nu_coarse=4, inner_first=4, inner_iters=8, inner_rate=0.05)
+    if args.fused_sweeps is not None:
+        form["fused_sweeps"] = args.fused_sweeps
     starts = {"zero": dict(guess=1), "analytic": dict(guess=2, atoms=w.batch_atoms),
               "learned": dict(guess=3, atoms=w.batch_atoms, guess_net=net)}
     res = {}
@@ -867,7 +880,7 @@ def bench_batched(args):
                       "loss_first": float(np.mean(hist[:k])), "loss_last": float(np.mean(hist[-k:]))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_half2<float, GS, *, *, true, true> (red-black half-sweep, finest level, 8 copies)",
+                     "kernel": smoother_label("float", form) + ", 8 copies",
                      "launches": sl, "avg_launch_us": round(sm * 1e3 / max(sl, 1), 2),
                      "algorithmic_bytes_per_launch": round(sb / max(sl, 1))},
     }

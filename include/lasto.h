@@ -202,6 +202,12 @@ typedef struct {
                            profile = 1 and a learned coarse correction always launch from the host */
     int nu_coarse;      /* > 0: red-black sweeps before and after the coarse correction on every level below
                            the finest (the finest keeps nu1, nu2); 0 (default): nu1, nu2 on every level */
+    int fused_sweeps;   /* red-black half-sweeps that share one pass over a level (lasto_smooth): 0 (default) or
+                           1 one launch per half-sweep; 2, 4 or 6 (FP64: at most 4) at most that many per pass on
+                           every level that sweeps: the pre-smoothing from zero and the start of the
+                           post-smoothing. The results are the same bits either way, apart from the order in
+                           which <r, z>_W sums its terms; the fused pass measured slower at 257^3 (its time is
+                           bound by latency per plane step, not by HBM) */
 } lasto_solve_opts;
 
 typedef struct {
@@ -514,6 +520,29 @@ lasto_status lasto_apply(lasto_grid g, const double* u, double* Au);
  *   u_in, rho, u_out: device [nz][ny][nx]; u_out must not alias u_in.
  */
 lasto_status lasto_rb_sweep(lasto_grid g, const double* u_in, const double* rho, double* u_out, int first_colour);
+
+/*
+ * Red-black Gauss-Seidel half-sweeps of the multigrid smoother (eq. (3.2)'s
+ * seven-point operator; the smoother of the multigrid solve the paper names)
+ * on the correction equation A u = f with zero faces at `level` of the grid:
+ * nsweeps half-sweeps (2, 4 or 6; a fused FP64 pass at most 4, its u and f
+ * rings filling a compute unit's LDS) updating colours first_colour,
+ * 1 - first_colour, ... in turn, starting from u (zero_in 0) or from zero
+ * (zero_in 1). fused 1 runs them as one pass over the level (a workgroup
+ * marches a ring of planes through LDS and recomputes its halo), fused 0 as
+ * one launch per half-sweep; both give the same bits. precision 1 runs in
+ * FP32 (u and f rounded on entry, the result widened on exit). dot (host,
+ * optional, not with zero_in): the sum over the nodes of the last two
+ * half-sweeps of vol * f * u (the smoother's share of <f, u>_W). Exposed for
+ * testing.
+ *   f, u: device [nz][ny][nx] of the level (lasto_grid_level_shape), FP64,
+ *   distinct; u in/out (interior nodes written, faces untouched). Faces of f
+ *   and u must be zero.
+ * Errors: LASTO_ERR_ARG (NULL or aliased buffers, bad level, precision,
+ * nsweeps, colour, zero_in or fused, dot with zero_in), LASTO_ERR_HIP.
+ */
+lasto_status lasto_smooth(lasto_grid g, int level, int precision, const double* f, double* u, int nsweeps,
+                          int first_colour, int zero_in, int fused, double* dot);
 
 /*
  * Streaming ceiling (measurement, not part of the method): dst = a over

@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblasto.so")
-SOURCES = ["api.hip", "grid.hip", "solve.hip", "mg_kernels.hip", "src_kernels.hip", "sphere.hip", "basis.hip",
+SOURCES = ["api.hip", "grid.hip", "solve.hip", "mg_kernels.hip", "gs_block.hip", "src_kernels.hip", "sphere.hip", "basis.hip",
            "fdm.hip", "net.hip", "net_kernels.hip", "host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -485,6 +485,7 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
     for (int l = 0; l < g->nlev; ++l) {
         nparts = std::max(nparts, (size_t)interior_blocks(g->lev[l].view));
         nparts = std::max(nparts, (size_t)2 * half_blocks(g->lev[l].view));
+        nparts = std::max(nparts, (size_t)gs_block_parts(g->lev[l].view));
         nparts = std::max(nparts, (size_t)row_blocks(g->lev[l].view));
         nparts = std::max(nparts, (size_t)flat_blocks<float>(g->lev[l].view));
         nparts = std::max(nparts, (size_t)flat_blocks<double>(g->lev[l].view));

@@ -284,6 +284,7 @@ struct lasto_grid_s {
     float* cfdm_tab32 = nullptr;
     int coarse_mode = 0;              // the current solve's opts.coarse
     int nu_coarse = 0;                // the current solve's opts.nu_coarse
+    int fused_sweeps = 0;             // the current solve's opts.fused_sweeps
     // the exact coarsest solve by GEMMs on a larger level (tables built on
     // first use; cg_level -1: no level qualifies)
     int cg_level = -1;
@@ -343,6 +344,20 @@ template <typename T>
 hipError_t launch_half(const LevelView& L, T* u, const T* f, int colour, int zero_in, T bscale, double* dotp,
                        hipStream_t s, int* nparts = nullptr, int top = 0, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
+// nsweeps (2, 4 or 6; at most gs_block_max<T>()) consecutive half-sweeps, colours c0, 1 - c0, ..., in
+// one pass (zero faces): colour 1 - c0 of uin is read (nothing with zero_in)
+// and both colours of the result written to uout, which must differ from uin
+// unless zero_in. dotp (not with zero_in): per-block partials of
+// sum vol * f * u over the nodes of the last two half-sweeps (*nparts of them).
+template <typename T>
+hipError_t launch_gs_block(const LevelView& L, const T* uin, const T* f, T* uout, int c0, int nsweeps, int zero_in,
+                           T bscale, double* dotp, hipStream_t st, int* nparts = nullptr, int top = 0,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+int gs_block_parts(const LevelView& L);   // partials a launch_gs_block with dotp may write
+template <typename T> int gs_block_max();   // the longest pass launch_gs_block takes (FP32 6, FP64 4)
+// whole-array precision changes (n elements, rounding to nearest)
+hipError_t launch_cast(const double* a, float* b, size_t n, hipStream_t s);
+hipError_t launch_cast(const float* a, double* b, size_t n, hipStream_t s);
 // the same on an array whose faces carry Dirichlet data (written back unchanged)
 template <typename T>
 hipError_t launch_half_keep_faces(const LevelView& L, T* u, const T* f, int colour, T bscale, hipStream_t s);
@@ -363,6 +378,10 @@ template <typename T>
 hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s);
+// the same interpolation, from uin, written to another array: out (red) = uin (red) + P e
+template <typename T>
+hipError_t launch_prolong_red_to(const LevelView& F, const LevelView& C, const T* e, const T* uin, T* out,
+                                 hipStream_t s);
 // V(nu1, nu2) on levels lv[0..nl-1] in one workgroup, from zero (lv[0]
 // from its current u unless top_zero); the coarsest runs csweeps (red,
 // black) sweeps then csweeps (black, red).

@@ -14,33 +14,11 @@
 #include <hip/hip_ext.h>
 
 #include "internal.h"
+#include "kern_util.h"
 
 namespace lasto {
 
 // ------------------------------------------------------------- helpers
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Deterministic block sum (fixed tree); result valid in thread 0. Every
-// thread of the block must call it.
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* sh)
-{
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < NT / 64; ++w) t += sh[w];
-    }
-    return t;
-}
-
 __device__ __forceinline__ int block_linear()
 {
     return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -175,44 +153,6 @@ __device__ __forceinline__ T prolong_at(const LevelView& C, const T* __restrict_
 }
 
 // --------------------------------------------------------- half-sweep
-// Workgroups are dispatched to the eight XCDs in turn; tile (id % 8) * per +
-// id / 8 hands each XCD a contiguous run of tiles, so tiles that share halo
-// rows share an L2. Ids past the last tile only contribute a zero partial.
-__device__ __forceinline__ int xcd_tile(int id, int per) { return (id & 7) * per + (id >> 3); }
-
-// 16 bytes of one colour row: VEC consecutive entries (4 FP32, 2 FP64)
-template <typename T> struct Vec16;
-template <> struct Vec16<float> {
-    typedef float V __attribute__((ext_vector_type(4)));
-    static constexpr int N = 4;
-};
-template <> struct Vec16<double> {
-    typedef double V __attribute__((ext_vector_type(2)));
-    static constexpr int N = 2;
-};
-
-template <typename T> __device__ __forceinline__ const T* tab_am(const Axis& a);
-template <typename T> __device__ __forceinline__ const T* tab_ap(const Axis& a);
-template <> __device__ __forceinline__ const float* tab_am<float>(const Axis& a) { return a.amf; }
-template <> __device__ __forceinline__ const float* tab_ap<float>(const Axis& a) { return a.apf; }
-template <> __device__ __forceinline__ const double* tab_am<double>(const Axis& a) { return a.am; }
-template <> __device__ __forceinline__ const double* tab_ap<double>(const Axis& a) { return a.ap; }
-
-// 1/d: the hardware reciprocal refined by Newton steps r <- r + r (1 - d r)
-// (one in FP32, two in FP64), within about half an ulp of the quotient
-__device__ __forceinline__ float recip(float d)
-{
-    const float r = __builtin_amdgcn_rcpf(d);
-    return fmaf(fmaf(-d, r, 1.0f), r, r);
-}
-__device__ __forceinline__ double recip(double d)
-{
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(fma(-d, r, 1.0), r, r);
-    r = fma(fma(-d, r, 1.0), r, r);
-    return r;
-}
-
 enum HalfMode { HM_GS = 0, HM_RESID = 1, HM_APPLY = 2 };
 
 // Over the nodes of colour c (VEC neighbouring entries m0 .. m0+VEC-1 of a
@@ -356,14 +296,11 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                 const T xl = o ? zc[e] : (e > 0 ? zc[e > 0 ? e - 1 : 0] : q.xe);
                 const T xr = o ? (e + 1 < VEC ? zc[e + 1 < VEC ? e + 1 : e] : q.xe) : zc[e];
                 if (MODE == HM_GS) {
-                    const T d = cxm[e] + cxp[e] + cym + cyp + czm + czp;
-                    T sum = T(0);
-                    if (NEED_U) {
-                        sum = cxm[e] * xl + cxp[e] * xr;
-                        sum += cym * q.ym[e] + cyp * q.yp[e];
-                        sum += czm * zm[e] + czp * zp[e];
-                    }
-                    r[e] = (sum - bscale * q.fv[e]) * recip(d);
+                    if (NEED_U)
+                        r[e] = gs_update(cxm[e], cxp[e], xl, xr, cym, cyp, q.ym[e], q.yp[e], czm, czp, zm[e], zp[e],
+                                         bscale, q.fv[e]);
+                    else
+                        r[e] = gs_update0(cxm[e], cxp[e], cym, cyp, czm, czp, bscale, q.fv[e]);
                 } else {
                     // (A u) in difference form, which keeps FP32 free of cancellation
                     const T c0 = q.cv[e];
@@ -1320,16 +1257,18 @@ hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* 
     return hipGetLastError();
 }
 
-// u += P e on the red nodes only: when a black half-sweep follows, it
+// u + P e on the red nodes only: when a black half-sweep follows, it
 // overwrites every black value, so correcting them would be wasted work. Two
 // consecutive red entries m, m+1 of a row per thread (fine nodes i0 = o + 2m
 // and i1 = i0 + 2, o = (j + k) & 1), KU planes. Their coarse nodes lie in
 // Ix0 .. Ix0 + 3 (Ix0 = pc(i0); a coarse step spans at most two fine steps),
 // which in each coarse row are two consecutive entries of each colour: two
-// pair loads per row serve both fine nodes.
+// pair loads per row serve both fine nodes. The result goes to uout, which
+// is uin (in place) or another array (its red entries written, the rest
+// untouched); each thread loads all its values before it stores any.
 template <typename T>
 __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C, const T* __restrict__ e,
-                                                       T* __restrict__ u, int nbx, int nby, int nb, int per)
+                                                       const T* uin, T* uout, int nbx, int nby, int nb, int per)
 {
     typedef typename Pair<T>::P P2;
     constexpr int KU = TransferUnroll<T>::KU;
@@ -1378,7 +1317,7 @@ __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C,
                 cv[q][c][b][2] = p0.y;
                 cv[q][c][b][3] = p1.y;
             }
-        uo[q] = *(const P2*)(u + (size_t)k * plane + row);
+        uo[q] = *(const P2*)(uin + (size_t)k * plane + row);
     }
 #pragma unroll
     for (int q = 0; q < KU; ++q) {
@@ -1406,7 +1345,7 @@ __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C,
             acc1 += wzc * s1;
         }
         const bool s_a = o ? oka[1] : oka[0], s_b = o ? okb[1] : okb[0];
-        T* out = u + (size_t)k * plane + row;
+        T* out = uout + (size_t)k * plane + row;
         if (s_a && s_b) {
             P2 w;
             w.x = uo[q].x + acc0;
@@ -1424,8 +1363,18 @@ hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e
 {
     // pairs of red entries m = 0, 2, ... <= (nx - 2) / 2
     const TileShape ts = tile_shape(((F.nx - 2) / 2) / 2 + 1, F.ny - 2, F.nz - 2, TransferUnroll<T>::KU);
-    hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, e, u, ts.nbx, ts.nby, ts.nb,
+    hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, e, u, u, ts.nbx, ts.nby, ts.nb,
                        ts.per);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_red_to(const LevelView& F, const LevelView& C, const T* e, const T* uin, T* out,
+                                 hipStream_t s)
+{
+    const TileShape ts = tile_shape(((F.nx - 2) / 2) / 2 + 1, F.ny - 2, F.nz - 2, TransferUnroll<T>::KU);
+    hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, e, uin, out, ts.nbx, ts.nby,
+                       ts.nb, ts.per);
     return hipGetLastError();
 }
 
@@ -1948,6 +1897,8 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
     template hipError_t launch_half_keep_faces<T>(const LevelView&, T*, const T*, int, T, hipStream_t);          \
     template hipError_t launch_prolong_add<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
     template hipError_t launch_prolong_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);      \
+    template hipError_t launch_prolong_red_to<T>(const LevelView&, const LevelView&, const T*, const T*, T*,        \
+                                                 hipStream_t);                                                  \
     template hipError_t launch_restrict_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);     \
     template hipError_t launch_residual_colour<T>(const LevelView&, const T*, const T*, T*, int, hipStream_t);    \
     template hipError_t launch_apply_colour<T>(const LevelView&, const T*, T*, int, double*, hipStream_t, int*);   \

@@ -81,6 +81,45 @@ static hipError_t half(lasto_grid g, int l, T* u, const T* f, int colour, int ze
     return hipSuccess;
 }
 
+// nsw half-sweeps at level l in one pass (launch_gs_block), timed and
+// counted as half() does: from zero it reads f and writes u (both colours),
+// otherwise it also reads one colour of uin.
+template <typename T>
+static hipError_t sweeps(lasto_grid g, int l, const T* uin, const T* f, T* u, int c0, int nsw, int zero_in,
+                         double* dotp, int* nparts = nullptr)
+{
+    const LevelView& V = g->lev[l].view;
+    const bool timed = g->prof_on && l == 0;
+    const double per_node = sizeof(T) * (zero_in ? 2.0 : 2.5);
+    count(g, l, per_node);
+    if (!timed) return launch_gs_block<T>(V, uin, f, u, c0, nsw, zero_in, T(1), dotp, g->stream, nparts, l == 0);
+    if ((size_t)(2 * g->prof_used + 2) > g->prof_ev.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            g->prof_ev.push_back(e);
+        }
+    }
+    hipError_t err = launch_gs_block<T>(V, uin, f, u, c0, nsw, zero_in, T(1), dotp, g->stream, nparts, 1,
+                                        g->prof_ev[2 * g->prof_used], g->prof_ev[2 * g->prof_used + 1]);
+    if (err != hipSuccess) return err;
+    g->prof_bytes += per_node * interior_pts(V);
+    if (sizeof(T) == 4) g->prof_fp32++;
+    g->prof_used++;
+    return hipSuccess;
+}
+
+// half-sweeps per pass at level l: opts.fused_sweeps when it sets a length
+// (every level that sweeps), else one launch each (measured faster at 257^3:
+// the half-sweep streams at the copy ceiling, while the fused pass is bound by
+// its per-step latency)
+static int pass_sweeps(lasto_grid g, int l)
+{
+    (void)l;
+    return g->fused_sweeps > 1 ? g->fused_sweeps : 1;
+}
+
 // V(nu1, nu2) at level l on A u = f with zero faces, in place in the split
 // layout, starting from u = 0 (zero_start) or from the u given (level 0
 // only; coarse levels always start from zero). Pre-smoothing sweeps update
@@ -141,10 +180,16 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
         if (lasto_status e = learned_coarse_start<T>(g, l, f, u, Buf<T>::r(L)); e != LASTO_OK) return e;
         zero_start = false;
     }
-    for (int k = 0; k < nu1; ++k) {
-        HIPCHK(half<T>(g, l, u, f, 0, k == 0 && zero_start, nullptr));
-        HIPCHK(half<T>(g, l, u, f, 1, 0, nullptr));
+    // pre-smoothing: half-sweep h updates colour h & 1 (red first); from a
+    // zero start the first blk of them share one pass (in place: nothing is
+    // read from u)
+    const int blk = std::min(pass_sweeps(g, l), gs_block_max<T>());
+    int h0 = 0;
+    if (zero_start && blk >= 2) {
+        h0 = std::min(blk, 2 * nu1);
+        HIPCHK(sweeps<T>(g, l, u, f, u, 0, h0, 1, nullptr));
     }
+    for (int h = h0; h < 2 * nu1; ++h) HIPCHK(half<T>(g, l, u, f, h & 1, h == 0 && zero_start, nullptr));
     // The pre-smoothing ended with a black half-sweep, so the residual is zero
     // on black nodes: compute and restrict the red part only. (The black part
     // of r is never written and stays zero.)
@@ -162,20 +207,30 @@ static lasto_status vcycle_level(lasto_grid g, int l, int nu1, int nu2, const T*
     lasto_status st = vcycle_level<T>(g, l + 1, nc1, nc2, Buf<T>::f(C), Buf<T>::u(C), nullptr, nullptr);
     if (st != LASTO_OK) return st;
     // a post-smoothing that starts with a black half-sweep recomputes every
-    // black value, so only red nodes take the interpolated correction
-    if (nu2 > 0) HIPCHK(launch_prolong_red<T>(V, C.view, Buf<T>::u(C), u, s));
+    // black value, so only red nodes take the interpolated correction. With
+    // a fused first pass the corrected red values go to r (free since the
+    // restriction) and the pass reads them there and writes u.
+    const int h1 = nu2 > 0 && blk >= 2 ? std::min(blk, 2 * nu2) : 0;
+    if (h1 > 0) HIPCHK(launch_prolong_red_to<T>(V, C.view, Buf<T>::u(C), u, r, s));
+    else if (nu2 > 0) HIPCHK(launch_prolong_red<T>(V, C.view, Buf<T>::u(C), u, s));
     else HIPCHK(launch_prolong_add<T>(V, C.view, Buf<T>::u(C), u, s));
     // read-modify-write of u at red (or all) nodes plus the coarse correction
     count(g, l, (nu2 > 0 ? 0.5 : 1.0) * 2 * sizeof(T) + cfrac * sizeof(T));
-    int nb1 = 0, nb2 = 0;
-    for (int k = 0; k < nu2; ++k) {
-        const bool last = (k == nu2 - 1) && dotp;
-        HIPCHK(half<T>(g, l, u, f, 1, 0, last ? dotp : nullptr, &nb1));
-        // the second half-sweep's partials follow the first's
-        HIPCHK(half<T>(g, l, u, f, 0, 0, last ? dotp + nb1 : nullptr, &nb2));
+    // post-smoothing: half-sweep h updates colour 1 - (h & 1) (black first);
+    // the last two carry the partials of <f, u>_W
+    int nb1 = 0, nb2 = 0, nbf = 0;
+    const bool dot_fused = dotp && h1 == 2 * nu2 && h1 > 0;
+    if (h1 > 0) HIPCHK(sweeps<T>(g, l, r, f, u, 1, h1, 0, dot_fused ? dotp : nullptr, &nbf));
+    for (int h = h1; h < 2 * nu2; ++h) {
+        const bool second_last = dotp && h == 2 * nu2 - 2, last = dotp && h == 2 * nu2 - 1;
+        // the last half-sweep's partials follow the second last's
+        HIPCHK(half<T>(g, l, u, f, (h & 1) ? 0 : 1, 0, second_last ? dotp : (last ? dotp + nb1 : nullptr),
+                       (h & 1) ? &nb2 : &nb1));
     }
     if (dotp) {
-        if (nu2 > 0) {
+        if (dot_fused) {
+            *ndot = nbf;
+        } else if (nu2 > 0) {
             *ndot = nb1 + nb2;
         } else {
             HIPCHK(launch_dot<T>(V, f, u, dotp, s));
@@ -252,7 +307,7 @@ static lasto_status vcycle0(lasto_grid g, const lasto_solve_opts& o, const T* f,
 {
     auto body = [&](int* nd) { return vcycle_level<T>(g, 0, o.nu1, o.nu2, f, u, dotp, nd); };
     if (!graphs_on(g, o)) return body(ndot);
-    const int key[8] = {1, (int)sizeof(T), o.nu1, o.nu2, g->coarse_mode, g->nu_coarse, 0, 0};
+    const int key[8] = {1, (int)sizeof(T), o.nu1, o.nu2, g->coarse_mode, g->nu_coarse, g->fused_sweeps, 0};
     const void* const ptr[4] = {f, u, dotp, nullptr};
     return graphed(g, key, ptr, body, ndot);
 }
@@ -366,8 +421,8 @@ static lasto_status pcg32_inner(lasto_grid g, const lasto_solve_opts& o, int ite
         auto body = [&](int*) { return pcg32_step(g, o, it, iters, v); };
         lasto_status st;
         if (graphs_on(g, o)) {
-            const int key[8] = {2, it % kInnerHist, last ? 1 : 0, o.nu1, o.nu2, g->coarse_mode, g->nu_coarse,
-                                it >= 2 ? 2 : it};
+            const int key[8] = {2, it % kInnerHist, last ? 1 : 0, o.nu1 * 64 + o.nu2, g->fused_sweeps,
+                                g->coarse_mode, g->nu_coarse, it >= 2 ? 2 : it};
             const void* const ptr[4] = {v, g->r32, g->z32, nullptr};
             st = graphed(g, key, ptr, body, nullptr);
         } else {
@@ -459,10 +514,12 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     if (o.method < 0 || o.method > 1 || o.precision < 0 || o.precision > 1 || o.bc < 0 || o.bc > 2 ||
         o.lmax_bc < 0 || o.lmax_bc > 4 || o.guess < 0 || o.guess > 3 || (o.precision == 1 && o.inner_iters < 1) ||
         o.inner_first < 0 || o.coarse < 0 || o.coarse > 2 || o.fallback < 0 || o.fallback > 1 ||
-        !(o.inner_rate >= 0.0 && o.inner_rate < 1.0) || o.nu_coarse < 0)
+        !(o.inner_rate >= 0.0 && o.inner_rate < 1.0) || o.nu_coarse < 0 ||
+        !(o.fused_sweeps == 0 || o.fused_sweeps == 1 || o.fused_sweeps == 2 || o.fused_sweeps == 4 ||
+          o.fused_sweeps == 6))
         return fail(LASTO_ERR_ARG,
                     "lasto_poisson_solve: bad method/precision/bc/lmax_bc/guess/inner_iters/coarse/fallback/"
-                    "inner_rate/nu_coarse");
+                    "inner_rate/nu_coarse/fused_sweeps");
     if (o.guess >= 2 && (o.n_atoms < 1 || !o.atoms))
         return fail(LASTO_ERR_ARG, "lasto_poisson_solve: guess 2 and 3 need the atom tables");
     if (o.guess == 3 && !o.guess_net) return fail(LASTO_ERR_ARG, "lasto_poisson_solve: guess 3 needs guess_net");
@@ -505,9 +562,11 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         {
             g->prof_on = false;
             g->nu_coarse = 0;
+            g->fused_sweeps = 0;
         }
     } prof_off{g};
     g->nu_coarse = o.nu_coarse;
+    g->fused_sweeps = o.fused_sweeps;
     for (hipEvent_t& e : g->ph_ev)
         if (!e) HIPCHK(hipEventCreate(&e));
     Level& L0 = g->lev[0];
@@ -1104,6 +1163,84 @@ extern "C" lasto_status lasto_apply(lasto_grid g, const double* u, double* Au)
     if (!g || !u || !Au || u == Au) return fail(LASTO_ERR_ARG, "lasto_apply: NULL or aliased buffers");
     HIPCHK(launch_apply_nat(g->lev[0].view, u, Au, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
+    return LASTO_OK;
+}
+
+// nsw half-sweeps at level l on split arrays, fused or one launch each
+template <typename T>
+static lasto_status smooth_split(lasto_grid g, int l, const T* uin, const T* f, T* u, int c0, int nsw, int zero_in,
+                                 int fused, double* dotp, int* ndot)
+{
+    const LevelView& V = g->lev[l].view;
+    hipStream_t s = g->stream;
+    if (fused) {
+        HIPCHK(launch_gs_block<T>(V, uin, f, u, c0, nsw, zero_in, T(1), dotp, s, ndot, l == 0));
+        return LASTO_OK;
+    }
+    HIPCHK(hipMemcpyAsync(u, uin, sizeof(T) * split_elems(V), hipMemcpyDeviceToDevice, s));
+    int off = 0;
+    for (int h = 0; h < nsw; ++h) {
+        const bool d = dotp && h >= nsw - 2;
+        int nb = 0;
+        HIPCHK(launch_half<T>(V, u, f, (c0 + h) & 1, h == 0 && zero_in, T(1), d ? dotp + off : nullptr, s, &nb,
+                              l == 0));
+        if (d) off += nb;
+    }
+    if (ndot) *ndot = off;
+    return LASTO_OK;
+}
+
+extern "C" lasto_status lasto_smooth(lasto_grid g, int level, int precision, const double* f, double* u, int nsweeps,
+                                     int first_colour, int zero_in, int fused, double* dot)
+{
+    if (!g || !f || !u || f == u) return fail(LASTO_ERR_ARG, "lasto_smooth: NULL or aliased buffers");
+    if (level < 0 || level >= g->nlev || precision < 0 || precision > 1 ||
+        !(nsweeps == 2 || nsweeps == 4 || nsweeps == 6) || (first_colour != 0 && first_colour != 1) ||
+        zero_in < 0 || zero_in > 1 || fused < 0 || fused > 1 || (dot && zero_in) ||
+        (fused && precision == 0 && nsweeps > gs_block_max<double>()))
+        return fail(LASTO_ERR_ARG, "lasto_smooth: bad level/precision/nsweeps/colour/zero_in/fused/dot");
+    Level& L = g->lev[level];
+    const LevelView& V = L.view;
+    hipStream_t s = g->stream;
+    const size_t n = split_elems(V);
+    // the level's own work arrays serve as scratch (level 0: the Krylov vectors)
+    double* U = level ? L.u64 : g->z;
+    double* F = level ? L.f64 : g->q;
+    double* I = L.r64;
+    HIPCHK(launch_nat_to_split(V, u, I, s));
+    HIPCHK(launch_nat_to_split(V, f, F, s));
+    int nd = 0;
+    double* dp = dot ? g->partials : nullptr;
+    if (precision == 0) {
+        if (lasto_status e = smooth_split<double>(g, level, I, F, U, first_colour, nsweeps, zero_in, fused, dp, &nd);
+            e != LASTO_OK)
+            return e;
+    } else {
+        float* U32 = level ? L.u32 : g->z32;
+        float* F32 = level ? L.f32 : g->q32;
+        float* I32 = L.r32;
+        HIPCHK(launch_cast(I, I32, n, s));
+        HIPCHK(launch_cast(F, F32, n, s));
+        if (lasto_status e = smooth_split<float>(g, level, I32, F32, U32, first_colour, nsweeps, zero_in, fused, dp,
+                                                 &nd);
+            e != LASTO_OK)
+            return e;
+        HIPCHK(launch_cast(U32, U, n, s));
+        HIPCHK(launch_fill_zero<float>(U32, n, s));
+        HIPCHK(launch_fill_zero<float>(F32, n, s));
+        HIPCHK(launch_fill_zero<float>(I32, n, s));
+    }
+    HIPCHK(launch_split_to_nat(V, U, u, s));
+    if (dot) {
+        HIPCHK(launch_reduce(g->partials, 1, nd, g->scalars + S_TMP, s));
+        if (lasto_status e = read_scalars(g, S_TMP, 1); e != LASTO_OK) return e;
+        *dot = g->h_scalars[S_TMP];
+    }
+    // the solver's arrays must come back with zero faces and padding
+    HIPCHK(launch_fill_zero<double>(U, n, s));
+    HIPCHK(launch_fill_zero<double>(F, n, s));
+    HIPCHK(launch_fill_zero<double>(I, n, s));
+    HIPCHK(hipStreamSynchronize(s));
     return LASTO_OK;
 }
 

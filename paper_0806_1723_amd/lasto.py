@@ -71,6 +71,7 @@ class SolveOpts(C.Structure):
         ("inner_rate", C.c_double),
         ("graphs", C.c_int),
         ("nu_coarse", C.c_int),
+        ("fused_sweeps", C.c_int),
     ]
 
 
@@ -125,7 +126,7 @@ SYMBOLS = [
     "lasto_solve_opts_default", "lasto_poisson_solve", "lasto_sphere_interp", "lasto_sphere_interp_noalloc",
     "lasto_spheres_create", "lasto_spheres_destroy", "lasto_sphere_density_terms", "lasto_sphere_project", "lasto_sphere_radial",
     "lasto_sphere_energy", "lasto_interstitial_density", "lasto_matrix_elements", "lasto_fdm_solve",
-    "lasto_fdm_axis", "lasto_apply", "lasto_rb_sweep", "lasto_stream_probe", "lasto_boundary_values", "lasto_analytic_guess",
+    "lasto_fdm_axis", "lasto_apply", "lasto_rb_sweep", "lasto_smooth", "lasto_stream_probe", "lasto_boundary_values", "lasto_analytic_guess",
     "lasto_net_create", "lasto_net_destroy", "lasto_net_set_grid",
     "lasto_net_param_count", "lasto_net_get_params", "lasto_net_set_params", "lasto_net_get_grads",
     "lasto_net_save", "lasto_net_load", "lasto_net_get_config", "lasto_net_tensor",
@@ -212,6 +213,8 @@ def load():
     L.lasto_stream_probe.restype = i
     L.lasto_rb_sweep.argtypes = [P, P, P, P, i]
     L.lasto_rb_sweep.restype = i
+    L.lasto_smooth.argtypes = [P, i, i, P, P, i, i, i, i, P]
+    L.lasto_smooth.restype = i
     L.lasto_boundary_values.argtypes = [P, P, i, i, P, P]
     L.lasto_boundary_values.restype = i
     L.lasto_analytic_guess.argtypes = [P, i, P, P]
@@ -461,6 +464,15 @@ class Grid:
             u_out = u_in.clone()
         _check(load().lasto_rb_sweep(self.h, _dev_ptr(u_in), _dev_ptr(rho), _dev_ptr(u_out), first_colour))
         return u_out
+
+    def smooth(self, level: int, f, u, nsweeps: int, first_colour: int = 0, zero_in: bool = False,
+               fused: bool = True, precision: int = 0, dot: bool = False):
+        """Red-black half-sweeps on A u = f (zero faces) at a level; u is updated in place.
+        Returns the partial <f, u>_W of the last two half-sweeps when dot is set, else None."""
+        d = C.c_double(0.0)
+        _check(load().lasto_smooth(self.h, level, precision, _dev_ptr(f), _dev_ptr(u), nsweeps, first_colour,
+                                   int(zero_in), int(fused), C.byref(d) if dot else None))
+        return d.value if dot else None
 
     def boundary_values(self, rho, v, bc: int = 1, lmax_bc: int = 4):
         Q = np.zeros((self.n_batch, 25))

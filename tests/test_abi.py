@@ -37,14 +37,14 @@ def test_library_exports_every_declared_call():
 def test_struct_layouts_match_the_header(tmp_path):
     prog = tmp_path / "sizes.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lasto.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lasto_atom), '
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lasto_atom), '
                     'sizeof(lasto_solve_opts), sizeof(lasto_solve_info), '
                     'offsetof(lasto_solve_info, smooth_ms), offsetof(lasto_atom, clm), '
                     'offsetof(lasto_solve_opts, atoms), offsetof(lasto_solve_opts, coarse_net_level), '
                     'offsetof(lasto_solve_info, ms_bc), offsetof(lasto_solve_info, alg_bytes), '
                     'offsetof(lasto_solve_opts, inner_rate), offsetof(lasto_solve_info, inner_rate), '
                     'offsetof(lasto_solve_info, rel_start), offsetof(lasto_solve_opts, graphs), '
-                    'offsetof(lasto_solve_opts, nu_coarse));return 0;}\n')
+                    'offsetof(lasto_solve_opts, nu_coarse), offsetof(lasto_solve_opts, fused_sweeps));return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
@@ -52,7 +52,7 @@ def test_struct_layouts_match_the_header(tmp_path):
             L.SolveInfo.smooth_ms.offset, L.Atom.clm.offset, L.SolveOpts.atoms.offset,
             L.SolveOpts.coarse_net_level.offset, L.SolveInfo.ms_bc.offset, L.SolveInfo.alg_bytes.offset,
             L.SolveOpts.inner_rate.offset, L.SolveInfo.inner_rate.offset, L.SolveInfo.rel_start.offset,
-            L.SolveOpts.graphs.offset, L.SolveOpts.nu_coarse.offset]
+            L.SolveOpts.graphs.offset, L.SolveOpts.nu_coarse.offset, L.SolveOpts.fused_sweeps.offset]
     assert got == want
 
 
@@ -63,6 +63,7 @@ def test_status_strings_and_defaults():
     assert (o.rtol, o.max_iters, o.nu1, o.nu2, o.method, o.precision, o.bc, o.lmax_bc, o.guess) == \
         (1e-10, 100, 2, 2, 0, 0, 1, 4, 0)
     assert o.debug_nan_iter == -1 and o.profile == 0 and o.inner_rate == 0.0 and o.graphs == 0
+    assert o.fused_sweeps == 0
 
 
 @pytest.mark.parametrize("cid,sample", [(1, 0), (2, 0), (3, 0), (5, 0), (4, 0), (4, 17)])
