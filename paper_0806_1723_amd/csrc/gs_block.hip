@@ -233,10 +233,13 @@ __global__ __launch_bounds__(GB_NT) void k_gs_block(LevelView L, const T* __rest
             static_for<0, S>([&](auto sc) {
                 constexpr int s = decltype(sc)::value;
                 const int p = tt - s;
-                const int c = (c0 + s) & 1;
                 T r = T(0);
                 if (p >= lo(s) && p <= hi(s) && w >= s + 1 && w <= GB_ROWS - 2 - s) {
-                    const T fv = (s & 1) ? qb[s - 1] : qa[s];
+                    T fv;
+                    if constexpr ((s & 1) != 0)
+                        fv = qb[s - 1];
+                    else
+                        fv = qa[s];
                     const T xl = o ? p1[s] : xn[s], xr = o ? xn[s] : p1[s];
                     if (ZERO_IN && s == 0)
                         r = gs_update0(cxm, cxp, cym, cyp, czm[s], czp[s], bscale, fv);
@@ -248,7 +251,6 @@ __global__ __launch_bounds__(GB_NT) void k_gs_block(LevelView L, const T* __rest
                     if (DOT && s >= S - 2 && tile && p >= k0 && p < k1) {
                         dot += (double)(o ? vx1 : vx0) * (vy * zv[s]) * (double)fv * (double)r;
                     }
-                    (void)c;
                 }
                 cur[s + 1] = r;
             });

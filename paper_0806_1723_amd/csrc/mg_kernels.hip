@@ -1160,11 +1160,9 @@ hipError_t launch_inject_nan(float* r, size_t idx, hipStream_t s)
 // Both transfers tile their level like the half-sweeps: a workgroup covers
 // 64 x 4 (x, y) columns, and tiles go to the XCDs in contiguous runs
 // (xcd_tile), so fine rows shared by neighbouring tiles are mostly read from
-// one L2. A thread takes KU consecutive planes and issues every gather of all
-// of them before it sums any (their table lookups first, then the values),
-// so it waits on memory twice rather than twice per plane.
-template <typename T> struct TransferUnroll { static constexpr int KU = 2; };
-template <> struct TransferUnroll<double> { static constexpr int KU = 2; };
+// one L2. A thread marches a chunk of planes (sized like the residual's), and
+// since both operators are products of per-axis weights, each plane's x-y sum
+// is formed once and reused by the neighbouring planes of the other level.
 
 struct TileShape {
     int nbx, nby, nb, per;
@@ -1190,88 +1188,106 @@ static TileShape tile_shape(int cols_x, int rows_y, int planes, int ku)
 }
 
 // f_coarse = R r on the interior of the coarse level, r vanishing on black
-// fine nodes; one coarse (I, J) column per thread, KU planes
+// fine nodes. One coarse (I, J) column per thread, marching a chunk of kc
+// coarse planes: R is a product of per-axis weights, so the x-y sum of fine
+// plane kk at the column is formed once (three two-entry loads) and kept
+// while the coarse planes that use it pass (a coarse step spans one or two
+// fine steps, so each coarse plane adds one or two fine planes). The sums are
+// taken in the order of the per-plane form (y inside z), so the result does
+// not depend on the chunking.
 template <typename T>
 __global__ __launch_bounds__(PT_NT) void k_restrict_red(LevelView F, LevelView C, const T* __restrict__ r,
-                                                        T* __restrict__ rc, int nbx, int nby, int nb, int per)
+                                                        T* __restrict__ rc, int nbx, int nby, int nb, int per, int kc)
 {
-    constexpr int KU = TransferUnroll<T>::KU;
     const int t = xcd_tile(blockIdx.x, per);
     const int I = 1 + (t % nbx) * PT_X + (threadIdx.x & (PT_X - 1));
     const int J = 1 + ((t / nbx) % nby) * PT_Y + (threadIdx.x >> 6);
     if (t >= nb || J > C.ny - 2) return;
     const bool inside = I <= C.nx - 2;
-    const int k0 = 1 + (t / (nbx * nby)) * KU;
-    // table lookups of the column and its planes (out-of-range planes are
-    // clamped to the last interior plane and not stored)
+    const int K0 = 1 + (t / (nbx * nby)) * kc;
+    const int K1 = min(K0 + kc, C.nz - 1);
     const RTaps<T> x = restrict_taps<T>(C, inside ? I : C.nx - 2);
     const int fj = C.ax[1].rf[J];
     const T wy0 = (T)C.ax[1].rw[3 * J], wy1 = (T)C.ax[1].rw[3 * J + 1], wy2 = (T)C.ax[1].rw[3 * J + 2];
-    int fk[KU];
-    T wz[KU][3];
+    // the x-y sum of fine plane kk: two consecutive red entries of each of
+    // the three fine rows, as one load (aligned to one element only)
+    auto pxy = [&](int kk) -> T {
+        T g0[3], g1[3];
 #pragma unroll
-    for (int u = 0; u < KU; ++u) {
-        const int K = min(k0 + u, C.nz - 2);
-        fk[u] = C.ax[2].rf[K];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) wz[u][c] = (T)C.ax[2].rw[3 * K + c];
-    }
-    // the gathers: two consecutive red entries of each of the 3 x 3 fine rows
-    // per plane, as one load (aligned to one element only)
-    T g0[KU][3][3], g1[KU][3][3];
-#pragma unroll
-    for (int u = 0; u < KU; ++u)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const T* row = r + ((size_t)(fk[u] - 1 + c) * F.ny + (fj - 1 + b)) * F.W + x.m0;
-                const typename Pair<T>::P q = *(const typename Pair<T>::P*)row;
-                g0[u][c][b] = q.x;
-                g1[u][c][b] = q.y;
-            }
-#pragma unroll
-    for (int u = 0; u < KU; ++u) {
-        T acc = T(0);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T plane = T(0);
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const bool same = ((fj - 1 + b + fk[u] - 1 + c) & 1) == x.e;
-                const T wy = b == 0 ? wy0 : (b == 1 ? wy1 : wy2);
-                plane += wy * ((same ? x.s0 : x.d0) * g0[u][c][b] + (same ? x.s1 : x.d1) * g1[u][c][b]);
-            }
-            acc += wz[u][c] * plane;
+        for (int b = 0; b < 3; ++b) {
+            const T* row = r + ((size_t)kk * F.ny + (fj - 1 + b)) * F.W + x.m0;
+            const typename Pair<T>::P q = *(const typename Pair<T>::P*)row;
+            g0[b] = q.x;
+            g1[b] = q.y;
         }
-        if (inside && k0 + u <= C.nz - 2 && C.zint[k0 + u]) rc[sidx(C, I, J, k0 + u)] = acc;
+        T plane = T(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const bool same = ((fj - 1 + b + kk) & 1) == x.e;
+            const T wy = b == 0 ? wy0 : (b == 1 ? wy1 : wy2);
+            plane += wy * ((same ? x.s0 : x.d0) * g0[b] + (same ? x.s1 : x.d1) * g1[b]);
+        }
+        return plane;
+    };
+    // sums of fine planes fk - 1, fk, fk + 1 of the previous coarse plane
+    int fprev = -8;
+    T w0 = T(0), w1 = T(0), w2 = T(0);
+    for (int K = K0; K < K1; ++K) {
+        const int fk = C.ax[2].rf[K];
+        if (fk == fprev + 1) {
+            w0 = w1;
+            w1 = w2;
+            w2 = pxy(fk + 1);
+        } else if (fk == fprev + 2) {
+            const T a = pxy(fk), b = pxy(fk + 1);
+            w0 = w2;
+            w1 = a;
+            w2 = b;
+        } else {
+            const T a = pxy(fk - 1), b = pxy(fk), c = pxy(fk + 1);
+            w0 = a;
+            w1 = b;
+            w2 = c;
+        }
+        fprev = fk;
+        T acc = T(0);
+        acc += (T)C.ax[2].rw[3 * K] * w0;
+        acc += (T)C.ax[2].rw[3 * K + 1] * w1;
+        acc += (T)C.ax[2].rw[3 * K + 2] * w2;
+        if (inside && C.zint[K]) rc[sidx(C, I, J, K)] = acc;
     }
 }
 
 template <typename T>
 hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s)
 {
-    const TileShape ts = tile_shape(C.nx - 2, C.ny - 2, C.nz - 2, TransferUnroll<T>::KU);
+    const int gx = (C.nx - 2 + PT_X - 1) / PT_X, gy = (C.ny - 2 + PT_Y - 1) / PT_Y;
+    const int kc = chunk_planes((long)gx * gy, C.nz - 2, resident_256(), PT_KP_MAX);
+    const TileShape ts = tile_shape(C.nx - 2, C.ny - 2, C.nz - 2, kc);
     hipLaunchKernelGGL(k_restrict_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, r, rc, ts.nbx, ts.nby, ts.nb,
-                       ts.per);
+                       ts.per, kc);
     return hipGetLastError();
 }
 
 // u + P e on the red nodes only: when a black half-sweep follows, it
 // overwrites every black value, so correcting them would be wasted work. Two
 // consecutive red entries m, m+1 of a row per thread (fine nodes i0 = o + 2m
-// and i1 = i0 + 2, o = (j + k) & 1), KU planes. Their coarse nodes lie in
-// Ix0 .. Ix0 + 3 (Ix0 = pc(i0); a coarse step spans at most two fine steps),
-// which in each coarse row are two consecutive entries of each colour: two
-// pair loads per row serve both fine nodes. The result goes to uout, which
-// is uin (in place) or another array (its red entries written, the rest
-// untouched); each thread loads all its values before it stores any.
+// and i1 = i0 + 2, o = (j + k) & 1), marching a chunk of kc fine planes.
+// Their coarse nodes lie in Ix0 .. Ix0 + 3 (Ix0 = pc(i0); a coarse step spans
+// at most two fine steps), which in each coarse row are two consecutive
+// entries of each colour: two pair loads per row serve both fine nodes. P is
+// a product of per-axis weights, so the x-y sums of a coarse plane (for both
+// row parities and both nodes) are formed once and kept while the fine
+// planes between it and the next pass (one or two of them); the sums are
+// taken in the order of the per-plane form (y inside z). The result goes to
+// uout, which is uin (in place) or another array (its red entries written,
+// the rest untouched); each thread reads its own entries before it writes
+// them.
 template <typename T>
 __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C, const T* __restrict__ e,
-                                                       const T* uin, T* uout, int nbx, int nby, int nb, int per)
+                                                       const T* uin, T* uout, int nbx, int nby, int nb, int per, int kc)
 {
     typedef typename Pair<T>::P P2;
-    constexpr int KU = TransferUnroll<T>::KU;
     const int t = xcd_tile(blockIdx.x, per);
     const int m = 2 * ((t % nbx) * PT_X + (threadIdx.x & (PT_X - 1)));
     const int j = 1 + ((t / nbx) % nby) * PT_Y + (threadIdx.x >> 6);
@@ -1289,71 +1305,83 @@ __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C,
         xb[o] = prolong_taps<T>(C.ax[0], min(max(i1, 1), F.nx - 2));
     }
     const PTaps<T> y = prolong_taps<T>(C.ax[1], j);
-    const int k0 = 1 + (t / (nbx * nby)) * KU;
-    PTaps<T> z[KU];
-#pragma unroll
-    for (int q = 0; q < KU; ++q) z[q] = prolong_taps<T>(C.ax[2], min(k0 + q, F.nz - 2));
+    const int k0 = 1 + (t / (nbx * nby)) * kc;
+    const int k1 = min(k0 + kc, F.nz - 1);
     const size_t plane = (size_t)F.ny * F.W;
     const size_t row = (size_t)j * F.W + m;
-    // per plane and coarse row (b, c): the coarse values at Ix0 .. Ix0 + 3
-    T cv[KU][2][2][4];
-    P2 uo[KU];
+    // the x-y sums of coarse plane Kc: sv[o][0] for node i0, sv[o][1] for i1
+    auto sums = [&](int Kc, T (&sv)[2][2]) {
+        T cv[2][2][4];
 #pragma unroll
-    for (int q = 0; q < KU; ++q) {
-        const int k = min(k0 + q, F.nz - 2);
-        const int o = (j + k) & 1;
-        const int I0 = o ? xa[1].I : xa[0].I;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int o = 0; o < 2; ++o) {
+            const int I0 = xa[o].I;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                const int Jb = y.I + b, Kc = z[q].I + c;
+                const int Jb = y.I + b;
                 const size_t crow = ((size_t)Kc * C.ny + Jb) * C.W;
                 const int c0 = (I0 + Jb + Kc) & 1;   // colour of I0 (and I0 + 2); I0 + 1, I0 + 3 have the other
                 const P2 p0 = *(const P2*)(e + (size_t)c0 * C.cs + crow + (I0 >> 1));
                 const P2 p1 = *(const P2*)(e + (size_t)(c0 ^ 1) * C.cs + crow + ((I0 + 1) >> 1));
-                cv[q][c][b][0] = p0.x;
-                cv[q][c][b][1] = p1.x;
-                cv[q][c][b][2] = p0.y;
-                cv[q][c][b][3] = p1.y;
+                cv[o][b][0] = p0.x;
+                cv[o][b][1] = p1.x;
+                cv[o][b][2] = p0.y;
+                cv[o][b][3] = p1.y;
             }
-        uo[q] = *(const P2*)(uin + (size_t)k * plane + row);
-    }
+        }
 #pragma unroll
-    for (int q = 0; q < KU; ++q) {
-        const int k = k0 + q;
-        if (k > F.nz - 2 || !F.zint[k]) continue;
-        const int o = (j + k) & 1;
-        const PTaps<T>& A = o ? xa[1] : xa[0];
-        const PTaps<T>& B = o ? xb[1] : xb[0];
-        const int d = B.I - A.I;   // 0, 1 or 2
-        T acc0 = T(0), acc1 = T(0);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int o = 0; o < 2; ++o) {
+            const PTaps<T>& A = xa[o];
+            const PTaps<T>& B = xb[o];
+            const int d = B.I - A.I;   // 0, 1 or 2
             T s0 = T(0), s1 = T(0);
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                const T* v = cv[q][c][b];
+                const T* v = cv[o][b];
                 const T wyb = b ? y.w1 : y.w0;
                 s0 += wyb * (A.w0 * v[0] + A.w1 * v[1]);
                 const T b0 = d == 0 ? v[0] : (d == 1 ? v[1] : v[2]);
                 const T b1 = d == 0 ? v[1] : (d == 1 ? v[2] : v[3]);
                 s1 += wyb * (B.w0 * b0 + B.w1 * b1);
             }
-            const T wzc = c ? z[q].w1 : z[q].w0;
-            acc0 += wzc * s0;
-            acc1 += wzc * s1;
+            sv[o][0] = s0;
+            sv[o][1] = s1;
         }
+    };
+    // sums of coarse planes kcur and kcur + 1 (the cell of the previous plane)
+    T sa[2][2], sb[2][2];
+    int kcur = -8;
+    for (int k = k0; k < k1; ++k) {
+        const PTaps<T> z = prolong_taps<T>(C.ax[2], k);
+        const P2 uo = *(const P2*)(uin + (size_t)k * plane + row);
+        if (z.I == kcur + 1) {
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+                sa[o][0] = sb[o][0];
+                sa[o][1] = sb[o][1];
+            }
+            sums(z.I + 1, sb);
+        } else if (z.I != kcur) {
+            sums(z.I, sa);
+            sums(z.I + 1, sb);
+        }
+        kcur = z.I;
+        if (!F.zint[k]) continue;
+        const int o = (j + k) & 1;
+        T acc0 = T(0), acc1 = T(0);
+        acc0 += z.w0 * sa[o][0];
+        acc1 += z.w0 * sa[o][1];
+        acc0 += z.w1 * sb[o][0];
+        acc1 += z.w1 * sb[o][1];
         const bool s_a = o ? oka[1] : oka[0], s_b = o ? okb[1] : okb[0];
         T* out = uout + (size_t)k * plane + row;
         if (s_a && s_b) {
             P2 w;
-            w.x = uo[q].x + acc0;
-            w.y = uo[q].y + acc1;
+            w.x = uo.x + acc0;
+            w.y = uo.y + acc1;
             *(P2*)out = w;
         } else {
-            if (s_a) out[0] = uo[q].x + acc0;
-            if (s_b) out[1] = uo[q].y + acc1;
+            if (s_a) out[0] = uo.x + acc0;
+            if (s_b) out[1] = uo.y + acc1;
         }
     }
 }
@@ -1361,10 +1389,7 @@ __global__ __launch_bounds__(PT_NT) void k_prolong_red(LevelView F, LevelView C,
 template <typename T>
 hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s)
 {
-    // pairs of red entries m = 0, 2, ... <= (nx - 2) / 2
-    const TileShape ts = tile_shape(((F.nx - 2) / 2) / 2 + 1, F.ny - 2, F.nz - 2, TransferUnroll<T>::KU);
-    hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, e, u, u, ts.nbx, ts.nby, ts.nb,
-                       ts.per);
+    return launch_prolong_red_to<T>(F, C, e, u, u, s);
     return hipGetLastError();
 }
 
@@ -1372,9 +1397,13 @@ template <typename T>
 hipError_t launch_prolong_red_to(const LevelView& F, const LevelView& C, const T* e, const T* uin, T* out,
                                  hipStream_t s)
 {
-    const TileShape ts = tile_shape(((F.nx - 2) / 2) / 2 + 1, F.ny - 2, F.nz - 2, TransferUnroll<T>::KU);
+    // pairs of red entries m = 0, 2, ... <= (nx - 2) / 2
+    const int cols = ((F.nx - 2) / 2) / 2 + 1;
+    const int gx = (cols + PT_X - 1) / PT_X, gy = (F.ny - 2 + PT_Y - 1) / PT_Y;
+    const int kc = chunk_planes((long)gx * gy, F.nz - 2, resident_256(), PT_KP_MAX);
+    const TileShape ts = tile_shape(cols, F.ny - 2, F.nz - 2, kc);
     hipLaunchKernelGGL(k_prolong_red<T>, dim3(8 * ts.per), dim3(PT_NT), 0, s, F, C, e, uin, out, ts.nbx, ts.nby,
-                       ts.nb, ts.per);
+                       ts.nb, ts.per, kc);
     return hipGetLastError();
 }
 
