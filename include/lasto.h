@@ -171,7 +171,7 @@ typedef struct {
                            its reduction is bounded by FP32 rounding of the operator sooner than later ones */
     int coarse;         /* coarsest solve of the cycle, exact by fast diagonalisation of the level's
                            tensor-product operator: 0 (default) on the first level below the finest with
-                           at most 1.2e6 nodes per right-hand side if that level has more than 16384 nodes
+                           at most 3e6 nodes per right-hand side if that level has more than 16384 nodes
                            (by GEMMs), else as 2; 2 on the first level with at most 16384 nodes (each axis
                            at most 34 nodes, the level below the finest, its block in one workgroup's LDS),
                            else as 1; 1 red-black sweeps on every level down to the coarsest */

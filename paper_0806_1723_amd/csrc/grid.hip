@@ -505,7 +505,8 @@ extern "C" lasto_status lasto_grid_create(const double* x, int nx, const double*
         st = alloc_zero(g, (void**)&g->stage, g->stage_bytes);
     }
     if (st == LASTO_OK) {
-        if (hipHostMalloc((void**)&g->h_scalars, sizeof(double) * kNumScalars) != hipSuccess)
+        // the scalars, then the first right-hand side's moments (copied while a solve runs)
+        if (hipHostMalloc((void**)&g->h_scalars, sizeof(double) * (kNumScalars + 25)) != hipSuccess)
             st = fail(LASTO_ERR_ALLOC, "lasto_grid_create: pinned host scalars");
     }
     if (st == LASTO_OK) {

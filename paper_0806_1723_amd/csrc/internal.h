@@ -164,7 +164,7 @@ template <> struct TailBuf<float> {
 };
 
 constexpr size_t kTailMaxPts = 16384;   // levels at or below this size run in the tail kernel
-constexpr size_t kGemmCoarseMaxPts = 1200000;   // per copy: the largest level the GEMM coarsest solve takes
+constexpr size_t kGemmCoarseMaxPts = 3000000;   // per copy: the largest level the GEMM coarsest solve takes
 
 // LDS layout of the FP32 tail. Per level q (0 = the first level it takes):
 // dims nx, ny, nz, W, cs; offsets (floats) of its correction and right-hand
@@ -262,7 +262,7 @@ struct lasto_grid_s {
     // reductions
     double* partials = nullptr;
     double* scalars = nullptr;      // [kNumScalars]
-    double* h_scalars = nullptr;    // pinned host mirror
+    double* h_scalars = nullptr;    // pinned host mirror (then 25 moments at h_scalars + kNumScalars)
     double* moments = nullptr;      // device [25 * n_batch]
     lasto::LevelView cview;         // the finest level as one copy of the batch sees it
     // scratch of the learned entry points (finest-level size, allocated on

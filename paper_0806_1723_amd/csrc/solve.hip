@@ -579,7 +579,11 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
     // face values (every right-hand side of a batch from its own moments)
     if (o.bc == 0 || o.bc == 1) {
         if (lasto_status e = set_faces(g, rho, o.bc, o.lmax_bc, v); e != LASTO_OK) return e;
-        // (the moments reach info at the end, when the solve has synchronised)
+        // the first right-hand side's moments for info, copied to pinned host
+        // memory while the solve runs (read after the solve's last wait)
+        if (o.bc == 1)
+            HIPCHK(hipMemcpyAsync(g->h_scalars + kNumScalars, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost,
+                                  s));
     }
     HIPCHK(hipEventRecord(g->ph_ev[1], s));
     // the start inside
@@ -641,7 +645,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         inf.n_batch = nbat;
         inf.ms_bc = event_ms(g->ph_ev[0], g->ph_ev[1]);
         inf.ms_guess = event_ms(g->ph_ev[1], g->ph_ev[2]);
-        if (o.bc == 1) HIPCHK(hipMemcpy(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost));
+        if (o.bc == 1) std::memcpy(inf.moments, g->h_scalars + kNumScalars, sizeof(double) * 25);
         inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         if (info) *info = inf;
         return LASTO_OK;
@@ -908,7 +912,7 @@ extern "C" lasto_status lasto_poisson_solve(lasto_grid g, const double* rho, dou
         result = LASTO_ERR_DIVERGED;
         why = "lasto_poisson_solve: residual not finite";
     }
-    if (o.bc == 1) HIPCHK(hipMemcpy(inf.moments, g->moments, sizeof(double) * 25, hipMemcpyDeviceToHost));
+    if (o.bc == 1) std::memcpy(inf.moments, g->h_scalars + kNumScalars, sizeof(double) * 25);
     inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (info) *info = inf;
     if (result != LASTO_OK) return fail(result, why);
