@@ -279,12 +279,69 @@ hipError_t launch_pseudo(lasto_grid g, const AtomDev* atoms, int n_atoms, const 
 // relative: far below what the guess itself misses (the l >= 1 terms, the
 // discretisation).
 constexpr int GU_X = 64, GU_Y = 4, GU_Z = 4, GU_NT = GU_X * GU_Y, GU_CHUNK = 512, GU_PART = 32;
+constexpr float kTwoOverSqrtPi = 1.12837916709551257f;
+
+// an atom's LDS entry (near-field radius^2 and the near-field constants):
+// kind 0 (Gaussian): (36 w^2, 1/w, the radius below which erf(r/w)/r takes
+// its r -> 0 limit, that limit 2/(sqrt(pi) w)); kind 1 (uniform ball):
+// (R^2, 0, 3 R^2, 1/(2 R^3))
+__device__ __forceinline__ float4 guess_params(const AtomDev& A)
+{
+    if (A.kind == 0) {
+        const float iw = (float)(1.0 / A.w);
+        return make_float4((float)(36.0 * A.w * A.w), iw, 1e-6f / iw, kTwoOverSqrtPi * iw);
+    }
+    return make_float4((float)(A.R * A.R), 0.0f, (float)(3.0 * A.R * A.R), (float)(0.5 / (A.R * A.R * A.R)));
+}
+
+// The workgroup's nodes as FP32 offsets from its origin (the same roundings
+// as the nodes' own offsets), and whether an atom's near field (squared
+// radius r2n) may reach one of them: the squared distance from the centre to
+// the box, taken a little short (a relative 1e-4 and 1e-30), below r2n. An
+// atom it clears is beyond r2n from every node by more than any rounding of
+// the nodes' own r^2, so those take the far field whichever path they run.
+struct GuessBox {
+    float xl, xh, yl, yh, zl, zh;
+    __device__ int reaches(const float4& c, float r2n) const
+    {
+        const float dx = fmaxf(fmaxf(xl - c.x, c.x - xh), 0.0f);
+        const float dy = fmaxf(fmaxf(yl - c.y, c.y - yh), 0.0f);
+        const float dz = fmaxf(fmaxf(zl - c.z, c.z - zh), 0.0f);
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        return d2 * (1.0f - 1e-4f) - 1e-30f < r2n ? 1 : 0;
+    }
+};
+
+__device__ __forceinline__ GuessBox guess_box(const LevelView& L, int i0, int j0, int k0, int nzp, double ox, double oy,
+                                              double oz)
+{
+    GuessBox b;
+    const int i1 = min(i0 + GU_X - 1, L.nx - 2), j1 = min(j0 + GU_Y - 1, L.ny - 2), k1 = min(k0 + nzp - 1, L.nz - 2);
+    b.xl = (float)(L.ax[0].x[i0] - ox);
+    b.xh = (float)(L.ax[0].x[i1] - ox);
+    b.yl = (float)(L.ax[1].x[j0] - oy);
+    b.yh = (float)(L.ax[1].x[j1] - oy);
+    b.zl = (float)(L.ax[2].x[min(k0, L.nz - 2)] - oz);
+    b.zh = (float)(L.ax[2].x[k1] - oz);
+    return b;
+}
+
+// the potential shape at squared distance r2 < p.x from the atom (near field)
+__device__ __forceinline__ float guess_near(float r2, const float4& p)
+{
+    if (p.y > 0.0f) {
+        const float r = sqrtf(r2);
+        return r > p.z ? erff(r * p.y) / r : p.w;   // erf(r/w)/r, its limit at r = 0
+    }
+    return (p.z - r2) * p.w;                         // (3R^2 - r^2)/(2R^3)
+}
 
 __global__ __launch_bounds__(GU_NT) void k_guess(LevelView L, const AtomDev* __restrict__ atoms, int n_atoms,
                                                  double* __restrict__ v)
 {
     __shared__ float4 sc[GU_CHUNK];   // atom centre relative to the origin, and charge
-    __shared__ float4 sp[GU_CHUNK];   // near-field radius^2, 1/w (kind 0) or 0, R^2 and 1/(2 R^3) (kind 1)
+    __shared__ float4 sp[GU_CHUNK];   // guess_params
+    __shared__ int sn[GU_CHUNK];      // 1: the atom's near field may reach this workgroup's nodes
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int i0 = 1 + blockIdx.x * GU_X, j0 = 1 + blockIdx.y * GU_Y, k0 = 1 + blockIdx.z * GU_Z;
     const int i = i0 + (threadIdx.x & (GU_X - 1)), j = j0 + (int)(threadIdx.x / GU_X);
@@ -298,18 +355,15 @@ __global__ __launch_bounds__(GU_NT) void k_guess(LevelView L, const AtomDev* __r
     double acc[GU_Z];
 #pragma unroll
     for (int t = 0; t < GU_Z; ++t) acc[t] = 0.0;
-    constexpr float kTwoOverSqrtPi = 1.12837916709551257f;
+    const GuessBox box = guess_box(L, i0, j0, k0, GU_Z, ox, oy, oz);
     for (int a0 = 0; a0 < n_atoms; a0 += GU_CHUNK) {
         const int na = min(GU_CHUNK, n_atoms - a0);
         __syncthreads();
         for (int t = threadIdx.x; t < na; t += GU_NT) {
             const AtomDev& A = atoms[a0 + t];
             sc[t] = make_float4((float)(A.c[0] - ox), (float)(A.c[1] - oy), (float)(A.c[2] - oz), (float)A.q);
-            if (A.kind == 0)
-                sp[t] = make_float4((float)(36.0 * A.w * A.w), (float)(1.0 / A.w), 0.0f, 0.0f);
-            else
-                sp[t] = make_float4((float)(A.R * A.R), 0.0f, (float)(3.0 * A.R * A.R),
-                                    (float)(0.5 / (A.R * A.R * A.R)));
+            sp[t] = guess_params(A);
+            sn[t] = box.reaches(sc[t], sp[t].x);
         }
         __syncthreads();
         for (int a1 = 0; a1 < na; a1 += GU_PART) {
@@ -322,22 +376,28 @@ __global__ __launch_bounds__(GU_NT) void k_guess(LevelView L, const AtomDev* __r
                 const float4 p = sp[a];
                 const float dx = fx - c.x, dy = fy - c.y;
                 const float dxy = fmaf(dx, dx, dy * dy);
+                // the far field 1/r on every plane, then the near field
+                // where a lane needs it (only for atoms whose near field may
+                // reach the workgroup, a test uniform over it)
+                float r2[GU_Z], f[GU_Z];
 #pragma unroll
                 for (int t = 0; t < GU_Z; ++t) {
                     const float dz = fz[t] - c.z;
-                    const float r2 = fmaf(dz, dz, dxy);
-                    float f;
-                    if (r2 >= p.x) {
-                        f = __builtin_amdgcn_rsqf(r2);   // -q/r
-                    } else if (p.y > 0.0f) {
-                        // Gaussian: erf(r/w)/r, 2/(sqrt(pi) w) at r = 0
-                        const float r = sqrtf(r2);
-                        f = r > 1e-6f / p.y ? erff(r * p.y) / r : kTwoOverSqrtPi * p.y;
-                    } else {
-                        f = (p.z - r2) * p.w;   // uniform ball: (3R^2 - r^2)/(2R^3)
-                    }
-                    part[t] = fmaf(-c.w, f, part[t]);
+                    r2[t] = fmaf(dz, dz, dxy);
+                    f[t] = __builtin_amdgcn_rsqf(r2[t]);
                 }
+                if (sn[a]) {
+                    bool near = false;
+#pragma unroll
+                    for (int t = 0; t < GU_Z; ++t) near |= !(r2[t] >= p.x);
+                    if (near) {
+#pragma unroll
+                        for (int t = 0; t < GU_Z; ++t)
+                            if (!(r2[t] >= p.x)) f[t] = guess_near(r2[t], p);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < GU_Z; ++t) part[t] = fmaf(-c.w, f[t], part[t]);
             }
 #pragma unroll
             for (int t = 0; t < GU_Z; ++t) acc[t] += (double)part[t];
@@ -373,6 +433,7 @@ __global__ __launch_bounds__(GU_NT) void k_guess_shared(LevelView L, const AtomD
     __shared__ float4 sc[GU_CHUNK];     // atom centre relative to the origin; w unused
     __shared__ float4 sp[GU_CHUNK];     // as in k_guess
     __shared__ float sq[GU_CHUNK][NB];  // the charge of the atom in each copy
+    __shared__ int sn[GU_CHUNK];        // as in k_guess
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int i0 = 1 + blockIdx.x * GU_X, j0 = 1 + blockIdx.y * GU_Y, k0 = 1 + blockIdx.z * GB_Z;
     const int i = i0 + (threadIdx.x & (GU_X - 1)), j = j0 + (int)(threadIdx.x / GU_X);
@@ -390,18 +451,15 @@ __global__ __launch_bounds__(GU_NT) void k_guess_shared(LevelView L, const AtomD
     for (int t = 0; t < GB_Z; ++t)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[t][b] = 0.0;
-    constexpr float kTwoOverSqrtPi = 1.12837916709551257f;
+    const GuessBox box = guess_box(L, i0, j0, k0, GB_Z, ox, oy, oz);
     for (int a0 = 0; a0 < n_atoms; a0 += GU_CHUNK) {
         const int na = min(GU_CHUNK, n_atoms - a0);
         __syncthreads();
         for (int t = threadIdx.x; t < na; t += GU_NT) {
             const AtomDev& A = atoms[a0 + t];
             sc[t] = make_float4((float)(A.c[0] - ox), (float)(A.c[1] - oy), (float)(A.c[2] - oz), 0.0f);
-            if (A.kind == 0)
-                sp[t] = make_float4((float)(36.0 * A.w * A.w), (float)(1.0 / A.w), 0.0f, 0.0f);
-            else
-                sp[t] = make_float4((float)(A.R * A.R), 0.0f, (float)(3.0 * A.R * A.R),
-                                    (float)(0.5 / (A.R * A.R * A.R)));
+            sp[t] = guess_params(A);
+            sn[t] = box.reaches(sc[t], sp[t].x);
 #pragma unroll
             for (int b = 0; b < NB; ++b) sq[t][b] = (float)atoms[(size_t)b * n_atoms + a0 + t].q;
         }
@@ -418,22 +476,27 @@ __global__ __launch_bounds__(GU_NT) void k_guess_shared(LevelView L, const AtomD
                 const float4 p = sp[a];
                 const float dx = fx - c.x, dy = fy - c.y;
                 const float dxy = fmaf(dx, dx, dy * dy);
+                float r2[GB_Z], f[GB_Z];
 #pragma unroll
                 for (int t = 0; t < GB_Z; ++t) {
                     const float dz = fz[t] - c.z;
-                    const float r2 = fmaf(dz, dz, dxy);
-                    float f;
-                    if (r2 >= p.x) {
-                        f = __builtin_amdgcn_rsqf(r2);
-                    } else if (p.y > 0.0f) {
-                        const float r = sqrtf(r2);
-                        f = r > 1e-6f / p.y ? erff(r * p.y) / r : kTwoOverSqrtPi * p.y;
-                    } else {
-                        f = (p.z - r2) * p.w;
-                    }
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) part[t][b] = fmaf(-sq[a][b], f, part[t][b]);
+                    r2[t] = fmaf(dz, dz, dxy);
+                    f[t] = __builtin_amdgcn_rsqf(r2[t]);
                 }
+                if (sn[a]) {
+                    bool near = false;
+#pragma unroll
+                    for (int t = 0; t < GB_Z; ++t) near |= !(r2[t] >= p.x);
+                    if (near) {
+#pragma unroll
+                        for (int t = 0; t < GB_Z; ++t)
+                            if (!(r2[t] >= p.x)) f[t] = guess_near(r2[t], p);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < GB_Z; ++t)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) part[t][b] = fmaf(-sq[a][b], f[t], part[t][b]);
             }
 #pragma unroll
             for (int t = 0; t < GB_Z; ++t)
