@@ -451,7 +451,12 @@ hipError_t launch_apply_colour(const LevelView& L, const T* p, T* q, int colour,
 // A workgroup covers a 64 x 4 tile of (i, j) interior columns over a chunk
 // of kp planes (kp chosen to keep about PT_BLOCKS workgroups); split arrays
 // are read through sidx, so a wavefront touches two contiguous runs (one per
-// colour). Reducing kernels write one partial per workgroup.
+// colour). Reducing kernels write one partial per tile.
+//
+// The grid is 1-D, eight runs of `per` workgroups: xcd_tile hands each XCD
+// a contiguous run of the gx x gy x gz tiles (x fastest), so tiles that
+// share the cache lines at their x ends and the rows next to them (the y
+// neighbours of a march) are read through one L2 instead of eight.
 constexpr int PT_X = 64, PT_Y = 4, PT_NT = PT_X * PT_Y, PT_BLOCKS = 4096, PT_KP_MAX = 32;
 
 struct PtShape {
@@ -459,13 +464,39 @@ struct PtShape {
     int kp;
 };
 
+static dim3 pt_grid(int gx, int gy, int gz)
+{
+    const long tiles = (long)gx * gy * gz;
+    return dim3((unsigned)(8 * ((tiles + 7) / 8)));
+}
+
 static PtShape pt_shape(const LevelView& L)
 {
     PtShape p;
     const int gx = (L.nx - 2 + PT_X - 1) / PT_X, gy = (L.ny - 2 + PT_Y - 1) / PT_Y;
     const long tiles = (long)gx * gy;
     p.kp = (int)std::min<long>(PT_KP_MAX, std::max<long>(1, (long)(L.nz - 2) * tiles / PT_BLOCKS));
-    p.grid = dim3(gx, gy, (L.nz - 2 + p.kp - 1) / p.kp);
+    p.grid = pt_grid(gx, gy, (L.nz - 2 + p.kp - 1) / p.kp);
+    return p;
+}
+
+// This workgroup's tile (bx, by, bz) and its linear index t = bx + gx (by +
+// gy bz); ok is false for the few ids past the last tile.
+struct PtTile {
+    int bx, by, bz, t;
+    bool ok;
+};
+
+__device__ __forceinline__ PtTile pt_tile(const LevelView& L, int kp)
+{
+    const int gx = (L.nx - 2 + PT_X - 1) / PT_X, gy = (L.ny - 2 + PT_Y - 1) / PT_Y;
+    const int gz = (L.nz - 2 + kp - 1) / kp;
+    PtTile p;
+    p.t = xcd_tile(blockIdx.x, gridDim.x >> 3);
+    p.ok = p.t < gx * gy * gz;
+    p.bx = p.t % gx;
+    p.by = (p.t / gx) % gy;
+    p.bz = p.t / (gx * gy);
     return p;
 }
 
@@ -491,23 +522,26 @@ static PtShape residual_shape(const LevelView& L)
     PtShape p;
     const int gx = (L.nx - 2 + PT_X - 1) / PT_X, gy = (L.ny - 2 + PT_Y - 1) / PT_Y;
     p.kp = chunk_planes((long)gx * gy, L.nz - 2, resident_256(), PT_KP_MAX);
-    p.grid = dim3(gx, gy, (L.nz - 2 + p.kp - 1) / p.kp);
+    p.grid = pt_grid(gx, gy, (L.nz - 2 + p.kp - 1) / p.kp);
     return p;
 }
 
-// partials of a residual norm (one per workgroup of residual_shape)
+// partials of a residual norm (one per tile of residual_shape)
 int interior_blocks(const LevelView& L)
 {
-    const dim3 g = residual_shape(L).grid;
-    return (int)(g.x * g.y * g.z);
+    const int gx = (L.nx - 2 + PT_X - 1) / PT_X, gy = (L.ny - 2 + PT_Y - 1) / PT_Y;
+    const int kp = residual_shape(L).kp;
+    return gx * gy * ((L.nz - 2 + kp - 1) / kp);
 }
 
 // (bodies skip planes that are faces of a batch copy: !L.zint[k])
 #define INTERIOR_LOOP                                                 \
-    const int i = 1 + blockIdx.x * PT_X + (threadIdx.x % PT_X);       \
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);       \
+    const PtTile tl_ = pt_tile(L, kp);                                \
+    if (!tl_.ok) return;                                              \
+    const int i = 1 + tl_.bx * PT_X + (threadIdx.x % PT_X);           \
+    const int j = 1 + tl_.by * PT_Y + (threadIdx.x / PT_X);           \
     const bool inside = (i <= L.nx - 2) && (j <= L.ny - 2);           \
-    const int kb_ = 1 + blockIdx.z * kp;                              \
+    const int kb_ = 1 + tl_.bz * kp;                                  \
     const int ke_ = min(kb_ + kp, L.nz - 1);                          \
     for (int k = kb_; k < ke_; ++k)
 
@@ -534,10 +568,12 @@ __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, c
     static_assert(PT_X == 64, "a wave covers one row segment");
     __shared__ double red[PT_NT / 64];
     double acc = 0.0;
+    const PtTile tl = pt_tile(L, kp);
+    if (!tl.ok) return;   // (the whole workgroup)
     const int lane = threadIdx.x % PT_X;
-    const int i = 1 + blockIdx.x * PT_X + lane;
-    const int j = 1 + blockIdx.y * PT_Y + (threadIdx.x / PT_X);
-    const int kb = 1 + blockIdx.z * kp;
+    const int i = 1 + tl.bx * PT_X + lane;
+    const int j = 1 + tl.by * PT_Y + (threadIdx.x / PT_X);
+    const int kb = 1 + tl.bz * kp;
     const int ke = min(kb + kp, L.nz - 1);
     const int nx = L.nx;
     // every lane of a row that exists takes part in the shuffles: lanes past
@@ -608,7 +644,7 @@ __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, c
         A = B;
     }
     const double t = block_sum<PT_NT>(acc, red);
-    if (threadIdx.x == 0) part[block_linear()] = t;
+    if (threadIdx.x == 0) part[tl.t] = t;
 }
 
 hipError_t launch_residual_nat(const LevelView& L, const double* v, const double* rho, double bscale, double* r_split,
@@ -1884,38 +1920,36 @@ int tail_lds_limit()
 }
 
 // ------------------------------------------------------------ reduction
-// out[c] = sum_b partials[b * stride + c], c < stride, in a fixed order
-// (thread t takes t, t+1024, ..., then a fixed tree): a given launch shape
-// always gives the same bits.
-// Sums of partials in a fixed order: thread t adds entries t, t + 256, ...
-// of each column, each wave combines its lanes by a butterfly, and thread 0
-// adds the four wave sums in order. One workgroup of 256 (a launch of this
-// size is latency-bound: fewer threads and no tree of barriers).
+// out[c] = sum_b partials[b * stride + c], c < stride, in a fixed order:
+// thread t adds entries t, t + 256, ... of its column, each wave combines its
+// lanes by a butterfly, and thread 0 adds the four wave sums in order, so a
+// given count always gives the same bits. One workgroup of 256 per column
+// (a launch of this size is latency-bound: few threads, no tree of
+// barriers, and the columns side by side rather than one after another).
 constexpr int RD_NT = 256;
 
 __global__ __launch_bounds__(RD_NT) void k_reduce(const double* __restrict__ part, int stride, int count,
                                                   double* __restrict__ out)
 {
     __shared__ double sh[RD_NT / 64];
-    for (int c = 0; c < stride; ++c) {
-        double a = 0.0;
-        for (int t = threadIdx.x; t < count; t += RD_NT) a += part[(size_t)t * stride + c];
+    const int c = blockIdx.x;
+    double a = 0.0;
+    for (int t = threadIdx.x; t < count; t += RD_NT) a += part[(size_t)t * stride + c];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < RD_NT / 64; ++w) t += sh[w];
-            out[c] = t;
-        }
-        __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RD_NT / 64; ++w) t += sh[w];
+        out[c] = t;
     }
 }
 
 hipError_t launch_reduce(const double* partials, int stride, int count, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RD_NT), 0, s, partials, stride, count, out);
+    if (stride < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce, dim3(stride), dim3(RD_NT), 0, s, partials, stride, count, out);
     return hipGetLastError();
 }
 
