@@ -1086,31 +1086,54 @@ hipError_t launch_add_f32_nat(const LevelView& L, double* v, const float* y, dou
 
 // v (natural) += e (FP32, split) and, with p given, + alpha p, alpha =
 // scal[i_num]/scal[i_den] (the last step of an inner PCG folded into v; a
-// non-finite alpha adds e alone), interior
+// non-finite alpha adds e alone), interior. A thread takes AD planes of its
+// column at a time: their loads are issued together, then the updates.
 template <bool FLAG>
 __global__ __launch_bounds__(PT_NT) void k_add32_nat(LevelView L, int kp, double* __restrict__ v,
                                                      const float* __restrict__ e, const float* __restrict__ p,
                                                      double* __restrict__ scal, int i_num, int i_den)
 {
+    constexpr int AD = 4;
     float alpha = 0.0f;
     if (p) {
         const double ad = scal[i_num] / scal[i_den];
         alpha = isfinite(ad) ? (float)ad : 0.0f;
     }
-    INTERIOR_LOOP
-    {
-        if (!inside || !L.zint[k]) continue;
-        const size_t at = sidx(L, i, j, k);
-        const float d = p ? e[at] + alpha * p[at] : e[at];
-        double& vv = v[((size_t)k * L.ny + j) * L.nx + i];
-        if (FLAG) {
-            // a broken-down FP32 correction never reaches v: the node keeps
-            // its value and the solve is told (every writer stores the same 1)
-            const double nv = vv + (double)d;
-            if (isfinite(nv)) vv = nv;
-            else scal[S_BAD] = 1.0;
-        } else {
-            vv += (double)d;
+    const PtTile tl = pt_tile(L, kp);
+    if (!tl.ok) return;
+    const int i = 1 + tl.bx * PT_X + (threadIdx.x % PT_X);
+    const int j = 1 + tl.by * PT_Y + (threadIdx.x / PT_X);
+    if (i > L.nx - 2 || j > L.ny - 2) return;   // (no barrier follows)
+    const int kb = 1 + tl.bz * kp, ke = min(kb + kp, L.nz - 1);
+    for (int k0 = kb; k0 < ke; k0 += AD) {
+        double vv[AD];
+        float d[AD];
+        bool ok[AD];
+#pragma unroll
+        for (int u = 0; u < AD; ++u) {
+            const int k = k0 + u;
+            ok[u] = k < ke && L.zint[k];
+            vv[u] = 0.0;
+            d[u] = 0.0f;
+            if (ok[u]) {
+                const size_t at = sidx(L, i, j, k);
+                vv[u] = v[((size_t)k * L.ny + j) * L.nx + i];
+                d[u] = p ? e[at] + alpha * p[at] : e[at];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < AD; ++u) {
+            if (!ok[u]) continue;
+            double& dst = v[((size_t)(k0 + u) * L.ny + j) * L.nx + i];
+            if (FLAG) {
+                // a broken-down FP32 correction never reaches v: the node keeps
+                // its value and the solve is told (every writer stores the same 1)
+                const double nv = vv[u] + (double)d[u];
+                if (isfinite(nv)) dst = nv;
+                else scal[S_BAD] = 1.0;
+            } else {
+                dst = vv[u] + (double)d[u];
+            }
         }
     }
 }

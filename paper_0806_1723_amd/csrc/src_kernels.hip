@@ -18,6 +18,87 @@ namespace lasto {
 __constant__ double c_ynorm[25];
 static bool g_ynorm_ready = false;
 
+// The solid harmonic r^l y_lm is a homogeneous polynomial of degree l in
+// (x, y, z): c_mono[lm][p] is its coefficient of the monomial p = (a, b, c),
+// a + b + c <= 4, numbered a-major (mono_index). Filled with c_ynorm.
+constexpr int kMono = 35;
+__constant__ double c_mono[25 * kMono];
+
+static int mono_index(int a, int b, int c)
+{
+    int p = 0;
+    for (int a2 = 0; a2 <= 4; ++a2)
+        for (int b2 = 0; b2 <= 4 - a2; ++b2)
+            for (int c2 = 0; c2 <= 4 - a2 - b2; ++c2) {
+                if (a2 == a && b2 == b && c2 == c) return p;
+                ++p;
+            }
+    return -1;
+}
+
+// polynomials of degree <= 4 in x, y, z: coefficient [a][b][c] of x^a y^b z^c
+struct Poly4 {
+    double c[5][5][5] = {};
+    Poly4 shifted(int d) const   // times x (d 0), y (1) or z (2)
+    {
+        Poly4 r;
+        for (int a = 0; a <= 4; ++a)
+            for (int b = 0; b <= 4; ++b)
+                for (int e = 0; e <= 4; ++e) {
+                    if (c[a][b][e] == 0.0) continue;
+                    const int a2 = a + (d == 0), b2 = b + (d == 1), e2 = e + (d == 2);
+                    if (a2 > 4 || b2 > 4 || e2 > 4) continue;   // (degree stays <= 4)
+                    r.c[a2][b2][e2] += c[a][b][e];
+                }
+        return r;
+    }
+    Poly4 lin(double s, const Poly4& o, double t) const   // s this + t o
+    {
+        Poly4 r;
+        for (int a = 0; a <= 4; ++a)
+            for (int b = 0; b <= 4; ++b)
+                for (int e = 0; e <= 4; ++e) r.c[a][b][e] = s * c[a][b][e] + t * o.c[a][b][e];
+        return r;
+    }
+};
+
+// the recurrence of solid_harmonics (below) carried out on polynomials
+static void harmonic_polys(const double* ynorm, double* mono)
+{
+    Poly4 S[25];
+    Poly4 mre, mim;
+    mre.c[0][0][0] = 1.0;
+    for (int m = 0; m <= 4; ++m) {
+        if (m > 0) {
+            const Poly4 nre = mre.shifted(0).lin(1.0, mim.shifted(1), -1.0);
+            const Poly4 nim = mre.shifted(1).lin(1.0, mim.shifted(0), 1.0);
+            mre = nre.lin(2.0 * m - 1.0, nre, 0.0);
+            mim = nim.lin(2.0 * m - 1.0, nim, 0.0);
+        }
+        Poly4 pre, pim, cre = mre, cim = mim;
+        for (int l = m; l <= 4; ++l) {
+            if (l > m) {
+                const double a = (2.0 * (l - 1) + 1.0) / (double)(l - m);
+                const double b = (double)(l - 1 + m) / (double)(l - m);
+                const Poly4 r2re = pre.shifted(0).shifted(0).lin(1.0, pre.shifted(1).shifted(1), 1.0)
+                                       .lin(1.0, pre.shifted(2).shifted(2), 1.0);
+                const Poly4 r2im = pim.shifted(0).shifted(0).lin(1.0, pim.shifted(1).shifted(1), 1.0)
+                                       .lin(1.0, pim.shifted(2).shifted(2), 1.0);
+                const Poly4 nre = cre.shifted(2).lin(a, r2re, -b);
+                const Poly4 nim = cim.shifted(2).lin(a, r2im, -b);
+                pre = cre; pim = cim;
+                cre = nre; cim = nim;
+            }
+            S[l * l + l + m] = cre.lin(ynorm[l * l + l + m], cre, 0.0);
+            if (m > 0) S[l * l + l - m] = cim.lin(ynorm[l * l + l - m], cim, 0.0);
+        }
+    }
+    for (int q = 0; q < 25; ++q)
+        for (int a = 0; a <= 4; ++a)
+            for (int b = 0; b <= 4 - a; ++b)
+                for (int e = 0; e <= 4 - a - b; ++e) mono[q * kMono + mono_index(a, b, e)] = S[q].c[a][b][e];
+}
+
 hipError_t init_harmonic_constants()
 {
     if (g_ynorm_ready) return hipSuccess;
@@ -32,6 +113,10 @@ hipError_t init_harmonic_constants()
             h[l * l + l + m] = nrm;
         }
     hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_ynorm), h, sizeof(h));
+    if (e != hipSuccess) return e;
+    static double mono[25 * kMono];
+    harmonic_polys(h, mono);
+    e = hipMemcpyToSymbol(HIP_SYMBOL(c_mono), mono, sizeof(mono));
     if (e == hipSuccess) g_ynorm_ready = true;
     return e;
 }
@@ -567,49 +652,93 @@ hipError_t launch_guess_all(lasto_grid g, const AtomDev* dev_atoms, const lasto_
 
 
 // --------------------------------------------------------------- moments
-constexpr int MO_NT = 256;
+// Q_lm = sum_n w_n S_lm(x_n - c), w_n = m_x,i m_y,j m_z,k rho_n. S_lm is a
+// polynomial of degree l, so Q_lm = sum_p c_mono[lm][p] M_p over the 35 raw
+// moments M_abc = sum_n w_n x^a y^b z^c, and on the tensor-product mesh
+// M_abc = sum_rows (m_y y^b)(m_z z^c) X_a(row), X_a = sum_i m_x,i x_i^a rho.
+// A wave takes whole rows (its lanes the nodes i = lane + 64 u, all loads of
+// a row in flight together); each lane folds its X_a into its 35 M's with the
+// row's y-z factors, so no lane-crossing sum is needed until the end. Each
+// workgroup then turns its M's into the 25 partials of Q.
+constexpr int MO_NT = 256, MO_AHEAD = 6;
 
 __global__ __launch_bounds__(MO_NT) void k_moments(LevelView L, const double* __restrict__ rho, double cx, double cy,
                                                    double cz, double* __restrict__ part)
 {
-    __shared__ double sh[MO_NT / 64];
-    const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const size_t n = (size_t)nx * ny * nz;
-    double acc[25];
-    for (int c = 0; c < 25; ++c) acc[c] = 0.0;
-    double S[25];
-    // the node index is decoded once and then advanced by the grid stride
-    // with carries (a 64-bit division per node cost more than the node)
-    size_t t = (size_t)blockIdx.x * MO_NT + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * MO_NT;
-    int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((size_t)nx * ny));
-    const int di = (int)(stride % nx), dj = (int)((stride / nx) % ny), dk = (int)(stride / ((size_t)nx * ny));
-    for (; t < n; t += stride) {
-        const double f = rho[t];
-        if (f != 0.0) {
-            const double w = L.ax[0].m[i] * L.ax[1].m[j] * L.ax[2].m[k] * f;
-            solid_harmonics(L.ax[0].x[i] - cx, L.ax[1].x[j] - cy, L.ax[2].x[k] - cz, 4, S);
-            for (int c = 0; c < 25; ++c) acc[c] += w * S[c];
+    constexpr int NW = MO_NT / 64;
+    __shared__ double sm[NW][kMono];
+    __shared__ double mb[kMono];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nx = L.nx, ny = L.ny;
+    const int rows = ny * L.nz;   // (node counts fit 32 bits per row index)
+    double M[kMono];
+#pragma unroll
+    for (int p = 0; p < kMono; ++p) M[p] = 0.0;
+    for (int row = blockIdx.x * NW + wid; row < rows; row += gridDim.x * NW) {
+        const double* rr = rho + (size_t)row * nx;
+        double X[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        bool any = false;
+        for (int i0 = lane; i0 < nx; i0 += 64 * MO_AHEAD) {
+            double f[MO_AHEAD];
+#pragma unroll
+            for (int u = 0; u < MO_AHEAD; ++u) {
+                const int i = i0 + 64 * u;
+                f[u] = i < nx ? rr[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < MO_AHEAD; ++u) {
+                if (f[u] == 0.0) continue;
+                const int i = i0 + 64 * u;
+                const double x = L.ax[0].x[i] - cx;
+                double t = L.ax[0].m[i] * f[u];
+                X[0] += t;
+                t *= x; X[1] += t;
+                t *= x; X[2] += t;
+                t *= x; X[3] += t;
+                t *= x; X[4] += t;
+                any = true;
+            }
         }
-        i += di;
-        int carry = i >= nx;
-        i -= carry * nx;
-        j += dj + carry;
-        carry = j >= ny;
-        j -= carry * ny;
-        k += dk + carry;
+        if (!__any(any)) continue;   // (a row of zeros adds nothing)
+        const int j = row % ny, k = row / ny;
+        const double y = L.ax[1].x[j] - cy, z = L.ax[2].x[k] - cz;
+        double Y[5], Z[5];
+        Y[0] = L.ax[1].m[j];
+        Z[0] = L.ax[2].m[k];
+#pragma unroll
+        for (int d = 1; d <= 4; ++d) {
+            Y[d] = Y[d - 1] * y;
+            Z[d] = Z[d - 1] * z;
+        }
+        int p = 0;
+#pragma unroll
+        for (int ea = 0; ea <= 4; ++ea)
+#pragma unroll
+            for (int eb = 0; eb <= 4 - ea; ++eb) {
+                const double xy = X[ea] * Y[eb];
+#pragma unroll
+                for (int ec = 0; ec <= 4 - ea - eb; ++ec) M[p++] += xy * Z[ec];
+            }
     }
-    for (int c = 0; c < 25; ++c) {
-        double v = acc[c];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int w = 0; w < MO_NT / 64; ++w) s += sh[w];
-            part[(size_t)blockIdx.x * 25 + c] = s;
-        }
+    // lanes, then waves in order, then the 25 partials of Q
+#pragma unroll
+    for (int p = 0; p < kMono; ++p) {
+        double v = M[p];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) sm[wid][p] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMono) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += sm[w][threadIdx.x];
+        mb[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 25) {
+        double q = 0.0;
+        for (int p = 0; p < kMono; ++p) q += c_mono[threadIdx.x * kMono + p] * mb[p];
+        part[(size_t)blockIdx.x * 25 + threadIdx.x] = q;
     }
 }
 
