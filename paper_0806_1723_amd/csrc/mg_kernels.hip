@@ -500,6 +500,20 @@ __device__ __forceinline__ PtTile pt_tile(const LevelView& L, int kp)
     return p;
 }
 
+// zint of the planes kb-1 .. kb+62 as the bits of a wave-uniform mask (bit
+// k - kb + 1 is zint[k]; one byte load per lane, once). Must be reached by
+// every lane of the wave. A byte load inside a plane loop goes through the
+// vector memory path, and the wait for it also waits for every load issued
+// before it, which undoes any prefetch.
+static_assert(PT_KP_MAX + 2 <= 64, "a chunk's planes and their neighbours fit one mask");
+__device__ __forceinline__ unsigned long long zint_mask(const LevelView& L, int kb)
+{
+    const int k = kb - 1 + (int)(threadIdx.x & 63);
+    return __ballot(k < L.nz && L.zint[k]);
+}
+
+__device__ __forceinline__ bool zbit(unsigned long long m, int k, int kb) { return (m >> (k - kb + 1)) & 1ull; }
+
 // Resident workgroups of 256 threads on the device when each takes at most
 // 64 VGPRs (eight per compute unit), at least 8
 static int resident_256()
@@ -534,7 +548,7 @@ int interior_blocks(const LevelView& L)
     return gx * gy * ((L.nz - 2 + kp - 1) / kp);
 }
 
-// (bodies skip planes that are faces of a batch copy: !L.zint[k])
+// (bodies skip planes that are faces of a batch copy: !ZINT(k))
 #define INTERIOR_LOOP                                                 \
     const PtTile tl_ = pt_tile(L, kp);                                \
     if (!tl_.ok) return;                                              \
@@ -543,7 +557,11 @@ int interior_blocks(const LevelView& L)
     const bool inside = (i <= L.nx - 2) && (j <= L.ny - 2);           \
     const int kb_ = 1 + tl_.bz * kp;                                  \
     const int ke_ = min(kb_ + kp, L.nz - 1);                          \
+    const unsigned long long zm_ = zint_mask(L, kb_);                 \
     for (int k = kb_; k < ke_; ++k)
+
+// zint[k] of a plane of this INTERIOR_LOOP's or ROW_LOOP's chunk
+#define ZINT(k) zbit(zm_, (k), kb_)
 
 #define PT_LAUNCH(kernel, L, s, ...)                                                         \
     do {                                                                                     \
@@ -552,15 +570,13 @@ int interior_blocks(const LevelView& L)
     } while (0)
 
 // Fine level, natural v and rho: r = bscale rho - A v (r in the split
-// layout, FP64 or FP32, when given) and partials of ||r||_W^2. IZ: the
-// interior of v is read as zero (the reference residual of the face data
-// alone: only rho and the face values next to a node are read). Each thread
+// layout, FP64 or FP32, when given) and partials of ||r||_W^2. Each thread
 // marches its (i, j) column up its chunk of planes: the centre values of
 // planes k-1, k, k+1 stay in registers, a wave covers 64 consecutive nodes
 // of a row, so the x neighbours are the adjacent lanes' centres (a lane at
 // either end of the wave loads its outer neighbour), and plane k+1's y
 // neighbours and rho are loaded before plane k is computed.
-template <typename TO, bool IZ>
+template <typename TO>
 __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, const double* __restrict__ v,
                                                           const double* __restrict__ rho, double bscale,
                                                           TO* __restrict__ r, double* __restrict__ part)
@@ -594,26 +610,14 @@ __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, c
         Ops o;
         const size_t idx = (size_t)k * sxy + col;
         o.b = inside ? rho[idx] : 0.0;
-        if (IZ) {
-            o.ym = (inside && j == 1) ? v[idx - nx] : 0.0;
-            o.yp = (inside && j == L.ny - 2) ? v[idx + nx] : 0.0;
-            o.xo = (inside && ((first && i == 1) || (last && i == nx - 2))) ? v[first ? idx - 1 : idx + 1] : 0.0;
-        } else {
-            o.ym = inside ? v[idx - nx] : 0.0;
-            o.yp = inside ? v[idx + nx] : 0.0;
-            o.xo = (inside && (first || last)) ? v[first ? idx - 1 : idx + 1] : 0.0;
-        }
+        o.ym = inside ? v[idx - nx] : 0.0;
+        o.yp = inside ? v[idx + nx] : 0.0;
+        o.xo = (inside && (first || last)) ? v[first ? idx - 1 : idx + 1] : 0.0;
         return o;
     };
-    // centres of planes k-1, k, k+1 (IZ: only face planes are not zero)
-    auto centre = [&](int k) -> double {
-        if (!row_ok) return 0.0;
-        if (IZ) {
-            const bool face_x = ic == 0 || ic == nx - 1;
-            if (!face_x && L.zint[k]) return 0.0;
-        }
-        return v[(size_t)k * sxy + col];
-    };
+    // centres of planes k-1, k, k+1
+    auto centre = [&](int k) -> double { return row_ok ? v[(size_t)k * sxy + col] : 0.0; };
+    const unsigned long long zm_ = zint_mask(L, kb);
     double zm = centre(kb - 1), zc = centre(kb);
     Ops A = load(kb);
     for (int k = kb; k < ke; ++k) {
@@ -623,18 +627,10 @@ __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, c
         // x neighbours from the adjacent lanes' centres
         const double sl = __shfl_up(zc, 1, 64), sr = __shfl_down(zc, 1, 64);
         const double xm = first ? A.xo : sl, xp = last ? A.xo : sr;
-        if (inside && L.zint[k]) {
-            double a;
-            if (IZ) {
-                // only neighbours on a face (of this copy) keep their values
-                a = (i == 1 ? cxm * xm : 0.0) + (i == nx - 2 ? cxp * xp : 0.0);
-                a += (j == 1 ? cym * A.ym : 0.0) + (j == L.ny - 2 ? cyp * A.yp : 0.0);
-                a += (!L.zint[k - 1] ? L.ax[2].am[k] * zm : 0.0) + (!L.zint[k + 1] ? L.ax[2].ap[k] * zp : 0.0);
-            } else {
-                a = cxm * (xm - zc) + cxp * (xp - zc);
-                a += cym * (A.ym - zc) + cyp * (A.yp - zc);
-                a += L.ax[2].am[k] * (zm - zc) + L.ax[2].ap[k] * (zp - zc);
-            }
+        if (inside && zbit(zm_, k, kb)) {
+            double a = cxm * (xm - zc) + cxp * (xp - zc);
+            a += cym * (A.ym - zc) + cyp * (A.yp - zc);
+            a += L.ax[2].am[k] * (zm - zc) + L.ax[2].ap[k] * (zp - zc);
             const double res = bscale * A.b - a;
             if (r) r[sidx(L, i, j, k)] = (TO)res;
             acc += vxy * L.ax[2].m[k] * res * res;
@@ -647,15 +643,78 @@ __global__ __launch_bounds__(PT_NT) void k_residual_march(LevelView L, int kp, c
     if (threadIdx.x == 0) part[tl.t] = t;
 }
 
+// The reference residual of the face data alone: the interior of v is read
+// as zero, so only rho and the face values next to a node are read. With no
+// neighbours to share there is no march: a thread takes RF planes of its
+// column at a time and issues all their loads together (the tiles and
+// partials are k_residual_march's).
+template <typename TO>
+__global__ __launch_bounds__(PT_NT) void k_residual_faces(LevelView L, int kp, const double* __restrict__ v,
+                                                          const double* __restrict__ rho, double bscale,
+                                                          TO* __restrict__ r, double* __restrict__ part)
+{
+    constexpr int RF = 2;
+    __shared__ double red[PT_NT / 64];
+    double acc = 0.0;
+    const PtTile tl = pt_tile(L, kp);
+    if (!tl.ok) return;   // (the whole workgroup)
+    const int i = 1 + tl.bx * PT_X + (threadIdx.x % PT_X);
+    const int j = 1 + tl.by * PT_Y + (threadIdx.x / PT_X);
+    const int kb = 1 + tl.bz * kp;
+    const int ke = min(kb + kp, L.nz - 1);
+    const int nx = L.nx, ny = L.ny;
+    const bool inside = i <= nx - 2 && j <= ny - 2;
+    const size_t sxy = (size_t)nx * ny;
+    const size_t col = (size_t)min(j, ny - 1) * nx + min(i, nx - 1);
+    const double cxm = L.ax[0].am[min(i, nx - 2)], cxp = L.ax[0].ap[min(i, nx - 2)];
+    const double cym = L.ax[1].am[min(j, ny - 2)], cyp = L.ax[1].ap[min(j, ny - 2)];
+    const double vxy = L.ax[0].m[min(i, nx - 2)] * L.ax[1].m[min(j, ny - 2)];
+    const bool fxm = i == 1, fxp = i == nx - 2, fym = j == 1, fyp = j == ny - 2;
+    const unsigned long long zm_ = zint_mask(L, kb);
+    for (int k0 = kb; k0 < ke; k0 += RF) {
+        double b[RF], xm[RF], xp[RF], ym[RF], yp[RF], zm[RF], zp[RF];
+        bool ok[RF], fzm[RF], fzp[RF];
+#pragma unroll
+        for (int u = 0; u < RF; ++u) {
+            const int k = k0 + u;
+            ok[u] = inside && k < ke && zbit(zm_, k, kb);
+            fzm[u] = ok[u] && !zbit(zm_, k - 1, kb);
+            fzp[u] = ok[u] && !zbit(zm_, k + 1, kb);
+            const size_t idx = (size_t)k * sxy + col;
+            b[u] = ok[u] ? rho[idx] : 0.0;
+            xm[u] = ok[u] && fxm ? v[idx - 1] : 0.0;
+            xp[u] = ok[u] && fxp ? v[idx + 1] : 0.0;
+            ym[u] = ok[u] && fym ? v[idx - nx] : 0.0;
+            yp[u] = ok[u] && fyp ? v[idx + nx] : 0.0;
+            zm[u] = fzm[u] ? v[idx - sxy] : 0.0;
+            zp[u] = fzp[u] ? v[idx + sxy] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RF; ++u) {
+            if (!ok[u]) continue;
+            const int k = k0 + u;
+            // only neighbours on a face (of this copy) keep their values
+            double a = (fxm ? cxm * xm[u] : 0.0) + (fxp ? cxp * xp[u] : 0.0);
+            a += (fym ? cym * ym[u] : 0.0) + (fyp ? cyp * yp[u] : 0.0);
+            a += (fzm[u] ? L.ax[2].am[k] * zm[u] : 0.0) + (fzp[u] ? L.ax[2].ap[k] * zp[u] : 0.0);
+            const double res = bscale * b[u] - a;
+            if (r) r[sidx(L, i, j, k)] = (TO)res;
+            acc += vxy * L.ax[2].m[k] * res * res;
+        }
+    }
+    const double t = block_sum<PT_NT>(acc, red);
+    if (threadIdx.x == 0) part[tl.t] = t;
+}
+
 hipError_t launch_residual_nat(const LevelView& L, const double* v, const double* rho, double bscale, double* r_split,
                                double* partials, int interior_zero, hipStream_t s)
 {
     const PtShape ps = residual_shape(L);
     if (interior_zero)
-        hipLaunchKernelGGL((k_residual_march<double, true>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale,
+        hipLaunchKernelGGL((k_residual_faces<double>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale,
                            r_split, partials);
     else
-        hipLaunchKernelGGL((k_residual_march<double, false>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale,
+        hipLaunchKernelGGL((k_residual_march<double>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale,
                            r_split, partials);
     return hipGetLastError();
 }
@@ -664,7 +723,7 @@ hipError_t launch_residual_nat32(const LevelView& L, const double* v, const doub
                                  double* partials, hipStream_t s)
 {
     const PtShape ps = residual_shape(L);
-    hipLaunchKernelGGL((k_residual_march<float, false>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale, r32,
+    hipLaunchKernelGGL((k_residual_march<float>), ps.grid, dim3(PT_NT), 0, s, L, ps.kp, v, rho, bscale, r32,
                        partials);
     return hipGetLastError();
 }
@@ -675,7 +734,7 @@ __global__ __launch_bounds__(PT_NT) void k_apply_nat(LevelView L, int kp, const 
 {
     INTERIOR_LOOP
     {
-        if (!inside || !L.zint[k]) continue;
+        if (!inside || !ZINT(k)) continue;
         const int nx = L.nx;
         const size_t sxy = (size_t)nx * L.ny;
         const size_t idx = (size_t)k * sxy + (size_t)j * nx + i;
@@ -725,6 +784,7 @@ int row_blocks(const LevelView& L)
     const bool inside = (m < L.W) && (j <= L.ny - 2);                     \
     const int kb_ = 1 + (blockIdx.z >> 1) * kp;                           \
     const int ke_ = min(kb_ + kp, L.nz - 1);                              \
+    const unsigned long long zm_ = zint_mask(L, kb_);                     \
     for (int k = kb_; k < ke_; ++k)
 
 #define ROW_AT ((size_t)c * L.cs + ((size_t)k * L.ny + j) * L.W + m)
@@ -744,7 +804,7 @@ __global__ __launch_bounds__(PT_NT) void k_dot(LevelView L, int kp, const T* __r
     double acc = 0.0;
     ROW_LOOP
     {
-        if (!inside || !L.zint[k]) continue;
+        if (!inside || !ZINT(k)) continue;
         const size_t at = ROW_AT;
         acc += ROW_VOL * (double)a[at] * (double)b[at];
     }
@@ -1055,7 +1115,7 @@ __global__ __launch_bounds__(PT_NT) void k_add_nat(LevelView L, int kp, double* 
 {
     INTERIOR_LOOP
     {
-        if (!inside || !L.zint[k]) continue;
+        if (!inside || !ZINT(k)) continue;
         v[((size_t)k * L.ny + j) * L.nx + i] += e[sidx(L, i, j, k)];
     }
 }
@@ -1072,7 +1132,7 @@ __global__ __launch_bounds__(PT_NT) void k_add_f32_nat(LevelView L, int kp, doub
 {
     INTERIOR_LOOP
     {
-        if (!inside || !L.zint[k]) continue;
+        if (!inside || !ZINT(k)) continue;
         const size_t at = ((size_t)k * L.ny + j) * L.nx + i;
         v[at] += s * (double)y[at];
     }
@@ -1103,8 +1163,9 @@ __global__ __launch_bounds__(PT_NT) void k_add32_nat(LevelView L, int kp, double
     if (!tl.ok) return;
     const int i = 1 + tl.bx * PT_X + (threadIdx.x % PT_X);
     const int j = 1 + tl.by * PT_Y + (threadIdx.x / PT_X);
-    if (i > L.nx - 2 || j > L.ny - 2) return;   // (no barrier follows)
     const int kb = 1 + tl.bz * kp, ke = min(kb + kp, L.nz - 1);
+    const unsigned long long zm_ = zint_mask(L, kb);
+    if (i > L.nx - 2 || j > L.ny - 2) return;   // (no barrier follows)
     for (int k0 = kb; k0 < ke; k0 += AD) {
         double vv[AD];
         float d[AD];
@@ -1112,7 +1173,7 @@ __global__ __launch_bounds__(PT_NT) void k_add32_nat(LevelView L, int kp, double
 #pragma unroll
         for (int u = 0; u < AD; ++u) {
             const int k = k0 + u;
-            ok[u] = k < ke && L.zint[k];
+            ok[u] = k < ke && zbit(zm_, k, kb);
             vv[u] = 0.0;
             d[u] = 0.0f;
             if (ok[u]) {
@@ -1162,7 +1223,7 @@ __global__ __launch_bounds__(PT_NT) void k_split_to_nat(LevelView L, int kp, con
 {
     INTERIOR_LOOP
     {
-        if (!inside || !L.zint[k]) continue;
+        if (!inside || !ZINT(k)) continue;
         a[((size_t)k * L.ny + j) * L.nx + i] = in[sidx(L, i, j, k)];
     }
 }
@@ -1474,7 +1535,7 @@ __global__ __launch_bounds__(PT_NT) void k_prolong_add(LevelView F, int kp, Leve
     const LevelView& L = F;
     INTERIOR_LOOP
     {
-        if (!inside || !L.zint[k]) continue;
+        if (!inside || !ZINT(k)) continue;
         u[sidx(F, i, j, k)] += prolong_at<T>(C, e, prolong_taps<T>(C.ax[0], i), j, k);
     }
 }
