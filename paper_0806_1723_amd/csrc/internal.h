@@ -375,6 +375,8 @@ template <typename T>
 hipError_t launch_apply_colour(const LevelView& L, const T* p, T* q, int colour, double* dotp, hipStream_t s,
                                int* nparts);
 template <typename T>
+hipError_t launch_apply_both(const LevelView& L, const T* p, T* q, double* dotp, hipStream_t s, int* nparts);
+template <typename T>
 hipError_t launch_restrict_red(const LevelView& F, const LevelView& C, const T* r, T* rc, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_red(const LevelView& F, const LevelView& C, const T* e, T* u, hipStream_t s);

@@ -153,7 +153,7 @@ __device__ __forceinline__ T prolong_at(const LevelView& C, const T* __restrict_
 }
 
 // --------------------------------------------------------- half-sweep
-enum HalfMode { HM_GS = 0, HM_RESID = 1, HM_APPLY = 2 };
+enum HalfMode { HM_GS = 0, HM_RESID = 1, HM_APPLY = 2, HM_APPLY2 = 3 };
 
 // Over the nodes of colour c (VEC neighbouring entries m0 .. m0+VEC-1 of a
 // colour row per thread, 16 bytes, loaded as one vector):
@@ -161,6 +161,11 @@ enum HalfMode { HM_GS = 0, HM_RESID = 1, HM_APPLY = 2 };
 //            (the Gauss-Seidel update of a red-black half-sweep; dot += vol f out)
 //   HM_RESID out_n = bscale f_n - (A u)_n
 //   HM_APPLY out_n = (A u)_n                                     (dot += vol u out)
+//   HM_APPLY2 HM_APPLY on both colours in one launch: tile ids 2t and 2t+1
+//            are the two colours of spatial tile t, side by side in an
+//            XCD's run, so the colour each reads as its neighbours is the
+//            one the other has just read (launched with c = 0: uo colour 1,
+//            ucen colour 0, out colour 0 of out's two colours)
 // The neighbours all have the other colour: entry m of the other colour on
 // planes k-1 and k+1 holds the z neighbours, entries m-1+o and m+o the x
 // neighbours (o = (c+j+k) & 1), rows j-1 and j+1 the y neighbours; the x
@@ -232,7 +237,9 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
     typedef typename Vec16<T>::V VT;
     constexpr int VEC = Vec16<T>::N;
     __shared__ double red[H2_NT / 64];
-    constexpr bool NEED_U = !ZERO_IN || MODE != HM_GS;
+    constexpr bool BOTH = MODE == HM_APPLY2;
+    constexpr int M = BOTH ? HM_APPLY : MODE;   // the node arithmetic
+    constexpr bool NEED_U = !ZERO_IN || M != HM_GS;
     double dot = 0.0;
     const int nx = L.nx, nz = L.nz, W = L.W;
     const size_t plane = (size_t)L.ny * W;
@@ -243,7 +250,12 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
     // gridDim.x, a multiple of 8, so every id it takes maps to a tile of the
     // XCD it runs on).
     for (int id = blockIdx.x; id < 8 * per; id += gridDim.x) {
-        const int t = xcd_tile(id, per);
+        const int tt = xcd_tile(id, per);
+        const int t = BOTH ? tt >> 1 : tt;          // the spatial tile
+        const int cc = BOTH ? (c ^ (tt & 1)) : c;   // and its colour
+        const T* __restrict__ po = BOTH && cc != c ? ucen : uo;   // other colour
+        const T* __restrict__ pc = BOTH && cc != c ? uo : ucen;   // this colour
+        T* __restrict__ pq = BOTH && cc != c ? out + L.cs : out;
         const int m0 = VEC * ((t % nbx) * H2_X + (threadIdx.x & (H2_X - 1)));
         const int j = 1 + ((t / nbx) % nby) * H2_Y + (threadIdx.x / H2_X);
         if (!(t < nb && j <= L.ny - 2 && m0 <= (nx - 2) / 2)) continue;
@@ -266,23 +278,23 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
         const int xoff1 = VEC, xoff0 = m0 > 0 ? -1 : 0;
         auto load_plane = [&](int k, HalfOps<T>& q) {
             const size_t at = (size_t)k * plane + row;
-            const int o = (c + j + k) & 1;
-            if (MODE != HM_APPLY) q.fv = *(const VT*)(fc + at);
-            if (MODE != HM_GS) q.cv = *(const VT*)(ucen + at);
+            const int o = (cc + j + k) & 1;
+            if (M != HM_APPLY) q.fv = *(const VT*)(fc + at);
+            if (M != HM_GS) q.cv = *(const VT*)(pc + at);
             if (NEED_U) {
-                q.ym = *(const VT*)(uo + at - W);
-                q.yp = *(const VT*)(uo + at + W);
-                q.xe = uo[at + (o ? xoff1 : xoff0)];
+                q.ym = *(const VT*)(po + at - W);
+                q.yp = *(const VT*)(po + at + W);
+                q.xe = po[at + (o ? xoff1 : xoff0)];
             }
         };
         auto load_z = [&](int k) -> VT {
             VT z = VT(T(0));
-            if (NEED_U) z = *(const VT*)(uo + (size_t)k * plane + row);
+            if (NEED_U) z = *(const VT*)(po + (size_t)k * plane + row);
             return z;
         };
         // plane k from its operands and the z neighbours (zm, zc, zp)
         auto compute = [&](int k, const HalfOps<T>& q, const VT& zm, const VT& zc, const VT& zp) {
-            const int o = (c + j + k) & 1;
+            const int o = (cc + j + k) & 1;
             const int i0 = o + 2 * m0;
             const bool okz = L.zint[k];   // planes next to another copy of a batch are faces
             const VT cxm = o ? axm1 : axm0, cxp = o ? axp1 : axp0;
@@ -295,7 +307,7 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                 // x neighbours of entry e: o = 1: (zc[e], zc[e+1] or xe); o = 0: (zc[e-1] or xe, zc[e])
                 const T xl = o ? zc[e] : (e > 0 ? zc[e > 0 ? e - 1 : 0] : q.xe);
                 const T xr = o ? (e + 1 < VEC ? zc[e + 1 < VEC ? e + 1 : e] : q.xe) : zc[e];
-                if (MODE == HM_GS) {
+                if (M == HM_GS) {
                     if (NEED_U)
                         r[e] = gs_update(cxm[e], cxp[e], xl, xr, cym, cyp, q.ym[e], q.yp[e], czm, czp, zm[e], zp[e],
                                          bscale, q.fv[e]);
@@ -307,7 +319,7 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                     T a = cxm[e] * (xl - c0) + cxp[e] * (xr - c0);
                     a += cym * (q.ym[e] - c0) + cyp * (q.yp[e] - c0);
                     a += czm * (zm[e] - c0) + czp * (zp[e] - c0);
-                    r[e] = MODE == HM_RESID ? bscale * q.fv[e] - a : a;
+                    r[e] = M == HM_RESID ? bscale * q.fv[e] - a : a;
                 }
             }
             const size_t at = (size_t)k * plane + row;
@@ -317,18 +329,18 @@ __global__ __launch_bounds__(H2_NT) void k_half2(LevelView L, const T* __restric
                 VT w;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) w[e] = ok[e] ? r[e] : T(0);
-                *(VT*)(out + at) = w;
+                *(VT*)(pq + at) = w;
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
-                    if (ok[e]) out[at + e] = r[e];
+                    if (ok[e]) pq[at + e] = r[e];
             }
             if (DOT) {
                 const double vz = okz ? vy * L.ax[2].m[k] : 0.0;
                 const VT av = o ? axv1 : axv0;   // zero off the interior
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    const T a = MODE == HM_APPLY ? q.cv[e] : q.fv[e];
+                    const T a = M == HM_APPLY ? q.cv[e] : q.fv[e];
                     dot += (double)av[e] * vz * (double)a * (double)(ok[e] ? r[e] : T(0));
                 }
             }
@@ -437,6 +449,21 @@ template <typename T>
 hipError_t launch_residual_colour(const LevelView& L, const T* u, const T* f, T* r, int colour, hipStream_t s)
 {
     return launch_half2<T, HM_RESID, false, false, true>(L, u, f, r, colour, T(1), nullptr, s, nullptr);
+}
+
+// q = A p on both colours in one launch (HM_APPLY2), with partials of
+// <p, q>_W
+template <typename T>
+hipError_t launch_apply_both(const LevelView& L, const T* p, T* q, double* dotp, hipStream_t s, int* nparts)
+{
+    const int cap = half_cap<T, HM_APPLY2, false, true, true, false>();
+    const HalfShape h = half_shape(L, Vec16<T>::N, cap);
+    const int per = (2 * h.nb + 7) / 8;   // ids over both colours of every tile
+    const int G = std::min(8 * per, cap);
+    hipLaunchKernelGGL((k_half2<T, HM_APPLY2, false, true, true, false>), dim3(G), dim3(H2_NT), 0, s, L, p + L.cs,
+                       (const T*)nullptr, p, q, 0, T(1), dotp, h.nbx, h.nby, h.nb, per, h.kc);
+    if (nparts) *nparts = G;
+    return hipGetLastError();
 }
 
 // q = A p on one colour, with partials of <p, q>_W over that colour
@@ -2049,6 +2076,7 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
     template hipError_t launch_restrict_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);     \
     template hipError_t launch_residual_colour<T>(const LevelView&, const T*, const T*, T*, int, hipStream_t);    \
     template hipError_t launch_apply_colour<T>(const LevelView&, const T*, T*, int, double*, hipStream_t, int*);   \
+    template hipError_t launch_apply_both<T>(const LevelView&, const T*, T*, double*, hipStream_t, int*);          \
     template hipError_t launch_tail<T>(const TailLevel*, int, int, int, int, int, hipStream_t);                    \
     template hipError_t launch_dot<T>(const LevelView&, const T*, const T*, double*, hipStream_t);                 \
     template hipError_t launch_update_p<T>(const LevelView&, const T*, const T*, T*, const double*, int, int, int,  \

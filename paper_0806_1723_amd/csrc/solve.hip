@@ -323,10 +323,7 @@ template <typename T>
 static lasto_status apply_dot(lasto_grid g, const T* p, T* q, int* count)
 {
     const LevelView& V = g->lev[0].view;
-    int nb0 = 0, nb1 = 0;
-    HIPCHK(launch_apply_colour<T>(V, p, q, 0, g->partials, g->stream, &nb0));
-    HIPCHK(launch_apply_colour<T>(V, p, q, 1, g->partials + nb0, g->stream, &nb1));
-    *count = nb0 + nb1;
+    HIPCHK(launch_apply_both<T>(V, p, q, g->partials, g->stream, count));
     // each colour reads p's other colour and centre, writes q
     lasto::count(g, 0, 3.0 * sizeof(T));
     return LASTO_OK;
