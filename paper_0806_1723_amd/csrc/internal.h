@@ -370,10 +370,7 @@ hipError_t launch_prolong_add(const LevelView& F, const LevelView& C, const T* e
 // half-sweep only red nodes need the coarse correction (prolong_red).
 template <typename T>
 hipError_t launch_residual_colour(const LevelView& L, const T* u, const T* f, T* r, int colour, hipStream_t s);
-// q = A p on the nodes of one colour, partials of <p, q>_W over them
-template <typename T>
-hipError_t launch_apply_colour(const LevelView& L, const T* p, T* q, int colour, double* dotp, hipStream_t s,
-                               int* nparts);
+// q = A p on both colours in one launch, partials of <p, q>_W
 template <typename T>
 hipError_t launch_apply_both(const LevelView& L, const T* p, T* q, double* dotp, hipStream_t s, int* nparts);
 template <typename T>

@@ -466,14 +466,6 @@ hipError_t launch_apply_both(const LevelView& L, const T* p, T* q, double* dotp,
     return hipGetLastError();
 }
 
-// q = A p on one colour, with partials of <p, q>_W over that colour
-template <typename T>
-hipError_t launch_apply_colour(const LevelView& L, const T* p, T* q, int colour, double* dotp, hipStream_t s,
-                               int* nparts)
-{
-    return launch_half2<T, HM_APPLY, false, true, true>(L, p, (const T*)nullptr, q, colour, T(1), dotp, s, nparts);
-}
-
 // ------------------------------------------------- pointwise 3-D launches
 // A workgroup covers a 64 x 4 tile of (i, j) interior columns over a chunk
 // of kp planes (kp chosen to keep about PT_BLOCKS workgroups); split arrays
@@ -2075,7 +2067,6 @@ hipError_t launch_reduce(const double* partials, int stride, int count, double* 
                                                  hipStream_t);                                                  \
     template hipError_t launch_restrict_red<T>(const LevelView&, const LevelView&, const T*, T*, hipStream_t);     \
     template hipError_t launch_residual_colour<T>(const LevelView&, const T*, const T*, T*, int, hipStream_t);    \
-    template hipError_t launch_apply_colour<T>(const LevelView&, const T*, T*, int, double*, hipStream_t, int*);   \
     template hipError_t launch_apply_both<T>(const LevelView&, const T*, T*, double*, hipStream_t, int*);          \
     template hipError_t launch_tail<T>(const TailLevel*, int, int, int, int, int, hipStream_t);                    \
     template hipError_t launch_dot<T>(const LevelView&, const T*, const T*, double*, hipStream_t);                 \
