@@ -656,8 +656,8 @@ hipError_t launch_guess_all(lasto_grid g, const AtomDev* dev_atoms, const lasto_
 // polynomial of degree l, so Q_lm = sum_p c_mono[lm][p] M_p over the 35 raw
 // moments M_abc = sum_n w_n x^a y^b z^c, and on the tensor-product mesh
 // M_abc = sum_rows (m_y y^b)(m_z z^c) X_a(row), X_a = sum_i m_x,i x_i^a rho.
-// A wave takes whole rows (its lanes the nodes i = lane + 64 u, all loads of
-// a row in flight together); each lane folds its X_a into its 35 M's with the
+// A wave takes whole rows (its lanes the nodes i = lane + 64 u, the loads of
+// up to 64 MO_AHEAD nodes of a row in flight together); each lane folds its X_a into its 35 M's with the
 // row's y-z factors, so no lane-crossing sum is needed until the end. Each
 // workgroup then turns its M's into the 25 partials of Q.
 constexpr int MO_NT = 256, MO_AHEAD = 6;
